@@ -1,0 +1,1174 @@
+/*
+ * lbm_oracle.c -- TEST INFRASTRUCTURE ONLY (see lbm_oracle.h).
+ *
+ * A plain FP64 CPU implementation of the dimensional LBM of arXiv 2302.04120.
+ * Written for readability against the paper, not for speed: one node at a
+ * time, separate arrays for the pre-collision state, the post-collision
+ * state and the streamed state, matrices applied as explicit 9x9 products.
+ * Every function names the passage of the paper it follows.  Where the paper
+ * is silent or inconsistent the reading taken is stated in a comment.
+ */
+#include "lbm_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------- */
+/* Velocity sets                                                              */
+/* ------------------------------------------------------------------------- */
+
+/* D2Q9 directions and weights (Eq. velocity_D2Q9, weights_D2Q9), in units of c */
+static const int EX9[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+static const int EY9[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+static const double W9[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                             1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+static const int OPP9[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+
+/* D2Q5 for the thermal populations: the paper only names this set (Sec. 2.2,
+ * flux BC passage).  Reading: rest weight 1/3, axis weights 1/6, c_s^2 = c^2/3
+ * (second moment of the weights). */
+static const int EX5[5] = {0, 1, 0, -1, 0};
+static const int EY5[5] = {0, 0, 1, 0, -1};
+static const double W5[5] = {1.0 / 3, 1.0 / 6, 1.0 / 6, 1.0 / 6, 1.0 / 6};
+static const int OPP5[5] = {0, 3, 4, 1, 2};
+
+/* Lattice-unit transformation matrix, rows rho, e, eps, J_x, q_x, J_y, q_y,
+ * p_xx, p_xy (Eq. M_matrix). */
+static const double MLAT9[9][9] = {
+    {1, 1, 1, 1, 1, 1, 1, 1, 1},
+    {-4, -1, -1, -1, -1, 2, 2, 2, 2},
+    {4, -2, -2, -2, -2, 1, 1, 1, 1},
+    {0, 1, 0, -1, 0, 1, -1, -1, 1},
+    {0, -2, 0, 2, 0, 1, -1, -1, 1},
+    {0, 0, 1, 0, -1, 1, 1, -1, -1},
+    {0, 0, -2, 0, 2, 1, 1, -1, -1},
+    {0, 1, -1, 1, -1, 0, 0, 0, 0},
+    {0, 0, 0, 0, 0, 1, -1, 1, -1}};
+/* moment order of each row: the power of c that scales it (Eq. M_matrix_dim) */
+static const int ORD9[9] = {0, 2, 4, 1, 3, 1, 3, 2, 2};
+
+/* D2Q5 moment basis for the two-rate thermal operator (reading: T, j_x, j_y,
+ * e, p_xx -- the D2Q5 analogue of the D2Q9 thermal operator of Sec. 3). */
+static const double MLAT5[5][5] = {
+    {1, 1, 1, 1, 1}, {0, 1, 0, -1, 0}, {0, 0, 1, 0, -1}, {-4, 1, 1, 1, 1}, {0, 1, -1, 1, -1}};
+static const int ORD5[5] = {0, 1, 1, 2, 2};
+
+/* ------------------------------------------------------------------------- */
+/* Small dense linear algebra                                                 */
+/* ------------------------------------------------------------------------- */
+
+/* Gauss-Jordan inversion with partial pivoting of an n x n row-major matrix. */
+static int invert(int n, const double* A, double* Ainv) {
+    double a[81 * 2];
+    int w = 2 * n;
+    for (int r = 0; r < n; ++r)
+        for (int k = 0; k < w; ++k)
+            a[r * w + k] = (k < n) ? A[r * n + k] : (k - n == r ? 1.0 : 0.0);
+    for (int col = 0; col < n; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < n; ++r)
+            if (fabs(a[r * w + col]) > fabs(a[piv * w + col])) piv = r;
+        if (a[piv * w + col] == 0.0) return -1;
+        if (piv != col)
+            for (int k = 0; k < w; ++k) {
+                double t = a[col * w + k];
+                a[col * w + k] = a[piv * w + k];
+                a[piv * w + k] = t;
+            }
+        double d = a[col * w + col];
+        for (int k = 0; k < w; ++k) a[col * w + k] /= d;
+        for (int r = 0; r < n; ++r) {
+            if (r == col) continue;
+            double fct = a[r * w + col];
+            if (fct != 0.0)
+                for (int k = 0; k < w; ++k) a[r * w + k] -= fct * a[col * w + k];
+        }
+    }
+    for (int r = 0; r < n; ++r)
+        for (int k = 0; k < n; ++k) Ainv[r * n + k] = a[r * w + n + k];
+    return 0;
+}
+
+static void matvec(int n, const double* A, const double* x, double* y) {
+    for (int r = 0; r < n; ++r) {
+        double s = 0.0;
+        for (int k = 0; k < n; ++k) s += A[r * n + k] * x[k];
+        y[r] = s;
+    }
+}
+
+static void matTvec(int n, const double* A, const double* x, double* y) {
+    for (int k = 0; k < n; ++k) {
+        double s = 0.0;
+        for (int r = 0; r < n; ++r) s += A[r * n + k] * x[r];
+        y[k] = s;
+    }
+}
+
+/* C = Minv * diag(d) * M  (n x n) */
+static void sandwich(int n, const double* Minv, const double* d, const double* M, double* C) {
+    for (int r = 0; r < n; ++r)
+        for (int k = 0; k < n; ++k) {
+            double s = 0.0;
+            for (int j = 0; j < n; ++j) s += Minv[r * n + j] * d[j] * M[j * n + k];
+            C[r * n + k] = s;
+        }
+}
+
+/* Dimensional transformation matrix: row k of the lattice matrix times c^order
+ * (Sec. 3, Eq. M_matrix_dim); its inverse by numerical inversion, as the
+ * paper prescribes (App. A). */
+static void build_mdim(int n, const double* Mlat, const int* ord, double c, double* Md,
+                       double* Mi) {
+    for (int r = 0; r < n; ++r)
+        for (int k = 0; k < n; ++k) Md[r * n + k] = pow(c, ord[r]) * Mlat[r * n + k];
+    invert(n, Md, Mi);
+}
+
+void orc_mdim(double c, double* M_out, double* Minv_out) {
+    build_mdim(9, &MLAT9[0][0], ORD9, c, M_out, Minv_out);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Equilibria and forcing                                                     */
+/* ------------------------------------------------------------------------- */
+
+/* second-order equilibrium (Eq. feq_geral) */
+static double feq9(int i, double rho, double ux, double uy, double c, double cs2) {
+    double cu = c * (EX9[i] * ux + EY9[i] * uy);
+    double uu = ux * ux + uy * uy;
+    return W9[i] * rho * (1.0 + cu / cs2 + cu * cu / (2.0 * cs2 * cs2) - uu / (2.0 * cs2));
+}
+
+/* Guo forcing term F-hat_i without the (1 - dt/2tau) prefactor (Eq. forcing_term) */
+static double guo9(int i, double ux, double uy, double Fx, double Fy, double c, double cs2) {
+    double cx = c * EX9[i], cy = c * EY9[i];
+    double cu = cx * ux + cy * uy;
+    double ax = (cx - ux) / cs2 + cu * cx / (cs2 * cs2);
+    double ay = (cy - uy) / cs2 + cu * cy / (cs2 * cs2);
+    return W9[i] * (ax * Fx + ay * Fy);
+}
+
+/* linear thermal equilibrium (Eq. geq_geral) on D2Q5.  Reading: the advective
+ * (first-order) part is built from T - T_ref, the temperature variable of the
+ * conventional LBM (Sec. 3); T_ref = 0 gives the printed form.  With T in
+ * kelvin the printed form turns the weak compressibility of the flow
+ * (div u != 0) into a spurious source -T div u; the datum removes it and makes
+ * the dimensional and conventional runs coincide. */
+static double geq5(int i, double T, double Tref, double ux, double uy, double c, double cs2) {
+    double cu = c * (EX5[i] * ux + EY5[i] * uy);
+    return W5[i] * (T + (T - Tref) * cu / cs2);
+}
+
+/* ------------------------------------------------------------------------- */
+/* 1D thermal LBM                                                             */
+/* ------------------------------------------------------------------------- */
+
+int orc_d1_run(int q, int n, double dx, double dt, double alpha, double qdot, double u,
+               double T0, double TL, const double* T_init, long nsteps, double* T_out) {
+    if ((q != 2 && q != 3) || n < 3 || dx <= 0 || dt <= 0 || alpha <= 0) return -1;
+    /* D1Q3: c_i = 0, +c, -c; w = 4/6, 1/6, 1/6; c_s^2 = c^2/3 (Sec. 4.1).
+     * D1Q2: c_i = +c, -c; w = 1/2, 1/2; reading c_s^2 = c^2 (second moment of
+     * the weights), the paper gives no D1Q2. */
+    int ex[3];
+    double w[3];
+    double c = dx / dt, cs2;
+    if (q == 3) {
+        ex[0] = 0; ex[1] = 1; ex[2] = -1;
+        w[0] = 4.0 / 6; w[1] = 1.0 / 6; w[2] = 1.0 / 6;
+        cs2 = c * c / 3.0;
+    } else {
+        ex[0] = 1; ex[1] = -1; ex[2] = 0;
+        w[0] = 0.5; w[1] = 0.5; w[2] = 0.0;
+        cs2 = c * c;
+    }
+    double tau = alpha / cs2 + 0.5 * dt; /* alpha = (tau - dt/2) c_s^2 */
+    if (tau <= 0.5 * dt) return -2;
+    double* g = (double*)malloc(sizeof(double) * q * n);
+    double* gs = (double*)malloc(sizeof(double) * q * n);
+    double* gn = (double*)malloc(sizeof(double) * q * n);
+    /* initial populations: equilibrium of the initial temperature */
+    for (int x = 0; x < n; ++x)
+        for (int i = 0; i < q; ++i) g[i * n + x] = w[i] * T_init[x] * (1.0 + c * ex[i] * u / cs2);
+    for (long step = 0; step < nsteps; ++step) {
+        for (int x = 0; x < n; ++x) {
+            double T = 0.0;
+            for (int i = 0; i < q; ++i) T += g[i * n + x];
+            T += 0.5 * dt * qdot; /* Eq. zero_moment_g */
+            for (int i = 0; i < q; ++i) {
+                double geq = w[i] * T * (1.0 + c * ex[i] * u / cs2);
+                double S = (1.0 - dt / (2.0 * tau)) * w[i] * qdot; /* Eq. forcing_term_g */
+                gs[i * n + x] = g[i * n + x] - dt / tau * (g[i * n + x] - geq) + dt * S;
+            }
+        }
+        for (int x = 0; x < n; ++x)
+            for (int i = 0; i < q; ++i) {
+                int xs = x - ex[i];
+                gn[i * n + x] = (xs >= 0 && xs < n) ? gs[i * n + xs] : 0.0;
+            }
+        /* wet-node Dirichlet (Eq. BCs_1D_advection_diffusion): the unknown
+         * population is set so that the node's temperature, including the
+         * half-source of Eq. zero_moment_g, equals the wall value. */
+        for (int side = 0; side < 2; ++side) {
+            int x = side == 0 ? 0 : n - 1;
+            double Tw = side == 0 ? T0 : TL;
+            int unknown = -1;
+            double known = 0.0;
+            for (int i = 0; i < q; ++i) {
+                int xs = x - ex[i];
+                if (xs < 0 || xs >= n) unknown = i;
+                else known += gn[i * n + x];
+            }
+            gn[unknown * n + x] = Tw - 0.5 * dt * qdot - known;
+        }
+        double* t = g; g = gn; gn = t;
+    }
+    for (int x = 0; x < n; ++x) {
+        double T = 0.0;
+        for (int i = 0; i < q; ++i) T += g[i * n + x];
+        T_out[x] = T + 0.5 * dt * qdot;
+    }
+    free(g); free(gs); free(gn);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Single-phase channel: D2Q9 (BGK or MRT) + D2Q5 thermal                     */
+/* ------------------------------------------------------------------------- */
+
+struct orc_chan {
+    orc_chan_params p;
+    double c, cs2, tau, tauT;
+    double Md[81], Mi[81], lam[9];   /* flow: dimensional M, inverse, rates (1/s) */
+    double A[81], B[81];             /* f* = f - A(f - feq) + B Fhat */
+    double dA[81], dB[81];           /* derivatives of A, B with respect to tau */
+    double M5d[25], M5i[25], lam5[5];
+    double AT[25], BT[25], dAT[25], dBT[25];
+    double *f, *g, *fs, *gs, *fn, *gn;
+    double *rho, *ux, *uy, *T;
+    double *flux, *inlet_u, *inlet_T;
+    long t;
+};
+
+#define IDX(s, i, x, y) ((size_t)(i) * (s)->p.nx * (s)->p.ny + (size_t)(y) * (s)->p.nx + (x))
+
+/* Relaxation rates and the collision matrices that follow from them.
+ * Momentum (Sec. 2.1 and Sec. 3): Lambda = diag(0, w_e, w_eps, 0, w_q, 0, w_q,
+ * w_nu, w_nu), w_nu = 1/tau, w_q = (3/dt)(2/dt - w_nu)/(3/dt - w_nu).
+ * Collision m* = m - dt Lambda (m - meq) + dt (I - dt Lambda/2) F_m
+ * (Eq. colisao_MRT), i.e. f* = f - A (f - feq) + B Fhat with
+ * A = M^-1 dt Lambda M and B = dt M^-1 (I - dt Lambda/2) M.  BGK: A = dt/tau I,
+ * B = dt (1 - dt/2tau) I (Eq. eq_lattice_boltzmann_BGK, forcing_term). */
+static void chan_rates(orc_chan* s) {
+    const orc_chan_params* p = &s->p;
+    double dt = p->dt;
+    s->tau = p->nu / s->cs2 + 0.5 * dt;        /* Eq. eq_kinematic_viscosity */
+    s->tauT = p->alpha / s->cs2 + 0.5 * dt;    /* alpha = (tau_T - dt/2) c_s^2 */
+    double wn = 1.0 / s->tau;
+    double wq = (3.0 / dt) * (2.0 / dt - wn) / (3.0 / dt - wn);
+    double dwn = -1.0 / (s->tau * s->tau);
+    double dwq = -3.0 / (dt * dt * (3.0 / dt - wn) * (3.0 / dt - wn)) * dwn;
+    double lam[9] = {0, p->omega_e, p->omega_eps, 0, wq, 0, wq, wn, wn};
+    double dlam[9] = {0, 0, 0, 0, dwq, 0, dwq, dwn, dwn};
+    memcpy(s->lam, lam, sizeof lam);
+    double d1[9], d2[9], d3[9], d4[9];
+    for (int k = 0; k < 9; ++k) {
+        d1[k] = dt * lam[k];
+        d2[k] = dt * (1.0 - 0.5 * dt * lam[k]);
+        d3[k] = dt * dlam[k];
+        d4[k] = -0.5 * dt * dt * dlam[k];
+    }
+    if (p->flow_mrt) {
+        sandwich(9, s->Mi, d1, s->Md, s->A);
+        sandwich(9, s->Mi, d2, s->Md, s->B);
+        sandwich(9, s->Mi, d3, s->Md, s->dA);
+        sandwich(9, s->Mi, d4, s->Md, s->dB);
+    } else {
+        memset(s->A, 0, sizeof s->A); memset(s->B, 0, sizeof s->B);
+        memset(s->dA, 0, sizeof s->dA); memset(s->dB, 0, sizeof s->dB);
+        for (int k = 0; k < 9; ++k) {
+            s->A[k * 9 + k] = dt / s->tau;
+            s->B[k * 9 + k] = dt * (1.0 - dt / (2.0 * s->tau));
+            s->dA[k * 9 + k] = -dt / (s->tau * s->tau);
+            s->dB[k * 9 + k] = dt * dt / (2.0 * s->tau * s->tau);
+        }
+    }
+    /* thermal: two-rate reading, Lambda_T = diag(0, 1/tau_T, 1/tau_T, 1/dt, 1/dt)
+     * (D2Q5 analogue of the dimensional thermal operator of Sec. 3); BGK = all
+     * rates 1/tau_T. */
+    double wT = 1.0 / s->tauT, dwT = -1.0 / (s->tauT * s->tauT);
+    double l5[5], dl5[5];
+    for (int k = 0; k < 5; ++k) {
+        int jk = (k == 1 || k == 2);
+        l5[k] = (p->thermal_mrt && !jk) ? (k == 0 ? 0.0 : 1.0 / dt) : wT;
+        dl5[k] = (p->thermal_mrt && !jk) ? 0.0 : dwT;
+    }
+    memcpy(s->lam5, l5, sizeof l5);
+    double e1[5], e2[5], e3[5], e4[5];
+    for (int k = 0; k < 5; ++k) {
+        e1[k] = dt * l5[k];
+        e2[k] = dt * (1.0 - 0.5 * dt * l5[k]);
+        e3[k] = dt * dl5[k];
+        e4[k] = -0.5 * dt * dt * dl5[k];
+    }
+    sandwich(5, s->M5i, e1, s->M5d, s->AT);
+    sandwich(5, s->M5i, e2, s->M5d, s->BT);
+    sandwich(5, s->M5i, e3, s->M5d, s->dAT);
+    sandwich(5, s->M5i, e4, s->M5d, s->dBT);
+}
+
+orc_chan* orc_chan_create(const orc_chan_params* p, const double* flux, const double* inlet_u,
+                          const double* inlet_T) {
+    if (p->nx < 2 || p->ny < 1 || p->dx <= 0 || p->dt <= 0) return NULL;
+    orc_chan* s = (orc_chan*)calloc(1, sizeof(orc_chan));
+    s->p = *p;
+    size_t N = (size_t)p->nx * p->ny;
+    s->c = p->dx / p->dt;               /* lattice speed (Sec. 2.1) */
+    s->cs2 = s->c * s->c / 3.0;         /* c_s = c / sqrt(3) */
+    build_mdim(9, &MLAT9[0][0], ORD9, s->c, s->Md, s->Mi);
+    build_mdim(5, &MLAT5[0][0], ORD5, s->c, s->M5d, s->M5i);
+    chan_rates(s);
+    s->f = (double*)calloc(9 * N, sizeof(double));
+    s->fs = (double*)calloc(9 * N, sizeof(double));
+    s->fn = (double*)calloc(9 * N, sizeof(double));
+    s->g = (double*)calloc(5 * N, sizeof(double));
+    s->gs = (double*)calloc(5 * N, sizeof(double));
+    s->gn = (double*)calloc(5 * N, sizeof(double));
+    s->rho = (double*)calloc(N, sizeof(double));
+    s->ux = (double*)calloc(N, sizeof(double));
+    s->uy = (double*)calloc(N, sizeof(double));
+    s->T = (double*)calloc(N, sizeof(double));
+    s->flux = (double*)calloc(p->nx, sizeof(double));
+    s->inlet_u = (double*)calloc(p->ny, sizeof(double));
+    s->inlet_T = (double*)calloc(p->ny, sizeof(double));
+    if (flux) memcpy(s->flux, flux, sizeof(double) * p->nx);
+    if (inlet_u) memcpy(s->inlet_u, inlet_u, sizeof(double) * p->ny);
+    if (inlet_T) memcpy(s->inlet_T, inlet_T, sizeof(double) * p->ny);
+    else for (int y = 0; y < p->ny; ++y) s->inlet_T[y] = p->T_ref;
+    return s;
+}
+
+void orc_chan_destroy(orc_chan* s) {
+    if (!s) return;
+    free(s->f); free(s->fs); free(s->fn); free(s->g); free(s->gs); free(s->gn);
+    free(s->rho); free(s->ux); free(s->uy); free(s->T);
+    free(s->flux); free(s->inlet_u); free(s->inlet_T);
+    free(s);
+}
+
+void orc_chan_set_flux(orc_chan* s, const double* flux) {
+    memcpy(s->flux, flux, sizeof(double) * s->p.nx);
+}
+
+void orc_chan_set_tau(orc_chan* s, double nu, double alpha) {
+    s->p.nu = nu;
+    s->p.alpha = alpha;
+    chan_rates(s);
+}
+
+void orc_chan_init(orc_chan* s, const double* rho, const double* ux, const double* uy,
+                   const double* T) {
+    int nx = s->p.nx, ny = s->p.ny;
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            size_t n = (size_t)y * nx + x;
+            for (int i = 0; i < 9; ++i)
+                s->f[IDX(s, i, x, y)] = feq9(i, rho[n], ux[n], uy[n], s->c, s->cs2);
+            for (int i = 0; i < 5; ++i)
+                s->g[IDX(s, i, x, y)] =
+                    geq5(i, T ? T[n] : s->p.T_ref, s->p.T_ref, ux[n], uy[n], s->c, s->cs2);
+        }
+    s->t = 0;
+}
+
+/* Macros of the pre-collision state: rho (Eq. zero_moment_f), u with the half
+ * force (Eq. first_moment_f), T with the half source (Eq. zero_moment_g). */
+static void chan_node_macros(const orc_chan* s, int x, int y, double* rho, double* ux,
+                             double* uy, double* T) {
+    const orc_chan_params* p = &s->p;
+    double r = 0, jx = 0, jy = 0, t = 0;
+    for (int i = 0; i < 9; ++i) {
+        double fi = s->f[IDX(s, i, x, y)];
+        r += fi;
+        jx += s->c * EX9[i] * fi;
+        jy += s->c * EY9[i] * fi;
+    }
+    for (int i = 0; i < 5; ++i) t += s->g[IDX(s, i, x, y)];
+    *rho = r;
+    *ux = (jx + 0.5 * p->dt * p->Fx) / r;
+    *uy = (jy + 0.5 * p->dt * p->Fy) / r;
+    *T = t + 0.5 * p->dt * p->qdot;
+}
+
+void orc_chan_macros(const orc_chan* s, double* rho, double* ux, double* uy, double* T) {
+    int nx = s->p.nx, ny = s->p.ny;
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            double r, a, b, t;
+            chan_node_macros(s, x, y, &r, &a, &b, &t);
+            size_t n = (size_t)y * nx + x;
+            if (rho) rho[n] = r;
+            if (ux) ux[n] = a;
+            if (uy) uy[n] = b;
+            if (T) T[n] = t;
+        }
+}
+
+long orc_chan_time(const orc_chan* s) { return s->t; }
+
+/* wall flux at time index t: q''(x) (1 + amp sin(omega t dt)) */
+static double chan_flux_mod(const orc_chan* s, long t) {
+    return 1.0 + s->p.flux_amp * sin(s->p.flux_omega * (double)t * s->p.dt);
+}
+
+/* Collision of one node given its macros (the same for the forward and the
+ * recomputation inside the adjoint). */
+static void chan_collide_node(orc_chan* s, int x, int y) {
+    const orc_chan_params* p = &s->p;
+    size_t n = (size_t)y * p->nx + x;
+    double rho = s->rho[n], ux = s->ux[n], uy = s->uy[n], T = s->T[n];
+    if (p->flow) {
+        double f[9], fe[9], Fh[9], d[9], a[9], b[9];
+        for (int i = 0; i < 9; ++i) {
+            f[i] = s->f[IDX(s, i, x, y)];
+            fe[i] = feq9(i, rho, ux, uy, s->c, s->cs2);
+            Fh[i] = guo9(i, ux, uy, p->Fx, p->Fy, s->c, s->cs2);
+        }
+        if (p->flow_mrt) {
+            /* moment space, Eq. colisao_MRT with the dimensional matrix of Sec. 3 */
+            double m[9], me[9], Fm[9], ms[9], out[9];
+            matvec(9, s->Md, f, m);
+            matvec(9, s->Md, fe, me);
+            matvec(9, s->Md, Fh, Fm);
+            for (int k = 0; k < 9; ++k)
+                ms[k] = m[k] - p->dt * s->lam[k] * (m[k] - me[k]) +
+                        p->dt * (1.0 - 0.5 * p->dt * s->lam[k]) * Fm[k];
+            matvec(9, s->Mi, ms, out);
+            for (int i = 0; i < 9; ++i) s->fs[IDX(s, i, x, y)] = out[i];
+        } else {
+            for (int i = 0; i < 9; ++i) d[i] = f[i] - fe[i];
+            for (int i = 0; i < 9; ++i) {
+                a[i] = -p->dt / s->tau * d[i];
+                b[i] = p->dt * (1.0 - p->dt / (2.0 * s->tau)) * Fh[i];
+                s->fs[IDX(s, i, x, y)] = f[i] + a[i] + b[i];
+            }
+        }
+    } else {
+        for (int i = 0; i < 9; ++i) s->fs[IDX(s, i, x, y)] = s->f[IDX(s, i, x, y)];
+    }
+    if (p->thermal) {
+        double g[5], ge[5], Sg[5], m[5], me[5], Sm[5], ms[5], out[5];
+        for (int i = 0; i < 5; ++i) {
+            g[i] = s->g[IDX(s, i, x, y)];
+            ge[i] = geq5(i, T, p->T_ref, ux, uy, s->c, s->cs2);
+            Sg[i] = W5[i] * p->qdot; /* Eq. forcing_term_g without its prefactor */
+        }
+        matvec(5, s->M5d, g, m);
+        matvec(5, s->M5d, ge, me);
+        matvec(5, s->M5d, Sg, Sm);
+        for (int k = 0; k < 5; ++k)
+            ms[k] = m[k] - p->dt * s->lam5[k] * (m[k] - me[k]) +
+                    p->dt * (1.0 - 0.5 * p->dt * s->lam5[k]) * Sm[k];
+        matvec(5, s->M5i, ms, out);
+        for (int i = 0; i < 5; ++i) s->gs[IDX(s, i, x, y)] = out[i];
+    }
+}
+
+/* classification of the source node x - e_i of a population i arriving at (x, y) */
+enum { SRC_IN = 0, SRC_WALL = 1, SRC_INLET = 2, SRC_OUTLET = 3 };
+static int chan_src(const orc_chan* s, int x, int y, int ex, int ey, int* xs, int* ys) {
+    int nx = s->p.nx, ny = s->p.ny;
+    int sx = x - ex, sy = y - ey;
+    int outy = 0, outx = 0;
+    if (s->p.bc_y == 0) sy = (sy + ny) % ny;
+    else outy = (sy < 0 || sy >= ny);
+    if (s->p.bc_x == 0) sx = (sx + nx) % nx;
+    else outx = (sx < 0 || sx >= nx);
+    *xs = sx; *ys = sy;
+    /* tie-break at corners (the paper is silent): a link whose source lies
+     * outside in y takes the wall rule, otherwise the x-boundary rule */
+    if (outy) return SRC_WALL;
+    if (outx) return sx < 0 ? SRC_INLET : SRC_OUTLET;
+    return SRC_IN;
+}
+
+/* Streaming (text after Eq. colisao_MRT) and the boundary substitutions. */
+static void chan_stream(orc_chan* s) {
+    const orc_chan_params* p = &s->p;
+    int nx = p->nx, ny = p->ny;
+    double c = s->c, cs2 = s->cs2;
+    double mod = chan_flux_mod(s, s->t);
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            /* outlet wall velocity by extrapolation from the time-t macros
+             * (text before Eq. anti_BB_vel) */
+            double uwx = 0, uwy = 0;
+            if (x == nx - 1 && p->bc_x == 1) {
+                size_t nb = (size_t)y * nx + x, nb1 = (size_t)y * nx + x - 1;
+                uwx = s->ux[nb] + 0.5 * (s->ux[nb] - s->ux[nb1]);
+                uwy = s->uy[nb] + 0.5 * (s->uy[nb] - s->uy[nb1]);
+            }
+            for (int i = 0; i < 9; ++i) {
+                int xs, ys, o = OPP9[i];
+                int kind = chan_src(s, x, y, EX9[i], EY9[i], &xs, &ys);
+                double v;
+                if (kind == SRC_IN) v = s->fs[IDX(s, i, xs, ys)];
+                else if (kind == SRC_WALL) v = s->fs[IDX(s, o, x, y)]; /* Eq. BB_vel, u_w = 0 */
+                else if (kind == SRC_INLET) {
+                    /* moving-wall bounce-back, Eq. BB_vel, with rho_w = rho_ref and
+                     * u_w the inlet profile; outgoing direction o, c_o = -c_i */
+                    double cu = c * EX9[o] * s->inlet_u[y];
+                    v = s->fs[IDX(s, o, x, y)] - 2.0 * W9[o] * p->rho_ref * cu / cs2;
+                } else {
+                    /* anti-bounce-back pressure outlet, Eq. anti_BB_vel, rho_w = rho_ref */
+                    double cu = c * (EX9[o] * uwx + EY9[o] * uwy);
+                    double uu = uwx * uwx + uwy * uwy;
+                    v = -s->fs[IDX(s, o, x, y)] +
+                        2.0 * W9[o] * p->rho_ref *
+                            (1.0 + cu * cu / (2.0 * cs2 * cs2) - uu / (2.0 * cs2));
+                }
+                s->fn[IDX(s, i, x, y)] = p->flow ? v : s->f[IDX(s, i, x, y)];
+            }
+            if (!p->thermal) continue;
+            for (int i = 0; i < 5; ++i) {
+                int xs, ys, o = OPP5[i];
+                int kind = chan_src(s, x, y, EX5[i], EY5[i], &xs, &ys);
+                double v = 0.0;
+                if (kind == SRC_IN) v = s->gs[IDX(s, i, xs, ys)];
+                else if (kind == SRC_WALL) {
+                    /* prescribed heat flux, Eq. BB_T.  Dimensional reading of the
+                     * constant: lambda_i = 2 w_i c^2 / c_s^2 = 6 w_i (1 for D2Q5), so
+                     * the incoming links of a wall node carry exactly q'' dt dx. */
+                    double lam = 6.0 * W5[o];
+                    v = s->gs[IDX(s, o, x, y)] +
+                        lam * (p->dt / p->dx) * (s->flux[x] * mod / p->rho_cp);
+                } else if (kind == SRC_INLET) {
+                    /* anti-bounce-back Dirichlet, Eq. anti_BB_T; reading: only the
+                     * even part of the linear equilibrium actually used, 2 w T_w */
+                    v = -s->gs[IDX(s, o, x, y)] + 2.0 * W5[o] * s->inlet_T[y];
+                }
+                /* outlet: filled in the second pass below */
+                s->gn[IDX(s, i, x, y)] = v;
+            }
+        }
+    if (p->thermal && p->bc_x == 1) {
+        /* first-order extrapolation outlet: g_i(x_b) = g_i(x_b - 1), both at t+dt */
+        int x = nx - 1;
+        for (int y = 0; y < ny; ++y)
+            for (int i = 0; i < 5; ++i) {
+                int xs, ys;
+                if (chan_src(s, x, y, EX5[i], EY5[i], &xs, &ys) == SRC_OUTLET)
+                    s->gn[IDX(s, i, x, y)] = s->gn[IDX(s, i, x - 1, y)];
+            }
+    }
+}
+
+static void chan_one_step(orc_chan* s) {
+    int nx = s->p.nx, ny = s->p.ny;
+    orc_chan_macros(s, s->rho, s->ux, s->uy, s->T);
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) chan_collide_node(s, x, y);
+    chan_stream(s);
+    double* t;
+    t = s->f; s->f = s->fn; s->fn = t;
+    t = s->g; s->g = s->gn; s->gn = t;
+    s->t += 1;
+}
+
+void orc_chan_step(orc_chan* s, long nsteps) {
+    for (long k = 0; k < nsteps; ++k) chan_one_step(s);
+}
+
+void orc_chan_get_state(const orc_chan* s, double* f, double* g) {
+    size_t N = (size_t)s->p.nx * s->p.ny;
+    if (f) memcpy(f, s->f, sizeof(double) * 9 * N);
+    if (g) memcpy(g, s->g, sizeof(double) * 5 * N);
+}
+
+void orc_chan_set_state(orc_chan* s, const double* f, const double* g, long t) {
+    size_t N = (size_t)s->p.nx * s->p.ny;
+    if (f) memcpy(s->f, f, sizeof(double) * 9 * N);
+    if (g) memcpy(s->g, g, sizeof(double) * 5 * N);
+    s->t = t;
+}
+
+/* Nusselt number.  The paper reports local and mean Nu but never writes its
+ * formula; reading: Nu(x) = q''(x) D_h / (k (T_w(x) - T_b(x))), D_h = 2H,
+ * H = ny dx, k = rho c_p alpha, T_b the mixing-cup temperature sum(u T)/sum(u)
+ * over the column, T_w the mean of the two wall-adjacent node temperatures
+ * plus q'' dx / (2k) (conduction across the half cell to the halfway wall). */
+void orc_chan_nusselt(const orc_chan* s, double* Tb, double* Tw, double* Nu) {
+    const orc_chan_params* p = &s->p;
+    int nx = p->nx, ny = p->ny;
+    size_t N = (size_t)nx * ny;
+    double* ux = (double*)malloc(sizeof(double) * N);
+    double* T = (double*)malloc(sizeof(double) * N);
+    orc_chan_macros(s, NULL, ux, NULL, T);
+    double k = p->rho_cp * p->alpha, Dh = 2.0 * ny * p->dx;
+    double mod = chan_flux_mod(s, s->t);
+    for (int x = 0; x < nx; ++x) {
+        double su = 0, suT = 0;
+        for (int y = 0; y < ny; ++y) {
+            su += ux[(size_t)y * nx + x];
+            suT += ux[(size_t)y * nx + x] * T[(size_t)y * nx + x];
+        }
+        double q = s->flux[x] * mod;
+        double tb = suT / su;
+        double tw = 0.5 * (T[x] + T[(size_t)(ny - 1) * nx + x]) + q * p->dx / (2.0 * k);
+        if (Tb) Tb[x] = tb;
+        if (Tw) Tw[x] = tw;
+        if (Nu) Nu[x] = q * Dh / (k * (tw - tb));
+    }
+    free(ux); free(T);
+}
+
+double orc_chan_objective(const orc_chan* s, int x_dev, double w_tout, double w_nu) {
+    int nx = s->p.nx;
+    double* Tb = (double*)malloc(sizeof(double) * nx);
+    double* Nu = (double*)malloc(sizeof(double) * nx);
+    orc_chan_nusselt(s, Tb, NULL, Nu);
+    double nbar = 0;
+    for (int x = x_dev; x < nx; ++x) nbar += Nu[x];
+    nbar /= (double)(nx - x_dev);
+    double J = w_tout * Tb[nx - 1] + w_nu * nbar;
+    free(Tb); free(Nu);
+    return J;
+}
+
+/* ------------------------------------------------------------------------- */
+/* FP64 discrete adjoint of the channel step                                   */
+/* ------------------------------------------------------------------------- */
+/* One forward step maps the pre-collision state (f, g) at time n to the state
+ * at n+1.  The reverse sweep applies the transpose of its Jacobian to the
+ * adjoint state, in the reverse order of the forward operations:
+ * boundary/streaming, thermal collision, flow collision, macros.  Parameters:
+ * the wall flux profile enters only the flux boundary rule; tau and tau_T
+ * enter the collision matrices. */
+
+/* seed: dJ/d(state) at the final state, and the direct dJ/dflux of the Nu term */
+static void chan_objective_seed(orc_chan* s, int x_dev, double w_tout, double w_nu,
+                                double* fb, double* gb, double* dflux, double* dtau) {
+    const orc_chan_params* p = &s->p;
+    int nx = p->nx, ny = p->ny;
+    size_t N = (size_t)nx * ny;
+    orc_chan_macros(s, s->rho, s->ux, s->uy, s->T);
+    double k = p->rho_cp * p->alpha, Dh = 2.0 * ny * p->dx;
+    double mod = chan_flux_mod(s, s->t);
+    double* Tbar = (double*)calloc(N, sizeof(double));
+    double* Ubar = (double*)calloc(N, sizeof(double)); /* adjoint of u_x */
+    int ndev = nx - x_dev;
+    for (int x = 0; x < nx; ++x) {
+        double su = 0, suT = 0;
+        for (int y = 0; y < ny; ++y) {
+            su += s->ux[(size_t)y * nx + x];
+            suT += s->ux[(size_t)y * nx + x] * s->T[(size_t)y * nx + x];
+        }
+        double tb = suT / su;
+        double q = s->flux[x] * mod;
+        double tw = 0.5 * (s->T[x] + s->T[(size_t)(ny - 1) * nx + x]) + q * p->dx / (2.0 * k);
+        double dT = tw - tb;
+        double bTb = 0.0, bTw = 0.0;
+        if (x == nx - 1) bTb += w_tout;
+        if (x >= x_dev) {
+            double nu_x = q * Dh / (k * dT);
+            double bNu = w_nu / ndev;
+            double bdT = -bNu * nu_x / dT;
+            bTw += bdT;
+            bTb -= bdT;
+            /* direct dependence of Nu on q'' (numerator and wall temperature) */
+            dflux[x] += bNu * mod * (Dh / (k * dT)) + bdT * mod * p->dx / (2.0 * k);
+            /* and on the conductivity k = rho c_p alpha, alpha = (tau_T - dt/2) c_s^2 */
+            double dNu_dk = -nu_x / k + (nu_x / dT) * q * p->dx / (2.0 * k * k);
+            dtau[1] += bNu * dNu_dk * p->rho_cp * s->cs2;
+        }
+        for (int y = 0; y < ny; ++y) {
+            size_t n = (size_t)y * nx + x;
+            Tbar[n] += bTb * s->ux[n] / su;
+            Ubar[n] += bTb * (s->T[n] - tb) / su;
+        }
+        Tbar[x] += 0.5 * bTw;
+        Tbar[(size_t)(ny - 1) * nx + x] += 0.5 * bTw;
+    }
+    memset(fb, 0, sizeof(double) * 9 * N);
+    memset(gb, 0, sizeof(double) * 5 * N);
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            size_t n = (size_t)y * nx + x;
+            for (int i = 0; i < 5; ++i) gb[IDX(s, i, x, y)] = Tbar[n]; /* T = sum g + ... */
+            if (p->flow)
+                for (int i = 0; i < 9; ++i) /* du_x/df_i = (c_ix - u_x)/rho */
+                    fb[IDX(s, i, x, y)] = Ubar[n] * (s->c * EX9[i] - s->ux[n]) / s->rho[n];
+        }
+    free(Tbar); free(Ubar);
+}
+
+/* Reverse of one step from the state held in s (time n, macros refreshed
+ * here).  fb/gb hold the adjoint of the state at n+1 on entry and the adjoint
+ * of the state at n on exit. */
+static void chan_adjoint_step(orc_chan* s, double* fb, double* gb, double* dflux,
+                              double* dtau) {
+    const orc_chan_params* p = &s->p;
+    int nx = p->nx, ny = p->ny;
+    size_t N = (size_t)nx * ny;
+    double c = s->c, cs2 = s->cs2, dt = p->dt;
+    orc_chan_macros(s, s->rho, s->ux, s->uy, s->T);
+    double mod = chan_flux_mod(s, s->t);
+    double* fsb = (double*)calloc(9 * N, sizeof(double)); /* adjoint of f* */
+    double* gsb = (double*)calloc(5 * N, sizeof(double)); /* adjoint of g* */
+    double* ubx = (double*)calloc(N, sizeof(double));     /* adjoint of u (time n) */
+    double* uby = (double*)calloc(N, sizeof(double));
+    /* 1. transpose of streaming and boundary rules */
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            double uwx = 0, uwy = 0;
+            if (x == nx - 1 && p->bc_x == 1) {
+                size_t nb = (size_t)y * nx + x, nb1 = (size_t)y * nx + x - 1;
+                uwx = 1.5 * s->ux[nb] - 0.5 * s->ux[nb1];
+                uwy = 1.5 * s->uy[nb] - 0.5 * s->uy[nb1];
+            }
+            if (p->flow)
+                for (int i = 0; i < 9; ++i) {
+                    int xs, ys, o = OPP9[i];
+                    int kind = chan_src(s, x, y, EX9[i], EY9[i], &xs, &ys);
+                    double a = fb[IDX(s, i, x, y)];
+                    if (kind == SRC_IN) fsb[IDX(s, i, xs, ys)] += a;
+                    else if (kind == SRC_WALL || kind == SRC_INLET) fsb[IDX(s, o, x, y)] += a;
+                    else {
+                        fsb[IDX(s, o, x, y)] -= a;
+                        /* d/du_w of 2 w rho_w [1 + (c.u)^2/2cs^4 - u.u/2cs^2] */
+                        double cx = c * EX9[o], cy = c * EY9[o];
+                        double cu = cx * uwx + cy * uwy;
+                        double k2 = 2.0 * W9[o] * p->rho_ref;
+                        double bx = a * k2 * (cu * cx / (cs2 * cs2) - uwx / cs2);
+                        double by = a * k2 * (cu * cy / (cs2 * cs2) - uwy / cs2);
+                        size_t nb = (size_t)y * nx + x, nb1 = (size_t)y * nx + x - 1;
+                        ubx[nb] += 1.5 * bx; uby[nb] += 1.5 * by;
+                        ubx[nb1] -= 0.5 * bx; uby[nb1] -= 0.5 * by;
+                    }
+                }
+            if (p->thermal)
+                for (int i = 0; i < 5; ++i) {
+                    int xs, ys, o = OPP5[i];
+                    int kind = chan_src(s, x, y, EX5[i], EY5[i], &xs, &ys);
+                    double a = gb[IDX(s, i, x, y)];
+                    if (kind == SRC_IN) gsb[IDX(s, i, xs, ys)] += a;
+                    else if (kind == SRC_WALL) {
+                        gsb[IDX(s, o, x, y)] += a;
+                        dflux[x] += a * 6.0 * W5[o] * (dt / p->dx) * mod / p->rho_cp;
+                    } else if (kind == SRC_INLET) gsb[IDX(s, o, x, y)] -= a;
+                    else {
+                        /* g_i(x_b) = g_i(x_b - 1) after streaming, and that value was
+                         * streamed from g_i*(x_b) */
+                        int xs2, ys2;
+                        int k2 = chan_src(s, x - 1, y, EX5[i], EY5[i], &xs2, &ys2);
+                        if (k2 == SRC_IN) gsb[IDX(s, i, xs2, ys2)] += a;
+                    }
+                }
+        }
+    if (!p->flow)
+        memcpy(fsb, fb, sizeof(double) * 9 * N); /* frozen flow: f passes through */
+    /* 2. thermal collision transpose, g* = (I - A_T) g + A_T geq(T, u) + B_T S */
+    if (p->thermal)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                size_t n = (size_t)y * nx + x;
+                double T = s->T[n], ux = s->ux[n], uy = s->uy[n];
+                double gbs[5], a[5], g[5], ge[5], S[5], tmp[5], tmp2[5];
+                for (int i = 0; i < 5; ++i) {
+                    gbs[i] = gsb[IDX(s, i, x, y)];
+                    g[i] = s->g[IDX(s, i, x, y)];
+                    ge[i] = geq5(i, T, p->T_ref, ux, uy, c, cs2);
+                    S[i] = W5[i] * p->qdot;
+                }
+                matTvec(5, s->AT, gbs, a);
+                double Tb = 0.0;
+                for (int i = 0; i < 5; ++i) {
+                    double cu = c * (EX5[i] * ux + EY5[i] * uy);
+                    Tb += a[i] * W5[i] * (1.0 + cu / cs2);
+                    ubx[n] += a[i] * W5[i] * (T - p->T_ref) * c * EX5[i] / cs2;
+                    uby[n] += a[i] * W5[i] * (T - p->T_ref) * c * EY5[i] / cs2;
+                }
+                for (int i = 0; i < 5; ++i) gb[IDX(s, i, x, y)] = gbs[i] - a[i] + Tb;
+                /* tau_T: d(g*)/d(tau_T) = -dA_T (g - geq) + dB_T S */
+                for (int i = 0; i < 5; ++i) tmp[i] = g[i] - ge[i];
+                matvec(5, s->dAT, tmp, tmp2);
+                double acc = 0;
+                for (int i = 0; i < 5; ++i) acc -= gbs[i] * tmp2[i];
+                matvec(5, s->dBT, S, tmp2);
+                for (int i = 0; i < 5; ++i) acc += gbs[i] * tmp2[i];
+                dtau[1] += acc;
+            }
+    /* 3. flow collision transpose, f* = (I - A) f + A feq(rho, u) + B Fhat(u) */
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            size_t n = (size_t)y * nx + x;
+            if (!p->flow) {
+                for (int i = 0; i < 9; ++i) fb[IDX(s, i, x, y)] = fsb[IDX(s, i, x, y)];
+                continue;
+            }
+            double rho = s->rho[n], ux = s->ux[n], uy = s->uy[n];
+            double fbs[9], a[9], b[9], f[9], fe[9], Fh[9], tmp[9], tmp2[9];
+            for (int i = 0; i < 9; ++i) {
+                fbs[i] = fsb[IDX(s, i, x, y)];
+                f[i] = s->f[IDX(s, i, x, y)];
+                fe[i] = feq9(i, rho, ux, uy, c, cs2);
+                Fh[i] = guo9(i, ux, uy, p->Fx, p->Fy, c, cs2);
+            }
+            matTvec(9, s->A, fbs, a);
+            matTvec(9, s->B, fbs, b);
+            double rb = 0.0, bx = ubx[n], by = uby[n];
+            for (int i = 0; i < 9; ++i) {
+                double cx = c * EX9[i], cy = c * EY9[i];
+                double cu = cx * ux + cy * uy;
+                /* derivatives of feq_i with respect to rho and u */
+                rb += a[i] * fe[i] / rho;
+                double gx = W9[i] * rho * (cx / cs2 + cu * cx / (cs2 * cs2) - ux / cs2);
+                double gy = W9[i] * rho * (cy / cs2 + cu * cy / (cs2 * cs2) - uy / cs2);
+                bx += a[i] * gx;
+                by += a[i] * gy;
+                /* d Fhat_i / d u: w [(-F)/cs2 + c (c.F)/cs4] per component */
+                double cF = cx * p->Fx + cy * p->Fy;
+                bx += b[i] * W9[i] * (-p->Fx / cs2 + cx * cF / (cs2 * cs2));
+                by += b[i] * W9[i] * (-p->Fy / cs2 + cy * cF / (cs2 * cs2));
+            }
+            for (int i = 0; i < 9; ++i) {
+                double cx = c * EX9[i], cy = c * EY9[i];
+                /* rho = sum f, u = (sum c f + dt F/2)/rho: du/df_i = (c_i - u)/rho */
+                fb[IDX(s, i, x, y)] = fbs[i] - a[i] + rb + (bx * (cx - ux) + by * (cy - uy)) / rho;
+            }
+            for (int i = 0; i < 9; ++i) tmp[i] = f[i] - fe[i];
+            matvec(9, s->dA, tmp, tmp2);
+            double acc = 0;
+            for (int i = 0; i < 9; ++i) acc -= fbs[i] * tmp2[i];
+            matvec(9, s->dB, Fh, tmp2);
+            for (int i = 0; i < 9; ++i) acc += fbs[i] * tmp2[i];
+            dtau[0] += acc;
+        }
+    free(fsb); free(gsb); free(ubx); free(uby);
+}
+
+int orc_chan_adjoint(orc_chan* s, long nsteps, int ckpt, int x_dev, double w_tout,
+                     double w_nu, double* J, double* dJ_dflux, double* dJ_dtau) {
+    if (nsteps < 0 || ckpt < 1) return -1;
+    int nx = s->p.nx, ny = s->p.ny;
+    size_t N = (size_t)nx * ny;
+    long nseg = (nsteps + ckpt - 1) / ckpt;
+    if (nsteps == 0) nseg = 0;
+    /* forward sweep, keeping the state at the start of every segment */
+    double* ck = (double*)malloc(sizeof(double) * 14 * N * (nseg > 0 ? nseg : 1));
+    long* ckt = (long*)malloc(sizeof(long) * (nseg > 0 ? nseg : 1));
+    for (long k = 0; k < nseg; ++k) {
+        orc_chan_get_state(s, ck + 14 * N * k, ck + 14 * N * k + 9 * N);
+        ckt[k] = s->t;
+        long len = (k == nseg - 1) ? nsteps - k * ckpt : ckpt;
+        orc_chan_step(s, len);
+    }
+    double* ffin = (double*)malloc(sizeof(double) * 14 * N);
+    orc_chan_get_state(s, ffin, ffin + 9 * N);
+    long tfin = s->t;
+    *J = orc_chan_objective(s, x_dev, w_tout, w_nu);
+    double* fb = (double*)calloc(9 * N, sizeof(double));
+    double* gb = (double*)calloc(5 * N, sizeof(double));
+    for (int x = 0; x < nx; ++x) dJ_dflux[x] = 0.0;
+    dJ_dtau[0] = dJ_dtau[1] = 0.0;
+    chan_objective_seed(s, x_dev, w_tout, w_nu, fb, gb, dJ_dflux, dJ_dtau);
+    /* reverse sweep: recompute each segment from its checkpoint, then walk it
+     * backwards */
+    double* seg = (double*)malloc(sizeof(double) * 14 * N * (size_t)ckpt);
+    for (long k = nseg - 1; k >= 0; --k) {
+        long len = (k == nseg - 1) ? nsteps - k * ckpt : ckpt;
+        orc_chan_set_state(s, ck + 14 * N * k, ck + 14 * N * k + 9 * N, ckt[k]);
+        for (long j = 0; j < len; ++j) {
+            orc_chan_get_state(s, seg + 14 * N * j, seg + 14 * N * j + 9 * N);
+            orc_chan_step(s, 1);
+        }
+        for (long j = len - 1; j >= 0; --j) {
+            orc_chan_set_state(s, seg + 14 * N * j, seg + 14 * N * j + 9 * N, ckt[k] + j);
+            chan_adjoint_step(s, fb, gb, dJ_dflux, dJ_dtau);
+        }
+    }
+    orc_chan_set_state(s, ffin, ffin + 9 * N, tfin);
+    free(ck); free(ckt); free(ffin); free(fb); free(gb); free(seg);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Two-phase model: conservative Allen-Cahn h_i and pressure-evolution z_i    */
+/* (Sec. 2.3), dimensional MRT for z_i (Sec. 3)                                */
+/* ------------------------------------------------------------------------- */
+
+struct orc_phase {
+    orc_phase_params p;
+    double c, cs2, tau_phi, beta, kappa;
+    double Md[81], Mi[81];
+    double *h, *z, *hs, *zs, *hn, *zn, *phiu, *phi;
+};
+
+#define PIDX(s, i, x, y) ((size_t)(i) * (s)->p.nx * (s)->p.ny + (size_t)(y) * (s)->p.nx + (x))
+
+orc_phase* orc_phase_create(const orc_phase_params* p) {
+    if (p->nx < 1 || p->ny < 1 || p->dx <= 0 || p->dt <= 0) return NULL;
+    orc_phase* s = (orc_phase*)calloc(1, sizeof(orc_phase));
+    s->p = *p;
+    size_t N = (size_t)p->nx * p->ny;
+    s->c = p->dx / p->dt;
+    s->cs2 = s->c * s->c / 3.0;
+    s->tau_phi = p->M / s->cs2 + 0.5 * p->dt; /* M = (tau_phi - dt/2) c_s^2 */
+    s->kappa = 1.5 * p->sigma * p->W;         /* kappa = 3 sigma W / 2 */
+    s->beta = 12.0 * p->sigma / p->W;         /* beta = 12 sigma / W */
+    build_mdim(9, &MLAT9[0][0], ORD9, s->c, s->Md, s->Mi);
+    s->h = (double*)calloc(9 * N, sizeof(double));
+    s->z = (double*)calloc(9 * N, sizeof(double));
+    s->hs = (double*)calloc(9 * N, sizeof(double));
+    s->zs = (double*)calloc(9 * N, sizeof(double));
+    s->hn = (double*)calloc(9 * N, sizeof(double));
+    s->zn = (double*)calloc(9 * N, sizeof(double));
+    s->phiu = (double*)calloc(2 * N, sizeof(double));
+    s->phi = (double*)calloc(N, sizeof(double));
+    return s;
+}
+
+void orc_phase_destroy(orc_phase* s) {
+    if (!s) return;
+    free(s->h); free(s->z); free(s->hs); free(s->zs); free(s->hn); free(s->zn);
+    free(s->phiu); free(s->phi);
+    free(s);
+}
+
+/* s_i(u) of Eq. s_i_Liang */
+static double s_liang(int i, double ux, double uy, double c, double cs2) {
+    double cu = c * (EX9[i] * ux + EY9[i] * uy);
+    double uu = ux * ux + uy * uy;
+    return W9[i] * (cu / cs2 + cu * cu / (2.0 * cs2 * cs2) - uu / (2.0 * cs2));
+}
+
+/* z_i^eq of Eq. zeq_liang */
+static double zeq(int i, double p, double rho, double ux, double uy, double c, double cs2) {
+    double base = (i == 0) ? (W9[0] - 1.0) : W9[i];
+    return p / cs2 * base + rho * s_liang(i, ux, uy, c, cs2);
+}
+
+void orc_phase_init(orc_phase* s, const double* phi, const double* pr, const double* ux,
+                    const double* uy) {
+    int nx = s->p.nx, ny = s->p.ny;
+    size_t N = (size_t)nx * ny;
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            size_t n = (size_t)y * nx + x;
+            double rho = s->p.rho_g + phi[n] * (s->p.rho_l - s->p.rho_g);
+            for (int i = 0; i < 9; ++i) {
+                double cu = s->c * (EX9[i] * ux[n] + EY9[i] * uy[n]);
+                s->h[PIDX(s, i, x, y)] = phi[n] * W9[i] * (1.0 + cu / s->cs2); /* Eq. heq_liang */
+                s->z[PIDX(s, i, x, y)] = zeq(i, pr[n], rho, ux[n], uy[n], s->c, s->cs2);
+            }
+            /* reading: (phi u) at t - dt is taken equal to its initial value */
+            s->phiu[n] = phi[n] * ux[n];
+            s->phiu[N + n] = phi[n] * uy[n];
+        }
+}
+
+/* neighbour value of phi: periodic wrap, or at a wall the mirror of the first
+ * fluid node (zero normal gradient; the paper gives no phase-field wall rule) */
+static double phase_phi_at(const orc_phase* s, int x, int y) {
+    int nx = s->p.nx, ny = s->p.ny;
+    x = (x % nx + nx) % nx;
+    if (s->p.bc_y == 0) y = (y % ny + ny) % ny;
+    else if (y < 0) y = 0;
+    else if (y >= ny) y = ny - 1;
+    return s->phi[(size_t)y * nx + x];
+}
+
+typedef struct {
+    double phi, rho, tau, gx, gy, lap, nx, ny, mu, Fx, Fy, ux, uy, p;
+} phase_macro;
+
+/* All node-local quantities of Sec. 2.3 in the order the model needs them:
+ * phi (all nodes, beforehand), rho and viscosity, stencils, normal, chemical
+ * potential, surface force, velocity, then pressure. */
+static void phase_node(const orc_phase* s, int x, int y, phase_macro* m) {
+    const orc_phase_params* p = &s->p;
+    double c = s->c, cs2 = s->cs2, dt = p->dt;
+    double phi = phase_phi_at(s, x, y);
+    m->phi = phi;
+    m->rho = p->rho_g + phi * (p->rho_l - p->rho_g);
+    double nu;
+    if (p->visc_mode == 0) nu = p->nu_g + phi * (p->nu_l - p->nu_g);
+    else nu = (p->zeta_g + phi * (p->zeta_l - p->zeta_g)) / m->rho; /* Sec. 4.4 */
+    m->tau = nu / cs2 + 0.5 * dt;
+    /* isotropic central stencils, Eq. gradient and Eq. laplacian */
+    double gx = 0, gy = 0, lap = 0;
+    for (int i = 1; i < 9; ++i) {
+        double pn = phase_phi_at(s, x + EX9[i], y + EY9[i]);
+        gx += W9[i] * c * EX9[i] * pn / (cs2 * dt);
+        gy += W9[i] * c * EY9[i] * pn / (cs2 * dt);
+        lap += 2.0 * W9[i] * (pn - phi) / (cs2 * dt * dt);
+    }
+    m->gx = gx; m->gy = gy; m->lap = lap;
+    double gn = sqrt(gx * gx + gy * gy);
+    if (gn > p->normal_eps) { m->nx = gx / gn; m->ny = gy / gn; }
+    else { m->nx = 0.0; m->ny = 0.0; }
+    /* chemical potential, Eq. chemical_potential */
+    m->mu = 4.0 * s->beta * phi * (phi - 1.0) * (phi - 0.5) - s->kappa * lap;
+    /* F = F_s + F_b with F_s = mu grad phi */
+    m->Fx = m->mu * gx + p->Fbx;
+    m->Fy = m->mu * gy + p->Fby;
+    double jx = 0, jy = 0, zsum = 0;
+    for (int i = 0; i < 9; ++i) {
+        double zi = s->z[PIDX(s, i, x, y)];
+        jx += c * EX9[i] * zi;
+        jy += c * EY9[i] * zi;
+        if (i > 0) zsum += zi;
+    }
+    /* velocity first (Eq. u_Liang), then pressure (Eq. p_Liang) */
+    m->ux = (jx + 0.5 * dt * m->Fx) / m->rho;
+    m->uy = (jy + 0.5 * dt * m->Fy) / m->rho;
+    double drx = (p->rho_l - p->rho_g) * gx, dry = (p->rho_l - p->rho_g) * gy;
+    double udr = m->ux * drx + m->uy * dry;
+    m->p = cs2 / (1.0 - W9[0]) *
+           (zsum + 0.5 * dt * udr + m->rho * s_liang(0, m->ux, m->uy, c, cs2));
+}
+
+static void phase_compute_phi(orc_phase* s) {
+    int nx = s->p.nx, ny = s->p.ny;
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            double a = 0;
+            for (int i = 0; i < 9; ++i) a += s->h[PIDX(s, i, x, y)]; /* Eq. zero_moment_h */
+            s->phi[(size_t)y * nx + x] = a;
+        }
+}
+
+void orc_phase_macros(const orc_phase* s0, double* phi, double* rho, double* p, double* ux,
+                      double* uy, double* mu) {
+    orc_phase* s = (orc_phase*)s0;
+    int nx = s->p.nx, ny = s->p.ny;
+    phase_compute_phi(s);
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            phase_macro m;
+            phase_node(s, x, y, &m);
+            size_t n = (size_t)y * nx + x;
+            if (phi) phi[n] = m.phi;
+            if (rho) rho[n] = m.rho;
+            if (p) p[n] = m.p;
+            if (ux) ux[n] = m.ux;
+            if (uy) uy[n] = m.uy;
+            if (mu) mu[n] = m.mu;
+        }
+}
+
+static void phase_one_step(orc_phase* s) {
+    const orc_phase_params* p = &s->p;
+    int nx = p->nx, ny = p->ny;
+    size_t N = (size_t)nx * ny;
+    double c = s->c, cs2 = s->cs2, dt = p->dt;
+    phase_compute_phi(s);
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            size_t n = (size_t)y * nx + x;
+            phase_macro m;
+            phase_node(s, x, y, &m);
+            /* time derivative of (phi u) by explicit Euler */
+            double pux = m.phi * m.ux, puy = m.phi * m.uy;
+            double dtx = (pux - s->phiu[n]) / dt, dty = (puy - s->phiu[N + n]) / dt;
+            s->phiu[n] = pux;
+            s->phiu[N + n] = puy;
+            /* interface populations: BGK with source (Eq. eq_lattice_boltzmann_interface,
+             * source_term_interface, heq_liang) */
+            double ax = dtx + cs2 * 4.0 * m.phi * (1.0 - m.phi) * m.nx / p->W;
+            double ay = dty + cs2 * 4.0 * m.phi * (1.0 - m.phi) * m.ny / p->W;
+            for (int i = 0; i < 9; ++i) {
+                double cx = c * EX9[i], cy = c * EY9[i];
+                double heq = m.phi * W9[i] * (1.0 + (cx * m.ux + cy * m.uy) / cs2);
+                double Sh = (1.0 - dt / (2.0 * s->tau_phi)) * W9[i] * (cx * ax + cy * ay) / cs2;
+                double hi = s->h[PIDX(s, i, x, y)];
+                s->hs[PIDX(s, i, x, y)] = hi - dt / s->tau_phi * (hi - heq) + dt * Sh;
+            }
+            /* pressure populations (Eq. eq_lattice_boltzmann_pressure, zeq_liang,
+             * forcing_term_pressure_evolution) */
+            double drx = (p->rho_l - p->rho_g) * m.gx, dry = (p->rho_l - p->rho_g) * m.gy;
+            double z[9], ze[9], Fz[9];
+            for (int i = 0; i < 9; ++i) {
+                double cx = c * EX9[i], cy = c * EY9[i];
+                z[i] = s->z[PIDX(s, i, x, y)];
+                ze[i] = zeq(i, m.p, m.rho, m.ux, m.uy, c, cs2);
+                /* (u grad rho):(c_i c_i) = (c_i.u)(c_i.grad rho) */
+                Fz[i] = W9[i] * ((cx * m.Fx + cy * m.Fy) / cs2 +
+                                 (cx * m.ux + cy * m.uy) * (cx * drx + cy * dry) / cs2);
+            }
+            if (p->z_mrt) {
+                /* dimensional two-phase rates (Sec. 3): 1/dt on rho, e, eps, J_x, J_y;
+                 * w_q2 on q_x (and q_y unless the printed variant is asked for);
+                 * 1/tau on p_xx, p_xy */
+                double wn = 1.0 / m.tau;
+                double wq2 = (3.0 / dt) * (2.0 / dt - wn) / (3.0 / dt - wn);
+                double lam[9] = {1.0 / dt, 1.0 / dt, 1.0 / dt, 1.0 / dt, wq2, 1.0 / dt,
+                                 p->qy_printed ? 1.0 / dt : wq2, wn, wn};
+                double mm[9], me[9], Fm[9], ms[9], out[9];
+                matvec(9, s->Md, z, mm);
+                matvec(9, s->Md, ze, me);
+                matvec(9, s->Md, Fz, Fm);
+                for (int k = 0; k < 9; ++k)
+                    ms[k] = mm[k] - dt * lam[k] * (mm[k] - me[k]) +
+                            dt * (1.0 - 0.5 * dt * lam[k]) * Fm[k];
+                matvec(9, s->Mi, ms, out);
+                for (int i = 0; i < 9; ++i) s->zs[PIDX(s, i, x, y)] = out[i];
+            } else {
+                for (int i = 0; i < 9; ++i)
+                    s->zs[PIDX(s, i, x, y)] = z[i] - dt / m.tau * (z[i] - ze[i]) +
+                                              dt * (1.0 - dt / (2.0 * m.tau)) * Fz[i];
+            }
+        }
+    /* streaming; x periodic, y periodic or halfway bounce-back walls for both
+     * populations (Eq. BB_vel with u_w = 0; no-flux for h) */
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x)
+            for (int i = 0; i < 9; ++i) {
+                int xs = ((x - EX9[i]) % nx + nx) % nx, ys = y - EY9[i];
+                if (p->bc_y == 0) ys = (ys % ny + ny) % ny;
+                if (ys < 0 || ys >= ny) {
+                    s->hn[PIDX(s, i, x, y)] = s->hs[PIDX(s, OPP9[i], x, y)];
+                    s->zn[PIDX(s, i, x, y)] = s->zs[PIDX(s, OPP9[i], x, y)];
+                } else {
+                    s->hn[PIDX(s, i, x, y)] = s->hs[PIDX(s, i, xs, ys)];
+                    s->zn[PIDX(s, i, x, y)] = s->zs[PIDX(s, i, xs, ys)];
+                }
+            }
+    double* t;
+    t = s->h; s->h = s->hn; s->hn = t;
+    t = s->z; s->z = s->zn; s->zn = t;
+}
+
+void orc_phase_step(orc_phase* s, long nsteps) {
+    for (long k = 0; k < nsteps; ++k) phase_one_step(s);
+}
+
+void orc_phase_gradients(const orc_phase* s0, double* gx, double* gy, double* lap) {
+    orc_phase* s = (orc_phase*)s0;
+    int nx = s->p.nx, ny = s->p.ny;
+    phase_compute_phi(s);
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            phase_macro m;
+            phase_node(s, x, y, &m);
+            size_t n = (size_t)y * nx + x;
+            gx[n] = m.gx;
+            gy[n] = m.gy;
+            lap[n] = m.lap;
+        }
+}
+
+void orc_phase_get_state(const orc_phase* s, double* h, double* z, double* phiu) {
+    size_t N = (size_t)s->p.nx * s->p.ny;
+    if (h) memcpy(h, s->h, sizeof(double) * 9 * N);
+    if (z) memcpy(z, s->z, sizeof(double) * 9 * N);
+    if (phiu) memcpy(phiu, s->phiu, sizeof(double) * 2 * N);
+}
+
+void orc_phase_set_state(orc_phase* s, const double* h, const double* z, const double* phiu) {
+    size_t N = (size_t)s->p.nx * s->p.ny;
+    if (h) memcpy(s->h, h, sizeof(double) * 9 * N);
+    if (z) memcpy(s->z, z, sizeof(double) * 9 * N);
+    if (phiu) memcpy(s->phiu, phiu, sizeof(double) * 2 * N);
+}

@@ -1,0 +1,186 @@
+"""Seeded synthetic workloads shaped like the paper's cases (arXiv 2302.04120).
+
+This module holds no lattice-Boltzmann arithmetic.  It only produces SI input
+values (property presets and discretisation choices) and the initial
+macroscopic fields, with numpy's PCG64 generator and a stated seed, so that
+the HIP path and the CPU oracle receive identical inputs.  Every entry states
+which case of the paper it is shaped after.
+
+All arrays are float64 in [ny][nx] layout (x fastest); batched fields are
+[batch][ny][nx].  Parameter dicts use SI units throughout.
+"""
+import math
+
+import numpy as np
+
+# --------------------------------------------------------------------------
+# Property presets (values printed in the paper's property tables)
+# --------------------------------------------------------------------------
+
+#: water at 301 K and 1 atm (Sec. 4.2, property table of the heated channel)
+WATER_301K = dict(rho=996.279, nu=8.382e-7, k=0.611, cp=4180.333, alpha=1.467e-7)
+
+#: the four two-phase systems of the static bubble (Sec. 4.3 property table);
+#: nu in m^2/s, zeta in Pa s, sigma in N/m
+TWO_PHASE_SYSTEMS = {
+    "air_water_25C": dict(rho_g=1.184, rho_l=997.048, nu_g=155.770e-7, nu_l=8.927e-7,
+                          zeta_g=1.845e-5, zeta_l=89.006e-5, sigma=0.072),
+    "sat_water_100C": dict(rho_g=0.598, rho_l=958.349, nu_g=204.493e-7, nu_l=2.938e-7,
+                           zeta_g=1.223e-5, zeta_l=28.158e-5, sigma=0.059),
+    "sat_water_80C": dict(rho_g=0.294, rho_l=971.766, nu_g=392.919e-7, nu_l=3.643e-7,
+                          zeta_g=1.154e-5, zeta_l=35.404e-5, sigma=0.063),
+    "sat_water_25C": dict(rho_g=0.023, rho_l=997.003, nu_g=4204.120e-7, nu_l=8.927e-7,
+                          zeta_g=0.970e-5, zeta_l=89.004e-5, sigma=0.072),
+}
+
+
+def rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def node_centres(n, dx):
+    """Halfway (link-wise) placement: node j sits at (j + 1/2) dx (Sec. 2.1)."""
+    return (np.arange(n) + 0.5) * dx
+
+
+def poiseuille_profile(y, H, u_m):
+    """Developed channel velocity, Eq. velocity_prof."""
+    eta = y / H
+    return 6.0 * u_m * (eta - eta * eta)
+
+
+def developed_temperature_profile(y, H, T_in, q_s, k):
+    """Developed channel temperature under uniform flux, Eq. temp_prof; its
+    constant 0.243 is 17/70 to the printed precision, which makes the
+    mixing-cup mean equal to T_in."""
+    eta = y / H
+    return T_in + q_s * H / k * (-(eta ** 4) + 2 * eta ** 3 - eta + 17.0 / 70.0)
+
+
+def tanh_profile(gamma, W):
+    """Planar equilibrium order parameter, Eq. diffuse_interface."""
+    return 0.5 + 0.5 * np.tanh(2.0 * gamma / W)
+
+
+# --------------------------------------------------------------------------
+# C1: 1D slab with uniform volumetric source (Sec. 4.1 machinery)
+# --------------------------------------------------------------------------
+
+def slab_1d(seed=0, n=101, L=0.1, alpha=1e-5, k=1.0, qvol=1e4, T_wall=300.0, dt=1e-2,
+            noise=0.1):
+    dx = L / (n - 1)  # wet nodes x_i = i dx spanning [0, L]
+    rho_cp = k / alpha
+    T0 = np.full(n, T_wall)
+    T0[1:-1] += rng(seed).uniform(-noise, noise, n - 2)
+    prm = dict(dx=dx, dt=dt, alpha=alpha, rho_cp=rho_cp, qdot=qvol / rho_cp, T0=T_wall,
+               TL=T_wall, k=k, L=L, qvol=qvol)
+    return prm, T0
+
+
+# --------------------------------------------------------------------------
+# C2 / C5: heated plane channel, D2Q9 flow + D2Q5 thermal (Sec. 4.2)
+# --------------------------------------------------------------------------
+
+def channel(nx=800, ny=40, dx=2.5e-5, nu=1e-6, Pr=7.0, Re=50.0, q_s=1e4, T_in=300.0,
+            tau_ratio=0.85, oscillating=False, developed=True, seed=0):
+    """Full channel of height H = ny dx between two heated halfway walls.
+
+    Re is based on the hydraulic diameter 2H; dt follows from tau/dt for the
+    viscosity; the inlet carries the developed velocity and (when
+    ``developed``) the developed temperature profile; the flow field starts
+    either developed everywhere or at rest (``developed=False``: u = 0
+    inside, parabolic inlet).  ``seed`` is unused (the case is deterministic)
+    and kept for a uniform signature.
+    """
+    H = ny * dx
+    L = nx * dx
+    rho = WATER_301K["rho"]
+    rho_cp = rho * WATER_301K["cp"]
+    alpha = nu / Pr
+    k = alpha * rho_cp
+    u_m = Re * nu / (2.0 * H)
+    dt = (tau_ratio - 0.5) * dx * dx / (3.0 * nu)
+    y = node_centres(ny, dx)
+    u_in = poiseuille_profile(y, H, u_m)
+    T_prof = developed_temperature_profile(y, H, T_in, q_s, k) if developed else np.full(ny, T_in)
+    prm = dict(dx=dx, dt=dt, rho_ref=rho, nu=nu, omega_e=1.0 / dt, omega_eps=1.0 / dt,
+               Fx=0.0, Fy=0.0, alpha=alpha, rho_cp=rho_cp, qdot=0.0, T_ref=T_in,
+               flux=np.full(nx, q_s), flux_amp=0.5 if oscillating else 0.0,
+               flux_omega=2.0 * math.pi * u_m / L if oscillating else 0.0,
+               inlet_u=u_in, inlet_T=T_prof, flow_mrt=1, thermal_mrt=1,
+               k=k, H=H, L=L, u_m=u_m, q_s=q_s, T_in=T_in)
+    rho0 = np.full((ny, nx), rho)
+    if developed:
+        ux0 = np.repeat(u_in[:, None], nx, axis=1)
+    else:
+        ux0 = np.zeros((ny, nx))
+    uy0 = np.zeros((ny, nx))
+    T0 = np.repeat(T_prof[:, None], nx, axis=1)
+    return prm, dict(rho=rho0, ux=ux0, uy=uy0, T=T0)
+
+
+def adjoint_channel(nx=1600, ny=80, dx=1.25e-5, **kw):
+    """C5: the C2 channel at half the spacing, flow starting from rest."""
+    return channel(nx=nx, ny=ny, dx=dx, developed=False, **kw)
+
+
+# --------------------------------------------------------------------------
+# C3: stationary bubble (Sec. 4.3)
+# --------------------------------------------------------------------------
+
+def bubble(n=256, radii=(20, 30, 40, 50), seed=0, dx=5e-6, dt=1e-7, W_nodes=4.0, M=1e-5,
+           rho_l=1000.0, rho_g=0.0231, nu_l=8.927e-7, nu_g=4.20412e-4, sigma=0.07,
+           batch=None):
+    """Periodic n x n cell with one gas bubble (phi = 0 inside), centre jittered
+    by U(-1/2, 1/2) nodes per axis; one replica per radius (cycled when
+    ``batch`` exceeds the number of radii).  p = 0 and u = 0 initially."""
+    if batch is None:
+        batch = len(radii)
+    g = rng(seed)
+    x = node_centres(n, dx)
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    W = W_nodes * dx
+    phi = np.zeros((batch, n, n))
+    centres = []
+    for b in range(batch):
+        R = radii[b % len(radii)] * dx
+        jx, jy = g.uniform(-0.5, 0.5, 2)
+        xc, yc = (n / 2 + jx) * dx, (n / 2 + jy) * dx
+        r = np.sqrt((X - xc) ** 2 + (Y - yc) ** 2)
+        phi[b] = tanh_profile(r - R, W)  # gas inside the bubble
+        centres.append((xc, yc, R))
+    prm = dict(dx=dx, dt=dt, rho_l=rho_l, rho_g=rho_g, nu_l=nu_l, nu_g=nu_g,
+               zeta_l=nu_l * rho_l, zeta_g=nu_g * rho_g, visc_mode=0, sigma=sigma, W=W, M=M,
+               Fx=0.0, Fy=0.0, z_mrt=1, qy_printed=0)
+    zeros = np.zeros_like(phi)
+    return prm, dict(phi=phi, p=zeros.copy(), ux=zeros.copy(), uy=zeros.copy()), centres
+
+
+# --------------------------------------------------------------------------
+# C4: layered two-phase Poiseuille flow (Sec. 4.4)
+# --------------------------------------------------------------------------
+
+def layered(nx=4, ny=512, seed=0, dx=1.25e-6, dt=1.25e-7, W_nodes=4.0, M=1e-5,
+            rho_l=1000.0, rho_g=0.0231, nu_l=8.927e-7, nu_g=4.20412e-4, sigma=0.07,
+            u_c=1e-4, batch=1):
+    """Liquid below the interface at y = H/2 + U(-1/2, 1/2) dx, gas above;
+    halfway walls at y = 0 and y = H; driving force u_c (zeta_l + zeta_g) / h^2
+    with h = H/2 (so that u_c is the interface speed of the sharp solution)."""
+    g = rng(seed)
+    H = ny * dx
+    h = 0.5 * H
+    zeta_l, zeta_g = nu_l * rho_l, nu_g * rho_g
+    Fx = u_c * (zeta_l + zeta_g) / (h * h)
+    W = W_nodes * dx
+    y = node_centres(ny, dx)
+    phi = np.zeros((batch, ny, nx))
+    offsets = []
+    for b in range(batch):
+        yi = h + g.uniform(-0.5, 0.5) * dx
+        phi[b] = tanh_profile(yi - y, W)[:, None]  # liquid (phi = 1) below
+        offsets.append(yi)
+    prm = dict(dx=dx, dt=dt, rho_l=rho_l, rho_g=rho_g, nu_l=nu_l, nu_g=nu_g, zeta_l=zeta_l,
+               zeta_g=zeta_g, visc_mode=1, sigma=sigma, W=W, M=M, Fx=Fx, Fy=0.0, z_mrt=1,
+               qy_printed=0, H=H, h=h, u_c=u_c)
+    zeros = np.zeros_like(phi)
+    return prm, dict(phi=phi, p=zeros.copy(), ux=zeros.copy(), uy=zeros.copy()), offsets
