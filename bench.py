@@ -1,0 +1,151 @@
+"""Throughput benchmark of the dimensional-LBM hot path on one MI355X.
+
+Workload: the stationary-bubble case (D2Q9 MRT pressure populations + D2Q9
+conservative Allen-Cahn populations, 256 x 256 periodic cell, liquid/gas
+density ratio ~43 300, viscosity ratio ~470, radii cycling over 20/30/40/50
+nodes with seeded centre jitter) run as a batch of independent replicas, FP32
+deviation storage.  One step = one fused stream-collide launch over every
+replica.  Inputs are synthetic and resident in HBM before timing starts.
+
+Prints ONE JSON line (see the keys below).  ``--gpus`` above 1 is refused:
+this benchmark measures one GPU.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per lattice update (each population read once and written
+# once): z 9 + h 9 + low part of h_0 + (phi u) 2, read + write
+BYTES_PER_LU = {"fp32": (9 + 9 + 1 + 2) * 4 * 2, "fp64": (9 + 9 + 2) * 8 * 2}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_gpu(batch, steps, warmup, prec, n=256):
+    import torch
+    from paper_2302_04120_amd import lbm, workloads as WL
+    prm, ini, _ = WL.bubble(n=n, batch=batch, seed=0)
+    L = lbm.Lattice("phase", n, n, batch=batch, prec=prec)
+    L.set_params(prm)
+    L.init(ini["p"], ini["ux"], ini["uy"], None, ini["phi"])
+    del ini
+    L.step(warmup)
+    stream = L.stream
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    t0 = time.perf_counter()
+    L.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = e0.elapsed_time(e1)
+    red = L.reduce(("phase", "nonfinite"))
+    if red["nonfinite"].sum() != 0:
+        raise RuntimeError("non-finite populations after the timed steps")
+    nodes = batch * n * n
+    return dict(wall=wall, ev_ms=ev_ms, nodes=nodes, kernel_ms=ev_ms / steps,
+                bytes_gb=L.bytes / 1e9)
+
+
+def cpu_baseline(seconds=12.0):
+    """The FP64 oracle on one 256 x 256 replica of the same workload."""
+    import oracle as O
+    from paper_2302_04120_amd import workloads as WL
+    prm, ini, _ = WL.bubble(n=256, batch=1, seed=0)
+    ph = O.Phase(256, 256, prm)
+    ph.init(ini["phi"][0], ini["p"][0], ini["ux"][0], ini["uy"][0])
+    t0 = time.perf_counter()
+    steps = 0
+    while time.perf_counter() - t0 < seconds:
+        ph.step(10)
+        steps += 10
+    dt = time.perf_counter() - t0
+    return dict(value=256 * 256 * steps / dt / 1e6, unit="MLUPS", cores=1, kind="oracle",
+                sample="one 256x256 replica of the bubble workload, %d steps, FP64, single thread"
+                       % steps)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--batch", type=int, default=1024, help="256x256 replicas per step")
+    ap.add_argument("--prec", default="fp32", choices=("fp32", "fp64"))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the FP64 and batch-4 legs")
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_phase_step.json"))
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only; --gpus %d is not supported" % args.gpus,
+              file=sys.stderr)
+        return 2
+    log("bench: phase workload batch=%d steps=%d warmup=%d prec=%s" %
+        (args.batch, args.steps, args.warmup, args.prec))
+    r = run_gpu(args.batch, args.steps, args.warmup, args.prec)
+    mlups = r["nodes"] * args.steps / r["wall"] / 1e6
+    bpl = BYTES_PER_LU[args.prec]
+    achieved = bpl * r["nodes"] / (r["kernel_ms"] * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(args.traffic):
+        with open(args.traffic) as f:
+            tr = json.load(f)
+        if tr.get("batch") == args.batch and tr.get("prec") == args.prec:
+            traffic = tr.get("bytes_per_launch")
+    extras = {}
+    if not args.no_extras:
+        log("bench: FP64 leg")
+        r64 = run_gpu(max(1, args.batch // 4), max(20, args.steps // 4), 5, "fp64")
+        extras["fp64_mlups"] = r64["nodes"] * max(20, args.steps // 4) / r64["wall"] / 1e6
+        extras["fp64_hbm_frac"] = (BYTES_PER_LU["fp64"] * r64["nodes"] / (r64["kernel_ms"] * 1e-3)
+                                   / 1e9 / HBM_PEAK_GBS)
+        log("bench: paper-sized leg (4 replicas)")
+        r4 = run_gpu(4, 1000, 50, args.prec)
+        extras["paper_config_batch4_mlups"] = r4["nodes"] * 1000 / r4["wall"] / 1e6
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("bench: CPU oracle baseline")
+        cpu = cpu_baseline()
+    line = {
+        "metric": "MLUPS (D2Q9 MRT + Allen-Cahn) FP32-dev vs FP64, % HBM roofline; adjoint/fwd cost",
+        "value": mlups,
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["wall"] * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.prec == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": "stationary bubble, D2Q9 MRT z + D2Q9 Allen-Cahn h, 256x256 "
+                               "periodic cell, rho_l/rho_g=43290, nu_g/nu_l=471, radii 20/30/40/50 "
+                               "nodes, %d replicas per step" % args.batch,
+                   "nodes_per_step": r["nodes"], "storage": args.prec + "-deviation"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "bytes_per_lu": bpl, "kernel": "k_phase<float,float,false>",
+                     "kernel_ms": r["kernel_ms"]},
+        "cpu_baseline": cpu,
+        "adjoint_over_forward": None,
+    }
+    line.update(extras)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

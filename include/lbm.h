@@ -1,0 +1,202 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) dimensional lattice Boltzmann library.
+ *
+ * The library advances the dimensional LBM of arXiv 2302.04120 -- the lattice
+ * Boltzmann equation solved directly in SI units with dx, dt and c = dx/dt in
+ * metres and seconds and every property physical (Sec. 3) -- with hand-written
+ * HIP kernels.  Models (Sec. 2):
+ *   LBM_D2Q9_D2Q5  : D2Q9 momentum (BGK or dimensional MRT, Guo forcing) plus
+ *                    an optional D2Q5 temperature field with heat source
+ *                    (Sec. 2.1, 2.2); halfway walls, velocity inlet, pressure
+ *                    outlet, flux walls (Eq. BB_vel, anti_BB_vel, anti_BB_T,
+ *                    BB_T and the first-order outlet extrapolation).
+ *   LBM_D2Q9_PHASE : conservative Allen-Cahn order parameter h_i and pressure-
+ *                    evolution populations z_i (Sec. 2.3), MRT for z_i in the
+ *                    dimensional form of Sec. 3, BGK for h_i.
+ *   LBM_D1Q2/D1Q3  : 1D thermal BGK with source and wet-node Dirichlet ends
+ *                    (Sec. 2.2, App. B).
+ *
+ * Conventions
+ *   - Every host number is an SI double.  No lattice units cross this ABI.
+ *   - Host arrays are float64, layout [batch][ny][nx] with x fastest, and are
+ *     copied before the call returns; the caller keeps ownership.
+ *   - Device memory is owned by the caller: lbm_query_bytes gives the size of
+ *     the one device buffer (desc.dev_buf) the library works in.  The library
+ *     never allocates device memory itself.  The buffer and the HIP stream
+ *     (desc.hip_stream) must stay valid until lbm_destroy.
+ *   - All device work is enqueued on desc.hip_stream.  Calls that return host
+ *     data synchronise that stream; lbm_step only enqueues.
+ *   - Every call returns an lbm_status; on error the context is unchanged and
+ *     lbm_last_error() describes the cause.  Argument checks happen before
+ *     any device work.  A context is used by one host thread at a time.
+ *   - Precision LBM_FP32_DEV stores populations in FP32 as deviations from
+ *     w_i * X_ref (X_ref = rho_ref for momentum, T_ref for temperature, 0 for
+ *     z_i and h_i) and collides in FP32; the rest population h_0 is kept as an
+ *     FP32 hi/lo pair that carries the node's exact order-parameter balance.
+ *     LBM_FP64 stores and collides in FP64.  Reductions are FP64 in both.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define LBM_API __attribute__((visibility("default")))
+#else
+#define LBM_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx;
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_E_ARG = -1,         /* invalid argument, size or combination             */
+    LBM_E_TAU = -2,         /* a relaxation time is not above dt/2 (Sec. 4 text on stability) */
+    LBM_E_DEVICE = -3,      /* a HIP call failed                                  */
+    LBM_E_STATE = -4,       /* wrong call order or malformed state blob           */
+    LBM_E_NONFINITE = -5,   /* a NaN/Inf was found in the populations             */
+    LBM_E_UNSUPPORTED = -6  /* combination not implemented                        */
+} lbm_status;
+
+enum { LBM_D1Q2 = 1, LBM_D1Q3 = 2, LBM_D2Q9_D2Q5 = 3, LBM_D2Q9_PHASE = 4 };
+enum { LBM_FP32_DEV = 0, LBM_FP64 = 1 };
+/* boundary kinds per side, order x-, x+, y-, y+ */
+enum {
+    LBM_BC_PERIODIC = 0,   /* Sec. 2.1, last paragraph                                */
+    LBM_BC_WALL = 1,       /* halfway bounce-back (Eq. BB_vel, u_w = 0); thermal flux Eq. BB_T */
+    LBM_BC_VEL_INLET = 2,  /* x- only: Eq. BB_vel with the inlet profile; thermal Eq. anti_BB_T */
+    LBM_BC_P_OUTLET = 3,   /* x+ only: Eq. anti_BB_vel; thermal first-order extrapolation */
+    LBM_BC_DIRICHLET = 4   /* 1D ends: wet-node fixed temperature (Eq. BCs_1D_advection_diffusion) */
+};
+enum { LBM_BGK = 0, LBM_MRT = 1 };
+/* desc.flags for LBM_D2Q9_D2Q5 */
+enum { LBM_FLAG_FLOW = 1, LBM_FLAG_THERMAL = 2 };
+
+typedef struct {
+    int lattice;            /* LBM_D1Q2 | LBM_D1Q3 | LBM_D2Q9_D2Q5 | LBM_D2Q9_PHASE        */
+    int nx, ny, batch;      /* grid per replica (1D: ny = 1) and number of replicas         */
+    int prec;               /* LBM_FP32_DEV | LBM_FP64 (1D: LBM_FP64 only)                  */
+    int bc[4];              /* x-, x+, y-, y+ ; see the enum above                           */
+    int flags;              /* LBM_D2Q9_D2Q5: LBM_FLAG_FLOW | LBM_FLAG_THERMAL               */
+    void* hip_stream;       /* hipStream_t the library enqueues on (NULL = default stream)  */
+    void* dev_buf;          /* caller-owned device memory of at least lbm_query_bytes()     */
+    size_t dev_buf_bytes;
+} lbm_desc;
+
+typedef struct {
+    double dx, dt;          /* m, s */
+    /* momentum (Sec. 2.1, Sec. 3) */
+    int flow_collision;     /* LBM_BGK | LBM_MRT                                            */
+    double rho_ref;         /* kg/m^3: reference density; also rho_w of inlet/outlet rules */
+    double nu;              /* m^2/s  -> tau = nu / c_s^2 + dt/2 (Eq. eq_kinematic_viscosity) */
+    double omega_e, omega_eps; /* 1/s, free MRT rates of e and eps (0 -> 1/dt)              */
+    double Fb[2];           /* N/m^3 body force                                             */
+    /* temperature (Sec. 2.2) */
+    int thermal_collision;  /* LBM_BGK | LBM_MRT (two-rate: j at 1/tau_T, e and p_xx at 1/dt) */
+    double T_ref;           /* K: deviation reference and datum of the advective equilibrium */
+    double alpha;           /* m^2/s  -> tau_T = alpha / c_s^2 + dt/2                       */
+    double rho_cp;          /* J/(m^3 K)                                                    */
+    double qvol;            /* W/m^3 volumetric source; qdot = qvol / rho_cp (Eq. forcing_term_g) */
+    const double* flux;     /* [nx] W/m^2 wall heat flux into the fluid, both walls (NULL = 0) */
+    double flux_amp, flux_omega; /* q''(x,t) = flux[x] (1 + amp sin(omega t)), t = step * dt  */
+    const double* inlet_u;  /* [ny] m/s inlet velocity profile (NULL = 0)                   */
+    const double* inlet_T;  /* [ny] K inlet temperature (NULL = T_ref)                       */
+    double T_wall[2];       /* K: 1D Dirichlet temperatures at x- and x+                    */
+    /* two-phase (Sec. 2.3, Sec. 4.4) */
+    double rho_l, rho_g;    /* kg/m^3 */
+    double nu_l, nu_g;      /* m^2/s, used when visc_mode = 0: nu = nu_g + phi (nu_l - nu_g) */
+    double zeta_l, zeta_g;  /* Pa s, used when visc_mode = 1: nu = zeta(phi) / rho(phi)       */
+    int visc_mode;
+    double sigma, W;        /* N/m, m: beta = 12 sigma / W, kappa = 3 sigma W / 2           */
+    double mobility;        /* m^2/s -> tau_phi = M / c_s^2 + dt/2                          */
+    int z_collision;        /* LBM_BGK | LBM_MRT                                             */
+    int qy_printed;         /* 0: omega_q2 on both q_x and q_y; 1: on q_x only (as printed)  */
+    double normal_eps;      /* 1/m: n = 0 where |grad phi| <= normal_eps (<= 0: default)     */
+} lbm_params_si;
+
+/* Size in bytes of the device buffer a context with this description needs.
+ * Errors: LBM_E_ARG, LBM_E_UNSUPPORTED. */
+LBM_API lbm_status lbm_query_bytes(const lbm_desc* desc, size_t* bytes);
+
+/* Create a context on the current HIP device.  desc->dev_buf must hold at
+ * least lbm_query_bytes() bytes.  *out is set only on success. */
+LBM_API lbm_status lbm_create(const lbm_desc* desc, lbm_ctx** out);
+
+/* Release host resources; enqueued work is not waited for (synchronise the
+ * stream first if the buffer is to be reused).  NULL is a no-op. */
+LBM_API void lbm_destroy(lbm_ctx* ctx);
+
+/* Compile SI parameters into relaxation rates and kernel constants (Sec. 3:
+ * c = dx/dt, c_s^2 = c^2/3 (D1Q2: c^2), tau from nu, tau_T from alpha, tau_phi
+ * from M, the dimensional MRT rates, beta, kappa, qdot).  Returns LBM_E_TAU if
+ * any relaxation time is not above dt/2, LBM_E_ARG for non-positive dx, dt or
+ * densities.  Copies the flux / inlet arrays to the device. */
+LBM_API lbm_status lbm_set_params_SI(lbm_ctx* ctx, const lbm_params_si* p);
+
+/* Set the populations to the equilibria of the given macroscopic fields
+ * (host float64 [batch][ny][nx], SI).  rho_or_p: density (D2Q9_D2Q5, ignored
+ * otherwise) or pressure in Pa (PHASE); ux, uy: m/s (NULL = 0); T: K
+ * (thermal and 1D); phi: order parameter (PHASE).  Also resets the step
+ * counter and, for PHASE, sets (phi u) of the previous step to phi u.
+ * Requires lbm_set_params_SI first. */
+LBM_API lbm_status lbm_init_fields(lbm_ctx* ctx, const double* rho_or_p, const double* ux,
+                           const double* uy, const double* T, const double* phi);
+
+/* Enqueue n time steps (collide + stream + boundary rules, Eq.
+ * eq_lattice_boltzmann_geral).  Asynchronous: a non-finite state is reported
+ * by lbm_reduce. */
+LBM_API lbm_status lbm_step(lbm_ctx* ctx, int n);
+
+/* Macroscopic fields of the current state, evaluated in FP64 from the stored
+ * populations.  mask selects fields; out receives them in bit order, each
+ * [batch][ny][nx] float64:
+ *   LBM_M_RHO (density), LBM_M_P (PHASE pressure, Pa), LBM_M_UX, LBM_M_UY (m/s),
+ *   LBM_M_T (K), LBM_M_PHI, LBM_M_MU (chemical potential, Pa).
+ * out_on_device != 0: out is a device pointer (written on the stream,
+ * asynchronous); otherwise a host pointer (synchronous). */
+enum { LBM_M_RHO = 1, LBM_M_P = 2, LBM_M_UX = 4, LBM_M_UY = 8, LBM_M_T = 16,
+       LBM_M_PHI = 32, LBM_M_MU = 64 };
+LBM_API lbm_status lbm_macros(lbm_ctx* ctx, unsigned mask, double* out, int out_on_device);
+
+/* FP64 global sums per replica, deterministic (fixed-order two-pass
+ * reduction).  out receives, per selected bit in bit order, batch values:
+ *   LBM_R_MASS (sum of rho, kg/m^3 * nodes), LBM_R_PHASE (sum of phi),
+ *   LBM_R_ENERGY (sum of T, K * nodes), LBM_R_NONFINITE (count of NaN/Inf
+ *   populations).  Synchronous.  Returns LBM_E_NONFINITE when any population
+ *   is not finite (out is still filled). */
+enum { LBM_R_MASS = 1, LBM_R_PHASE = 2, LBM_R_ENERGY = 4, LBM_R_NONFINITE = 8 };
+LBM_API lbm_status lbm_reduce(lbm_ctx* ctx, unsigned mask, double* out);
+
+/* Heated-channel diagnostics of replica 0 (LBM_D2Q9_D2Q5 with flow and
+ * thermal): per column the mixing-cup temperature Tb = sum(u T)/sum(u), the
+ * wall temperature Tw = mean of the two wall-adjacent nodes + q'' dx/(2k), and
+ * Nu = q'' 2H / (k (Tw - Tb)), k = rho_cp alpha, H = ny dx (the paper reports
+ * Nu without a formula; this is the reading used).  Any output may be NULL;
+ * nu_mean is the mean of Nu over columns x >= x_dev; T_out = Tb[nx-1].
+ * Synchronous. */
+LBM_API lbm_status lbm_nusselt(lbm_ctx* ctx, int x_dev, double* Tb, double* Tw, double* Nu,
+                       double* nu_mean, double* T_out);
+
+/* Number of steps taken since lbm_init_fields / lbm_load_state. */
+LBM_API long long lbm_time(const lbm_ctx* ctx);
+
+/* Serialise the state (populations, (phi u), step counter, a hash of the
+ * description and parameters) to host memory.  Call with host = NULL to get
+ * the size in *bytes.  Synchronous. */
+LBM_API lbm_status lbm_save_state(lbm_ctx* ctx, void* host, size_t* bytes);
+
+/* Restore a state written by lbm_save_state for an identical description
+ * and parameters; LBM_E_STATE on size, magic or hash mismatch. */
+LBM_API lbm_status lbm_load_state(lbm_ctx* ctx, const void* host, size_t bytes);
+
+/* Text of the last error on this context (never NULL). */
+LBM_API const char* lbm_last_error(const lbm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

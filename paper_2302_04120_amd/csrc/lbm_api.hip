@@ -1,0 +1,588 @@
+// C-ABI layer of liblbm: argument checks, the SI parameter compiler, the
+// layout of the caller-owned device buffer, and the enqueue loops.  No device
+// memory is allocated here; every kernel runs on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "lbm_internal.h"
+
+using namespace lbm;
+
+namespace {
+
+constexpr uint32_t kMagic = 0x534d424cu;  // "LBMS"
+constexpr uint32_t kVersion = 1;
+
+struct Layout {
+    long long N = 0, P = 0;
+    int npop = 0;
+    size_t es = 0;
+    size_t offA = 0, offB = 0, offPhiu = 0, offAux = 0, offStage = 0, offPartial = 0;
+    size_t offSmall = 0, total = 0;
+};
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+lbm_status check_desc(const lbm_desc* d, Layout* L, std::string* err) {
+    auto fail = [&](lbm_status st, const char* m) {
+        if (err) *err = m;
+        return st;
+    };
+    if (!d) return fail(LBM_E_ARG, "desc is NULL");
+    if (d->nx < 1 || d->ny < 1 || d->batch < 1) return fail(LBM_E_ARG, "nx, ny, batch must be >= 1");
+    if (d->prec != LBM_FP32_DEV && d->prec != LBM_FP64) return fail(LBM_E_ARG, "unknown precision");
+    if (d->batch > 65535 || d->ny > 65535 * 4) return fail(LBM_E_ARG, "grid too large for the launch geometry");
+    for (int s = 0; s < 4; ++s)
+        if (d->bc[s] < LBM_BC_PERIODIC || d->bc[s] > LBM_BC_DIRICHLET) return fail(LBM_E_ARG, "unknown boundary kind");
+    Layout l;
+    l.N = (long long)d->batch * d->nx * d->ny;
+    l.P = (l.N + 63) / 64 * 64;
+    l.es = d->prec == LBM_FP64 ? 8 : 4;
+    switch (d->lattice) {
+        case LBM_D1Q2:
+        case LBM_D1Q3:
+            if (d->prec != LBM_FP64) return fail(LBM_E_UNSUPPORTED, "1D lattices run in FP64 only");
+            if (d->ny != 1 || d->batch != 1) return fail(LBM_E_ARG, "1D lattices need ny = batch = 1");
+            if (d->nx < 3 || d->nx > 1024) return fail(LBM_E_UNSUPPORTED, "1D lattices need 3 <= nx <= 1024");
+            if (d->bc[0] != LBM_BC_DIRICHLET || d->bc[1] != LBM_BC_DIRICHLET)
+                return fail(LBM_E_UNSUPPORTED, "1D lattices need Dirichlet ends");
+            l.npop = d->lattice == LBM_D1Q2 ? 2 : 3;
+            l.P = d->nx;
+            break;
+        case LBM_D2Q9_D2Q5: {
+            const bool xp = d->bc[0] == LBM_BC_PERIODIC && d->bc[1] == LBM_BC_PERIODIC;
+            const bool xio = d->bc[0] == LBM_BC_VEL_INLET && d->bc[1] == LBM_BC_P_OUTLET;
+            const bool yp = d->bc[2] == LBM_BC_PERIODIC && d->bc[3] == LBM_BC_PERIODIC;
+            const bool yw = d->bc[2] == LBM_BC_WALL && d->bc[3] == LBM_BC_WALL;
+            if (!(xp || xio) || !(yp || yw))
+                return fail(LBM_E_UNSUPPORTED, "D2Q9_D2Q5: x periodic or inlet/outlet, y periodic or walls");
+            if (xio && d->nx < 2) return fail(LBM_E_ARG, "inlet/outlet needs nx >= 2");
+            if ((d->flags & ~(LBM_FLAG_FLOW | LBM_FLAG_THERMAL)) != 0 || d->flags == 0)
+                return fail(LBM_E_ARG, "flags must be a non-empty subset of FLOW | THERMAL");
+            l.npop = 9 + ((d->flags & LBM_FLAG_THERMAL) ? 5 : 0);
+            break;
+        }
+        case LBM_D2Q9_PHASE: {
+            const bool xp = d->bc[0] == LBM_BC_PERIODIC && d->bc[1] == LBM_BC_PERIODIC;
+            const bool yp = d->bc[2] == LBM_BC_PERIODIC && d->bc[3] == LBM_BC_PERIODIC;
+            const bool yw = d->bc[2] == LBM_BC_WALL && d->bc[3] == LBM_BC_WALL;
+            if (!xp || !(yp || yw)) return fail(LBM_E_UNSUPPORTED, "PHASE: x periodic, y periodic or walls");
+            l.npop = 18 + (d->prec == LBM_FP32_DEV ? 1 : 0);
+            break;
+        }
+        default:
+            return fail(LBM_E_ARG, "unknown lattice");
+    }
+    size_t off = 0;
+    const size_t popbytes = align256((size_t)l.npop * l.P * l.es);
+    l.offA = off; off += popbytes;
+    l.offB = off; off += popbytes;
+    l.offPhiu = off;
+    if (d->lattice == LBM_D2Q9_PHASE) off += align256(2 * (size_t)l.P * l.es);
+    l.offAux = off; off += align256((size_t)(d->nx + 2 * d->ny) * l.es);
+    l.offStage = off; off += align256(7 * (size_t)l.P * sizeof(double));
+    l.offPartial = off; off += align256((size_t)d->batch * 4 * kRedBlocks * sizeof(double));
+    l.offSmall = off; off += align256((size_t)(3 * d->nx + 64 + 4 * d->batch) * sizeof(double));
+    l.total = off;
+    *L = l;
+    return LBM_OK;
+}
+
+lbm_status set_err(lbm_ctx* c, lbm_status st, const std::string& m) {
+    c->err = m;
+    return st;
+}
+
+lbm_status hip_fail(lbm_ctx* c, hipError_t e, const char* where) {
+    return set_err(c, LBM_E_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+        else prev = -1;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+uint64_t fnv(uint64_t h, const void* p, size_t n) {
+    const unsigned char* b = (const unsigned char*)p;
+    for (size_t i = 0; i < n; ++i) {
+        h ^= b[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+char* bufA(lbm_ctx* c) { return c->cur == 0 ? c->popA : c->popB; }
+char* bufB(lbm_ctx* c) { return c->cur == 0 ? c->popB : c->popA; }
+
+template <typename S>
+S* aux_qw(lbm_ctx* c) { return (S*)c->aux; }
+template <typename S>
+S* aux_uin(lbm_ctx* c) { return (S*)c->aux + c->desc.nx; }
+template <typename S>
+S* aux_tin(lbm_ctx* c) { return (S*)c->aux + c->desc.nx + c->desc.ny; }
+
+double flux_mod(const lbm_ctx* c) {
+    return 1.0 + c->flux_amp * std::sin(c->flux_omega * (double)c->t * c->dt);
+}
+
+template <typename S>
+hipError_t step_once(lbm_ctx* c) {
+    const int lat = c->desc.lattice;
+    S* a = (S*)bufA(c);
+    S* b = (S*)bufB(c);
+    const long long P = c->P;
+    if (lat == LBM_D2Q9_D2Q5) {
+        const bool th = c->ck.thermal;
+        return launch_chan_step<S>(c->ck, a, b, th ? a + 9 * P : nullptr, th ? b + 9 * P : nullptr,
+                                   aux_qw<S>(c), aux_uin<S>(c), aux_tin<S>(c), flux_mod(c),
+                                   c->stream);
+    }
+    return launch_phase_step<S>(c->pk, a, b, a + 9 * P, b + 9 * P, (S*)c->phiu, c->stream);
+}
+
+template <typename S>
+hipError_t upload_aux(lbm_ctx* c, const lbm_params_si* p) {
+    const int nx = c->desc.nx, ny = c->desc.ny;
+    std::vector<S> h(nx + 2 * ny);
+    const double cc = p->dx / p->dt;
+    for (int x = 0; x < nx; ++x)
+        h[x] = S(p->flux ? p->flux[x] * p->dt / (p->dx * p->rho_cp) : 0.0);
+    for (int y = 0; y < ny; ++y) {
+        h[nx + y] = S(p->inlet_u ? p->inlet_u[y] / cc : 0.0);
+        h[nx + ny + y] = S(p->inlet_T ? p->inlet_T[y] - p->T_ref : 0.0);
+    }
+    hipError_t e = hipMemcpyAsync(c->aux, h.data(), h.size() * sizeof(S), hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(c->stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_query_bytes(const lbm_desc* desc, size_t* bytes) {
+    if (!bytes) return LBM_E_ARG;
+    Layout L;
+    lbm_status st = check_desc(desc, &L, nullptr);
+    if (st != LBM_OK) return st;
+    *bytes = L.total;
+    return LBM_OK;
+}
+
+lbm_status lbm_create(const lbm_desc* desc, lbm_ctx** out) {
+    if (!out) return LBM_E_ARG;
+    Layout L;
+    lbm_status st = check_desc(desc, &L, nullptr);
+    if (st != LBM_OK) return st;
+    if (!desc->dev_buf || desc->dev_buf_bytes < L.total) return LBM_E_ARG;
+    if (((uintptr_t)desc->dev_buf & 255) != 0) return LBM_E_ARG;  // 256-byte aligned planes
+    lbm_ctx* c = new (std::nothrow) lbm_ctx();
+    if (!c) return LBM_E_ARG;
+    c->desc = *desc;
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return LBM_E_DEVICE;
+    }
+    c->stream = (hipStream_t)desc->hip_stream;
+    c->N = L.N;
+    c->P = L.P;
+    c->npop = L.npop;
+    c->esize = L.es;
+    char* base = (char*)desc->dev_buf;
+    c->popA = base + L.offA;
+    c->popB = base + L.offB;
+    c->phiu = base + L.offPhiu;
+    c->aux = base + L.offAux;
+    c->staging = (double*)(base + L.offStage);
+    c->partial = (double*)(base + L.offPartial);
+    c->small = (double*)(base + L.offSmall);
+    c->cur = 0;
+    c->t = 0;
+    c->has_params = c->has_state = false;
+    *out = c;
+    return LBM_OK;
+}
+
+void lbm_destroy(lbm_ctx* ctx) { delete ctx; }
+
+const char* lbm_last_error(const lbm_ctx* ctx) { return ctx ? ctx->err.c_str() : "NULL context"; }
+
+long long lbm_time(const lbm_ctx* ctx) { return ctx ? ctx->t : -1; }
+
+lbm_status lbm_set_params_SI(lbm_ctx* c, const lbm_params_si* p) {
+    if (!c) return LBM_E_ARG;
+    if (!p) return set_err(c, LBM_E_ARG, "params is NULL");
+    if (!(p->dx > 0) || !(p->dt > 0)) return set_err(c, LBM_E_ARG, "dx and dt must be positive");
+    const lbm_desc& d = c->desc;
+    const double dx = p->dx, dt = p->dt, cc = dx / dt;
+    ChanK ck{};
+    PhaseK pk{};
+    D1K dk{};
+    if (d.lattice == LBM_D1Q2 || d.lattice == LBM_D1Q3) {
+        const double cs2 = d.lattice == LBM_D1Q2 ? cc * cc : cc * cc / 3.0;
+        if (!(p->rho_cp > 0)) return set_err(c, LBM_E_ARG, "rho_cp must be positive");
+        if (!(p->alpha > 0)) return set_err(c, LBM_E_TAU, "tau_T not above dt/2 (alpha <= 0)");
+        const double tau = p->alpha / cs2 + 0.5 * dt;
+        dk.n = d.nx;
+        dk.q = d.lattice == LBM_D1Q2 ? 2 : 3;
+        dk.w_tau = dt / tau;
+        dk.qdt = p->qvol / p->rho_cp * dt;
+        dk.ufac = 0.0;
+        dk.T0 = p->T_wall[0];
+        dk.TL = p->T_wall[1];
+    } else if (d.lattice == LBM_D2Q9_D2Q5) {
+        const double cs2 = cc * cc / 3.0;
+        ck.nx = d.nx; ck.ny = d.ny; ck.batch = d.batch; ck.P = c->P;
+        ck.bcx = d.bc[0] == LBM_BC_VEL_INLET ? 1 : 0;
+        ck.bcy = d.bc[2] == LBM_BC_WALL ? 1 : 0;
+        ck.flow = (d.flags & LBM_FLAG_FLOW) ? 1 : 0;
+        ck.thermal = (d.flags & LBM_FLAG_THERMAL) ? 1 : 0;
+        ck.flow_mrt = p->flow_collision == LBM_MRT;
+        ck.thermal_mrt = p->thermal_collision == LBM_MRT;
+        if (!(p->rho_ref > 0)) return set_err(c, LBM_E_ARG, "rho_ref must be positive");
+        ck.rho_ref = p->rho_ref;
+        if (ck.flow) {
+            if (!(p->nu > 0)) return set_err(c, LBM_E_TAU, "tau not above dt/2 (nu <= 0)");
+            const double tau = p->nu / cs2 + 0.5 * dt;  // Eq. eq_kinematic_viscosity
+            const double wn = dt / tau;
+            // dimensional w_q = (3/dt)(2/dt - w_nu)/(3/dt - w_nu) (Sec. 3), times dt
+            const double wq = 3.0 * (2.0 - wn) / (3.0 - wn);
+            const double we = p->omega_e > 0 ? p->omega_e * dt : 1.0;
+            const double wpe = p->omega_eps > 0 ? p->omega_eps * dt : 1.0;
+            const double Lf[9] = {0, we, wpe, 0, wq, 0, wq, wn, wn};
+            for (int q = 0; q < 9; ++q) ck.Lf[q] = Lf[q];
+        }
+        ck.Ft[0] = p->Fb[0] * dt * dt / dx;
+        ck.Ft[1] = p->Fb[1] * dt * dt / dx;
+        if (ck.thermal) {
+            if (!(p->alpha > 0)) return set_err(c, LBM_E_TAU, "tau_T not above dt/2 (alpha <= 0)");
+            if (!(p->rho_cp > 0)) return set_err(c, LBM_E_ARG, "rho_cp must be positive");
+            const double wT = dt / (p->alpha / cs2 + 0.5 * dt);
+            for (int q = 0; q < 5; ++q)
+                ck.Lt[q] = ck.thermal_mrt ? ((q == 1 || q == 2) ? wT : (q == 0 ? 0.0 : 1.0)) : wT;
+            ck.qdt = p->qvol / p->rho_cp * dt;
+        }
+        ck.c = cc;
+        ck.T_ref = p->T_ref;
+    } else {
+        const double cs2 = cc * cc / 3.0;
+        pk.nx = d.nx; pk.ny = d.ny; pk.batch = d.batch; pk.P = c->P;
+        pk.bcy = d.bc[2] == LBM_BC_WALL ? 1 : 0;
+        pk.z_mrt = p->z_collision == LBM_MRT;
+        pk.qy_printed = p->qy_printed ? 1 : 0;
+        pk.visc_mode = p->visc_mode ? 1 : 0;
+        if (!(p->rho_l > 0) || !(p->rho_g > 0)) return set_err(c, LBM_E_ARG, "densities must be positive");
+        pk.rho_l = p->rho_l;
+        pk.rho_g = p->rho_g;
+        const double s = dt / (dx * dx);
+        if (pk.visc_mode == 0) {
+            if (!(p->nu_l > 0) || !(p->nu_g > 0)) return set_err(c, LBM_E_TAU, "tau not above dt/2 (nu <= 0)");
+        } else {
+            if (!(p->zeta_l > 0) || !(p->zeta_g > 0)) return set_err(c, LBM_E_TAU, "tau not above dt/2 (zeta <= 0)");
+        }
+        pk.nuh_l = p->nu_l * s; pk.nuh_g = p->nu_g * s;
+        pk.zh_l = p->zeta_l * s; pk.zh_g = p->zeta_g * s;
+        if (!(p->mobility > 0)) return set_err(c, LBM_E_TAU, "tau_phi not above dt/2 (mobility <= 0)");
+        if (!(p->W > 0)) return set_err(c, LBM_E_ARG, "interface width must be positive");
+        pk.w_phi = dt / (p->mobility / cs2 + 0.5 * dt);  // M = (tau_phi - dt/2) c_s^2
+        pk.beta = 12.0 * p->sigma / p->W;                 // beta = 12 sigma / W
+        const double kappa = 1.5 * p->sigma * p->W;       // kappa = 3 sigma W / 2
+        pk.kap6 = 6.0 * kappa / (dx * dx);
+        pk.fs_scale = 3.0 * dt * dt / (dx * dx);
+        pk.Fbt[0] = p->Fb[0] * dt * dt / dx;
+        pk.Fbt[1] = p->Fb[1] * dt * dt / dx;
+        pk.dxW = dx / p->W;
+        const double eps = p->normal_eps > 0 ? p->normal_eps
+                                             : (d.prec == LBM_FP64 ? 1e-12 : 1e-6) / dx;
+        pk.Geps = eps * dx / 3.0;
+        pk.c = cc;
+        pk.cs2 = cs2;
+    }
+    c->ck = ck;
+    c->pk = pk;
+    c->dk = dk;
+    c->sp = *p;
+    c->sp.flux = c->sp.inlet_u = c->sp.inlet_T = nullptr;
+    c->flux_amp = p->flux_amp;
+    c->flux_omega = p->flux_omega;
+    c->dt = dt;
+    c->dx = dx;
+    c->rho_cp = p->rho_cp;
+    c->k_cond = p->rho_cp * p->alpha;
+    c->Dh = 2.0 * d.ny * dx;
+    uint64_t h = 1469598103934665603ull;
+    h = fnv(h, &d.lattice, sizeof(int) * 5);
+    h = fnv(h, d.bc, sizeof d.bc);
+    h = fnv(h, &d.flags, sizeof(int));
+    h = fnv(h, &ck, sizeof ck);
+    h = fnv(h, &pk, sizeof pk);
+    h = fnv(h, &dk, sizeof dk);
+    c->hash = h;
+    DeviceGuard g(c->device);
+    if (d.lattice == LBM_D2Q9_D2Q5) {
+        hipError_t e = d.prec == LBM_FP64 ? upload_aux<double>(c, p) : upload_aux<float>(c, p);
+        if (e != hipSuccess) return hip_fail(c, e, "upload of flux/inlet arrays");
+    }
+    c->has_params = true;
+    return LBM_OK;
+}
+
+lbm_status lbm_init_fields(lbm_ctx* c, const double* rho_or_p, const double* ux, const double* uy,
+                           const double* T, const double* phi) {
+    if (!c) return LBM_E_ARG;
+    if (!c->has_params) return set_err(c, LBM_E_STATE, "lbm_set_params_SI must come first");
+    const lbm_desc& d = c->desc;
+    const long long N = c->N, P = c->P;
+    const bool d1 = d.lattice == LBM_D1Q2 || d.lattice == LBM_D1Q3;
+    if (d1 && !T) return set_err(c, LBM_E_ARG, "1D lattices need T");
+    if (d.lattice == LBM_D2Q9_D2Q5 && !rho_or_p) return set_err(c, LBM_E_ARG, "rho is required");
+    if (d.lattice == LBM_D2Q9_PHASE && !phi) return set_err(c, LBM_E_ARG, "phi is required");
+    DeviceGuard g(c->device);
+    std::vector<double> host(5 * (size_t)N, 0.0);
+    auto put = [&](int slot, const double* src, double dflt) {
+        for (long long n = 0; n < N; ++n) host[slot * (size_t)N + n] = src ? src[n] : dflt;
+    };
+    put(0, d.lattice == LBM_D2Q9_PHASE ? rho_or_p : (d1 ? T : rho_or_p), 0.0);
+    put(1, ux, 0.0);
+    put(2, uy, 0.0);
+    put(3, T, c->sp.T_ref);
+    put(4, phi, 0.0);
+    for (int s = 0; s < 5; ++s) {
+        hipError_t e = hipMemcpyAsync(c->staging + s * P, host.data() + s * (size_t)N,
+                                      N * sizeof(double), hipMemcpyHostToDevice, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "field upload");
+    }
+    c->cur = 0;
+    hipError_t e;
+    if (d1) {
+        e = launch_d1_init(c->dk, c->staging, (double*)c->popA, c->stream);
+    } else if (d.lattice == LBM_D2Q9_D2Q5) {
+        if (d.prec == LBM_FP64)
+            e = launch_chan_init<double>(c->ck, c->staging, (double*)c->popA,
+                                         c->ck.thermal ? (double*)c->popA + 9 * P : nullptr, c->stream);
+        else
+            e = launch_chan_init<float>(c->ck, c->staging, (float*)c->popA,
+                                        c->ck.thermal ? (float*)c->popA + 9 * P : nullptr, c->stream);
+    } else {
+        if (d.prec == LBM_FP64)
+            e = launch_phase_init<double>(c->pk, c->staging, (double*)c->popA,
+                                          (double*)c->popA + 9 * P, (double*)c->phiu, c->stream);
+        else
+            e = launch_phase_init<float>(c->pk, c->staging, (float*)c->popA, (float*)c->popA + 9 * P,
+                                         (float*)c->phiu, c->stream);
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "init kernel");
+    e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "init");
+    c->t = 0;
+    c->has_state = true;
+    return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_ctx* c, int n) {
+    if (!c) return LBM_E_ARG;
+    if (n < 0) return set_err(c, LBM_E_ARG, "n must be >= 0");
+    if (!c->has_state) return set_err(c, LBM_E_STATE, "no state: call lbm_init_fields or lbm_load_state");
+    DeviceGuard g(c->device);
+    const int lat = c->desc.lattice;
+    if (lat == LBM_D1Q2 || lat == LBM_D1Q3) {
+        if (n == 0) return LBM_OK;
+        hipError_t e = launch_d1(c->dk, (double*)c->popA, n, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "d1 kernel");
+        c->t += n;
+        return LBM_OK;
+    }
+    for (int s = 0; s < n; ++s) {
+        hipError_t e = c->desc.prec == LBM_FP64 ? step_once<double>(c) : step_once<float>(c);
+        if (e != hipSuccess) return hip_fail(c, e, "step kernel");
+        c->cur ^= 1;
+        c->t += 1;
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_macros(lbm_ctx* c, unsigned mask, double* out, int out_on_device) {
+    if (!c) return LBM_E_ARG;
+    if (!out) return set_err(c, LBM_E_ARG, "out is NULL");
+    if (!c->has_state) return set_err(c, LBM_E_STATE, "no state");
+    const int lat = c->desc.lattice;
+    unsigned avail;
+    if (lat == LBM_D2Q9_D2Q5) avail = LBM_M_RHO | LBM_M_UX | LBM_M_UY | (c->ck.thermal ? LBM_M_T : 0u);
+    else if (lat == LBM_D2Q9_PHASE) avail = LBM_M_RHO | LBM_M_P | LBM_M_UX | LBM_M_UY | LBM_M_PHI | LBM_M_MU;
+    else avail = LBM_M_T;
+    if (mask == 0 || (mask & ~avail)) return set_err(c, LBM_E_ARG, "field not available for this lattice");
+    DeviceGuard g(c->device);
+    const long long P = c->P, N = c->N;
+    hipError_t e;
+    const bool f64 = c->desc.prec == LBM_FP64;
+    char* a = bufA(c);
+    if (lat == LBM_D2Q9_D2Q5) {
+        if (f64) e = launch_chan_macros<double>(c->ck, (double*)a, c->ck.thermal ? (double*)a + 9 * P : nullptr, c->staging, c->stream);
+        else e = launch_chan_macros<float>(c->ck, (float*)a, c->ck.thermal ? (float*)a + 9 * P : nullptr, c->staging, c->stream);
+    } else if (lat == LBM_D2Q9_PHASE) {
+        if (f64) e = launch_phase_macros<double>(c->pk, (double*)a, (double*)a + 9 * P, c->staging, c->stream);
+        else e = launch_phase_macros<float>(c->pk, (float*)a, (float*)a + 9 * P, c->staging, c->stream);
+    } else {
+        e = launch_d1_macros(c->dk, (double*)c->popA, c->staging, P, c->stream);
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "macros kernel");
+    int k = 0;
+    for (int bit = 0; bit < 7; ++bit) {
+        if (!(mask & (1u << bit))) continue;
+        e = hipMemcpyAsync(out + (size_t)k * N, c->staging + bit * P, N * sizeof(double),
+                           out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "macros copy");
+        ++k;
+    }
+    if (!out_on_device) {
+        e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "macros");
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_reduce(lbm_ctx* c, unsigned mask, double* out) {
+    if (!c) return LBM_E_ARG;
+    if (!out) return set_err(c, LBM_E_ARG, "out is NULL");
+    if (!c->has_state) return set_err(c, LBM_E_STATE, "no state");
+    if (mask == 0 || (mask & ~15u)) return set_err(c, LBM_E_ARG, "bad reduction mask");
+    DeviceGuard g(c->device);
+    const int lat = c->desc.lattice;
+    const int batch = c->desc.batch;
+    double* res = c->small + 3 * c->desc.nx + 64;
+    hipError_t e;
+    if (c->desc.prec == LBM_FP64)
+        e = launch_reduce<double>(lat, c->ck, c->pk, c->dk, (const double*)bufA(c), c->npop,
+                                  c->partial, res, c->stream);
+    else
+        e = launch_reduce<float>(lat, c->ck, c->pk, c->dk, (const float*)bufA(c), c->npop,
+                                 c->partial, res, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "reduce kernel");
+    std::vector<double> h(4 * (size_t)batch);
+    e = hipMemcpyAsync(h.data(), res, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "reduce");
+    int k = 0;
+    bool nonfinite = false;
+    for (int f = 0; f < 4; ++f) {
+        for (int b = 0; b < batch; ++b) {
+            if (h[b * 4 + 3] > 0) nonfinite = true;
+            if (mask & (1u << f)) out[(size_t)k * batch + b] = h[b * 4 + f];
+        }
+        if (mask & (1u << f)) ++k;
+    }
+    if (nonfinite) return set_err(c, LBM_E_NONFINITE, "non-finite populations in the state");
+    return LBM_OK;
+}
+
+lbm_status lbm_nusselt(lbm_ctx* c, int x_dev, double* Tb, double* Tw, double* Nu, double* nu_mean,
+                       double* T_out) {
+    if (!c) return LBM_E_ARG;
+    if (c->desc.lattice != LBM_D2Q9_D2Q5 || !c->ck.flow || !c->ck.thermal || !c->ck.bcy)
+        return set_err(c, LBM_E_UNSUPPORTED, "Nusselt needs D2Q9_D2Q5 with flow, thermal and walls");
+    if (!c->has_state) return set_err(c, LBM_E_STATE, "no state");
+    const int nx = c->desc.nx;
+    if (x_dev < 0 || x_dev >= nx) return set_err(c, LBM_E_ARG, "x_dev out of range");
+    DeviceGuard g(c->device);
+    double* dTb = c->small;
+    double* dTw = c->small + nx;
+    double* dNu = c->small + 2 * nx;
+    double* dres = c->small + 3 * nx;
+    const double qsi = c->dx * c->rho_cp / c->dt * flux_mod(c);
+    const long long P = c->P;
+    hipError_t e;
+    if (c->desc.prec == LBM_FP64) {
+        const double* a = (const double*)bufA(c);
+        e = launch_nusselt<double>(c->ck, a, a + 9 * P, aux_qw<double>(c), qsi, c->Dh, c->k_cond,
+                                   c->dx, x_dev, dTb, dTw, dNu, dres, c->stream);
+    } else {
+        const float* a = (const float*)bufA(c);
+        e = launch_nusselt<float>(c->ck, a, a + 9 * P, aux_qw<float>(c), qsi, c->Dh, c->k_cond, c->dx,
+                                  x_dev, dTb, dTw, dNu, dres, c->stream);
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "nusselt kernel");
+    std::vector<double> h(3 * (size_t)nx + 2);
+    e = hipMemcpyAsync(h.data(), c->small, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "nusselt");
+    if (Tb) std::memcpy(Tb, h.data(), nx * sizeof(double));
+    if (Tw) std::memcpy(Tw, h.data() + nx, nx * sizeof(double));
+    if (Nu) std::memcpy(Nu, h.data() + 2 * nx, nx * sizeof(double));
+    if (nu_mean) *nu_mean = h[3 * nx];
+    if (T_out) *T_out = h[3 * nx + 1];
+    return LBM_OK;
+}
+
+struct StateHeader {
+    uint32_t magic, version;
+    int32_t lattice, nx, ny, batch, prec, npop;
+    uint64_t hash;
+    int64_t t;
+    uint64_t pop_bytes, phiu_bytes;
+};
+
+lbm_status lbm_save_state(lbm_ctx* c, void* host, size_t* bytes) {
+    if (!c) return LBM_E_ARG;
+    if (!bytes) return set_err(c, LBM_E_ARG, "bytes is NULL");
+    const size_t pop = (size_t)c->npop * c->P * c->esize;
+    const size_t pu = c->desc.lattice == LBM_D2Q9_PHASE ? 2 * (size_t)c->P * c->esize : 0;
+    const size_t need = sizeof(StateHeader) + pop + pu;
+    if (!host) {
+        *bytes = need;
+        return LBM_OK;
+    }
+    if (*bytes < need) return set_err(c, LBM_E_ARG, "host buffer too small");
+    if (!c->has_state) return set_err(c, LBM_E_STATE, "no state");
+    DeviceGuard g(c->device);
+    StateHeader hd{kMagic, kVersion, c->desc.lattice, c->desc.nx, c->desc.ny, c->desc.batch,
+                   c->desc.prec, c->npop, c->hash, c->t, pop, pu};
+    std::memcpy(host, &hd, sizeof hd);
+    char* p = (char*)host + sizeof hd;
+    hipError_t e = hipMemcpyAsync(p, bufA(c), pop, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess && pu) e = hipMemcpyAsync(p + pop, c->phiu, pu, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "save state");
+    *bytes = need;
+    return LBM_OK;
+}
+
+lbm_status lbm_load_state(lbm_ctx* c, const void* host, size_t bytes) {
+    if (!c) return LBM_E_ARG;
+    if (!host) return set_err(c, LBM_E_ARG, "host is NULL");
+    if (!c->has_params) return set_err(c, LBM_E_STATE, "lbm_set_params_SI must come first");
+    if (bytes < sizeof(StateHeader)) return set_err(c, LBM_E_STATE, "state blob truncated");
+    StateHeader hd;
+    std::memcpy(&hd, host, sizeof hd);
+    const size_t pop = (size_t)c->npop * c->P * c->esize;
+    const size_t pu = c->desc.lattice == LBM_D2Q9_PHASE ? 2 * (size_t)c->P * c->esize : 0;
+    if (hd.magic != kMagic || hd.version != kVersion) return set_err(c, LBM_E_STATE, "not a state blob");
+    if (hd.lattice != c->desc.lattice || hd.nx != c->desc.nx || hd.ny != c->desc.ny ||
+        hd.batch != c->desc.batch || hd.prec != c->desc.prec || hd.npop != c->npop ||
+        hd.pop_bytes != pop || hd.phiu_bytes != pu)
+        return set_err(c, LBM_E_STATE, "state blob is for another description");
+    if (hd.hash != c->hash) return set_err(c, LBM_E_STATE, "state blob is for other parameters");
+    if (bytes < sizeof hd + pop + pu) return set_err(c, LBM_E_STATE, "state blob truncated");
+    DeviceGuard g(c->device);
+    const char* p = (const char*)host + sizeof hd;
+    c->cur = 0;
+    hipError_t e = hipMemcpyAsync(c->popA, p, pop, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess && pu) e = hipMemcpyAsync(c->phiu, p + pop, pu, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "load state");
+    c->t = hd.t;
+    c->has_state = true;
+    return LBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,132 @@
+// Internal declarations of liblbm: context, kernel-argument structs and the
+// launch wrappers the C-ABI layer calls.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "lbm.h"
+
+namespace lbm {
+
+// Kernel constants of the D2Q9 momentum + D2Q5 temperature step.  Everything
+// is pre-scaled by the host into lattice-normalised form (velocities in units
+// of c, forces as F dt^2/dx, rates as Lambda dt): the dimensional matrix of
+// Sec. 3 is the lattice matrix with rows scaled by c^order, so moment-space
+// relaxation gives identical populations in either normalisation.
+struct ChanK {
+    int nx, ny, batch;
+    long long P;          // plane stride (elements)
+    int bcx, bcy;         // 0 periodic; bcx 1 = inlet/outlet; bcy 1 = walls
+    int flow, thermal, flow_mrt, thermal_mrt;
+    double rho_ref;
+    double Lf[9];         // flow rates * dt in the order rho,e,eps,jx,qx,jy,qy,pxx,pxy
+    double Ft[2];         // body force * dt^2 / dx
+    double Lt[5];         // thermal rates * dt in the order T,jx,jy,e,pxx
+    double qdt;           // qdot * dt (K)
+    double c;             // lattice speed dx/dt (m/s), for outputs
+    double T_ref;
+};
+
+struct PhaseK {
+    int nx, ny, batch;
+    long long P;
+    int bcy;              // 0 periodic, 1 walls (x periodic)
+    int z_mrt, qy_printed, visc_mode;
+    double rho_l, rho_g;
+    double nuh_l, nuh_g;  // lattice viscosities nu dt/dx^2 (visc_mode 0)
+    double zh_l, zh_g;    // zeta dt/dx^2 (visc_mode 1)
+    double w_phi;         // dt / tau_phi
+    double beta;          // 12 sigma / W        (Pa)
+    double kap6;          // 6 kappa / dx^2      (Pa): mu = 4 beta phi(phi-1)(phi-1/2) - kap6 L
+    double fs_scale;      // 3 dt^2 / dx^2: F~_s = mu G fs_scale
+    double Fbt[2];        // body force * dt^2 / dx
+    double dxW;           // dx / W
+    double Geps;          // |G| threshold for n = 0 (= normal_eps dx / 3)
+    double c, cs2;        // outputs
+};
+
+struct D1K {
+    int n, q;
+    double w_tau;         // dt / tau
+    double qdt;           // qdot * dt
+    double ufac;          // c u / c_s^2 (multiplies e_i in the equilibrium)
+    double T0, TL;
+};
+
+}  // namespace lbm
+
+struct lbm_ctx {
+    lbm_desc desc;
+    int device;
+    hipStream_t stream;
+    // layout
+    long long N;          // nodes per replica * batch
+    long long P;          // plane stride
+    int npop;             // planes per population buffer
+    size_t esize;         // bytes per population value
+    char* popA;
+    char* popB;
+    char* phiu;
+    char* aux;            // flux (qw), inlet_u (uin), inlet_T (tin): storage type
+    double* staging;      // 7 planes of FP64
+    double* partial;      // reduction partials
+    double* small;        // small FP64 results
+    int cur;              // 0: A holds the state, 1: B holds it
+    long long t;          // steps since init
+    bool has_params, has_state;
+    lbm_params_si sp;     // SI scalars (array pointers cleared)
+    lbm::ChanK ck;
+    lbm::PhaseK pk;
+    lbm::D1K dk;
+    double flux_amp, flux_omega, dt;
+    double k_cond, Dh, dx, rho_cp;
+    std::string err;
+    uint64_t hash;
+};
+
+namespace lbm {
+
+constexpr int kRedBlocks = 256;  // first-pass blocks per replica and field
+
+// launch wrappers (lbm_kernels.hip); all enqueue on s and return hipGetLastError()
+template <typename S>
+hipError_t launch_chan_step(const ChanK& k, const S* fc, S* fn, const S* gc, S* gn,
+                            const S* qw, const S* uin, const S* tin, double mod, hipStream_t s);
+template <typename S>
+hipError_t launch_phase_step(const PhaseK& k, const S* hc, S* hn, const S* zc, S* zn, S* phiu,
+                             hipStream_t s);
+hipError_t launch_d1(const D1K& k, double* g, int nsteps, hipStream_t s);
+
+template <typename S>
+hipError_t launch_chan_init(const ChanK& k, const double* fields, S* f, S* g, hipStream_t s);
+template <typename S>
+hipError_t launch_phase_init(const PhaseK& k, const double* fields, S* h, S* z, S* phiu,
+                             hipStream_t s);
+hipError_t launch_d1_init(const D1K& k, const double* T, double* g, hipStream_t s);
+
+// macros into staging slots [7][P]: rho, p, ux, uy, T, phi, mu
+template <typename S>
+hipError_t launch_chan_macros(const ChanK& k, const S* f, const S* g, double* out, hipStream_t s);
+template <typename S>
+hipError_t launch_phase_macros(const PhaseK& k, const S* h, const S* z, double* out,
+                               hipStream_t s);
+hipError_t launch_d1_macros(const D1K& k, const double* g, double* out, long long P,
+                            hipStream_t s);
+
+// per-replica FP64 sums: out[b*4 + f], f = mass, phase, energy, nonfinite
+template <typename S>
+hipError_t launch_reduce(int lattice, const ChanK& ck, const PhaseK& pk, const D1K& dk,
+                         const S* pops, int npop, double* partial, double* out, hipStream_t s);
+
+// qsi converts the stored scaled flux to W/m^2 (including the time modulation);
+// small receives (mean Nu over x >= x_dev, Tb[nx-1])
+template <typename S>
+hipError_t launch_nusselt(const ChanK& k, const S* f, const S* g, const S* qw, double qsi,
+                          double Dh, double kc, double dx, int x_dev, double* Tb, double* Tw,
+                          double* Nu, double* small, hipStream_t s);
+
+}  // namespace lbm

@@ -1,0 +1,105 @@
+"""C-ABI checks that need no GPU: the library loads, exports exactly the
+entry points include/lbm.h declares, and validates descriptions."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbm.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"LBM_API\s+[\w\s\*]*?\b(lbm_\w+)\s*\(", txt)))
+
+
+def _lbm():
+    from paper_2302_04120_amd import lbm
+    if not os.path.exists(lbm.LIB_PATH):
+        pytest.skip("liblbm.so not built")
+    return lbm
+
+
+def test_header_declares_the_binding_exports():
+    lbm = _lbm()
+    assert _declared() == sorted(lbm.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lbm = _lbm()
+    out = subprocess.check_output(["nm", "-D", "--defined-only", lbm.LIB_PATH], text=True)
+    exported = sorted(l.split()[-1] for l in out.splitlines() if l.split()[-1].startswith("lbm_"))
+    assert exported == _declared()
+    L = lbm.lib()
+    for name in _declared():
+        assert getattr(L, name) is not None
+
+
+def _desc(lbm, **kw):
+    d = lbm.Desc()
+    d.lattice = kw.get("lattice", lbm.LBM_D2Q9_PHASE)
+    d.nx, d.ny, d.batch = kw.get("nx", 64), kw.get("ny", 64), kw.get("batch", 1)
+    d.prec = kw.get("prec", lbm.LBM_FP32_DEV)
+    for i, v in enumerate(kw.get("bc", (0, 0, 0, 0))):
+        d.bc[i] = v
+    d.flags = kw.get("flags", 1)
+    return d
+
+
+def test_query_bytes_layout_and_validation():
+    lbm = _lbm()
+    L = lbm.lib()
+    n = C.c_size_t()
+    d = _desc(lbm)
+    assert L.lbm_query_bytes(C.byref(d), C.byref(n)) == lbm.LBM_OK
+    N = 64 * 64
+    # two buffers of 19 FP32 planes + (phi u) + 7 FP64 staging planes at least
+    assert n.value >= (2 * 19 + 2) * N * 4 + 7 * N * 8
+    d64 = _desc(lbm, prec=lbm.LBM_FP64)
+    n64 = C.c_size_t()
+    assert L.lbm_query_bytes(C.byref(d64), C.byref(n64)) == lbm.LBM_OK
+    assert n64.value > n.value
+    bad = [
+        _desc(lbm, nx=0),
+        _desc(lbm, prec=7),
+        _desc(lbm, lattice=99),
+        _desc(lbm, bc=(2, 3, 0, 0)),  # inlet/outlet not supported for the phase lattice
+        _desc(lbm, lattice=lbm.LBM_D2Q9_D2Q5, bc=(2, 0, 0, 0)),
+        _desc(lbm, lattice=lbm.LBM_D2Q9_D2Q5, flags=0),
+        _desc(lbm, lattice=lbm.LBM_D1Q2, nx=101, ny=1, prec=lbm.LBM_FP32_DEV, bc=(4, 4, 0, 0)),
+        _desc(lbm, lattice=lbm.LBM_D1Q2, nx=2000, ny=1, prec=lbm.LBM_FP64, bc=(4, 4, 0, 0)),
+    ]
+    for d in bad:
+        assert L.lbm_query_bytes(C.byref(d), C.byref(n)) in (lbm.LBM_E_ARG, lbm.LBM_E_UNSUPPORTED)
+    ok = _desc(lbm, lattice=lbm.LBM_D1Q3, nx=101, ny=1, prec=lbm.LBM_FP64, bc=(4, 4, 0, 0))
+    assert L.lbm_query_bytes(C.byref(ok), C.byref(n)) == lbm.LBM_OK
+    assert L.lbm_create(None, None) == lbm.LBM_E_ARG
+    assert L.lbm_query_bytes(C.byref(ok), None) == lbm.LBM_E_ARG
+
+
+def test_create_rejects_small_or_misaligned_buffer():
+    lbm = _lbm()
+    L = lbm.lib()
+    d = _desc(lbm)
+    h = C.c_void_p()
+    d.dev_buf = C.c_void_p(0x100000)
+    d.dev_buf_bytes = 16
+    assert L.lbm_create(C.byref(d), C.byref(h)) == lbm.LBM_E_ARG
+    n = C.c_size_t()
+    L.lbm_query_bytes(C.byref(d), C.byref(n))
+    d.dev_buf_bytes = n.value
+    d.dev_buf = C.c_void_p(0x100004)
+    assert L.lbm_create(C.byref(d), C.byref(h)) == lbm.LBM_E_ARG
+    assert not h.value
+
+
+def test_product_binding_refuses_without_gpu():
+    lbm = _lbm()
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    with pytest.raises(RuntimeError):
+        lbm.Lattice("phase", 16, 16)
