@@ -34,6 +34,12 @@ TWO_PHASE_SYSTEMS = {
 }
 
 
+#: interface-normal guard: n = 0 where |grad phi| <= NORMAL_EPS_NODES / dx.  The
+#: paper zeroes n only where the gradient is exactly zero; a threshold well
+#: above FP32 rounding of phi keeps both precisions on the same side of it.
+NORMAL_EPS_NODES = 1e-6
+
+
 def rng(seed):
     return np.random.Generator(np.random.PCG64(seed))
 
@@ -82,7 +88,7 @@ def slab_1d(seed=0, n=101, L=0.1, alpha=1e-5, k=1.0, qvol=1e4, T_wall=300.0, dt=
 # --------------------------------------------------------------------------
 
 def channel(nx=800, ny=40, dx=2.5e-5, nu=1e-6, Pr=7.0, Re=50.0, q_s=1e4, T_in=300.0,
-            tau_ratio=0.85, oscillating=False, developed=True, seed=0):
+            tau_ratio=0.64, oscillating=False, developed=True, seed=0):
     """Full channel of height H = ny dx between two heated halfway walls.
 
     Re is based on the hydraulic diameter 2H; dt follows from tau/dt for the
@@ -130,28 +136,30 @@ def adjoint_channel(nx=1600, ny=80, dx=1.25e-5, **kw):
 
 def bubble(n=256, radii=(20, 30, 40, 50), seed=0, dx=5e-6, dt=1e-7, W_nodes=4.0, M=1e-5,
            rho_l=1000.0, rho_g=0.0231, nu_l=8.927e-7, nu_g=4.20412e-4, sigma=0.07,
-           batch=None):
-    """Periodic n x n cell with one gas bubble (phi = 0 inside), centre jittered
-    by U(-1/2, 1/2) nodes per axis; one replica per radius (cycled when
-    ``batch`` exceeds the number of radii).  p = 0 and u = 0 initially."""
+           batch=None, ny=None):
+    """Periodic n x ny cell (ny = n by default) with one gas bubble (phi = 0
+    inside), centre jittered by U(-1/2, 1/2) nodes per axis; one replica per
+    radius (cycled when ``batch`` exceeds the number of radii).  p = 0 and u = 0
+    initially."""
     if batch is None:
         batch = len(radii)
+    if ny is None:
+        ny = n
     g = rng(seed)
-    x = node_centres(n, dx)
-    X, Y = np.meshgrid(x, x, indexing="xy")
+    X, Y = np.meshgrid(node_centres(n, dx), node_centres(ny, dx), indexing="xy")
     W = W_nodes * dx
-    phi = np.zeros((batch, n, n))
+    phi = np.zeros((batch, ny, n))
     centres = []
     for b in range(batch):
         R = radii[b % len(radii)] * dx
         jx, jy = g.uniform(-0.5, 0.5, 2)
-        xc, yc = (n / 2 + jx) * dx, (n / 2 + jy) * dx
+        xc, yc = (n / 2 + jx) * dx, (ny / 2 + jy) * dx
         r = np.sqrt((X - xc) ** 2 + (Y - yc) ** 2)
         phi[b] = tanh_profile(r - R, W)  # gas inside the bubble
         centres.append((xc, yc, R))
     prm = dict(dx=dx, dt=dt, rho_l=rho_l, rho_g=rho_g, nu_l=nu_l, nu_g=nu_g,
                zeta_l=nu_l * rho_l, zeta_g=nu_g * rho_g, visc_mode=0, sigma=sigma, W=W, M=M,
-               Fx=0.0, Fy=0.0, z_mrt=1, qy_printed=0)
+               Fx=0.0, Fy=0.0, z_mrt=1, qy_printed=0, normal_eps=NORMAL_EPS_NODES / dx)
     zeros = np.zeros_like(phi)
     return prm, dict(phi=phi, p=zeros.copy(), ux=zeros.copy(), uy=zeros.copy()), centres
 
@@ -160,12 +168,13 @@ def bubble(n=256, radii=(20, 30, 40, 50), seed=0, dx=5e-6, dt=1e-7, W_nodes=4.0,
 # C4: layered two-phase Poiseuille flow (Sec. 4.4)
 # --------------------------------------------------------------------------
 
-def layered(nx=4, ny=512, seed=0, dx=1.25e-6, dt=1.25e-7, W_nodes=4.0, M=1e-5,
+def layered(nx=4, ny=512, seed=0, dx=1.25e-6, dt=1.25e-7, W_nodes=20.0, M=1e-5,
             rho_l=1000.0, rho_g=0.0231, nu_l=8.927e-7, nu_g=4.20412e-4, sigma=0.07,
             u_c=1e-4, batch=1):
     """Liquid below the interface at y = H/2 + U(-1/2, 1/2) dx, gas above;
     halfway walls at y = 0 and y = H; driving force u_c (zeta_l + zeta_g) / h^2
-    with h = H/2 (so that u_c is the interface speed of the sharp solution)."""
+    with h = H/2 (so that u_c is the interface speed of the sharp solution).
+    The interface width defaults to the paper's W = 25 um (20 dx here)."""
     g = rng(seed)
     H = ny * dx
     h = 0.5 * H
@@ -181,6 +190,6 @@ def layered(nx=4, ny=512, seed=0, dx=1.25e-6, dt=1.25e-7, W_nodes=4.0, M=1e-5,
         offsets.append(yi)
     prm = dict(dx=dx, dt=dt, rho_l=rho_l, rho_g=rho_g, nu_l=nu_l, nu_g=nu_g, zeta_l=zeta_l,
                zeta_g=zeta_g, visc_mode=1, sigma=sigma, W=W, M=M, Fx=Fx, Fy=0.0, z_mrt=1,
-               qy_printed=0, H=H, h=h, u_c=u_c)
+               qy_printed=0, H=H, h=h, u_c=u_c, normal_eps=NORMAL_EPS_NODES / dx)
     zeros = np.zeros_like(phi)
     return prm, dict(phi=phi, p=zeros.copy(), ux=zeros.copy(), uy=zeros.copy()), offsets
