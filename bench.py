@@ -59,6 +59,39 @@ def run_gpu(batch, steps, warmup, prec, n=256):
                 bytes_gb=L.bytes / 1e9)
 
 
+def adjoint_cost(steps=20000, ckpt=500, prec="fp32"):
+    """Adjoint/forward cost on the C5 heated channel (1600 x 80 nodes, flow from
+    rest): plain forward time, record time (forward + checkpoints) and the
+    reverse time of lbm_grad (recompute of every segment + adjoint steps)."""
+    import torch
+    from paper_2302_04120_amd import lbm, workloads as WL
+    prm, ini = WL.adjoint_channel()
+    nx, ny = 1600, 80
+    L = lbm.Lattice("channel", nx, ny, prec=prec,
+                    bc=(lbm.BC_VEL_INLET, lbm.BC_P_OUTLET, lbm.BC_WALL, lbm.BC_WALL),
+                    flow=True, thermal=True)
+    L.set_params(prm)
+    L.init(ini["rho"], ini["ux"], ini["uy"], ini["T"])
+    L.step(200)
+    torch.cuda.synchronize()
+    L.init(ini["rho"], ini["ux"], ini["uy"], ini["T"])
+    t0 = time.perf_counter()
+    L.step(steps)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    L.init(ini["rho"], ini["ux"], ini["uy"], ini["T"])
+    t0 = time.perf_counter()
+    L.record(steps, ckpt, nx // 2)
+    t_rec = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    L.grad()
+    t_grad = time.perf_counter() - t0
+    return dict(forward_s=t_fwd, record_s=t_rec, grad_s=t_grad,
+                adjoint_over_forward=t_grad / t_fwd,
+                record_plus_grad_over_forward=(t_rec + t_grad) / t_fwd,
+                forward_mlups=nx * ny * steps / t_fwd / 1e6)
+
+
 def cpu_baseline(seconds=12.0):
     """The FP64 oracle on one 256 x 256 replica of the same workload."""
     import oracle as O
@@ -77,6 +110,20 @@ def cpu_baseline(seconds=12.0):
                        % steps)
 
 
+def copy_calibration(nbytes, reps=5):
+    """A plain device copy of known size (torch's own copy kernel), used to
+    scale rocprofv3's FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": b.numel() * 4,
+                      "reps": reps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,7 +134,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP64 and batch-4 legs")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_phase_step.json"))
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain copy of BYTES (counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return 0
     if args.gpus != 1:
         print("bench.py measures one GPU only; --gpus %d is not supported" % args.gpus,
               file=sys.stderr)
@@ -114,6 +166,8 @@ def main():
         log("bench: paper-sized leg (4 replicas)")
         r4 = run_gpu(4, 1000, 50, args.prec)
         extras["paper_config_batch4_mlups"] = r4["nodes"] * 1000 / r4["wall"] / 1e6
+        log("bench: adjoint/forward cost leg (C5 channel)")
+        extras["adjoint"] = adjoint_cost()
     cpu = None
     if not args.no_cpu_baseline:
         log("bench: CPU oracle baseline")
@@ -143,6 +197,8 @@ def main():
         "adjoint_over_forward": None,
     }
     line.update(extras)
+    if "adjoint" in extras:
+        line["adjoint_over_forward"] = extras["adjoint"]["adjoint_over_forward"]
     print(json.dumps(line), flush=True)
     return 0
 

@@ -181,6 +181,42 @@ LBM_API lbm_status lbm_reduce(lbm_ctx* ctx, unsigned mask, double* out);
 LBM_API lbm_status lbm_nusselt(lbm_ctx* ctx, int x_dev, double* Tb, double* Tw, double* Nu,
                        double* nu_mean, double* T_out);
 
+/* ---- discrete adjoint of the heated channel --------------------------------
+ * Objective (the paper gives no gradients; this is the differentiated quantity):
+ * J = w_tout * T_out + w_nu * mean_{x >= x_dev} Nu(x) at the last recorded step,
+ * with T_out and Nu as in lbm_nusselt.  Parameters: the wall-flux profile
+ * flux[nx] (both walls) and the relaxation times tau (momentum) and tau_T
+ * (temperature), which set nu = (tau - dt/2) c_s^2 and alpha = (tau_T - dt/2) c_s^2.
+ * Supported for LBM_D2Q9_D2Q5 with flow and thermal populations, inlet/outlet
+ * in x, walls in y, batch 1. */
+typedef struct {
+    int x_dev;              /* first column of the Nusselt average                          */
+    double w_tout, w_nu;    /* weights of the two terms                                     */
+} lbm_objective;
+
+/* Bytes of the caller-owned device work buffer lbm_record needs for nsteps
+ * steps with a checkpoint every ckpt_every steps: the checkpoints, a
+ * recomputation tape of ckpt_every + 1 states, two adjoint states and the FP64
+ * accumulators. */
+LBM_API lbm_status lbm_query_record_bytes(const lbm_ctx* ctx, int nsteps, int ckpt_every,
+                                          size_t* bytes);
+
+/* Advance nsteps from the current state (as lbm_step), saving the state every
+ * ckpt_every steps into work (device memory of lbm_query_record_bytes bytes,
+ * 256-byte aligned, kept alive until lbm_grad), and return J (synchronous).
+ * The context then holds the final state. */
+LBM_API lbm_status lbm_record(lbm_ctx* ctx, int nsteps, int ckpt_every,
+                              const lbm_objective* obj, void* work, size_t work_bytes,
+                              double* J);
+
+/* Reverse sweep of the last lbm_record: recompute each checkpoint segment
+ * (the forward step kernel writes the tape), then apply the hand-written
+ * discrete adjoint step backwards.  Outputs dL/dJ * dJ/dflux[nx] (per W/m^2)
+ * and dL/dJ * dJ/dtau[2] = (d/dtau, d/dtau_T) (per second), accumulated in
+ * FP64 in a fixed order (deterministic).  Synchronous.  The context keeps the
+ * final state. */
+LBM_API lbm_status lbm_grad(lbm_ctx* ctx, double dL_dJ, double* dJ_dflux, double* dJ_dtau);
+
 /* Number of steps taken since lbm_init_fields / lbm_load_state. */
 LBM_API long long lbm_time(const lbm_ctx* ctx);
 

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "liblbm.so")
-SOURCES = ["lbm_api.hip", "lbm_kernels.hip"]
+SOURCES = ["lbm_api.hip", "lbm_kernels.hip", "lbm_adjoint.hip"]
 
 
 def hipcc():

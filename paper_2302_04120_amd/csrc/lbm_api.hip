@@ -78,6 +78,10 @@ lbm_status check_desc(const lbm_desc* d, Layout* L, std::string* err) {
         default:
             return fail(LBM_E_ARG, "unknown lattice");
     }
+    {
+        const long long tiles = (long long)((d->nx + 63) / 64) * ((d->ny + 3) / 4) * d->batch;
+        if (tiles > (1LL << 30)) return fail(LBM_E_ARG, "grid too large for the launch geometry");
+    }
     size_t off = 0;
     const size_t popbytes = align256((size_t)l.npop * l.P * l.es);
     l.offA = off; off += popbytes;
@@ -210,6 +214,7 @@ lbm_status lbm_create(const lbm_desc* desc, lbm_ctx** out) {
     c->cur = 0;
     c->t = 0;
     c->has_params = c->has_state = false;
+    c->has_record = false;
     *out = c;
     return LBM_OK;
 }
@@ -229,6 +234,7 @@ lbm_status lbm_set_params_SI(lbm_ctx* c, const lbm_params_si* p) {
     ChanK ck{};
     PhaseK pk{};
     D1K dk{};
+    AdjK ak{};
     if (d.lattice == LBM_D1Q2 || d.lattice == LBM_D1Q3) {
         const double cs2 = d.lattice == LBM_D1Q2 ? cc * cc : cc * cc / 3.0;
         if (!(p->rho_cp > 0)) return set_err(c, LBM_E_ARG, "rho_cp must be positive");
@@ -262,15 +268,25 @@ lbm_status lbm_set_params_SI(lbm_ctx* c, const lbm_params_si* p) {
             const double wpe = p->omega_eps > 0 ? p->omega_eps * dt : 1.0;
             const double Lf[9] = {0, we, wpe, 0, wq, 0, wq, wn, wn};
             for (int q = 0; q < 9; ++q) ck.Lf[q] = Lf[q];
+            // derivatives with respect to tau of w_nu dt = dt/tau and w_q dt
+            const double dwn = -dt / (tau * tau);
+            const double dwq = 3.0 * dt / (tau * tau * (3.0 - wn) * (3.0 - wn));
+            const double dL[9] = {0, 0, 0, 0, dwq, 0, dwq, dwn, dwn};
+            for (int q = 0; q < 9; ++q) ak.dLf[q] = ck.flow_mrt ? dL[q] : (q == 7 ? dwn : 0.0);
         }
         ck.Ft[0] = p->Fb[0] * dt * dt / dx;
         ck.Ft[1] = p->Fb[1] * dt * dt / dx;
         if (ck.thermal) {
             if (!(p->alpha > 0)) return set_err(c, LBM_E_TAU, "tau_T not above dt/2 (alpha <= 0)");
             if (!(p->rho_cp > 0)) return set_err(c, LBM_E_ARG, "rho_cp must be positive");
-            const double wT = dt / (p->alpha / cs2 + 0.5 * dt);
-            for (int q = 0; q < 5; ++q)
-                ck.Lt[q] = ck.thermal_mrt ? ((q == 1 || q == 2) ? wT : (q == 0 ? 0.0 : 1.0)) : wT;
+            const double tauT = p->alpha / cs2 + 0.5 * dt;
+            const double wT = dt / tauT, dwT = -dt / (tauT * tauT);
+            for (int q = 0; q < 5; ++q) {
+                const bool j = (q == 1 || q == 2);
+                ck.Lt[q] = ck.thermal_mrt ? (j ? wT : (q == 0 ? 0.0 : 1.0)) : wT;
+                ak.dLt[q] = (ck.thermal_mrt && !j) ? 0.0 : dwT;
+            }
+            ak.qgrad = dt / (dx * p->rho_cp);
             ck.qdt = p->qvol / p->rho_cp * dt;
         }
         ck.c = cc;
@@ -312,6 +328,9 @@ lbm_status lbm_set_params_SI(lbm_ctx* c, const lbm_params_si* p) {
     c->ck = ck;
     c->pk = pk;
     c->dk = dk;
+    c->ak = ak;
+    c->cs2 = cc * cc / 3.0;
+    c->has_record = false;
     c->sp = *p;
     c->sp.flux = c->sp.inlet_u = c->sp.inlet_T = nullptr;
     c->flux_amp = p->flux_amp;
@@ -523,6 +542,182 @@ lbm_status lbm_nusselt(lbm_ctx* c, int x_dev, double* Tb, double* Tw, double* Nu
     if (T_out) *T_out = h[3 * nx + 1];
     return LBM_OK;
 }
+
+}  // extern "C"
+
+// ---- discrete adjoint ------------------------------------------------------
+namespace {
+
+struct RecLayout {
+    size_t state, offCk, offTape, offLam, offDq, offAcc, offGrad, total;
+    int nseg, tiles;
+};
+
+lbm_status rec_layout(const lbm_ctx* c, int nsteps, int K, RecLayout* R, std::string* err) {
+    const lbm_desc& d = c->desc;
+    auto fail = [&](lbm_status st, const char* m) {
+        if (err) *err = m;
+        return st;
+    };
+    if (d.lattice != LBM_D2Q9_D2Q5 || !c->ck.flow || !c->ck.thermal || !c->ck.bcx || !c->ck.bcy ||
+        d.batch != 1)
+        return fail(LBM_E_UNSUPPORTED,
+                    "the adjoint needs the channel lattice with flow, thermal, inlet/outlet, walls, batch 1");
+    if (nsteps < 1 || K < 1) return fail(LBM_E_ARG, "nsteps and ckpt_every must be >= 1");
+    RecLayout r{};
+    r.state = align256((size_t)c->npop * c->P * c->esize);
+    r.nseg = (nsteps + K - 1) / K;
+    const int Kt = K < nsteps ? K : nsteps;
+    r.tiles = chan_tiles(c->ck);
+    size_t off = 0;
+    r.offCk = off; off += (size_t)r.nseg * r.state;
+    r.offTape = off; off += (size_t)(Kt + 1) * r.state;
+    r.offLam = off; off += 2 * r.state;
+    r.offDq = off; off += align256(4 * (size_t)d.nx * sizeof(double));
+    r.offAcc = off; off += align256(2 * (size_t)r.tiles * sizeof(double));
+    r.offGrad = off; off += align256(((size_t)d.nx + 2) * sizeof(double));
+    r.total = off;
+    *R = r;
+    return LBM_OK;
+}
+
+template <typename S>
+hipError_t chan_step_ptr(lbm_ctx* c, const S* a, S* b, long long t) {
+    const long long P = c->P;
+    const double mod = 1.0 + c->flux_amp * std::sin(c->flux_omega * (double)t * c->dt);
+    return launch_chan_step<S>(c->ck, a, b, a + 9 * P, b + 9 * P, aux_qw<S>(c), aux_uin<S>(c),
+                               aux_tin<S>(c), mod, c->stream);
+}
+
+template <typename S>
+hipError_t grad_impl(lbm_ctx* c, const RecLayout& R, double scale) {
+    const long long P = c->P;
+    const int nx = c->desc.nx;
+    char* w = c->rec_work;
+    double* dq = (double*)(w + R.offDq);
+    double* acc = (double*)(w + R.offAcc);
+    double* grad = (double*)(w + R.offGrad);
+    S* lam[2] = {(S*)(w + R.offLam), (S*)(w + R.offLam + R.state)};
+    hipError_t e = hipMemsetAsync(dq, 0, 4 * (size_t)nx * sizeof(double), c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(acc, 0, 2 * (size_t)R.tiles * sizeof(double), c->stream);
+    if (e != hipSuccess) return e;
+    // seed from the final state (the context's current buffer)
+    const long long tN = c->rec_t0 + c->rec_nsteps;
+    const double modN = 1.0 + c->flux_amp * std::sin(c->flux_omega * (double)tN * c->dt);
+    const S* fin = (const S*)bufA(c);
+    e = launch_adj_seed<S>(c->ck, fin, fin + 9 * P, aux_qw<S>(c), c->dx * c->rho_cp / c->dt * modN,
+                           modN, c->Dh, c->k_cond, c->dx, c->rho_cp, c->cs2, c->rec_obj.x_dev,
+                           c->rec_obj.w_tout, c->rec_obj.w_nu, lam[0], lam[0] + 9 * P, dq + 2 * nx,
+                           dq + 3 * nx, c->stream);
+    if (e != hipSuccess) return e;
+    int cur = 0;
+    for (int sg = R.nseg - 1; sg >= 0; --sg) {
+        const long long t0 = c->rec_t0 + (long long)sg * c->rec_K;
+        const int len = (sg == R.nseg - 1) ? c->rec_nsteps - sg * c->rec_K : c->rec_K;
+        S* tape = (S*)(w + R.offTape);
+        e = hipMemcpyAsync(tape, w + R.offCk + (size_t)sg * R.state, R.state, hipMemcpyDeviceToDevice,
+                           c->stream);
+        if (e != hipSuccess) return e;
+        for (int j = 0; j < len; ++j) {
+            e = chan_step_ptr<S>(c, (const S*)((char*)tape + (size_t)j * R.state),
+                                 (S*)((char*)tape + (size_t)(j + 1) * R.state), t0 + j);
+            if (e != hipSuccess) return e;
+        }
+        for (int j = len - 1; j >= 0; --j) {
+            const S* st = (const S*)((char*)tape + (size_t)j * R.state);
+            const double mod = 1.0 + c->flux_amp * std::sin(c->flux_omega * (double)(t0 + j) * c->dt);
+            e = launch_adj_step<S>(c->ck, c->ak, st, st + 9 * P, lam[cur], lam[cur] + 9 * P,
+                                   lam[cur ^ 1], lam[cur ^ 1] + 9 * P, mod, dq, dq + nx, acc,
+                                   c->stream);
+            if (e != hipSuccess) return e;
+            cur ^= 1;
+        }
+    }
+    return launch_adj_final(nx, R.tiles, scale, dq, dq + nx, dq + 2 * nx, dq + 3 * nx, acc, grad,
+                            grad + nx, c->stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_query_record_bytes(const lbm_ctx* c, int nsteps, int ckpt_every, size_t* bytes) {
+    if (!c || !bytes) return LBM_E_ARG;
+    if (!c->has_params) return LBM_E_STATE;
+    RecLayout R;
+    lbm_status st = rec_layout(c, nsteps, ckpt_every, &R, nullptr);
+    if (st != LBM_OK) return st;
+    *bytes = R.total;
+    return LBM_OK;
+}
+
+lbm_status lbm_record(lbm_ctx* c, int nsteps, int ckpt_every, const lbm_objective* obj, void* work,
+                      size_t work_bytes, double* J) {
+    if (!c) return LBM_E_ARG;
+    if (!obj || !work || !J) return set_err(c, LBM_E_ARG, "obj, work and J are required");
+    if (!c->has_state) return set_err(c, LBM_E_STATE, "no state");
+    RecLayout R;
+    lbm_status st = rec_layout(c, nsteps, ckpt_every, &R, &c->err);
+    if (st != LBM_OK) return st;
+    if (work_bytes < R.total || ((uintptr_t)work & 255) != 0)
+        return set_err(c, LBM_E_ARG, "work buffer too small or not 256-byte aligned");
+    if (obj->x_dev < 0 || obj->x_dev >= c->desc.nx) return set_err(c, LBM_E_ARG, "x_dev out of range");
+    DeviceGuard g(c->device);
+    char* w = (char*)work;
+    c->has_record = false;
+    const long long t0 = c->t;
+    for (int sg = 0; sg < R.nseg; ++sg) {
+        hipError_t e = hipMemcpyAsync(w + R.offCk + (size_t)sg * R.state, bufA(c),
+                                      (size_t)c->npop * c->P * c->esize, hipMemcpyDeviceToDevice,
+                                      c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "checkpoint copy");
+        const int len = (sg == R.nseg - 1) ? nsteps - sg * ckpt_every : ckpt_every;
+        st = lbm_step(c, len);
+        if (st != LBM_OK) return st;
+    }
+    double nm = 0, tout = 0;
+    st = lbm_nusselt(c, obj->x_dev, nullptr, nullptr, nullptr, &nm, &tout);
+    if (st != LBM_OK) return st;
+    *J = obj->w_tout * tout + obj->w_nu * nm;
+    c->rec_work = w;
+    c->rec_bytes = work_bytes;
+    c->rec_nsteps = nsteps;
+    c->rec_K = ckpt_every;
+    c->rec_nseg = R.nseg;
+    c->rec_t0 = t0;
+    c->rec_obj = *obj;
+    c->has_record = true;
+    return LBM_OK;
+}
+
+lbm_status lbm_grad(lbm_ctx* c, double dL_dJ, double* dJ_dflux, double* dJ_dtau) {
+    if (!c) return LBM_E_ARG;
+    if (!dJ_dflux || !dJ_dtau) return set_err(c, LBM_E_ARG, "output arrays are required");
+    if (!c->has_record) return set_err(c, LBM_E_STATE, "call lbm_record first");
+    if (c->t != c->rec_t0 + c->rec_nsteps)
+        return set_err(c, LBM_E_STATE, "the state moved since lbm_record");
+    RecLayout R;
+    lbm_status st = rec_layout(c, c->rec_nsteps, c->rec_K, &R, &c->err);
+    if (st != LBM_OK) return st;
+    DeviceGuard g(c->device);
+    hipError_t e = c->desc.prec == LBM_FP64 ? grad_impl<double>(c, R, dL_dJ)
+                                            : grad_impl<float>(c, R, dL_dJ);
+    if (e != hipSuccess) return hip_fail(c, e, "adjoint");
+    const int nx = c->desc.nx;
+    std::vector<double> h(nx + 2);
+    e = hipMemcpyAsync(h.data(), c->rec_work + R.offGrad, h.size() * sizeof(double),
+                       hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "adjoint");
+    std::memcpy(dJ_dflux, h.data(), nx * sizeof(double));
+    dJ_dtau[0] = h[nx];
+    dJ_dtau[1] = h[nx + 1];
+    return LBM_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
 
 struct StateHeader {
     uint32_t magic, version;

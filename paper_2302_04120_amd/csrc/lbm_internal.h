@@ -49,6 +49,14 @@ struct PhaseK {
     double c, cs2;        // outputs
 };
 
+// Derivatives of the relaxation rates (times dt) with respect to tau and tau_T,
+// in 1/s, and the flux boundary coefficient dt / (dx rho_cp).
+struct AdjK {
+    double dLf[9];
+    double dLt[5];
+    double qgrad;
+};
+
 struct D1K {
     int n, q;
     double w_tau;         // dt / tau
@@ -86,6 +94,15 @@ struct lbm_ctx {
     double k_cond, Dh, dx, rho_cp;
     std::string err;
     uint64_t hash;
+    // adjoint
+    lbm::AdjK ak;
+    double cs2;
+    bool has_record;
+    char* rec_work;
+    size_t rec_bytes;
+    int rec_nsteps, rec_K, rec_nseg;
+    long long rec_t0;
+    lbm_objective rec_obj;
 };
 
 namespace lbm {
@@ -128,5 +145,25 @@ template <typename S>
 hipError_t launch_nusselt(const ChanK& k, const S* f, const S* g, const S* qw, double qsi,
                           double Dh, double kc, double dx, int x_dev, double* Tb, double* Tw,
                           double* Nu, double* small, hipStream_t s);
+
+// ---- discrete adjoint of the heated channel (lbm_adjoint.hip)
+// seed at the final state: lambda_f, lambda_g, and the objective's direct
+// derivatives per column (dq_direct[x], dtauT_direct[x])
+template <typename S>
+hipError_t launch_adj_seed(const ChanK& k, const S* f, const S* g, const S* qw, double qsi,
+                           double mod, double Dh, double kc, double dx, double rho_cp,
+                           double cs2, int x_dev, double w_tout, double w_nu, S* lf, S* lg,
+                           double* dq_direct, double* dtauT_direct, hipStream_t s);
+// one reverse step: lambda(n) from lambda(n+1) and the state at n
+template <typename S>
+hipError_t launch_adj_step(const ChanK& k, const AdjK& a, const S* f, const S* g, const S* lfn,
+                           const S* lgn, S* lf, S* lg, double mod, double* dq_bot,
+                           double* dq_top, double* dtau_acc, hipStream_t s);
+// gradient assembly (fixed order): grad_flux[nx], grad_tau[2]
+hipError_t launch_adj_final(int nx, int ntiles, double scale, const double* dq_bot,
+                            const double* dq_top, const double* dq_direct,
+                            const double* dtauT_direct, const double* dtau_acc,
+                            double* grad_flux, double* grad_tau, hipStream_t s);
+int chan_tiles(const ChanK& k);
 
 }  // namespace lbm

@@ -14,135 +14,13 @@
 // the rows of the lattice matrix by c^order and its inverse's columns by
 // c^-order; a diagonal relaxation commutes with that scaling, so the
 // post-collision populations are the same in either form.
-#include "lbm_internal.h"
+#include "lbm_device.h"
 
 #include <cmath>
 #include <type_traits>
 
 namespace lbm {
 namespace {
-
-// D2Q9: rest, E, N, W, S, NE, NW, SW, SE (Eq. velocity_D2Q9, weights_D2Q9)
-__device__ constexpr int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
-__device__ constexpr int EY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
-__device__ constexpr int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
-template <typename C>
-__device__ __forceinline__ C wgt(int i) {
-    return i == 0 ? C(4) / C(9) : (i < 5 ? C(1) / C(9) : C(1) / C(36));
-}
-// D2Q5 for temperature: rest 1/3, axes 1/6, c_s^2 = c^2/3
-__device__ constexpr int EX5[5] = {0, 1, 0, -1, 0};
-__device__ constexpr int EY5[5] = {0, 0, 1, 0, -1};
-__device__ constexpr int OPP5[5] = {0, 3, 4, 1, 2};
-template <typename C>
-__device__ __forceinline__ C wgt5(int i) {
-    return i == 0 ? C(1) / C(3) : C(1) / C(6);
-}
-
-// m = M v with the integer D2Q9 matrix (rows rho, e, eps, J_x, q_x, J_y, q_y,
-// p_xx, p_xy of Eq. M_matrix), as sums and differences.
-template <typename C>
-__device__ __forceinline__ void moments9(const C v[9], C m[9]) {
-    const C s14 = v[1] + v[2] + v[3] + v[4];
-    const C s58 = v[5] + v[6] + v[7] + v[8];
-    const C x13 = v[1] - v[3], y24 = v[2] - v[4];
-    const C x58 = (v[5] - v[7]) + (v[8] - v[6]);
-    const C y58 = (v[5] - v[7]) + (v[6] - v[8]);
-    m[0] = v[0] + s14 + s58;
-    m[1] = C(-4) * v[0] - s14 + C(2) * s58;
-    m[2] = C(4) * v[0] - C(2) * s14 + s58;
-    m[3] = x13 + x58;
-    m[4] = C(-2) * x13 + x58;
-    m[5] = y24 + y58;
-    m[6] = C(-2) * y24 + y58;
-    m[7] = (v[1] + v[3]) - (v[2] + v[4]);
-    m[8] = (v[5] + v[7]) - (v[6] + v[8]);
-}
-
-// v = M^-1 m = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4) m
-// (rows of M are orthogonal); computed from the exact inverse, not the
-// printed one of App. A.
-template <typename C>
-__device__ __forceinline__ void inverse9(const C m[9], C v[9]) {
-    const C a0 = m[0] * (C(1) / C(9)), a1 = m[1] * (C(1) / C(36)), a2 = m[2] * (C(1) / C(36));
-    const C a3 = m[3] * (C(1) / C(6)), a4 = m[4] * (C(1) / C(12));
-    const C a5 = m[5] * (C(1) / C(6)), a6 = m[6] * (C(1) / C(12));
-    const C a7 = m[7] * C(0.25), a8 = m[8] * C(0.25);
-    const C axis = a0 - a1 - C(2) * a2;     // common part of populations 1..4
-    const C diag = a0 + C(2) * a1 + a2;     // common part of populations 5..8
-    const C jx = a3 - C(2) * a4, jy = a5 - C(2) * a6;
-    const C dx = a3 + a4, dy = a5 + a6;
-    v[0] = a0 - C(4) * a1 + C(4) * a2;
-    v[1] = axis + jx + a7;
-    v[2] = axis + jy - a7;
-    v[3] = axis - jx + a7;
-    v[4] = axis - jy - a7;
-    v[5] = diag + dx + dy + a8;
-    v[6] = diag - dx + dy - a8;
-    v[7] = diag - dx - dy + a8;
-    v[8] = diag + dx - dy - a8;
-}
-
-// D2Q5 basis T, j_x, j_y, e, p_xx
-template <typename C>
-__device__ __forceinline__ void moments5(const C v[5], C m[5]) {
-    const C s = v[1] + v[2] + v[3] + v[4];
-    m[0] = v[0] + s;
-    m[1] = v[1] - v[3];
-    m[2] = v[2] - v[4];
-    m[3] = C(-4) * v[0] + s;
-    m[4] = (v[1] + v[3]) - (v[2] + v[4]);
-}
-template <typename C>
-__device__ __forceinline__ void inverse5(const C m[5], C v[5]) {
-    const C a0 = m[0] * C(0.2), a1 = m[1] * C(0.5), a2 = m[2] * C(0.5);
-    const C a3 = m[3] * C(0.05), a4 = m[4] * C(0.25);
-    v[0] = a0 - C(4) * a3;
-    v[1] = a0 + a1 + a3 + a4;
-    v[2] = a0 + a2 + a3 - a4;
-    v[3] = a0 - a1 + a3 + a4;
-    v[4] = a0 - a2 + a3 - a4;
-}
-
-// error-free transformations for the FP32 hi/lo rest population
-__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
-    s = a + b;
-    const float bb = s - a;
-    e = (a - (s - bb)) + (b - bb);
-}
-__device__ __forceinline__ void df_add(float& hi, float& lo, float b) {
-    float s, e;
-    two_sum(hi, b, s, e);
-    e += lo;
-    hi = s + e;
-    lo = e - (hi - s);
-}
-
-__device__ __forceinline__ int wrap(int v, int n) {
-    if (v < 0) return v + n;
-    if (v >= n) return v - n;
-    return v;
-}
-
-// ---------------------------------------------------------------------------
-// D2Q9 flow + D2Q5 temperature: one node per thread
-// ---------------------------------------------------------------------------
-
-// lattice-normalised macros of one node from its deviation populations
-template <typename C, typename S>
-__device__ __forceinline__ void chan_flow_macros(const S* __restrict__ f, long long P,
-                                                 long long n, C rho_ref, C ftx, C fty,
-                                                 C d[9], C& drho, C& rho, C& ux, C& uy) {
-#pragma unroll
-    for (int i = 0; i < 9; ++i) d[i] = C(f[i * P + n]);
-    drho = ((d[0] + (d[1] + d[3])) + (d[2] + d[4])) + ((d[5] + d[7]) + (d[6] + d[8]));
-    rho = rho_ref + drho;
-    const C jx = (d[1] - d[3]) + ((d[5] - d[7]) + (d[8] - d[6]));
-    const C jy = (d[2] - d[4]) + ((d[5] - d[7]) + (d[6] - d[8]));
-    const C ir = C(1) / rho;
-    ux = (jx + C(0.5) * ftx) * ir;  // Eq. first_moment_f, divided by c
-    uy = (jy + C(0.5) * fty) * ir;
-}
 
 template <typename S>
 __global__ __launch_bounds__(256) void k_chan_step(ChanK k, const S* __restrict__ fc,
@@ -151,10 +29,13 @@ __global__ __launch_bounds__(256) void k_chan_step(ChanK k, const S* __restrict_
                                                    const S* __restrict__ uin,
                                                    const S* __restrict__ tin, S mod) {
     using C = S;
-    const int x = blockIdx.x * 64 + threadIdx.x;
-    const int y = blockIdx.y * 4 + threadIdx.y;
-    const int b = blockIdx.z;
     const int nx = k.nx, ny = k.ny;
+    const int gx = (nx + 63) / 64, gy = (ny + 3) / 4;
+    int tile;
+    if (!xcd_tile(gx * gy * k.batch, tile)) return;
+    const int b = tile / (gx * gy), r = tile - b * gx * gy;
+    const int x = (r % gx) * 64 + threadIdx.x;
+    const int y = (r / gx) * 4 + threadIdx.y;
     if (x >= nx || y >= ny) return;
     const long long P = k.P;
     const long long base = (long long)b * ny * nx;
@@ -297,7 +178,11 @@ __global__ __launch_bounds__(256) void k_chan_step(ChanK k, const S* __restrict_
 // Buffer planes: 0-8 h_i, 9-17 z_i, 18 low part of h_0 (FP32 storage only).
 // ---------------------------------------------------------------------------
 
-constexpr int TX = 64, TY = 4;
+#ifndef LBM_PHASE_TY
+#define LBM_PHASE_TY 8
+#endif
+constexpr int TX = 64, TY = LBM_PHASE_TY;
+static_assert(2 * (TX + 2) + 2 * TY <= TX * TY, "the ring must fit in one pass of the block");
 
 template <typename S, typename C>
 __device__ __forceinline__ C node_phi(const S* __restrict__ h, const S* __restrict__ hlo,
@@ -310,7 +195,7 @@ __device__ __forceinline__ C node_phi(const S* __restrict__ h, const S* __restri
 }
 
 template <typename S, typename C, bool MACROS>
-__global__ __launch_bounds__(256) void k_phase(PhaseK k, const S* __restrict__ hc,
+__global__ __launch_bounds__(TX * TY) void k_phase(PhaseK k, const S* __restrict__ hc,
                                                S* __restrict__ hn, const S* __restrict__ zc,
                                                S* __restrict__ zn, S* __restrict__ phiu,
                                                double* __restrict__ mout) {
@@ -319,8 +204,11 @@ __global__ __launch_bounds__(256) void k_phase(PhaseK k, const S* __restrict__ h
     const int nx = k.nx, ny = k.ny;
     const long long P = k.P;
     const int tx = threadIdx.x, ty = threadIdx.y;
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
-    const int b = blockIdx.z;
+    const int gx = (nx + TX - 1) / TX, gy = (ny + TY - 1) / TY;
+    int tile;
+    if (!xcd_tile(gx * gy * k.batch, tile)) return;  // whole workgroup, before any barrier
+    const int b = tile / (gx * gy), r = tile - b * gx * gy;
+    const int x0 = (r % gx) * TX, y0 = (r / gx) * TY;
     const long long base = (long long)b * ny * nx;
     const S* hlo_c = RMASS ? hc + 18 * P : nullptr;  // h_0 low part (plane 18)
     auto gxw = [&](int gx) { return ((gx % nx) + nx) % nx; };
@@ -328,29 +216,43 @@ __global__ __launch_bounds__(256) void k_phase(PhaseK k, const S* __restrict__ h
         if (k.bcy) return gy < 0 ? 0 : (gy >= ny ? ny - 1 : gy);  // mirror ghost at walls
         return ((gy % ny) + ny) % ny;
     };
-    // interior entries (computed for the wrapped position even outside the grid)
+    // Every load of the tile is issued before the barrier: the node's own h, z
+    // and (phi u) (kept in registers for the collision) and, for 140 threads,
+    // the 10 values of one ring node; the barrier then waits for memory once.
     const int x = x0 + tx, y = y0 + ty;
     const bool valid = x < nx && y < ny;
-    {
-        const long long nn = base + (long long)gyw(y) * nx + gxw(x);
-        sphi[ty + 1][tx + 1] = node_phi<S, C>(hc, hlo_c, P, nn);
+    const long long n = base + (long long)gyw(y) * nx + gxw(x);  // == own node when valid
+    C h[9], z[9], hlo = C(0), pu0 = C(0), pu1 = C(0);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) h[i] = C(hc[i * P + n]);
+    if (RMASS) hlo = C(hlo_c[n]);
+    if (valid) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) z[i] = C(zc[i * P + n]);
+        if constexpr (!MACROS) {
+            pu0 = C(phiu[n]);
+            pu1 = C(phiu[P + n]);
+        }
     }
-    // ring of 2 * (TX + 2) + 2 * TY = 140 entries
+    int hx = -2, hy = -2;
     {
         const int t = ty * TX + tx;
-        int hx = -2, hy = -2;
         if (t < TX + 2) { hy = -1; hx = t - 1; }
         else if (t < 2 * (TX + 2)) { hy = TY; hx = t - (TX + 2) - 1; }
         else if (t < 2 * (TX + 2) + TY) { hx = -1; hy = t - 2 * (TX + 2); }
         else if (t < 2 * (TX + 2) + 2 * TY) { hx = TX; hy = t - 2 * (TX + 2) - TY; }
-        if (hx > -2) {
-            const long long nn = base + (long long)gyw(y0 + hy) * nx + gxw(x0 + hx);
-            sphi[hy + 1][hx + 1] = node_phi<S, C>(hc, hlo_c, P, nn);
-        }
     }
+    C ring = C(0);
+    if (hx > -2) {
+        const long long nn = base + (long long)gyw(y0 + hy) * nx + gxw(x0 + hx);
+        ring = node_phi<S, C>(hc, hlo_c, P, nn);
+    }
+    // phi of the node, Eq. zero_moment_h (rest population with its low part)
+    const C phi_own = (h[0] + hlo) + (((h[1] + h[3]) + (h[2] + h[4])) + ((h[5] + h[7]) + (h[6] + h[8])));
+    sphi[ty + 1][tx + 1] = phi_own;
+    if (hx > -2) sphi[hy + 1][hx + 1] = ring;
     __syncthreads();
     if (!valid) return;
-    const long long n = base + (long long)y * nx + x;
 
     // ---- stencils, Eq. gradient and Eq. laplacian in lattice form:
     //      grad phi = 3 G / dx, lap phi = 6 L / dx^2
@@ -382,9 +284,6 @@ __global__ __launch_bounds__(256) void k_phase(PhaseK k, const S* __restrict__ h
         nyv = Gy * ig;
     }
     // ---- pressure populations: velocity first (Eq. u_Liang), then pressure
-    C z[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) z[i] = C(zc[i * P + n]);
     const C jx = (z[1] - z[3]) + ((z[5] - z[7]) + (z[8] - z[6]));
     const C jy = (z[2] - z[4]) + ((z[5] - z[7]) + (z[6] - z[8]));
     const C ir = C(1) / rho;
@@ -409,13 +308,10 @@ __global__ __launch_bounds__(256) void k_phase(PhaseK k, const S* __restrict__ h
     } else {
         // ---- interface populations (Eq. eq_lattice_boltzmann_interface,
         //      source_term_interface, heq_liang); d(phi u)/dt by explicit Euler
-        C h[9];
-#pragma unroll
-        for (int i = 0; i < 9; ++i) h[i] = C(hc[i * P + n]);
         const C pux = phi * ux, puy = phi * uy;
-        const C dpx = pux - C(phiu[n]), dpy = puy - C(phiu[P + n]);
-        phiu[n] = S(pux);
-        phiu[P + n] = S(puy);
+        const C dpx = pux - pu0, dpy = puy - pu1;
+        st(phiu + n, S(pux));
+        st(phiu + P + n, S(puy));
         const C wphi = C(k.w_phi);
         const C sfac = C(1) - C(0.5) * wphi;
         const C sharp = C(4) * phi * (C(1) - phi) * C(k.dxW);
@@ -433,9 +329,9 @@ __global__ __launch_bounds__(256) void k_phase(PhaseK k, const S* __restrict__ h
         if constexpr (RMASS) {
             // rest population takes the node's exact balance: h0* = phi - sum_{i>0} h_i*
             // with the stored (rounded) h_i*, carried as a double-float
-            float hi = hc[n], lo = hc[18 * P + n];
+            float hi = float(h[0]), lo = float(hlo);
 #pragma unroll
-            for (int i = 1; i < 9; ++i) df_add(hi, lo, float(hc[i * P + n]));
+            for (int i = 1; i < 9; ++i) df_add(hi, lo, float(h[i]));
 #pragma unroll
             for (int i = 1; i < 9; ++i) df_add(hi, lo, -float(hs[i]));
             h0hi = hi;
@@ -480,21 +376,21 @@ __global__ __launch_bounds__(256) void k_phase(PhaseK k, const S* __restrict__ h
             }
         }
         // ---- streaming: x periodic; y periodic or halfway bounce-back walls
-        hn[n] = h0hi;
-        if constexpr (RMASS) hn[18 * P + n] = h0lo;
-        zn[n] = S(zst[0]);
+        st(hn + n, h0hi);
+        if constexpr (RMASS) st(hn + 18 * P + n, h0lo);
+        st(zn + n, S(zst[0]));
 #pragma unroll
         for (int i = 1; i < 9; ++i) {
             const int txd = wrap(x + EX[i], nx);
             int tyd = y + EY[i];
             if (k.bcy && (tyd < 0 || tyd >= ny)) {
-                hn[OPP[i] * P + n] = S(hs[i]);
-                zn[OPP[i] * P + n] = S(zst[i]);
+                st(hn + OPP[i] * P + n, S(hs[i]));
+                st(zn + OPP[i] * P + n, S(zst[i]));
             } else {
                 tyd = wrap(tyd, ny);
                 const long long d = base + (long long)tyd * nx + txd;
-                hn[i * P + d] = S(hs[i]);
-                zn[i * P + d] = S(zst[i]);
+                st(hn + i * P + d, S(hs[i]));
+                st(zn + i * P + d, S(zst[i]));
             }
         }
     }
@@ -790,7 +686,8 @@ inline unsigned grid1(long long N, int bs) {
 template <typename S>
 hipError_t launch_chan_step(const ChanK& k, const S* fc, S* fn, const S* gc, S* gn, const S* qw,
                             const S* uin, const S* tin, double mod, hipStream_t s) {
-    dim3 blk(64, 4), grd((k.nx + 63) / 64, (k.ny + 3) / 4, k.batch);
+    const long long tiles = (long long)((k.nx + 63) / 64) * ((k.ny + 3) / 4) * k.batch;
+    dim3 blk(64, 4), grd(unsigned((tiles + kXCD - 1) / kXCD * kXCD));
     hipLaunchKernelGGL(k_chan_step<S>, grd, blk, 0, s, k, fc, fn, gc, gn, qw, uin, tin, S(mod));
     return hipGetLastError();
 }
@@ -798,7 +695,8 @@ hipError_t launch_chan_step(const ChanK& k, const S* fc, S* fn, const S* gc, S* 
 template <typename S>
 hipError_t launch_phase_step(const PhaseK& k, const S* hc, S* hn, const S* zc, S* zn, S* phiu,
                              hipStream_t s) {
-    dim3 blk(TX, TY), grd((k.nx + TX - 1) / TX, (k.ny + TY - 1) / TY, k.batch);
+    const long long tiles = (long long)((k.nx + TX - 1) / TX) * ((k.ny + TY - 1) / TY) * k.batch;
+    dim3 blk(TX, TY), grd(unsigned((tiles + kXCD - 1) / kXCD * kXCD));
     hipLaunchKernelGGL((k_phase<S, S, false>), grd, blk, 0, s, k, hc, hn, zc, zn, phiu,
                        (double*)nullptr);
     return hipGetLastError();
@@ -841,7 +739,8 @@ hipError_t launch_chan_macros(const ChanK& k, const S* f, const S* g, double* ou
 template <typename S>
 hipError_t launch_phase_macros(const PhaseK& k, const S* h, const S* z, double* out,
                                hipStream_t s) {
-    dim3 blk(TX, TY), grd((k.nx + TX - 1) / TX, (k.ny + TY - 1) / TY, k.batch);
+    const long long tiles = (long long)((k.nx + TX - 1) / TX) * ((k.ny + TY - 1) / TY) * k.batch;
+    dim3 blk(TX, TY), grd(unsigned((tiles + kXCD - 1) / kXCD * kXCD));
     hipLaunchKernelGGL((k_phase<S, double, true>), grd, blk, 0, s, k, h, (S*)nullptr, z,
                        (S*)nullptr, (S*)nullptr, out);
     return hipGetLastError();

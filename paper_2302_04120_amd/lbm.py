@@ -30,7 +30,8 @@ MACRO_BITS = {"rho": 1, "p": 2, "ux": 4, "uy": 8, "T": 16, "phi": 32, "mu": 64}
 REDUCE_BITS = {"mass": 1, "phase": 2, "energy": 4, "nonfinite": 8}
 
 EXPORTS = ("lbm_query_bytes", "lbm_create", "lbm_destroy", "lbm_set_params_SI",
-           "lbm_init_fields", "lbm_step", "lbm_macros", "lbm_reduce", "lbm_nusselt", "lbm_time",
+           "lbm_init_fields", "lbm_step", "lbm_macros", "lbm_reduce", "lbm_nusselt",
+           "lbm_query_record_bytes", "lbm_record", "lbm_grad", "lbm_time",
            "lbm_save_state", "lbm_load_state", "lbm_last_error")
 
 
@@ -47,6 +48,10 @@ class Desc(C.Structure):
 
 
 _dp = C.POINTER(C.c_double)
+
+
+class Objective(C.Structure):
+    _fields_ = [("x_dev", C.c_int), ("w_tout", C.c_double), ("w_nu", C.c_double)]
 
 
 class ParamsSI(C.Structure):
@@ -92,8 +97,11 @@ def lib():
         L.lbm_load_state.argtypes = [vp, vp, C.c_size_t]
         L.lbm_last_error.argtypes = [vp]
         L.lbm_last_error.restype = C.c_char_p
-        for name in EXPORTS[:-3]:
-            if name not in ("lbm_destroy", "lbm_time"):
+        L.lbm_query_record_bytes.argtypes = [vp, C.c_int, C.c_int, C.POINTER(C.c_size_t)]
+        L.lbm_record.argtypes = [vp, C.c_int, C.c_int, C.POINTER(Objective), vp, C.c_size_t, _dp]
+        L.lbm_grad.argtypes = [vp, C.c_double, _dp, _dp]
+        for name in EXPORTS:
+            if name not in ("lbm_destroy", "lbm_time", "lbm_last_error"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -268,6 +276,29 @@ class Lattice:
         self._check(lib().lbm_nusselt(self.ctx, int(x_dev), _ptr(Tb), _ptr(Tw), _ptr(Nu),
                                       C.byref(nm), C.byref(to)))
         return Tb, Tw, Nu, nm.value, to.value
+
+    def record(self, nsteps, ckpt_every, x_dev, w_tout=1.0, w_nu=1.0):
+        """Run nsteps keeping checkpoints for the adjoint; returns J."""
+        nbytes = C.c_size_t()
+        self._check(lib().lbm_query_record_bytes(self.ctx, int(nsteps), int(ckpt_every),
+                                                 C.byref(nbytes)))
+        if getattr(self, "_work", None) is None or self._work.numel() < nbytes.value:
+            self._work = None
+            self._work = self.torch.empty(int(nbytes.value), dtype=self.torch.uint8,
+                                          device=self.device)
+        obj = Objective(int(x_dev), float(w_tout), float(w_nu))
+        J = C.c_double()
+        self._check(lib().lbm_record(self.ctx, int(nsteps), int(ckpt_every), C.byref(obj),
+                                     C.c_void_p(self._work.data_ptr()), self._work.numel(),
+                                     C.byref(J)))
+        return J.value
+
+    def grad(self, dL_dJ=1.0):
+        """Discrete adjoint of the last record(): (dJ/dflux[nx], dJ/dtau[2])."""
+        gq = np.zeros(self.nx)
+        gt = np.zeros(2)
+        self._check(lib().lbm_grad(self.ctx, float(dL_dJ), _ptr(gq), _ptr(gt)))
+        return gq, gt
 
     def save_state(self):
         n = C.c_size_t()

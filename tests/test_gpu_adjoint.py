@@ -1,0 +1,154 @@
+"""GPU discrete adjoint (through the C ABI) against the FP64 oracle's
+adjoint and against central finite differences of FP64 GPU forward runs."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2302_04120_amd import workloads as WL
+
+from gpu_cases import print_case
+
+pytestmark = pytest.mark.gpu
+
+
+def _lattice(prm, ini, nx, ny, prec):
+    from paper_2302_04120_amd import lbm
+    L = lbm.Lattice("channel", nx, ny, prec=prec,
+                    bc=(lbm.BC_VEL_INLET, lbm.BC_P_OUTLET, lbm.BC_WALL, lbm.BC_WALL),
+                    flow=True, thermal=True)
+    L.set_params(prm)
+    L.init(ini["rho"], ini["ux"], ini["uy"], ini["T"])
+    return L
+
+
+def _case(nx, ny, dx, seed=1, oscillating=False):
+    prm, ini = WL.adjoint_channel(nx=nx, ny=ny, dx=dx, tau_ratio=0.7, oscillating=oscillating)
+    prm["flux"] = WL.rng(seed).uniform(5e3, 1.5e4, nx)
+    return prm, ini
+
+
+def _oracle_adjoint(prm, ini, nx, ny, steps, ckpt):
+    o = O.Chan(nx, ny, prm, bc_x="inlet_outlet", bc_y="walls", thermal=True)
+    o.init(**ini)
+    return o.adjoint(steps, ckpt, nx // 2)
+
+
+def _rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+@pytest.mark.parametrize("nx,ny,steps,ckpt,osc", [(16, 6, 300, 64, False), (70, 12, 400, 64, True)])
+def test_adjoint_fp64_matches_oracle_adjoint(nx, ny, steps, ckpt, osc):
+    print_case(test="adj_fp64", nx=nx, ny=ny, steps=steps)
+    prm, ini = _case(nx, ny, 1e-4, oscillating=osc)
+    if osc:
+        prm["flux_omega"] = 2 * np.pi / (97 * prm["dt"])
+    J0, gq0, gt0 = _oracle_adjoint(prm, ini, nx, ny, steps, ckpt)
+    L = _lattice(prm, ini, nx, ny, "fp64")
+    J = L.record(steps, ckpt, nx // 2)
+    gq, gt = L.grad()
+    print("J", J, J0, "flux rel", _rel(gq, gq0), "tau", gt, gt0, flush=True)
+    # the start-up objective (flow from rest) amplifies FP64 rounding-order
+    # differences to ~1e-11 in J and ~1e-9 in the gradient
+    assert J == pytest.approx(J0, rel=1e-10)
+    assert _rel(gq, gq0) < 1e-8
+    np.testing.assert_allclose(gt, gt0, rtol=1e-8)
+
+
+def test_adjoint_fp32_matches_oracle_adjoint():
+    nx, ny, steps = 70, 12, 400
+    print_case(test="adj_fp32")
+    prm, ini = _case(nx, ny, 1e-4)
+    J0, gq0, gt0 = _oracle_adjoint(prm, ini, nx, ny, steps, 64)
+    L = _lattice(prm, ini, nx, ny, "fp32")
+    J = L.record(steps, 64, nx // 2)
+    gq, gt = L.grad()
+    print("J", J, J0, "flux rel", _rel(gq, gq0), "tau", gt, gt0, flush=True)
+    assert J == pytest.approx(J0, rel=1e-6)
+    assert _rel(gq, gq0) < 1e-4
+    np.testing.assert_allclose(gt, gt0, rtol=1e-3)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32", 1e-4)])
+def test_adjoint_c5_copy_200x10(prec, tol):
+    """The C5 channel's 200 x 10 copy (same spacing, properties and inlet
+    speed), 2000 steps with a checkpoint every 500, against the FP64 CPU
+    adjoint."""
+    print_case(test="adj_c5_copy", prec=prec)
+    prm, ini = WL.adjoint_channel(nx=200, ny=10)
+    J0, gq0, gt0 = _oracle_adjoint(prm, ini, 200, 10, 2000, 500)
+    L = _lattice(prm, ini, 200, 10, prec)
+    J = L.record(2000, 500, 100)
+    gq, gt = L.grad()
+    print("J", J, J0, "flux rel", _rel(gq, gq0), "tau", gt, gt0, flush=True)
+    assert _rel(gq, gq0) < tol
+    np.testing.assert_allclose(gt, gt0, rtol=max(tol, 1e-8) * 10)
+
+
+def test_autograd_function_matches_lbm_grad():
+    import torch
+    from paper_2302_04120_amd.adjoint import ChannelAdjoint
+    print_case(test="autograd")
+    nx, ny = 40, 8
+    prm, ini = _case(nx, ny, 1e-4)
+    prob = ChannelAdjoint(prm, ini, nx, ny, nsteps=200, ckpt_every=50, prec="fp64")
+    flux = torch.tensor(prm["flux"], dtype=torch.float64, requires_grad=True)
+    tau = torch.tensor(prob.tau_of(), dtype=torch.float64, requires_grad=True)
+    J = prob.J(flux, tau)
+    (2.0 * J).backward()
+    J0, gq0, gt0 = _oracle_adjoint(prm, ini, nx, ny, 200, 50)
+    assert float(J) == pytest.approx(J0, rel=1e-12)
+    assert _rel(flux.grad.numpy(), 2 * gq0) < 1e-9
+    np.testing.assert_allclose(tau.grad.numpy(), 2 * gt0, rtol=1e-8)
+
+
+def test_adjoint_c5_full_size_vs_finite_differences():
+    """C5 at its full 1600 x 80 size, 20 000 steps, checkpoint every 500:
+    FP32 and FP64 adjoint gradients against central differences of FP64
+    forward runs on 16 seeded flux nodes of the downstream half and on both
+    relaxation times.  Step h = 1e-4 relative (the objective's curvature makes
+    the truncation error of h = 1e-3 reach 1e-3 relative at some nodes)."""
+    nx, ny, steps, ckpt = 1600, 80, 20000, 500
+    prm, ini = WL.adjoint_channel()
+    x_dev = nx // 2
+    nodes = np.sort(WL.rng(0).choice(np.arange(x_dev, nx), 16, replace=False))
+    print_case(test="c5_full", nodes=list(nodes))
+    grads = {}
+    for prec in ("fp64", "fp32"):
+        L = _lattice(prm, ini, nx, ny, prec)
+        J = L.record(steps, ckpt, x_dev)
+        grads[prec] = (J,) + L.grad()
+        del L
+    L = _lattice(prm, ini, nx, ny, "fp64")
+
+    def J_of(p):
+        L.set_params(p)
+        L.init(ini["rho"], ini["ux"], ini["uy"], ini["T"])
+        L.step(steps)
+        _, _, _, nm, tout = L.nusselt(x_dev)
+        return tout + nm
+
+    fd = []
+    for k in nodes:
+        h = 1e-4 * prm["flux"][k]
+        fp, fm = prm["flux"].copy(), prm["flux"].copy()
+        fp[k] += h
+        fm[k] -= h
+        fd.append((J_of(dict(prm, flux=fp)) - J_of(dict(prm, flux=fm))) / (2 * h))
+    fd = np.array(fd)
+    c = prm["dx"] / prm["dt"]
+    cs2 = c * c / 3
+    fdt = []
+    for key in ("nu", "alpha"):
+        tau = prm[key] / cs2 + prm["dt"] / 2
+        h = 1e-5 * tau
+        Jp = J_of(dict(prm, **{key: (tau + h - prm["dt"] / 2) * cs2}))
+        Jm = J_of(dict(prm, **{key: (tau - h - prm["dt"] / 2) * cs2}))
+        fdt.append((Jp - Jm) / (2 * h))
+    for prec, (J, gq, gt) in grads.items():
+        e_q = np.abs(gq[nodes] - fd).max() / np.abs(fd).max()
+        e_t = np.abs(gt - np.array(fdt)) / np.abs(np.array(fdt))
+        print(prec, "J", J, "flux grad rel err vs FD", e_q, "tau rel err", e_t, flush=True)
+        assert e_q < 1e-4
+        assert e_t.max() < 1e-3
