@@ -25,6 +25,20 @@ HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per lattice update (each population read once and written
 # once): z 9 + h 9 + low part of h_0 + (phi u) 2, read + write
 BYTES_PER_LU = {"fp32": (9 + 9 + 1 + 2) * 4 * 2, "fp64": (9 + 9 + 2) * 8 * 2}
+# the files whose contents decide the step kernel's machine code
+KERNEL_SOURCES = ("paper_2302_04120_amd/csrc/lbm_kernels.hip", "paper_2302_04120_amd/csrc/lbm_device.h",
+                  "paper_2302_04120_amd/csrc/lbm_internal.h", "paper_2302_04120_amd/csrc/build.py")
+
+
+def kernel_source_hash():
+    """SHA-256 over the step kernel's sources and build flags: the counter
+    traffic stored beside the profiles is reported only while it matches."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def log(*a):
@@ -154,7 +168,8 @@ def main():
     if os.path.exists(args.traffic):
         with open(args.traffic) as f:
             tr = json.load(f)
-        if tr.get("batch") == args.batch and tr.get("prec") == args.prec:
+        if (tr.get("batch") == args.batch and tr.get("prec") == args.prec
+                and tr.get("source_sha256") == kernel_source_hash()):
             traffic = tr.get("bytes_per_launch")
     extras = {}
     if not args.no_extras:

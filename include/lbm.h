@@ -148,8 +148,22 @@ LBM_API lbm_status lbm_init_fields(lbm_ctx* ctx, const double* rho_or_p, const d
 
 /* Enqueue n time steps (collide + stream + boundary rules, Eq.
  * eq_lattice_boltzmann_geral).  Asynchronous: a non-finite state is reported
- * by lbm_reduce. */
+ * by lbm_reduce.  When n is at least twice the graph step count (see
+ * lbm_set_graph_steps), runs of that many steps are enqueued as one replay
+ * of a HIP graph captured from the same kernel launches (bit-identical
+ * results, one launch instead of many on small grids); the remainder and
+ * every step whose arguments change with time (the oscillating wall flux)
+ * are launched one by one.  No replay is used while desc.hip_stream is being
+ * captured by the caller. */
 LBM_API lbm_status lbm_step(lbm_ctx* ctx, int n);
+
+/* Steps per captured graph used by lbm_step (default 64; 0 disables graph
+ * replay; otherwise even, at most 4096).  Graphs are captured lazily on a
+ * library-owned stream, one per population-buffer parity, dropped when the
+ * count or the parameters change, and released by lbm_destroy.  Not an
+ * operation of the paper: a launch-overhead control for small grids.
+ * LBM_E_ARG on an odd, negative or too large count. */
+LBM_API lbm_status lbm_set_graph_steps(lbm_ctx* ctx, int steps);
 
 /* Macroscopic fields of the current state, evaluated in FP64 from the stored
  * populations.  mask selects fields; out receives them in bit order, each

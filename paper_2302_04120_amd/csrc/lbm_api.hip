@@ -155,6 +155,63 @@ hipError_t step_once(lbm_ctx* c) {
     return launch_phase_step<S>(c->pk, a, b, a + 9 * P, b + 9 * P, (S*)c->phiu, c->stream);
 }
 
+void drop_graphs(lbm_ctx* c) {
+    for (hipGraphExec_t& g : c->step_graph) {
+        if (g) (void)hipGraphExecDestroy(g);
+        g = nullptr;
+    }
+}
+
+// A captured run of steps replays its kernel arguments unchanged, so it is
+// only valid while no argument depends on the step count (the oscillating
+// wall flux does) and while the caller's stream is not itself capturing.
+bool graph_usable(lbm_ctx* c) {
+    if (c->graph_steps <= 0) return false;
+    if (c->desc.lattice == LBM_D2Q9_D2Q5 && c->ck.thermal && c->flux_amp != 0.0) return false;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(c->stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+        return false;
+    return true;
+}
+
+// Enqueue graph_steps steps as one graph launch.  The graph for the current
+// buffer parity is captured on first use; graph_steps is even, so the state
+// ends in the buffer it started in.
+template <typename S>
+hipError_t step_replay(lbm_ctx* c) {
+    hipGraphExec_t& ex = c->step_graph[c->cur];
+    if (!ex) {
+        hipError_t e = hipSuccess;
+        if (!c->cap_stream) e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return e;
+        e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return e;
+        const hipStream_t user = c->stream;
+        const int cur0 = c->cur;
+        c->stream = c->cap_stream;
+        hipError_t el = hipSuccess;
+        for (int k = 0; k < c->graph_steps && el == hipSuccess; ++k) {
+            el = step_once<S>(c);
+            c->cur ^= 1;
+        }
+        c->stream = user;
+        c->cur = cur0;
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(c->cap_stream, &g);
+        if (el != hipSuccess || e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return el != hipSuccess ? el : e;
+        }
+        e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            ex = nullptr;
+            return e;
+        }
+    }
+    return hipGraphLaunch(ex, c->stream);
+}
+
 template <typename S>
 hipError_t upload_aux(lbm_ctx* c, const lbm_params_si* p) {
     const int nx = c->desc.nx, ny = c->desc.ny;
@@ -219,7 +276,27 @@ lbm_status lbm_create(const lbm_desc* desc, lbm_ctx** out) {
     return LBM_OK;
 }
 
-void lbm_destroy(lbm_ctx* ctx) { delete ctx; }
+void lbm_destroy(lbm_ctx* ctx) {
+    if (!ctx) return;
+    {
+        DeviceGuard g(ctx->device);
+        drop_graphs(ctx);
+        if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    }
+    delete ctx;
+}
+
+lbm_status lbm_set_graph_steps(lbm_ctx* c, int steps) {
+    if (!c) return LBM_E_ARG;
+    if (steps < 0 || steps > 4096 || (steps & 1))
+        return set_err(c, LBM_E_ARG, "graph steps must be 0 or an even number up to 4096");
+    if (steps != c->graph_steps) {
+        DeviceGuard g(c->device);
+        drop_graphs(c);
+        c->graph_steps = steps;
+    }
+    return LBM_OK;
+}
 
 const char* lbm_last_error(const lbm_ctx* ctx) { return ctx ? ctx->err.c_str() : "NULL context"; }
 
@@ -353,6 +430,10 @@ lbm_status lbm_set_params_SI(lbm_ctx* c, const lbm_params_si* p) {
         hipError_t e = d.prec == LBM_FP64 ? upload_aux<double>(c, p) : upload_aux<float>(c, p);
         if (e != hipSuccess) return hip_fail(c, e, "upload of flux/inlet arrays");
     }
+    {
+        DeviceGuard g(c->device);
+        drop_graphs(c);  // captured kernel arguments are stale now
+    }
     c->has_params = true;
     return LBM_OK;
 }
@@ -422,7 +503,15 @@ lbm_status lbm_step(lbm_ctx* c, int n) {
         c->t += n;
         return LBM_OK;
     }
-    for (int s = 0; s < n; ++s) {
+    int s = 0;
+    if (n >= 2 * c->graph_steps && graph_usable(c)) {
+        for (; s + c->graph_steps <= n; s += c->graph_steps) {
+            hipError_t e = c->desc.prec == LBM_FP64 ? step_replay<double>(c) : step_replay<float>(c);
+            if (e != hipSuccess) return hip_fail(c, e, "step graph");
+            c->t += c->graph_steps;
+        }
+    }
+    for (; s < n; ++s) {
         hipError_t e = c->desc.prec == LBM_FP64 ? step_once<double>(c) : step_once<float>(c);
         if (e != hipSuccess) return hip_fail(c, e, "step kernel");
         c->cur ^= 1;

@@ -103,6 +103,11 @@ struct lbm_ctx {
     int rec_nsteps, rec_K, rec_nseg;
     long long rec_t0;
     lbm_objective rec_obj;
+    // step replay: graph_steps (even) steps captured once per buffer parity
+    // on a private stream and replayed on `stream`; 0 disables
+    int graph_steps = 64;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t step_graph[2] = {nullptr, nullptr};
 };
 
 namespace lbm {

@@ -174,14 +174,30 @@ __global__ __launch_bounds__(256) void k_chan_step(ChanK k, const S* __restrict_
 
 // ---------------------------------------------------------------------------
 // Two-phase step: conservative Allen-Cahn h_i (BGK) + pressure z_i (MRT/BGK)
-// Tile of 64 x 4 nodes per block; phi of the tile and a one-node ring in LDS.
+// Tile of 64 x TY nodes per block; phi of the tile and a one-node ring in LDS.
 // Buffer planes: 0-8 h_i, 9-17 z_i, 18 low part of h_0 (FP32 storage only).
 // ---------------------------------------------------------------------------
 
 #ifndef LBM_PHASE_TY
 #define LBM_PHASE_TY 8
 #endif
+// optional occupancy target (waves per SIMD) for the step kernel; 0 = compiler's choice
+#ifndef LBM_PHASE_WPE
+#define LBM_PHASE_WPE 0
+#endif
+#if LBM_PHASE_WPE > 0
+#define LBM_PHASE_OCC __attribute__((amdgpu_waves_per_eu(LBM_PHASE_WPE)))
+#else
+#define LBM_PHASE_OCC
+#endif
 constexpr int TX = 64, TY = LBM_PHASE_TY;
+// LDS reserved by each FP32 step workgroup beyond its own 2.6 KB: it holds
+// residency at two 512-thread workgroups per CU (4 waves per SIMD).  With
+// more waves resident, more of the 42 population streams per wave are open
+// in DRAM at once and the step runs slower (67M-node bubble batch: 2.82 ms
+// at 8 waves per SIMD, 2.56 ms at 4).  The FP64 kernel's register use
+// already gives 4 waves per SIMD.
+constexpr unsigned kPhaseLdsReserve = 61440;
 static_assert(2 * (TX + 2) + 2 * TY <= TX * TY, "the ring must fit in one pass of the block");
 
 template <typename S, typename C>
@@ -195,7 +211,7 @@ __device__ __forceinline__ C node_phi(const S* __restrict__ h, const S* __restri
 }
 
 template <typename S, typename C, bool MACROS>
-__global__ __launch_bounds__(TX * TY) void k_phase(PhaseK k, const S* __restrict__ hc,
+__global__ __launch_bounds__(TX * TY) LBM_PHASE_OCC void k_phase(PhaseK k, const S* __restrict__ hc,
                                                S* __restrict__ hn, const S* __restrict__ zc,
                                                S* __restrict__ zn, S* __restrict__ phiu,
                                                double* __restrict__ mout) {
@@ -340,55 +356,47 @@ __global__ __launch_bounds__(TX * TY) void k_phase(PhaseK k, const S* __restrict
             const C heq0 = phi * wgt<C>(0);
             h0hi = S(h[0] - wphi * (h[0] - heq0));
         }
-        // ---- pressure collision
-        C zst[9];
+        // ---- pressure collision in moment space.  The moments of z_i^eq
+        //      (Eq. zeq_liang with Eq. s_i_Liang) and of dt F^z_i (Eq.
+        //      forcing_term_pressure_evolution) under the integer matrix of
+        //      Eq. M_matrix, in closed form:
+        //        m^eq = (0, 2 p~ + 3 rho u^2, -3 (p~ + rho u^2), rho u_x, -rho u_x,
+        //                rho u_y, -rho u_y, rho (u_x^2 - u_y^2), rho u_x u_y)
+        //        m^F  = (3 D, 0, -3 D, F_x, -F_x, F_y, -F_y,
+        //                2 drho (G_x u_x - G_y u_y), drho (G_x u_y + G_y u_x))
+        //      with p~ = p / c_s^2, D = drho (u . G) and every velocity in units
+        //      of c.  BGK is the same update with every rate equal to dt/tau.
+        C m[9];
+        moments9(z, m);
         {
-            C zeq[9], fz[9];
-            const C fx = fsx, fy = fsy;
+            const C ruu = rho * uu, D = drl * ug;
+            const C meq[9] = {C(0), C(2) * ph + C(3) * ruu, C(-3) * (ph + ruu), rho * ux, -rho * ux,
+                              rho * uy, -rho * uy, rho * (ux * ux - uy * uy), rho * ux * uy};
+            const C mf[9] = {C(3) * D, C(0), C(-3) * D, fsx, -fsx, fsy, -fsy,
+                             C(2) * drl * (Gx * ux - Gy * uy), drl * (Gx * uy + Gy * ux)};
+            const C wq = C(3) * (C(2) - wn) / (C(3) - wn);
+            const C Lm[9] = {C(1), C(1), C(1), C(1), wq, C(1), k.qy_printed ? C(1) : wq, wn, wn};
 #pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                const C eu = C(EX[i]) * ux + C(EY[i]) * uy;
-                const C eg = C(EX[i]) * Gx + C(EY[i]) * Gy;
-                const C w = wgt<C>(i);
-                // Eq. zeq_liang with Eq. s_i_Liang
-                zeq[i] = ph * (i == 0 ? w - C(1) : w) +
-                         rho * w * (C(3) * eu + C(4.5) * eu * eu - C(1.5) * uu);
-                // dt * F^z_i of Eq. forcing_term_pressure_evolution without prefactor
-                fz[i] = w * (C(3) * (C(EX[i]) * fx + C(EY[i]) * fy) + C(9) * drl * eu * eg);
-            }
-            if (k.z_mrt) {
-                C mz[9], me[9], mf[9], dm[9], dv[9];
-                moments9(z, mz);
-                moments9(zeq, me);
-                moments9(fz, mf);
-                const C wq = C(3) * (C(2) - wn) / (C(3) - wn);
-                C L[9] = {C(1), C(1), C(1), C(1), wq, C(1), k.qy_printed ? C(1) : wq, wn, wn};
-#pragma unroll
-                for (int q = 0; q < 9; ++q)
-                    dm[q] = -L[q] * (mz[q] - me[q]) + (C(1) - C(0.5) * L[q]) * mf[q];
-                inverse9(dm, dv);
-#pragma unroll
-                for (int i = 0; i < 9; ++i) zst[i] = z[i] + dv[i];
-            } else {
-#pragma unroll
-                for (int i = 0; i < 9; ++i)
-                    zst[i] = z[i] - wn * (z[i] - zeq[i]) + (C(1) - C(0.5) * wn) * fz[i];
+            for (int q = 0; q < 9; ++q) {
+                const C L = k.z_mrt ? Lm[q] : wn;
+                m[q] += -L * (m[q] - meq[q]) + (C(1) - C(0.5) * L) * mf[q];
             }
         }
-        // ---- streaming: x periodic; y periodic or halfway bounce-back walls
+        C zst[9];
+        inverse9(m, zst);
+        // ---- streaming of h and z: x periodic; y periodic or halfway
+        //      bounce-back walls
         st(hn + n, h0hi);
         if constexpr (RMASS) st(hn + 18 * P + n, h0lo);
         st(zn + n, S(zst[0]));
 #pragma unroll
         for (int i = 1; i < 9; ++i) {
-            const int txd = wrap(x + EX[i], nx);
-            int tyd = y + EY[i];
+            const int tyd = y + EY[i];
             if (k.bcy && (tyd < 0 || tyd >= ny)) {
                 st(hn + OPP[i] * P + n, S(hs[i]));
                 st(zn + OPP[i] * P + n, S(zst[i]));
             } else {
-                tyd = wrap(tyd, ny);
-                const long long d = base + (long long)tyd * nx + txd;
+                const long long d = base + (long long)wrap(tyd, ny) * nx + wrap(x + EX[i], nx);
                 st(hn + i * P + d, S(hs[i]));
                 st(zn + i * P + d, S(zst[i]));
             }
@@ -697,7 +705,8 @@ hipError_t launch_phase_step(const PhaseK& k, const S* hc, S* hn, const S* zc, S
                              hipStream_t s) {
     const long long tiles = (long long)((k.nx + TX - 1) / TX) * ((k.ny + TY - 1) / TY) * k.batch;
     dim3 blk(TX, TY), grd(unsigned((tiles + kXCD - 1) / kXCD * kXCD));
-    hipLaunchKernelGGL((k_phase<S, S, false>), grd, blk, 0, s, k, hc, hn, zc, zn, phiu,
+    const unsigned lds = std::is_same<S, float>::value ? kPhaseLdsReserve : 0u;
+    hipLaunchKernelGGL((k_phase<S, S, false>), grd, blk, lds, s, k, hc, hn, zc, zn, phiu,
                        (double*)nullptr);
     return hipGetLastError();
 }

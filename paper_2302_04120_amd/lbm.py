@@ -32,7 +32,7 @@ REDUCE_BITS = {"mass": 1, "phase": 2, "energy": 4, "nonfinite": 8}
 EXPORTS = ("lbm_query_bytes", "lbm_create", "lbm_destroy", "lbm_set_params_SI",
            "lbm_init_fields", "lbm_step", "lbm_macros", "lbm_reduce", "lbm_nusselt",
            "lbm_query_record_bytes", "lbm_record", "lbm_grad", "lbm_time",
-           "lbm_save_state", "lbm_load_state", "lbm_last_error")
+           "lbm_save_state", "lbm_load_state", "lbm_last_error", "lbm_set_graph_steps")
 
 
 class LbmError(RuntimeError):
@@ -100,6 +100,7 @@ def lib():
         L.lbm_query_record_bytes.argtypes = [vp, C.c_int, C.c_int, C.POINTER(C.c_size_t)]
         L.lbm_record.argtypes = [vp, C.c_int, C.c_int, C.POINTER(Objective), vp, C.c_size_t, _dp]
         L.lbm_grad.argtypes = [vp, C.c_double, _dp, _dp]
+        L.lbm_set_graph_steps.argtypes = [vp, C.c_int]
         for name in EXPORTS:
             if name not in ("lbm_destroy", "lbm_time", "lbm_last_error"):
                 getattr(L, name).restype = C.c_int
@@ -193,6 +194,7 @@ class Lattice:
         h = C.c_void_p()
         self._check(lib().lbm_create(C.byref(d), C.byref(h)), None)
         self.ctx = h
+        self._lib = lib()
         self.lattice, self.nx, self.ny, self.batch, self.prec = lattice, nx, ny, batch, prec
         self.bytes = int(nbytes.value)
 
@@ -203,12 +205,15 @@ class Lattice:
             raise LbmError(st, msg)
 
     def __del__(self):
-        if getattr(self, "ctx", None):
+        # the library handle is held on the instance: at interpreter shutdown
+        # the module globals may already be gone
+        L = getattr(self, "_lib", None)
+        if getattr(self, "ctx", None) and L is not None:
             try:
                 self.torch.cuda.synchronize(self.device)
             except Exception:
                 pass
-            lib().lbm_destroy(self.ctx)
+            L.lbm_destroy(self.ctx)
             self.ctx = None
 
     @property
@@ -231,6 +236,10 @@ class Lattice:
 
     def step(self, n=1):
         self._check(lib().lbm_step(self.ctx, int(n)))
+
+    def set_graph_steps(self, steps):
+        """Steps per captured HIP graph replayed by ``step`` (0 disables)."""
+        self._check(lib().lbm_set_graph_steps(self.ctx, int(steps)))
 
     @property
     def t(self):

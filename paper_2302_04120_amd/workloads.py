@@ -168,7 +168,7 @@ def bubble(n=256, radii=(20, 30, 40, 50), seed=0, dx=5e-6, dt=1e-7, W_nodes=4.0,
 # C4: layered two-phase Poiseuille flow (Sec. 4.4)
 # --------------------------------------------------------------------------
 
-def layered(nx=4, ny=512, seed=0, dx=1.25e-6, dt=1.25e-7, W_nodes=20.0, M=1e-5,
+def layered(nx=4, ny=512, seed=0, dx=1.25e-6, dt=1.25e-8, W_nodes=20.0, M=1e-5,
             rho_l=1000.0, rho_g=0.0231, nu_l=8.927e-7, nu_g=4.20412e-4, sigma=0.07,
             u_c=1e-4, batch=1):
     """Liquid below the interface at y = H/2 + U(-1/2, 1/2) dx, gas above;
