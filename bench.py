@@ -4,8 +4,10 @@ Workload: the stationary-bubble case (D2Q9 MRT pressure populations + D2Q9
 conservative Allen-Cahn populations, 256 x 256 periodic cell, liquid/gas
 density ratio ~43 300, viscosity ratio ~470, radii cycling over 20/30/40/50
 nodes with seeded centre jitter) run as a batch of independent replicas, FP32
-deviation storage.  One step = one fused stream-collide launch over every
-replica.  Inputs are synthetic and resident in HBM before timing starts.
+deviation storage.  One step = one stream-collide update of every node of
+every replica; by default the library's two-step kernel performs two steps
+per launch (--fusion 1 times the single-step kernel instead).  Inputs are
+synthetic and resident in HBM before timing starts.
 
 Prints ONE JSON line (see the keys below).  ``--gpus`` above 1 is refused:
 this benchmark measures one GPU.
@@ -45,11 +47,12 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_gpu(batch, steps, warmup, prec, n=256):
+def run_gpu(batch, steps, warmup, prec, n=256, fusion=0):
     import torch
     from paper_2302_04120_amd import lbm, workloads as WL
     prm, ini, _ = WL.bubble(n=n, batch=batch, seed=0)
     L = lbm.Lattice("phase", n, n, batch=batch, prec=prec)
+    L.set_step_fusion(fusion)
     L.set_params(prm)
     L.init(ini["p"], ini["ux"], ini["uy"], None, ini["phi"])
     del ini
@@ -145,6 +148,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--batch", type=int, default=1024, help="256x256 replicas per step")
     ap.add_argument("--prec", default="fp32", choices=("fp32", "fp64"))
+    ap.add_argument("--fusion", type=int, default=2, choices=(0, 1, 2),
+                    help="two-phase kernel: 2 two-step (default), 1 single-step, 0 library's choice")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP64 and batch-4 legs")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_phase_step.json"))
@@ -158,24 +163,34 @@ def main():
         print("bench.py measures one GPU only; --gpus %d is not supported" % args.gpus,
               file=sys.stderr)
         return 2
-    log("bench: phase workload batch=%d steps=%d warmup=%d prec=%s" %
-        (args.batch, args.steps, args.warmup, args.prec))
-    r = run_gpu(args.batch, args.steps, args.warmup, args.prec)
+    if args.steps % 2 and args.fusion == 2:
+        print("--steps must be even with the two-step kernel", file=sys.stderr)
+        return 2
+    log("bench: phase workload batch=%d steps=%d warmup=%d prec=%s fusion=%d" %
+        (args.batch, args.steps, args.warmup, args.prec, args.fusion))
+    r = run_gpu(args.batch, args.steps, args.warmup, args.prec, fusion=args.fusion)
     mlups = r["nodes"] * args.steps / r["wall"] / 1e6
     bpl = BYTES_PER_LU[args.prec]
-    achieved = bpl * r["nodes"] / (r["kernel_ms"] * 1e-3) / 1e9
+    spl = 2 if args.fusion == 2 else 1  # steps per launch
+    kname = ("k_phase_tb2<%s>" % ("float" if args.prec == "fp32" else "double") if spl == 2 else
+             "k_phase<%s>" % ("float,float,false" if args.prec == "fp32" else "double,double,false"))
+    launch_ms = r["kernel_ms"] * spl
+    # algorithmic bytes of one launch (bpl x nodes x steps it performs) / its duration
+    achieved = bpl * r["nodes"] * spl / (launch_ms * 1e-3) / 1e9
     traffic = None
     if os.path.exists(args.traffic):
         with open(args.traffic) as f:
             tr = json.load(f)
         if (tr.get("batch") == args.batch and tr.get("prec") == args.prec
+                and tr.get("kernel") == kname
                 and tr.get("source_sha256") == kernel_source_hash()):
             traffic = tr.get("bytes_per_launch")
     extras = {}
     if not args.no_extras:
         log("bench: FP64 leg")
-        r64 = run_gpu(max(1, args.batch // 4), max(20, args.steps // 4), 5, "fp64")
-        extras["fp64_mlups"] = r64["nodes"] * max(20, args.steps // 4) / r64["wall"] / 1e6
+        s64 = max(20, args.steps // 4) // 2 * 2
+        r64 = run_gpu(max(1, args.batch // 4), s64, 6, "fp64", fusion=args.fusion)
+        extras["fp64_mlups"] = r64["nodes"] * s64 / r64["wall"] / 1e6
         extras["fp64_hbm_frac"] = (BYTES_PER_LU["fp64"] * r64["nodes"] / (r64["kernel_ms"] * 1e-3)
                                    / 1e9 / HBM_PEAK_GBS)
         log("bench: paper-sized leg (4 replicas)")
@@ -206,8 +221,11 @@ def main():
                    "nodes_per_step": r["nodes"], "storage": args.prec + "-deviation"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "bytes_per_lu": bpl, "kernel": "k_phase<float,float,false>",
-                     "kernel_ms": r["kernel_ms"]},
+                     "bytes_per_lu": bpl, "kernel": kname, "steps_per_launch": spl,
+                     "launch_ms": launch_ms,
+                     "lu_per_launch": r["nodes"] * spl,
+                     "hbm_measured_GBps": (traffic / (launch_ms * 1e-3) / 1e9
+                                           if traffic is not None else None)},
         "cpu_baseline": cpu,
         "adjoint_over_forward": None,
     }

@@ -2,7 +2,10 @@
 
 Compiles the HIP sources of this directory into ``../liblbm.so``.  Only the
 ``extern "C"`` entry points of include/lbm.h are exported.  Packed-FP32
-instructions are disabled for all device code.
+instructions are disabled for all device code.  Multiply-adds are fused only
+within one source expression (-ffp-contract=on), never across statements:
+the fusion then depends on the source alone, so kernels that inline the same
+per-node function round identically.
 """
 import os
 import subprocess
@@ -24,7 +27,8 @@ def hipcc():
 
 def build(verbose=False, extra=()):
     cmd = [hipcc(), "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
-           "-fvisibility=hidden", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           "-fvisibility=hidden", "-ffp-contract=on",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-I" + os.path.join(ROOT, "include"), "-I" + HERE]
     cmd += list(extra)
     cmd += [os.path.join(HERE, s) for s in SOURCES]

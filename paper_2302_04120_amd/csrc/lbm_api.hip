@@ -16,13 +16,13 @@ using namespace lbm;
 namespace {
 
 constexpr uint32_t kMagic = 0x534d424cu;  // "LBMS"
-constexpr uint32_t kVersion = 1;
+constexpr uint32_t kVersion = 2;
 
 struct Layout {
     long long N = 0, P = 0;
-    int npop = 0;
+    int npop = 0, nplanes = 0;
     size_t es = 0;
-    size_t offA = 0, offB = 0, offPhiu = 0, offAux = 0, offStage = 0, offPartial = 0;
+    size_t offA = 0, offB = 0, offAux = 0, offStage = 0, offPartial = 0;
     size_t offSmall = 0, total = 0;
 };
 
@@ -82,12 +82,12 @@ lbm_status check_desc(const lbm_desc* d, Layout* L, std::string* err) {
         const long long tiles = (long long)((d->nx + 63) / 64) * ((d->ny + 3) / 4) * d->batch;
         if (tiles > (1LL << 30)) return fail(LBM_E_ARG, "grid too large for the launch geometry");
     }
+    // the PHASE state also carries (phi u) of the previous step: 2 planes
+    l.nplanes = l.npop + (d->lattice == LBM_D2Q9_PHASE ? 2 : 0);
     size_t off = 0;
-    const size_t popbytes = align256((size_t)l.npop * l.P * l.es);
+    const size_t popbytes = align256((size_t)l.nplanes * l.P * l.es);
     l.offA = off; off += popbytes;
     l.offB = off; off += popbytes;
-    l.offPhiu = off;
-    if (d->lattice == LBM_D2Q9_PHASE) off += align256(2 * (size_t)l.P * l.es);
     l.offAux = off; off += align256((size_t)(d->nx + 2 * d->ny) * l.es);
     l.offStage = off; off += align256(7 * (size_t)l.P * sizeof(double));
     l.offPartial = off; off += align256((size_t)d->batch * 4 * kRedBlocks * sizeof(double));
@@ -152,7 +152,42 @@ hipError_t step_once(lbm_ctx* c) {
                                    aux_qw<S>(c), aux_uin<S>(c), aux_tin<S>(c), flux_mod(c),
                                    c->stream);
     }
-    return launch_phase_step<S>(c->pk, a, b, a + 9 * P, b + 9 * P, (S*)c->phiu, c->stream);
+    return launch_phase_step<S>(c->pk, a, b, a + 9 * P, b + 9 * P, a + c->npop * P,
+                                b + c->npop * P, c->stream);
+}
+
+// Whether the next two steps go through the two-step kernel.  Automatic
+// mode takes it when its workgroups (one per 64-row segment and replica)
+// fill the chip; small grids keep the single-step kernel, whose tiles
+// spread over more CUs.
+bool use_tb2(const lbm_ctx* c) {
+    if (c->desc.lattice != LBM_D2Q9_PHASE || c->fusion == 1 || !phase_tb2_fits(c->pk)) return false;
+    if (c->fusion == 2) return true;
+    const long long wgs = (long long)((c->desc.ny + 63) / 64) * c->desc.batch;
+    return wgs >= 1024;
+}
+
+// Enqueue m (1 or 2) steps, advancing the buffer parity and the step count;
+// *swaps receives the number of buffer swaps made.
+template <typename S>
+hipError_t advance(lbm_ctx* c, int m, int* swaps) {
+    *swaps = 0;
+    if (m == 2 && use_tb2(c)) {
+        hipError_t e = launch_phase_tb2<S>(c->pk, (const S*)bufA(c), (S*)bufB(c), c->stream);
+        if (e != hipSuccess) return e;
+        c->cur ^= 1;
+        c->t += 2;
+        *swaps = 1;
+        return hipSuccess;
+    }
+    for (int k = 0; k < m; ++k) {
+        hipError_t e = step_once<S>(c);
+        if (e != hipSuccess) return e;
+        c->cur ^= 1;
+        c->t += 1;
+        ++*swaps;
+    }
+    return hipSuccess;
 }
 
 void drop_graphs(lbm_ctx* c) {
@@ -175,11 +210,11 @@ bool graph_usable(lbm_ctx* c) {
 }
 
 // Enqueue graph_steps steps as one graph launch.  The graph for the current
-// buffer parity is captured on first use; graph_steps is even, so the state
-// ends in the buffer it started in.
+// buffer parity is captured on first use, with the buffer swaps it makes.
 template <typename S>
 hipError_t step_replay(lbm_ctx* c) {
-    hipGraphExec_t& ex = c->step_graph[c->cur];
+    const int p0 = c->cur;
+    hipGraphExec_t& ex = c->step_graph[p0];
     if (!ex) {
         hipError_t e = hipSuccess;
         if (!c->cap_stream) e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
@@ -189,13 +224,18 @@ hipError_t step_replay(lbm_ctx* c) {
         const hipStream_t user = c->stream;
         const int cur0 = c->cur;
         c->stream = c->cap_stream;
+        const long long t0 = c->t;
         hipError_t el = hipSuccess;
-        for (int k = 0; k < c->graph_steps && el == hipSuccess; ++k) {
-            el = step_once<S>(c);
-            c->cur ^= 1;
+        int swaps = 0;
+        for (int k = 0; k < c->graph_steps && el == hipSuccess; k += 2) {
+            int sw = 0;
+            el = advance<S>(c, 2, &sw);
+            swaps += sw;
         }
         c->stream = user;
         c->cur = cur0;
+        c->t = t0;
+        c->graph_swaps[p0] = swaps;
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(c->cap_stream, &g);
         if (el != hipSuccess || e != hipSuccess) {
@@ -209,7 +249,9 @@ hipError_t step_replay(lbm_ctx* c) {
             return e;
         }
     }
-    return hipGraphLaunch(ex, c->stream);
+    hipError_t e = hipGraphLaunch(ex, c->stream);
+    if (e == hipSuccess) c->cur ^= (c->graph_swaps[p0] & 1);
+    return e;
 }
 
 template <typename S>
@@ -259,11 +301,11 @@ lbm_status lbm_create(const lbm_desc* desc, lbm_ctx** out) {
     c->N = L.N;
     c->P = L.P;
     c->npop = L.npop;
+    c->nplanes = L.nplanes;
     c->esize = L.es;
     char* base = (char*)desc->dev_buf;
     c->popA = base + L.offA;
     c->popB = base + L.offB;
-    c->phiu = base + L.offPhiu;
     c->aux = base + L.offAux;
     c->staging = (double*)(base + L.offStage);
     c->partial = (double*)(base + L.offPartial);
@@ -294,6 +336,20 @@ lbm_status lbm_set_graph_steps(lbm_ctx* c, int steps) {
         DeviceGuard g(c->device);
         drop_graphs(c);
         c->graph_steps = steps;
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_set_step_fusion(lbm_ctx* c, int mode) {
+    if (!c) return LBM_E_ARG;
+    if (mode < 0 || mode > 2) return set_err(c, LBM_E_ARG, "fusion mode must be 0, 1 or 2");
+    if (mode == 2 && c->desc.lattice == LBM_D2Q9_PHASE &&
+        (c->desc.nx % 64 != 0 || c->desc.nx > 256))
+        return set_err(c, LBM_E_UNSUPPORTED, "two-step kernel needs nx a multiple of 64, at most 256");
+    if (mode != c->fusion) {
+        DeviceGuard g(c->device);
+        drop_graphs(c);
+        c->fusion = mode;
     }
     return LBM_OK;
 }
@@ -477,10 +533,11 @@ lbm_status lbm_init_fields(lbm_ctx* c, const double* rho_or_p, const double* ux,
     } else {
         if (d.prec == LBM_FP64)
             e = launch_phase_init<double>(c->pk, c->staging, (double*)c->popA,
-                                          (double*)c->popA + 9 * P, (double*)c->phiu, c->stream);
+                                          (double*)c->popA + 9 * P,
+                                          (double*)c->popA + c->npop * P, c->stream);
         else
             e = launch_phase_init<float>(c->pk, c->staging, (float*)c->popA, (float*)c->popA + 9 * P,
-                                         (float*)c->phiu, c->stream);
+                                         (float*)c->popA + c->npop * P, c->stream);
     }
     if (e != hipSuccess) return hip_fail(c, e, "init kernel");
     e = hipStreamSynchronize(c->stream);
@@ -503,19 +560,21 @@ lbm_status lbm_step(lbm_ctx* c, int n) {
         c->t += n;
         return LBM_OK;
     }
+    const bool f64 = c->desc.prec == LBM_FP64;
     int s = 0;
     if (n >= 2 * c->graph_steps && graph_usable(c)) {
         for (; s + c->graph_steps <= n; s += c->graph_steps) {
-            hipError_t e = c->desc.prec == LBM_FP64 ? step_replay<double>(c) : step_replay<float>(c);
+            hipError_t e = f64 ? step_replay<double>(c) : step_replay<float>(c);
             if (e != hipSuccess) return hip_fail(c, e, "step graph");
             c->t += c->graph_steps;
         }
     }
-    for (; s < n; ++s) {
-        hipError_t e = c->desc.prec == LBM_FP64 ? step_once<double>(c) : step_once<float>(c);
+    while (s < n) {
+        const int m = n - s >= 2 ? 2 : 1;
+        int sw = 0;
+        hipError_t e = f64 ? advance<double>(c, m, &sw) : advance<float>(c, m, &sw);
         if (e != hipSuccess) return hip_fail(c, e, "step kernel");
-        c->cur ^= 1;
-        c->t += 1;
+        s += m;
     }
     return LBM_OK;
 }
@@ -654,7 +713,7 @@ lbm_status rec_layout(const lbm_ctx* c, int nsteps, int K, RecLayout* R, std::st
                     "the adjoint needs the channel lattice with flow, thermal, inlet/outlet, walls, batch 1");
     if (nsteps < 1 || K < 1) return fail(LBM_E_ARG, "nsteps and ckpt_every must be >= 1");
     RecLayout r{};
-    r.state = align256((size_t)c->npop * c->P * c->esize);
+    r.state = align256((size_t)c->nplanes * c->P * c->esize);
     r.nseg = (nsteps + K - 1) / K;
     const int Kt = K < nsteps ? K : nsteps;
     r.tiles = chan_tiles(c->ck);
@@ -757,7 +816,7 @@ lbm_status lbm_record(lbm_ctx* c, int nsteps, int ckpt_every, const lbm_objectiv
     const long long t0 = c->t;
     for (int sg = 0; sg < R.nseg; ++sg) {
         hipError_t e = hipMemcpyAsync(w + R.offCk + (size_t)sg * R.state, bufA(c),
-                                      (size_t)c->npop * c->P * c->esize, hipMemcpyDeviceToDevice,
+                                      (size_t)c->nplanes * c->P * c->esize, hipMemcpyDeviceToDevice,
                                       c->stream);
         if (e != hipSuccess) return hip_fail(c, e, "checkpoint copy");
         const int len = (sg == R.nseg - 1) ? nsteps - sg * ckpt_every : ckpt_every;
@@ -819,8 +878,8 @@ struct StateHeader {
 lbm_status lbm_save_state(lbm_ctx* c, void* host, size_t* bytes) {
     if (!c) return LBM_E_ARG;
     if (!bytes) return set_err(c, LBM_E_ARG, "bytes is NULL");
-    const size_t pop = (size_t)c->npop * c->P * c->esize;
-    const size_t pu = c->desc.lattice == LBM_D2Q9_PHASE ? 2 * (size_t)c->P * c->esize : 0;
+    const size_t pop = (size_t)c->nplanes * c->P * c->esize;
+    const size_t pu = 0;  // (phi u) is part of the state buffer
     const size_t need = sizeof(StateHeader) + pop + pu;
     if (!host) {
         *bytes = need;
@@ -834,7 +893,6 @@ lbm_status lbm_save_state(lbm_ctx* c, void* host, size_t* bytes) {
     std::memcpy(host, &hd, sizeof hd);
     char* p = (char*)host + sizeof hd;
     hipError_t e = hipMemcpyAsync(p, bufA(c), pop, hipMemcpyDeviceToHost, c->stream);
-    if (e == hipSuccess && pu) e = hipMemcpyAsync(p + pop, c->phiu, pu, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "save state");
     *bytes = need;
@@ -848,8 +906,8 @@ lbm_status lbm_load_state(lbm_ctx* c, const void* host, size_t bytes) {
     if (bytes < sizeof(StateHeader)) return set_err(c, LBM_E_STATE, "state blob truncated");
     StateHeader hd;
     std::memcpy(&hd, host, sizeof hd);
-    const size_t pop = (size_t)c->npop * c->P * c->esize;
-    const size_t pu = c->desc.lattice == LBM_D2Q9_PHASE ? 2 * (size_t)c->P * c->esize : 0;
+    const size_t pop = (size_t)c->nplanes * c->P * c->esize;
+    const size_t pu = 0;  // (phi u) is part of the state buffer
     if (hd.magic != kMagic || hd.version != kVersion) return set_err(c, LBM_E_STATE, "not a state blob");
     if (hd.lattice != c->desc.lattice || hd.nx != c->desc.nx || hd.ny != c->desc.ny ||
         hd.batch != c->desc.batch || hd.prec != c->desc.prec || hd.npop != c->npop ||
@@ -861,7 +919,6 @@ lbm_status lbm_load_state(lbm_ctx* c, const void* host, size_t bytes) {
     const char* p = (const char*)host + sizeof hd;
     c->cur = 0;
     hipError_t e = hipMemcpyAsync(c->popA, p, pop, hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess && pu) e = hipMemcpyAsync(c->phiu, p + pop, pu, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "load state");
     c->t = hd.t;

@@ -74,11 +74,11 @@ struct lbm_ctx {
     // layout
     long long N;          // nodes per replica * batch
     long long P;          // plane stride
-    int npop;             // planes per population buffer
+    int npop;             // population planes (non-finite checks, reductions)
+    int nplanes;          // planes per state buffer: npop, plus (phi u) for PHASE
     size_t esize;         // bytes per population value
     char* popA;
     char* popB;
-    char* phiu;
     char* aux;            // flux (qw), inlet_u (uin), inlet_T (tin): storage type
     double* staging;      // 7 planes of FP64
     double* partial;      // reduction partials
@@ -108,6 +108,10 @@ struct lbm_ctx {
     int graph_steps = 64;
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t step_graph[2] = {nullptr, nullptr};
+    int graph_swaps[2] = {0, 0};  // buffer swaps made by each captured graph
+    // two-phase steps: 0 automatic, 1 single-step kernel only, 2 two-step
+    // kernel whenever the grid allows it
+    int fusion = 0;
 };
 
 namespace lbm {
@@ -119,8 +123,13 @@ template <typename S>
 hipError_t launch_chan_step(const ChanK& k, const S* fc, S* fn, const S* gc, S* gn,
                             const S* qw, const S* uin, const S* tin, double mod, hipStream_t s);
 template <typename S>
-hipError_t launch_phase_step(const PhaseK& k, const S* hc, S* hn, const S* zc, S* zn, S* phiu,
-                             hipStream_t s);
+hipError_t launch_phase_step(const PhaseK& k, const S* hc, S* hn, const S* zc, S* zn, const S* puc,
+                             S* pun, hipStream_t s);
+// two steps in one launch; the whole state (populations and (phi u)) moves
+// from buffer a to buffer b; needs phase_tb2_fits
+bool phase_tb2_fits(const PhaseK& k);
+template <typename S>
+hipError_t launch_phase_tb2(const PhaseK& k, const S* a, S* b, hipStream_t s);
 hipError_t launch_d1(const D1K& k, double* g, int nsteps, hipStream_t s);
 
 template <typename S>

@@ -173,48 +173,177 @@ __global__ __launch_bounds__(256) void k_chan_step(ChanK k, const S* __restrict_
 }
 
 // ---------------------------------------------------------------------------
-// Two-phase step: conservative Allen-Cahn h_i (BGK) + pressure z_i (MRT/BGK)
-// Tile of 64 x TY nodes per block; phi of the tile and a one-node ring in LDS.
-// Buffer planes: 0-8 h_i, 9-17 z_i, 18 low part of h_0 (FP32 storage only).
+// Two-phase model: conservative Allen-Cahn h_i (BGK) + pressure z_i (MRT/BGK)
+// Buffer planes: 0-8 h_i, 9-17 z_i, then (FP32 storage only) the low part of
+// h_0, then (phi u) of the previous step (2 planes): npop = 19 (FP32) or 18
+// (FP64) population planes plus 2.
 // ---------------------------------------------------------------------------
 
 #ifndef LBM_PHASE_TY
 #define LBM_PHASE_TY 8
 #endif
-// optional occupancy target (waves per SIMD) for the step kernel; 0 = compiler's choice
-#ifndef LBM_PHASE_WPE
-#define LBM_PHASE_WPE 0
-#endif
-#if LBM_PHASE_WPE > 0
-#define LBM_PHASE_OCC __attribute__((amdgpu_waves_per_eu(LBM_PHASE_WPE)))
-#else
-#define LBM_PHASE_OCC
-#endif
 constexpr int TX = 64, TY = LBM_PHASE_TY;
-// LDS reserved by each FP32 step workgroup beyond its own 2.6 KB: it holds
-// residency at two 512-thread workgroups per CU (4 waves per SIMD).  With
-// more waves resident, more of the 42 population streams per wave are open
-// in DRAM at once and the step runs slower (67M-node bubble batch: 2.82 ms
-// at 8 waves per SIMD, 2.56 ms at 4).  The FP64 kernel's register use
-// already gives 4 waves per SIMD.
+// LDS reserved by each FP32 single-step workgroup beyond its own 2.6 KB: it
+// holds residency at two 512-thread workgroups per CU (4 waves per SIMD).
+// With more waves resident, more of the 42 population streams per wave are
+// open in DRAM at once and the step runs slower (67M-node bubble batch:
+// 2.82 ms at 8 waves per SIMD, 2.56 ms at 4).  The FP64 kernel's register
+// use already gives 4 waves per SIMD.
 constexpr unsigned kPhaseLdsReserve = 61440;
 static_assert(2 * (TX + 2) + 2 * TY <= TX * TY, "the ring must fit in one pass of the block");
 
-template <typename S, typename C>
-__device__ __forceinline__ C node_phi(const S* __restrict__ h, const S* __restrict__ hlo,
-                                      long long P, long long n) {
-    C a = C(h[n]);
-    if (hlo) a += C(hlo[n]);
-    C s = (C(h[P + n]) + C(h[3 * P + n])) + (C(h[2 * P + n]) + C(h[4 * P + n]));
-    s += (C(h[5 * P + n]) + C(h[7 * P + n])) + (C(h[6 * P + n]) + C(h[8 * P + n]));
-    return a + s;  // Eq. zero_moment_h
+// phi of a node from its stored h_i, Eq. zero_moment_h (rest population with
+// its low part).  One summation order everywhere, so that every kernel sees
+// the same phi for the same populations.
+template <typename C>
+__device__ __forceinline__ C phi_sum(const C (&h)[9], C hlo) {
+    return (h[0] + hlo) + (((h[1] + h[3]) + (h[2] + h[4])) + ((h[5] + h[7]) + (h[6] + h[8])));
 }
 
+// Everything a node derives from its phi neighbourhood and its z_i before
+// the collision.  pn[i] = phi at x + e_i (pn[0] = phi at the node).
+template <typename C>
+struct PhaseLocal {
+    C phi, Gx, Gy, rho, drl, wn, mu, fsx, fsy, nxv, nyv, ux, uy, uu, ug, ph;
+};
+
+template <typename C>
+__device__ __forceinline__ PhaseLocal<C> phase_local(const PhaseK& k, const C (&pn)[9],
+                                                     const C (&z)[9]) {
+    PhaseLocal<C> L;
+    // ---- stencils, Eq. gradient and Eq. laplacian in lattice form:
+    //      grad phi = 3 G / dx, lap phi = 6 L / dx^2
+    const C phi = pn[0];
+    C Gx = C(0), Gy = C(0), Lp = C(0);
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+        Gx += wgt<C>(i) * C(EX[i]) * pn[i];
+        Gy += wgt<C>(i) * C(EY[i]) * pn[i];
+        Lp += wgt<C>(i) * (pn[i] - phi);
+    }
+    const C drl = C(k.rho_l - k.rho_g);
+    const C rho = C(k.rho_g) + phi * drl;  // linear in phi (Sec. 2.3)
+    C nuh;
+    if (k.visc_mode == 0) nuh = C(k.nuh_g) + phi * C(k.nuh_l - k.nuh_g);
+    else nuh = (C(k.zh_g) + phi * C(k.zh_l - k.zh_g)) / rho;  // nu = zeta / rho (Sec. 4.4)
+    L.wn = C(1) / (C(3) * nuh + C(0.5));                      // dt / tau
+    // chemical potential, Eq. chemical_potential; surface force F_s = mu grad phi
+    const C mu = C(4) * C(k.beta) * phi * (phi - C(1)) * (phi - C(0.5)) - C(k.kap6) * Lp;
+    L.fsx = mu * Gx * C(k.fs_scale) + C(k.Fbt[0]);
+    L.fsy = mu * Gy * C(k.fs_scale) + C(k.Fbt[1]);
+    // guarded interface normal (text after Eq. laplacian)
+    const C gn2 = Gx * Gx + Gy * Gy;
+    L.nxv = C(0);
+    L.nyv = C(0);
+    if (gn2 > C(k.Geps) * C(k.Geps)) {
+        const C ig = C(1) / sqrt(gn2);
+        L.nxv = Gx * ig;
+        L.nyv = Gy * ig;
+    }
+    // ---- pressure populations: velocity first (Eq. u_Liang), then pressure
+    const C jx = (z[1] - z[3]) + ((z[5] - z[7]) + (z[8] - z[6]));
+    const C jy = (z[2] - z[4]) + ((z[5] - z[7]) + (z[6] - z[8]));
+    const C ir = C(1) / rho;
+    L.ux = (jx + C(0.5) * L.fsx) * ir;
+    L.uy = (jy + C(0.5) * L.fsy) * ir;
+    L.uu = L.ux * L.ux + L.uy * L.uy;
+    L.ug = L.ux * Gx + L.uy * Gy;
+    const C zs = ((z[1] + z[3]) + (z[2] + z[4])) + ((z[5] + z[7]) + (z[6] + z[8]));
+    // p / c_s^2, Eq. p_Liang: c_s^2/(1 - w_0) [sum_{i>0} z_i + dt/2 u.grad rho + rho s_0(u)]
+    L.ph = C(1.8) * (zs + C(1.5) * drl * L.ug - C(1.5) * wgt<C>(0) * rho * L.uu);
+    L.phi = phi;
+    L.Gx = Gx;
+    L.Gy = Gy;
+    L.rho = rho;
+    L.drl = drl;
+    L.mu = mu;
+    return L;
+}
+
+// The collision of one node.  In: its stored h_i (with the low part of h_0
+// for FP32 storage), z_i, (phi u) of the previous step and its PhaseLocal.
+// Out: post-collision h_i* (i > 0, in hs), h_0* as a hi/lo pair, z_i*, and
+// the node's (phi u).
+template <typename S, typename C>
+__device__ __forceinline__ void phase_collide(const PhaseK& k, const PhaseLocal<C>& L,
+                                              const C (&h)[9], C hlo, const C (&z)[9], C pu0,
+                                              C pu1, C (&hs)[9], S& h0hi, S& h0lo, C (&zst)[9],
+                                              C& pux, C& puy) {
+    constexpr bool RMASS = std::is_same<S, float>::value;
+    const C phi = L.phi, ux = L.ux, uy = L.uy;
+    // ---- interface populations (Eq. eq_lattice_boltzmann_interface,
+    //      source_term_interface, heq_liang); d(phi u)/dt by explicit Euler
+    pux = phi * ux;
+    puy = phi * uy;
+    const C dpx = pux - pu0, dpy = puy - pu1;
+    const C wphi = C(k.w_phi);
+    const C sfac = C(1) - C(0.5) * wphi;
+    const C sharp = C(4) * phi * (C(1) - phi) * C(k.dxW);
+    hs[0] = C(0);
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+        const C eu = C(EX[i]) * ux + C(EY[i]) * uy;
+        const C heq = phi * wgt<C>(i) * (C(1) + C(3) * eu);
+        const C sh = sfac * wgt<C>(i) *
+                     (C(3) * (C(EX[i]) * dpx + C(EY[i]) * dpy) +
+                      sharp * (C(EX[i]) * L.nxv + C(EY[i]) * L.nyv));
+        hs[i] = h[i] - wphi * (h[i] - heq) + sh;
+    }
+    h0lo = S(0);
+    if constexpr (RMASS) {
+        // rest population takes the node's exact balance: h0* = phi - sum_{i>0} h_i*
+        // with the stored (rounded) h_i*, carried as a double-float
+        float hi = float(h[0]), lo = float(hlo);
+#pragma unroll
+        for (int i = 1; i < 9; ++i) df_add(hi, lo, float(h[i]));
+#pragma unroll
+        for (int i = 1; i < 9; ++i) df_add(hi, lo, -float(hs[i]));
+        h0hi = hi;
+        h0lo = lo;
+    } else {
+        const C heq0 = phi * wgt<C>(0);
+        h0hi = S(h[0] - wphi * (h[0] - heq0));
+    }
+    // ---- pressure collision in moment space.  The moments of z_i^eq
+    //      (Eq. zeq_liang with Eq. s_i_Liang) and of dt F^z_i (Eq.
+    //      forcing_term_pressure_evolution) under the integer matrix of
+    //      Eq. M_matrix, in closed form:
+    //        m^eq = (0, 2 p~ + 3 rho u^2, -3 (p~ + rho u^2), rho u_x, -rho u_x,
+    //                rho u_y, -rho u_y, rho (u_x^2 - u_y^2), rho u_x u_y)
+    //        m^F  = (3 D, 0, -3 D, F_x, -F_x, F_y, -F_y,
+    //                2 drho (G_x u_x - G_y u_y), drho (G_x u_y + G_y u_x))
+    //      with p~ = p / c_s^2, D = drho (u . G) and every velocity in units
+    //      of c.  BGK is the same update with every rate equal to dt/tau.
+    const C rho = L.rho, drl = L.drl, wn = L.wn, Gx = L.Gx, Gy = L.Gy;
+    C m[9];
+    moments9(z, m);
+    {
+        const C ruu = rho * L.uu, D = drl * L.ug;
+        const C meq[9] = {C(0), C(2) * L.ph + C(3) * ruu, C(-3) * (L.ph + ruu), rho * ux, -rho * ux,
+                          rho * uy, -rho * uy, rho * (ux * ux - uy * uy), rho * ux * uy};
+        const C mf[9] = {C(3) * D, C(0), C(-3) * D, L.fsx, -L.fsx, L.fsy, -L.fsy,
+                         C(2) * drl * (Gx * ux - Gy * uy), drl * (Gx * uy + Gy * ux)};
+        const C wq = C(3) * (C(2) - wn) / (C(3) - wn);
+        const C Lm[9] = {C(1), C(1), C(1), C(1), wq, C(1), k.qy_printed ? C(1) : wq, wn, wn};
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            const C Lq = k.z_mrt ? Lm[q] : wn;
+            m[q] += -Lq * (m[q] - meq[q]) + (C(1) - C(0.5) * Lq) * mf[q];
+        }
+    }
+    inverse9(m, zst);
+}
+
+// ---------------------------------------------------------------------------
+// Single step.  Tile of 64 x TY nodes per block; phi of the tile and a
+// one-node ring in LDS.  MACROS: evaluate the macroscopic fields of the
+// stored state into mout instead of stepping.
+// ---------------------------------------------------------------------------
 template <typename S, typename C, bool MACROS>
-__global__ __launch_bounds__(TX * TY) LBM_PHASE_OCC void k_phase(PhaseK k, const S* __restrict__ hc,
+__global__ __launch_bounds__(TX * TY) void k_phase(PhaseK k, const S* __restrict__ hc,
                                                S* __restrict__ hn, const S* __restrict__ zc,
-                                               S* __restrict__ zn, S* __restrict__ phiu,
-                                               double* __restrict__ mout) {
+                                               S* __restrict__ zn, const S* __restrict__ puc,
+                                               S* __restrict__ pun, double* __restrict__ mout) {
     constexpr bool RMASS = std::is_same<S, float>::value;
     __shared__ C sphi[TY + 2][TX + 2];
     const int nx = k.nx, ny = k.ny;
@@ -233,7 +362,7 @@ __global__ __launch_bounds__(TX * TY) LBM_PHASE_OCC void k_phase(PhaseK k, const
         return ((gy % ny) + ny) % ny;
     };
     // Every load of the tile is issued before the barrier: the node's own h, z
-    // and (phi u) (kept in registers for the collision) and, for 140 threads,
+    // and (phi u) (kept in registers for the collision) and, for 148 threads,
     // the 10 values of one ring node; the barrier then waits for memory once.
     const int x = x0 + tx, y = y0 + ty;
     const bool valid = x < nx && y < ny;
@@ -246,8 +375,8 @@ __global__ __launch_bounds__(TX * TY) LBM_PHASE_OCC void k_phase(PhaseK k, const
 #pragma unroll
         for (int i = 0; i < 9; ++i) z[i] = C(zc[i * P + n]);
         if constexpr (!MACROS) {
-            pu0 = C(phiu[n]);
-            pu1 = C(phiu[P + n]);
+            pu0 = C(puc[n]);
+            pu1 = C(puc[P + n]);
         }
     }
     int hx = -2, hy = -2;
@@ -261,129 +390,37 @@ __global__ __launch_bounds__(TX * TY) LBM_PHASE_OCC void k_phase(PhaseK k, const
     C ring = C(0);
     if (hx > -2) {
         const long long nn = base + (long long)gyw(y0 + hy) * nx + gxw(x0 + hx);
-        ring = node_phi<S, C>(hc, hlo_c, P, nn);
+        C hr[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) hr[i] = C(hc[i * P + nn]);
+        ring = phi_sum(hr, RMASS ? C(hlo_c[nn]) : C(0));
     }
-    // phi of the node, Eq. zero_moment_h (rest population with its low part)
-    const C phi_own = (h[0] + hlo) + (((h[1] + h[3]) + (h[2] + h[4])) + ((h[5] + h[7]) + (h[6] + h[8])));
-    sphi[ty + 1][tx + 1] = phi_own;
+    sphi[ty + 1][tx + 1] = phi_sum(h, hlo);
     if (hx > -2) sphi[hy + 1][hx + 1] = ring;
     __syncthreads();
     if (!valid) return;
 
-    // ---- stencils, Eq. gradient and Eq. laplacian in lattice form:
-    //      grad phi = 3 G / dx, lap phi = 6 L / dx^2
-    const C phi = sphi[ty + 1][tx + 1];
-    C Gx = C(0), Gy = C(0), Lp = C(0);
+    C pn[9];
 #pragma unroll
-    for (int i = 1; i < 9; ++i) {
-        const C pn = sphi[ty + 1 + EY[i]][tx + 1 + EX[i]];
-        Gx += wgt<C>(i) * C(EX[i]) * pn;
-        Gy += wgt<C>(i) * C(EY[i]) * pn;
-        Lp += wgt<C>(i) * (pn - phi);
-    }
-    const C drl = C(k.rho_l - k.rho_g);
-    const C rho = C(k.rho_g) + phi * drl;  // linear in phi (Sec. 2.3)
-    C nuh;
-    if (k.visc_mode == 0) nuh = C(k.nuh_g) + phi * C(k.nuh_l - k.nuh_g);
-    else nuh = (C(k.zh_g) + phi * C(k.zh_l - k.zh_g)) / rho;  // nu = zeta / rho (Sec. 4.4)
-    const C wn = C(1) / (C(3) * nuh + C(0.5));                // dt / tau
-    // chemical potential, Eq. chemical_potential; surface force F_s = mu grad phi
-    const C mu = C(4) * C(k.beta) * phi * (phi - C(1)) * (phi - C(0.5)) - C(k.kap6) * Lp;
-    const C fsx = mu * Gx * C(k.fs_scale) + C(k.Fbt[0]);
-    const C fsy = mu * Gy * C(k.fs_scale) + C(k.Fbt[1]);
-    // guarded interface normal (text after Eq. laplacian)
-    const C gn2 = Gx * Gx + Gy * Gy;
-    C nxv = C(0), nyv = C(0);
-    if (gn2 > C(k.Geps) * C(k.Geps)) {
-        const C ig = C(1) / sqrt(gn2);
-        nxv = Gx * ig;
-        nyv = Gy * ig;
-    }
-    // ---- pressure populations: velocity first (Eq. u_Liang), then pressure
-    const C jx = (z[1] - z[3]) + ((z[5] - z[7]) + (z[8] - z[6]));
-    const C jy = (z[2] - z[4]) + ((z[5] - z[7]) + (z[6] - z[8]));
-    const C ir = C(1) / rho;
-    const C ux = (jx + C(0.5) * fsx) * ir;
-    const C uy = (jy + C(0.5) * fsy) * ir;
-    const C uu = ux * ux + uy * uy;
-    const C ug = ux * Gx + uy * Gy;
-    const C zs = ((z[1] + z[3]) + (z[2] + z[4])) + ((z[5] + z[7]) + (z[6] + z[8]));
-    // p / c_s^2, Eq. p_Liang: c_s^2/(1 - w_0) [sum_{i>0} z_i + dt/2 u.grad rho + rho s_0(u)]
-    const C ph = C(1.8) * (zs + C(1.5) * drl * ug - C(1.5) * wgt<C>(0) * rho * uu);
+    for (int i = 0; i < 9; ++i) pn[i] = sphi[ty + 1 + EY[i]][tx + 1 + EX[i]];
+    const PhaseLocal<C> L = phase_local(k, pn, z);
 
     if constexpr (MACROS) {
         const long long Q = k.P;
-        mout[0 * Q + n] = double(rho);
-        mout[1 * Q + n] = double(ph) * k.cs2;
-        mout[2 * Q + n] = double(ux) * k.c;
-        mout[3 * Q + n] = double(uy) * k.c;
+        mout[0 * Q + n] = double(L.rho);
+        mout[1 * Q + n] = double(L.ph) * k.cs2;
+        mout[2 * Q + n] = double(L.ux) * k.c;
+        mout[3 * Q + n] = double(L.uy) * k.c;
         mout[4 * Q + n] = 0.0;
-        mout[5 * Q + n] = double(phi);
-        mout[6 * Q + n] = double(mu);
+        mout[5 * Q + n] = double(L.phi);
+        mout[6 * Q + n] = double(L.mu);
         return;
     } else {
-        // ---- interface populations (Eq. eq_lattice_boltzmann_interface,
-        //      source_term_interface, heq_liang); d(phi u)/dt by explicit Euler
-        const C pux = phi * ux, puy = phi * uy;
-        const C dpx = pux - pu0, dpy = puy - pu1;
-        st(phiu + n, S(pux));
-        st(phiu + P + n, S(puy));
-        const C wphi = C(k.w_phi);
-        const C sfac = C(1) - C(0.5) * wphi;
-        const C sharp = C(4) * phi * (C(1) - phi) * C(k.dxW);
-        C hs[9];
-#pragma unroll
-        for (int i = 1; i < 9; ++i) {
-            const C eu = C(EX[i]) * ux + C(EY[i]) * uy;
-            const C heq = phi * wgt<C>(i) * (C(1) + C(3) * eu);
-            const C sh = sfac * wgt<C>(i) *
-                         (C(3) * (C(EX[i]) * dpx + C(EY[i]) * dpy) +
-                          sharp * (C(EX[i]) * nxv + C(EY[i]) * nyv));
-            hs[i] = h[i] - wphi * (h[i] - heq) + sh;
-        }
-        S h0hi, h0lo = S(0);
-        if constexpr (RMASS) {
-            // rest population takes the node's exact balance: h0* = phi - sum_{i>0} h_i*
-            // with the stored (rounded) h_i*, carried as a double-float
-            float hi = float(h[0]), lo = float(hlo);
-#pragma unroll
-            for (int i = 1; i < 9; ++i) df_add(hi, lo, float(h[i]));
-#pragma unroll
-            for (int i = 1; i < 9; ++i) df_add(hi, lo, -float(hs[i]));
-            h0hi = hi;
-            h0lo = lo;
-        } else {
-            const C heq0 = phi * wgt<C>(0);
-            h0hi = S(h[0] - wphi * (h[0] - heq0));
-        }
-        // ---- pressure collision in moment space.  The moments of z_i^eq
-        //      (Eq. zeq_liang with Eq. s_i_Liang) and of dt F^z_i (Eq.
-        //      forcing_term_pressure_evolution) under the integer matrix of
-        //      Eq. M_matrix, in closed form:
-        //        m^eq = (0, 2 p~ + 3 rho u^2, -3 (p~ + rho u^2), rho u_x, -rho u_x,
-        //                rho u_y, -rho u_y, rho (u_x^2 - u_y^2), rho u_x u_y)
-        //        m^F  = (3 D, 0, -3 D, F_x, -F_x, F_y, -F_y,
-        //                2 drho (G_x u_x - G_y u_y), drho (G_x u_y + G_y u_x))
-        //      with p~ = p / c_s^2, D = drho (u . G) and every velocity in units
-        //      of c.  BGK is the same update with every rate equal to dt/tau.
-        C m[9];
-        moments9(z, m);
-        {
-            const C ruu = rho * uu, D = drl * ug;
-            const C meq[9] = {C(0), C(2) * ph + C(3) * ruu, C(-3) * (ph + ruu), rho * ux, -rho * ux,
-                              rho * uy, -rho * uy, rho * (ux * ux - uy * uy), rho * ux * uy};
-            const C mf[9] = {C(3) * D, C(0), C(-3) * D, fsx, -fsx, fsy, -fsy,
-                             C(2) * drl * (Gx * ux - Gy * uy), drl * (Gx * uy + Gy * ux)};
-            const C wq = C(3) * (C(2) - wn) / (C(3) - wn);
-            const C Lm[9] = {C(1), C(1), C(1), C(1), wq, C(1), k.qy_printed ? C(1) : wq, wn, wn};
-#pragma unroll
-            for (int q = 0; q < 9; ++q) {
-                const C L = k.z_mrt ? Lm[q] : wn;
-                m[q] += -L * (m[q] - meq[q]) + (C(1) - C(0.5) * L) * mf[q];
-            }
-        }
-        C zst[9];
-        inverse9(m, zst);
+        C hs[9], zst[9], pux, puy;
+        S h0hi, h0lo;
+        phase_collide<S, C>(k, L, h, hlo, z, pu0, pu1, hs, h0hi, h0lo, zst, pux, puy);
+        st(pun + n, S(pux));
+        st(pun + P + n, S(puy));
         // ---- streaming of h and z: x periodic; y periodic or halfway
         //      bounce-back walls
         st(hn + n, h0hi);
@@ -400,6 +437,246 @@ __global__ __launch_bounds__(TX * TY) LBM_PHASE_OCC void k_phase(PhaseK k, const
                 st(hn + i * P + d, S(hs[i]));
                 st(zn + i * P + d, S(zst[i]));
             }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Two steps per launch (temporal blocking).  A workgroup of nx threads (one
+// per column, nx a multiple of 64 up to 256) marches up the rows of one
+// segment [a, e) of one replica.  At row v it collides step n at row v and
+// step n + 1 at row v - 3:
+//   - the post-collision values of step n are exchanged in x through LDS and
+//     accumulated, per column, into the step-(n + 1) state of rows v - 1, v
+//     and v + 1, which stays in registers (a row's state is complete once
+//     the row above it has collided);
+//   - step n + 1 at row r needs phi_{n+1} of rows r - 1 .. r + 1, i.e. the
+//     step-n collisions of rows r - 2 .. r + 2, hence the lag;
+//   - phi of both steps lives in LDS rings of four rows.
+// Only the state at n and at n + 2 touches memory: half the traffic of two
+// single steps.  Periodic y: step n also collides the two rows on each side
+// of the segment (their outputs feed only this workgroup's registers), so
+// every segment is independent.  Walls: rows outside [0, ny) do not exist
+// and the bounce-back of the single step applies at both walls.  The
+// arithmetic per node is phase_local + phase_collide, as in k_phase.
+// ---------------------------------------------------------------------------
+constexpr int kTbMaxNx = 256;
+constexpr int kTbSeg = 64;  // rows per segment
+
+// register state of one row of one column: h 0-8, low part of h_0, z 0-8, (phi u)
+constexpr int kH = 0, kLO = 9, kZ = 10, kPU = 19, kNS = 21;
+
+template <typename S>
+__global__ __launch_bounds__(kTbMaxNx) void k_phase_tb2(PhaseK k, const S* __restrict__ A,
+                                                        S* __restrict__ B, int seg) {
+    using C = S;
+    constexpr bool RMASS = std::is_same<S, float>::value;
+    const int nx = k.nx, ny = k.ny;
+    const long long P = k.P;
+    const int npop = RMASS ? 19 : 18;
+    const int nseg = (ny + seg - 1) / seg;
+    int w;
+    if (!xcd_tile(nseg * k.batch, w)) return;  // whole workgroup, before any barrier
+    const int b = w / nseg;
+    const int a = (w - b * nseg) * seg;
+    const int e = min(a + seg, ny);
+    const bool walls = k.bcy != 0;
+    const int s1 = walls ? max(a - 2, 0) : a - 2;   // first row of step n
+    const int e1 = walls ? min(e + 2, ny) : e + 2;  // end of step-n rows
+    const int lastload = walls ? min(e1, ny - 1) : e1;
+    const long long base = (long long)b * ny * nx;
+    const int x = threadIdx.x;
+    const int xm = x == 0 ? nx - 1 : x - 1;
+    const int xp = x == nx - 1 ? 0 : x + 1;
+
+    __shared__ C phN[4][kTbMaxNx];   // phi_n, rows v mod 4
+    __shared__ C phN1[4][kTbMaxNx];  // phi_{n+1}
+    __shared__ C xch[12][kTbMaxNx];  // x-moving post-collision values of step n
+
+    auto rowoff = [&](int v) {  // memory row of virtual row v
+        const int r = walls ? v : ((v % ny) + ny) % ny;
+        return base + (long long)r * nx;
+    };
+    auto load_row = [&](int v, C (&s)[kNS]) {
+        const long long n = rowoff(v) + x;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) s[kH + i] = C(A[i * P + n]);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) s[kZ + i] = C(A[(9 + i) * P + n]);
+        s[kLO] = RMASS ? C(A[18 * P + n]) : C(0);
+        s[kPU] = C(A[npop * P + n]);
+        s[kPU + 1] = C(A[(npop + 1) * P + n]);
+    };
+    auto phi_of = [&](const C (&s)[kNS]) {
+        const C hh[9] = {s[0], s[1], s[2], s[3], s[4], s[5], s[6], s[7], s[8]};
+        return phi_sum(hh, s[kLO]);
+    };
+    // phi of row v into a ring, with the wall ghost rows (copies of the
+    // first and last rows: zero normal gradient)
+    auto put_phi = [&](C (&ring)[4][kTbMaxNx], int v, C ph) {
+        ring[v & 3][x] = ph;
+        if (walls && v == 0) ring[3][x] = ph;                // row -1
+        if (walls && v == ny - 1) ring[ny & 3][x] = ph;      // row ny
+    };
+    auto gather = [&](C (&ring)[4][kTbMaxNx], int v, C (&pn)[9]) {
+        const C* rm = ring[(v - 1) & 3];
+        const C* r0 = ring[v & 3];
+        const C* rp = ring[(v + 1) & 3];
+        pn[0] = r0[x];
+        pn[1] = r0[xp];
+        pn[2] = rp[x];
+        pn[3] = r0[xm];
+        pn[4] = rm[x];
+        pn[5] = rp[xp];
+        pn[6] = rp[xm];
+        pn[7] = rm[xm];
+        pn[8] = rm[xp];
+    };
+
+    C cur[kNS], nxt[kNS];
+    // accumulated step-(n+1) state of rows v-3 (A3) .. v+1 (Ap)
+    C A3[kNS], A2[kNS], A1[kNS], A0[kNS], Ap[kNS];
+#pragma unroll
+    for (int q = 0; q < kNS; ++q) {
+        nxt[q] = C(0);
+        A3[q] = A2[q] = A1[q] = A0[q] = Ap[q] = C(0);
+    }
+    // prologue: phi_n of rows s1 - 1 and s1, state of row s1
+    if (!walls || s1 > 0) {
+        load_row(s1 - 1, nxt);
+        put_phi(phN, s1 - 1, phi_of(nxt));
+    }
+    load_row(s1, cur);
+    put_phi(phN, s1, phi_of(cur));
+    // (the first barrier of the loop orders these LDS writes)
+
+    for (int v = s1; v < e + 3; ++v) {
+        const bool do_n = v < e1;
+        const bool do_load = v + 1 <= lastload;
+        const int r = v - 3;
+        if (do_load) load_row(v + 1, nxt);
+        __syncthreads();  // phi_{n+1} of row v - 2 and the previous exchange reads are done
+        // ---- step n + 1 at row r = v - 3, straight to memory
+        if (r >= a && r < e) {
+            C pn[9], h[9], z[9], hs[9], zst[9], pux, puy;
+            S h0hi, h0lo;
+            gather(phN1, r, pn);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                h[i] = A3[kH + i];
+                z[i] = A3[kZ + i];
+            }
+            const PhaseLocal<C> L = phase_local(k, pn, z);
+            phase_collide<S, C>(k, L, h, A3[kLO], z, A3[kPU], A3[kPU + 1], hs, h0hi, h0lo, zst, pux,
+                                puy);
+            const long long n = rowoff(r) + x;
+            st(B + npop * P + n, S(pux));
+            st(B + (npop + 1) * P + n, S(puy));
+            st(B + n, h0hi);
+            if constexpr (RMASS) st(B + 18 * P + n, h0lo);
+            st(B + 9 * P + n, S(zst[0]));
+#pragma unroll
+            for (int i = 1; i < 9; ++i) {
+                const int ryd = r + EY[i];
+                if (walls && (ryd < 0 || ryd >= ny)) {
+                    st(B + OPP[i] * P + n, S(hs[i]));
+                    st(B + (9 + OPP[i]) * P + n, S(zst[i]));
+                } else {
+                    const int xd = EX[i] == 0 ? x : (EX[i] > 0 ? xp : xm);
+                    const long long d = rowoff(ryd) + xd;
+                    st(B + i * P + d, S(hs[i]));
+                    st(B + (9 + i) * P + d, S(zst[i]));
+                }
+            }
+        }
+        // ---- phi_n of row v + 1
+        if (do_load) put_phi(phN, v + 1, phi_of(nxt));
+        __syncthreads();
+        // ---- step n at row v
+        C hs[9], zst[9], pux = C(0), puy = C(0);
+        S h0hi = S(0), h0lo = S(0);
+        if (do_n) {
+            C pn[9], h[9], z[9];
+            gather(phN, v, pn);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                h[i] = cur[kH + i];
+                z[i] = cur[kZ + i];
+            }
+            const PhaseLocal<C> L = phase_local(k, pn, z);
+            phase_collide<S, C>(k, L, h, cur[kLO], z, cur[kPU], cur[kPU + 1], hs, h0hi, h0lo, zst,
+                                pux, puy);
+            xch[0][x] = hs[1];
+            xch[1][x] = hs[3];
+            xch[2][x] = hs[5];
+            xch[3][x] = hs[6];
+            xch[4][x] = hs[7];
+            xch[5][x] = hs[8];
+            xch[6][x] = zst[1];
+            xch[7][x] = zst[3];
+            xch[8][x] = zst[5];
+            xch[9][x] = zst[6];
+            xch[10][x] = zst[7];
+            xch[11][x] = zst[8];
+        }
+        __syncthreads();
+        if (do_n) {
+            // pushes of row v: +y movers to row v + 1, rest and x movers to
+            // row v, -y movers to row v - 1 (x movers come from x -+ 1)
+            A0[kH + 0] = C(h0hi);
+            A0[kLO] = C(h0lo);
+            A0[kZ + 0] = zst[0];
+            A0[kPU] = pux;
+            A0[kPU + 1] = puy;
+            A0[kH + 1] = xch[0][xm];
+            A0[kH + 3] = xch[1][xp];
+            A0[kZ + 1] = xch[6][xm];
+            A0[kZ + 3] = xch[7][xp];
+            if (walls && v == ny - 1) {  // top wall: +y movers come back reversed
+                A0[kH + 4] = hs[2];
+                A0[kH + 7] = hs[5];
+                A0[kH + 8] = hs[6];
+                A0[kZ + 4] = zst[2];
+                A0[kZ + 7] = zst[5];
+                A0[kZ + 8] = zst[6];
+            } else {
+                Ap[kH + 2] = hs[2];
+                Ap[kH + 5] = xch[2][xm];
+                Ap[kH + 6] = xch[3][xp];
+                Ap[kZ + 2] = zst[2];
+                Ap[kZ + 5] = xch[8][xm];
+                Ap[kZ + 6] = xch[9][xp];
+            }
+            if (walls && v == 0) {  // bottom wall: -y movers come back reversed
+                A0[kH + 2] = hs[4];
+                A0[kH + 5] = hs[7];
+                A0[kH + 6] = hs[8];
+                A0[kZ + 2] = zst[4];
+                A0[kZ + 5] = zst[7];
+                A0[kZ + 6] = zst[8];
+            } else {
+                A1[kH + 4] = hs[4];
+                A1[kH + 7] = xch[4][xp];
+                A1[kH + 8] = xch[5][xm];
+                A1[kZ + 4] = zst[4];
+                A1[kZ + 7] = xch[10][xp];
+                A1[kZ + 8] = xch[11][xm];
+            }
+        }
+        // ---- phi_{n+1} of row v - 1, whose state is complete now
+        {
+            const int q = v - 1;
+            const bool need = q >= a - 1 && q <= e && (!walls || (q >= 0 && q < ny));
+            if (need) put_phi(phN1, q, phi_of(A1));
+        }
+        // ---- rotate
+#pragma unroll
+        for (int q = 0; q < kNS; ++q) {
+            A3[q] = A2[q];
+            A2[q] = A1[q];
+            A1[q] = A0[q];
+            A0[q] = Ap[q];
+            cur[q] = nxt[q];
         }
     }
 }
@@ -701,13 +978,25 @@ hipError_t launch_chan_step(const ChanK& k, const S* fc, S* fn, const S* gc, S* 
 }
 
 template <typename S>
-hipError_t launch_phase_step(const PhaseK& k, const S* hc, S* hn, const S* zc, S* zn, S* phiu,
-                             hipStream_t s) {
+hipError_t launch_phase_step(const PhaseK& k, const S* hc, S* hn, const S* zc, S* zn, const S* puc,
+                             S* pun, hipStream_t s) {
     const long long tiles = (long long)((k.nx + TX - 1) / TX) * ((k.ny + TY - 1) / TY) * k.batch;
     dim3 blk(TX, TY), grd(unsigned((tiles + kXCD - 1) / kXCD * kXCD));
     const unsigned lds = std::is_same<S, float>::value ? kPhaseLdsReserve : 0u;
-    hipLaunchKernelGGL((k_phase<S, S, false>), grd, blk, lds, s, k, hc, hn, zc, zn, phiu,
+    hipLaunchKernelGGL((k_phase<S, S, false>), grd, blk, lds, s, k, hc, hn, zc, zn, puc, pun,
                        (double*)nullptr);
+    return hipGetLastError();
+}
+
+bool phase_tb2_fits(const PhaseK& k) { return k.nx % 64 == 0 && k.nx <= kTbMaxNx; }
+
+template <typename S>
+hipError_t launch_phase_tb2(const PhaseK& k, const S* a, S* b, hipStream_t s) {
+    if (!phase_tb2_fits(k)) return hipErrorInvalidValue;
+    const int seg = k.ny < 2 * kTbSeg ? k.ny : kTbSeg;
+    const long long wgs = (long long)((k.ny + seg - 1) / seg) * k.batch;
+    dim3 blk(k.nx), grd(unsigned((wgs + kXCD - 1) / kXCD * kXCD));
+    hipLaunchKernelGGL(k_phase_tb2<S>, grd, blk, 0, s, k, a, b, seg);
     return hipGetLastError();
 }
 
@@ -751,7 +1040,7 @@ hipError_t launch_phase_macros(const PhaseK& k, const S* h, const S* z, double* 
     const long long tiles = (long long)((k.nx + TX - 1) / TX) * ((k.ny + TY - 1) / TY) * k.batch;
     dim3 blk(TX, TY), grd(unsigned((tiles + kXCD - 1) / kXCD * kXCD));
     hipLaunchKernelGGL((k_phase<S, double, true>), grd, blk, 0, s, k, h, (S*)nullptr, z,
-                       (S*)nullptr, (S*)nullptr, out);
+                       (S*)nullptr, (const S*)nullptr, (S*)nullptr, out);
     return hipGetLastError();
 }
 
@@ -789,8 +1078,9 @@ hipError_t launch_nusselt(const ChanK& k, const S* f, const S* g, const S* qw, d
 #define LBM_INST(S)                                                                              \
     template hipError_t launch_chan_step<S>(const ChanK&, const S*, S*, const S*, S*, const S*, \
                                             const S*, const S*, double, hipStream_t);             \
-    template hipError_t launch_phase_step<S>(const PhaseK&, const S*, S*, const S*, S*, S*,      \
-                                             hipStream_t);                                        \
+    template hipError_t launch_phase_step<S>(const PhaseK&, const S*, S*, const S*, S*,          \
+                                             const S*, S*, hipStream_t);                          \
+    template hipError_t launch_phase_tb2<S>(const PhaseK&, const S*, S*, hipStream_t);           \
     template hipError_t launch_chan_init<S>(const ChanK&, const double*, S*, S*, hipStream_t);   \
     template hipError_t launch_phase_init<S>(const PhaseK&, const double*, S*, S*, S*,           \
                                              hipStream_t);                                        \

@@ -32,7 +32,8 @@ REDUCE_BITS = {"mass": 1, "phase": 2, "energy": 4, "nonfinite": 8}
 EXPORTS = ("lbm_query_bytes", "lbm_create", "lbm_destroy", "lbm_set_params_SI",
            "lbm_init_fields", "lbm_step", "lbm_macros", "lbm_reduce", "lbm_nusselt",
            "lbm_query_record_bytes", "lbm_record", "lbm_grad", "lbm_time",
-           "lbm_save_state", "lbm_load_state", "lbm_last_error", "lbm_set_graph_steps")
+           "lbm_save_state", "lbm_load_state", "lbm_last_error", "lbm_set_graph_steps",
+           "lbm_set_step_fusion")
 
 
 class LbmError(RuntimeError):
@@ -101,6 +102,7 @@ def lib():
         L.lbm_record.argtypes = [vp, C.c_int, C.c_int, C.POINTER(Objective), vp, C.c_size_t, _dp]
         L.lbm_grad.argtypes = [vp, C.c_double, _dp, _dp]
         L.lbm_set_graph_steps.argtypes = [vp, C.c_int]
+        L.lbm_set_step_fusion.argtypes = [vp, C.c_int]
         for name in EXPORTS:
             if name not in ("lbm_destroy", "lbm_time", "lbm_last_error"):
                 getattr(L, name).restype = C.c_int
@@ -240,6 +242,10 @@ class Lattice:
     def set_graph_steps(self, steps):
         """Steps per captured HIP graph replayed by ``step`` (0 disables)."""
         self._check(lib().lbm_set_graph_steps(self.ctx, int(steps)))
+
+    def set_step_fusion(self, mode):
+        """Two-phase kernel choice: 0 automatic, 1 single-step, 2 two-step."""
+        self._check(lib().lbm_set_step_fusion(self.ctx, int(mode)))
 
     @property
     def t(self):

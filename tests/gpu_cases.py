@@ -60,13 +60,14 @@ def channel_pair(prm, ini, nx, ny, steps, prec, bc_x="inlet_outlet", bc_y="walls
     return {k: v[0] for k, v in g.items()}, o.macros(), L, o
 
 
-def phase_pair(prm, ini, nx, ny, steps, prec, bc_y="periodic", replica=0, batch=None):
+def phase_pair(prm, ini, nx, ny, steps, prec, bc_y="periodic", replica=0, batch=None, fusion=0):
     from paper_2302_04120_amd import lbm
     phi = ini["phi"]
     if batch is None:
         batch = phi.shape[0]
     bcy = (lbm.BC_WALL, lbm.BC_WALL) if bc_y == "walls" else (0, 0)
     L = lbm.Lattice("phase", nx, ny, batch=batch, prec=prec, bc=(0, 0) + bcy)
+    L.set_step_fusion(fusion)
     L.set_params(prm)
     L.init(ini["p"][:batch], ini["ux"][:batch], ini["uy"][:batch], None, phi[:batch])
     L.step(steps)

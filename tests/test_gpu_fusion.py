@@ -1,0 +1,105 @@
+"""The two-step (temporally blocked) two-phase kernel against the single-step
+kernel and the oracle.  Both kernels evaluate the same per-node arithmetic
+in the same order, so a run of either must give the same state to the last
+bit; the cases cover periodic and walled y, one and several 64-row
+segments, odd step counts (the last step single) and graph replay."""
+import numpy as np
+import pytest
+
+from paper_2302_04120_amd import workloads as WL
+
+from gpu_cases import phase_pair, print_case, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(prm, ini, nx, ny, batch, prec, fusion, steps, walls, graph_steps=0):
+    from paper_2302_04120_amd import lbm
+    bc = (0, 0, lbm.BC_WALL, lbm.BC_WALL) if walls else (0, 0, 0, 0)
+    L = lbm.Lattice("phase", nx, ny, batch=batch, prec=prec, bc=bc)
+    L.set_step_fusion(fusion)
+    L.set_graph_steps(graph_steps)
+    L.set_params(prm)
+    L.init(ini["p"], ini["ux"], ini["uy"], None, ini["phi"])
+    for s in steps:
+        L.step(s)
+    return L
+
+
+def _bubble_case(nx, ny, batch, seed):
+    """Bubbles of radius 12-20 nodes in an nx x ny periodic cell."""
+    prm, ini, _ = WL.bubble(n=nx, ny=ny, radii=(12, 16, 20), batch=batch, seed=seed)
+    return prm, ini
+
+
+def _layered_case(nx, ny):
+    prm, ini, _ = WL.layered(nx=nx, ny=ny, seed=0, dx=5e-6, dt=1e-7, W_nodes=5.0)
+    return prm, ini
+
+
+CASES = [
+    # nx, ny, batch, walls, steps
+    (64, 64, 2, False, (7, 10)),      # one segment, odd call
+    (128, 160, 1, False, (12,)),      # three segments, ragged last one
+    (256, 256, 2, False, (6, 5)),     # four segments, the bench cell
+    (64, 200, 1, True, (9, 8)),       # walls, ragged segments
+    (192, 40, 1, True, (10,)),        # walls, one short segment
+]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("nx,ny,batch,walls,steps", CASES)
+def test_two_step_kernel_bit_identical(nx, ny, batch, walls, steps, prec):
+    print_case(test="tb2-bits", nx=nx, ny=ny, batch=batch, walls=walls, prec=prec)
+    if walls:
+        prm, ini = _layered_case(nx, ny)
+        batch = 1
+    else:
+        prm, ini = _bubble_case(nx, ny, batch, seed=nx + ny)
+    one = _run(prm, ini, nx, ny, batch, prec, 1, steps, walls)
+    two = _run(prm, ini, nx, ny, batch, prec, 2, steps, walls)
+    s1, s2 = one.save_state(), two.save_state()
+    if s1 != s2:
+        m1, m2 = one.macros(("phi", "p", "ux")), two.macros(("phi", "p", "ux"))
+        diffs = {k: float(np.abs(m1[k] - m2[k]).max()) for k in m1}
+        raise AssertionError("two-step state differs from single-step: %s" % diffs)
+    assert one.t == two.t == sum(steps)
+    red = two.reduce(("phase", "nonfinite"))
+    assert red["nonfinite"].sum() == 0
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_two_step_kernel_with_graph_replay(prec):
+    """Graph replay of two-step launches: the graph makes an odd number of
+    buffer swaps per replay (graph_steps / 2 = 3)."""
+    prm, ini = _bubble_case(128, 128, 2, seed=5)
+    print_case(test="tb2-graph", prec=prec)
+    ref = _run(prm, ini, 128, 128, 2, prec, 1, (), False)
+    gr = _run(prm, ini, 128, 128, 2, prec, 2, (), False, graph_steps=6)
+    for rep, n in enumerate((13, 12, 25)):
+        ref.step(n)
+        gr.step(n)
+        assert ref.save_state() == gr.save_state(), rep
+
+
+def test_two_step_kernel_against_oracle():
+    """Direct parity of the two-step path with the FP64 oracle (FP32
+    deviation storage, 20 steps, one bubble in a 256 x 128 cell: two segments)."""
+    prm, ini = _bubble_case(256, 128, 1, seed=11)
+    print_case(test="tb2-oracle")
+    g, o, L, _ = phase_pair(prm, ini, 256, 128, 20, "fp32", fusion=2)
+    scale_p = max(float(np.abs(o["p"]).max()), prm["sigma"] / prm["W"])
+    assert rel_err(g["phi"], o["phi"], scale=1.0) < 1e-5
+    assert rel_err(g["p"], o["p"], scale=scale_p) < 1e-5
+    assert rel_err(g["ux"], o["ux"]) < 1e-4
+
+
+def test_fusion_validation():
+    from paper_2302_04120_amd import lbm
+    prm, ini = _bubble_case(96, 64, 1, seed=0)
+    L = lbm.Lattice("phase", 96, 64, prec="fp32")
+    with pytest.raises(lbm.LbmError):
+        L.set_step_fusion(2)  # nx not a multiple of 64
+    with pytest.raises(lbm.LbmError):
+        L.set_step_fusion(3)
+    L.set_step_fusion(1)
