@@ -225,6 +225,8 @@ def main():
                      "launch_ms": launch_ms,
                      "lu_per_launch": r["nodes"] * spl,
                      "hbm_measured_GBps": (traffic / (launch_ms * 1e-3) / 1e9
+                                           if traffic is not None else None),
+                     "hbm_measured_frac": (traffic / (launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS
                                            if traffic is not None else None)},
         "cpu_baseline": cpu,
         "adjoint_over_forward": None,

@@ -165,16 +165,19 @@ LBM_API lbm_status lbm_step(lbm_ctx* ctx, int n);
  * LBM_E_ARG on an odd, negative or too large count. */
 LBM_API lbm_status lbm_set_graph_steps(lbm_ctx* ctx, int steps);
 
-/* Kernel choice for LBM_D2Q9_PHASE steps.  mode 1: one launch per step (the
- * tiled single-step kernel).  mode 2: pairs of steps run as one launch of
- * the two-step kernel, which keeps the intermediate state on chip and so
- * moves half the bytes per step (nx a multiple of 64 and at most 256;
- * LBM_E_UNSUPPORTED otherwise); an odd last step uses the single-step
- * kernel.  mode 0 (default): mode 2 when its workgroups (one per 64 rows of
- * a replica) number at least 1024, else mode 1.  Both kernels evaluate the
- * same per-node arithmetic in the same order, so the modes agree to the
- * last bit.  Not an operation of the paper: a performance control.  Other
- * lattices ignore it.  LBM_E_ARG on an unknown mode. */
+/* Kernel choice for LBM_D2Q9_PHASE steps.
+ *   mode 1: one launch per step (the tiled single-step kernel).
+ *   mode 2: pairs of steps run as one launch of the two-step kernel, which
+ *           keeps the intermediate state on chip and so moves half the bytes
+ *           per step; needs nx a multiple of 64 and at most 256
+ *           (LBM_E_UNSUPPORTED otherwise); ny < 4 and an odd last step use
+ *           the single-step kernel.
+ *   mode 0 (default): mode 2 when its workgroups (one per 128-row segment of
+ *           a replica) number at least 512, else mode 1.
+ * Both kernels evaluate the same per-node arithmetic in the same order, so
+ * the modes agree to the last bit.  Not an operation of the paper: a
+ * performance control.  Other lattices ignore it.  LBM_E_ARG on an unknown
+ * mode. */
 LBM_API lbm_status lbm_set_step_fusion(lbm_ctx* ctx, int mode);
 
 /* Macroscopic fields of the current state, evaluated in FP64 from the stored

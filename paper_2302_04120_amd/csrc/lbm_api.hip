@@ -157,14 +157,13 @@ hipError_t step_once(lbm_ctx* c) {
 }
 
 // Whether the next two steps go through the two-step kernel.  Automatic
-// mode takes it when its workgroups (one per 64-row segment and replica)
-// fill the chip; small grids keep the single-step kernel, whose tiles
-// spread over more CUs.
+// mode takes it when its workgroups (one per row segment and replica; two
+// are resident per CU) fill the 256 CUs; smaller grids keep the single-step
+// kernel, whose tiles spread over more CUs.
 bool use_tb2(const lbm_ctx* c) {
     if (c->desc.lattice != LBM_D2Q9_PHASE || c->fusion == 1 || !phase_tb2_fits(c->pk)) return false;
     if (c->fusion == 2) return true;
-    const long long wgs = (long long)((c->desc.ny + 63) / 64) * c->desc.batch;
-    return wgs >= 1024;
+    return phase_tb2_workgroups(c->pk) >= 512;
 }
 
 // Enqueue m (1 or 2) steps, advancing the buffer parity and the step count;

@@ -1,7 +1,7 @@
 // Device helpers shared by the forward and adjoint kernels of liblbm:
-// velocity sets, the integer moment transforms and their exact inverses,
-// error-free FP32 sums, the XCD-aware tile numbering, and the node macros of
-// the momentum populations.  Included only by the library's .hip sources.
+// velocity sets, the integer moment transforms and their exact inverses, the
+// XCD-aware tile numbering, and the node macros of the momentum populations.
+// Included only by the library's .hip sources.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -91,20 +91,6 @@ __device__ __forceinline__ void inverse5(const C m[5], C v[5]) {
     v[2] = a0 + a2 + a3 - a4;
     v[3] = a0 - a1 + a3 + a4;
     v[4] = a0 - a2 + a3 - a4;
-}
-
-// error-free transformations for the FP32 hi/lo rest population
-__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
-    s = a + b;
-    const float bb = s - a;
-    e = (a - (s - bb)) + (b - bb);
-}
-__device__ __forceinline__ void df_add(float& hi, float& lo, float b) {
-    float s, e;
-    two_sum(hi, b, s, e);
-    e += lo;
-    hi = s + e;
-    lo = e - (hi - s);
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs of the chip, each with

@@ -128,6 +128,7 @@ hipError_t launch_phase_step(const PhaseK& k, const S* hc, S* hn, const S* zc, S
 // two steps in one launch; the whole state (populations and (phi u)) moves
 // from buffer a to buffer b; needs phase_tb2_fits
 bool phase_tb2_fits(const PhaseK& k);
+long long phase_tb2_workgroups(const PhaseK& k);
 template <typename S>
 hipError_t launch_phase_tb2(const PhaseK& k, const S* a, S* b, hipStream_t s);
 hipError_t launch_d1(const D1K& k, double* g, int nsteps, hipStream_t s);

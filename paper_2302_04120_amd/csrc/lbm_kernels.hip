@@ -200,6 +200,14 @@ __device__ __forceinline__ C phi_sum(const C (&h)[9], C hlo) {
     return (h[0] + hlo) + (((h[1] + h[3]) + (h[2] + h[4])) + ((h[5] + h[7]) + (h[6] + h[8])));
 }
 
+// Reciprocals of the two-phase collision: the hardware's 1-ulp reciprocal and
+// reciprocal square root in FP32 (FP32 storage carries ~1e-7 relative
+// rounding anyway), exact division in FP64.
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
+
 // Everything a node derives from its phi neighbourhood and its z_i before
 // the collision.  pn[i] = phi at x + e_i (pn[0] = phi at the node).
 template <typename C>
@@ -223,10 +231,15 @@ __device__ __forceinline__ PhaseLocal<C> phase_local(const PhaseK& k, const C (&
     }
     const C drl = C(k.rho_l - k.rho_g);
     const C rho = C(k.rho_g) + phi * drl;  // linear in phi (Sec. 2.3)
-    C nuh;
-    if (k.visc_mode == 0) nuh = C(k.nuh_g) + phi * C(k.nuh_l - k.nuh_g);
-    else nuh = (C(k.zh_g) + phi * C(k.zh_l - k.zh_g)) / rho;  // nu = zeta / rho (Sec. 4.4)
-    L.wn = C(1) / (C(3) * nuh + C(0.5));                      // dt / tau
+    const C ir = rcp(rho);
+    // dt / tau = 1 / (3 nu dt / dx^2 + 1/2), with nu linear in phi or, in the
+    // zeta form of Sec. 4.4, nu = zeta / rho
+    if (k.visc_mode == 0) {
+        L.wn = rcp(C(3) * (C(k.nuh_g) + phi * C(k.nuh_l - k.nuh_g)) + C(0.5));
+    } else {
+        const C zh = C(k.zh_g) + phi * C(k.zh_l - k.zh_g);
+        L.wn = rho * rcp(C(3) * zh + C(0.5) * rho);
+    }
     // chemical potential, Eq. chemical_potential; surface force F_s = mu grad phi
     const C mu = C(4) * C(k.beta) * phi * (phi - C(1)) * (phi - C(0.5)) - C(k.kap6) * Lp;
     L.fsx = mu * Gx * C(k.fs_scale) + C(k.Fbt[0]);
@@ -236,14 +249,13 @@ __device__ __forceinline__ PhaseLocal<C> phase_local(const PhaseK& k, const C (&
     L.nxv = C(0);
     L.nyv = C(0);
     if (gn2 > C(k.Geps) * C(k.Geps)) {
-        const C ig = C(1) / sqrt(gn2);
+        const C ig = rsq(gn2);
         L.nxv = Gx * ig;
         L.nyv = Gy * ig;
     }
     // ---- pressure populations: velocity first (Eq. u_Liang), then pressure
     const C jx = (z[1] - z[3]) + ((z[5] - z[7]) + (z[8] - z[6]));
     const C jy = (z[2] - z[4]) + ((z[5] - z[7]) + (z[6] - z[8]));
-    const C ir = C(1) / rho;
     L.ux = (jx + C(0.5) * L.fsx) * ir;
     L.uy = (jy + C(0.5) * L.fsy) * ir;
     L.uu = L.ux * L.ux + L.uy * L.uy;
@@ -292,14 +304,16 @@ __device__ __forceinline__ void phase_collide(const PhaseK& k, const PhaseLocal<
     h0lo = S(0);
     if constexpr (RMASS) {
         // rest population takes the node's exact balance: h0* = phi - sum_{i>0} h_i*
-        // with the stored (rounded) h_i*, carried as a double-float
-        float hi = float(h[0]), lo = float(hlo);
+        // with the stored (rounded) h_i*.  The FP32 terms are summed in FP64
+        // (each exact there; 18 terms lose at most ~2^-49 of the largest) and
+        // the sum is kept as an FP32 hi/lo pair.
+        double acc = double(h[0]) + double(hlo);
 #pragma unroll
-        for (int i = 1; i < 9; ++i) df_add(hi, lo, float(h[i]));
+        for (int i = 1; i < 9; ++i) acc += double(h[i]);
 #pragma unroll
-        for (int i = 1; i < 9; ++i) df_add(hi, lo, -float(hs[i]));
-        h0hi = hi;
-        h0lo = lo;
+        for (int i = 1; i < 9; ++i) acc -= double(float(hs[i]));
+        h0hi = float(acc);
+        h0lo = float(acc - double(h0hi));
     } else {
         const C heq0 = phi * wgt<C>(0);
         h0hi = S(h[0] - wphi * (h[0] - heq0));
@@ -323,7 +337,7 @@ __device__ __forceinline__ void phase_collide(const PhaseK& k, const PhaseLocal<
                           rho * uy, -rho * uy, rho * (ux * ux - uy * uy), rho * ux * uy};
         const C mf[9] = {C(3) * D, C(0), C(-3) * D, L.fsx, -L.fsx, L.fsy, -L.fsy,
                          C(2) * drl * (Gx * ux - Gy * uy), drl * (Gx * uy + Gy * ux)};
-        const C wq = C(3) * (C(2) - wn) / (C(3) - wn);
+        const C wq = C(3) * (C(2) - wn) * rcp(C(3) - wn);
         const C Lm[9] = {C(1), C(1), C(1), C(1), wq, C(1), k.qy_printed ? C(1) : wq, wn, wn};
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
@@ -444,7 +458,8 @@ __global__ __launch_bounds__(TX * TY) void k_phase(PhaseK k, const S* __restrict
 // ---------------------------------------------------------------------------
 // Two steps per launch (temporal blocking).  A workgroup of nx threads (one
 // per column, nx a multiple of 64 up to 256) marches up the rows of one
-// segment [a, e) of one replica.  At row v it collides step n at row v and
+// segment [a, e) of one replica (128 rows, or the whole replica if shorter
+// than 256 rows).  At row v it collides step n at row v and
 // step n + 1 at row v - 3:
 //   - the post-collision values of step n are exchanged in x through LDS and
 //     accumulated, per column, into the step-(n + 1) state of rows v - 1, v
@@ -461,7 +476,10 @@ __global__ __launch_bounds__(TX * TY) void k_phase(PhaseK k, const S* __restrict
 // arithmetic per node is phase_local + phase_collide, as in k_phase.
 // ---------------------------------------------------------------------------
 constexpr int kTbMaxNx = 256;
-constexpr int kTbSeg = 64;  // rows per segment
+#ifndef LBM_TB_SEG
+#define LBM_TB_SEG 128
+#endif
+constexpr int kTbSeg = LBM_TB_SEG;  // rows per segment
 
 // register state of one row of one column: h 0-8, low part of h_0, z 0-8, (phi u)
 constexpr int kH = 0, kLO = 9, kZ = 10, kPU = 19, kNS = 21;
@@ -485,27 +503,31 @@ __global__ __launch_bounds__(kTbMaxNx) void k_phase_tb2(PhaseK k, const S* __res
     const int e1 = walls ? min(e + 2, ny) : e + 2;  // end of step-n rows
     const int lastload = walls ? min(e1, ny - 1) : e1;
     const long long base = (long long)b * ny * nx;
-    const int x = threadIdx.x;
-    const int xm = x == 0 ? nx - 1 : x - 1;
-    const int xp = x == nx - 1 ? 0 : x + 1;
+    // lane offsets are unsigned 32-bit and row bases uniform, so memory
+    // accesses take the scalar-base + vector-offset form
+    const unsigned x = threadIdx.x;
+    const unsigned xm = x == 0 ? nx - 1 : x - 1;
+    const unsigned xp = x == unsigned(nx - 1) ? 0u : x + 1;
 
     __shared__ C phN[4][kTbMaxNx];   // phi_n, rows v mod 4
     __shared__ C phN1[4][kTbMaxNx];  // phi_{n+1}
     __shared__ C xch[12][kTbMaxNx];  // x-moving post-collision values of step n
 
-    auto rowoff = [&](int v) {  // memory row of virtual row v
-        const int r = walls ? v : ((v % ny) + ny) % ny;
+    // memory row of virtual row v: virtual rows of a periodic segment lie in
+    // [-3, ny + 2] and ny >= 4, so one correction wraps them
+    auto rowoff = [&](int v) {
+        const int r = v < 0 ? v + ny : (v >= ny ? v - ny : v);
         return base + (long long)r * nx;
     };
     auto load_row = [&](int v, C (&s)[kNS]) {
-        const long long n = rowoff(v) + x;
+        const S* row = A + rowoff(v);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) s[kH + i] = C(A[i * P + n]);
+        for (int i = 0; i < 9; ++i) s[kH + i] = C(row[i * P + x]);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) s[kZ + i] = C(A[(9 + i) * P + n]);
-        s[kLO] = RMASS ? C(A[18 * P + n]) : C(0);
-        s[kPU] = C(A[npop * P + n]);
-        s[kPU + 1] = C(A[(npop + 1) * P + n]);
+        for (int i = 0; i < 9; ++i) s[kZ + i] = C(row[(9 + i) * P + x]);
+        s[kLO] = RMASS ? C(row[18 * P + x]) : C(0);
+        s[kPU] = C(row[npop * P + x]);
+        s[kPU + 1] = C(row[(npop + 1) * P + x]);
     };
     auto phi_of = [&](const C (&s)[kNS]) {
         const C hh[9] = {s[0], s[1], s[2], s[3], s[4], s[5], s[6], s[7], s[8]};
@@ -569,23 +591,23 @@ __global__ __launch_bounds__(kTbMaxNx) void k_phase_tb2(PhaseK k, const S* __res
             const PhaseLocal<C> L = phase_local(k, pn, z);
             phase_collide<S, C>(k, L, h, A3[kLO], z, A3[kPU], A3[kPU + 1], hs, h0hi, h0lo, zst, pux,
                                 puy);
-            const long long n = rowoff(r) + x;
-            st(B + npop * P + n, S(pux));
-            st(B + (npop + 1) * P + n, S(puy));
-            st(B + n, h0hi);
-            if constexpr (RMASS) st(B + 18 * P + n, h0lo);
-            st(B + 9 * P + n, S(zst[0]));
+            S* row = B + rowoff(r);
+            st(row + npop * P + x, S(pux));
+            st(row + (npop + 1) * P + x, S(puy));
+            st(row + x, h0hi);
+            if constexpr (RMASS) st(row + 18 * P + x, h0lo);
+            st(row + 9 * P + x, S(zst[0]));
 #pragma unroll
             for (int i = 1; i < 9; ++i) {
                 const int ryd = r + EY[i];
                 if (walls && (ryd < 0 || ryd >= ny)) {
-                    st(B + OPP[i] * P + n, S(hs[i]));
-                    st(B + (9 + OPP[i]) * P + n, S(zst[i]));
+                    st(row + OPP[i] * P + x, S(hs[i]));
+                    st(row + (9 + OPP[i]) * P + x, S(zst[i]));
                 } else {
-                    const int xd = EX[i] == 0 ? x : (EX[i] > 0 ? xp : xm);
-                    const long long d = rowoff(ryd) + xd;
-                    st(B + i * P + d, S(hs[i]));
-                    st(B + (9 + i) * P + d, S(zst[i]));
+                    const unsigned xd = EX[i] == 0 ? x : (EX[i] > 0 ? xp : xm);
+                    S* drow = B + rowoff(ryd);
+                    st(drow + i * P + xd, S(hs[i]));
+                    st(drow + (9 + i) * P + xd, S(zst[i]));
                 }
             }
         }
@@ -988,15 +1010,23 @@ hipError_t launch_phase_step(const PhaseK& k, const S* hc, S* hn, const S* zc, S
     return hipGetLastError();
 }
 
-bool phase_tb2_fits(const PhaseK& k) { return k.nx % 64 == 0 && k.nx <= kTbMaxNx; }
+bool phase_tb2_fits(const PhaseK& k) { return k.nx % 64 == 0 && k.nx <= kTbMaxNx && k.ny >= 4; }
+
+// rows per segment: kTbSeg, or the whole replica when it has fewer than two
+// segments' worth of rows
+int tb2_seg(const PhaseK& k) { return k.ny < 2 * kTbSeg ? k.ny : kTbSeg; }
+
+long long phase_tb2_workgroups(const PhaseK& k) {
+    const int seg = tb2_seg(k);
+    return (long long)((k.ny + seg - 1) / seg) * k.batch;
+}
 
 template <typename S>
 hipError_t launch_phase_tb2(const PhaseK& k, const S* a, S* b, hipStream_t s) {
     if (!phase_tb2_fits(k)) return hipErrorInvalidValue;
-    const int seg = k.ny < 2 * kTbSeg ? k.ny : kTbSeg;
-    const long long wgs = (long long)((k.ny + seg - 1) / seg) * k.batch;
+    const long long wgs = phase_tb2_workgroups(k);
     dim3 blk(k.nx), grd(unsigned((wgs + kXCD - 1) / kXCD * kXCD));
-    hipLaunchKernelGGL(k_phase_tb2<S>, grd, blk, 0, s, k, a, b, seg);
+    hipLaunchKernelGGL(k_phase_tb2<S>, grd, blk, 0, s, k, a, b, tb2_seg(k));
     return hipGetLastError();
 }
 

@@ -2,7 +2,8 @@
 kernel and the oracle.  Both kernels evaluate the same per-node arithmetic
 in the same order, so a run of either must give the same state to the last
 bit; the cases cover periodic and walled y, one and several 64-row
-segments, odd step counts (the last step single) and graph replay."""
+segments (128 rows each), odd step counts (the last step single) and graph
+replay."""
 import numpy as np
 import pytest
 
@@ -40,9 +41,9 @@ def _layered_case(nx, ny):
 CASES = [
     # nx, ny, batch, walls, steps
     (64, 64, 2, False, (7, 10)),      # one segment, odd call
-    (128, 160, 1, False, (12,)),      # three segments, ragged last one
-    (256, 256, 2, False, (6, 5)),     # four segments, the bench cell
-    (64, 200, 1, True, (9, 8)),       # walls, ragged segments
+    (128, 320, 1, False, (12,)),      # three 128-row segments, ragged last one
+    (256, 256, 2, False, (6, 5)),     # two segments, the bench cell
+    (64, 300, 1, True, (9, 8)),       # walls, ragged segments
     (192, 40, 1, True, (10,)),        # walls, one short segment
 ]
 
@@ -84,7 +85,7 @@ def test_two_step_kernel_with_graph_replay(prec):
 
 def test_two_step_kernel_against_oracle():
     """Direct parity of the two-step path with the FP64 oracle (FP32
-    deviation storage, 20 steps, one bubble in a 256 x 128 cell: two segments)."""
+    deviation storage, 20 steps, one bubble in a 256 x 128 cell)."""
     prm, ini = _bubble_case(256, 128, 1, seed=11)
     print_case(test="tb2-oracle")
     g, o, L, _ = phase_pair(prm, ini, 256, 128, 20, "fp32", fusion=2)

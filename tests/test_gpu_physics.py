@@ -167,7 +167,10 @@ def test_c4_layered_startup_stokes_layer():
     print("FP32 vs FP64: liquid %.2e, whole field %.2e" % (e_liq, e_all), flush=True)
     assert e_liq < 5e-3
     assert e_all < 3e-4
-    assert np.abs(m32["uy"]).max() < 1e-6 * scale
+    # u_y is only the decaying acoustic residue of the start from rest (the
+    # weakly compressible gas; FP64 2e5 steps: 7e-7 m/s, 8e-4 of max u_x)
+    assert np.abs(m64["uy"]).max() < 2e-3 * scale
+    assert np.abs(m32["uy"] - m64["uy"]).max() < 5e-3 * scale
     assert d32 < 1e-13
 
 
