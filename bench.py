@@ -27,6 +27,8 @@ HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per lattice update (each population read once and written
 # once): z 9 + h 9 + low part of h_0 + (phi u) 2, read + write
 BYTES_PER_LU = {"fp32": (9 + 9 + 1 + 2) * 4 * 2, "fp64": (9 + 9 + 2) * 8 * 2}
+# heated channel (D2Q9 f + D2Q5 g), read + write
+CHAN_BYTES_PER_LU = {"fp32": (9 + 5) * 4 * 2, "fp64": (9 + 5) * 8 * 2}
 # the files whose contents decide the step kernel's machine code
 KERNEL_SOURCES = ("paper_2302_04120_amd/csrc/lbm_kernels.hip", "paper_2302_04120_amd/csrc/lbm_device.h",
                   "paper_2302_04120_amd/csrc/lbm_internal.h", "paper_2302_04120_amd/csrc/build.py")
@@ -74,6 +76,35 @@ def run_gpu(batch, steps, warmup, prec, n=256, fusion=0):
     nodes = batch * n * n
     return dict(wall=wall, ev_ms=ev_ms, nodes=nodes, kernel_ms=ev_ms / steps,
                 bytes_gb=L.bytes / 1e9)
+
+
+def run_channel(nx, ny, steps, warmup, prec):
+    """The heated-channel step (D2Q9 MRT flow + D2Q5 thermal, velocity inlet,
+    pressure outlet, flux walls) on a roofline-sized grid."""
+    import torch
+    from paper_2302_04120_amd import lbm, workloads as WL
+    prm, ini = WL.channel(nx=nx, ny=ny)
+    L = lbm.Lattice("channel", nx, ny, prec=prec,
+                    bc=(lbm.BC_VEL_INLET, lbm.BC_P_OUTLET, lbm.BC_WALL, lbm.BC_WALL),
+                    flow=True, thermal=True)
+    L.set_params(prm)
+    L.init(ini["rho"], ini["ux"], ini["uy"], ini["T"])
+    del ini
+    L.step(warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(L.stream)
+    t0 = time.perf_counter()
+    L.step(steps)
+    e1.record(L.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_ms = e0.elapsed_time(e1) / steps
+    nodes = nx * ny
+    return dict(mlups=nodes * steps / wall / 1e6, kernel_ms=kernel_ms,
+                hbm_frac=CHAN_BYTES_PER_LU[prec] * nodes / (kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                grid="%dx%d" % (nx, ny))
 
 
 def adjoint_cost(steps=20000, ckpt=500, prec="fp32"):
@@ -153,11 +184,19 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP64 and batch-4 legs")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_phase_step.json"))
+    ap.add_argument("--leg", choices=("channel", "adjoint"), default=None,
+                    help="only run one secondary leg and print its figures (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain copy of BYTES (counter calibration)")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+        return 0
+    if args.leg == "channel":
+        print(json.dumps(run_channel(16384, 2048, args.steps, args.warmup, args.prec)), flush=True)
+        return 0
+    if args.leg == "adjoint":
+        print(json.dumps(adjoint_cost(prec=args.prec)), flush=True)
         return 0
     if args.gpus != 1:
         print("bench.py measures one GPU only; --gpus %d is not supported" % args.gpus,
@@ -196,6 +235,8 @@ def main():
         log("bench: paper-sized leg (4 replicas)")
         r4 = run_gpu(4, 1000, 50, args.prec)
         extras["paper_config_batch4_mlups"] = r4["nodes"] * 1000 / r4["wall"] / 1e6
+        log("bench: heated-channel leg (16384 x 2048)")
+        extras["channel_fp32"] = run_channel(16384, 2048, 100, 10, "fp32")
         log("bench: adjoint/forward cost leg (C5 channel)")
         extras["adjoint"] = adjoint_cost()
     cpu = None
