@@ -70,7 +70,9 @@ enum {
     LBM_BC_WALL = 1,       /* halfway bounce-back (Eq. BB_vel, u_w = 0); thermal flux Eq. BB_T */
     LBM_BC_VEL_INLET = 2,  /* x- only: Eq. BB_vel with the inlet profile; thermal Eq. anti_BB_T */
     LBM_BC_P_OUTLET = 3,   /* x+ only: Eq. anti_BB_vel; thermal first-order extrapolation */
-    LBM_BC_DIRICHLET = 4   /* 1D ends: wet-node fixed temperature (Eq. BCs_1D_advection_diffusion) */
+    LBM_BC_DIRICHLET = 4   /* 1D ends: wet-node fixed temperature (Eq. BCs_1D_advection_diffusion);
+                              D2Q9_D2Q5 x sides (both): no-slip halfway wall (Eq. BB_vel)
+                              held at T_wall by Eq. anti_BB_T (App. D)                    */
 };
 enum { LBM_BGK = 0, LBM_MRT = 1 };
 /* desc.flags for LBM_D2Q9_D2Q5 */
@@ -105,7 +107,8 @@ typedef struct {
     double flux_amp, flux_omega; /* q''(x,t) = flux[x] (1 + amp sin(omega t)), t = step * dt  */
     const double* inlet_u;  /* [ny] m/s inlet velocity profile (NULL = 0)                   */
     const double* inlet_T;  /* [ny] K inlet temperature (NULL = T_ref)                       */
-    double T_wall[2];       /* K: 1D Dirichlet temperatures at x- and x+                    */
+    double T_wall[2];       /* K: Dirichlet temperatures at x- and x+ (1D ends, or the
+                               D2Q9_D2Q5 side walls of kind LBM_BC_DIRICHLET)             */
     /* two-phase (Sec. 2.3, Sec. 4.4) */
     double rho_l, rho_g;    /* kg/m^3 */
     double nu_l, nu_g;      /* m^2/s, used when visc_mode = 0: nu = nu_g + phi (nu_l - nu_g) */
@@ -116,6 +119,10 @@ typedef struct {
     int z_collision;        /* LBM_BGK | LBM_MRT                                             */
     int qy_printed;         /* 0: omega_q2 on both q_x and q_y; 1: on q_x only (as printed)  */
     double normal_eps;      /* 1/m: n = 0 where |grad phi| <= normal_eps (<= 0: default)     */
+    /* natural convection (App. D): Boussinesq force -rho_ref beta_T (T - T_ref) g added
+       to Fb at every node (Eq. buoyancy_force); needs the thermal field */
+    double beta_T;          /* 1/K thermal expansion coefficient (0: no buoyancy)           */
+    double gravity[2];      /* m/s^2                                                         */
 } lbm_params_si;
 
 /* Size in bytes of the device buffer a context with this description needs.

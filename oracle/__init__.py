@@ -47,7 +47,8 @@ class ChanParams(C.Structure):
                 ("omega_eps", C.c_double), ("Fx", C.c_double), ("Fy", C.c_double),
                 ("thermal", C.c_int), ("thermal_mrt", C.c_int),
                 ("alpha", C.c_double), ("rho_cp", C.c_double), ("qdot", C.c_double),
-                ("T_ref", C.c_double), ("flux_amp", C.c_double), ("flux_omega", C.c_double)]
+                ("T_ref", C.c_double), ("flux_amp", C.c_double), ("flux_omega", C.c_double),
+                ("Tw_x", C.c_double * 2), ("buoy", C.c_double * 2)]
 
 
 class PhaseParams(C.Structure):
@@ -123,7 +124,10 @@ def mdim(c):
 class Chan:
     """D2Q9 flow (BGK/MRT) + optional D2Q5 thermal on an nx x ny grid.
 
-    ``bc_x``: 'periodic' or 'inlet_outlet'; ``bc_y``: 'periodic' or 'walls'.
+    ``bc_x``: 'periodic', 'inlet_outlet' or 'walls_T' (no-slip walls held at
+    prm['T_wall'] = (T at x-, T at x+), App. D); ``bc_y``: 'periodic' or
+    'walls'.  prm['beta_T'] (1/K) with prm['gravity'] (m/s^2) adds the
+    Boussinesq force -rho_ref beta (T - T_ref) g of Eq. buoyancy_force.
     """
 
     def __init__(self, nx, ny, prm, bc_x="periodic", bc_y="periodic", flow=True,
@@ -131,7 +135,7 @@ class Chan:
         self.nx, self.ny = nx, ny
         P = ChanParams()
         P.nx, P.ny = nx, ny
-        P.bc_x = {"periodic": 0, "inlet_outlet": 1}[bc_x]
+        P.bc_x = {"periodic": 0, "inlet_outlet": 1, "walls_T": 2}[bc_x]
         P.bc_y = {"periodic": 0, "walls": 1}[bc_y]
         P.dx, P.dt = prm["dx"], prm["dt"]
         P.flow = 1 if flow else 0
@@ -149,6 +153,12 @@ class Chan:
         P.T_ref = prm.get("T_ref", 0.0)
         P.flux_amp = prm.get("flux_amp", 0.0)
         P.flux_omega = prm.get("flux_omega", 0.0)
+        tw = prm.get("T_wall", (P.T_ref, P.T_ref))
+        P.Tw_x[0], P.Tw_x[1] = tw[0], tw[1]
+        # Boussinesq force per kelvin, -rho_ref beta g (Eq. buoyancy_force)
+        beta = prm.get("beta_T", 0.0)
+        gx, gy = prm.get("gravity", (0.0, 0.0))
+        P.buoy[0], P.buoy[1] = -P.rho_ref * beta * gx, -P.rho_ref * beta * gy
         self.P = P
         flux = _f64(prm.get("flux", 0.0), (nx,))
         inlet_u = _f64(prm.get("inlet_u", 0.0), (ny,))

@@ -382,8 +382,18 @@ void orc_chan_init(orc_chan* s, const double* rho, const double* ux, const doubl
     s->t = 0;
 }
 
-/* Macros of the pre-collision state: rho (Eq. zero_moment_f), u with the half
- * force (Eq. first_moment_f), T with the half source (Eq. zero_moment_g). */
+/* Body force at a node of temperature T: the constant force plus, for
+ * natural convection, the Boussinesq force -rho_ref beta (T - T_ref) g of
+ * Eq. buoyancy_force (App. D), with buoy = -rho_ref beta g. */
+static void chan_force(const orc_chan* s, double T, double* Fx, double* Fy) {
+    const orc_chan_params* p = &s->p;
+    *Fx = p->Fx + p->buoy[0] * (T - p->T_ref);
+    *Fy = p->Fy + p->buoy[1] * (T - p->T_ref);
+}
+
+/* Macros of the pre-collision state: rho (Eq. zero_moment_f), T with the half
+ * source (Eq. zero_moment_g), then u with the half force (Eq. first_moment_f),
+ * the force taken at this T. */
 static void chan_node_macros(const orc_chan* s, int x, int y, double* rho, double* ux,
                              double* uy, double* T) {
     const orc_chan_params* p = &s->p;
@@ -396,9 +406,11 @@ static void chan_node_macros(const orc_chan* s, int x, int y, double* rho, doubl
     }
     for (int i = 0; i < 5; ++i) t += s->g[IDX(s, i, x, y)];
     *rho = r;
-    *ux = (jx + 0.5 * p->dt * p->Fx) / r;
-    *uy = (jy + 0.5 * p->dt * p->Fy) / r;
     *T = t + 0.5 * p->dt * p->qdot;
+    double Fx, Fy;
+    chan_force(s, *T, &Fx, &Fy);
+    *ux = (jx + 0.5 * p->dt * Fx) / r;
+    *uy = (jy + 0.5 * p->dt * Fy) / r;
 }
 
 void orc_chan_macros(const orc_chan* s, double* rho, double* ux, double* uy, double* T) {
@@ -429,11 +441,12 @@ static void chan_collide_node(orc_chan* s, int x, int y) {
     size_t n = (size_t)y * p->nx + x;
     double rho = s->rho[n], ux = s->ux[n], uy = s->uy[n], T = s->T[n];
     if (p->flow) {
-        double f[9], fe[9], Fh[9], d[9], a[9], b[9];
+        double f[9], fe[9], Fh[9], d[9], a[9], b[9], Fx, Fy;
+        chan_force(s, T, &Fx, &Fy);
         for (int i = 0; i < 9; ++i) {
             f[i] = s->f[IDX(s, i, x, y)];
             fe[i] = feq9(i, rho, ux, uy, s->c, s->cs2);
-            Fh[i] = guo9(i, ux, uy, p->Fx, p->Fy, s->c, s->cs2);
+            Fh[i] = guo9(i, ux, uy, Fx, Fy, s->c, s->cs2);
         }
         if (p->flow_mrt) {
             /* moment space, Eq. colisao_MRT with the dimensional matrix of Sec. 3 */
@@ -476,7 +489,7 @@ static void chan_collide_node(orc_chan* s, int x, int y) {
 }
 
 /* classification of the source node x - e_i of a population i arriving at (x, y) */
-enum { SRC_IN = 0, SRC_WALL = 1, SRC_INLET = 2, SRC_OUTLET = 3 };
+enum { SRC_IN = 0, SRC_WALL = 1, SRC_INLET = 2, SRC_OUTLET = 3, SRC_XWALL = 4 };
 static int chan_src(const orc_chan* s, int x, int y, int ex, int ey, int* xs, int* ys) {
     int nx = s->p.nx, ny = s->p.ny;
     int sx = x - ex, sy = y - ey;
@@ -489,6 +502,7 @@ static int chan_src(const orc_chan* s, int x, int y, int ex, int ey, int* xs, in
     /* tie-break at corners (the paper is silent): a link whose source lies
      * outside in y takes the wall rule, otherwise the x-boundary rule */
     if (outy) return SRC_WALL;
+    if (outx && s->p.bc_x == 2) return SRC_XWALL;
     if (outx) return sx < 0 ? SRC_INLET : SRC_OUTLET;
     return SRC_IN;
 }
@@ -514,7 +528,8 @@ static void chan_stream(orc_chan* s) {
                 int kind = chan_src(s, x, y, EX9[i], EY9[i], &xs, &ys);
                 double v;
                 if (kind == SRC_IN) v = s->fs[IDX(s, i, xs, ys)];
-                else if (kind == SRC_WALL) v = s->fs[IDX(s, o, x, y)]; /* Eq. BB_vel, u_w = 0 */
+                else if (kind == SRC_WALL || kind == SRC_XWALL)
+                    v = s->fs[IDX(s, o, x, y)]; /* Eq. BB_vel, u_w = 0 */
                 else if (kind == SRC_INLET) {
                     /* moving-wall bounce-back, Eq. BB_vel, with rho_w = rho_ref and
                      * u_w the inlet profile; outgoing direction o, c_o = -c_i */
@@ -547,6 +562,9 @@ static void chan_stream(orc_chan* s) {
                     /* anti-bounce-back Dirichlet, Eq. anti_BB_T; reading: only the
                      * even part of the linear equilibrium actually used, 2 w T_w */
                     v = -s->gs[IDX(s, o, x, y)] + 2.0 * W5[o] * s->inlet_T[y];
+                } else if (kind == SRC_XWALL) {
+                    /* fixed-temperature side wall (App. D), the same Eq. anti_BB_T */
+                    v = -s->gs[IDX(s, o, x, y)] + 2.0 * W5[o] * p->Tw_x[xs < 0 ? 0 : 1];
                 }
                 /* outlet: filled in the second pass below */
                 s->gn[IDX(s, i, x, y)] = v;
@@ -851,6 +869,8 @@ static void chan_adjoint_step(orc_chan* s, double* fb, double* gb, double* dflux
 int orc_chan_adjoint(orc_chan* s, long nsteps, int ckpt, int x_dev, double w_tout,
                      double w_nu, double* J, double* dJ_dflux, double* dJ_dtau) {
     if (nsteps < 0 || ckpt < 1) return -1;
+    /* the adjoint covers the heated channel only: inlet/outlet, no buoyancy */
+    if (s->p.bc_x != 1 || s->p.buoy[0] != 0.0 || s->p.buoy[1] != 0.0) return -2;
     int nx = s->p.nx, ny = s->p.ny;
     size_t N = (size_t)nx * ny;
     long nseg = (nsteps + ckpt - 1) / ckpt;

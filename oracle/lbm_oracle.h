@@ -38,7 +38,8 @@ void orc_mdim(double c, double* M_out, double* Minv_out);
 /* ---------------- single-phase channel: D2Q9 flow + optional D2Q5 thermal --- */
 typedef struct {
     int nx, ny;
-    int bc_x;          /* 0 periodic, 1 velocity inlet (x-) + pressure outlet (x+) */
+    int bc_x;          /* 0 periodic, 1 velocity inlet (x-) + pressure outlet (x+),
+                          2 no-slip walls at fixed temperatures Tw_x (App. D)      */
     int bc_y;          /* 0 periodic, 1 halfway walls at y- and y+                  */
     double dx, dt;
     /* flow */
@@ -51,6 +52,9 @@ typedef struct {
     int thermal_mrt;   /* 0 BGK, 1 two-rate (T, j at 1/tau_T; e, pxx at 1/dt) */
     double alpha, rho_cp, qdot, T_ref;       /* qdot in K/s */
     double flux_amp, flux_omega;              /* q''(x,t) = flux[x](1 + amp sin(omega t)) */
+    double Tw_x[2];    /* bc_x == 2: wall temperatures at x- and x+ (K)               */
+    double buoy[2];    /* Boussinesq force per kelvin of T - T_ref, -rho_ref beta g
+                          (Eq. buoyancy_force), N/m^3/K; 0 disables                  */
 } orc_chan_params;
 
 typedef struct orc_chan orc_chan;

@@ -57,11 +57,15 @@ lbm_status check_desc(const lbm_desc* d, Layout* L, std::string* err) {
         case LBM_D2Q9_D2Q5: {
             const bool xp = d->bc[0] == LBM_BC_PERIODIC && d->bc[1] == LBM_BC_PERIODIC;
             const bool xio = d->bc[0] == LBM_BC_VEL_INLET && d->bc[1] == LBM_BC_P_OUTLET;
+            const bool xd = d->bc[0] == LBM_BC_DIRICHLET && d->bc[1] == LBM_BC_DIRICHLET;
             const bool yp = d->bc[2] == LBM_BC_PERIODIC && d->bc[3] == LBM_BC_PERIODIC;
             const bool yw = d->bc[2] == LBM_BC_WALL && d->bc[3] == LBM_BC_WALL;
-            if (!(xp || xio) || !(yp || yw))
-                return fail(LBM_E_UNSUPPORTED, "D2Q9_D2Q5: x periodic or inlet/outlet, y periodic or walls");
+            if (!(xp || xio || xd) || !(yp || yw))
+                return fail(LBM_E_UNSUPPORTED,
+                            "D2Q9_D2Q5: x periodic, inlet/outlet or fixed-T walls; y periodic or walls");
             if (xio && d->nx < 2) return fail(LBM_E_ARG, "inlet/outlet needs nx >= 2");
+            if (xd && !(d->flags & LBM_FLAG_THERMAL))
+                return fail(LBM_E_ARG, "fixed-temperature walls need the thermal field");
             if ((d->flags & ~(LBM_FLAG_FLOW | LBM_FLAG_THERMAL)) != 0 || d->flags == 0)
                 return fail(LBM_E_ARG, "flags must be a non-empty subset of FLOW | THERMAL");
             l.npop = 9 + ((d->flags & LBM_FLAG_THERMAL) ? 5 : 0);
@@ -382,7 +386,7 @@ lbm_status lbm_set_params_SI(lbm_ctx* c, const lbm_params_si* p) {
     } else if (d.lattice == LBM_D2Q9_D2Q5) {
         const double cs2 = cc * cc / 3.0;
         ck.nx = d.nx; ck.ny = d.ny; ck.batch = d.batch; ck.P = c->P;
-        ck.bcx = d.bc[0] == LBM_BC_VEL_INLET ? 1 : 0;
+        ck.bcx = d.bc[0] == LBM_BC_VEL_INLET ? 1 : (d.bc[0] == LBM_BC_DIRICHLET ? 2 : 0);
         ck.bcy = d.bc[2] == LBM_BC_WALL ? 1 : 0;
         ck.flow = (d.flags & LBM_FLAG_FLOW) ? 1 : 0;
         ck.thermal = (d.flags & LBM_FLAG_THERMAL) ? 1 : 0;
@@ -423,6 +427,14 @@ lbm_status lbm_set_params_SI(lbm_ctx* c, const lbm_params_si* p) {
         }
         ck.c = cc;
         ck.T_ref = p->T_ref;
+        ck.Tw[0] = p->T_wall[0] - p->T_ref;
+        ck.Tw[1] = p->T_wall[1] - p->T_ref;
+        // Boussinesq force -rho_ref beta (T - T_ref) g (Eq. buoyancy_force), per kelvin
+        ck.buoy = p->beta_T != 0.0 && (p->gravity[0] != 0.0 || p->gravity[1] != 0.0);
+        if (ck.buoy && !ck.thermal)
+            return set_err(c, LBM_E_ARG, "the Boussinesq force needs the thermal field");
+        ck.Bt[0] = -p->rho_ref * p->beta_T * p->gravity[0] * dt * dt / dx;
+        ck.Bt[1] = -p->rho_ref * p->beta_T * p->gravity[1] * dt * dt / dx;
     } else {
         const double cs2 = cc * cc / 3.0;
         pk.nx = d.nx; pk.ny = d.ny; pk.batch = d.batch; pk.P = c->P;
@@ -706,7 +718,8 @@ lbm_status rec_layout(const lbm_ctx* c, int nsteps, int K, RecLayout* R, std::st
         if (err) *err = m;
         return st;
     };
-    if (d.lattice != LBM_D2Q9_D2Q5 || !c->ck.flow || !c->ck.thermal || !c->ck.bcx || !c->ck.bcy ||
+    if (d.lattice != LBM_D2Q9_D2Q5 || !c->ck.flow || !c->ck.thermal || c->ck.bcx != 1 || !c->ck.bcy ||
+        c->ck.buoy ||
         d.batch != 1)
         return fail(LBM_E_UNSUPPORTED,
                     "the adjoint needs the channel lattice with flow, thermal, inlet/outlet, walls, batch 1");

@@ -147,5 +147,28 @@ __device__ __forceinline__ void chan_flow_macros(const S* __restrict__ f, long l
     uy = (jy + C(0.5) * fty) * ir;
 }
 
+// T - T_ref of a node from its stored (deviation) D2Q5 populations, with the
+// half source (Eq. zero_moment_g)
+template <typename C, typename S>
+__device__ __forceinline__ C chan_theta(const S* __restrict__ g, long long P, long long n, C qdt) {
+    C e[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) e[i] = C(g[i * P + n]);
+    return (e[0] + (e[1] + e[3]) + (e[2] + e[4])) + C(0.5) * qdt;
+}
+
+// Lattice body force at a node whose temperature is T = T_ref + th: the
+// constant force plus, when on, the Boussinesq force -rho_ref beta th g of
+// Eq. buoyancy_force (App. D).
+template <typename C>
+__device__ __forceinline__ void chan_force(const ChanK& k, C th, C& fx, C& fy) {
+    fx = C(k.Ft[0]);
+    fy = C(k.Ft[1]);
+    if (k.buoy) {
+        fx += C(k.Bt[0]) * th;
+        fy += C(k.Bt[1]) * th;
+    }
+}
+
 }  // namespace
 }  // namespace lbm

@@ -20,7 +20,7 @@ namespace lbm {
 struct ChanK {
     int nx, ny, batch;
     long long P;          // plane stride (elements)
-    int bcx, bcy;         // 0 periodic; bcx 1 = inlet/outlet; bcy 1 = walls
+    int bcx, bcy;         // 0 periodic; bcx 1 inlet/outlet, 2 fixed-T walls; bcy 1 walls
     int flow, thermal, flow_mrt, thermal_mrt;
     double rho_ref;
     double Lf[9];         // flow rates * dt in the order rho,e,eps,jx,qx,jy,qy,pxx,pxy
@@ -29,6 +29,9 @@ struct ChanK {
     double qdt;           // qdot * dt (K)
     double c;             // lattice speed dx/dt (m/s), for outputs
     double T_ref;
+    double Tw[2];         // bcx 2: wall temperature - T_ref at x- and x+ (K)
+    int buoy;             // Boussinesq force on
+    double Bt[2];         // its lattice force per kelvin: -rho_ref beta g dt^2 / dx
 };
 
 struct PhaseK {

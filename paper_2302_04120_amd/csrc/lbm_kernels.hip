@@ -40,7 +40,18 @@ __global__ __launch_bounds__(256) void k_chan_step(ChanK k, const S* __restrict_
     const long long P = k.P;
     const long long base = (long long)b * ny * nx;
     const long long n = base + (long long)y * nx + x;
-    const C rho_ref = C(k.rho_ref), ftx = C(k.Ft[0]), fty = C(k.Ft[1]);
+    const C rho_ref = C(k.rho_ref);
+    const C qdt = C(k.qdt);
+
+    // temperature first: the Boussinesq force depends on it
+    C e[5], th = C(0);
+    if (k.thermal) {
+#pragma unroll
+        for (int i = 0; i < 5; ++i) e[i] = C(gc[i * P + n]);
+        th = (e[0] + (e[1] + e[3]) + (e[2] + e[4])) + C(0.5) * qdt;  // Eq. zero_moment_g
+    }
+    C ftx, fty;
+    chan_force(k, th, ftx, fty);
 
     C d[9], drho, rho, ux, uy;
     chan_flow_macros<C, S>(fc, P, n, rho_ref, ftx, fty, d, drho, rho, ux, uy);
@@ -85,11 +96,7 @@ __global__ __launch_bounds__(256) void k_chan_step(ChanK k, const S* __restrict_
     // ---- temperature collision (Sec. 2.2), advective part built on T - T_ref
     C es[5];
     if (k.thermal) {
-        C e[5], neq[5], m[5], dm[5], dv[5];
-#pragma unroll
-        for (int i = 0; i < 5; ++i) e[i] = C(gc[i * P + n]);
-        const C qdt = C(k.qdt);
-        const C th = (e[0] + (e[1] + e[3]) + (e[2] + e[4])) + C(0.5) * qdt;  // Eq. zero_moment_g
+        C neq[5], m[5], dm[5], dv[5];
 #pragma unroll
         for (int i = 0; i < 5; ++i)
             neq[i] = e[i] - wgt5<C>(i) * th * (C(1) + C(3) * (C(EX5[i]) * ux + C(EY5[i]) * uy));
@@ -108,10 +115,11 @@ __global__ __launch_bounds__(256) void k_chan_step(ChanK k, const S* __restrict_
 
     // ---- outlet wall velocity: 1.5 u(x_b) - 0.5 u(x_b - 1) at time t
     C uwx = C(0), uwy = C(0);
-    const bool outlet = k.bcx && x == nx - 1;
+    const bool outlet = k.bcx == 1 && x == nx - 1;
     if (k.flow && outlet) {
-        C d2[9], dr2, r2, ux2, uy2;
-        chan_flow_macros<C, S>(fc, P, n - 1, rho_ref, ftx, fty, d2, dr2, r2, ux2, uy2);
+        C d2[9], dr2, r2, ux2, uy2, fx2 = ftx, fy2 = fty;
+        if (k.buoy) chan_force(k, chan_theta<C, S>(gc, P, n - 1, qdt), fx2, fy2);
+        chan_flow_macros<C, S>(fc, P, n - 1, rho_ref, fx2, fy2, d2, dr2, r2, ux2, uy2);
         uwx = C(1.5) * ux - C(0.5) * ux2;
         uwy = C(1.5) * uy - C(0.5) * uy2;
     }
@@ -132,7 +140,7 @@ __global__ __launch_bounds__(256) void k_chan_step(ChanK k, const S* __restrict_
             fn[i * P + base + (long long)ty * nx + tx] = S(ds[i]);
         } else {
             C v;
-            if (outy) {
+            if (outy || k.bcx == 2) {
                 v = ds[i];  // halfway bounce-back, Eq. BB_vel with u_w = 0
             } else if (tx < 0) {
                 // moving-wall bounce-back with the inlet profile, Eq. BB_vel
@@ -160,6 +168,9 @@ __global__ __launch_bounds__(256) void k_chan_step(ChanK k, const S* __restrict_
             } else if (outy) {
                 // prescribed flux, Eq. BB_T with lambda = 1 on D2Q5
                 gn[OPP5[i] * P + n] = S(es[i] + C(qw[x]) * C(mod));
+            } else if (k.bcx == 2) {
+                // fixed-temperature side wall (App. D): Eq. anti_BB_T (deviation form)
+                gn[OPP5[i] * P + n] = S(-es[i] + C(2) * wgt5<C>(i) * C(k.Tw[tx < 0 ? 0 : 1]));
             } else if (tx < 0) {
                 // anti-bounce-back Dirichlet inlet, Eq. anti_BB_T (deviation form)
                 gn[OPP5[i] * P + n] = S(-es[i] + C(2) * wgt5<C>(i) * C(tin[y]));
@@ -838,18 +849,20 @@ __global__ void k_chan_macros(ChanK k, const S* __restrict__ f, const S* __restr
     const long long P = k.P;
     for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < N;
          n += (long long)gridDim.x * blockDim.x) {
-        double d[9], drho, rho, ux, uy;
-        chan_flow_macros<double, S>(f, P, n, k.rho_ref, k.Ft[0], k.Ft[1], d, drho, rho, ux, uy);
-        out[n] = rho;
-        out[2 * P + n] = ux * k.c;
-        out[3 * P + n] = uy * k.c;
-        double T = k.T_ref;
+        double th = 0.0;
         if (g) {
             double s = 0;
             for (int i = 0; i < 5; ++i) s += double(g[i * P + n]);
-            T = k.T_ref + s + 0.5 * k.qdt;
+            th = s + 0.5 * k.qdt;
         }
-        out[4 * P + n] = T;
+        double fx, fy;
+        chan_force(k, th, fx, fy);
+        double d[9], drho, rho, ux, uy;
+        chan_flow_macros<double, S>(f, P, n, k.rho_ref, fx, fy, d, drho, rho, ux, uy);
+        out[n] = rho;
+        out[2 * P + n] = ux * k.c;
+        out[3 * P + n] = uy * k.c;
+        out[4 * P + n] = k.T_ref + th;
     }
 }
 
@@ -952,11 +965,13 @@ __global__ void k_nusselt(ChanK k, const S* __restrict__ f, const S* __restrict_
     double su = 0, suT = 0, T0 = 0, T1 = 0;
     for (int y = 0; y < k.ny; ++y) {
         const long long n = (long long)y * k.nx + x;
-        double d[9], drho, rho, ux, uy;
-        chan_flow_macros<double, S>(f, P, n, k.rho_ref, k.Ft[0], k.Ft[1], d, drho, rho, ux, uy);
         double s = 0;
         for (int i = 0; i < 5; ++i) s += double(g[i * P + n]);
         const double T = k.T_ref + s + 0.5 * k.qdt;
+        double fx, fy;
+        chan_force(k, T - k.T_ref, fx, fy);
+        double d[9], drho, rho, ux, uy;
+        chan_flow_macros<double, S>(f, P, n, k.rho_ref, fx, fy, d, drho, rho, ux, uy);
         su += ux;
         suT += ux * T;
         if (y == 0) T0 = T;

@@ -67,7 +67,7 @@ class ParamsSI(C.Structure):
                 ("nu_g", C.c_double), ("zeta_l", C.c_double), ("zeta_g", C.c_double),
                 ("visc_mode", C.c_int), ("sigma", C.c_double), ("W", C.c_double),
                 ("mobility", C.c_double), ("z_collision", C.c_int), ("qy_printed", C.c_int),
-                ("normal_eps", C.c_double)]
+                ("normal_eps", C.c_double), ("beta_T", C.c_double), ("gravity", C.c_double * 2)]
 
 
 _lib = None
@@ -147,7 +147,11 @@ def make_params(prm, nx=None, ny=None):
             setattr(P, key, _ptr(arr))
     P.flux_amp = float(prm.get("flux_amp", 0.0))
     P.flux_omega = float(prm.get("flux_omega", 0.0))
-    P.T_wall[0], P.T_wall[1] = float(prm.get("T0", 0.0)), float(prm.get("TL", 0.0))
+    tw = prm.get("T_wall", (prm.get("T0", 0.0), prm.get("TL", 0.0)))
+    P.T_wall[0], P.T_wall[1] = float(tw[0]), float(tw[1])
+    P.beta_T = float(prm.get("beta_T", 0.0))
+    gv = prm.get("gravity", (0.0, 0.0))
+    P.gravity[0], P.gravity[1] = float(gv[0]), float(gv[1])
     for k in ("rho_l", "rho_g", "nu_l", "nu_g", "sigma", "W"):
         setattr(P, k, float(prm.get(k, 0.0)))
     P.zeta_l = float(prm.get("zeta_l", prm.get("nu_l", 0.0) * prm.get("rho_l", 0.0)))

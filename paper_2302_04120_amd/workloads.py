@@ -193,3 +193,42 @@ def layered(nx=4, ny=512, seed=0, dx=1.25e-6, dt=1.25e-8, W_nodes=20.0, M=1e-5,
                qy_printed=0, H=H, h=h, u_c=u_c, normal_eps=NORMAL_EPS_NODES / dx)
     zeros = np.zeros_like(phi)
     return prm, dict(phi=phi, p=zeros.copy(), ux=zeros.copy(), uy=zeros.copy()), offsets
+
+
+# --------------------------------------------------------------------------
+# Natural convection in a square enclosure (App. D)
+# --------------------------------------------------------------------------
+
+AIR_333K = dict(rho=1.059, cp=1008.045, k=0.029, alpha=2.702e-5, nu=1.90e-5, beta=3.004e-3)
+
+
+def cavity(Ra=1e4, dx=2e-4, dt=2e-4, n=None, g=9.81):
+    """Square air-filled cavity: left wall hot, right wall cold, top and
+    bottom insulated, fluid at rest at the cold temperature initially.
+    Ra = 1e4: L = 13 mm, T_h = 373.15 K, T_c = 293.85 K; Ra = 1e6: L = 60 mm,
+    T_h = 373.85 K, T_c = 293.15 K; properties at T_ref = 333.50 K.  (App. D
+    prints L = 0.60 m for Ra = 1e6, which with its properties and wall
+    temperatures gives Ra = 1.0e9; 0.060 m gives 1.0e6.)  ``n``
+    overrides the node count across (L = n dx) for smaller test cavities
+    with the same temperatures and properties."""
+    if Ra == 1e4:
+        L, Th, Tc = 0.0130, 373.15, 293.85
+    elif Ra == 1e6:
+        L, Th, Tc = 0.060, 373.85, 293.15
+    else:
+        raise ValueError("Ra must be 1e4 or 1e6")
+    if n is None:
+        n = int(round(L / dx))
+    L = n * dx
+    a = AIR_333K
+    T_ref = 333.50
+    prm = dict(dx=dx, dt=dt, rho_ref=a["rho"], nu=a["nu"], omega_e=1.0 / dt, omega_eps=1.0 / dt,
+               Fx=0.0, Fy=0.0, alpha=a["alpha"], rho_cp=a["rho"] * a["cp"], qdot=0.0,
+               T_ref=T_ref, flux=np.zeros(n), flux_amp=0.0, flux_omega=0.0,
+               inlet_u=np.zeros(n), inlet_T=np.full(n, T_ref), flow_mrt=0, thermal_mrt=1,
+               T_wall=(Th, Tc), beta_T=a["beta"], gravity=(0.0, -g),
+               L=L, Th=Th, Tc=Tc,
+               Ra=g * a["beta"] * L ** 3 * (Th - Tc) / (a["nu"] * a["alpha"]))
+    ini = dict(rho=np.full((n, n), a["rho"]), ux=np.zeros((n, n)), uy=np.zeros((n, n)),
+               T=np.full((n, n), Tc))
+    return prm, ini
