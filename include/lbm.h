@@ -70,20 +70,23 @@ enum {
     LBM_BC_WALL = 1,       /* halfway bounce-back (Eq. BB_vel, u_w = 0); thermal flux Eq. BB_T */
     LBM_BC_VEL_INLET = 2,  /* x- only: Eq. BB_vel with the inlet profile; thermal Eq. anti_BB_T */
     LBM_BC_P_OUTLET = 3,   /* x+ only: Eq. anti_BB_vel; thermal first-order extrapolation */
-    LBM_BC_DIRICHLET = 4   /* 1D ends: wet-node fixed temperature (Eq. BCs_1D_advection_diffusion);
+    LBM_BC_DIRICHLET = 4,  /* 1D ends: wet-node fixed temperature (Eq. BCs_1D_advection_diffusion);
                               D2Q9_D2Q5 x sides (both): no-slip halfway wall (Eq. BB_vel)
                               held at T_wall by Eq. anti_BB_T (App. D)                    */
+    LBM_BC_SYMMETRY = 5    /* D2Q9_D2Q5 y+ only, with LBM_BC_WALL at y-: symmetry plane of
+                              Eq. simetria (the lower half of a channel)                   */
 };
 enum { LBM_BGK = 0, LBM_MRT = 1 };
 /* desc.flags for LBM_D2Q9_D2Q5 */
-enum { LBM_FLAG_FLOW = 1, LBM_FLAG_THERMAL = 2 };
+enum { LBM_FLAG_FLOW = 1, LBM_FLAG_THERMAL = 2, LBM_FLAG_THERMAL_D2Q9 = 4 };
 
 typedef struct {
     int lattice;            /* LBM_D1Q2 | LBM_D1Q3 | LBM_D2Q9_D2Q5 | LBM_D2Q9_PHASE        */
     int nx, ny, batch;      /* grid per replica (1D: ny = 1) and number of replicas         */
     int prec;               /* LBM_FP32_DEV | LBM_FP64 (1D: LBM_FP64 only)                  */
     int bc[4];              /* x-, x+, y-, y+ ; see the enum above                           */
-    int flags;              /* LBM_D2Q9_D2Q5: LBM_FLAG_FLOW | LBM_FLAG_THERMAL               */
+    int flags;              /* LBM_D2Q9_D2Q5: LBM_FLAG_FLOW | LBM_FLAG_THERMAL, plus
+                               LBM_FLAG_THERMAL_D2Q9 for the D2Q9 thermal set (Sec. 3)     */
     void* hip_stream;       /* hipStream_t the library enqueues on (NULL = default stream)  */
     void* dev_buf;          /* caller-owned device memory of at least lbm_query_bytes()     */
     size_t dev_buf_bytes;
@@ -98,7 +101,8 @@ typedef struct {
     double omega_e, omega_eps; /* 1/s, free MRT rates of e and eps (0 -> 1/dt)              */
     double Fb[2];           /* N/m^3 body force                                             */
     /* temperature (Sec. 2.2) */
-    int thermal_collision;  /* LBM_BGK | LBM_MRT (two-rate: j at 1/tau_T, e and p_xx at 1/dt) */
+    int thermal_collision;  /* LBM_BGK | LBM_MRT: j at 1/tau_T, the rest at 1/dt (D2Q5 two-rate;
+                               D2Q9 Lambda_T,dim of Sec. 3)                                 */
     double T_ref;           /* K: deviation reference and datum of the advective equilibrium */
     double alpha;           /* m^2/s  -> tau_T = alpha / c_s^2 + dt/2                       */
     double rho_cp;          /* J/(m^3 K)                                                    */

@@ -122,11 +122,12 @@ def mdim(c):
 
 
 class Chan:
-    """D2Q9 flow (BGK/MRT) + optional D2Q5 thermal on an nx x ny grid.
+    """D2Q9 flow (BGK/MRT) + optional thermal field on an nx x ny grid.
 
     ``bc_x``: 'periodic', 'inlet_outlet' or 'walls_T' (no-slip walls held at
-    prm['T_wall'] = (T at x-, T at x+), App. D); ``bc_y``: 'periodic' or
-    'walls'.  prm['beta_T'] (1/K) with prm['gravity'] (m/s^2) adds the
+    prm['T_wall'] = (T at x-, T at x+), App. D); ``bc_y``: 'periodic',
+    'walls' or 'wall_symmetry' (wall at y-, symmetry plane at y+: the lower
+    half of a channel).  ``thermal``: False, True or 'd2q5' (D2Q5), 'd2q9'.  prm['beta_T'] (1/K) with prm['gravity'] (m/s^2) adds the
     Boussinesq force -rho_ref beta (T - T_ref) g of Eq. buoyancy_force.
     """
 
@@ -136,7 +137,7 @@ class Chan:
         P = ChanParams()
         P.nx, P.ny = nx, ny
         P.bc_x = {"periodic": 0, "inlet_outlet": 1, "walls_T": 2}[bc_x]
-        P.bc_y = {"periodic": 0, "walls": 1}[bc_y]
+        P.bc_y = {"periodic": 0, "walls": 1, "wall_symmetry": 2}[bc_y]
         P.dx, P.dt = prm["dx"], prm["dt"]
         P.flow = 1 if flow else 0
         P.flow_mrt = int(prm.get("flow_mrt", 1))
@@ -145,7 +146,8 @@ class Chan:
         P.omega_e = prm.get("omega_e", 1.0 / prm["dt"])
         P.omega_eps = prm.get("omega_eps", 1.0 / prm["dt"])
         P.Fx, P.Fy = prm.get("Fx", 0.0), prm.get("Fy", 0.0)
-        P.thermal = 1 if thermal else 0
+        P.thermal = {False: 0, True: 1, "d2q5": 1, "d2q9": 2}[thermal]
+        self.qT = 9 if P.thermal == 2 else 5
         P.thermal_mrt = int(prm.get("thermal_mrt", 1))
         P.alpha = prm.get("alpha", 1e-7)
         P.rho_cp = prm.get("rho_cp", 1.0)
@@ -192,7 +194,7 @@ class Chan:
 
     def get_state(self):
         f = np.zeros((9, self.ny, self.nx))
-        g = np.zeros((5, self.ny, self.nx))
+        g = np.zeros((self.qT, self.ny, self.nx))
         lib().orc_chan_get_state(self.h, _ptr(f), _ptr(g))
         return f, g
 

@@ -32,6 +32,9 @@ static const int EX5[5] = {0, 1, 0, -1, 0};
 static const int EY5[5] = {0, 0, 1, 0, -1};
 static const double W5[5] = {1.0 / 3, 1.0 / 6, 1.0 / 6, 1.0 / 6, 1.0 / 6};
 static const int OPP5[5] = {0, 3, 4, 1, 2};
+/* mirror images in y (same c_x, opposite c_y), for the symmetry plane */
+static const int MIRY9[9] = {0, 1, 4, 3, 2, 8, 7, 6, 5};
+static const int MIRY5[5] = {0, 1, 4, 3, 2};
 
 /* Lattice-unit transformation matrix, rows rho, e, eps, J_x, q_x, J_y, q_y,
  * p_xx, p_xy (Eq. M_matrix). */
@@ -160,6 +163,11 @@ static double geq5(int i, double T, double Tref, double ux, double uy, double c,
     double cu = c * (EX5[i] * ux + EY5[i] * uy);
     return W5[i] * (T + (T - Tref) * cu / cs2);
 }
+/* the same equilibrium on D2Q9 (the thermal set of Sec. 3 and App. D) */
+static double geq9t(int i, double T, double Tref, double ux, double uy, double c, double cs2) {
+    double cu = c * (EX9[i] * ux + EY9[i] * uy);
+    return W9[i] * (T + (T - Tref) * cu / cs2);
+}
 
 /* ------------------------------------------------------------------------- */
 /* 1D thermal LBM                                                             */
@@ -243,8 +251,12 @@ struct orc_chan {
     double Md[81], Mi[81], lam[9];   /* flow: dimensional M, inverse, rates (1/s) */
     double A[81], B[81];             /* f* = f - A(f - feq) + B Fhat */
     double dA[81], dB[81];           /* derivatives of A, B with respect to tau */
-    double M5d[25], M5i[25], lam5[5];
-    double AT[25], BT[25], dAT[25], dBT[25];
+    /* thermal lattice: D2Q5 (thermal == 1) or D2Q9 (thermal == 2) */
+    int qT;
+    const int *EXT, *EYT, *OPPT, *MIRT;
+    const double* WT;
+    double MTd[81], MTi[81], lamT[9];
+    double AT[81], BT[81], dAT[81], dBT[81];
     double *f, *g, *fs, *gs, *fn, *gn;
     double *rho, *ux, *uy, *T;
     double *flux, *inlet_u, *inlet_T;
@@ -294,28 +306,30 @@ static void chan_rates(orc_chan* s) {
             s->dB[k * 9 + k] = dt * dt / (2.0 * s->tau * s->tau);
         }
     }
-    /* thermal: two-rate reading, Lambda_T = diag(0, 1/tau_T, 1/tau_T, 1/dt, 1/dt)
-     * (D2Q5 analogue of the dimensional thermal operator of Sec. 3); BGK = all
-     * rates 1/tau_T. */
+    /* thermal MRT.  D2Q9 (Sec. 3): Lambda_T,dim = diag(0, 1/dt, 1/dt, w_T, 1/dt,
+     * w_T, 1/dt, 1/dt, 1/dt) in the basis of Eq. M_matrix_dim.  D2Q5 (reading):
+     * the two-rate analogue diag(0, w_T, w_T, 1/dt, 1/dt) in the basis T, j_x,
+     * j_y, e, p_xx.  BGK: every rate w_T = 1/tau_T. */
     double wT = 1.0 / s->tauT, dwT = -1.0 / (s->tauT * s->tauT);
-    double l5[5], dl5[5];
-    for (int k = 0; k < 5; ++k) {
-        int jk = (k == 1 || k == 2);
-        l5[k] = (p->thermal_mrt && !jk) ? (k == 0 ? 0.0 : 1.0 / dt) : wT;
-        dl5[k] = (p->thermal_mrt && !jk) ? 0.0 : dwT;
+    int q = s->qT;
+    double lT[9], dlT[9];
+    for (int k = 0; k < q; ++k) {
+        int jk = (q == 9) ? (k == 3 || k == 5) : (k == 1 || k == 2);
+        lT[k] = (p->thermal_mrt && !jk) ? (k == 0 ? 0.0 : 1.0 / dt) : wT;
+        dlT[k] = (p->thermal_mrt && !jk) ? 0.0 : dwT;
     }
-    memcpy(s->lam5, l5, sizeof l5);
-    double e1[5], e2[5], e3[5], e4[5];
-    for (int k = 0; k < 5; ++k) {
-        e1[k] = dt * l5[k];
-        e2[k] = dt * (1.0 - 0.5 * dt * l5[k]);
-        e3[k] = dt * dl5[k];
-        e4[k] = -0.5 * dt * dt * dl5[k];
+    memcpy(s->lamT, lT, sizeof(double) * q);
+    double e1[9], e2[9], e3[9], e4[9];
+    for (int k = 0; k < q; ++k) {
+        e1[k] = dt * lT[k];
+        e2[k] = dt * (1.0 - 0.5 * dt * lT[k]);
+        e3[k] = dt * dlT[k];
+        e4[k] = -0.5 * dt * dt * dlT[k];
     }
-    sandwich(5, s->M5i, e1, s->M5d, s->AT);
-    sandwich(5, s->M5i, e2, s->M5d, s->BT);
-    sandwich(5, s->M5i, e3, s->M5d, s->dAT);
-    sandwich(5, s->M5i, e4, s->M5d, s->dBT);
+    sandwich(q, s->MTi, e1, s->MTd, s->AT);
+    sandwich(q, s->MTi, e2, s->MTd, s->BT);
+    sandwich(q, s->MTi, e3, s->MTd, s->dAT);
+    sandwich(q, s->MTi, e4, s->MTd, s->dBT);
 }
 
 orc_chan* orc_chan_create(const orc_chan_params* p, const double* flux, const double* inlet_u,
@@ -327,14 +341,20 @@ orc_chan* orc_chan_create(const orc_chan_params* p, const double* flux, const do
     s->c = p->dx / p->dt;               /* lattice speed (Sec. 2.1) */
     s->cs2 = s->c * s->c / 3.0;         /* c_s = c / sqrt(3) */
     build_mdim(9, &MLAT9[0][0], ORD9, s->c, s->Md, s->Mi);
-    build_mdim(5, &MLAT5[0][0], ORD5, s->c, s->M5d, s->M5i);
+    if (p->thermal == 2) {
+        s->qT = 9; s->EXT = EX9; s->EYT = EY9; s->OPPT = OPP9; s->MIRT = MIRY9; s->WT = W9;
+        build_mdim(9, &MLAT9[0][0], ORD9, s->c, s->MTd, s->MTi);
+    } else {
+        s->qT = 5; s->EXT = EX5; s->EYT = EY5; s->OPPT = OPP5; s->MIRT = MIRY5; s->WT = W5;
+        build_mdim(5, &MLAT5[0][0], ORD5, s->c, s->MTd, s->MTi);
+    }
     chan_rates(s);
     s->f = (double*)calloc(9 * N, sizeof(double));
     s->fs = (double*)calloc(9 * N, sizeof(double));
     s->fn = (double*)calloc(9 * N, sizeof(double));
-    s->g = (double*)calloc(5 * N, sizeof(double));
-    s->gs = (double*)calloc(5 * N, sizeof(double));
-    s->gn = (double*)calloc(5 * N, sizeof(double));
+    s->g = (double*)calloc(s->qT * N, sizeof(double));
+    s->gs = (double*)calloc(s->qT * N, sizeof(double));
+    s->gn = (double*)calloc(s->qT * N, sizeof(double));
     s->rho = (double*)calloc(N, sizeof(double));
     s->ux = (double*)calloc(N, sizeof(double));
     s->uy = (double*)calloc(N, sizeof(double));
@@ -367,6 +387,12 @@ void orc_chan_set_tau(orc_chan* s, double nu, double alpha) {
     chan_rates(s);
 }
 
+/* thermal equilibrium on the lattice of this channel */
+static double chan_geq(const orc_chan* s, int i, double T, double ux, double uy) {
+    return s->qT == 9 ? geq9t(i, T, s->p.T_ref, ux, uy, s->c, s->cs2)
+                      : geq5(i, T, s->p.T_ref, ux, uy, s->c, s->cs2);
+}
+
 void orc_chan_init(orc_chan* s, const double* rho, const double* ux, const double* uy,
                    const double* T) {
     int nx = s->p.nx, ny = s->p.ny;
@@ -375,9 +401,8 @@ void orc_chan_init(orc_chan* s, const double* rho, const double* ux, const doubl
             size_t n = (size_t)y * nx + x;
             for (int i = 0; i < 9; ++i)
                 s->f[IDX(s, i, x, y)] = feq9(i, rho[n], ux[n], uy[n], s->c, s->cs2);
-            for (int i = 0; i < 5; ++i)
-                s->g[IDX(s, i, x, y)] =
-                    geq5(i, T ? T[n] : s->p.T_ref, s->p.T_ref, ux[n], uy[n], s->c, s->cs2);
+            for (int i = 0; i < s->qT; ++i)
+                s->g[IDX(s, i, x, y)] = chan_geq(s, i, T ? T[n] : s->p.T_ref, ux[n], uy[n]);
         }
     s->t = 0;
 }
@@ -404,7 +429,7 @@ static void chan_node_macros(const orc_chan* s, int x, int y, double* rho, doubl
         jx += s->c * EX9[i] * fi;
         jy += s->c * EY9[i] * fi;
     }
-    for (int i = 0; i < 5; ++i) t += s->g[IDX(s, i, x, y)];
+    for (int i = 0; i < s->qT; ++i) t += s->g[IDX(s, i, x, y)];
     *rho = r;
     *T = t + 0.5 * p->dt * p->qdot;
     double Fx, Fy;
@@ -471,25 +496,26 @@ static void chan_collide_node(orc_chan* s, int x, int y) {
         for (int i = 0; i < 9; ++i) s->fs[IDX(s, i, x, y)] = s->f[IDX(s, i, x, y)];
     }
     if (p->thermal) {
-        double g[5], ge[5], Sg[5], m[5], me[5], Sm[5], ms[5], out[5];
-        for (int i = 0; i < 5; ++i) {
+        int q = s->qT;
+        double g[9], ge[9], Sg[9], m[9], me[9], Sm[9], ms[9], out[9];
+        for (int i = 0; i < q; ++i) {
             g[i] = s->g[IDX(s, i, x, y)];
-            ge[i] = geq5(i, T, p->T_ref, ux, uy, s->c, s->cs2);
-            Sg[i] = W5[i] * p->qdot; /* Eq. forcing_term_g without its prefactor */
+            ge[i] = chan_geq(s, i, T, ux, uy);
+            Sg[i] = s->WT[i] * p->qdot; /* Eq. forcing_term_g without its prefactor */
         }
-        matvec(5, s->M5d, g, m);
-        matvec(5, s->M5d, ge, me);
-        matvec(5, s->M5d, Sg, Sm);
-        for (int k = 0; k < 5; ++k)
-            ms[k] = m[k] - p->dt * s->lam5[k] * (m[k] - me[k]) +
-                    p->dt * (1.0 - 0.5 * p->dt * s->lam5[k]) * Sm[k];
-        matvec(5, s->M5i, ms, out);
-        for (int i = 0; i < 5; ++i) s->gs[IDX(s, i, x, y)] = out[i];
+        matvec(q, s->MTd, g, m);
+        matvec(q, s->MTd, ge, me);
+        matvec(q, s->MTd, Sg, Sm);
+        for (int k = 0; k < q; ++k)
+            ms[k] = m[k] - p->dt * s->lamT[k] * (m[k] - me[k]) +
+                    p->dt * (1.0 - 0.5 * p->dt * s->lamT[k]) * Sm[k];
+        matvec(q, s->MTi, ms, out);
+        for (int i = 0; i < q; ++i) s->gs[IDX(s, i, x, y)] = out[i];
     }
 }
 
 /* classification of the source node x - e_i of a population i arriving at (x, y) */
-enum { SRC_IN = 0, SRC_WALL = 1, SRC_INLET = 2, SRC_OUTLET = 3, SRC_XWALL = 4 };
+enum { SRC_IN = 0, SRC_WALL = 1, SRC_INLET = 2, SRC_OUTLET = 3, SRC_XWALL = 4, SRC_SYM = 5 };
 static int chan_src(const orc_chan* s, int x, int y, int ex, int ey, int* xs, int* ys) {
     int nx = s->p.nx, ny = s->p.ny;
     int sx = x - ex, sy = y - ey;
@@ -499,6 +525,14 @@ static int chan_src(const orc_chan* s, int x, int y, int ex, int ey, int* xs, in
     if (s->p.bc_x == 0) sx = (sx + nx) % nx;
     else outx = (sx < 0 || sx >= nx);
     *xs = sx; *ys = sy;
+    /* symmetry plane at y+ (Eq. simetria): the population arriving from above
+     * is the mirror image of the one that left the node x_b = (x - c_x, ny - 1)
+     * there; when x_b lies outside in x, the x-boundary rule applies */
+    if (outy && s->p.bc_y == 2 && sy >= ny) {
+        *ys = ny - 1;
+        if (!outx) return SRC_SYM;
+        outy = 0;
+    }
     /* tie-break at corners (the paper is silent): a link whose source lies
      * outside in y takes the wall rule, otherwise the x-boundary rule */
     if (outy) return SRC_WALL;
@@ -528,6 +562,7 @@ static void chan_stream(orc_chan* s) {
                 int kind = chan_src(s, x, y, EX9[i], EY9[i], &xs, &ys);
                 double v;
                 if (kind == SRC_IN) v = s->fs[IDX(s, i, xs, ys)];
+                else if (kind == SRC_SYM) v = s->fs[IDX(s, MIRY9[i], xs, ys)];
                 else if (kind == SRC_WALL || kind == SRC_XWALL)
                     v = s->fs[IDX(s, o, x, y)]; /* Eq. BB_vel, u_w = 0 */
                 else if (kind == SRC_INLET) {
@@ -546,25 +581,32 @@ static void chan_stream(orc_chan* s) {
                 s->fn[IDX(s, i, x, y)] = p->flow ? v : s->f[IDX(s, i, x, y)];
             }
             if (!p->thermal) continue;
-            for (int i = 0; i < 5; ++i) {
-                int xs, ys, o = OPP5[i];
-                int kind = chan_src(s, x, y, EX5[i], EY5[i], &xs, &ys);
+            for (int i = 0; i < s->qT; ++i) {
+                int xs, ys, o = s->OPPT[i];
+                int kind = chan_src(s, x, y, s->EXT[i], s->EYT[i], &xs, &ys);
                 double v = 0.0;
                 if (kind == SRC_IN) v = s->gs[IDX(s, i, xs, ys)];
+                else if (kind == SRC_SYM) v = s->gs[IDX(s, s->MIRT[i], xs, ys)];
                 else if (kind == SRC_WALL) {
                     /* prescribed heat flux, Eq. BB_T.  Dimensional reading of the
                      * constant: lambda_i = 2 w_i c^2 / c_s^2 = 6 w_i (1 for D2Q5), so
                      * the incoming links of a wall node carry exactly q'' dt dx. */
-                    double lam = 6.0 * W5[o];
+                    double lam = 6.0 * s->WT[o];
                     v = s->gs[IDX(s, o, x, y)] +
                         lam * (p->dt / p->dx) * (s->flux[x] * mod / p->rho_cp);
                 } else if (kind == SRC_INLET) {
                     /* anti-bounce-back Dirichlet, Eq. anti_BB_T; reading: only the
-                     * even part of the linear equilibrium actually used, 2 w T_w */
-                    v = -s->gs[IDX(s, o, x, y)] + 2.0 * W5[o] * s->inlet_T[y];
+                     * even part of the linear equilibrium actually used, 2 w T_w.
+                     * T_w is the inlet temperature where the link crosses the
+                     * inlet, halfway between the rows y and y - c_y (D2Q9
+                     * diagonals; the same row otherwise) */
+                    int y2 = y - s->EYT[i];
+                    double Tw = (y2 >= 0 && y2 < ny) ? 0.5 * (s->inlet_T[y] + s->inlet_T[y2])
+                                                     : s->inlet_T[y];
+                    v = -s->gs[IDX(s, o, x, y)] + 2.0 * s->WT[o] * Tw;
                 } else if (kind == SRC_XWALL) {
                     /* fixed-temperature side wall (App. D), the same Eq. anti_BB_T */
-                    v = -s->gs[IDX(s, o, x, y)] + 2.0 * W5[o] * p->Tw_x[xs < 0 ? 0 : 1];
+                    v = -s->gs[IDX(s, o, x, y)] + 2.0 * s->WT[o] * p->Tw_x[xs < 0 ? 0 : 1];
                 }
                 /* outlet: filled in the second pass below */
                 s->gn[IDX(s, i, x, y)] = v;
@@ -574,9 +616,9 @@ static void chan_stream(orc_chan* s) {
         /* first-order extrapolation outlet: g_i(x_b) = g_i(x_b - 1), both at t+dt */
         int x = nx - 1;
         for (int y = 0; y < ny; ++y)
-            for (int i = 0; i < 5; ++i) {
+            for (int i = 0; i < s->qT; ++i) {
                 int xs, ys;
-                if (chan_src(s, x, y, EX5[i], EY5[i], &xs, &ys) == SRC_OUTLET)
+                if (chan_src(s, x, y, s->EXT[i], s->EYT[i], &xs, &ys) == SRC_OUTLET)
                     s->gn[IDX(s, i, x, y)] = s->gn[IDX(s, i, x - 1, y)];
             }
     }
@@ -601,13 +643,13 @@ void orc_chan_step(orc_chan* s, long nsteps) {
 void orc_chan_get_state(const orc_chan* s, double* f, double* g) {
     size_t N = (size_t)s->p.nx * s->p.ny;
     if (f) memcpy(f, s->f, sizeof(double) * 9 * N);
-    if (g) memcpy(g, s->g, sizeof(double) * 5 * N);
+    if (g) memcpy(g, s->g, sizeof(double) * s->qT * N);
 }
 
 void orc_chan_set_state(orc_chan* s, const double* f, const double* g, long t) {
     size_t N = (size_t)s->p.nx * s->p.ny;
     if (f) memcpy(s->f, f, sizeof(double) * 9 * N);
-    if (g) memcpy(s->g, g, sizeof(double) * 5 * N);
+    if (g) memcpy(s->g, g, sizeof(double) * s->qT * N);
     s->t = t;
 }
 
@@ -623,7 +665,9 @@ void orc_chan_nusselt(const orc_chan* s, double* Tb, double* Tw, double* Nu) {
     double* ux = (double*)malloc(sizeof(double) * N);
     double* T = (double*)malloc(sizeof(double) * N);
     orc_chan_macros(s, NULL, ux, NULL, T);
-    double k = p->rho_cp * p->alpha, Dh = 2.0 * ny * p->dx;
+    /* with a symmetry plane the grid is the lower half of a channel twice as high */
+    int half = p->bc_y == 2;
+    double k = p->rho_cp * p->alpha, Dh = 2.0 * ny * p->dx * (half ? 2.0 : 1.0);
     double mod = chan_flux_mod(s, s->t);
     for (int x = 0; x < nx; ++x) {
         double su = 0, suT = 0;
@@ -633,7 +677,8 @@ void orc_chan_nusselt(const orc_chan* s, double* Tb, double* Tw, double* Nu) {
         }
         double q = s->flux[x] * mod;
         double tb = suT / su;
-        double tw = 0.5 * (T[x] + T[(size_t)(ny - 1) * nx + x]) + q * p->dx / (2.0 * k);
+        double tw = (half ? T[x] : 0.5 * (T[x] + T[(size_t)(ny - 1) * nx + x])) +
+                    q * p->dx / (2.0 * k);
         if (Tb) Tb[x] = tb;
         if (Tw) Tw[x] = tw;
         if (Nu) Nu[x] = q * Dh / (k * (tw - tb));
@@ -869,8 +914,11 @@ static void chan_adjoint_step(orc_chan* s, double* fb, double* gb, double* dflux
 int orc_chan_adjoint(orc_chan* s, long nsteps, int ckpt, int x_dev, double w_tout,
                      double w_nu, double* J, double* dJ_dflux, double* dJ_dtau) {
     if (nsteps < 0 || ckpt < 1) return -1;
-    /* the adjoint covers the heated channel only: inlet/outlet, no buoyancy */
-    if (s->p.bc_x != 1 || s->p.buoy[0] != 0.0 || s->p.buoy[1] != 0.0) return -2;
+    /* the adjoint covers the heated channel only: inlet/outlet, both walls
+     * heated, D2Q5 thermal, no buoyancy */
+    if (s->p.bc_x != 1 || s->p.bc_y != 1 || s->qT != 5 || s->p.buoy[0] != 0.0 ||
+        s->p.buoy[1] != 0.0)
+        return -2;
     int nx = s->p.nx, ny = s->p.ny;
     size_t N = (size_t)nx * ny;
     long nseg = (nsteps + ckpt - 1) / ckpt;

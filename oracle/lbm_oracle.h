@@ -40,7 +40,8 @@ typedef struct {
     int nx, ny;
     int bc_x;          /* 0 periodic, 1 velocity inlet (x-) + pressure outlet (x+),
                           2 no-slip walls at fixed temperatures Tw_x (App. D)      */
-    int bc_y;          /* 0 periodic, 1 halfway walls at y- and y+                  */
+    int bc_y;          /* 0 periodic, 1 halfway walls at y- and y+, 2 halfway wall at
+                          y- and a symmetry plane at y+ (Eq. simetria)               */
     double dx, dt;
     /* flow */
     int flow;          /* 0 frozen (populations not updated), 1 D2Q9 */
@@ -48,8 +49,10 @@ typedef struct {
     double rho_ref, nu, omega_e, omega_eps;  /* omega_* in 1/s */
     double Fx, Fy;     /* body force, N/m^3 */
     /* thermal */
-    int thermal;       /* 0 none, 1 D2Q5 */
-    int thermal_mrt;   /* 0 BGK, 1 two-rate (T, j at 1/tau_T; e, pxx at 1/dt) */
+    int thermal;       /* 0 none, 1 D2Q5, 2 D2Q9 */
+    int thermal_mrt;   /* 0 BGK; 1 MRT: D2Q5 two-rate (j at 1/tau_T, e and pxx at
+                          1/dt), D2Q9 Lambda_T,dim of Sec. 3 (j at 1/tau_T, the
+                          rest at 1/dt)                                           */
     double alpha, rho_cp, qdot, T_ref;       /* qdot in K/s */
     double flux_amp, flux_omega;              /* q''(x,t) = flux[x](1 + amp sin(omega t)) */
     double Tw_x[2];    /* bc_x == 2: wall temperatures at x- and x+ (K)               */
@@ -68,7 +71,7 @@ void orc_chan_step(orc_chan* s, long nsteps);
 /* macros of the current (pre-collision) state; any pointer may be NULL */
 void orc_chan_macros(const orc_chan* s, double* rho, double* ux, double* uy, double* T);
 long orc_chan_time(const orc_chan* s);
-/* raw state: f[9][ny][nx] then g[5][ny][nx]; plus the time index */
+/* raw state: f[9][ny][nx] then g[5 or 9][ny][nx]; plus the time index */
 void orc_chan_get_state(const orc_chan* s, double* f, double* g);
 void orc_chan_set_state(orc_chan* s, const double* f, const double* g, long t);
 /* replace the wall flux profile / inlet temperature (W/m^2 per column) */

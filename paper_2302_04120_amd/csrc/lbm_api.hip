@@ -38,7 +38,7 @@ lbm_status check_desc(const lbm_desc* d, Layout* L, std::string* err) {
     if (d->prec != LBM_FP32_DEV && d->prec != LBM_FP64) return fail(LBM_E_ARG, "unknown precision");
     if (d->batch > 65535 || d->ny > 65535 * 4) return fail(LBM_E_ARG, "grid too large for the launch geometry");
     for (int s = 0; s < 4; ++s)
-        if (d->bc[s] < LBM_BC_PERIODIC || d->bc[s] > LBM_BC_DIRICHLET) return fail(LBM_E_ARG, "unknown boundary kind");
+        if (d->bc[s] < LBM_BC_PERIODIC || d->bc[s] > LBM_BC_SYMMETRY) return fail(LBM_E_ARG, "unknown boundary kind");
     Layout l;
     l.N = (long long)d->batch * d->nx * d->ny;
     l.P = (l.N + 63) / 64 * 64;
@@ -60,15 +60,20 @@ lbm_status check_desc(const lbm_desc* d, Layout* L, std::string* err) {
             const bool xd = d->bc[0] == LBM_BC_DIRICHLET && d->bc[1] == LBM_BC_DIRICHLET;
             const bool yp = d->bc[2] == LBM_BC_PERIODIC && d->bc[3] == LBM_BC_PERIODIC;
             const bool yw = d->bc[2] == LBM_BC_WALL && d->bc[3] == LBM_BC_WALL;
-            if (!(xp || xio || xd) || !(yp || yw))
+            const bool ys = d->bc[2] == LBM_BC_WALL && d->bc[3] == LBM_BC_SYMMETRY;
+            if (!(xp || xio || xd) || !(yp || yw || ys))
                 return fail(LBM_E_UNSUPPORTED,
-                            "D2Q9_D2Q5: x periodic, inlet/outlet or fixed-T walls; y periodic or walls");
+                            "D2Q9_D2Q5: x periodic, inlet/outlet or fixed-T walls; y periodic, walls, "
+                            "or wall + symmetry plane");
             if (xio && d->nx < 2) return fail(LBM_E_ARG, "inlet/outlet needs nx >= 2");
             if (xd && !(d->flags & LBM_FLAG_THERMAL))
                 return fail(LBM_E_ARG, "fixed-temperature walls need the thermal field");
-            if ((d->flags & ~(LBM_FLAG_FLOW | LBM_FLAG_THERMAL)) != 0 || d->flags == 0)
-                return fail(LBM_E_ARG, "flags must be a non-empty subset of FLOW | THERMAL");
-            l.npop = 9 + ((d->flags & LBM_FLAG_THERMAL) ? 5 : 0);
+            if ((d->flags & ~(LBM_FLAG_FLOW | LBM_FLAG_THERMAL | LBM_FLAG_THERMAL_D2Q9)) != 0 ||
+                (d->flags & (LBM_FLAG_FLOW | LBM_FLAG_THERMAL)) == 0)
+                return fail(LBM_E_ARG, "flags must be a non-empty subset of FLOW | THERMAL (| THERMAL_D2Q9)");
+            if ((d->flags & LBM_FLAG_THERMAL_D2Q9) && !(d->flags & LBM_FLAG_THERMAL))
+                return fail(LBM_E_ARG, "THERMAL_D2Q9 needs THERMAL");
+            l.npop = 9 + ((d->flags & LBM_FLAG_THERMAL) ? ((d->flags & LBM_FLAG_THERMAL_D2Q9) ? 9 : 5) : 0);
             break;
         }
         case LBM_D2Q9_PHASE: {
@@ -387,9 +392,10 @@ lbm_status lbm_set_params_SI(lbm_ctx* c, const lbm_params_si* p) {
         const double cs2 = cc * cc / 3.0;
         ck.nx = d.nx; ck.ny = d.ny; ck.batch = d.batch; ck.P = c->P;
         ck.bcx = d.bc[0] == LBM_BC_VEL_INLET ? 1 : (d.bc[0] == LBM_BC_DIRICHLET ? 2 : 0);
-        ck.bcy = d.bc[2] == LBM_BC_WALL ? 1 : 0;
+        ck.bcy = d.bc[2] == LBM_BC_WALL ? (d.bc[3] == LBM_BC_SYMMETRY ? 2 : 1) : 0;
         ck.flow = (d.flags & LBM_FLAG_FLOW) ? 1 : 0;
         ck.thermal = (d.flags & LBM_FLAG_THERMAL) ? 1 : 0;
+        ck.tq = (d.flags & LBM_FLAG_THERMAL_D2Q9) ? 9 : 5;
         ck.flow_mrt = p->flow_collision == LBM_MRT;
         ck.thermal_mrt = p->thermal_collision == LBM_MRT;
         if (!(p->rho_ref > 0)) return set_err(c, LBM_E_ARG, "rho_ref must be positive");
@@ -417,10 +423,12 @@ lbm_status lbm_set_params_SI(lbm_ctx* c, const lbm_params_si* p) {
             if (!(p->rho_cp > 0)) return set_err(c, LBM_E_ARG, "rho_cp must be positive");
             const double tauT = p->alpha / cs2 + 0.5 * dt;
             const double wT = dt / tauT, dwT = -dt / (tauT * tauT);
-            for (int q = 0; q < 5; ++q) {
-                const bool j = (q == 1 || q == 2);
+            // MRT: the fluxes j relax at dt/tau_T, the conserved T not at all, the
+            // rest at 1 (Lambda_T,dim of Sec. 3 on D2Q9; its two-rate analogue on D2Q5)
+            for (int q = 0; q < ck.tq; ++q) {
+                const bool j = ck.tq == 9 ? (q == 3 || q == 5) : (q == 1 || q == 2);
                 ck.Lt[q] = ck.thermal_mrt ? (j ? wT : (q == 0 ? 0.0 : 1.0)) : wT;
-                ak.dLt[q] = (ck.thermal_mrt && !j) ? 0.0 : dwT;
+                if (q < 5) ak.dLt[q] = (ck.thermal_mrt && !j) ? 0.0 : dwT;
             }
             ak.qgrad = dt / (dx * p->rho_cp);
             ck.qdt = p->qvol / p->rho_cp * dt;
@@ -483,7 +491,8 @@ lbm_status lbm_set_params_SI(lbm_ctx* c, const lbm_params_si* p) {
     c->dx = dx;
     c->rho_cp = p->rho_cp;
     c->k_cond = p->rho_cp * p->alpha;
-    c->Dh = 2.0 * d.ny * dx;
+    // hydraulic diameter 2H; with a symmetry plane the grid is half of H
+    c->Dh = 2.0 * d.ny * dx * (d.lattice == LBM_D2Q9_D2Q5 && d.bc[3] == LBM_BC_SYMMETRY ? 2.0 : 1.0);
     uint64_t h = 1469598103934665603ull;
     h = fnv(h, &d.lattice, sizeof(int) * 5);
     h = fnv(h, d.bc, sizeof d.bc);
@@ -718,11 +727,12 @@ lbm_status rec_layout(const lbm_ctx* c, int nsteps, int K, RecLayout* R, std::st
         if (err) *err = m;
         return st;
     };
-    if (d.lattice != LBM_D2Q9_D2Q5 || !c->ck.flow || !c->ck.thermal || c->ck.bcx != 1 || !c->ck.bcy ||
-        c->ck.buoy ||
+    if (d.lattice != LBM_D2Q9_D2Q5 || !c->ck.flow || !c->ck.thermal || c->ck.bcx != 1 ||
+        c->ck.bcy != 1 || c->ck.buoy || c->ck.tq != 5 ||
         d.batch != 1)
         return fail(LBM_E_UNSUPPORTED,
-                    "the adjoint needs the channel lattice with flow, thermal, inlet/outlet, walls, batch 1");
+                    "the adjoint needs the channel lattice with flow, D2Q5 thermal, inlet/outlet, "
+                    "walls on both sides, no buoyancy, batch 1");
     if (nsteps < 1 || K < 1) return fail(LBM_E_ARG, "nsteps and ckpt_every must be >= 1");
     RecLayout r{};
     r.state = align256((size_t)c->nplanes * c->P * c->esize);

@@ -15,6 +15,8 @@ namespace {
 __device__ constexpr int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 __device__ constexpr int EY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 __device__ constexpr int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+// mirror images in y (same c_x, opposite c_y), for the symmetry plane
+__device__ constexpr int MIRY[9] = {0, 1, 4, 3, 2, 8, 7, 6, 5};
 template <typename C>
 __device__ __forceinline__ C wgt(int i) {
     return i == 0 ? C(4) / C(9) : (i < 5 ? C(1) / C(9) : C(1) / C(36));
@@ -23,6 +25,7 @@ __device__ __forceinline__ C wgt(int i) {
 __device__ constexpr int EX5[5] = {0, 1, 0, -1, 0};
 __device__ constexpr int EY5[5] = {0, 0, 1, 0, -1};
 __device__ constexpr int OPP5[5] = {0, 3, 4, 1, 2};
+__device__ constexpr int MIRY5[5] = {0, 1, 4, 3, 2};
 template <typename C>
 __device__ __forceinline__ C wgt5(int i) {
     return i == 0 ? C(1) / C(3) : C(1) / C(6);
@@ -154,7 +157,7 @@ __device__ __forceinline__ C chan_theta(const S* __restrict__ g, long long P, lo
     C e[5];
 #pragma unroll
     for (int i = 0; i < 5; ++i) e[i] = C(g[i * P + n]);
-    return (e[0] + (e[1] + e[3]) + (e[2] + e[4])) + C(0.5) * qdt;
+    return (e[0] + (e[1] + e[3]) + (e[2] + e[4])) + C(0.5) * qdt;  // D2Q5 (adjoint path)
 }
 
 // Lattice body force at a node whose temperature is T = T_ref + th: the

@@ -20,12 +20,14 @@ namespace lbm {
 struct ChanK {
     int nx, ny, batch;
     long long P;          // plane stride (elements)
-    int bcx, bcy;         // 0 periodic; bcx 1 inlet/outlet, 2 fixed-T walls; bcy 1 walls
+    int bcx, bcy;         // 0 periodic; bcx 1 inlet/outlet, 2 fixed-T walls;
+                          // bcy 1 walls, 2 wall at y- + symmetry plane at y+
     int flow, thermal, flow_mrt, thermal_mrt;
     double rho_ref;
     double Lf[9];         // flow rates * dt in the order rho,e,eps,jx,qx,jy,qy,pxx,pxy
     double Ft[2];         // body force * dt^2 / dx
-    double Lt[5];         // thermal rates * dt in the order T,jx,jy,e,pxx
+    int tq;               // thermal lattice: 5 (D2Q5) or 9 (D2Q9)
+    double Lt[9];         // thermal rates * dt: D2Q5 T,jx,jy,e,pxx; D2Q9 the flow basis
     double qdt;           // qdot * dt (K)
     double c;             // lattice speed dx/dt (m/s), for outputs
     double T_ref;

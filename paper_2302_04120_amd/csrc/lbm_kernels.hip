@@ -22,7 +22,22 @@
 namespace lbm {
 namespace {
 
-template <typename S>
+// Thermal lattice of the channel: D2Q5 (QT = 5) or D2Q9 (QT = 9, the set of
+// Sec. 3 and App. D).
+template <int QT> __device__ __forceinline__ int tex(int i) { return QT == 9 ? EX[i] : EX5[i]; }
+template <int QT> __device__ __forceinline__ int tey(int i) { return QT == 9 ? EY[i] : EY5[i]; }
+template <int QT> __device__ __forceinline__ int topp(int i) { return QT == 9 ? OPP[i] : OPP5[i]; }
+template <int QT> __device__ __forceinline__ int tmir(int i) { return QT == 9 ? MIRY[i] : MIRY5[i]; }
+template <int QT, typename C> __device__ __forceinline__ C twt(int i) {
+    return QT == 9 ? wgt<C>(i) : wgt5<C>(i);
+}
+
+// One step of the channel model: D2Q9 flow (BGK or dimensional MRT, Guo
+// forcing, optional Boussinesq force) + D2Q5 or D2Q9 temperature.  Tiles of
+// 64 x 4 nodes.  y: periodic (bcy 0), halfway walls (1), or a wall at y- and
+// the symmetry plane of Eq. simetria at y+ (2).  x: periodic (bcx 0), velocity
+// inlet + pressure outlet (1), fixed-temperature walls (2).
+template <typename S, int QT>
 __global__ __launch_bounds__(256) void k_chan_step(ChanK k, const S* __restrict__ fc,
                                                    S* __restrict__ fn, const S* __restrict__ gc,
                                                    S* __restrict__ gn, const S* __restrict__ qw,
@@ -44,11 +59,15 @@ __global__ __launch_bounds__(256) void k_chan_step(ChanK k, const S* __restrict_
     const C qdt = C(k.qdt);
 
     // temperature first: the Boussinesq force depends on it
-    C e[5], th = C(0);
+    C e[QT], th = C(0);
     if (k.thermal) {
 #pragma unroll
-        for (int i = 0; i < 5; ++i) e[i] = C(gc[i * P + n]);
-        th = (e[0] + (e[1] + e[3]) + (e[2] + e[4])) + C(0.5) * qdt;  // Eq. zero_moment_g
+        for (int i = 0; i < QT; ++i) e[i] = C(gc[i * P + n]);
+        if constexpr (QT == 9)
+            th = ((e[0] + (e[1] + e[3]) + (e[2] + e[4])) + ((e[5] + e[7]) + (e[6] + e[8]))) +
+                 C(0.5) * qdt;  // Eq. zero_moment_g
+        else
+            th = (e[0] + (e[1] + e[3]) + (e[2] + e[4])) + C(0.5) * qdt;
     }
     C ftx, fty;
     chan_force(k, th, ftx, fty);
@@ -93,24 +112,37 @@ __global__ __launch_bounds__(256) void k_chan_step(ChanK k, const S* __restrict_
         for (int i = 0; i < 9; ++i) ds[i] = d[i];
     }
 
-    // ---- temperature collision (Sec. 2.2), advective part built on T - T_ref
-    C es[5];
+    // ---- temperature collision (Sec. 2.2 and Sec. 3), advective part built on
+    //      T - T_ref, in moment space with the rates Lt
+    C es[QT];
     if (k.thermal) {
-        C neq[5], m[5], dm[5], dv[5];
+        C neq[QT], m[QT], dm[QT], dv[QT];
 #pragma unroll
-        for (int i = 0; i < 5; ++i)
-            neq[i] = e[i] - wgt5<C>(i) * th * (C(1) + C(3) * (C(EX5[i]) * ux + C(EY5[i]) * uy));
-        moments5(neq, m);
-        // moments of the source w_i qdot dt: qdt (1, 0, 0, -2/3, 0)
-        const C ms[5] = {qdt, C(0), C(0), C(-2) / C(3) * qdt, C(0)};
+        for (int i = 0; i < QT; ++i)
+            neq[i] = e[i] - twt<QT, C>(i) * th * (C(1) + C(3) * (C(tex<QT>(i)) * ux + C(tey<QT>(i)) * uy));
+        if constexpr (QT == 9) {
+            moments9(neq, m);
+            // moments of the source w_i qdot dt: qdt (1, -2, 1, 0, ...)
 #pragma unroll
-        for (int q = 0; q < 5; ++q) {
-            const C L = C(k.Lt[q]);
-            dm[q] = -L * m[q] + (C(1) - C(0.5) * L) * ms[q];
+            for (int q = 0; q < 9; ++q) {
+                const C L = C(k.Lt[q]);
+                const C ms = q == 0 ? qdt : (q == 1 ? C(-2) * qdt : (q == 2 ? qdt : C(0)));
+                dm[q] = -L * m[q] + (C(1) - C(0.5) * L) * ms;
+            }
+            inverse9(dm, dv);
+        } else {
+            moments5(neq, m);
+            // moments of the source w_i qdot dt: qdt (1, 0, 0, -2/3, 0)
+            const C ms[5] = {qdt, C(0), C(0), C(-2) / C(3) * qdt, C(0)};
+#pragma unroll
+            for (int q = 0; q < 5; ++q) {
+                const C L = C(k.Lt[q]);
+                dm[q] = -L * m[q] + (C(1) - C(0.5) * L) * ms[q];
+            }
+            inverse5(dm, dv);
         }
-        inverse5(dm, dv);
 #pragma unroll
-        for (int i = 0; i < 5; ++i) es[i] = e[i] + dv[i];
+        for (int i = 0; i < QT; ++i) es[i] = e[i] + dv[i];
     }
 
     // ---- outlet wall velocity: 1.5 u(x_b) - 0.5 u(x_b - 1) at time t
@@ -118,67 +150,97 @@ __global__ __launch_bounds__(256) void k_chan_step(ChanK k, const S* __restrict_
     const bool outlet = k.bcx == 1 && x == nx - 1;
     if (k.flow && outlet) {
         C d2[9], dr2, r2, ux2, uy2, fx2 = ftx, fy2 = fty;
-        if (k.buoy) chan_force(k, chan_theta<C, S>(gc, P, n - 1, qdt), fx2, fy2);
+        if (k.buoy) {
+            C th2 = C(0);
+#pragma unroll
+            for (int i = 0; i < QT; ++i) th2 += C(gc[i * P + n - 1]);
+            chan_force(k, th2 + C(0.5) * qdt, fx2, fy2);
+        }
         chan_flow_macros<C, S>(fc, P, n - 1, rho_ref, fx2, fy2, d2, dr2, r2, ux2, uy2);
         uwx = C(1.5) * ux - C(0.5) * ux2;
         uwy = C(1.5) * uy - C(0.5) * uy2;
     }
 
-    // ---- streaming with boundary substitution (a frozen flow keeps its populations)
+    // ---- streaming with boundary substitution (a frozen flow keeps its
+    //      populations).  A population leaving through the symmetry plane
+    //      re-enters as its mirror image at x + c_x (Eq. simetria); where that
+    //      lies outside in x the x rule applies.
     if (!k.flow) {
 #pragma unroll
         for (int i = 0; i < 9; ++i) fn[i * P + n] = S(d[i]);
     } else {
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        int tx = x + EX[i], ty = y + EY[i];
-        const bool outy = k.bcy && (ty < 0 || ty >= ny);
-        const bool outx = k.bcx && (tx < 0 || tx >= nx);
-        if (!outy && !outx) {
-            tx = wrap(tx, nx);
-            ty = wrap(ty, ny);
-            fn[i * P + base + (long long)ty * nx + tx] = S(ds[i]);
-        } else {
-            C v;
-            if (outy || k.bcx == 2) {
-                v = ds[i];  // halfway bounce-back, Eq. BB_vel with u_w = 0
-            } else if (tx < 0) {
-                // moving-wall bounce-back with the inlet profile, Eq. BB_vel
-                v = ds[i] - C(6) * wgt<C>(i) * rho_ref * (C(EX[i]) * C(uin[y]));
-            } else {
-                // anti-bounce-back pressure outlet, Eq. anti_BB_vel, rho_w = rho_ref
-                const C eu = C(EX[i]) * uwx + C(EY[i]) * uwy;
-                v = -ds[i] + C(2) * wgt<C>(i) * rho_ref *
-                                 (C(4.5) * eu * eu - C(1.5) * (uwx * uwx + uwy * uwy));
+        for (int i = 0; i < 9; ++i) {
+            int tx = x + EX[i], ty = y + EY[i], j = i;
+            const bool sym = k.bcy == 2 && ty >= ny;
+            if (sym) {
+                ty = ny - 1;
+                j = MIRY[i];
             }
-            fn[OPP[i] * P + n] = S(v);
-        }
-    }
-    }
-    if (k.thermal) {
-#pragma unroll
-        for (int i = 0; i < 5; ++i) {
-            int tx = x + EX5[i], ty = y + EY5[i];
-            const bool outy = k.bcy && (ty < 0 || ty >= ny);
+            const bool outy = k.bcy && !sym && (ty < 0 || ty >= ny);
             const bool outx = k.bcx && (tx < 0 || tx >= nx);
             if (!outy && !outx) {
                 tx = wrap(tx, nx);
                 ty = wrap(ty, ny);
-                gn[i * P + base + (long long)ty * nx + tx] = S(es[i]);
+                fn[j * P + base + (long long)ty * nx + tx] = S(ds[i]);
+            } else {
+                C v;
+                if (outy || k.bcx == 2) {
+                    v = ds[i];  // halfway bounce-back, Eq. BB_vel with u_w = 0
+                } else if (tx < 0) {
+                    // moving-wall bounce-back with the inlet profile, Eq. BB_vel
+                    v = ds[i] - C(6) * wgt<C>(i) * rho_ref * (C(EX[i]) * C(uin[y]));
+                } else {
+                    // anti-bounce-back pressure outlet, Eq. anti_BB_vel, rho_w = rho_ref
+                    const C eu = C(EX[i]) * uwx + C(EY[i]) * uwy;
+                    v = -ds[i] + C(2) * wgt<C>(i) * rho_ref *
+                                     (C(4.5) * eu * eu - C(1.5) * (uwx * uwx + uwy * uwy));
+                }
+                fn[OPP[i] * P + n] = S(v);
+            }
+        }
+    }
+    if (k.thermal) {
+        // Thermal outlet, first-order extrapolation g_j(x_b) = g_j(x_b - 1) at
+        // t + dt: each value stored into column nx - 2 for a population with
+        // c_x < 0 is stored into the outlet column as well, unless a wall rule
+        // owns that outlet slot (its source lies beyond a wall in y).
+        auto put = [&](int j, int tx, int ty, C v) {
+            gn[j * P + base + (long long)ty * nx + tx] = S(v);
+            if (k.bcx == 1 && tx == nx - 2 && tex<QT>(j) < 0) {
+                const int sy = ty - tey<QT>(j);
+                const bool wall_owned = k.bcy && (sy < 0 || (k.bcy == 1 && sy >= ny));
+                if (!wall_owned) gn[j * P + base + (long long)ty * nx + nx - 1] = S(v);
+            }
+        };
+#pragma unroll
+        for (int i = 0; i < QT; ++i) {
+            int tx = x + tex<QT>(i), ty = y + tey<QT>(i), j = i;
+            const bool sym = k.bcy == 2 && ty >= ny;
+            if (sym) {
+                ty = ny - 1;
+                j = tmir<QT>(i);
+            }
+            const bool outy = k.bcy && !sym && (ty < 0 || ty >= ny);
+            const bool outx = k.bcx && (tx < 0 || tx >= nx);
+            if (!outy && !outx) {
+                put(j, wrap(tx, nx), wrap(ty, ny), es[i]);
             } else if (outy) {
-                // prescribed flux, Eq. BB_T with lambda = 1 on D2Q5
-                gn[OPP5[i] * P + n] = S(es[i] + C(qw[x]) * C(mod));
+                // prescribed flux, Eq. BB_T with lambda_i = 6 w_i (1 on D2Q5)
+                const C lam = QT == 9 ? C(6) * wgt<C>(i) : C(1);
+                put(topp<QT>(i), x, y, es[i] + lam * C(qw[x]) * C(mod));
             } else if (k.bcx == 2) {
                 // fixed-temperature side wall (App. D): Eq. anti_BB_T (deviation form)
-                gn[OPP5[i] * P + n] = S(-es[i] + C(2) * wgt5<C>(i) * C(k.Tw[tx < 0 ? 0 : 1]));
+                put(topp<QT>(i), x, y, -es[i] + C(2) * twt<QT, C>(i) * C(k.Tw[tx < 0 ? 0 : 1]));
             } else if (tx < 0) {
-                // anti-bounce-back Dirichlet inlet, Eq. anti_BB_T (deviation form)
-                gn[OPP5[i] * P + n] = S(-es[i] + C(2) * wgt5<C>(i) * C(tin[y]));
-            } else {
-                // first-order extrapolation outlet: the incoming population keeps
-                // the value streamed into x_b - 1, i.e. this node's own post-collision
-                gn[OPP5[i] * P + n] = S(es[OPP5[i]]);
+                // anti-bounce-back Dirichlet inlet, Eq. anti_BB_T (deviation form),
+                // T_w where the link crosses the inlet (between rows y and y + c_y)
+                const int y2 = y + tey<QT>(i);
+                const C tw = (y2 >= 0 && y2 < ny) ? C(0.5) * (C(tin[y]) + C(tin[y2])) : C(tin[y]);
+                put(topp<QT>(i), x, y, -es[i] + C(2) * twt<QT, C>(i) * tw);
             }
+            // populations leaving through the outlet: the outlet slots are filled
+            // by the extrapolation stores of put()
         }
     }
 }
@@ -787,7 +849,10 @@ __global__ void k_chan_init(ChanK k, const double* __restrict__ fld, S* __restri
             f[i * P + n] = S(wgt<double>(i) * ((rho - k.rho_ref) +
                                                rho * (3 * eu + 4.5 * eu * eu - 1.5 * uu)));
         }
-        if (g)
+        if (g && k.tq == 9)
+            for (int i = 0; i < 9; ++i)
+                g[i * P + n] = S(wgt<double>(i) * th * (1 + 3 * (EX[i] * ux + EY[i] * uy)));
+        else if (g)
             for (int i = 0; i < 5; ++i)
                 g[i * P + n] = S(wgt5<double>(i) * th * (1 + 3 * (EX5[i] * ux + EY5[i] * uy)));
     }
@@ -852,7 +917,7 @@ __global__ void k_chan_macros(ChanK k, const S* __restrict__ f, const S* __restr
         double th = 0.0;
         if (g) {
             double s = 0;
-            for (int i = 0; i < 5; ++i) s += double(g[i * P + n]);
+            for (int i = 0; i < k.tq; ++i) s += double(g[i * P + n]);
             th = s + 0.5 * k.qdt;
         }
         double fx, fy;
@@ -931,7 +996,7 @@ __global__ __launch_bounds__(256) void k_reduce1(int lattice, ChanK ck, PhaseK p
             v[0] += ck.rho_ref + a;
             if (ck.thermal) {
                 double s = 0;
-                for (int i = 0; i < 5; ++i) s += double(pops[(9 + i) * P + n]);
+                for (int i = 0; i < ck.tq; ++i) s += double(pops[(9 + i) * P + n]);
                 v[2] += ck.T_ref + s + 0.5 * ck.qdt;
             }
         } else {
@@ -966,7 +1031,7 @@ __global__ void k_nusselt(ChanK k, const S* __restrict__ f, const S* __restrict_
     for (int y = 0; y < k.ny; ++y) {
         const long long n = (long long)y * k.nx + x;
         double s = 0;
-        for (int i = 0; i < 5; ++i) s += double(g[i * P + n]);
+        for (int i = 0; i < k.tq; ++i) s += double(g[i * P + n]);
         const double T = k.T_ref + s + 0.5 * k.qdt;
         double fx, fy;
         chan_force(k, T - k.T_ref, fx, fy);
@@ -979,7 +1044,9 @@ __global__ void k_nusselt(ChanK k, const S* __restrict__ f, const S* __restrict_
     }
     const double q = double(qw[x]) * qsi;  // W/m^2 including the time modulation
     const double tb = suT / su;
-    const double tw = 0.5 * (T0 + T1) + q * dx / (2.0 * kc);
+    // wall temperature: mean of the two wall-adjacent nodes, or the lower one
+    // with a symmetry plane on top; plus the half-cell conduction q dx / 2k
+    const double tw = (k.bcy == 2 ? T0 : 0.5 * (T0 + T1)) + q * dx / (2.0 * kc);
     Tb[x] = tb;
     Tw[x] = tw;
     Nu[x] = q * Dh / (kc * (tw - tb));
@@ -1010,7 +1077,10 @@ hipError_t launch_chan_step(const ChanK& k, const S* fc, S* fn, const S* gc, S* 
                             const S* uin, const S* tin, double mod, hipStream_t s) {
     const long long tiles = (long long)((k.nx + 63) / 64) * ((k.ny + 3) / 4) * k.batch;
     dim3 blk(64, 4), grd(unsigned((tiles + kXCD - 1) / kXCD * kXCD));
-    hipLaunchKernelGGL(k_chan_step<S>, grd, blk, 0, s, k, fc, fn, gc, gn, qw, uin, tin, S(mod));
+    if (k.tq == 9)
+        hipLaunchKernelGGL((k_chan_step<S, 9>), grd, blk, 0, s, k, fc, fn, gc, gn, qw, uin, tin, S(mod));
+    else
+        hipLaunchKernelGGL((k_chan_step<S, 5>), grd, blk, 0, s, k, fc, fn, gc, gn, qw, uin, tin, S(mod));
     return hipGetLastError();
 }
 

@@ -23,9 +23,9 @@ LBM_OK, LBM_E_ARG, LBM_E_TAU, LBM_E_DEVICE, LBM_E_STATE, LBM_E_NONFINITE, LBM_E_
     0, -1, -2, -3, -4, -5, -6
 LBM_D1Q2, LBM_D1Q3, LBM_D2Q9_D2Q5, LBM_D2Q9_PHASE = 1, 2, 3, 4
 LBM_FP32_DEV, LBM_FP64 = 0, 1
-BC_PERIODIC, BC_WALL, BC_VEL_INLET, BC_P_OUTLET, BC_DIRICHLET = 0, 1, 2, 3, 4
+BC_PERIODIC, BC_WALL, BC_VEL_INLET, BC_P_OUTLET, BC_DIRICHLET, BC_SYMMETRY = 0, 1, 2, 3, 4, 5
 LBM_BGK, LBM_MRT = 0, 1
-FLAG_FLOW, FLAG_THERMAL = 1, 2
+FLAG_FLOW, FLAG_THERMAL, FLAG_THERMAL_D2Q9 = 1, 2, 4
 MACRO_BITS = {"rho": 1, "p": 2, "ux": 4, "uy": 8, "T": 16, "phi": 32, "mu": 64}
 REDUCE_BITS = {"mass": 1, "phase": 2, "energy": 4, "nonfinite": 8}
 
@@ -189,7 +189,9 @@ class Lattice:
         d.prec = LBM_FP64 if prec == "fp64" else LBM_FP32_DEV
         for i in range(4):
             d.bc[i] = bc[i]
-        d.flags = (FLAG_FLOW if flow else 0) | (FLAG_THERMAL if thermal else 0)
+        # thermal: False, True / 'd2q5' (D2Q5), or 'd2q9' (D2Q9 thermal set)
+        d.flags = ((FLAG_FLOW if flow else 0) | (FLAG_THERMAL if thermal else 0) |
+                   (FLAG_THERMAL_D2Q9 if thermal == "d2q9" else 0))
         d.hip_stream = C.c_void_p(self.stream.cuda_stream)
         nbytes = C.c_size_t()
         self._check(lib().lbm_query_bytes(C.byref(d), C.byref(nbytes)), None)

@@ -232,3 +232,49 @@ def cavity(Ra=1e4, dx=2e-4, dt=2e-4, n=None, g=9.81):
     ini = dict(rho=np.full((n, n), a["rho"]), ux=np.zeros((n, n)), uy=np.zeros((n, n)),
                T=np.full((n, n), Tc))
     return prm, ini
+
+
+# --------------------------------------------------------------------------
+# The paper's own heated-channel cases (Sec. 4.2): lower half of the channel
+# with a symmetry plane at mid-height
+# --------------------------------------------------------------------------
+
+WATER_301K_SEC42 = dict(rho=996.279, nu=8.382e-7, k=0.611, cp=4180.333, alpha=1.467e-7)
+
+
+def paper_channel(case, H=0.5e-3, L=10e-3, T_in=300.0, q_s=4e4, dq=4e4, L_h=1e-3):
+    """case 'developed_alternating': developed inlet (Eq. velocity_prof with
+    u_m = 0.2 m/s, Eq. temp_prof for the mean flux), flux q_s + dq sign(sin(2 pi
+    x / L_h)) (Eq. var_flux), dx = 5 um, dt = 2 us.  'developing_constant':
+    uniform inlet u_m = 0.02 m/s and T_in, flux q_s, dx = 2.5 um, dt = 0.625 us.
+    'developing_alternating': the same with the alternating flux.  Grid: the
+    lower half (H/2) of the channel, L long; BGK flow, D2Q9 MRT thermal."""
+    w = WATER_301K_SEC42
+    if case == "developed_alternating":
+        dx, dt, u_m, developed, alternating = 5e-6, 2e-6, 0.2, True, True
+    elif case == "developing_constant":
+        dx, dt, u_m, developed, alternating = 2.5e-6, 6.25e-7, 0.02, False, False
+    elif case == "developing_alternating":
+        dx, dt, u_m, developed, alternating = 2.5e-6, 6.25e-7, 0.02, False, True
+    else:
+        raise ValueError(case)
+    nx, ny = int(round(L / dx)), int(round(0.5 * H / dx))
+    y = node_centres(ny, dx)
+    x = node_centres(nx, dx)
+    rho_cp = w["rho"] * w["cp"]
+    k = w["k"]
+    flux = q_s + (dq * np.sign(np.sin(2 * math.pi * x / L_h)) if alternating else 0.0 * x)
+    if developed:
+        u_in = poiseuille_profile(y, H, u_m)
+        T_prof = developed_temperature_profile(y, H, T_in, q_s, k)
+    else:
+        u_in = np.full(ny, u_m)
+        T_prof = np.full(ny, T_in)
+    prm = dict(dx=dx, dt=dt, rho_ref=w["rho"], nu=w["nu"], omega_e=1.0 / dt, omega_eps=1.0 / dt,
+               Fx=0.0, Fy=0.0, alpha=w["alpha"], rho_cp=rho_cp, qdot=0.0, T_ref=T_in,
+               flux=flux, flux_amp=0.0, flux_omega=0.0, inlet_u=u_in, inlet_T=T_prof,
+               flow_mrt=0, thermal_mrt=1, k=k, H=H, L=L, u_m=u_m, q_s=q_s, T_in=T_in)
+    ux0 = np.repeat(u_in[:, None], nx, axis=1) if developed else np.zeros((ny, nx))
+    ini = dict(rho=np.full((ny, nx), w["rho"]), ux=ux0, uy=np.zeros((ny, nx)),
+               T=np.repeat(T_prof[:, None], nx, axis=1))
+    return prm, ini

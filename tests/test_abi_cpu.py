@@ -103,3 +103,31 @@ def test_product_binding_refuses_without_gpu():
         pytest.skip("a GPU is visible")
     with pytest.raises(RuntimeError):
         lbm.Lattice("phase", 16, 16)
+
+
+def test_channel_description_validation():
+    """D2Q9_D2Q5 descriptions: the D2Q9 thermal flag needs THERMAL, the
+    symmetry plane only sits at y+ above a wall, fixed-temperature side walls
+    need the thermal field."""
+    lbm = _lbm()
+    L = lbm.lib()
+    n = C.c_size_t()
+    cases = [((1 | 2 | 4), (2, 3, 1, 1), lbm.LBM_OK),
+             ((1 | 2), (2, 3, 1, 5), lbm.LBM_OK),
+             ((1 | 2 | 4), (2, 3, 1, 5), lbm.LBM_OK),
+             ((1 | 2), (4, 4, 1, 1), lbm.LBM_OK),
+             ((1 | 4), (2, 3, 1, 1), lbm.LBM_E_ARG),
+             ((1 | 2), (0, 0, 5, 1), lbm.LBM_E_UNSUPPORTED),
+             ((1 | 2), (0, 0, 5, 5), lbm.LBM_E_UNSUPPORTED),
+             (1, (4, 4, 1, 1), lbm.LBM_E_ARG),
+             ((1 | 2), (0, 0, 1, 6), lbm.LBM_E_ARG)]
+    for flags, bc, want in cases:
+        d = _desc(lbm, lattice=lbm.LBM_D2Q9_D2Q5, nx=64, ny=12, bc=bc, flags=flags)
+        assert L.lbm_query_bytes(C.byref(d), C.byref(n)) == want, (flags, bc)
+    # D2Q9 thermal planes: 9 + 9 per buffer instead of 9 + 5
+    d5 = _desc(lbm, lattice=lbm.LBM_D2Q9_D2Q5, nx=64, ny=12, bc=(2, 3, 1, 1), flags=3)
+    d9 = _desc(lbm, lattice=lbm.LBM_D2Q9_D2Q5, nx=64, ny=12, bc=(2, 3, 1, 1), flags=7)
+    n5, n9 = C.c_size_t(), C.c_size_t()
+    L.lbm_query_bytes(C.byref(d5), C.byref(n5))
+    L.lbm_query_bytes(C.byref(d9), C.byref(n9))
+    assert n9.value - n5.value == 2 * 4 * 64 * 12 * 4

@@ -104,12 +104,13 @@ def test_pressure_equilibrium_moments():
 
 
 # ---------------------------------------------------------------- PIN-3
-def test_dimensional_equals_conventional_channel():
+@pytest.mark.parametrize("tq", ["d2q5", "d2q9"])
+def test_dimensional_equals_conventional_channel(tq):
     """Sec. 3 central claim: the dimensional run (SI) and the conventional
     run (lattice units, C_x = dx, C_t = dt) are the same computation."""
     prm, ini = WL.channel(nx=24, ny=10, dx=5e-5, tau_ratio=0.7, oscillating=True)
     prm["flux"] = 1e4 * (1 + 0.5 * np.sign(np.sin(np.arange(24) / 3.0)))
-    kw = dict(bc_x="inlet_outlet", bc_y="walls", thermal=True)
+    kw = dict(bc_x="inlet_outlet", bc_y="walls", thermal=tq)
     a = O.Chan(24, 10, prm, **kw)
     a.init(**ini)
     lat = chan_to_lattice(prm)
@@ -174,13 +175,16 @@ def test_shear_wave_decay_nu(mrt):
 
 
 @pytest.mark.parametrize("tmrt", [0, 1])
-def test_thermal_sine_decay_alpha(tmrt):
-    """alpha = (tau_T - dt/2) c_s^2 (Sec. 2.2): a sine temperature decays at alpha k^2."""
+@pytest.mark.parametrize("tq", ["d2q5", "d2q9"])
+def test_thermal_sine_decay_alpha(tmrt, tq):
+    """alpha = (tau_T - dt/2) c_s^2 (Sec. 2.2): a sine temperature decays at
+    alpha k^2, on D2Q5 and on the D2Q9 thermal set (with Lambda_T,dim of
+    Sec. 3 for MRT)."""
     n, dx, alpha = 32, 1e-5, 1e-7
     dt = 0.2 * dx * dx / (3 * alpha)
     prm = dict(dx=dx, dt=dt, rho_ref=1000.0, nu=1e-6, alpha=alpha, rho_cp=4e6, T_ref=300.0,
                thermal_mrt=tmrt)
-    ch = O.Chan(n, n, prm, flow=False, thermal=True)
+    ch = O.Chan(n, n, prm, flow=False, thermal=tq)
     x = WL.node_centres(n, dx)
     k = 2 * np.pi / (n * dx)
     T0 = 300 + np.repeat((np.sin(k * x))[None, :], n, 0)
@@ -262,7 +266,8 @@ def test_poiseuille_exact_discrete_profile(mrt, tau):
 
 # ---------------------------------------------------------------- PIN-7
 @pytest.mark.slow
-def test_channel_developed_nusselt():
+@pytest.mark.parametrize("tq", ["d2q5", "d2q9"])
+def test_channel_developed_nusselt(tq):
     """Sec. 4.2: with the developed velocity and temperature profiles at the
     inlet (Eq. velocity_prof, Eq. temp_prof) and equal uniform flux on both
     walls, the local Nu is the developed value 140/17 = 8.235 (the paper quotes
@@ -272,7 +277,7 @@ def test_channel_developed_nusselt():
     assert 17 / 70 == pytest.approx(pv["developed_profile_constant"]["value"], abs=5e-4)
     assert 140 / 17 == pytest.approx(pv["nusselt_developed"]["theory"], abs=5e-3)
     prm, ini = WL.channel(nx=60, ny=20, dx=5e-5, tau_ratio=0.6)
-    ch = O.Chan(60, 20, prm, bc_x="inlet_outlet", bc_y="walls", thermal=True)
+    ch = O.Chan(60, 20, prm, bc_x="inlet_outlet", bc_y="walls", thermal=tq)
     ch.init(**ini)
     ch.step(8000)
     Tb, Tw, Nu = ch.nusselt()
@@ -506,3 +511,34 @@ def test_layered_coarse_grid_study_against_paper():
     assert g["uy_max_abs"] < 1e-6 * np.abs(u).max()
     # the sharp-interface profile is further away: the interface is 5 dx wide
     assert g["E2_vs_sharp_percent"] > e2
+
+
+@pytest.mark.parametrize("tq", ["d2q5", "d2q9"])
+def test_symmetry_plane_half_channel_equals_full_channel(tq):
+    """Eq. simetria: the lower half of a channel with a symmetry plane at its
+    top reproduces the lower half of the full channel started from a
+    mirror-symmetric state, node for node, for flow and temperature, with the
+    inlet and outlet corners of the plane included."""
+    nx, nh = 24, 6
+    prm, ini = WL.channel(nx=nx, ny=2 * nh, dx=5e-5, tau_ratio=0.7)
+    prm["flux"] = 1e4 * (1 + 0.5 * np.sign(np.sin(np.arange(nx) / 3.0)))
+    g = WL.rng(21)
+    pert = g.uniform(-1, 1, (nh, nx))
+    sym = lambda a: np.concatenate([a, a[::-1]], axis=0)
+    ini_f = dict(rho=ini["rho"] * (1 + 1e-4 * sym(pert)), ux=ini["ux"] * (1 + 0.05 * sym(pert)),
+                 uy=1e-4 * np.concatenate([pert, -pert[::-1]], axis=0), T=ini["T"] + sym(pert))
+    full = O.Chan(nx, 2 * nh, prm, bc_x="inlet_outlet", bc_y="walls", thermal=tq)
+    full.init(**ini_f)
+    half_prm = dict(prm, inlet_u=prm["inlet_u"][:nh], inlet_T=prm["inlet_T"][:nh])
+    half = O.Chan(nx, nh, half_prm, bc_x="inlet_outlet", bc_y="wall_symmetry", thermal=tq)
+    half.init(**{k: v[:nh] for k, v in ini_f.items()})
+    full.step(300)
+    half.step(300)
+    mf, mh = full.macros(), half.macros()
+    for k in ("rho", "ux", "T"):
+        np.testing.assert_allclose(mh[k], mf[k][:nh], rtol=1e-12, atol=1e-12 * np.abs(mf[k]).max())
+    np.testing.assert_allclose(mh["uy"], mf["uy"][:nh], rtol=0, atol=1e-10 * np.abs(mf["ux"]).max())
+    # the mirrored upper half of the full run agrees too (the full run stays symmetric)
+    np.testing.assert_allclose(mf["T"][nh:][::-1], mf["T"][:nh], rtol=1e-12)
+    # and the half channel's Nusselt number is the full channel's
+    np.testing.assert_allclose(half.nusselt()[2], full.nusselt()[2], rtol=1e-9)
