@@ -7,6 +7,7 @@ replay."""
 import numpy as np
 import pytest
 
+import oracle as O
 from paper_2302_04120_amd import workloads as WL
 
 from gpu_cases import phase_pair, print_case, rel_err
@@ -104,3 +105,36 @@ def test_fusion_validation():
     with pytest.raises(lbm.LbmError):
         L.set_step_fusion(3)
     L.set_step_fusion(1)
+
+
+@pytest.mark.timeout(300)
+def test_bench_size_two_step_sampled_against_oracle():
+    """The benchmark's own launch configuration: 1024 replicas of the 256 x 256
+    bubble cell (67 M nodes, FP32, two-step kernel), 20 steps.  Sampled
+    replicas (the first, a middle and the last, which sit in different
+    segments and XCD bands) against the FP64 oracle run one by one; every
+    replica's phi sum conserved and no non-finite population anywhere."""
+    from paper_2302_04120_amd import lbm
+    batch, n, steps = 1024, 256, 20
+    prm, ini, _ = WL.bubble(n=n, batch=batch, seed=0)
+    print_case(test="tb2-bench-size", batch=batch, steps=steps)
+    L = lbm.Lattice("phase", n, n, batch=batch, prec="fp32")
+    L.set_step_fusion(2)
+    L.set_params(prm)
+    L.init(ini["p"], ini["ux"], ini["uy"], None, ini["phi"])
+    m0 = L.reduce(("phase",))["phase"]
+    L.step(steps)
+    red = L.reduce(("phase", "nonfinite"))
+    assert red["nonfinite"].sum() == 0
+    assert (np.abs(red["phase"] - m0) / m0).max() < 1e-13
+    m = L.macros(("phi", "p", "ux"))
+    for b in (0, 513, 1023):
+        o = O.Phase(n, n, prm)
+        o.init(ini["phi"][b], ini["p"][b], ini["ux"][b], ini["uy"][b])
+        o.step(steps)
+        mo = o.macros()
+        scale_p = max(float(np.abs(mo["p"]).max()), prm["sigma"] / prm["W"])
+        e = (rel_err(m["phi"][b], mo["phi"], scale=1.0), rel_err(m["p"][b], mo["p"], scale=scale_p),
+             rel_err(m["ux"][b], mo["ux"]))
+        print("replica %d: phi %.2e p %.2e ux %.2e" % (b, *e), flush=True)
+        assert e[0] < 1e-5 and e[1] < 1e-5 and e[2] < 1e-4
