@@ -61,6 +61,13 @@ class PhaseParams(C.Structure):
                 ("z_mrt", C.c_int), ("qy_printed", C.c_int), ("normal_eps", C.c_double)]
 
 
+class D3Params(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("bc_x", C.c_int), ("bc_y", C.c_int),
+                ("bc_z", C.c_int), ("dx", C.c_double), ("dt", C.c_double), ("mrt", C.c_int),
+                ("rho_ref", C.c_double), ("nu", C.c_double), ("omega_e", C.c_double),
+                ("omega_eps", C.c_double), ("F", C.c_double * 3)]
+
+
 def _declare(L):
     L.orc_d1_run.restype = C.c_int
     L.orc_d1_run.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, C.c_double, C.c_double,
@@ -93,6 +100,14 @@ def _declare(L):
     L.orc_phase_get_state.argtypes = [C.c_void_p, _dp, _dp, _dp]
     L.orc_phase_gradients.argtypes = [C.c_void_p, _dp, _dp, _dp]
     L.orc_phase_set_state.argtypes = [C.c_void_p, _dp, _dp, _dp]
+    L.orc_d3_mdim.argtypes = [C.c_double, _dp, _dp]
+    L.orc_d3_create.restype = C.c_void_p
+    L.orc_d3_create.argtypes = [C.POINTER(D3Params)]
+    L.orc_d3_destroy.argtypes = [C.c_void_p]
+    L.orc_d3_init.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp]
+    L.orc_d3_step.argtypes = [C.c_void_p, C.c_long]
+    L.orc_d3_macros.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp]
+    L.orc_d3_get_state.argtypes = [C.c_void_p, _dp]
 
 
 def _f64(a, shape=None):
@@ -285,6 +300,59 @@ class Phase:
 
     def set_state(self, h, z, pu):
         lib().orc_phase_set_state(self.h, _ptr(_f64(h)), _ptr(_f64(z)), _ptr(_f64(pu)))
+
+
+def d3_mdim(c):
+    """The dimensional D3Q19 moment matrix and its inverse (Sec. 3 in 3D)."""
+    M = np.zeros((19, 19))
+    Mi = np.zeros((19, 19))
+    lib().orc_d3_mdim(float(c), _ptr(M), _ptr(Mi))
+    return M, Mi
+
+
+class D3:
+    """D3Q19 momentum (BGK or the dimensional MRT) on nx x ny x nz, arrays
+    indexed [z][y][x]; each axis periodic or closed by halfway walls."""
+
+    def __init__(self, nx, ny, nz, prm, bc_x="periodic", bc_y="periodic", bc_z="periodic",
+                 mrt=True):
+        self.shape = (nz, ny, nx)
+        P = D3Params()
+        P.nx, P.ny, P.nz = nx, ny, nz
+        kinds = {"periodic": 0, "walls": 1}
+        P.bc_x, P.bc_y, P.bc_z = kinds[bc_x], kinds[bc_y], kinds[bc_z]
+        P.dx, P.dt, P.mrt = prm["dx"], prm["dt"], int(mrt)
+        P.rho_ref, P.nu = prm["rho_ref"], prm["nu"]
+        P.omega_e, P.omega_eps = prm.get("omega_e", 0.0), prm.get("omega_eps", 0.0)
+        F = prm.get("F", (0.0, 0.0, 0.0))
+        for i in range(3):
+            P.F[i] = F[i]
+        self.P = P
+        self.h = lib().orc_d3_create(C.byref(P))
+        if not self.h:
+            raise ValueError("orc_d3_create failed")
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().orc_d3_destroy(self.h)
+            self.h = None
+
+    def init(self, rho, ux, uy, uz):
+        sh = self.shape
+        lib().orc_d3_init(self.h, *(_ptr(_f64(a, sh)) for a in (rho, ux, uy, uz)))
+
+    def step(self, n):
+        lib().orc_d3_step(self.h, int(n))
+
+    def macros(self):
+        out = {k: np.zeros(self.shape) for k in ("rho", "ux", "uy", "uz")}
+        lib().orc_d3_macros(self.h, *(_ptr(out[k]) for k in ("rho", "ux", "uy", "uz")))
+        return out
+
+    def get_state(self):
+        f = np.zeros((19,) + self.shape)
+        lib().orc_d3_get_state(self.h, _ptr(f))
+        return f
 
 
 # --------------------------------------------------------------------------

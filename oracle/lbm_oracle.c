@@ -63,7 +63,7 @@ static const int ORD5[5] = {0, 1, 1, 2, 2};
 
 /* Gauss-Jordan inversion with partial pivoting of an n x n row-major matrix. */
 static int invert(int n, const double* A, double* Ainv) {
-    double a[81 * 2];
+    double a[19 * 38]; /* n <= 19 */
     int w = 2 * n;
     for (int r = 0; r < n; ++r)
         for (int k = 0; k < w; ++k)
@@ -1239,4 +1239,211 @@ void orc_phase_set_state(orc_phase* s, const double* h, const double* z, const d
     if (h) memcpy(s->h, h, sizeof(double) * 9 * N);
     if (z) memcpy(s->z, z, sizeof(double) * 9 * N);
     if (phiu) memcpy(s->phiu, phiu, sizeof(double) * 2 * N);
+}
+
+/* ------------------------------------------------------------------------- */
+/* 3D momentum: D3Q19 with the dimensional MRT of Sec. 3                       */
+/* ------------------------------------------------------------------------- */
+/* The paper works in 2D and states that the method extends to 3D (Sec. 5).
+ * Reading for the extension: the D3Q19 velocity set and the orthogonal
+ * moment basis of d'Humieres et al. (2002) -- rows 1, e, eps, j, q, 3p_xx,
+ * 3pi_xx, p_ww, pi_ww, p_xy, p_yz, p_xz, m_x, m_y, m_z as polynomials of the
+ * lattice velocity -- each row multiplied by c^(its degree) exactly as in
+ * Eq. M_matrix_dim, inverted numerically.  Rates: e, eps free (omega_e,
+ * omega_eps), the stresses at 1/tau, q and m at omega_q of Sec. 3, pi at
+ * 1/dt.  Guo forcing and the second-order equilibrium as in 2D. */
+
+static const int EX19[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+static const int EY19[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+static const int EZ19[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+static const int OPP19[19] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+static double w19(int i) { return i == 0 ? 1.0 / 3 : (i < 7 ? 1.0 / 18 : 1.0 / 36); }
+/* degree of each moment row */
+static const int ORD19[19] = {0, 2, 4, 1, 3, 1, 3, 1, 3, 2, 4, 2, 4, 2, 2, 2, 3, 3, 3};
+
+/* row k of the lattice-unit moment basis at velocity (cx, cy, cz) */
+static double d3_row(int k, int cx, int cy, int cz) {
+    double c2 = cx * cx + cy * cy + cz * cz;
+    switch (k) {
+        case 0: return 1;
+        case 1: return 19 * c2 - 30;
+        case 2: return (21 * c2 * c2 - 53 * c2 + 24) / 2;
+        case 3: return cx;
+        case 4: return (5 * c2 - 9) * cx;
+        case 5: return cy;
+        case 6: return (5 * c2 - 9) * cy;
+        case 7: return cz;
+        case 8: return (5 * c2 - 9) * cz;
+        case 9: return 3 * cx * cx - c2;
+        case 10: return (3 * c2 - 5) * (3 * cx * cx - c2);
+        case 11: return cy * cy - cz * cz;
+        case 12: return (3 * c2 - 5) * (cy * cy - cz * cz);
+        case 13: return cx * cy;
+        case 14: return cy * cz;
+        case 15: return cx * cz;
+        case 16: return (cy * cy - cz * cz) * cx;
+        case 17: return (cz * cz - cx * cx) * cy;
+        default: return (cx * cx - cy * cy) * cz;
+    }
+}
+
+void orc_d3_mdim(double c, double* M, double* Minv) {
+    double Ml[361];
+    for (int k = 0; k < 19; ++k)
+        for (int i = 0; i < 19; ++i) Ml[k * 19 + i] = d3_row(k, EX19[i], EY19[i], EZ19[i]);
+    build_mdim(19, Ml, ORD19, c, M, Minv);
+}
+
+struct orc_d3 {
+    orc_d3_params p;
+    double c, cs2, tau;
+    double Md[361], Mi[361], lam[19];
+    double *f, *fs, *fn;
+    long t;
+};
+
+#define IDX3(s, i, x, y, z) \
+    (((size_t)(i) * (s)->p.nz + (size_t)(z)) * (s)->p.ny * (s)->p.nx + (size_t)(y) * (s)->p.nx + (x))
+
+static double feq19(int i, double rho, double ux, double uy, double uz, double c, double cs2) {
+    double cu = c * (EX19[i] * ux + EY19[i] * uy + EZ19[i] * uz);
+    double uu = ux * ux + uy * uy + uz * uz;
+    return w19(i) * rho * (1.0 + cu / cs2 + cu * cu / (2.0 * cs2 * cs2) - uu / (2.0 * cs2));
+}
+
+/* Guo forcing term without its prefactor (Eq. forcing_term, in 3D) */
+static double guo19(int i, double ux, double uy, double uz, const double* F, double c,
+                    double cs2) {
+    double cx = c * EX19[i], cy = c * EY19[i], cz = c * EZ19[i];
+    double cu = cx * ux + cy * uy + cz * uz;
+    double a = (cx - ux) / cs2 + cu * cx / (cs2 * cs2);
+    double b = (cy - uy) / cs2 + cu * cy / (cs2 * cs2);
+    double d = (cz - uz) / cs2 + cu * cz / (cs2 * cs2);
+    return w19(i) * (a * F[0] + b * F[1] + d * F[2]);
+}
+
+orc_d3* orc_d3_create(const orc_d3_params* p) {
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1 || p->dx <= 0 || p->dt <= 0) return NULL;
+    orc_d3* s = (orc_d3*)calloc(1, sizeof(orc_d3));
+    s->p = *p;
+    s->c = p->dx / p->dt;
+    s->cs2 = s->c * s->c / 3.0;
+    s->tau = p->nu / s->cs2 + 0.5 * p->dt;
+    double dt = p->dt, wn = 1.0 / s->tau;
+    double wq = (3.0 / dt) * (2.0 / dt - wn) / (3.0 / dt - wn);
+    double we = p->omega_e > 0 ? p->omega_e : 1.0 / dt;
+    double wp = p->omega_eps > 0 ? p->omega_eps : 1.0 / dt;
+    double lam[19] = {0, we, wp, 0, wq, 0, wq, 0, wq, wn, 1.0 / dt, wn, 1.0 / dt, wn, wn, wn,
+                      wq, wq, wq};
+    memcpy(s->lam, lam, sizeof lam);
+    orc_d3_mdim(s->c, s->Md, s->Mi);
+    size_t N = (size_t)p->nx * p->ny * p->nz;
+    s->f = (double*)calloc(19 * N, sizeof(double));
+    s->fs = (double*)calloc(19 * N, sizeof(double));
+    s->fn = (double*)calloc(19 * N, sizeof(double));
+    return s;
+}
+
+void orc_d3_destroy(orc_d3* s) {
+    if (!s) return;
+    free(s->f); free(s->fs); free(s->fn);
+    free(s);
+}
+
+void orc_d3_init(orc_d3* s, const double* rho, const double* ux, const double* uy,
+                 const double* uz) {
+    size_t N = (size_t)s->p.nx * s->p.ny * s->p.nz;
+    for (size_t n = 0; n < N; ++n)
+        for (int i = 0; i < 19; ++i)
+            s->f[(size_t)i * N + n] = feq19(i, rho[n], ux[n], uy[n], uz[n], s->c, s->cs2);
+    s->t = 0;
+}
+
+static void d3_node_macros(const orc_d3* s, size_t n, double* rho, double* ux, double* uy,
+                           double* uz) {
+    size_t N = (size_t)s->p.nx * s->p.ny * s->p.nz;
+    double r = 0, jx = 0, jy = 0, jz = 0;
+    for (int i = 0; i < 19; ++i) {
+        double fi = s->f[(size_t)i * N + n];
+        r += fi;
+        jx += s->c * EX19[i] * fi;
+        jy += s->c * EY19[i] * fi;
+        jz += s->c * EZ19[i] * fi;
+    }
+    *rho = r;
+    *ux = (jx + 0.5 * s->p.dt * s->p.F[0]) / r;
+    *uy = (jy + 0.5 * s->p.dt * s->p.F[1]) / r;
+    *uz = (jz + 0.5 * s->p.dt * s->p.F[2]) / r;
+}
+
+void orc_d3_macros(const orc_d3* s, double* rho, double* ux, double* uy, double* uz) {
+    size_t N = (size_t)s->p.nx * s->p.ny * s->p.nz;
+    for (size_t n = 0; n < N; ++n) {
+        double r, a, b, d;
+        d3_node_macros(s, n, &r, &a, &b, &d);
+        if (rho) rho[n] = r;
+        if (ux) ux[n] = a;
+        if (uy) uy[n] = b;
+        if (uz) uz[n] = d;
+    }
+}
+
+static void d3_one_step(orc_d3* s) {
+    const orc_d3_params* p = &s->p;
+    int nx = p->nx, ny = p->ny, nz = p->nz;
+    size_t N = (size_t)nx * ny * nz;
+    double dt = p->dt;
+    /* collision, node by node (Eq. colisao_MRT or the BGK form) */
+    for (size_t n = 0; n < N; ++n) {
+        double rho, ux, uy, uz;
+        d3_node_macros(s, n, &rho, &ux, &uy, &uz);
+        double f[19], fe[19], Fh[19], out[19];
+        for (int i = 0; i < 19; ++i) {
+            f[i] = s->f[(size_t)i * N + n];
+            fe[i] = feq19(i, rho, ux, uy, uz, s->c, s->cs2);
+            Fh[i] = guo19(i, ux, uy, uz, p->F, s->c, s->cs2);
+        }
+        if (p->mrt) {
+            double m[19], me[19], Fm[19], ms[19];
+            matvec(19, s->Md, f, m);
+            matvec(19, s->Md, fe, me);
+            matvec(19, s->Md, Fh, Fm);
+            for (int k = 0; k < 19; ++k)
+                ms[k] = m[k] - dt * s->lam[k] * (m[k] - me[k]) +
+                        dt * (1.0 - 0.5 * dt * s->lam[k]) * Fm[k];
+            matvec(19, s->Mi, ms, out);
+        } else {
+            for (int i = 0; i < 19; ++i)
+                out[i] = f[i] - dt / s->tau * (f[i] - fe[i]) +
+                         dt * (1.0 - dt / (2.0 * s->tau)) * Fh[i];
+        }
+        for (int i = 0; i < 19; ++i) s->fs[(size_t)i * N + n] = out[i];
+    }
+    /* streaming: pull from x - c_i dt; each axis periodic or closed by
+     * halfway bounce-back walls (Eq. BB_vel, u_w = 0) */
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x)
+                for (int i = 0; i < 19; ++i) {
+                    int sx = x - EX19[i], sy = y - EY19[i], sz = z - EZ19[i];
+                    int out = 0;
+                    if (p->bc_x) out |= (sx < 0 || sx >= nx);
+                    else sx = (sx + nx) % nx;
+                    if (p->bc_y) out |= (sy < 0 || sy >= ny);
+                    else sy = (sy + ny) % ny;
+                    if (p->bc_z) out |= (sz < 0 || sz >= nz);
+                    else sz = (sz + nz) % nz;
+                    double v = out ? s->fs[IDX3(s, OPP19[i], x, y, z)] : s->fs[IDX3(s, i, sx, sy, sz)];
+                    s->fn[IDX3(s, i, x, y, z)] = v;
+                }
+    double* t = s->f; s->f = s->fn; s->fn = t;
+    s->t += 1;
+}
+
+void orc_d3_step(orc_d3* s, long nsteps) {
+    for (long k = 0; k < nsteps; ++k) d3_one_step(s);
+}
+
+void orc_d3_get_state(const orc_d3* s, double* f) {
+    memcpy(f, s->f, sizeof(double) * 19 * (size_t)s->p.nx * s->p.ny * s->p.nz);
 }

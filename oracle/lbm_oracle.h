@@ -121,6 +121,28 @@ void orc_phase_gradients(const orc_phase* s, double* gx, double* gy, double* lap
 void orc_phase_get_state(const orc_phase* s, double* h, double* z, double* phiu);
 void orc_phase_set_state(orc_phase* s, const double* h, const double* z, const double* phiu);
 
+/* ---- 3D momentum: D3Q19 with the dimensional MRT (Sec. 3 in three dimensions) ---- */
+typedef struct {
+    int nx, ny, nz;
+    int bc_x, bc_y, bc_z; /* per axis: 0 periodic, 1 halfway walls on both sides */
+    double dx, dt;
+    int mrt;           /* 0 BGK, 1 dimensional MRT */
+    double rho_ref, nu, omega_e, omega_eps;  /* omega_* in 1/s (<= 0: 1/dt) */
+    double F[3];       /* body force, N/m^3 */
+} orc_d3_params;
+
+typedef struct orc_d3 orc_d3;
+/* the dimensional D3Q19 moment matrix (rows scaled by c^degree) and its inverse */
+void orc_d3_mdim(double c, double* M /*[19*19]*/, double* Minv /*[19*19]*/);
+orc_d3* orc_d3_create(const orc_d3_params* p);
+void orc_d3_destroy(orc_d3* s);
+/* equilibrium populations from macros, arrays [nz][ny][nx] */
+void orc_d3_init(orc_d3* s, const double* rho, const double* ux, const double* uy,
+                 const double* uz);
+void orc_d3_step(orc_d3* s, long nsteps);
+void orc_d3_macros(const orc_d3* s, double* rho, double* ux, double* uy, double* uz);
+void orc_d3_get_state(const orc_d3* s, double* f /*[19][nz][ny][nx]*/);
+
 #ifdef __cplusplus
 }
 #endif
