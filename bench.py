@@ -29,6 +29,8 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_LU = {"fp32": (9 + 9 + 1 + 2) * 4 * 2, "fp64": (9 + 9 + 2) * 8 * 2}
 # heated channel (D2Q9 f + D2Q5 g), read + write
 CHAN_BYTES_PER_LU = {"fp32": (9 + 5) * 4 * 2, "fp64": (9 + 5) * 8 * 2}
+# D3Q19 momentum, read + write
+D3_BYTES_PER_LU = {"fp32": 19 * 4 * 2, "fp64": 19 * 8 * 2}
 # the files whose contents decide the step kernel's machine code
 KERNEL_SOURCES = ("paper_2302_04120_amd/csrc/lbm_kernels.hip", "paper_2302_04120_amd/csrc/lbm_device.h",
                   "paper_2302_04120_amd/csrc/lbm_internal.h", "paper_2302_04120_amd/csrc/build.py")
@@ -105,6 +107,36 @@ def run_channel(nx, ny, steps, warmup, prec):
     return dict(mlups=nodes * steps / wall / 1e6, kernel_ms=kernel_ms,
                 hbm_frac=CHAN_BYTES_PER_LU[prec] * nodes / (kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                 grid="%dx%d" % (nx, ny))
+
+
+def run_d3(n, steps, warmup, prec, mrt=True):
+    """The D3Q19 momentum step (dimensional MRT with Guo forcing) on an n^3
+    periodic box of water with a random velocity field."""
+    import torch
+    from paper_2302_04120_amd import lbm, workloads as WL
+    prm, ini = WL.box3d(n, n, n, seed=0, F=(30.0, 20.0, -10.0), mrt=mrt)
+    L = lbm.Lattice("d3q19", n, n, prec=prec, nz=n)
+    L.set_params(prm)
+    L.init3d(ini["rho"], ini["ux"], ini["uy"], ini["uz"])
+    del ini
+    L.step(warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(L.stream)
+    t0 = time.perf_counter()
+    L.step(steps)
+    e1.record(L.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    if L.reduce(("nonfinite",))["nonfinite"].sum() != 0:
+        raise RuntimeError("non-finite populations after the timed steps")
+    kernel_ms = e0.elapsed_time(e1) / steps
+    nodes = n ** 3
+    gbs = D3_BYTES_PER_LU[prec] * nodes / (kernel_ms * 1e-3) / 1e9
+    return dict(mlups=nodes * steps / wall / 1e6, kernel_ms=kernel_ms, hbm_GBps=gbs,
+                hbm_frac=gbs / HBM_PEAK_GBS, grid="%d^3" % n, collision="mrt" if mrt else "bgk",
+                kernel="k_d3_step<%s>" % ("float" if prec == "fp32" else "double"))
 
 
 def adjoint_cost(steps=20000, ckpt=500, prec="fp32"):
@@ -184,7 +216,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP64 and batch-4 legs")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_phase_step.json"))
-    ap.add_argument("--leg", choices=("channel", "adjoint"), default=None,
+    ap.add_argument("--leg", choices=("channel", "adjoint", "d3q19"), default=None,
                     help="only run one secondary leg and print its figures (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain copy of BYTES (counter calibration)")
@@ -197,6 +229,9 @@ def main():
         return 0
     if args.leg == "adjoint":
         print(json.dumps(adjoint_cost(prec=args.prec)), flush=True)
+        return 0
+    if args.leg == "d3q19":
+        print(json.dumps(run_d3(256, args.steps, args.warmup, args.prec)), flush=True)
         return 0
     if args.gpus != 1:
         print("bench.py measures one GPU only; --gpus %d is not supported" % args.gpus,
@@ -237,6 +272,9 @@ def main():
         extras["paper_config_batch4_mlups"] = r4["nodes"] * 1000 / r4["wall"] / 1e6
         log("bench: heated-channel leg (16384 x 2048)")
         extras["channel_fp32"] = run_channel(16384, 2048, 100, 10, "fp32")
+        log("bench: D3Q19 leg (256^3)")
+        extras["d3q19_fp32"] = run_d3(256, 100, 10, "fp32")
+        extras["d3q19_fp64"] = run_d3(256, 40, 4, "fp64")
         log("bench: adjoint/forward cost leg (C5 channel)")
         extras["adjoint"] = adjoint_cost()
     cpu = None

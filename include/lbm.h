@@ -15,11 +15,16 @@
  *                    dimensional form of Sec. 3, BGK for h_i.
  *   LBM_D1Q2/D1Q3  : 1D thermal BGK with source and wet-node Dirichlet ends
  *                    (Sec. 2.2, App. B).
+ *   LBM_D3Q19      : 3D momentum, BGK or the dimensional MRT of Sec. 3 carried
+ *                    to three dimensions (moment basis of d'Humieres et al.
+ *                    2002, row k scaled by c^order(k)), Guo forcing; each axis
+ *                    periodic or closed by halfway walls (Eq. BB_vel, u_w = 0).
  *
  * Conventions
  *   - Every host number is an SI double.  No lattice units cross this ABI.
- *   - Host arrays are float64, layout [batch][ny][nx] with x fastest, and are
- *     copied before the call returns; the caller keeps ownership.
+ *   - Host arrays are float64, layout [batch][ny][nx] with x fastest
+ *     ([batch][nz][ny][nx] for LBM_D3Q19), and are copied before the call
+ *     returns; the caller keeps ownership.
  *   - Device memory is owned by the caller: lbm_query_bytes gives the size of
  *     the one device buffer (desc.dev_buf) the library works in.  The library
  *     never allocates device memory itself.  The buffer and the HIP stream
@@ -62,12 +67,13 @@ typedef enum {
     LBM_E_UNSUPPORTED = -6  /* combination not implemented                        */
 } lbm_status;
 
-enum { LBM_D1Q2 = 1, LBM_D1Q3 = 2, LBM_D2Q9_D2Q5 = 3, LBM_D2Q9_PHASE = 4 };
+enum { LBM_D1Q2 = 1, LBM_D1Q3 = 2, LBM_D2Q9_D2Q5 = 3, LBM_D2Q9_PHASE = 4, LBM_D3Q19 = 5 };
 enum { LBM_FP32_DEV = 0, LBM_FP64 = 1 };
 /* boundary kinds per side, order x-, x+, y-, y+ */
 enum {
     LBM_BC_PERIODIC = 0,   /* Sec. 2.1, last paragraph                                */
-    LBM_BC_WALL = 1,       /* halfway bounce-back (Eq. BB_vel, u_w = 0); thermal flux Eq. BB_T */
+    LBM_BC_WALL = 1,       /* halfway bounce-back (Eq. BB_vel, u_w = 0); thermal flux Eq. BB_T;
+                              D3Q19: on any axis, both sides of it                        */
     LBM_BC_VEL_INLET = 2,  /* x- only: Eq. BB_vel with the inlet profile; thermal Eq. anti_BB_T */
     LBM_BC_P_OUTLET = 3,   /* x+ only: Eq. anti_BB_vel; thermal first-order extrapolation */
     LBM_BC_DIRICHLET = 4,  /* 1D ends: wet-node fixed temperature (Eq. BCs_1D_advection_diffusion);
@@ -81,7 +87,7 @@ enum { LBM_BGK = 0, LBM_MRT = 1 };
 enum { LBM_FLAG_FLOW = 1, LBM_FLAG_THERMAL = 2, LBM_FLAG_THERMAL_D2Q9 = 4 };
 
 typedef struct {
-    int lattice;            /* LBM_D1Q2 | LBM_D1Q3 | LBM_D2Q9_D2Q5 | LBM_D2Q9_PHASE        */
+    int lattice;            /* LBM_D1Q2 | LBM_D1Q3 | LBM_D2Q9_D2Q5 | LBM_D2Q9_PHASE | LBM_D3Q19 */
     int nx, ny, batch;      /* grid per replica (1D: ny = 1) and number of replicas         */
     int prec;               /* LBM_FP32_DEV | LBM_FP64 (1D: LBM_FP64 only)                  */
     int bc[4];              /* x-, x+, y-, y+ ; see the enum above                           */
@@ -90,6 +96,8 @@ typedef struct {
     void* hip_stream;       /* hipStream_t the library enqueues on (NULL = default stream)  */
     void* dev_buf;          /* caller-owned device memory of at least lbm_query_bytes()     */
     size_t dev_buf_bytes;
+    int nz;                 /* LBM_D3Q19: nodes in z; other lattices: 0 or 1                 */
+    int bc_z[2];            /* LBM_D3Q19: z-, z+ (PERIODIC or WALL, both alike); else 0      */
 } lbm_desc;
 
 typedef struct {
@@ -127,6 +135,11 @@ typedef struct {
        to Fb at every node (Eq. buoyancy_force); needs the thermal field */
     double beta_T;          /* 1/K thermal expansion coefficient (0: no buoyancy)           */
     double gravity[2];      /* m/s^2                                                         */
+    /* 3D (LBM_D3Q19): the z component of the body force; Fb holds x and y.  The
+       rates are those of Sec. 3 with the 3D basis: e at omega_e, eps at omega_eps,
+       the stresses p at 1/tau, q and m at (3/dt)(2/dt - 1/tau)/(3/dt - 1/tau),
+       pi at 1/dt (BGK: every non-conserved moment at 1/tau) */
+    double Fb_z;            /* N/m^3                                                         */
 } lbm_params_si;
 
 /* Size in bytes of the device buffer a context with this description needs.
@@ -147,6 +160,13 @@ LBM_API void lbm_destroy(lbm_ctx* ctx);
  * any relaxation time is not above dt/2, LBM_E_ARG for non-positive dx, dt or
  * densities.  Copies the flux / inlet arrays to the device. */
 LBM_API lbm_status lbm_set_params_SI(lbm_ctx* ctx, const lbm_params_si* p);
+
+/* LBM_D3Q19: the populations at the equilibria of rho (kg/m^3, required) and
+ * ux, uy, uz (m/s, NULL = 0), host float64 [batch][nz][ny][nx].  Resets the
+ * step counter.  Requires lbm_set_params_SI first; LBM_E_ARG for other
+ * lattices. */
+LBM_API lbm_status lbm_init_fields3d(lbm_ctx* ctx, const double* rho, const double* ux,
+                                     const double* uy, const double* uz);
 
 /* Set the populations to the equilibria of the given macroscopic fields
  * (host float64 [batch][ny][nx], SI).  rho_or_p: density (D2Q9_D2Q5, ignored
@@ -195,11 +215,12 @@ LBM_API lbm_status lbm_set_step_fusion(lbm_ctx* ctx, int mode);
  * populations.  mask selects fields; out receives them in bit order, each
  * [batch][ny][nx] float64:
  *   LBM_M_RHO (density), LBM_M_P (PHASE pressure, Pa), LBM_M_UX, LBM_M_UY (m/s),
- *   LBM_M_T (K), LBM_M_PHI, LBM_M_MU (chemical potential, Pa).
+ *   LBM_M_T (K), LBM_M_PHI, LBM_M_MU (chemical potential, Pa), LBM_M_UZ (m/s,
+ *   D3Q19).
  * out_on_device != 0: out is a device pointer (written on the stream,
  * asynchronous); otherwise a host pointer (synchronous). */
 enum { LBM_M_RHO = 1, LBM_M_P = 2, LBM_M_UX = 4, LBM_M_UY = 8, LBM_M_T = 16,
-       LBM_M_PHI = 32, LBM_M_MU = 64 };
+       LBM_M_PHI = 32, LBM_M_MU = 64, LBM_M_UZ = 128 };
 LBM_API lbm_status lbm_macros(lbm_ctx* ctx, unsigned mask, double* out, int out_on_device);
 
 /* FP64 global sums per replica, deterministic (fixed-order two-pass

@@ -39,8 +39,12 @@ lbm_status check_desc(const lbm_desc* d, Layout* L, std::string* err) {
     if (d->batch > 65535 || d->ny > 65535 * 4) return fail(LBM_E_ARG, "grid too large for the launch geometry");
     for (int s = 0; s < 4; ++s)
         if (d->bc[s] < LBM_BC_PERIODIC || d->bc[s] > LBM_BC_SYMMETRY) return fail(LBM_E_ARG, "unknown boundary kind");
+    const bool d3 = d->lattice == LBM_D3Q19;
+    if (d3 ? d->nz < 1 : (d->nz < 0 || d->nz > 1 || d->bc_z[0] != 0 || d->bc_z[1] != 0))
+        return fail(LBM_E_ARG, d3 ? "nz must be >= 1" : "nz and bc_z are for LBM_D3Q19 (0 or 1, and 0)");
+    const long long nz = d3 ? d->nz : 1;
     Layout l;
-    l.N = (long long)d->batch * d->nx * d->ny;
+    l.N = (long long)d->batch * d->nx * d->ny * nz;
     l.P = (l.N + 63) / 64 * 64;
     l.es = d->prec == LBM_FP64 ? 8 : 4;
     switch (d->lattice) {
@@ -84,12 +88,25 @@ lbm_status check_desc(const lbm_desc* d, Layout* L, std::string* err) {
             l.npop = 18 + (d->prec == LBM_FP32_DEV ? 1 : 0);
             break;
         }
+        case LBM_D3Q19: {
+            auto pair_ok = [](int a, int b) {
+                return a == b && (a == LBM_BC_PERIODIC || a == LBM_BC_WALL);
+            };
+            if (!pair_ok(d->bc[0], d->bc[1]) || !pair_ok(d->bc[2], d->bc[3]) ||
+                !pair_ok(d->bc_z[0], d->bc_z[1]))
+                return fail(LBM_E_UNSUPPORTED, "D3Q19: each axis periodic or walls on both sides");
+            if ((d->flags & ~LBM_FLAG_FLOW) != 0) return fail(LBM_E_ARG, "D3Q19 takes no flags but FLOW");
+            l.npop = 19;
+            break;
+        }
         default:
             return fail(LBM_E_ARG, "unknown lattice");
     }
     {
-        const long long tiles = (long long)((d->nx + 63) / 64) * ((d->ny + 3) / 4) * d->batch;
-        if (tiles > (1LL << 30)) return fail(LBM_E_ARG, "grid too large for the launch geometry");
+        // one 256-thread workgroup per 64 x 4 tile (x 4 z planes for D3Q19):
+        // the total thread count must fit the 32-bit launch grid
+        const long long tiles = (long long)((d->nx + 63) / 64) * ((d->ny + 3) / 4) * nz * d->batch;
+        if (tiles >= (1LL << 24)) return fail(LBM_E_ARG, "grid too large for the launch geometry");
     }
     // the PHASE state also carries (phi u) of the previous step: 2 planes
     l.nplanes = l.npop + (d->lattice == LBM_D2Q9_PHASE ? 2 : 0);
@@ -98,7 +115,7 @@ lbm_status check_desc(const lbm_desc* d, Layout* L, std::string* err) {
     l.offA = off; off += popbytes;
     l.offB = off; off += popbytes;
     l.offAux = off; off += align256((size_t)(d->nx + 2 * d->ny) * l.es);
-    l.offStage = off; off += align256(7 * (size_t)l.P * sizeof(double));
+    l.offStage = off; off += align256(8 * (size_t)l.P * sizeof(double));
     l.offPartial = off; off += align256((size_t)d->batch * 4 * kRedBlocks * sizeof(double));
     l.offSmall = off; off += align256((size_t)(3 * d->nx + 64 + 4 * d->batch) * sizeof(double));
     l.total = off;
@@ -155,6 +172,7 @@ hipError_t step_once(lbm_ctx* c) {
     S* a = (S*)bufA(c);
     S* b = (S*)bufB(c);
     const long long P = c->P;
+    if (lat == LBM_D3Q19) return launch_d3_step<S>(c->d3k, a, b, c->stream);
     if (lat == LBM_D2Q9_D2Q5) {
         const bool th = c->ck.thermal;
         return launch_chan_step<S>(c->ck, a, b, th ? a + 9 * P : nullptr, th ? b + 9 * P : nullptr,
@@ -375,8 +393,37 @@ lbm_status lbm_set_params_SI(lbm_ctx* c, const lbm_params_si* p) {
     ChanK ck{};
     PhaseK pk{};
     D1K dk{};
+    D3K d3k{};
     AdjK ak{};
-    if (d.lattice == LBM_D1Q2 || d.lattice == LBM_D1Q3) {
+    if (d.lattice == LBM_D3Q19) {
+        const double cs2 = cc * cc / 3.0;
+        d3k.nx = d.nx; d3k.ny = d.ny; d3k.nz = d.nz; d3k.batch = d.batch; d3k.P = c->P;
+        d3k.bcx = d.bc[0] == LBM_BC_WALL;
+        d3k.bcy = d.bc[2] == LBM_BC_WALL;
+        d3k.bcz = d.bc_z[0] == LBM_BC_WALL;
+        if (!(p->rho_ref > 0)) return set_err(c, LBM_E_ARG, "rho_ref must be positive");
+        if (!(p->nu > 0)) return set_err(c, LBM_E_TAU, "tau not above dt/2 (nu <= 0)");
+        d3k.rho_ref = p->rho_ref;
+        const double tau = p->nu / cs2 + 0.5 * dt;  // Eq. eq_kinematic_viscosity
+        const double wn = dt / tau;
+        if (p->flow_collision == LBM_MRT) {
+            // Sec. 3 in the 3D basis: e, eps free; stresses at 1/tau; q (and the
+            // third-order m) at (3/dt)(2/dt - w)/(3/dt - w); pi at 1/dt -- all times dt
+            const double wq = 3.0 * (2.0 - wn) / (3.0 - wn);
+            const double we = p->omega_e > 0 ? p->omega_e * dt : 1.0;
+            const double wpe = p->omega_eps > 0 ? p->omega_eps * dt : 1.0;
+            const double L[19] = {0, we, wpe, 0, wq, 0, wq, 0, wq, wn, 1.0, wn, 1.0,
+                                  wn, wn, wn, wq, wq, wq};
+            for (int q = 0; q < 19; ++q) d3k.L[q] = L[q];
+        } else {
+            // BGK: every non-conserved moment at dt/tau
+            for (int q = 0; q < 19; ++q) d3k.L[q] = (q == 0 || q == 3 || q == 5 || q == 7) ? 0.0 : wn;
+        }
+        d3k.Ft[0] = p->Fb[0] * dt * dt / dx;
+        d3k.Ft[1] = p->Fb[1] * dt * dt / dx;
+        d3k.Ft[2] = p->Fb_z * dt * dt / dx;
+        d3k.c = cc;
+    } else if (d.lattice == LBM_D1Q2 || d.lattice == LBM_D1Q3) {
         const double cs2 = d.lattice == LBM_D1Q2 ? cc * cc : cc * cc / 3.0;
         if (!(p->rho_cp > 0)) return set_err(c, LBM_E_ARG, "rho_cp must be positive");
         if (!(p->alpha > 0)) return set_err(c, LBM_E_TAU, "tau_T not above dt/2 (alpha <= 0)");
@@ -480,6 +527,7 @@ lbm_status lbm_set_params_SI(lbm_ctx* c, const lbm_params_si* p) {
     c->ck = ck;
     c->pk = pk;
     c->dk = dk;
+    c->d3k = d3k;
     c->ak = ak;
     c->cs2 = cc * cc / 3.0;
     c->has_record = false;
@@ -500,6 +548,9 @@ lbm_status lbm_set_params_SI(lbm_ctx* c, const lbm_params_si* p) {
     h = fnv(h, &ck, sizeof ck);
     h = fnv(h, &pk, sizeof pk);
     h = fnv(h, &dk, sizeof dk);
+    h = fnv(h, &d.nz, sizeof d.nz);
+    h = fnv(h, d.bc_z, sizeof d.bc_z);
+    h = fnv(h, &d3k, sizeof d3k);
     c->hash = h;
     DeviceGuard g(c->device);
     if (d.lattice == LBM_D2Q9_D2Q5) {
@@ -524,6 +575,7 @@ lbm_status lbm_init_fields(lbm_ctx* c, const double* rho_or_p, const double* ux,
     if (d1 && !T) return set_err(c, LBM_E_ARG, "1D lattices need T");
     if (d.lattice == LBM_D2Q9_D2Q5 && !rho_or_p) return set_err(c, LBM_E_ARG, "rho is required");
     if (d.lattice == LBM_D2Q9_PHASE && !phi) return set_err(c, LBM_E_ARG, "phi is required");
+    if (d.lattice == LBM_D3Q19) return set_err(c, LBM_E_ARG, "D3Q19 is initialised by lbm_init_fields3d");
     DeviceGuard g(c->device);
     std::vector<double> host(5 * (size_t)N, 0.0);
     auto put = [&](int slot, const double* src, double dflt) {
@@ -559,6 +611,37 @@ lbm_status lbm_init_fields(lbm_ctx* c, const double* rho_or_p, const double* ux,
             e = launch_phase_init<float>(c->pk, c->staging, (float*)c->popA, (float*)c->popA + 9 * P,
                                          (float*)c->popA + c->npop * P, c->stream);
     }
+    if (e != hipSuccess) return hip_fail(c, e, "init kernel");
+    e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "init");
+    c->t = 0;
+    c->has_state = true;
+    return LBM_OK;
+}
+
+lbm_status lbm_init_fields3d(lbm_ctx* c, const double* rho, const double* ux, const double* uy,
+                             const double* uz) {
+    if (!c) return LBM_E_ARG;
+    if (c->desc.lattice != LBM_D3Q19) return set_err(c, LBM_E_ARG, "lbm_init_fields3d is for LBM_D3Q19");
+    if (!c->has_params) return set_err(c, LBM_E_STATE, "lbm_set_params_SI must come first");
+    if (!rho) return set_err(c, LBM_E_ARG, "rho is required");
+    const long long N = c->N, P = c->P;
+    DeviceGuard g(c->device);
+    std::vector<double> host((size_t)N);
+    const double* src[4] = {rho, ux, uy, uz};
+    const int slot[4] = {0, 2, 3, 7};
+    for (int k = 0; k < 4; ++k) {
+        for (long long n = 0; n < N; ++n) host[n] = src[k] ? src[k][n] : 0.0;
+        hipError_t e = hipMemcpyAsync(c->staging + slot[k] * P, host.data(), N * sizeof(double),
+                                      hipMemcpyHostToDevice, c->stream);
+        // the host vector is reused: wait for each copy
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "field upload");
+    }
+    c->cur = 0;
+    hipError_t e = c->desc.prec == LBM_FP64
+                       ? launch_d3_init<double>(c->d3k, c->staging, (double*)c->popA, c->stream)
+                       : launch_d3_init<float>(c->d3k, c->staging, (float*)c->popA, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "init kernel");
     e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "init");
@@ -607,6 +690,7 @@ lbm_status lbm_macros(lbm_ctx* c, unsigned mask, double* out, int out_on_device)
     unsigned avail;
     if (lat == LBM_D2Q9_D2Q5) avail = LBM_M_RHO | LBM_M_UX | LBM_M_UY | (c->ck.thermal ? LBM_M_T : 0u);
     else if (lat == LBM_D2Q9_PHASE) avail = LBM_M_RHO | LBM_M_P | LBM_M_UX | LBM_M_UY | LBM_M_PHI | LBM_M_MU;
+    else if (lat == LBM_D3Q19) avail = LBM_M_RHO | LBM_M_UX | LBM_M_UY | LBM_M_UZ;
     else avail = LBM_M_T;
     if (mask == 0 || (mask & ~avail)) return set_err(c, LBM_E_ARG, "field not available for this lattice");
     DeviceGuard g(c->device);
@@ -614,7 +698,10 @@ lbm_status lbm_macros(lbm_ctx* c, unsigned mask, double* out, int out_on_device)
     hipError_t e;
     const bool f64 = c->desc.prec == LBM_FP64;
     char* a = bufA(c);
-    if (lat == LBM_D2Q9_D2Q5) {
+    if (lat == LBM_D3Q19) {
+        if (f64) e = launch_d3_macros<double>(c->d3k, (double*)a, c->staging, c->stream);
+        else e = launch_d3_macros<float>(c->d3k, (float*)a, c->staging, c->stream);
+    } else if (lat == LBM_D2Q9_D2Q5) {
         if (f64) e = launch_chan_macros<double>(c->ck, (double*)a, c->ck.thermal ? (double*)a + 9 * P : nullptr, c->staging, c->stream);
         else e = launch_chan_macros<float>(c->ck, (float*)a, c->ck.thermal ? (float*)a + 9 * P : nullptr, c->staging, c->stream);
     } else if (lat == LBM_D2Q9_PHASE) {
@@ -625,7 +712,7 @@ lbm_status lbm_macros(lbm_ctx* c, unsigned mask, double* out, int out_on_device)
     }
     if (e != hipSuccess) return hip_fail(c, e, "macros kernel");
     int k = 0;
-    for (int bit = 0; bit < 7; ++bit) {
+    for (int bit = 0; bit < 8; ++bit) {
         if (!(mask & (1u << bit))) continue;
         e = hipMemcpyAsync(out + (size_t)k * N, c->staging + bit * P, N * sizeof(double),
                            out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream);
@@ -650,10 +737,10 @@ lbm_status lbm_reduce(lbm_ctx* c, unsigned mask, double* out) {
     double* res = c->small + 3 * c->desc.nx + 64;
     hipError_t e;
     if (c->desc.prec == LBM_FP64)
-        e = launch_reduce<double>(lat, c->ck, c->pk, c->dk, (const double*)bufA(c), c->npop,
+        e = launch_reduce<double>(lat, c->ck, c->pk, c->dk, c->d3k, (const double*)bufA(c), c->npop,
                                   c->partial, res, c->stream);
     else
-        e = launch_reduce<float>(lat, c->ck, c->pk, c->dk, (const float*)bufA(c), c->npop,
+        e = launch_reduce<float>(lat, c->ck, c->pk, c->dk, c->d3k, (const float*)bufA(c), c->npop,
                                  c->partial, res, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "reduce kernel");
     std::vector<double> h(4 * (size_t)batch);

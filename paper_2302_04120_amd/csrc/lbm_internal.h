@@ -62,6 +62,18 @@ struct AdjK {
     double qgrad;
 };
 
+// D3Q19 momentum: lattice-normalised like ChanK
+struct D3K {
+    int nx, ny, nz, batch;
+    long long P;
+    int bcx, bcy, bcz;    // per axis: 0 periodic, 1 halfway walls on both sides
+    double rho_ref;
+    double L[19];         // rates * dt in the basis order rho, e, eps, j_x, q_x, j_y, q_y,
+                          // j_z, q_z, 3p_xx, 3pi_xx, p_ww, pi_ww, p_xy, p_yz, p_xz, m_x, m_y, m_z
+    double Ft[3];         // body force * dt^2 / dx
+    double c;             // dx / dt (outputs)
+};
+
 struct D1K {
     int n, q;
     double w_tau;         // dt / tau
@@ -85,7 +97,7 @@ struct lbm_ctx {
     char* popA;
     char* popB;
     char* aux;            // flux (qw), inlet_u (uin), inlet_T (tin): storage type
-    double* staging;      // 7 planes of FP64
+    double* staging;      // 8 planes of FP64
     double* partial;      // reduction partials
     double* small;        // small FP64 results
     int cur;              // 0: A holds the state, 1: B holds it
@@ -95,6 +107,7 @@ struct lbm_ctx {
     lbm::ChanK ck;
     lbm::PhaseK pk;
     lbm::D1K dk;
+    lbm::D3K d3k;
     double flux_amp, flux_omega, dt;
     double k_cond, Dh, dx, rho_cp;
     std::string err;
@@ -145,7 +158,16 @@ hipError_t launch_phase_init(const PhaseK& k, const double* fields, S* h, S* z, 
                              hipStream_t s);
 hipError_t launch_d1_init(const D1K& k, const double* T, double* g, hipStream_t s);
 
-// macros into staging slots [7][P]: rho, p, ux, uy, T, phi, mu
+// D3Q19 (lbm_d3q19.hip)
+long long d3_tiles(const D3K& k);
+template <typename S>
+hipError_t launch_d3_step(const D3K& k, const S* fc, S* fn, hipStream_t s);
+template <typename S>
+hipError_t launch_d3_init(const D3K& k, const double* fields, S* f, hipStream_t s);
+template <typename S>
+hipError_t launch_d3_macros(const D3K& k, const S* f, double* out, hipStream_t s);
+
+// macros into staging slots [8][P]: rho, p, ux, uy, T, phi, mu, uz
 template <typename S>
 hipError_t launch_chan_macros(const ChanK& k, const S* f, const S* g, double* out, hipStream_t s);
 template <typename S>
@@ -157,7 +179,8 @@ hipError_t launch_d1_macros(const D1K& k, const double* g, double* out, long lon
 // per-replica FP64 sums: out[b*4 + f], f = mass, phase, energy, nonfinite
 template <typename S>
 hipError_t launch_reduce(int lattice, const ChanK& ck, const PhaseK& pk, const D1K& dk,
-                         const S* pops, int npop, double* partial, double* out, hipStream_t s);
+                         const D3K& d3, const S* pops, int npop, double* partial, double* out,
+                         hipStream_t s);
 
 // qsi converts the stored scaled flux to W/m^2 (including the time modulation);
 // small receives (mean Nu over x >= x_dev, Tb[nx-1])

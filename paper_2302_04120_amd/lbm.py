@@ -9,7 +9,7 @@ Parameter dicts use SI units and the keys of ``workloads``: dx, dt, rho_ref,
 nu, omega_e, omega_eps, Fx, Fy, flow_mrt, thermal_mrt, T_ref, alpha, rho_cp,
 qdot (K/s), flux, flux_amp, flux_omega, inlet_u, inlet_T, T0, TL, rho_l,
 rho_g, nu_l, nu_g, zeta_l, zeta_g, visc_mode, sigma, W, M, z_mrt, qy_printed,
-normal_eps.
+normal_eps, beta_T, gravity, T_wall; and for D3Q19 F = (Fx, Fy, Fz).
 """
 import ctypes as C
 import os
@@ -21,19 +21,19 @@ LIB_PATH = os.path.join(_HERE, "liblbm.so")
 
 LBM_OK, LBM_E_ARG, LBM_E_TAU, LBM_E_DEVICE, LBM_E_STATE, LBM_E_NONFINITE, LBM_E_UNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6
-LBM_D1Q2, LBM_D1Q3, LBM_D2Q9_D2Q5, LBM_D2Q9_PHASE = 1, 2, 3, 4
+LBM_D1Q2, LBM_D1Q3, LBM_D2Q9_D2Q5, LBM_D2Q9_PHASE, LBM_D3Q19 = 1, 2, 3, 4, 5
 LBM_FP32_DEV, LBM_FP64 = 0, 1
 BC_PERIODIC, BC_WALL, BC_VEL_INLET, BC_P_OUTLET, BC_DIRICHLET, BC_SYMMETRY = 0, 1, 2, 3, 4, 5
 LBM_BGK, LBM_MRT = 0, 1
 FLAG_FLOW, FLAG_THERMAL, FLAG_THERMAL_D2Q9 = 1, 2, 4
-MACRO_BITS = {"rho": 1, "p": 2, "ux": 4, "uy": 8, "T": 16, "phi": 32, "mu": 64}
+MACRO_BITS = {"rho": 1, "p": 2, "ux": 4, "uy": 8, "T": 16, "phi": 32, "mu": 64, "uz": 128}
 REDUCE_BITS = {"mass": 1, "phase": 2, "energy": 4, "nonfinite": 8}
 
 EXPORTS = ("lbm_query_bytes", "lbm_create", "lbm_destroy", "lbm_set_params_SI",
            "lbm_init_fields", "lbm_step", "lbm_macros", "lbm_reduce", "lbm_nusselt",
            "lbm_query_record_bytes", "lbm_record", "lbm_grad", "lbm_time",
            "lbm_save_state", "lbm_load_state", "lbm_last_error", "lbm_set_graph_steps",
-           "lbm_set_step_fusion")
+           "lbm_set_step_fusion", "lbm_init_fields3d")
 
 
 class LbmError(RuntimeError):
@@ -45,7 +45,8 @@ class LbmError(RuntimeError):
 class Desc(C.Structure):
     _fields_ = [("lattice", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("batch", C.c_int),
                 ("prec", C.c_int), ("bc", C.c_int * 4), ("flags", C.c_int),
-                ("hip_stream", C.c_void_p), ("dev_buf", C.c_void_p), ("dev_buf_bytes", C.c_size_t)]
+                ("hip_stream", C.c_void_p), ("dev_buf", C.c_void_p), ("dev_buf_bytes", C.c_size_t),
+                ("nz", C.c_int), ("bc_z", C.c_int * 2)]
 
 
 _dp = C.POINTER(C.c_double)
@@ -67,7 +68,8 @@ class ParamsSI(C.Structure):
                 ("nu_g", C.c_double), ("zeta_l", C.c_double), ("zeta_g", C.c_double),
                 ("visc_mode", C.c_int), ("sigma", C.c_double), ("W", C.c_double),
                 ("mobility", C.c_double), ("z_collision", C.c_int), ("qy_printed", C.c_int),
-                ("normal_eps", C.c_double), ("beta_T", C.c_double), ("gravity", C.c_double * 2)]
+                ("normal_eps", C.c_double), ("beta_T", C.c_double), ("gravity", C.c_double * 2),
+                ("Fb_z", C.c_double)]
 
 
 _lib = None
@@ -88,6 +90,7 @@ def lib():
         L.lbm_destroy.restype = None
         L.lbm_set_params_SI.argtypes = [vp, C.POINTER(ParamsSI)]
         L.lbm_init_fields.argtypes = [vp, _dp, _dp, _dp, _dp, _dp]
+        L.lbm_init_fields3d.argtypes = [vp, _dp, _dp, _dp, _dp]
         L.lbm_step.argtypes = [vp, C.c_int]
         L.lbm_macros.argtypes = [vp, C.c_uint, _dp, C.c_int]
         L.lbm_reduce.argtypes = [vp, C.c_uint, _dp]
@@ -133,7 +136,9 @@ def make_params(prm, nx=None, ny=None):
     P.nu = float(prm.get("nu", 1e-6))
     P.omega_e = float(prm.get("omega_e", 0.0))
     P.omega_eps = float(prm.get("omega_eps", 0.0))
-    P.Fb[0], P.Fb[1] = float(prm.get("Fx", 0.0)), float(prm.get("Fy", 0.0))
+    F = prm.get("F", (prm.get("Fx", 0.0), prm.get("Fy", 0.0), prm.get("Fz", 0.0)))
+    P.Fb[0], P.Fb[1] = float(F[0]), float(F[1])
+    P.Fb_z = float(F[2]) if len(F) > 2 else 0.0
     P.thermal_collision = LBM_MRT if int(prm.get("thermal_mrt", 1)) else LBM_BGK
     P.T_ref = float(prm.get("T_ref", 0.0))
     P.alpha = float(prm.get("alpha", 1e-7))
@@ -167,12 +172,13 @@ def make_params(prm, nx=None, ny=None):
 class Lattice:
     """One lbm_ctx with its torch-owned device buffer and stream.
 
-    lattice: 'd1q2' | 'd1q3' | 'channel' | 'phase'.  bc: 4 kinds (x-, x+, y-, y+).
+    lattice: 'd1q2' | 'd1q3' | 'channel' | 'phase' | 'd3q19'.  bc: 4 kinds (x-, x+,
+    y-, y+), plus bc_z (z-, z+) and nz for 'd3q19'.
     prec: 'fp32' (FP32 deviation storage) | 'fp64'.
     """
 
     def __init__(self, lattice, nx, ny=1, batch=1, prec="fp32", bc=None, flow=True,
-                 thermal=False, device="cuda:0", stream=None):
+                 thermal=False, device="cuda:0", stream=None, nz=1, bc_z=(0, 0)):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("liblbm needs a HIP device (torch.cuda.is_available() is False)")
@@ -181,7 +187,7 @@ class Lattice:
         torch.cuda.set_device(self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         lat = {"d1q2": LBM_D1Q2, "d1q3": LBM_D1Q3, "channel": LBM_D2Q9_D2Q5,
-               "phase": LBM_D2Q9_PHASE}[lattice]
+               "phase": LBM_D2Q9_PHASE, "d3q19": LBM_D3Q19}[lattice]
         if bc is None:
             bc = {"d1q2": (4, 4, 0, 0), "d1q3": (4, 4, 0, 0)}.get(lattice, (0, 0, 0, 0))
         d = Desc()
@@ -189,9 +195,12 @@ class Lattice:
         d.prec = LBM_FP64 if prec == "fp64" else LBM_FP32_DEV
         for i in range(4):
             d.bc[i] = bc[i]
+        if lat == LBM_D3Q19:
+            d.nz = nz
+            d.bc_z[0], d.bc_z[1] = bc_z
         # thermal: False, True / 'd2q5' (D2Q5), or 'd2q9' (D2Q9 thermal set)
-        d.flags = ((FLAG_FLOW if flow else 0) | (FLAG_THERMAL if thermal else 0) |
-                   (FLAG_THERMAL_D2Q9 if thermal == "d2q9" else 0))
+        d.flags = ((FLAG_FLOW if flow and lat != LBM_D3Q19 else 0) |
+                   (FLAG_THERMAL if thermal else 0) | (FLAG_THERMAL_D2Q9 if thermal == "d2q9" else 0))
         d.hip_stream = C.c_void_p(self.stream.cuda_stream)
         nbytes = C.c_size_t()
         self._check(lib().lbm_query_bytes(C.byref(d), C.byref(nbytes)), None)
@@ -204,6 +213,7 @@ class Lattice:
         self.ctx = h
         self._lib = lib()
         self.lattice, self.nx, self.ny, self.batch, self.prec = lattice, nx, ny, batch, prec
+        self.nz = nz if lat == LBM_D3Q19 else 1
         self.bytes = int(nbytes.value)
 
     def _check(self, st, ctx="self"):
@@ -226,6 +236,8 @@ class Lattice:
 
     @property
     def shape(self):
+        if self.lattice == "d3q19":
+            return (self.batch, self.nz, self.ny, self.nx)
         return (self.batch, self.ny, self.nx)
 
     def set_params(self, prm):
@@ -241,6 +253,13 @@ class Lattice:
         for a in arrs:
             assert a is None or a.size == n
         self._check(lib().lbm_init_fields(self.ctx, *(_ptr(a) for a in arrs)))
+
+    def init3d(self, rho, ux=None, uy=None, uz=None):
+        """D3Q19: equilibria of rho, u (arrays broadcast to [batch][nz][ny][nx])."""
+        arrs = [None if a is None else _f64(np.broadcast_to(np.asarray(a, dtype=np.float64),
+                                                            self.shape).reshape(-1))
+                for a in (rho, ux, uy, uz)]
+        self._check(lib().lbm_init_fields3d(self.ctx, *(_ptr(a) for a in arrs)))
 
     def step(self, n=1):
         self._check(lib().lbm_step(self.ctx, int(n)))
@@ -260,7 +279,8 @@ class Lattice:
     def macros(self, fields=None):
         if fields is None:
             fields = {"channel": ("rho", "ux", "uy") + (("T",) if self.desc.flags & FLAG_THERMAL else ()),
-                      "phase": ("rho", "p", "ux", "uy", "phi", "mu")}.get(self.lattice, ("T",))
+                      "phase": ("rho", "p", "ux", "uy", "phi", "mu"),
+                      "d3q19": ("rho", "ux", "uy", "uz")}.get(self.lattice, ("T",))
         mask = 0
         for f in fields:
             mask |= MACRO_BITS[f]

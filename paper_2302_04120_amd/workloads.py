@@ -278,3 +278,26 @@ def paper_channel(case, H=0.5e-3, L=10e-3, T_in=300.0, q_s=4e4, dq=4e4, L_h=1e-3
     ini = dict(rho=np.full((ny, nx), w["rho"]), ux=ux0, uy=np.zeros((ny, nx)),
                T=np.repeat(T_prof[:, None], nx, axis=1))
     return prm, ini
+
+
+def box3d(nx=64, ny=64, nz=64, batch=1, seed=0, dx=1e-4, tau_ratio=0.8, fluid=None,
+          u_frac=0.02, rho_frac=1e-3, F=(0.0, 0.0, 0.0), period=None, mrt=True):
+    """A 3D box of water at 301 K (the fluid of Sec. 4.2) for the D3Q19 model:
+    dt from tau / dt = tau_ratio, a random velocity field of rms u_frac * c and a
+    random density perturbation rho_frac * rho.  ``period`` = (px, py) makes the
+    fields periodic in x and y with that period (a small cell tiled over the
+    box).  Arrays are [batch][nz][ny][nx]."""
+    fl = fluid or WATER_301K
+    nu = fl["nu"]
+    dt = (tau_ratio - 0.5) * dx * dx / (3.0 * nu)
+    c = dx / dt
+    prm = dict(dx=dx, dt=dt, rho_ref=fl["rho"], nu=nu, F=tuple(F), flow_mrt=int(mrt))
+    g = rng(seed)
+    px, py = period if period is not None else (nx, ny)
+    shape = (batch, nz, py, px)
+    rho = fl["rho"] * (1.0 + rho_frac * g.standard_normal(shape))
+    u = [u_frac * c * g.standard_normal(shape) for _ in range(3)]
+    reps = (1, 1, ny // py, nx // px)
+    tile = lambda a: np.tile(a, reps)
+    ini = dict(rho=tile(rho), ux=tile(u[0]), uy=tile(u[1]), uz=tile(u[2]))
+    return prm, ini

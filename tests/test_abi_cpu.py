@@ -131,3 +131,43 @@ def test_channel_description_validation():
     L.lbm_query_bytes(C.byref(d5), C.byref(n5))
     L.lbm_query_bytes(C.byref(d9), C.byref(n9))
     assert n9.value - n5.value == 2 * 4 * 64 * 12 * 4
+
+
+def test_d3q19_description_validation():
+    """D3Q19: nz >= 1, each axis periodic or walls on both sides, no flags but
+    FLOW; the 2D lattices refuse nz > 1 and z boundaries.  The buffer holds
+    two states of 19 planes over nx ny nz batch nodes."""
+    lbm = _lbm()
+    L = lbm.lib()
+    n = C.c_size_t()
+
+    def d3(nz=8, bc=(0, 0, 1, 1), bcz=(1, 1), flags=0, prec=lbm.LBM_FP32_DEV, batch=1):
+        d = _desc(lbm, lattice=lbm.LBM_D3Q19, nx=32, ny=16, bc=bc, flags=flags, prec=prec,
+                  batch=batch)
+        d.nz = nz
+        d.bc_z[0], d.bc_z[1] = bcz
+        return d
+
+    for d, want in [(d3(), lbm.LBM_OK), (d3(bc=(1, 1, 1, 1)), lbm.LBM_OK),
+                    (d3(flags=1), lbm.LBM_OK), (d3(nz=1, bcz=(0, 0)), lbm.LBM_OK),
+                    (d3(nz=0), lbm.LBM_E_ARG), (d3(flags=2), lbm.LBM_E_ARG),
+                    (d3(bc=(2, 3, 1, 1)), lbm.LBM_E_UNSUPPORTED),
+                    (d3(bc=(1, 0, 1, 1)), lbm.LBM_E_UNSUPPORTED),
+                    (d3(bcz=(1, 0)), lbm.LBM_E_UNSUPPORTED),
+                    (d3(bcz=(5, 5)), lbm.LBM_E_UNSUPPORTED)]:
+        assert L.lbm_query_bytes(C.byref(d), C.byref(n)) == want, (d.nz, list(d.bc), list(d.bc_z))
+    N = 32 * 16 * 8
+    assert L.lbm_query_bytes(C.byref(d3()), C.byref(n)) == lbm.LBM_OK
+    assert n.value >= 2 * 19 * N * 4 + 8 * N * 8
+    n2 = C.c_size_t()
+    assert L.lbm_query_bytes(C.byref(d3(batch=3)), C.byref(n2)) == lbm.LBM_OK
+    assert n2.value >= 3 * 2 * 19 * N * 4
+    twod = _desc(lbm)
+    twod.nz = 4
+    assert L.lbm_query_bytes(C.byref(twod), C.byref(n)) == lbm.LBM_E_ARG
+    twod.nz, twod.bc_z[0] = 1, 1
+    assert L.lbm_query_bytes(C.byref(twod), C.byref(n)) == lbm.LBM_E_ARG
+    # a grid whose 64 x 4 tiles do not fit the 32-bit launch grid
+    big = d3(nz=1 << 14)
+    big.nx, big.ny = 4096, 4096
+    assert L.lbm_query_bytes(C.byref(big), C.byref(n)) == lbm.LBM_E_ARG
