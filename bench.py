@@ -31,9 +31,11 @@ BYTES_PER_LU = {"fp32": (9 + 9 + 1 + 2) * 4 * 2, "fp64": (9 + 9 + 2) * 8 * 2}
 CHAN_BYTES_PER_LU = {"fp32": (9 + 5) * 4 * 2, "fp64": (9 + 5) * 8 * 2}
 # D3Q19 momentum, read + write
 D3_BYTES_PER_LU = {"fp32": 19 * 4 * 2, "fp64": 19 * 8 * 2}
-# the files whose contents decide the step kernel's machine code
+# the files whose contents decide the step kernel's machine code and the
+# buffer layout it streams through
 KERNEL_SOURCES = ("paper_2302_04120_amd/csrc/lbm_kernels.hip", "paper_2302_04120_amd/csrc/lbm_device.h",
-                  "paper_2302_04120_amd/csrc/lbm_internal.h", "paper_2302_04120_amd/csrc/build.py")
+                  "paper_2302_04120_amd/csrc/lbm_internal.h", "paper_2302_04120_amd/csrc/build.py",
+                  "paper_2302_04120_amd/csrc/lbm_api.hip")
 
 
 def kernel_source_hash():

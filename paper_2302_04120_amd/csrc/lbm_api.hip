@@ -16,7 +16,7 @@ using namespace lbm;
 namespace {
 
 constexpr uint32_t kMagic = 0x534d424cu;  // "LBMS"
-constexpr uint32_t kVersion = 2;
+constexpr uint32_t kVersion = 3;
 
 struct Layout {
     long long N = 0, P = 0;
@@ -25,6 +25,16 @@ struct Layout {
     size_t offA = 0, offB = 0, offAux = 0, offStage = 0, offPartial = 0;
     size_t offSmall = 0, total = 0;
 };
+
+// Extra elements between population planes (a multiple of 64).  Planes whose
+// spacing is a power of two (a 256^3 box, a batch of 2^k 256^2 cells) start
+// at addresses congruent modulo every power of two up to the plane size, so
+// the 19-38 streams of a step hit the same HBM channels at once; a spacing of
+// 2^k + 64 KiB + 256 B (FP32) spreads them (256^3 D3Q19 step: 27.8 -> 31.0
+// GLUPS; 67 M-node single-step phase kernel: 2.45 -> 2.25 ms).
+#ifndef LBM_PLANE_PAD
+#define LBM_PLANE_PAD 16448
+#endif
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
@@ -45,7 +55,7 @@ lbm_status check_desc(const lbm_desc* d, Layout* L, std::string* err) {
     const long long nz = d3 ? d->nz : 1;
     Layout l;
     l.N = (long long)d->batch * d->nx * d->ny * nz;
-    l.P = (l.N + 63) / 64 * 64;
+    l.P = (l.N + 63) / 64 * 64 + LBM_PLANE_PAD;
     l.es = d->prec == LBM_FP64 ? 8 : 4;
     switch (d->lattice) {
         case LBM_D1Q2:
@@ -987,7 +997,10 @@ struct StateHeader {
 lbm_status lbm_save_state(lbm_ctx* c, void* host, size_t* bytes) {
     if (!c) return LBM_E_ARG;
     if (!bytes) return set_err(c, LBM_E_ARG, "bytes is NULL");
-    const size_t pop = (size_t)c->nplanes * c->P * c->esize;
+    // the blob holds the N node values of each plane, without the padding
+    // between planes (which no kernel writes)
+    const size_t row = (size_t)c->N * c->esize;
+    const size_t pop = (size_t)c->nplanes * row;
     const size_t pu = 0;  // (phi u) is part of the state buffer
     const size_t need = sizeof(StateHeader) + pop + pu;
     if (!host) {
@@ -1001,7 +1014,8 @@ lbm_status lbm_save_state(lbm_ctx* c, void* host, size_t* bytes) {
                    c->desc.prec, c->npop, c->hash, c->t, pop, pu};
     std::memcpy(host, &hd, sizeof hd);
     char* p = (char*)host + sizeof hd;
-    hipError_t e = hipMemcpyAsync(p, bufA(c), pop, hipMemcpyDeviceToHost, c->stream);
+    hipError_t e = hipMemcpy2DAsync(p, row, bufA(c), (size_t)c->P * c->esize, row, c->nplanes,
+                                    hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "save state");
     *bytes = need;
@@ -1015,7 +1029,8 @@ lbm_status lbm_load_state(lbm_ctx* c, const void* host, size_t bytes) {
     if (bytes < sizeof(StateHeader)) return set_err(c, LBM_E_STATE, "state blob truncated");
     StateHeader hd;
     std::memcpy(&hd, host, sizeof hd);
-    const size_t pop = (size_t)c->nplanes * c->P * c->esize;
+    const size_t row = (size_t)c->N * c->esize;
+    const size_t pop = (size_t)c->nplanes * row;
     const size_t pu = 0;  // (phi u) is part of the state buffer
     if (hd.magic != kMagic || hd.version != kVersion) return set_err(c, LBM_E_STATE, "not a state blob");
     if (hd.lattice != c->desc.lattice || hd.nx != c->desc.nx || hd.ny != c->desc.ny ||
@@ -1027,7 +1042,8 @@ lbm_status lbm_load_state(lbm_ctx* c, const void* host, size_t bytes) {
     DeviceGuard g(c->device);
     const char* p = (const char*)host + sizeof hd;
     c->cur = 0;
-    hipError_t e = hipMemcpyAsync(c->popA, p, pop, hipMemcpyHostToDevice, c->stream);
+    hipError_t e = hipMemcpy2DAsync(c->popA, (size_t)c->P * c->esize, p, row, row, c->nplanes,
+                                    hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "load state");
     c->t = hd.t;
