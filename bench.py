@@ -31,6 +31,8 @@ BYTES_PER_LU = {"fp32": (9 + 9 + 1 + 2) * 4 * 2, "fp64": (9 + 9 + 2) * 8 * 2}
 CHAN_BYTES_PER_LU = {"fp32": (9 + 5) * 4 * 2, "fp64": (9 + 5) * 8 * 2}
 # D3Q19 momentum, read + write
 D3_BYTES_PER_LU = {"fp32": 19 * 4 * 2, "fp64": 19 * 8 * 2}
+# 3D two-phase: h 19 (+ low part of h_0 in FP32) + z 19 + (phi u) 3, read + write
+P3_BYTES_PER_LU = {"fp32": (19 + 1 + 19 + 3) * 4 * 2, "fp64": (19 + 19 + 3) * 8 * 2}
 # the files whose contents decide the step kernel's machine code and the
 # buffer layout it streams through
 KERNEL_SOURCES = ("paper_2302_04120_amd/csrc/lbm_kernels.hip", "paper_2302_04120_amd/csrc/lbm_device.h",
@@ -141,6 +143,42 @@ def run_d3(n, steps, warmup, prec, mrt=True):
                 kernel="k_d3_step<%s>" % ("float" if prec == "fp32" else "double"))
 
 
+def run_p3(n, steps, warmup, prec, cell=64, R_nodes=16.0):
+    """The 3D two-phase step (phi pass + step kernel) on an n^3 periodic box
+    filled with air spheres of radius R_nodes in water, one per cell^3 (the
+    air-water system of the Sec. 4.3 property table, density ratio 842)."""
+    import torch
+    from paper_2302_04120_amd import lbm, workloads as WL
+    props = {k: v for k, v in WL.TWO_PHASE_SYSTEMS["air_water_25C"].items()
+             if k not in ("zeta_l", "zeta_g")}
+    prm, ini = WL.bubble3d(n=cell, R_nodes=R_nodes, seed=0, **props)
+    reps = (1, n // cell, n // cell, n // cell)
+    ini = {k: np.tile(v, reps) for k, v in ini.items()}
+    L = lbm.Lattice("phase3d", n, n, prec=prec, nz=n)
+    L.set_params(prm)
+    L.init3d(ini["p"], ini["ux"], ini["uy"], ini["uz"], ini["phi"])
+    del ini
+    L.step(warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(L.stream)
+    t0 = time.perf_counter()
+    L.step(steps)
+    e1.record(L.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    if L.reduce(("nonfinite",))["nonfinite"].sum() != 0:
+        raise RuntimeError("non-finite populations after the timed steps")
+    step_ms = e0.elapsed_time(e1) / steps
+    nodes = n ** 3
+    gbs = P3_BYTES_PER_LU[prec] * nodes / (step_ms * 1e-3) / 1e9
+    return dict(mlups=nodes * steps / wall / 1e6, step_ms=step_ms, state_GBps=gbs,
+                state_frac=gbs / HBM_PEAK_GBS, grid="%d^3" % n,
+                kernels="k_p3_phi<%s> + k_p3_step<%s,false>" % ((("float",) * 2) if prec == "fp32"
+                                                               else (("double",) * 2)))
+
+
 def adjoint_cost(steps=20000, ckpt=500, prec="fp32"):
     """Adjoint/forward cost on the C5 heated channel (1600 x 80 nodes, flow from
     rest): plain forward time, record time (forward + checkpoints) and the
@@ -218,7 +256,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP64 and batch-4 legs")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_phase_step.json"))
-    ap.add_argument("--leg", choices=("channel", "adjoint", "d3q19"), default=None,
+    ap.add_argument("--leg", choices=("channel", "adjoint", "d3q19", "phase3d"), default=None,
                     help="only run one secondary leg and print its figures (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain copy of BYTES (counter calibration)")
@@ -234,6 +272,9 @@ def main():
         return 0
     if args.leg == "d3q19":
         print(json.dumps(run_d3(256, args.steps, args.warmup, args.prec)), flush=True)
+        return 0
+    if args.leg == "phase3d":
+        print(json.dumps(run_p3(256, args.steps, args.warmup, args.prec)), flush=True)
         return 0
     if args.gpus != 1:
         print("bench.py measures one GPU only; --gpus %d is not supported" % args.gpus,
@@ -277,6 +318,8 @@ def main():
         log("bench: D3Q19 leg (256^3)")
         extras["d3q19_fp32"] = run_d3(256, 100, 10, "fp32")
         extras["d3q19_fp64"] = run_d3(256, 40, 4, "fp64")
+        log("bench: 3D two-phase leg (256^3)")
+        extras["phase3d_fp32"] = run_p3(256, 40, 4, "fp32")
         log("bench: adjoint/forward cost leg (C5 channel)")
         extras["adjoint"] = adjoint_cost()
     cpu = None

@@ -19,6 +19,11 @@
  *                    to three dimensions (moment basis of d'Humieres et al.
  *                    2002, row k scaled by c^order(k)), Guo forcing; each axis
  *                    periodic or closed by halfway walls (Eq. BB_vel, u_w = 0).
+ *   LBM_D3Q19_PHASE: the two-phase model of Sec. 2.3 in 3D: h_i and z_i on
+ *                    D3Q19, z_i with the dimensional MRT (rates as in 2D, row by
+ *                    row: 1/dt on rho, e, eps, j, pi; omega_q2 on q and m; 1/tau
+ *                    on the stresses), the isotropic D3Q19 stencils; each axis
+ *                    periodic or walls.
  *
  * Conventions
  *   - Every host number is an SI double.  No lattice units cross this ABI.
@@ -67,13 +72,14 @@ typedef enum {
     LBM_E_UNSUPPORTED = -6  /* combination not implemented                        */
 } lbm_status;
 
-enum { LBM_D1Q2 = 1, LBM_D1Q3 = 2, LBM_D2Q9_D2Q5 = 3, LBM_D2Q9_PHASE = 4, LBM_D3Q19 = 5 };
+enum { LBM_D1Q2 = 1, LBM_D1Q3 = 2, LBM_D2Q9_D2Q5 = 3, LBM_D2Q9_PHASE = 4, LBM_D3Q19 = 5,
+       LBM_D3Q19_PHASE = 6 };
 enum { LBM_FP32_DEV = 0, LBM_FP64 = 1 };
 /* boundary kinds per side, order x-, x+, y-, y+ */
 enum {
     LBM_BC_PERIODIC = 0,   /* Sec. 2.1, last paragraph                                */
     LBM_BC_WALL = 1,       /* halfway bounce-back (Eq. BB_vel, u_w = 0); thermal flux Eq. BB_T;
-                              D3Q19: on any axis, both sides of it                        */
+                              D3Q19 and D3Q19_PHASE: on any axis, both sides of it        */
     LBM_BC_VEL_INLET = 2,  /* x- only: Eq. BB_vel with the inlet profile; thermal Eq. anti_BB_T */
     LBM_BC_P_OUTLET = 3,   /* x+ only: Eq. anti_BB_vel; thermal first-order extrapolation */
     LBM_BC_DIRICHLET = 4,  /* 1D ends: wet-node fixed temperature (Eq. BCs_1D_advection_diffusion);
@@ -87,7 +93,8 @@ enum { LBM_BGK = 0, LBM_MRT = 1 };
 enum { LBM_FLAG_FLOW = 1, LBM_FLAG_THERMAL = 2, LBM_FLAG_THERMAL_D2Q9 = 4 };
 
 typedef struct {
-    int lattice;            /* LBM_D1Q2 | LBM_D1Q3 | LBM_D2Q9_D2Q5 | LBM_D2Q9_PHASE | LBM_D3Q19 */
+    int lattice;            /* LBM_D1Q2 | LBM_D1Q3 | LBM_D2Q9_D2Q5 | LBM_D2Q9_PHASE | LBM_D3Q19
+                               | LBM_D3Q19_PHASE                                            */
     int nx, ny, batch;      /* grid per replica (1D: ny = 1) and number of replicas         */
     int prec;               /* LBM_FP32_DEV | LBM_FP64 (1D: LBM_FP64 only)                  */
     int bc[4];              /* x-, x+, y-, y+ ; see the enum above                           */
@@ -96,8 +103,8 @@ typedef struct {
     void* hip_stream;       /* hipStream_t the library enqueues on (NULL = default stream)  */
     void* dev_buf;          /* caller-owned device memory of at least lbm_query_bytes()     */
     size_t dev_buf_bytes;
-    int nz;                 /* LBM_D3Q19: nodes in z; other lattices: 0 or 1                 */
-    int bc_z[2];            /* LBM_D3Q19: z-, z+ (PERIODIC or WALL, both alike); else 0      */
+    int nz;                 /* 3D lattices: nodes in z; other lattices: 0 or 1               */
+    int bc_z[2];            /* 3D lattices: z-, z+ (PERIODIC or WALL, both alike); else 0    */
 } lbm_desc;
 
 typedef struct {
@@ -135,10 +142,11 @@ typedef struct {
        to Fb at every node (Eq. buoyancy_force); needs the thermal field */
     double beta_T;          /* 1/K thermal expansion coefficient (0: no buoyancy)           */
     double gravity[2];      /* m/s^2                                                         */
-    /* 3D (LBM_D3Q19): the z component of the body force; Fb holds x and y.  The
+    /* 3D lattices: the z component of the body force; Fb holds x and y.  LBM_D3Q19
        rates are those of Sec. 3 with the 3D basis: e at omega_e, eps at omega_eps,
        the stresses p at 1/tau, q and m at (3/dt)(2/dt - 1/tau)/(3/dt - 1/tau),
-       pi at 1/dt (BGK: every non-conserved moment at 1/tau) */
+       pi at 1/dt (BGK: every non-conserved moment at 1/tau).  LBM_D3Q19_PHASE
+       takes the two-phase fields above */
     double Fb_z;            /* N/m^3                                                         */
 } lbm_params_si;
 
@@ -161,12 +169,14 @@ LBM_API void lbm_destroy(lbm_ctx* ctx);
  * densities.  Copies the flux / inlet arrays to the device. */
 LBM_API lbm_status lbm_set_params_SI(lbm_ctx* ctx, const lbm_params_si* p);
 
-/* LBM_D3Q19: the populations at the equilibria of rho (kg/m^3, required) and
- * ux, uy, uz (m/s, NULL = 0), host float64 [batch][nz][ny][nx].  Resets the
- * step counter.  Requires lbm_set_params_SI first; LBM_E_ARG for other
- * lattices. */
-LBM_API lbm_status lbm_init_fields3d(lbm_ctx* ctx, const double* rho, const double* ux,
-                                     const double* uy, const double* uz);
+/* 3D lattices: the populations at the equilibria of the given fields, host
+ * float64 [batch][nz][ny][nx].  LBM_D3Q19: rho_or_p is the density (kg/m^3,
+ * required), phi is ignored.  LBM_D3Q19_PHASE: rho_or_p is the pressure (Pa,
+ * NULL = 0), phi the order parameter (required), and (phi u) of the previous
+ * step is set to phi u.  ux, uy, uz in m/s (NULL = 0).  Resets the step
+ * counter.  Requires lbm_set_params_SI first; LBM_E_ARG for 2D lattices. */
+LBM_API lbm_status lbm_init_fields3d(lbm_ctx* ctx, const double* rho_or_p, const double* ux,
+                                     const double* uy, const double* uz, const double* phi);
 
 /* Set the populations to the equilibria of the given macroscopic fields
  * (host float64 [batch][ny][nx], SI).  rho_or_p: density (D2Q9_D2Q5, ignored
@@ -216,7 +226,7 @@ LBM_API lbm_status lbm_set_step_fusion(lbm_ctx* ctx, int mode);
  * [batch][ny][nx] float64:
  *   LBM_M_RHO (density), LBM_M_P (PHASE pressure, Pa), LBM_M_UX, LBM_M_UY (m/s),
  *   LBM_M_T (K), LBM_M_PHI, LBM_M_MU (chemical potential, Pa), LBM_M_UZ (m/s,
- *   D3Q19).
+ *   3D lattices).  LBM_D3Q19_PHASE offers RHO, P, UX, UY, UZ, PHI and MU.
  * out_on_device != 0: out is a device pointer (written on the stream,
  * asynchronous); otherwise a host pointer (synchronous). */
 enum { LBM_M_RHO = 1, LBM_M_P = 2, LBM_M_UX = 4, LBM_M_UY = 8, LBM_M_T = 16,

@@ -68,6 +68,16 @@ class D3Params(C.Structure):
                 ("omega_eps", C.c_double), ("F", C.c_double * 3)]
 
 
+class P3Params(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("bc_x", C.c_int),
+                ("bc_y", C.c_int), ("bc_z", C.c_int), ("dx", C.c_double), ("dt", C.c_double),
+                ("rho_l", C.c_double), ("rho_g", C.c_double), ("nu_l", C.c_double),
+                ("nu_g", C.c_double), ("zeta_l", C.c_double), ("zeta_g", C.c_double),
+                ("visc_mode", C.c_int), ("sigma", C.c_double), ("W", C.c_double),
+                ("M", C.c_double), ("Fb", C.c_double * 3), ("z_mrt", C.c_int),
+                ("normal_eps", C.c_double)]
+
+
 def _declare(L):
     L.orc_d1_run.restype = C.c_int
     L.orc_d1_run.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, C.c_double, C.c_double,
@@ -108,6 +118,14 @@ def _declare(L):
     L.orc_d3_step.argtypes = [C.c_void_p, C.c_long]
     L.orc_d3_macros.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp]
     L.orc_d3_get_state.argtypes = [C.c_void_p, _dp]
+    L.orc_p3_create.restype = C.c_void_p
+    L.orc_p3_create.argtypes = [C.POINTER(P3Params)]
+    L.orc_p3_destroy.argtypes = [C.c_void_p]
+    L.orc_p3_init.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp, _dp]
+    L.orc_p3_step.argtypes = [C.c_void_p, C.c_long]
+    L.orc_p3_macros.argtypes = [C.c_void_p] + [_dp] * 7
+    L.orc_p3_gradients.argtypes = [C.c_void_p] + [_dp] * 4
+    L.orc_p3_get_state.argtypes = [C.c_void_p, _dp, _dp, _dp]
 
 
 def _f64(a, shape=None):
@@ -353,6 +371,63 @@ class D3:
         f = np.zeros((19,) + self.shape)
         lib().orc_d3_get_state(self.h, _ptr(f))
         return f
+
+
+class Phase3:
+    """3D two-phase model (Sec. 2.3 on D3Q19) on nx x ny x nz, arrays [z][y][x];
+    each axis periodic or closed by halfway walls."""
+
+    def __init__(self, nx, ny, nz, prm, bc_x="periodic", bc_y="periodic", bc_z="periodic"):
+        self.shape = (nz, ny, nx)
+        kinds = {"periodic": 0, "walls": 1}
+        P = P3Params()
+        P.nx, P.ny, P.nz = nx, ny, nz
+        P.bc_x, P.bc_y, P.bc_z = kinds[bc_x], kinds[bc_y], kinds[bc_z]
+        P.dx, P.dt = prm["dx"], prm["dt"]
+        for k in ("rho_l", "rho_g", "nu_l", "nu_g", "sigma", "W", "M"):
+            setattr(P, k, prm[k])
+        P.zeta_l = prm.get("zeta_l", prm["nu_l"] * prm["rho_l"])
+        P.zeta_g = prm.get("zeta_g", prm["nu_g"] * prm["rho_g"])
+        P.visc_mode = int(prm.get("visc_mode", 0))
+        F = prm.get("F", (prm.get("Fx", 0.0), prm.get("Fy", 0.0), prm.get("Fz", 0.0)))
+        for a in range(3):
+            P.Fb[a] = F[a]
+        P.z_mrt = int(prm.get("z_mrt", 1))
+        P.normal_eps = prm.get("normal_eps", 1e-12 / prm["dx"])
+        self.P = P
+        self.h = lib().orc_p3_create(C.byref(P))
+        if not self.h:
+            raise ValueError("orc_p3_create failed")
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().orc_p3_destroy(self.h)
+            self.h = None
+
+    def init(self, phi, p, ux, uy, uz):
+        sh = self.shape
+        lib().orc_p3_init(self.h, *(_ptr(_f64(a, sh)) for a in (phi, p, ux, uy, uz)))
+
+    def step(self, n):
+        lib().orc_p3_step(self.h, int(n))
+
+    def macros(self):
+        keys = ("phi", "rho", "p", "ux", "uy", "uz", "mu")
+        out = {k: np.zeros(self.shape) for k in keys}
+        lib().orc_p3_macros(self.h, *(_ptr(out[k]) for k in keys))
+        return out
+
+    def gradients(self):
+        g = [np.zeros(self.shape) for _ in range(4)]
+        lib().orc_p3_gradients(self.h, *(_ptr(a) for a in g))
+        return g
+
+    def get_state(self):
+        h = np.zeros((19,) + self.shape)
+        z = np.zeros((19,) + self.shape)
+        pu = np.zeros((3,) + self.shape)
+        lib().orc_p3_get_state(self.h, _ptr(h), _ptr(z), _ptr(pu))
+        return h, z, pu
 
 
 # --------------------------------------------------------------------------

@@ -1447,3 +1447,296 @@ void orc_d3_step(orc_d3* s, long nsteps) {
 void orc_d3_get_state(const orc_d3* s, double* f) {
     memcpy(f, s->f, sizeof(double) * 19 * (size_t)s->p.nx * s->p.ny * s->p.nz);
 }
+
+/* ------------------------------------------------------------------------- */
+/* 3D two-phase model: the conservative Allen-Cahn h_i and the pressure-      */
+/* evolution z_i of Sec. 2.3 on D3Q19, z_i with the dimensional MRT of Sec. 3 */
+/* ------------------------------------------------------------------------- */
+/* Reading for 3D (the paper works in 2D): both population sets on D3Q19 with
+ * the weights 1/3, 1/18, 1/36 (w_0 = 1/3 enters Eq. p_Liang and zeq_liang);
+ * gradient and Laplacian are the same isotropic central stencils (Eq.
+ * gradient, Eq. laplacian) over the 18 neighbours; the z_i rates follow the
+ * 2D two-phase choice of Sec. 3 row by row in the d'Humieres basis: 1/dt on
+ * rho, e, eps, j and pi, omega_q2 on q and m, 1/tau on the five stresses. */
+
+struct orc_p3 {
+    orc_p3_params p;
+    double c, cs2, tau_phi, beta, kappa;
+    double Md[361], Mi[361];
+    double *h, *z, *hs, *zs, *hn, *zn, *phiu, *phi;
+};
+
+#define P3IDX(s, i, x, y, z) \
+    (((size_t)(i) * (s)->p.nz + (size_t)(z)) * (s)->p.ny * (s)->p.nx + (size_t)(y) * (s)->p.nx + (x))
+
+orc_p3* orc_p3_create(const orc_p3_params* p) {
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1 || p->dx <= 0 || p->dt <= 0) return NULL;
+    orc_p3* s = (orc_p3*)calloc(1, sizeof(orc_p3));
+    s->p = *p;
+    size_t N = (size_t)p->nx * p->ny * p->nz;
+    s->c = p->dx / p->dt;
+    s->cs2 = s->c * s->c / 3.0;
+    s->tau_phi = p->M / s->cs2 + 0.5 * p->dt; /* M = (tau_phi - dt/2) c_s^2 */
+    s->kappa = 1.5 * p->sigma * p->W;         /* kappa = 3 sigma W / 2 */
+    s->beta = 12.0 * p->sigma / p->W;         /* beta = 12 sigma / W */
+    orc_d3_mdim(s->c, s->Md, s->Mi);
+    s->h = (double*)calloc(19 * N, sizeof(double));
+    s->z = (double*)calloc(19 * N, sizeof(double));
+    s->hs = (double*)calloc(19 * N, sizeof(double));
+    s->zs = (double*)calloc(19 * N, sizeof(double));
+    s->hn = (double*)calloc(19 * N, sizeof(double));
+    s->zn = (double*)calloc(19 * N, sizeof(double));
+    s->phiu = (double*)calloc(3 * N, sizeof(double));
+    s->phi = (double*)calloc(N, sizeof(double));
+    return s;
+}
+
+void orc_p3_destroy(orc_p3* s) {
+    if (!s) return;
+    free(s->h); free(s->z); free(s->hs); free(s->zs); free(s->hn); free(s->zn);
+    free(s->phiu); free(s->phi);
+    free(s);
+}
+
+/* s_i(u) of Eq. s_i_Liang on D3Q19 */
+static double p3_s(int i, const double* u, double c, double cs2) {
+    double cu = c * (EX19[i] * u[0] + EY19[i] * u[1] + EZ19[i] * u[2]);
+    double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    return w19(i) * (cu / cs2 + cu * cu / (2.0 * cs2 * cs2) - uu / (2.0 * cs2));
+}
+
+/* z_i^eq of Eq. zeq_liang on D3Q19 */
+static double p3_zeq(int i, double pr, double rho, const double* u, double c, double cs2) {
+    double base = (i == 0) ? (w19(0) - 1.0) : w19(i);
+    return pr / cs2 * base + rho * p3_s(i, u, c, cs2);
+}
+
+void orc_p3_init(orc_p3* s, const double* phi, const double* pr, const double* ux,
+                 const double* uy, const double* uz) {
+    size_t N = (size_t)s->p.nx * s->p.ny * s->p.nz;
+    for (size_t n = 0; n < N; ++n) {
+        double rho = s->p.rho_g + phi[n] * (s->p.rho_l - s->p.rho_g);
+        double u[3] = {ux[n], uy[n], uz[n]};
+        for (int i = 0; i < 19; ++i) {
+            double cu = s->c * (EX19[i] * u[0] + EY19[i] * u[1] + EZ19[i] * u[2]);
+            s->h[(size_t)i * N + n] = phi[n] * w19(i) * (1.0 + cu / s->cs2); /* Eq. heq_liang */
+            s->z[(size_t)i * N + n] = p3_zeq(i, pr[n], rho, u, s->c, s->cs2);
+        }
+        /* reading: (phi u) at t - dt is taken equal to its initial value */
+        for (int a = 0; a < 3; ++a) s->phiu[a * N + n] = phi[n] * u[a];
+    }
+}
+
+/* phi at a possibly outside node: periodic wrap, or at a wall the value of the
+ * first fluid node (zero normal gradient; the paper gives no wall rule) */
+static double p3_phi_at(const orc_p3* s, int x, int y, int z) {
+    const orc_p3_params* p = &s->p;
+    int nx = p->nx, ny = p->ny, nz = p->nz;
+    if (p->bc_x) x = x < 0 ? 0 : (x >= nx ? nx - 1 : x);
+    else x = (x % nx + nx) % nx;
+    if (p->bc_y) y = y < 0 ? 0 : (y >= ny ? ny - 1 : y);
+    else y = (y % ny + ny) % ny;
+    if (p->bc_z) z = z < 0 ? 0 : (z >= nz ? nz - 1 : z);
+    else z = (z % nz + nz) % nz;
+    return s->phi[((size_t)z * ny + y) * nx + x];
+}
+
+typedef struct {
+    double phi, rho, tau, g[3], lap, n[3], mu, F[3], u[3], p;
+} p3_macro;
+
+/* the node-local quantities of Sec. 2.3 in the model's order (as phase_node) */
+static void p3_node(const orc_p3* s, int x, int y, int zc, p3_macro* m) {
+    const orc_p3_params* p = &s->p;
+    double c = s->c, cs2 = s->cs2, dt = p->dt;
+    size_t N = (size_t)p->nx * p->ny * p->nz;
+    size_t n = ((size_t)zc * p->ny + y) * p->nx + x;
+    double phi = p3_phi_at(s, x, y, zc);
+    m->phi = phi;
+    m->rho = p->rho_g + phi * (p->rho_l - p->rho_g);
+    double nu;
+    if (p->visc_mode == 0) nu = p->nu_g + phi * (p->nu_l - p->nu_g);
+    else nu = (p->zeta_g + phi * (p->zeta_l - p->zeta_g)) / m->rho; /* Sec. 4.4 */
+    m->tau = nu / cs2 + 0.5 * dt;
+    /* isotropic central stencils, Eq. gradient and Eq. laplacian */
+    double g[3] = {0, 0, 0}, lap = 0;
+    for (int i = 1; i < 19; ++i) {
+        double pn = p3_phi_at(s, x + EX19[i], y + EY19[i], zc + EZ19[i]);
+        g[0] += w19(i) * c * EX19[i] * pn / (cs2 * dt);
+        g[1] += w19(i) * c * EY19[i] * pn / (cs2 * dt);
+        g[2] += w19(i) * c * EZ19[i] * pn / (cs2 * dt);
+        lap += 2.0 * w19(i) * (pn - phi) / (cs2 * dt * dt);
+    }
+    for (int a = 0; a < 3; ++a) m->g[a] = g[a];
+    m->lap = lap;
+    double gn = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+    for (int a = 0; a < 3; ++a) m->n[a] = gn > p->normal_eps ? g[a] / gn : 0.0;
+    /* chemical potential, Eq. chemical_potential; F = mu grad phi + F_b */
+    m->mu = 4.0 * s->beta * phi * (phi - 1.0) * (phi - 0.5) - s->kappa * lap;
+    for (int a = 0; a < 3; ++a) m->F[a] = m->mu * g[a] + p->Fb[a];
+    /* velocity first (Eq. u_Liang), then pressure (Eq. p_Liang) */
+    double j[3] = {0, 0, 0}, zsum = 0;
+    for (int i = 0; i < 19; ++i) {
+        double zi = s->z[(size_t)i * N + n];
+        j[0] += c * EX19[i] * zi;
+        j[1] += c * EY19[i] * zi;
+        j[2] += c * EZ19[i] * zi;
+        if (i > 0) zsum += zi;
+    }
+    for (int a = 0; a < 3; ++a) m->u[a] = (j[a] + 0.5 * dt * m->F[a]) / m->rho;
+    double udr = 0;
+    for (int a = 0; a < 3; ++a) udr += m->u[a] * (p->rho_l - p->rho_g) * g[a];
+    m->p = cs2 / (1.0 - w19(0)) * (zsum + 0.5 * dt * udr + m->rho * p3_s(0, m->u, c, cs2));
+}
+
+static void p3_compute_phi(orc_p3* s) {
+    size_t N = (size_t)s->p.nx * s->p.ny * s->p.nz;
+    for (size_t n = 0; n < N; ++n) {
+        double a = 0;
+        for (int i = 0; i < 19; ++i) a += s->h[(size_t)i * N + n]; /* Eq. zero_moment_h */
+        s->phi[n] = a;
+    }
+}
+
+void orc_p3_macros(const orc_p3* s0, double* phi, double* rho, double* pr, double* ux,
+                   double* uy, double* uz, double* mu) {
+    orc_p3* s = (orc_p3*)s0;
+    const orc_p3_params* p = &s->p;
+    p3_compute_phi(s);
+    for (int z = 0; z < p->nz; ++z)
+        for (int y = 0; y < p->ny; ++y)
+            for (int x = 0; x < p->nx; ++x) {
+                p3_macro m;
+                p3_node(s, x, y, z, &m);
+                size_t n = ((size_t)z * p->ny + y) * p->nx + x;
+                if (phi) phi[n] = m.phi;
+                if (rho) rho[n] = m.rho;
+                if (pr) pr[n] = m.p;
+                if (ux) ux[n] = m.u[0];
+                if (uy) uy[n] = m.u[1];
+                if (uz) uz[n] = m.u[2];
+                if (mu) mu[n] = m.mu;
+            }
+}
+
+void orc_p3_gradients(const orc_p3* s0, double* gx, double* gy, double* gz, double* lap) {
+    orc_p3* s = (orc_p3*)s0;
+    const orc_p3_params* p = &s->p;
+    p3_compute_phi(s);
+    for (int z = 0; z < p->nz; ++z)
+        for (int y = 0; y < p->ny; ++y)
+            for (int x = 0; x < p->nx; ++x) {
+                p3_macro m;
+                p3_node(s, x, y, z, &m);
+                size_t n = ((size_t)z * p->ny + y) * p->nx + x;
+                gx[n] = m.g[0];
+                gy[n] = m.g[1];
+                gz[n] = m.g[2];
+                lap[n] = m.lap;
+            }
+}
+
+static void p3_one_step(orc_p3* s) {
+    const orc_p3_params* p = &s->p;
+    int nx = p->nx, ny = p->ny, nz = p->nz;
+    size_t N = (size_t)nx * ny * nz;
+    double c = s->c, cs2 = s->cs2, dt = p->dt;
+    p3_compute_phi(s);
+    for (int zc = 0; zc < nz; ++zc)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                size_t n = ((size_t)zc * ny + y) * nx + x;
+                p3_macro m;
+                p3_node(s, x, y, zc, &m);
+                /* time derivative of (phi u) by explicit Euler */
+                double dpu[3];
+                for (int a = 0; a < 3; ++a) {
+                    double pu = m.phi * m.u[a];
+                    dpu[a] = (pu - s->phiu[a * N + n]) / dt;
+                    s->phiu[a * N + n] = pu;
+                }
+                /* interface populations: BGK with source (Eq.
+                 * eq_lattice_boltzmann_interface, source_term_interface, heq_liang) */
+                double A[3];
+                for (int a = 0; a < 3; ++a)
+                    A[a] = dpu[a] + cs2 * 4.0 * m.phi * (1.0 - m.phi) * m.n[a] / p->W;
+                for (int i = 0; i < 19; ++i) {
+                    double ci[3] = {c * EX19[i], c * EY19[i], c * EZ19[i]};
+                    double cu = ci[0] * m.u[0] + ci[1] * m.u[1] + ci[2] * m.u[2];
+                    double heq = m.phi * w19(i) * (1.0 + cu / cs2);
+                    double cA = ci[0] * A[0] + ci[1] * A[1] + ci[2] * A[2];
+                    double Sh = (1.0 - dt / (2.0 * s->tau_phi)) * w19(i) * cA / cs2;
+                    double hi = s->h[(size_t)i * N + n];
+                    s->hs[(size_t)i * N + n] = hi - dt / s->tau_phi * (hi - heq) + dt * Sh;
+                }
+                /* pressure populations (Eq. eq_lattice_boltzmann_pressure,
+                 * zeq_liang, forcing_term_pressure_evolution) */
+                double drho[3];
+                for (int a = 0; a < 3; ++a) drho[a] = (p->rho_l - p->rho_g) * m.g[a];
+                double zz[19], ze[19], Fz[19];
+                for (int i = 0; i < 19; ++i) {
+                    double ci[3] = {c * EX19[i], c * EY19[i], c * EZ19[i]};
+                    zz[i] = s->z[(size_t)i * N + n];
+                    ze[i] = p3_zeq(i, m.p, m.rho, m.u, c, cs2);
+                    double cF = ci[0] * m.F[0] + ci[1] * m.F[1] + ci[2] * m.F[2];
+                    double cu = ci[0] * m.u[0] + ci[1] * m.u[1] + ci[2] * m.u[2];
+                    double cd = ci[0] * drho[0] + ci[1] * drho[1] + ci[2] * drho[2];
+                    /* (u grad rho):(c_i c_i) = (c_i.u)(c_i.grad rho) */
+                    Fz[i] = w19(i) * (cF / cs2 + cu * cd / cs2);
+                }
+                double out[19];
+                if (p->z_mrt) {
+                    double wn = 1.0 / m.tau, id = 1.0 / dt;
+                    double wq2 = (3.0 / dt) * (2.0 / dt - wn) / (3.0 / dt - wn);
+                    double lam[19] = {id, id, id, id, wq2, id, wq2, id, wq2, wn, id, wn, id,
+                                      wn, wn, wn, wq2, wq2, wq2};
+                    double mm[19], me[19], Fm[19], ms[19];
+                    matvec(19, s->Md, zz, mm);
+                    matvec(19, s->Md, ze, me);
+                    matvec(19, s->Md, Fz, Fm);
+                    for (int k = 0; k < 19; ++k)
+                        ms[k] = mm[k] - dt * lam[k] * (mm[k] - me[k]) +
+                                dt * (1.0 - 0.5 * dt * lam[k]) * Fm[k];
+                    matvec(19, s->Mi, ms, out);
+                } else {
+                    for (int i = 0; i < 19; ++i)
+                        out[i] = zz[i] - dt / m.tau * (zz[i] - ze[i]) +
+                                 dt * (1.0 - dt / (2.0 * m.tau)) * Fz[i];
+                }
+                for (int i = 0; i < 19; ++i) s->zs[(size_t)i * N + n] = out[i];
+            }
+    /* streaming: pull from x - c_i dt; periodic axes wrap, walled axes bounce
+     * back (Eq. BB_vel with u_w = 0 for z_i; no-flux for h_i) */
+    for (int zc = 0; zc < nz; ++zc)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x)
+                for (int i = 0; i < 19; ++i) {
+                    int sx = x - EX19[i], sy = y - EY19[i], sz = zc - EZ19[i];
+                    int out = 0;
+                    if (p->bc_x) out |= (sx < 0 || sx >= nx); else sx = (sx + nx) % nx;
+                    if (p->bc_y) out |= (sy < 0 || sy >= ny); else sy = (sy + ny) % ny;
+                    if (p->bc_z) out |= (sz < 0 || sz >= nz); else sz = (sz + nz) % nz;
+                    size_t dst = P3IDX(s, i, x, y, zc);
+                    if (out) {
+                        s->hn[dst] = s->hs[P3IDX(s, OPP19[i], x, y, zc)];
+                        s->zn[dst] = s->zs[P3IDX(s, OPP19[i], x, y, zc)];
+                    } else {
+                        s->hn[dst] = s->hs[P3IDX(s, i, sx, sy, sz)];
+                        s->zn[dst] = s->zs[P3IDX(s, i, sx, sy, sz)];
+                    }
+                }
+    double* t;
+    t = s->h; s->h = s->hn; s->hn = t;
+    t = s->z; s->z = s->zn; s->zn = t;
+}
+
+void orc_p3_step(orc_p3* s, long nsteps) {
+    for (long k = 0; k < nsteps; ++k) p3_one_step(s);
+}
+
+void orc_p3_get_state(const orc_p3* s, double* h, double* z, double* phiu) {
+    size_t N = (size_t)s->p.nx * s->p.ny * s->p.nz;
+    if (h) memcpy(h, s->h, sizeof(double) * 19 * N);
+    if (z) memcpy(z, s->z, sizeof(double) * 19 * N);
+    if (phiu) memcpy(phiu, s->phiu, sizeof(double) * 3 * N);
+}

@@ -143,6 +143,32 @@ void orc_d3_step(orc_d3* s, long nsteps);
 void orc_d3_macros(const orc_d3* s, double* rho, double* ux, double* uy, double* uz);
 void orc_d3_get_state(const orc_d3* s, double* f /*[19][nz][ny][nx]*/);
 
+/* ---- 3D two-phase model (Sec. 2.3 on D3Q19, z_i with the dimensional MRT) ---- */
+typedef struct {
+    int nx, ny, nz;
+    int bc_x, bc_y, bc_z;   /* per axis: 0 periodic, 1 halfway walls on both sides */
+    double dx, dt;
+    double rho_l, rho_g, nu_l, nu_g, zeta_l, zeta_g;
+    int visc_mode;          /* 0: nu linear in phi; 1: zeta linear, nu = zeta / rho */
+    double sigma, W, M;     /* N/m, m, m^2/s */
+    double Fb[3];           /* N/m^3 */
+    int z_mrt;              /* 0 BGK, 1 dimensional MRT */
+    double normal_eps;      /* 1/m: n = 0 where |grad phi| <= normal_eps */
+} orc_p3_params;
+
+typedef struct orc_p3 orc_p3;
+orc_p3* orc_p3_create(const orc_p3_params* p);
+void orc_p3_destroy(orc_p3* s);
+/* equilibria of phi, pressure p (Pa) and u (m/s), arrays [nz][ny][nx] */
+void orc_p3_init(orc_p3* s, const double* phi, const double* p, const double* ux,
+                 const double* uy, const double* uz);
+void orc_p3_step(orc_p3* s, long nsteps);
+void orc_p3_macros(const orc_p3* s, double* phi, double* rho, double* p, double* ux,
+                   double* uy, double* uz, double* mu);
+void orc_p3_gradients(const orc_p3* s, double* gx, double* gy, double* gz, double* lap);
+void orc_p3_get_state(const orc_p3* s, double* h /*[19]*/, double* z /*[19]*/,
+                      double* phiu /*[3]*/);
+
 #ifdef __cplusplus
 }
 #endif

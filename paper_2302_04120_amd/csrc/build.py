@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "liblbm.so")
-SOURCES = ["lbm_api.hip", "lbm_kernels.hip", "lbm_adjoint.hip", "lbm_d3q19.hip"]
+SOURCES = ["lbm_api.hip", "lbm_kernels.hip", "lbm_adjoint.hip", "lbm_d3q19.hip", "lbm_phase3d.hip"]
 
 
 def hipcc():

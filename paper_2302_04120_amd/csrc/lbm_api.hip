@@ -22,7 +22,7 @@ struct Layout {
     long long N = 0, P = 0;
     int npop = 0, nplanes = 0;
     size_t es = 0;
-    size_t offA = 0, offB = 0, offAux = 0, offStage = 0, offPartial = 0;
+    size_t offA = 0, offB = 0, offAux = 0, offStage = 0, offPartial = 0, offPhi = 0;
     size_t offSmall = 0, total = 0;
 };
 
@@ -49,7 +49,7 @@ lbm_status check_desc(const lbm_desc* d, Layout* L, std::string* err) {
     if (d->batch > 65535 || d->ny > 65535 * 4) return fail(LBM_E_ARG, "grid too large for the launch geometry");
     for (int s = 0; s < 4; ++s)
         if (d->bc[s] < LBM_BC_PERIODIC || d->bc[s] > LBM_BC_SYMMETRY) return fail(LBM_E_ARG, "unknown boundary kind");
-    const bool d3 = d->lattice == LBM_D3Q19;
+    const bool d3 = d->lattice == LBM_D3Q19 || d->lattice == LBM_D3Q19_PHASE;
     if (d3 ? d->nz < 1 : (d->nz < 0 || d->nz > 1 || d->bc_z[0] != 0 || d->bc_z[1] != 0))
         return fail(LBM_E_ARG, d3 ? "nz must be >= 1" : "nz and bc_z are for LBM_D3Q19 (0 or 1, and 0)");
     const long long nz = d3 ? d->nz : 1;
@@ -109,6 +109,17 @@ lbm_status check_desc(const lbm_desc* d, Layout* L, std::string* err) {
             l.npop = 19;
             break;
         }
+        case LBM_D3Q19_PHASE: {
+            auto pair_ok = [](int a, int b) {
+                return a == b && (a == LBM_BC_PERIODIC || a == LBM_BC_WALL);
+            };
+            if (!pair_ok(d->bc[0], d->bc[1]) || !pair_ok(d->bc[2], d->bc[3]) ||
+                !pair_ok(d->bc_z[0], d->bc_z[1]))
+                return fail(LBM_E_UNSUPPORTED, "D3Q19_PHASE: each axis periodic or walls on both sides");
+            if (d->flags != 0) return fail(LBM_E_ARG, "D3Q19_PHASE takes no flags");
+            l.npop = 38 + (d->prec == LBM_FP32_DEV ? 1 : 0);
+            break;
+        }
         default:
             return fail(LBM_E_ARG, "unknown lattice");
     }
@@ -118,8 +129,8 @@ lbm_status check_desc(const lbm_desc* d, Layout* L, std::string* err) {
         const long long tiles = (long long)((d->nx + 63) / 64) * ((d->ny + 3) / 4) * nz * d->batch;
         if (tiles >= (1LL << 24)) return fail(LBM_E_ARG, "grid too large for the launch geometry");
     }
-    // the PHASE state also carries (phi u) of the previous step: 2 planes
-    l.nplanes = l.npop + (d->lattice == LBM_D2Q9_PHASE ? 2 : 0);
+    // the PHASE states also carry (phi u) of the previous step: 2 or 3 planes
+    l.nplanes = l.npop + (d->lattice == LBM_D2Q9_PHASE ? 2 : (d->lattice == LBM_D3Q19_PHASE ? 3 : 0));
     size_t off = 0;
     const size_t popbytes = align256((size_t)l.nplanes * l.P * l.es);
     l.offA = off; off += popbytes;
@@ -128,6 +139,8 @@ lbm_status check_desc(const lbm_desc* d, Layout* L, std::string* err) {
     l.offStage = off; off += align256(8 * (size_t)l.P * sizeof(double));
     l.offPartial = off; off += align256((size_t)d->batch * 4 * kRedBlocks * sizeof(double));
     l.offSmall = off; off += align256((size_t)(3 * d->nx + 64 + 4 * d->batch) * sizeof(double));
+    // D3Q19_PHASE: phi of the current state, recomputed before every step
+    l.offPhi = off; off += d->lattice == LBM_D3Q19_PHASE ? align256((size_t)l.P * l.es) : 0;
     l.total = off;
     *L = l;
     return LBM_OK;
@@ -183,6 +196,7 @@ hipError_t step_once(lbm_ctx* c) {
     S* b = (S*)bufB(c);
     const long long P = c->P;
     if (lat == LBM_D3Q19) return launch_d3_step<S>(c->d3k, a, b, c->stream);
+    if (lat == LBM_D3Q19_PHASE) return launch_p3_step<S>(c->p3k, a, b, (S*)c->phi3, c->stream);
     if (lat == LBM_D2Q9_D2Q5) {
         const bool th = c->ck.thermal;
         return launch_chan_step<S>(c->ck, a, b, th ? a + 9 * P : nullptr, th ? b + 9 * P : nullptr,
@@ -346,6 +360,7 @@ lbm_status lbm_create(const lbm_desc* desc, lbm_ctx** out) {
     c->staging = (double*)(base + L.offStage);
     c->partial = (double*)(base + L.offPartial);
     c->small = (double*)(base + L.offSmall);
+    c->phi3 = base + L.offPhi;
     c->cur = 0;
     c->t = 0;
     c->has_params = c->has_state = false;
@@ -404,8 +419,43 @@ lbm_status lbm_set_params_SI(lbm_ctx* c, const lbm_params_si* p) {
     PhaseK pk{};
     D1K dk{};
     D3K d3k{};
+    P3K p3k{};
     AdjK ak{};
-    if (d.lattice == LBM_D3Q19) {
+    if (d.lattice == LBM_D3Q19_PHASE) {
+        const double cs2 = cc * cc / 3.0;
+        p3k.nx = d.nx; p3k.ny = d.ny; p3k.nz = d.nz; p3k.batch = d.batch; p3k.P = c->P;
+        p3k.bcx = d.bc[0] == LBM_BC_WALL;
+        p3k.bcy = d.bc[2] == LBM_BC_WALL;
+        p3k.bcz = d.bc_z[0] == LBM_BC_WALL;
+        p3k.z_mrt = p->z_collision == LBM_MRT;
+        p3k.visc_mode = p->visc_mode ? 1 : 0;
+        if (!(p->rho_l > 0) || !(p->rho_g > 0)) return set_err(c, LBM_E_ARG, "densities must be positive");
+        p3k.rho_l = p->rho_l;
+        p3k.rho_g = p->rho_g;
+        const double sc = dt / (dx * dx);
+        if (p3k.visc_mode == 0) {
+            if (!(p->nu_l > 0) || !(p->nu_g > 0)) return set_err(c, LBM_E_TAU, "tau not above dt/2 (nu <= 0)");
+        } else {
+            if (!(p->zeta_l > 0) || !(p->zeta_g > 0)) return set_err(c, LBM_E_TAU, "tau not above dt/2 (zeta <= 0)");
+        }
+        p3k.nuh_l = p->nu_l * sc; p3k.nuh_g = p->nu_g * sc;
+        p3k.zh_l = p->zeta_l * sc; p3k.zh_g = p->zeta_g * sc;
+        if (!(p->mobility > 0)) return set_err(c, LBM_E_TAU, "tau_phi not above dt/2 (mobility <= 0)");
+        if (!(p->W > 0)) return set_err(c, LBM_E_ARG, "interface width must be positive");
+        p3k.w_phi = dt / (p->mobility / cs2 + 0.5 * dt);  // M = (tau_phi - dt/2) c_s^2
+        p3k.beta = 12.0 * p->sigma / p->W;
+        p3k.kap6 = 6.0 * 1.5 * p->sigma * p->W / (dx * dx);  // 6 kappa / dx^2, kappa = 3 sigma W / 2
+        p3k.fs_scale = 3.0 * dt * dt / (dx * dx);
+        p3k.Fbt[0] = p->Fb[0] * dt * dt / dx;
+        p3k.Fbt[1] = p->Fb[1] * dt * dt / dx;
+        p3k.Fbt[2] = p->Fb_z * dt * dt / dx;
+        p3k.dxW = dx / p->W;
+        const double eps = p->normal_eps > 0 ? p->normal_eps
+                                             : (d.prec == LBM_FP64 ? 1e-12 : 1e-6) / dx;
+        p3k.Geps = eps * dx / 3.0;
+        p3k.c = cc;
+        p3k.cs2 = cs2;
+    } else if (d.lattice == LBM_D3Q19) {
         const double cs2 = cc * cc / 3.0;
         d3k.nx = d.nx; d3k.ny = d.ny; d3k.nz = d.nz; d3k.batch = d.batch; d3k.P = c->P;
         d3k.bcx = d.bc[0] == LBM_BC_WALL;
@@ -538,6 +588,7 @@ lbm_status lbm_set_params_SI(lbm_ctx* c, const lbm_params_si* p) {
     c->pk = pk;
     c->dk = dk;
     c->d3k = d3k;
+    c->p3k = p3k;
     c->ak = ak;
     c->cs2 = cc * cc / 3.0;
     c->has_record = false;
@@ -561,6 +612,7 @@ lbm_status lbm_set_params_SI(lbm_ctx* c, const lbm_params_si* p) {
     h = fnv(h, &d.nz, sizeof d.nz);
     h = fnv(h, d.bc_z, sizeof d.bc_z);
     h = fnv(h, &d3k, sizeof d3k);
+    h = fnv(h, &p3k, sizeof p3k);
     c->hash = h;
     DeviceGuard g(c->device);
     if (d.lattice == LBM_D2Q9_D2Q5) {
@@ -585,7 +637,8 @@ lbm_status lbm_init_fields(lbm_ctx* c, const double* rho_or_p, const double* ux,
     if (d1 && !T) return set_err(c, LBM_E_ARG, "1D lattices need T");
     if (d.lattice == LBM_D2Q9_D2Q5 && !rho_or_p) return set_err(c, LBM_E_ARG, "rho is required");
     if (d.lattice == LBM_D2Q9_PHASE && !phi) return set_err(c, LBM_E_ARG, "phi is required");
-    if (d.lattice == LBM_D3Q19) return set_err(c, LBM_E_ARG, "D3Q19 is initialised by lbm_init_fields3d");
+    if (d.lattice == LBM_D3Q19 || d.lattice == LBM_D3Q19_PHASE)
+        return set_err(c, LBM_E_ARG, "3D lattices are initialised by lbm_init_fields3d");
     DeviceGuard g(c->device);
     std::vector<double> host(5 * (size_t)N, 0.0);
     auto put = [&](int slot, const double* src, double dflt) {
@@ -629,18 +682,22 @@ lbm_status lbm_init_fields(lbm_ctx* c, const double* rho_or_p, const double* ux,
     return LBM_OK;
 }
 
-lbm_status lbm_init_fields3d(lbm_ctx* c, const double* rho, const double* ux, const double* uy,
-                             const double* uz) {
+lbm_status lbm_init_fields3d(lbm_ctx* c, const double* rho_or_p, const double* ux,
+                             const double* uy, const double* uz, const double* phi) {
     if (!c) return LBM_E_ARG;
-    if (c->desc.lattice != LBM_D3Q19) return set_err(c, LBM_E_ARG, "lbm_init_fields3d is for LBM_D3Q19");
+    const int lat = c->desc.lattice;
+    if (lat != LBM_D3Q19 && lat != LBM_D3Q19_PHASE)
+        return set_err(c, LBM_E_ARG, "lbm_init_fields3d is for the 3D lattices");
     if (!c->has_params) return set_err(c, LBM_E_STATE, "lbm_set_params_SI must come first");
-    if (!rho) return set_err(c, LBM_E_ARG, "rho is required");
+    if (lat == LBM_D3Q19 && !rho_or_p) return set_err(c, LBM_E_ARG, "rho is required");
+    if (lat == LBM_D3Q19_PHASE && !phi) return set_err(c, LBM_E_ARG, "phi is required");
     const long long N = c->N, P = c->P;
     DeviceGuard g(c->device);
     std::vector<double> host((size_t)N);
-    const double* src[4] = {rho, ux, uy, uz};
-    const int slot[4] = {0, 2, 3, 7};
-    for (int k = 0; k < 4; ++k) {
+    // staging slots: rho 0 or p 1, ux 2, uy 3, phi 5, uz 7
+    const double* src[5] = {rho_or_p, ux, uy, uz, phi};
+    const int slot[5] = {lat == LBM_D3Q19 ? 0 : 1, 2, 3, 7, 5};
+    for (int k = 0; k < 5; ++k) {
         for (long long n = 0; n < N; ++n) host[n] = src[k] ? src[k][n] : 0.0;
         hipError_t e = hipMemcpyAsync(c->staging + slot[k] * P, host.data(), N * sizeof(double),
                                       hipMemcpyHostToDevice, c->stream);
@@ -649,9 +706,14 @@ lbm_status lbm_init_fields3d(lbm_ctx* c, const double* rho, const double* ux, co
         if (e != hipSuccess) return hip_fail(c, e, "field upload");
     }
     c->cur = 0;
-    hipError_t e = c->desc.prec == LBM_FP64
-                       ? launch_d3_init<double>(c->d3k, c->staging, (double*)c->popA, c->stream)
-                       : launch_d3_init<float>(c->d3k, c->staging, (float*)c->popA, c->stream);
+    const bool f64 = c->desc.prec == LBM_FP64;
+    hipError_t e;
+    if (lat == LBM_D3Q19)
+        e = f64 ? launch_d3_init<double>(c->d3k, c->staging, (double*)c->popA, c->stream)
+                : launch_d3_init<float>(c->d3k, c->staging, (float*)c->popA, c->stream);
+    else
+        e = f64 ? launch_p3_init<double>(c->p3k, c->staging, (double*)c->popA, c->stream)
+                : launch_p3_init<float>(c->p3k, c->staging, (float*)c->popA, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "init kernel");
     e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "init");
@@ -701,6 +763,8 @@ lbm_status lbm_macros(lbm_ctx* c, unsigned mask, double* out, int out_on_device)
     if (lat == LBM_D2Q9_D2Q5) avail = LBM_M_RHO | LBM_M_UX | LBM_M_UY | (c->ck.thermal ? LBM_M_T : 0u);
     else if (lat == LBM_D2Q9_PHASE) avail = LBM_M_RHO | LBM_M_P | LBM_M_UX | LBM_M_UY | LBM_M_PHI | LBM_M_MU;
     else if (lat == LBM_D3Q19) avail = LBM_M_RHO | LBM_M_UX | LBM_M_UY | LBM_M_UZ;
+    else if (lat == LBM_D3Q19_PHASE)
+        avail = LBM_M_RHO | LBM_M_P | LBM_M_UX | LBM_M_UY | LBM_M_UZ | LBM_M_PHI | LBM_M_MU;
     else avail = LBM_M_T;
     if (mask == 0 || (mask & ~avail)) return set_err(c, LBM_E_ARG, "field not available for this lattice");
     DeviceGuard g(c->device);
@@ -711,6 +775,9 @@ lbm_status lbm_macros(lbm_ctx* c, unsigned mask, double* out, int out_on_device)
     if (lat == LBM_D3Q19) {
         if (f64) e = launch_d3_macros<double>(c->d3k, (double*)a, c->staging, c->stream);
         else e = launch_d3_macros<float>(c->d3k, (float*)a, c->staging, c->stream);
+    } else if (lat == LBM_D3Q19_PHASE) {
+        if (f64) e = launch_p3_macros<double>(c->p3k, (double*)a, (double*)c->phi3, c->staging, c->stream);
+        else e = launch_p3_macros<float>(c->p3k, (float*)a, (float*)c->phi3, c->staging, c->stream);
     } else if (lat == LBM_D2Q9_D2Q5) {
         if (f64) e = launch_chan_macros<double>(c->ck, (double*)a, c->ck.thermal ? (double*)a + 9 * P : nullptr, c->staging, c->stream);
         else e = launch_chan_macros<float>(c->ck, (float*)a, c->ck.thermal ? (float*)a + 9 * P : nullptr, c->staging, c->stream);
@@ -747,10 +814,10 @@ lbm_status lbm_reduce(lbm_ctx* c, unsigned mask, double* out) {
     double* res = c->small + 3 * c->desc.nx + 64;
     hipError_t e;
     if (c->desc.prec == LBM_FP64)
-        e = launch_reduce<double>(lat, c->ck, c->pk, c->dk, c->d3k, (const double*)bufA(c), c->npop,
+        e = launch_reduce<double>(lat, c->ck, c->pk, c->dk, c->d3k, c->p3k, (const double*)bufA(c), c->npop,
                                   c->partial, res, c->stream);
     else
-        e = launch_reduce<float>(lat, c->ck, c->pk, c->dk, c->d3k, (const float*)bufA(c), c->npop,
+        e = launch_reduce<float>(lat, c->ck, c->pk, c->dk, c->d3k, c->p3k, (const float*)bufA(c), c->npop,
                                  c->partial, res, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "reduce kernel");
     std::vector<double> h(4 * (size_t)batch);

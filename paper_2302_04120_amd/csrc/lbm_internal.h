@@ -74,6 +74,25 @@ struct D3K {
     double c;             // dx / dt (outputs)
 };
 
+// 3D two-phase model (h_i and z_i on D3Q19), lattice-normalised like PhaseK
+struct P3K {
+    int nx, ny, nz, batch;
+    long long P;
+    int bcx, bcy, bcz;    // per axis: 0 periodic, 1 halfway walls on both sides
+    int z_mrt, visc_mode;
+    double rho_l, rho_g;
+    double nuh_l, nuh_g;  // nu dt / dx^2 (visc_mode 0)
+    double zh_l, zh_g;    // zeta dt / dx^2 (visc_mode 1)
+    double w_phi;         // dt / tau_phi
+    double beta;          // 12 sigma / W (Pa)
+    double kap6;          // 6 kappa / dx^2 (Pa)
+    double fs_scale;      // 3 dt^2 / dx^2
+    double Fbt[3];        // body force * dt^2 / dx
+    double dxW;           // dx / W
+    double Geps;          // |G| threshold for n = 0
+    double c, cs2;        // outputs
+};
+
 struct D1K {
     int n, q;
     double w_tau;         // dt / tau
@@ -108,6 +127,8 @@ struct lbm_ctx {
     lbm::PhaseK pk;
     lbm::D1K dk;
     lbm::D3K d3k;
+    lbm::P3K p3k;
+    char* phi3;           // D3Q19_PHASE: phi of the current state (one plane, storage type)
     double flux_amp, flux_omega, dt;
     double k_cond, Dh, dx, rho_cp;
     std::string err;
@@ -167,6 +188,17 @@ hipError_t launch_d3_init(const D3K& k, const double* fields, S* f, hipStream_t 
 template <typename S>
 hipError_t launch_d3_macros(const D3K& k, const S* f, double* out, hipStream_t s);
 
+// 3D two-phase (lbm_phase3d.hip).  A step is two launches: phi of the stored
+// state into one plane, then the step kernel, which reads phi through an LDS
+// tile with a one-node halo.  Buffer planes: h 0-18, z 19-37, the low part of
+// h_0 at 38 (FP32 only), then (phi u) of the previous step (3 planes).
+template <typename S>
+hipError_t launch_p3_step(const P3K& k, const S* a, S* b, S* phi, hipStream_t s);
+template <typename S>
+hipError_t launch_p3_init(const P3K& k, const double* fields, S* a, hipStream_t s);
+template <typename S>
+hipError_t launch_p3_macros(const P3K& k, const S* a, S* phi, double* out, hipStream_t s);
+
 // macros into staging slots [8][P]: rho, p, ux, uy, T, phi, mu, uz
 template <typename S>
 hipError_t launch_chan_macros(const ChanK& k, const S* f, const S* g, double* out, hipStream_t s);
@@ -179,8 +211,8 @@ hipError_t launch_d1_macros(const D1K& k, const double* g, double* out, long lon
 // per-replica FP64 sums: out[b*4 + f], f = mass, phase, energy, nonfinite
 template <typename S>
 hipError_t launch_reduce(int lattice, const ChanK& ck, const PhaseK& pk, const D1K& dk,
-                         const D3K& d3, const S* pops, int npop, double* partial, double* out,
-                         hipStream_t s);
+                         const D3K& d3, const P3K& p3, const S* pops, int npop, double* partial,
+                         double* out, hipStream_t s);
 
 // qsi converts the stored scaled flux to W/m^2 (including the time modulation);
 // small receives (mean Nu over x >= x_dev, Tb[nx-1])

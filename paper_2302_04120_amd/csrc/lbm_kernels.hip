@@ -967,13 +967,14 @@ __device__ void block_sums(double (&v)[NF], double* dst, int stride) {
 // pass 1: grid (kRedBlocks, batch), 256 threads; partial[(b*4 + f) * kRedBlocks + blk]
 template <typename S>
 __global__ __launch_bounds__(256) void k_reduce1(int lattice, ChanK ck, PhaseK pk, D1K dk,
-                                                 D3K d3, const S* __restrict__ pops, int npop,
-                                                 double* __restrict__ partial) {
+                                                 D3K d3, P3K p3, const S* __restrict__ pops,
+                                                 int npop, double* __restrict__ partial) {
     const int b = blockIdx.y;
     long long M, P;
     if (lattice == LBM_D2Q9_PHASE) { M = (long long)pk.nx * pk.ny; P = pk.P; }
     else if (lattice == LBM_D2Q9_D2Q5) { M = (long long)ck.nx * ck.ny; P = ck.P; }
     else if (lattice == LBM_D3Q19) { M = (long long)d3.nx * d3.ny * d3.nz; P = d3.P; }
+    else if (lattice == LBM_D3Q19_PHASE) { M = (long long)p3.nx * p3.ny * p3.nz; P = p3.P; }
     else { M = dk.n; P = dk.n; }
     const long long base = b * M;
     double v[4] = {0, 0, 0, 0};
@@ -991,6 +992,12 @@ __global__ __launch_bounds__(256) void k_reduce1(int lattice, ChanK ck, PhaseK p
             if (std::is_same<S, float>::value) a += double(pops[18 * P + n]);
             v[1] += a;
             v[0] += pk.rho_g + a * (pk.rho_l - pk.rho_g);
+        } else if (lattice == LBM_D3Q19_PHASE) {
+            double a = 0;
+            for (int i = 0; i < 19; ++i) a += double(pops[i * P + n]);
+            if (std::is_same<S, float>::value) a += double(pops[38 * P + n]);
+            v[1] += a;
+            v[0] += p3.rho_g + a * (p3.rho_l - p3.rho_g);
         } else if (lattice == LBM_D3Q19) {
             double a = 0;
             for (int i = 0; i < 19; ++i) a += double(pops[i * P + n]);
@@ -1172,14 +1179,15 @@ hipError_t launch_d1_macros(const D1K& k, const double* g, double* out, long lon
 
 template <typename S>
 hipError_t launch_reduce(int lattice, const ChanK& ck, const PhaseK& pk, const D1K& dk,
-                         const D3K& d3, const S* pops, int npop, double* partial, double* out,
-                         hipStream_t s) {
-    const int batch = lattice == LBM_D2Q9_PHASE ? pk.batch
-                      : lattice == LBM_D2Q9_D2Q5 ? ck.batch
-                      : lattice == LBM_D3Q19     ? d3.batch
-                                                 : 1;
+                         const D3K& d3, const P3K& p3, const S* pops, int npop, double* partial,
+                         double* out, hipStream_t s) {
+    const int batch = lattice == LBM_D2Q9_PHASE    ? pk.batch
+                      : lattice == LBM_D2Q9_D2Q5    ? ck.batch
+                      : lattice == LBM_D3Q19        ? d3.batch
+                      : lattice == LBM_D3Q19_PHASE  ? p3.batch
+                                                    : 1;
     hipLaunchKernelGGL(k_reduce1<S>, dim3(kRedBlocks, batch), dim3(256), 0, s, lattice, ck, pk,
-                       dk, d3, pops, npop, partial);
+                       dk, d3, p3, pops, npop, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_reduce2, dim3((batch * 4 + 63) / 64), dim3(64), 0, s, partial, out,
@@ -1213,8 +1221,8 @@ hipError_t launch_nusselt(const ChanK& k, const S* f, const S* g, const S* qw, d
     template hipError_t launch_phase_macros<S>(const PhaseK&, const S*, const S*, double*,       \
                                                hipStream_t);                                      \
     template hipError_t launch_reduce<S>(int, const ChanK&, const PhaseK&, const D1K&,           \
-                                         const D3K&, const S*, int, double*, double*,             \
-                                         hipStream_t);                                            \
+                                         const D3K&, const P3K&, const S*, int, double*,          \
+                                         double*, hipStream_t);                                   \
     template hipError_t launch_nusselt<S>(const ChanK&, const S*, const S*, const S*, double,    \
                                           double, double, double, int, double*, double*, double*, \
                                           double*, hipStream_t);

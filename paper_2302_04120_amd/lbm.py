@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_HERE, "liblbm.so")
 
 LBM_OK, LBM_E_ARG, LBM_E_TAU, LBM_E_DEVICE, LBM_E_STATE, LBM_E_NONFINITE, LBM_E_UNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6
-LBM_D1Q2, LBM_D1Q3, LBM_D2Q9_D2Q5, LBM_D2Q9_PHASE, LBM_D3Q19 = 1, 2, 3, 4, 5
+LBM_D1Q2, LBM_D1Q3, LBM_D2Q9_D2Q5, LBM_D2Q9_PHASE, LBM_D3Q19, LBM_D3Q19_PHASE = 1, 2, 3, 4, 5, 6
 LBM_FP32_DEV, LBM_FP64 = 0, 1
 BC_PERIODIC, BC_WALL, BC_VEL_INLET, BC_P_OUTLET, BC_DIRICHLET, BC_SYMMETRY = 0, 1, 2, 3, 4, 5
 LBM_BGK, LBM_MRT = 0, 1
@@ -90,7 +90,7 @@ def lib():
         L.lbm_destroy.restype = None
         L.lbm_set_params_SI.argtypes = [vp, C.POINTER(ParamsSI)]
         L.lbm_init_fields.argtypes = [vp, _dp, _dp, _dp, _dp, _dp]
-        L.lbm_init_fields3d.argtypes = [vp, _dp, _dp, _dp, _dp]
+        L.lbm_init_fields3d.argtypes = [vp, _dp, _dp, _dp, _dp, _dp]
         L.lbm_step.argtypes = [vp, C.c_int]
         L.lbm_macros.argtypes = [vp, C.c_uint, _dp, C.c_int]
         L.lbm_reduce.argtypes = [vp, C.c_uint, _dp]
@@ -172,8 +172,8 @@ def make_params(prm, nx=None, ny=None):
 class Lattice:
     """One lbm_ctx with its torch-owned device buffer and stream.
 
-    lattice: 'd1q2' | 'd1q3' | 'channel' | 'phase' | 'd3q19'.  bc: 4 kinds (x-, x+,
-    y-, y+), plus bc_z (z-, z+) and nz for 'd3q19'.
+    lattice: 'd1q2' | 'd1q3' | 'channel' | 'phase' | 'd3q19' | 'phase3d'.  bc: 4 kinds
+    (x-, x+, y-, y+), plus bc_z (z-, z+) and nz for the 3D lattices.
     prec: 'fp32' (FP32 deviation storage) | 'fp64'.
     """
 
@@ -187,7 +187,7 @@ class Lattice:
         torch.cuda.set_device(self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         lat = {"d1q2": LBM_D1Q2, "d1q3": LBM_D1Q3, "channel": LBM_D2Q9_D2Q5,
-               "phase": LBM_D2Q9_PHASE, "d3q19": LBM_D3Q19}[lattice]
+               "phase": LBM_D2Q9_PHASE, "d3q19": LBM_D3Q19, "phase3d": LBM_D3Q19_PHASE}[lattice]
         if bc is None:
             bc = {"d1q2": (4, 4, 0, 0), "d1q3": (4, 4, 0, 0)}.get(lattice, (0, 0, 0, 0))
         d = Desc()
@@ -195,11 +195,12 @@ class Lattice:
         d.prec = LBM_FP64 if prec == "fp64" else LBM_FP32_DEV
         for i in range(4):
             d.bc[i] = bc[i]
-        if lat == LBM_D3Q19:
+        three_d = lat in (LBM_D3Q19, LBM_D3Q19_PHASE)
+        if three_d:
             d.nz = nz
             d.bc_z[0], d.bc_z[1] = bc_z
         # thermal: False, True / 'd2q5' (D2Q5), or 'd2q9' (D2Q9 thermal set)
-        d.flags = ((FLAG_FLOW if flow and lat != LBM_D3Q19 else 0) |
+        d.flags = ((FLAG_FLOW if flow and not three_d else 0) |
                    (FLAG_THERMAL if thermal else 0) | (FLAG_THERMAL_D2Q9 if thermal == "d2q9" else 0))
         d.hip_stream = C.c_void_p(self.stream.cuda_stream)
         nbytes = C.c_size_t()
@@ -213,7 +214,7 @@ class Lattice:
         self.ctx = h
         self._lib = lib()
         self.lattice, self.nx, self.ny, self.batch, self.prec = lattice, nx, ny, batch, prec
-        self.nz = nz if lat == LBM_D3Q19 else 1
+        self.nz = nz if three_d else 1
         self.bytes = int(nbytes.value)
 
     def _check(self, st, ctx="self"):
@@ -236,7 +237,7 @@ class Lattice:
 
     @property
     def shape(self):
-        if self.lattice == "d3q19":
+        if self.lattice in ("d3q19", "phase3d"):
             return (self.batch, self.nz, self.ny, self.nx)
         return (self.batch, self.ny, self.nx)
 
@@ -254,11 +255,12 @@ class Lattice:
             assert a is None or a.size == n
         self._check(lib().lbm_init_fields(self.ctx, *(_ptr(a) for a in arrs)))
 
-    def init3d(self, rho, ux=None, uy=None, uz=None):
-        """D3Q19: equilibria of rho, u (arrays broadcast to [batch][nz][ny][nx])."""
+    def init3d(self, rho_or_p=None, ux=None, uy=None, uz=None, phi=None):
+        """3D lattices: equilibria of rho (D3Q19) or p and phi (phase3d) and u;
+        arrays broadcast to [batch][nz][ny][nx]."""
         arrs = [None if a is None else _f64(np.broadcast_to(np.asarray(a, dtype=np.float64),
                                                             self.shape).reshape(-1))
-                for a in (rho, ux, uy, uz)]
+                for a in (rho_or_p, ux, uy, uz, phi)]
         self._check(lib().lbm_init_fields3d(self.ctx, *(_ptr(a) for a in arrs)))
 
     def step(self, n=1):
@@ -280,7 +282,8 @@ class Lattice:
         if fields is None:
             fields = {"channel": ("rho", "ux", "uy") + (("T",) if self.desc.flags & FLAG_THERMAL else ()),
                       "phase": ("rho", "p", "ux", "uy", "phi", "mu"),
-                      "d3q19": ("rho", "ux", "uy", "uz")}.get(self.lattice, ("T",))
+                      "d3q19": ("rho", "ux", "uy", "uz"),
+                      "phase3d": ("rho", "p", "ux", "uy", "uz", "phi", "mu")}.get(self.lattice, ("T",))
         mask = 0
         for f in fields:
             mask |= MACRO_BITS[f]

@@ -301,3 +301,40 @@ def box3d(nx=64, ny=64, nz=64, batch=1, seed=0, dx=1e-4, tau_ratio=0.8, fluid=No
     tile = lambda a: np.tile(a, reps)
     ini = dict(rho=tile(rho), ux=tile(u[0]), uy=tile(u[1]), uz=tile(u[2]))
     return prm, ini
+
+
+def bubble3d(n=64, ny=None, nz=None, R_nodes=12.0, shape="sphere", axis=2, seed=0, dx=5e-6,
+             dt=1e-7, W_nodes=4.0, M=1e-5, rho_l=1000.0, rho_g=0.0231, nu_l=8.927e-7,
+             nu_g=4.20412e-4, sigma=0.07, batch=1, u_noise=0.0, p_laplace=False):
+    """The C3 bubble (air/water-like properties of the stationary-bubble case,
+    Sec. 4.3) in a periodic 3D box: a gas sphere, or a gas cylinder whose axis
+    runs along ``axis`` (0 x, 1 y, 2 z), radius R_nodes, centre jittered by
+    U(-1/2, 1/2) nodes per axis.  p = 0, or with ``p_laplace`` the Laplace
+    jump (2 sigma / R for the sphere, sigma / R for the cylinder) weighted by
+    the gas fraction 1 - phi: started from p = 0, a large sphere's start-up
+    pressure wave focuses at its centre and can push phi below -rho_g / drho,
+    where the linear density law gives rho <= 0.  ``u_noise`` adds a seeded
+    random velocity of that many m/s (rms per component).  Arrays
+    [batch][nz][ny][nx]."""
+    ny = n if ny is None else ny
+    nz = n if nz is None else nz
+    g = rng(seed)
+    Z, Y, X = np.meshgrid(node_centres(nz, dx), node_centres(ny, dx), node_centres(n, dx),
+                          indexing="ij")
+    W = W_nodes * dx
+    phi = np.zeros((batch, nz, ny, n))
+    for b in range(batch):
+        j = g.uniform(-0.5, 0.5, 3)
+        c = ((n / 2 + j[0]) * dx, (ny / 2 + j[1]) * dx, (nz / 2 + j[2]) * dx)
+        d = [(X - c[0]) ** 2, (Y - c[1]) ** 2, (Z - c[2]) ** 2]
+        if shape == "cylinder":
+            d[axis] = 0.0 * d[axis]
+        r = np.sqrt(d[0] + d[1] + d[2])
+        phi[b] = tanh_profile(r - R_nodes * dx, W)
+    prm = dict(dx=dx, dt=dt, rho_l=rho_l, rho_g=rho_g, nu_l=nu_l, nu_g=nu_g,
+               zeta_l=nu_l * rho_l, zeta_g=nu_g * rho_g, visc_mode=0, sigma=sigma, W=W, M=M,
+               F=(0.0, 0.0, 0.0), z_mrt=1, normal_eps=NORMAL_EPS_NODES / dx)
+    u = [u_noise * g.standard_normal(phi.shape) for _ in range(3)]
+    jump = (1.0 if shape == "cylinder" else 2.0) * sigma / (R_nodes * dx)
+    p = jump * (1.0 - phi) if p_laplace else np.zeros_like(phi)
+    return prm, dict(phi=phi, p=p, ux=u[0], uy=u[1], uz=u[2])
