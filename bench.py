@@ -179,6 +179,35 @@ def run_p3(n, steps, warmup, prec, cell=64, R_nodes=16.0):
                                                                else (("double",) * 2)))
 
 
+def run_layered_batch(batch, steps, warmup, prec):
+    """C4's layered two-phase channel (4 x 512 nodes, walls) as a batch of
+    independent replicas: the roofline-sized form of a launch-bound case."""
+    import torch
+    from paper_2302_04120_amd import lbm, workloads as WL
+    prm, ini, _ = WL.layered(nx=4, ny=512, batch=batch, seed=0)
+    L = lbm.Lattice("phase", 4, 512, batch=batch, prec=prec, bc=(0, 0, lbm.BC_WALL, lbm.BC_WALL))
+    L.set_params(prm)
+    L.init(ini["p"], ini["ux"], ini["uy"], None, ini["phi"])
+    del ini
+    L.step(warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(L.stream)
+    t0 = time.perf_counter()
+    L.step(steps)
+    e1.record(L.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    if L.reduce(("nonfinite",))["nonfinite"].sum() != 0:
+        raise RuntimeError("non-finite populations after the timed steps")
+    step_ms = e0.elapsed_time(e1) / steps
+    nodes = batch * 4 * 512
+    gbs = BYTES_PER_LU[prec] * nodes / (step_ms * 1e-3) / 1e9
+    return dict(mlups=nodes * steps / wall / 1e6, step_ms=step_ms, hbm_GBps=gbs,
+                hbm_frac=gbs / HBM_PEAK_GBS, replicas=batch, grid="4x512")
+
+
 def adjoint_cost(steps=20000, ckpt=500, prec="fp32"):
     """Adjoint/forward cost on the C5 heated channel (1600 x 80 nodes, flow from
     rest): plain forward time, record time (forward + checkpoints) and the
@@ -256,7 +285,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP64 and batch-4 legs")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_phase_step.json"))
-    ap.add_argument("--leg", choices=("channel", "adjoint", "d3q19", "phase3d"), default=None,
+    ap.add_argument("--leg", choices=("channel", "adjoint", "d3q19", "phase3d", "layered"),
+                    default=None,
                     help="only run one secondary leg and print its figures (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain copy of BYTES (counter calibration)")
@@ -275,6 +305,9 @@ def main():
         return 0
     if args.leg == "phase3d":
         print(json.dumps(run_p3(256, args.steps, args.warmup, args.prec)), flush=True)
+        return 0
+    if args.leg == "layered":
+        print(json.dumps(run_layered_batch(4096, args.steps, args.warmup, args.prec)), flush=True)
         return 0
     if args.gpus != 1:
         print("bench.py measures one GPU only; --gpus %d is not supported" % args.gpus,
@@ -313,6 +346,8 @@ def main():
         log("bench: paper-sized leg (4 replicas)")
         r4 = run_gpu(4, 1000, 50, args.prec)
         extras["paper_config_batch4_mlups"] = r4["nodes"] * 1000 / r4["wall"] / 1e6
+        log("bench: C4 layered batch leg (4096 x 4 x 512)")
+        extras["layered_batch_fp32"] = run_layered_batch(4096, 200, 20, "fp32")
         log("bench: heated-channel leg (16384 x 2048)")
         extras["channel_fp32"] = run_channel(16384, 2048, 100, 10, "fp32")
         log("bench: D3Q19 leg (256^3)")

@@ -263,8 +263,6 @@ constexpr int TX = 64, TY = LBM_PHASE_TY;
 // 2.82 ms at 8 waves per SIMD, 2.56 ms at 4).  The FP64 kernel's register
 // use already gives 4 waves per SIMD.
 constexpr unsigned kPhaseLdsReserve = 61440;
-static_assert(2 * (TX + 2) + 2 * TY <= TX * TY, "the ring must fit in one pass of the block");
-
 // phi of a node from its stored h_i, Eq. zero_moment_h (rest population with
 // its low part).  One summation order everywhere, so that every kernel sees
 // the same phi for the same populations.
@@ -422,16 +420,19 @@ __device__ __forceinline__ void phase_collide(const PhaseK& k, const PhaseLocal<
 }
 
 // ---------------------------------------------------------------------------
-// Single step.  Tile of 64 x TY nodes per block; phi of the tile and a
-// one-node ring in LDS.  MACROS: evaluate the macroscopic fields of the
-// stored state into mout instead of stepping.
+// Single step.  Tile of TX x TY nodes per block (64 x 8, or nx x 512/nx for
+// replicas narrower than 64 nodes, so that no lane idles and a wave still
+// covers 64 contiguous nodes); phi of the tile and a one-node ring in LDS.
+// MACROS: evaluate the macroscopic fields of the stored state into mout
+// instead of stepping.
 // ---------------------------------------------------------------------------
-template <typename S, typename C, bool MACROS>
+template <typename S, typename C, bool MACROS, int TX = lbm::TX, int TY = lbm::TY>
 __global__ __launch_bounds__(TX * TY) void k_phase(PhaseK k, const S* __restrict__ hc,
                                                S* __restrict__ hn, const S* __restrict__ zc,
                                                S* __restrict__ zn, const S* __restrict__ puc,
                                                S* __restrict__ pun, double* __restrict__ mout) {
     constexpr bool RMASS = std::is_same<S, float>::value;
+    static_assert(2 * (TX + 2) + 2 * TY <= TX * TY, "the ring must fit in one pass of the block");
     __shared__ C sphi[TY + 2][TX + 2];
     const int nx = k.nx, ny = k.ny;
     const long long P = k.P;
@@ -1096,15 +1097,31 @@ hipError_t launch_chan_step(const ChanK& k, const S* fc, S* fn, const S* gc, S* 
     return hipGetLastError();
 }
 
+// One launch of k_phase with the tile shape for the replica width: 64 x TY,
+// or, for nx in {4, 8, 16, 32}, nx x (512 / nx).
+template <typename S, typename C, bool MACROS>
+hipError_t launch_phase_kernel(const PhaseK& k, const S* hc, S* hn, const S* zc, S* zn,
+                               const S* puc, S* pun, double* out, unsigned lds, hipStream_t s) {
+    auto go = [&](auto kern, int tx, int ty) {
+        const long long tiles = (long long)((k.nx + tx - 1) / tx) * ((k.ny + ty - 1) / ty) * k.batch;
+        dim3 blk(tx, ty), grd(unsigned((tiles + kXCD - 1) / kXCD * kXCD));
+        hipLaunchKernelGGL(kern, grd, blk, lds, s, k, hc, hn, zc, zn, puc, pun, out);
+        return hipGetLastError();
+    };
+    switch (k.nx) {
+        case 4: return go(k_phase<S, C, MACROS, 4, 128>, 4, 128);
+        case 8: return go(k_phase<S, C, MACROS, 8, 64>, 8, 64);
+        case 16: return go(k_phase<S, C, MACROS, 16, 32>, 16, 32);
+        case 32: return go(k_phase<S, C, MACROS, 32, 16>, 32, 16);
+        default: return go(k_phase<S, C, MACROS>, TX, TY);
+    }
+}
+
 template <typename S>
 hipError_t launch_phase_step(const PhaseK& k, const S* hc, S* hn, const S* zc, S* zn, const S* puc,
                              S* pun, hipStream_t s) {
-    const long long tiles = (long long)((k.nx + TX - 1) / TX) * ((k.ny + TY - 1) / TY) * k.batch;
-    dim3 blk(TX, TY), grd(unsigned((tiles + kXCD - 1) / kXCD * kXCD));
     const unsigned lds = std::is_same<S, float>::value ? kPhaseLdsReserve : 0u;
-    hipLaunchKernelGGL((k_phase<S, S, false>), grd, blk, lds, s, k, hc, hn, zc, zn, puc, pun,
-                       (double*)nullptr);
-    return hipGetLastError();
+    return launch_phase_kernel<S, S, false>(k, hc, hn, zc, zn, puc, pun, (double*)nullptr, lds, s);
 }
 
 bool phase_tb2_fits(const PhaseK& k) { return k.nx % 64 == 0 && k.nx <= kTbMaxNx && k.ny >= 4; }
@@ -1164,11 +1181,8 @@ hipError_t launch_chan_macros(const ChanK& k, const S* f, const S* g, double* ou
 template <typename S>
 hipError_t launch_phase_macros(const PhaseK& k, const S* h, const S* z, double* out,
                                hipStream_t s) {
-    const long long tiles = (long long)((k.nx + TX - 1) / TX) * ((k.ny + TY - 1) / TY) * k.batch;
-    dim3 blk(TX, TY), grd(unsigned((tiles + kXCD - 1) / kXCD * kXCD));
-    hipLaunchKernelGGL((k_phase<S, double, true>), grd, blk, 0, s, k, h, (S*)nullptr, z,
-                       (S*)nullptr, (const S*)nullptr, (S*)nullptr, out);
-    return hipGetLastError();
+    return launch_phase_kernel<S, double, true>(k, h, (S*)nullptr, z, (S*)nullptr,
+                                                (const S*)nullptr, (S*)nullptr, out, 0u, s);
 }
 
 hipError_t launch_d1_macros(const D1K& k, const double* g, double* out, long long P,
