@@ -80,3 +80,31 @@ def test_cavity_ra1e4_steady_nusselt():
     assert np.abs(m["T"][mid] - np.asarray(gold["row_mid_T"])).max() < 1e-4 * dT
     assert np.abs(m["ux"][:, mid] - np.asarray(gold["col_mid_ux"])).max() < \
         1e-3 * np.abs(gold["col_mid_ux"]).max()
+
+
+@pytest.mark.timeout(300)
+def test_cavity_ra1e6_steady_nusselt():
+    """The steady Ra = 1e6 cavity (300 x 300, 260 000 steps, FP32 deviation
+    storage): mean and hot-wall Nusselt numbers equal the FP64 oracle's stored
+    run to 1e-4 and the paper's 8.805 (Table results_nat_conv, dimensional LBM;
+    benchmark 8.800) to 0.3 %; mid-line profiles match the oracle's."""
+    with open(os.path.join(HERE, "golden", "cavity_ra1e6_oracle.json")) as f:
+        gold = json.load(f)
+    prm, ini = WL.cavity(1e6)
+    n = ini["rho"].shape[0]
+    print_case(test="cavity-steady-1e6", n=n, steps=gold["steps"])
+    L = _gpu_cavity(prm, ini, n, "fp32")
+    L.step(gold["steps"])
+    assert L.reduce(("nonfinite",))["nonfinite"].sum() == 0
+    m = {k: v[0] for k, v in L.macros().items()}
+    nu, nu0 = nusselt_mean(m["ux"], m["T"], prm), nusselt_hot_wall(m["T"], prm)
+    print("Ra 1e6: Nu mean %.5f (oracle %.5f, paper 8.805), hot wall %.5f (oracle %.5f)" %
+          (nu, gold["Nu_mean"], nu0, gold["Nu_hot_wall"]), flush=True)
+    assert nu == pytest.approx(gold["Nu_mean"], rel=1e-4)
+    assert nu0 == pytest.approx(gold["Nu_hot_wall"], rel=1e-4)
+    assert nu == pytest.approx(8.805, rel=3e-3)
+    mid = n // 2
+    dT = prm["Th"] - prm["Tc"]
+    uy_o = np.asarray(gold["row_mid_uy"])
+    assert np.abs(m["uy"][mid] - uy_o).max() < 1e-3 * np.abs(uy_o).max()
+    assert np.abs(m["T"][mid] - np.asarray(gold["row_mid_T"])).max() < 1e-4 * dT

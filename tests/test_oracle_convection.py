@@ -95,3 +95,22 @@ def test_cavity_ra1e4_nusselt_against_paper():
     # the flow turns clockwise with the hot wall on the left: up near it, down at the cold one
     uy = np.asarray(g["row_mid_uy"])
     assert uy[2] > 0 > uy[-3]
+
+
+def test_cavity_ra1e6_nusselt_against_paper():
+    """The stored FP64 oracle run at Ra = 1e6 (300 x 300, 260 000 steps,
+    tests/golden/make_cavity.py 1e6) is steady and its mean Nusselt number is
+    the paper's 8.805 (Table results_nat_conv, dimensional LBM) and the
+    benchmark's 8.800 to within 0.3 %; hot-wall and mean values agree to
+    0.5 %; the boundary layers make the mid-height vertical velocity peak
+    near the walls."""
+    with open(os.path.join(HERE, "golden", "cavity_ra1e6_oracle.json")) as f:
+        g = json.load(f)
+    assert g["Nu_change_last_interval"] < 5e-4 * g["Nu_mean"]
+    assert g["Nu_mean"] == pytest.approx(8.805, rel=3e-3)
+    assert g["Nu_mean"] == pytest.approx(8.800, rel=3e-3)
+    assert g["Nu_hot_wall"] == pytest.approx(g["Nu_mean"], rel=5e-3)
+    uy = np.asarray(g["row_mid_uy"])
+    n = uy.size
+    assert uy[: n // 10].max() == pytest.approx(uy.max())  # peak within a tenth of the hot wall
+    assert uy[-(n // 10):].min() == pytest.approx(uy.min())
