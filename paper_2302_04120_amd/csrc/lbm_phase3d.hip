@@ -68,67 +68,31 @@ __global__ __launch_bounds__(256) void k_p3_phi(P3K k, const S* __restrict__ a,
     }
 }
 
-// One step (or, with MACROS, the macroscopic fields of the stored state).
+// Everything one node does once phi of itself and its 18 neighbours is known
+// (pn[i] = phi at x + e_i): stencils, macros, both collisions and the push
+// of its populations into b -- or, with MACROS, its macroscopic fields into
+// mout.  Shared by both step kernels, so that they agree to the last bit.
 template <typename S, bool MACROS>
-__global__ __launch_bounds__(kPThreads) void k_p3_step(P3K k, const S* __restrict__ a,
-                                                        S* __restrict__ b,
-                                                        const S* __restrict__ phig,
-                                                        double* __restrict__ mout) {
+__device__ __forceinline__ void p3_node(const P3K& k, const S (&pn)[19], const S (&h)[19], S hlo,
+                                        const S (&zz)[19], const S (&pu)[3], long long n, int x,
+                                        int y, int z, long long base, S* __restrict__ b,
+                                        double* __restrict__ mout, long long P) {
     using C = S;
     constexpr bool RMASS = std::is_same<S, float>::value;
     constexpr int PU = RMASS ? 39 : 38;  // first (phi u) plane
-    __shared__ C sphi[kHZ][kHY][kHX];
     const int nx = k.nx, ny = k.ny, nz = k.nz;
-    const long long P = k.P;
-    const int gx = (nx + kPX - 1) / kPX, gy = (ny + kPY - 1) / kPY, gz = (nz + kPZ - 1) / kPZ;
-    int tile;
-    if (!xcd_tile(gx * gy * gz * k.batch, tile)) return;  // whole workgroup, before the barrier
-    const int per = gx * gy * gz;
-    const int bb = tile / per, r = tile - bb * per;
-    const int x0 = (r % gx) * kPX, y0 = ((r / gx) % gy) * kPY, z0 = (r / (gx * gy)) * kPZ;
     const long long plane = (long long)nx * ny;
-    const long long base = (long long)bb * nz * plane;
-    const int tx = threadIdx.x, ty = threadIdx.y, tz = threadIdx.z;
-    const int x = x0 + tx, y = y0 + ty, z = z0 + tz;
-    const bool valid = x < nx && y < ny && z < nz;
-    const long long n = base + (long long)z * plane + (long long)y * nx + x;
-
-    // the node's own populations first, then the phi halo, then one barrier
-    C h[19], zz[19], hlo = C(0), pu[3] = {C(0), C(0), C(0)};
-    if (valid) {
-#pragma unroll
-        for (int i = 0; i < 19; ++i) h[i] = C(a[i * P + n]);
-#pragma unroll
-        for (int i = 0; i < 19; ++i) zz[i] = C(a[(19 + i) * P + n]);
-        if (RMASS) hlo = C(a[38 * P + n]);
-        if constexpr (!MACROS) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) pu[c] = C(a[(PU + c) * P + n]);
-        }
-    }
-    const int t = (tz * kPY + ty) * kPX + tx;
-    for (int j = t; j < kHalo; j += kPThreads) {
-        const int hx = j % kHX, hy = (j / kHX) % kHY, hz = j / (kHX * kHY);
-        const int gxx = ghost(x0 + hx - 1, nx, k.bcx);
-        const int gyy = ghost(y0 + hy - 1, ny, k.bcy);
-        const int gzz = ghost(z0 + hz - 1, nz, k.bcz);
-        sphi[hz][hy][hx] = C(phig[base + (long long)gzz * plane + (long long)gyy * nx + gxx]);
-    }
-    __syncthreads();
-    if (!valid) return;
-
     // ---- stencils (Eq. gradient, Eq. laplacian): grad phi = 3 G / dx,
     //      lap phi = 6 L / dx^2
-    const C phi = sphi[tz + 1][ty + 1][tx + 1];
+    const C phi = pn[0];
     C G[3] = {C(0), C(0), C(0)}, Lp = C(0);
 #pragma unroll
     for (int i = 1; i < 19; ++i) {
-        const C pn = sphi[tz + 1 + E3Z[i]][ty + 1 + E3Y[i]][tx + 1 + E3X[i]];
-        const C wp = w19<C>(i) * pn;
+        const C wp = w19<C>(i) * pn[i];
         G[0] += C(E3X[i]) * wp;
         G[1] += C(E3Y[i]) * wp;
         G[2] += C(E3Z[i]) * wp;
-        Lp += w19<C>(i) * (pn - phi);
+        Lp += w19<C>(i) * (pn[i] - phi);
     }
     const C drl = C(k.rho_l - k.rho_g);
     const C rho = C(k.rho_g) + phi * drl;
@@ -276,6 +240,61 @@ __global__ __launch_bounds__(kPThreads) void k_p3_step(P3K k, const S* __restric
         }
     }
 }
+
+// One step (or, with MACROS, the macroscopic fields of the stored state).
+template <typename S, bool MACROS>
+__global__ __launch_bounds__(kPThreads) void k_p3_step(P3K k, const S* __restrict__ a,
+                                                        S* __restrict__ b,
+                                                        const S* __restrict__ phig,
+                                                        double* __restrict__ mout) {
+    using C = S;
+    constexpr bool RMASS = std::is_same<S, float>::value;
+    constexpr int PU = RMASS ? 39 : 38;  // first (phi u) plane
+    __shared__ C sphi[kHZ][kHY][kHX];
+    const int nx = k.nx, ny = k.ny, nz = k.nz;
+    const long long P = k.P;
+    const int gx = (nx + kPX - 1) / kPX, gy = (ny + kPY - 1) / kPY, gz = (nz + kPZ - 1) / kPZ;
+    int tile;
+    if (!xcd_tile(gx * gy * gz * k.batch, tile)) return;  // whole workgroup, before the barrier
+    const int per = gx * gy * gz;
+    const int bb = tile / per, r = tile - bb * per;
+    const int x0 = (r % gx) * kPX, y0 = ((r / gx) % gy) * kPY, z0 = (r / (gx * gy)) * kPZ;
+    const long long plane = (long long)nx * ny;
+    const long long base = (long long)bb * nz * plane;
+    const int tx = threadIdx.x, ty = threadIdx.y, tz = threadIdx.z;
+    const int x = x0 + tx, y = y0 + ty, z = z0 + tz;
+    const bool valid = x < nx && y < ny && z < nz;
+    const long long n = base + (long long)z * plane + (long long)y * nx + x;
+
+    // the node's own populations first, then the phi halo, then one barrier
+    C h[19], zz[19], hlo = C(0), pu[3] = {C(0), C(0), C(0)};
+    if (valid) {
+#pragma unroll
+        for (int i = 0; i < 19; ++i) h[i] = C(a[i * P + n]);
+#pragma unroll
+        for (int i = 0; i < 19; ++i) zz[i] = C(a[(19 + i) * P + n]);
+        if (RMASS) hlo = C(a[38 * P + n]);
+        if constexpr (!MACROS) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) pu[c] = C(a[(PU + c) * P + n]);
+        }
+    }
+    const int t = (tz * kPY + ty) * kPX + tx;
+    for (int j = t; j < kHalo; j += kPThreads) {
+        const int hx = j % kHX, hy = (j / kHX) % kHY, hz = j / (kHX * kHY);
+        const int gxx = ghost(x0 + hx - 1, nx, k.bcx);
+        const int gyy = ghost(y0 + hy - 1, ny, k.bcy);
+        const int gzz = ghost(z0 + hz - 1, nz, k.bcz);
+        sphi[hz][hy][hx] = C(phig[base + (long long)gzz * plane + (long long)gyy * nx + gxx]);
+    }
+    __syncthreads();
+    if (!valid) return;
+    C pn[19];
+#pragma unroll
+    for (int i = 0; i < 19; ++i) pn[i] = sphi[tz + 1 + E3Z[i]][ty + 1 + E3Y[i]][tx + 1 + E3X[i]];
+    p3_node<S, MACROS>(k, pn, h, hlo, zz, pu, n, x, y, z, base, b, mout, P);
+}
+
 
 // equilibria from FP64 fields (staging slots 1 p, 2 ux, 3 uy, 7 uz, 5 phi)
 template <typename S>

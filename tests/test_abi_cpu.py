@@ -172,3 +172,30 @@ def test_d3q19_description_validation():
     big = d3(nz=1 << 14)
     big.nx, big.ny = 4096, 4096
     assert L.lbm_query_bytes(C.byref(big), C.byref(n)) == lbm.LBM_E_ARG
+
+
+def test_d3q19_phase_description_validation():
+    """D3Q19_PHASE: each axis periodic or walls, no flags; its buffer holds two
+    states of h 19 + z 19 (+ the low part of h_0 in FP32) + (phi u) 3 planes
+    and one phi plane."""
+    lbm = _lbm()
+    L = lbm.lib()
+    n = C.c_size_t()
+
+    def p3(nz=6, bc=(0, 0, 1, 1), bcz=(0, 0), flags=0, prec=lbm.LBM_FP32_DEV):
+        d = _desc(lbm, lattice=lbm.LBM_D3Q19_PHASE, nx=32, ny=8, bc=bc, flags=flags, prec=prec)
+        d.nz = nz
+        d.bc_z[0], d.bc_z[1] = bcz
+        return d
+
+    for d, want in [(p3(), lbm.LBM_OK), (p3(bc=(1, 1, 1, 1), bcz=(1, 1)), lbm.LBM_OK),
+                    (p3(flags=1), lbm.LBM_E_ARG), (p3(nz=0), lbm.LBM_E_ARG),
+                    (p3(bc=(2, 3, 0, 0)), lbm.LBM_E_UNSUPPORTED),
+                    (p3(bcz=(0, 1)), lbm.LBM_E_UNSUPPORTED)]:
+        assert L.lbm_query_bytes(C.byref(d), C.byref(n)) == want, (list(d.bc), list(d.bc_z), d.flags)
+    N = 32 * 8 * 6
+    assert L.lbm_query_bytes(C.byref(p3()), C.byref(n)) == lbm.LBM_OK
+    assert n.value >= 2 * (39 + 3) * N * 4 + N * 4 + 8 * N * 8
+    n64 = C.c_size_t()
+    assert L.lbm_query_bytes(C.byref(p3(prec=lbm.LBM_FP64)), C.byref(n64)) == lbm.LBM_OK
+    assert n64.value >= 2 * (38 + 3) * N * 8 + N * 8 + 8 * N * 8
