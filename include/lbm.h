@@ -213,9 +213,22 @@ LBM_API lbm_status lbm_set_graph_steps(lbm_ctx* ctx, int steps);
  *           per step; needs nx a multiple of 64 and at most 256
  *           (LBM_E_UNSUPPORTED otherwise); ny < 4 and an odd last step use
  *           the single-step kernel.
+ *   mode 3: every lbm_step call runs as one cooperative launch (per 16384
+ *           steps) of the many-steps kernel: one resident workgroup per
+ *           tile, which steps its tile and waits for its neighbouring tiles'
+ *           step counters before the next step, so small grids pay no
+ *           launch per step.  Needs a split into at most 16 tiles of 512
+ *           nodes over all replicas (64 x 8, or nx x 512/nx for nx = 4, 8,
+ *           16, 32), LBM_E_UNSUPPORTED otherwise; grids that split into at
+ *           most 16 tiles of 128 or 256 nodes run on those.
+ *           lbm_step then synchronises the stream before it returns, to read
+ *           the kernel's error word: a wait that timed out (a failed launch
+ *           neighbour) gives LBM_E_DEVICE and drops the state.  The step
+ *           counters live in the context's buffer and are reset by
+ *           lbm_init_fields and lbm_load_state.
  *   mode 0 (default): mode 2 when its workgroups (one per 128-row segment of
  *           a replica) number at least 512, else mode 1.
- * Both kernels evaluate the same per-node arithmetic in the same order, so
+ * The kernels evaluate the same per-node arithmetic in the same order, so
  * the modes agree to the last bit.  Not an operation of the paper: a
  * performance control.  Other lattices ignore it.  LBM_E_ARG on an unknown
  * mode. */

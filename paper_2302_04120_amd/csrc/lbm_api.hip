@@ -23,7 +23,7 @@ struct Layout {
     int npop = 0, nplanes = 0;
     size_t es = 0;
     size_t offA = 0, offB = 0, offAux = 0, offStage = 0, offPartial = 0, offPhi = 0;
-    size_t offSmall = 0, total = 0;
+    size_t offSmall = 0, offFlags = 0, total = 0;
 };
 
 // Extra elements between population planes (a multiple of 64).  Planes whose
@@ -141,6 +141,9 @@ lbm_status check_desc(const lbm_desc* d, Layout* L, std::string* err) {
     l.offSmall = off; off += align256((size_t)(3 * d->nx + 64 + 4 * d->batch) * sizeof(double));
     // D3Q19_PHASE: phi of the current state, recomputed before every step
     l.offPhi = off; off += d->lattice == LBM_D3Q19_PHASE ? align256((size_t)l.P * l.es) : 0;
+    // D2Q9_PHASE: per-tile step counters and the error word of the
+    // many-steps-per-launch kernel
+    l.offFlags = off; off += d->lattice == LBM_D2Q9_PHASE ? 256 : 0;
     l.total = off;
     *L = l;
     return LBM_OK;
@@ -215,6 +218,56 @@ bool use_tb2(const lbm_ctx* c) {
     if (c->desc.lattice != LBM_D2Q9_PHASE || c->fusion == 1 || !phase_tb2_fits(c->pk)) return false;
     if (c->fusion == 2) return true;
     return phase_tb2_workgroups(c->pk) >= 512;
+}
+
+// The many-steps kernel needs the grid split into at most 16 tiles (of 512,
+// 256 or 128 nodes) over all replicas, all resident at once.
+bool phase_persist_fits_desc(const lbm_desc& d) {
+    PhaseK k{};
+    k.nx = d.nx;
+    k.ny = d.ny;
+    k.batch = d.batch;
+    return phase_persist_fits(k);
+}
+
+bool use_persist(const lbm_ctx* c) {
+    return c->desc.lattice == LBM_D2Q9_PHASE && c->fusion == 3 && phase_persist_fits(c->pk);
+}
+
+// Zero the step counters and the error word: with the state (re)set no
+// launch of the many-steps kernel is pending.
+hipError_t reset_persist(lbm_ctx* c) {
+    c->persist_epoch = 0;
+    if (!c->persist_flags) return hipSuccess;
+    return hipMemsetAsync(c->persist_flags, 0, 256, c->stream);
+}
+
+// n steps in launches of the many-steps kernel (at most kPersistChunk steps
+// each), then one synchronisation to read the error word.
+constexpr int kPersistChunk = 1 << 14;
+template <typename S>
+lbm_status step_persist(lbm_ctx* c, int n) {
+    unsigned* err = c->persist_flags + 16;
+    for (int s = 0; s < n;) {
+        const int m = std::min(kPersistChunk, n - s);
+        hipError_t e = launch_phase_persist<S>(c->pk, (S*)bufA(c), (S*)bufB(c), m, c->persist_epoch,
+                                               c->persist_flags, err, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "many-steps kernel");
+        c->persist_epoch += unsigned(m);
+        c->cur ^= (m & 1);
+        c->t += m;
+        s += m;
+    }
+    unsigned herr = 0;
+    hipError_t e = hipMemcpyAsync(&herr, err, sizeof(herr), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "many-steps kernel");
+    if (herr) {
+        c->has_state = false;
+        return set_err(c, LBM_E_DEVICE, "many-steps kernel: a tile's wait for its neighbours timed "
+                                        "out; the state is lost (reinitialise it)");
+    }
+    return LBM_OK;
 }
 
 // Enqueue m (1 or 2) steps, advancing the buffer parity and the step count;
@@ -361,6 +414,7 @@ lbm_status lbm_create(const lbm_desc* desc, lbm_ctx** out) {
     c->partial = (double*)(base + L.offPartial);
     c->small = (double*)(base + L.offSmall);
     c->phi3 = base + L.offPhi;
+    c->persist_flags = desc->lattice == LBM_D2Q9_PHASE ? (unsigned*)(base + L.offFlags) : nullptr;
     c->cur = 0;
     c->t = 0;
     c->has_params = c->has_state = false;
@@ -393,7 +447,10 @@ lbm_status lbm_set_graph_steps(lbm_ctx* c, int steps) {
 
 lbm_status lbm_set_step_fusion(lbm_ctx* c, int mode) {
     if (!c) return LBM_E_ARG;
-    if (mode < 0 || mode > 2) return set_err(c, LBM_E_ARG, "fusion mode must be 0, 1 or 2");
+    if (mode < 0 || mode > 3) return set_err(c, LBM_E_ARG, "fusion mode must be 0, 1, 2 or 3");
+    if (mode == 3 && c->desc.lattice == LBM_D2Q9_PHASE && !phase_persist_fits_desc(c->desc))
+        return set_err(c, LBM_E_UNSUPPORTED,
+                       "many-steps kernel needs at most 16 tiles of 512 nodes over all replicas");
     if (mode == 2 && c->desc.lattice == LBM_D2Q9_PHASE &&
         (c->desc.nx % 64 != 0 || c->desc.nx > 256))
         return set_err(c, LBM_E_UNSUPPORTED, "two-step kernel needs nx a multiple of 64, at most 256");
@@ -655,7 +712,8 @@ lbm_status lbm_init_fields(lbm_ctx* c, const double* rho_or_p, const double* ux,
         if (e != hipSuccess) return hip_fail(c, e, "field upload");
     }
     c->cur = 0;
-    hipError_t e;
+    hipError_t e = reset_persist(c);
+    if (e != hipSuccess) return hip_fail(c, e, "step counter reset");
     if (d1) {
         e = launch_d1_init(c->dk, c->staging, (double*)c->popA, c->stream);
     } else if (d.lattice == LBM_D2Q9_D2Q5) {
@@ -736,6 +794,7 @@ lbm_status lbm_step(lbm_ctx* c, int n) {
         return LBM_OK;
     }
     const bool f64 = c->desc.prec == LBM_FP64;
+    if (n > 0 && use_persist(c)) return f64 ? step_persist<double>(c, n) : step_persist<float>(c, n);
     int s = 0;
     if (n >= 2 * c->graph_steps && graph_usable(c)) {
         for (; s + c->graph_steps <= n; s += c->graph_steps) {
@@ -1109,8 +1168,10 @@ lbm_status lbm_load_state(lbm_ctx* c, const void* host, size_t bytes) {
     DeviceGuard g(c->device);
     const char* p = (const char*)host + sizeof hd;
     c->cur = 0;
-    hipError_t e = hipMemcpy2DAsync(c->popA, (size_t)c->P * c->esize, p, row, row, c->nplanes,
-                                    hipMemcpyHostToDevice, c->stream);
+    hipError_t e = reset_persist(c);
+    if (e == hipSuccess)
+        e = hipMemcpy2DAsync(c->popA, (size_t)c->P * c->esize, p, row, row, c->nplanes,
+                             hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "load state");
     c->t = hd.t;

@@ -149,8 +149,10 @@ struct lbm_ctx {
     hipGraphExec_t step_graph[2] = {nullptr, nullptr};
     int graph_swaps[2] = {0, 0};  // buffer swaps made by each captured graph
     // two-phase steps: 0 automatic, 1 single-step kernel only, 2 two-step
-    // kernel whenever the grid allows it
+    // kernel whenever the grid allows it, 3 many steps per cooperative launch
     int fusion = 0;
+    unsigned* persist_flags = nullptr;  // [kPersistMaxTiles] step counters, then the error word
+    unsigned persist_epoch = 0;         // steps taken by persistent launches since the reset
 };
 
 namespace lbm {
@@ -170,6 +172,14 @@ bool phase_tb2_fits(const PhaseK& k);
 long long phase_tb2_workgroups(const PhaseK& k);
 template <typename S>
 hipError_t launch_phase_tb2(const PhaseK& k, const S* a, S* b, hipStream_t s);
+// many steps in one cooperative launch for grids that split into at most 16
+// tiles of 512 threads (phase_persist_fits); flags: one step counter per tile
+// (zeroed with the state, advanced to epoch0 + steps), err: set when a
+// bounded wait ran out
+bool phase_persist_fits(const PhaseK& k);
+template <typename S>
+hipError_t launch_phase_persist(const PhaseK& k, S* A, S* B, int nsteps, unsigned epoch0,
+                                unsigned* flags, unsigned* err, hipStream_t s);
 hipError_t launch_d1(const D1K& k, double* g, int nsteps, hipStream_t s);
 
 template <typename S>

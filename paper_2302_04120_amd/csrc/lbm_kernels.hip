@@ -426,20 +426,19 @@ __device__ __forceinline__ void phase_collide(const PhaseK& k, const PhaseLocal<
 // MACROS: evaluate the macroscopic fields of the stored state into mout
 // instead of stepping.
 // ---------------------------------------------------------------------------
-template <typename S, typename C, bool MACROS, int TX = lbm::TX, int TY = lbm::TY>
-__global__ __launch_bounds__(TX * TY) void k_phase(PhaseK k, const S* __restrict__ hc,
-                                               S* __restrict__ hn, const S* __restrict__ zc,
-                                               S* __restrict__ zn, const S* __restrict__ puc,
-                                               S* __restrict__ pun, double* __restrict__ mout) {
+// One tile of the single step (every thread of the block calls it; it has
+// one barrier).  Returns early for threads without a node, after the barrier.
+template <typename S, typename C, bool MACROS, int TX, int TY>
+__device__ __forceinline__ void phase_tile(const PhaseK& k, int tile, const S* __restrict__ hc,
+                                           S* __restrict__ hn, const S* __restrict__ zc,
+                                           S* __restrict__ zn, const S* __restrict__ puc,
+                                           S* __restrict__ pun, double* __restrict__ mout,
+                                           C (&sphi)[TY + 2][TX + 2]) {
     constexpr bool RMASS = std::is_same<S, float>::value;
-    static_assert(2 * (TX + 2) + 2 * TY <= TX * TY, "the ring must fit in one pass of the block");
-    __shared__ C sphi[TY + 2][TX + 2];
     const int nx = k.nx, ny = k.ny;
     const long long P = k.P;
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int gx = (nx + TX - 1) / TX, gy = (ny + TY - 1) / TY;
-    int tile;
-    if (!xcd_tile(gx * gy * k.batch, tile)) return;  // whole workgroup, before any barrier
     const int b = tile / (gx * gy), r = tile - b * gx * gy;
     const int x0 = (r % gx) * TX, y0 = (r / gx) * TY;
     const long long base = (long long)b * ny * nx;
@@ -526,6 +525,112 @@ __global__ __launch_bounds__(TX * TY) void k_phase(PhaseK k, const S* __restrict
                 st(zn + i * P + d, S(zst[i]));
             }
         }
+    }
+}
+
+template <typename S, typename C, bool MACROS, int TX = lbm::TX, int TY = lbm::TY>
+__global__ __launch_bounds__(TX * TY) void k_phase(PhaseK k, const S* __restrict__ hc,
+                                               S* __restrict__ hn, const S* __restrict__ zc,
+                                               S* __restrict__ zn, const S* __restrict__ puc,
+                                               S* __restrict__ pun, double* __restrict__ mout) {
+    static_assert(2 * (TX + 2) + 2 * TY <= TX * TY, "the ring must fit in one pass of the block");
+    __shared__ C sphi[TY + 2][TX + 2];
+    const int gx = (k.nx + TX - 1) / TX, gy = (k.ny + TY - 1) / TY;
+    int tile;
+    if (!xcd_tile(gx * gy * k.batch, tile)) return;  // whole workgroup, before any barrier
+    phase_tile<S, C, MACROS, TX, TY>(k, tile, hc, hn, zc, zn, puc, pun, mout, sphi);
+}
+
+// ---------------------------------------------------------------------------
+// Many steps in one launch for grids of a few tiles (the paper's C4 channel is
+// 4 x 512 nodes: four 4 x 128 tiles).  One workgroup per tile, all resident
+// at once (cooperative launch).  Between steps a tile waits only for the
+// tiles within one node of it -- those whose pushes it reads and whose reads
+// its next pushes would overwrite -- through per-tile step counters with
+// device-scope release / acquire; a grid-wide barrier costs several times
+// more on this GPU.  Every wait is bounded: past the bound the workgroup
+// flags an error and leaves, and so do its neighbours in turn, so the grid
+// always drains.  The per-tile work is phase_tile, as in k_phase, so the
+// states agree with single-step launches to the last bit.
+// ---------------------------------------------------------------------------
+constexpr int kPersistMaxTiles = 16;
+constexpr unsigned kPersistSpin = 1u << 22;  // polls before a wait counts as failed
+
+template <typename S, int TX, int TY>
+__global__ __launch_bounds__(TX * TY) void k_phase_persist(PhaseK k, S* __restrict__ A,
+                                                           S* __restrict__ B, int nsteps,
+                                                           unsigned epoch0,
+                                                           unsigned* __restrict__ flags,
+                                                           unsigned* __restrict__ err) {
+    static_assert(2 * (TX + 2) + 2 * TY <= TX * TY, "the ring of a tile needs a thread per node");
+    __shared__ S sphi[TY + 2][TX + 2];
+    __shared__ int bad;
+    const long long P = k.P;
+    const int npop = std::is_same<S, float>::value ? 19 : 18;
+    const int gx = (k.nx + TX - 1) / TX, gy = (k.ny + TY - 1) / TY;
+    const int tile = blockIdx.x;
+    const int b = tile / (gx * gy), r = tile - b * gx * gy;
+    const int bx = r % gx, by = r / gx;
+    // Tiles whose step s - 1 must be complete before this tile's step s: those
+    // that write the tile's nodes or its ring in step s - 1 (data it reads) and
+    // those that read, in step s - 1, the nodes it writes in step s.  When
+    // every tile spans at least two nodes in x and y these are the tiles of the
+    // same replica within one node (x periodic, y periodic or closed by
+    // walls); a one-node ragged tail reaches further, and then the tile waits
+    // for every tile of its replica.
+    const bool thin = (gx > 1 && k.nx - (gx - 1) * TX < 2) || (gy > 1 && k.ny - (gy - 1) * TY < 2);
+    auto waits_for = [&](int rt) {
+        const int ddx = min(abs(rt % gx - bx), gx - abs(rt % gx - bx));  // x periodic
+        const int ddy = k.bcy ? abs(rt / gx - by) : min(abs(rt / gx - by), gy - abs(rt / gx - by));
+        return rt != r && (thin || (ddx <= 1 && ddy <= 1));
+    };
+    const int lin = threadIdx.y * TX + threadIdx.x;
+    // lane j of the first wave watches tile j of the replica (at most 16)
+    const bool watch = lin < gx * gy && waits_for(lin);
+    const unsigned* wflag = flags + b * gx * gy + (watch ? lin : 0);
+    if (lin == 0) bad = 0;
+    for (int s = 0; s < nsteps; ++s) {
+        if (s > 0 && lin < 64) {
+            const unsigned want = epoch0 + unsigned(s);
+            unsigned spins = 0;
+            bool fail = false;
+            for (;;) {
+                // modular comparison: the counter is behind want
+                const bool behind =
+                    watch && __hip_atomic_load(wflag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) -
+                                     want > 0x7fffffffu;
+                if (!__any(behind)) break;
+                if (++spins > kPersistSpin ||
+                    __any(__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
+                    fail = true;
+                    break;
+                }
+            }
+            if (fail && lin == 0) {
+                bad = 1;
+                __hip_atomic_fetch_or(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            // one acquire for the workgroup: its waves share this CU's caches
+            // and follow the first wave through the barrier below
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        __syncthreads();
+        if (bad) return;  // uniform: every thread read it after the barrier
+        const S* a = (s & 1) ? B : A;
+        S* o = (s & 1) ? A : B;
+        phase_tile<S, S, false, TX, TY>(k, tile, a, o, a + 9 * P, o + 9 * P, a + npop * P,
+                                        o + npop * P, (double*)nullptr, sphi);
+        // Every wave waits until its stores have reached the L2 (vmcnt counts
+        // stores on this GPU), the barrier orders them before the first
+        // lane's device-scope release, whose L2 write-back then carries the
+        // whole tile: one write-back per workgroup and step instead of one
+        // per wave.
+        __builtin_amdgcn_s_waitcnt(0);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __syncthreads();
+        if (lin == 0)
+            __hip_atomic_store(&flags[tile], epoch0 + unsigned(s + 1), __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -1117,6 +1222,60 @@ hipError_t launch_phase_kernel(const PhaseK& k, const S* hc, S* hn, const S* zc,
     }
 }
 
+#ifndef LBM_PERSIST_MIN_THREADS
+#define LBM_PERSIST_MIN_THREADS 128
+#endif
+
+// Tile shape of the many-steps kernel for a workgroup of `threads` threads:
+// nx x threads/nx for the narrow replicas (nx = 4, 8, 16, 32), else 64 x
+// threads/64 (at least 256 threads, so that a thread holds each ring node).
+void persist_shape(const PhaseK& k, int threads, int* tx, int* ty) {
+    const bool narrow = k.nx == 4 || k.nx == 8 || k.nx == 16 || k.nx == 32;
+    if (!narrow && threads < 256) threads = 256;
+    *tx = narrow ? k.nx : 64;
+    *ty = threads / *tx;
+}
+
+long long persist_tiles(const PhaseK& k, int threads) {
+    int tx, ty;
+    persist_shape(k, threads, &tx, &ty);
+    return (long long)((k.nx + tx - 1) / tx) * ((k.ny + ty - 1) / ty) * k.batch;
+}
+
+// The smallest workgroup (most tiles, least work per CU) whose tiles number
+// at most kPersistMaxTiles; 0 if none does.
+int persist_threads(const PhaseK& k) {
+    for (int t = LBM_PERSIST_MIN_THREADS; t <= 512; t *= 2)
+        if (persist_tiles(k, t) <= kPersistMaxTiles) return t;
+    return 0;
+}
+
+bool phase_persist_fits(const PhaseK& k) { return persist_threads(k) != 0; }
+
+template <typename S>
+hipError_t launch_phase_persist(const PhaseK& k, S* A, S* B, int nsteps, unsigned epoch0,
+                                unsigned* flags, unsigned* err, hipStream_t s) {
+    const int threads = persist_threads(k);
+    if (!threads || nsteps < 1) return hipErrorInvalidValue;
+    int tx, ty;
+    persist_shape(k, threads, &tx, &ty);
+    const unsigned tiles = unsigned(persist_tiles(k, threads));
+    void* args[] = {(void*)&k, (void*)&A, (void*)&B, (void*)&nsteps, (void*)&epoch0, (void*)&flags,
+                    (void*)&err};
+    auto go = [&](const void* kern) {
+        return hipLaunchCooperativeKernel(kern, dim3(tiles), dim3(tx, ty), args, 0, s);
+    };
+#define LBM_PERSIST_CASE(X, Y) \
+    if (tx == X && ty == Y) return go(reinterpret_cast<const void*>(&k_phase_persist<S, X, Y>));
+    LBM_PERSIST_CASE(4, 32) LBM_PERSIST_CASE(4, 64) LBM_PERSIST_CASE(4, 128)
+    LBM_PERSIST_CASE(8, 16) LBM_PERSIST_CASE(8, 32) LBM_PERSIST_CASE(8, 64)
+    LBM_PERSIST_CASE(16, 8) LBM_PERSIST_CASE(16, 16) LBM_PERSIST_CASE(16, 32)
+    LBM_PERSIST_CASE(32, 4) LBM_PERSIST_CASE(32, 8) LBM_PERSIST_CASE(32, 16)
+    LBM_PERSIST_CASE(64, 4) LBM_PERSIST_CASE(64, 8)
+#undef LBM_PERSIST_CASE
+    return hipErrorInvalidValue;
+}
+
 template <typename S>
 hipError_t launch_phase_step(const PhaseK& k, const S* hc, S* hn, const S* zc, S* zn, const S* puc,
                              S* pun, hipStream_t s) {
@@ -1227,6 +1386,8 @@ hipError_t launch_nusselt(const ChanK& k, const S* f, const S* g, const S* qw, d
     template hipError_t launch_phase_step<S>(const PhaseK&, const S*, S*, const S*, S*,          \
                                              const S*, S*, hipStream_t);                          \
     template hipError_t launch_phase_tb2<S>(const PhaseK&, const S*, S*, hipStream_t);           \
+    template hipError_t launch_phase_persist<S>(const PhaseK&, S*, S*, int, unsigned, unsigned*,  \
+                                                unsigned*, hipStream_t);                          \
     template hipError_t launch_chan_init<S>(const ChanK&, const double*, S*, S*, hipStream_t);   \
     template hipError_t launch_phase_init<S>(const PhaseK&, const double*, S*, S*, S*,           \
                                              hipStream_t);                                        \

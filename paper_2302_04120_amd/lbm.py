@@ -271,7 +271,8 @@ class Lattice:
         self._check(lib().lbm_set_graph_steps(self.ctx, int(steps)))
 
     def set_step_fusion(self, mode):
-        """Two-phase kernel choice: 0 automatic, 1 single-step, 2 two-step."""
+        """Two-phase kernel choice: 0 automatic, 1 single-step, 2 two-step,
+        3 many steps per cooperative launch (grids of at most 16 tiles)."""
         self._check(lib().lbm_set_step_fusion(self.ctx, int(mode)))
 
     @property

@@ -103,7 +103,7 @@ def test_fusion_validation():
     with pytest.raises(lbm.LbmError):
         L.set_step_fusion(2)  # nx not a multiple of 64
     with pytest.raises(lbm.LbmError):
-        L.set_step_fusion(3)
+        L.set_step_fusion(4)
     L.set_step_fusion(1)
 
 
