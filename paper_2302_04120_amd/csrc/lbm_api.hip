@@ -143,7 +143,7 @@ lbm_status check_desc(const lbm_desc* d, Layout* L, std::string* err) {
     l.offPhi = off; off += d->lattice == LBM_D3Q19_PHASE ? align256((size_t)l.P * l.es) : 0;
     // D2Q9_PHASE: per-tile step counters and the error word of the
     // many-steps-per-launch kernel
-    l.offFlags = off; off += d->lattice == LBM_D2Q9_PHASE ? 256 : 0;
+    l.offFlags = off; off += d->lattice == LBM_D2Q9_PHASE ? kPersistFlagBytes : 0;
     l.total = off;
     *L = l;
     return LBM_OK;
@@ -220,8 +220,8 @@ bool use_tb2(const lbm_ctx* c) {
     return phase_tb2_workgroups(c->pk) >= 512;
 }
 
-// The many-steps kernel needs the grid split into at most 16 tiles (of 512,
-// 256 or 128 nodes) over all replicas, all resident at once.
+// The many-steps kernel needs the grid split into at most kPersistMaxTiles
+// tiles (of 512, 256 or 128 nodes) over all replicas, all resident at once.
 bool phase_persist_fits_desc(const lbm_desc& d) {
     PhaseK k{};
     k.nx = d.nx;
@@ -239,7 +239,7 @@ bool use_persist(const lbm_ctx* c) {
 hipError_t reset_persist(lbm_ctx* c) {
     c->persist_epoch = 0;
     if (!c->persist_flags) return hipSuccess;
-    return hipMemsetAsync(c->persist_flags, 0, 256, c->stream);
+    return hipMemsetAsync(c->persist_flags, 0, kPersistFlagBytes, c->stream);
 }
 
 // n steps in launches of the many-steps kernel (at most kPersistChunk steps
@@ -247,7 +247,7 @@ hipError_t reset_persist(lbm_ctx* c) {
 constexpr int kPersistChunk = 1 << 14;
 template <typename S>
 lbm_status step_persist(lbm_ctx* c, int n) {
-    unsigned* err = c->persist_flags + 16;
+    unsigned* err = c->persist_flags + kPersistMaxTiles;
     for (int s = 0; s < n;) {
         const int m = std::min(kPersistChunk, n - s);
         hipError_t e = launch_phase_persist<S>(c->pk, (S*)bufA(c), (S*)bufB(c), m, c->persist_epoch,

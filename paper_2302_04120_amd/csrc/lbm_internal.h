@@ -151,7 +151,7 @@ struct lbm_ctx {
     // two-phase steps: 0 automatic, 1 single-step kernel only, 2 two-step
     // kernel whenever the grid allows it, 3 many steps per cooperative launch
     int fusion = 0;
-    unsigned* persist_flags = nullptr;  // [kPersistMaxTiles] step counters, then the error word
+    unsigned* persist_flags = nullptr;  // kPersistMaxTiles step counters, then the error word
     unsigned persist_epoch = 0;         // steps taken by persistent launches since the reset
 };
 
@@ -172,10 +172,15 @@ bool phase_tb2_fits(const PhaseK& k);
 long long phase_tb2_workgroups(const PhaseK& k);
 template <typename S>
 hipError_t launch_phase_tb2(const PhaseK& k, const S* a, S* b, hipStream_t s);
-// many steps in one cooperative launch for grids that split into at most 16
-// tiles of 512 threads (phase_persist_fits); flags: one step counter per tile
-// (zeroed with the state, advanced to epoch0 + steps), err: set when a
-// bounded wait ran out
+// many steps in one cooperative launch for grids that split into at most
+// kPersistMaxTiles tiles of 512 threads (phase_persist_fits); flags: one step
+// counter per tile (zeroed with the state, advanced to epoch0 + steps), err:
+// set when a bounded wait ran out
+#ifndef LBM_PERSIST_MAX_TILES
+#define LBM_PERSIST_MAX_TILES 16
+#endif
+constexpr int kPersistMaxTiles = LBM_PERSIST_MAX_TILES;
+constexpr size_t kPersistFlagBytes = 256 * ((kPersistMaxTiles + 1) * 4 / 256 + 1);
 bool phase_persist_fits(const PhaseK& k);
 template <typename S>
 hipError_t launch_phase_persist(const PhaseK& k, S* A, S* B, int nsteps, unsigned epoch0,

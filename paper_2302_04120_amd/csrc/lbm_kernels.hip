@@ -553,7 +553,6 @@ __global__ __launch_bounds__(TX * TY) void k_phase(PhaseK k, const S* __restrict
 // always drains.  The per-tile work is phase_tile, as in k_phase, so the
 // states agree with single-step launches to the last bit.
 // ---------------------------------------------------------------------------
-constexpr int kPersistMaxTiles = 16;
 constexpr unsigned kPersistSpin = 1u << 22;  // polls before a wait counts as failed
 
 template <typename S, int TX, int TY>
@@ -579,15 +578,24 @@ __global__ __launch_bounds__(TX * TY) void k_phase_persist(PhaseK k, S* __restri
     // walls); a one-node ragged tail reaches further, and then the tile waits
     // for every tile of its replica.
     const bool thin = (gx > 1 && k.nx - (gx - 1) * TX < 2) || (gy > 1 && k.ny - (gy - 1) * TY < 2);
-    auto waits_for = [&](int rt) {
-        const int ddx = min(abs(rt % gx - bx), gx - abs(rt % gx - bx));  // x periodic
-        const int ddy = k.bcy ? abs(rt / gx - by) : min(abs(rt / gx - by), gy - abs(rt / gx - by));
-        return rt != r && (thin || (ddx <= 1 && ddy <= 1));
-    };
     const int lin = threadIdx.y * TX + threadIdx.x;
-    // lane j of the first wave watches tile j of the replica (at most 16)
-    const bool watch = lin < gx * gy && waits_for(lin);
-    const unsigned* wflag = flags + b * gx * gy + (watch ? lin : 0);
+    // Lanes of the first wave watch one tile each: lane j < 8 the j-th of
+    // the eight surrounding tiles (x wraps; y wraps unless walls close it),
+    // or, for a one-node tail, lane j tile j of the replica (at most 64).
+    int wt = -1;
+    if (thin) {
+        if (lin < gx * gy && lin != r) wt = lin;
+    } else if (lin < 8) {
+        const int j = lin < 4 ? lin : lin + 1;  // skip the centre of the 3 x 3 block
+        const int ox = j % 3 - 1, oy = j / 3 - 1;
+        int ty_ = by + oy;
+        const bool outside = ty_ < 0 || ty_ >= gy;
+        ty_ = (ty_ + gy) % gy;
+        const int t = ty_ * gx + (bx + ox + gx) % gx;
+        if (!(outside && k.bcy) && t != r) wt = t;
+    }
+    const bool watch = wt >= 0;
+    const unsigned* wflag = flags + b * gx * gy + (watch ? wt : 0);
     if (lin == 0) bad = 0;
     for (int s = 0; s < nsteps; ++s) {
         if (s > 0 && lin < 64) {
@@ -1242,11 +1250,21 @@ long long persist_tiles(const PhaseK& k, int threads) {
     return (long long)((k.nx + tx - 1) / tx) * ((k.ny + ty - 1) / ty) * k.batch;
 }
 
-// The smallest workgroup (most tiles, least work per CU) whose tiles number
-// at most kPersistMaxTiles; 0 if none does.
+// At most kPersistMaxTiles tiles; with a one-node tail every tile of a
+// replica is watched by one wave, so a replica then has at most 64.
+bool persist_ok(const PhaseK& k, int threads) {
+    int tx, ty;
+    persist_shape(k, threads, &tx, &ty);
+    const int gx = (k.nx + tx - 1) / tx, gy = (k.ny + ty - 1) / ty;
+    const bool thin = (gx > 1 && k.nx - (gx - 1) * tx < 2) || (gy > 1 && k.ny - (gy - 1) * ty < 2);
+    return persist_tiles(k, threads) <= kPersistMaxTiles && !(thin && (long long)gx * gy > 64);
+}
+
+// The smallest workgroup (most tiles, least work per CU) that fits; 0 if
+// none does.
 int persist_threads(const PhaseK& k) {
     for (int t = LBM_PERSIST_MIN_THREADS; t <= 512; t *= 2)
-        if (persist_tiles(k, t) <= kPersistMaxTiles) return t;
+        if (persist_ok(k, t)) return t;
     return 0;
 }
 
