@@ -208,6 +208,36 @@ def run_layered_batch(batch, steps, warmup, prec):
                 hbm_frac=gbs / HBM_PEAK_GBS, replicas=batch, grid="4x512")
 
 
+def run_c4_single(steps=20000, warmup=200, prec="fp32"):
+    """One C4 replica (4 x 512 nodes, walls), launch-bound: microseconds per
+    step with graph replay of single-step launches and with the many-steps
+    kernel (step fusion mode 3), and whether the two end in the same state."""
+    import torch
+    from paper_2302_04120_amd import lbm, workloads as WL
+    prm, ini, _ = WL.layered(nx=4, ny=512, batch=1, seed=0)
+    out = {}
+    states = {}
+    for name, fusion, graph in (("graph_replay", 1, 64), ("many_steps", 3, 0)):
+        L = lbm.Lattice("phase", 4, 512, batch=1, prec=prec, bc=(0, 0, lbm.BC_WALL, lbm.BC_WALL))
+        L.set_step_fusion(fusion)
+        L.set_graph_steps(graph)
+        L.set_params(prm)
+        L.init(ini["p"], ini["ux"], ini["uy"], None, ini["phi"])
+        L.step(warmup)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(L.stream)
+        L.step(steps)
+        e1.record(L.stream)
+        torch.cuda.synchronize()
+        out[name + "_us_per_step"] = e0.elapsed_time(e1) / steps * 1e3
+        states[name] = L.save_state()
+    out["bit_identical"] = states["graph_replay"] == states["many_steps"]
+    out["steps"] = steps
+    return out
+
+
 def adjoint_cost(steps=20000, ckpt=500, prec="fp32"):
     """Adjoint/forward cost on the C5 heated channel (1600 x 80 nodes, flow from
     rest): plain forward time, record time (forward + checkpoints) and the
@@ -285,7 +315,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP64 and batch-4 legs")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_phase_step.json"))
-    ap.add_argument("--leg", choices=("channel", "adjoint", "d3q19", "phase3d", "layered"),
+    ap.add_argument("--leg", choices=("channel", "adjoint", "d3q19", "phase3d", "layered", "c4single"),
                     default=None,
                     help="only run one secondary leg and print its figures (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -308,6 +338,9 @@ def main():
         return 0
     if args.leg == "layered":
         print(json.dumps(run_layered_batch(4096, args.steps, args.warmup, args.prec)), flush=True)
+        return 0
+    if args.leg == "c4single":
+        print(json.dumps(run_c4_single(args.steps, args.warmup, args.prec)), flush=True)
         return 0
     if args.gpus != 1:
         print("bench.py measures one GPU only; --gpus %d is not supported" % args.gpus,
@@ -348,6 +381,8 @@ def main():
         extras["paper_config_batch4_mlups"] = r4["nodes"] * 1000 / r4["wall"] / 1e6
         log("bench: C4 layered batch leg (4096 x 4 x 512)")
         extras["layered_batch_fp32"] = run_layered_batch(4096, 200, 20, "fp32")
+        log("bench: C4 single replica, graph replay and many-steps kernel")
+        extras["c4_single_replica"] = run_c4_single()
         log("bench: heated-channel leg (16384 x 2048)")
         extras["channel_fp32"] = run_channel(16384, 2048, 100, 10, "fp32")
         log("bench: D3Q19 leg (256^3)")
