@@ -64,6 +64,7 @@ def run_gpu(batch, steps, warmup, prec, n=256, fusion=0):
     L.set_params(prm)
     L.init(ini["p"], ini["ux"], ini["uy"], None, ini["phi"])
     del ini
+    phase0 = L.reduce(("phase",))["phase"]
     L.step(warmup)
     stream = L.stream
     torch.cuda.synchronize()
@@ -80,8 +81,10 @@ def run_gpu(batch, steps, warmup, prec, n=256, fusion=0):
     if red["nonfinite"].sum() != 0:
         raise RuntimeError("non-finite populations after the timed steps")
     nodes = batch * n * n
+    # sum of phi per replica, FP64 reduction: drift over warm-up + timed steps
+    drift = float((abs(red["phase"] - phase0) / abs(phase0)).max())
     return dict(wall=wall, ev_ms=ev_ms, nodes=nodes, kernel_ms=ev_ms / steps,
-                bytes_gb=L.bytes / 1e9)
+                bytes_gb=L.bytes / 1e9, phi_sum_drift=drift)
 
 
 def run_channel(nx, ny, steps, warmup, prec):
@@ -284,9 +287,48 @@ def cpu_baseline(seconds=12.0):
         ph.step(10)
         steps += 10
     dt = time.perf_counter() - t0
-    return dict(value=256 * 256 * steps / dt / 1e6, unit="MLUPS", cores=1, kind="oracle",
+    base = dict(value=256 * 256 * steps / dt / 1e6, unit="MLUPS", cores=1, kind="oracle",
                 sample="one 256x256 replica of the bubble workload, %d steps, FP64, single thread"
                        % steps)
+    return base, parity_vs_oracle(prm, ini, ph.macros(), steps)
+
+
+def parity_vs_oracle(prm, ini, mo_long, steps_long, steps_short=20):
+    """The GPU path on the oracle's sample (replica 0 of the bench workload;
+    FP32 deviation storage with the bench's two-step kernel, and FP64).
+    Pointwise after a short horizon: max |GPU - oracle| per field relative to
+    the field's scale (1 for phi; max |p| or sigma / W for p; max |u| for u).
+    After the CPU sample's long horizon, where the model amplifies rounding
+    differences (the interface normal flips where grad phi passes through
+    zero), the observables: the bubble's pressure jump and the phi sum."""
+    import numpy as np
+    import oracle as O
+    from paper_2302_04120_amd import lbm
+    o = O.Phase(256, 256, prm)
+    o.init(ini["phi"][0], ini["p"][0], ini["ux"][0], ini["uy"][0])
+    o.step(steps_short)
+    mo = o.macros()
+    scale_p = max(float(np.abs(mo["p"]).max()), prm["sigma"] / prm["W"])
+    scale_u = max(float(np.abs(mo["ux"]).max()), float(np.abs(mo["uy"]).max()), 1e-300)
+    scales = {"phi": 1.0, "p": scale_p, "ux": scale_u, "uy": scale_u}
+    gas, liq = mo_long["phi"] < 0.01, mo_long["phi"] > 0.99
+    jump = lambda m: float(m["p"][gas].mean() - m["p"][liq].mean())
+    out = {"pointwise_steps": steps_short, "long_steps": steps_long, "replica": 0,
+           "oracle_dP_Pa": jump(mo_long)}
+    for prec, fusion in (("fp32", 2), ("fp64", 1)):
+        L = lbm.Lattice("phase", 256, 256, batch=1, prec=prec)
+        L.set_step_fusion(fusion)
+        L.set_params(prm)
+        L.init(ini["p"][:1], ini["ux"][:1], ini["uy"][:1], None, ini["phi"][:1])
+        L.step(steps_short)
+        g = L.macros(tuple(scales))
+        r = {"pointwise": {k: float(np.abs(g[k][0] - mo[k]).max() / sc) for k, sc in scales.items()}}
+        L.step(steps_long - steps_short)
+        g = {k: v[0] for k, v in L.macros(("p", "phi")).items()}
+        r["dP_rel"] = abs(jump(g) / jump(mo_long) - 1.0)
+        r["phi_sum_rel"] = abs(float(g["phi"].sum()) / float(mo_long["phi"].sum()) - 1.0)
+        out[prec] = r
+    return out
 
 
 def copy_calibration(nbytes, reps=5):
@@ -392,10 +434,10 @@ def main():
         extras["phase3d_fp32"] = run_p3(256, 40, 4, "fp32")
         log("bench: adjoint/forward cost leg (C5 channel)")
         extras["adjoint"] = adjoint_cost()
-    cpu = None
+    cpu = parity = None
     if not args.no_cpu_baseline:
-        log("bench: CPU oracle baseline")
-        cpu = cpu_baseline()
+        log("bench: CPU oracle baseline and parity of the GPU path on its sample")
+        cpu, parity = cpu_baseline()
     line = {
         "metric": "MLUPS (D2Q9 MRT + Allen-Cahn) FP32-dev vs FP64, % HBM roofline; adjoint/fwd cost",
         "value": mlups,
@@ -423,6 +465,8 @@ def main():
                      "hbm_measured_frac": (traffic / (launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS
                                            if traffic is not None else None)},
         "cpu_baseline": cpu,
+        "parity_vs_oracle": parity,
+        "phi_sum_drift": r["phi_sum_drift"],
         "adjoint_over_forward": None,
     }
     line.update(extras)
