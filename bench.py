@@ -274,6 +274,20 @@ def adjoint_cost(steps=20000, ckpt=500, prec="fp32"):
                 forward_mlups=nx * ny * steps / t_fwd / 1e6)
 
 
+def host_cpu():
+    """Logical CPUs visible to this process and the CPU model name."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": len(os.sched_getaffinity(0)), "model": model}
+
+
 def cpu_baseline(seconds=12.0):
     """The FP64 oracle on one 256 x 256 replica of the same workload."""
     import oracle as O
@@ -289,7 +303,7 @@ def cpu_baseline(seconds=12.0):
     dt = time.perf_counter() - t0
     base = dict(value=256 * 256 * steps / dt / 1e6, unit="MLUPS", cores=1, kind="oracle",
                 sample="one 256x256 replica of the bubble workload, %d steps, FP64, single thread"
-                       % steps)
+                       % steps, host=host_cpu())
     return base, parity_vs_oracle(prm, ini, ph.macros(), steps)
 
 

@@ -195,7 +195,9 @@ LBM_API lbm_status lbm_init_fields(lbm_ctx* ctx, const double* rho_or_p, const d
  * results, one launch instead of many on small grids); the remainder and
  * every step whose arguments change with time (the oscillating wall flux)
  * are launched one by one.  No replay is used while desc.hip_stream is being
- * captured by the caller. */
+ * captured by the caller.  A caller that captures lbm_step(n) and replays the
+ * graph gets n steps per replay from the buffer the capture started in, so n
+ * must be even; lbm_time counts the captured steps once. */
 LBM_API lbm_status lbm_step(lbm_ctx* ctx, int n);
 
 /* Steps per captured graph used by lbm_step (default 64; 0 disables graph
@@ -223,7 +225,8 @@ LBM_API lbm_status lbm_set_graph_steps(lbm_ctx* ctx, int steps);
  *           most 16 tiles of 128 or 256 nodes run on those.
  *           lbm_step then synchronises the stream before it returns, to read
  *           the kernel's error word: a wait that timed out (a failed launch
- *           neighbour) gives LBM_E_DEVICE and drops the state.  The step
+ *           neighbour) gives LBM_E_DEVICE and drops the state.  While the
+ *           stream is being captured, steps use the single-step kernel.  The step
  *           counters live in the context's buffer and are reset by
  *           lbm_init_fields and lbm_load_state.
  *   mode 0 (default): mode 2 when its workgroups (one per 128-row segment of

@@ -230,8 +230,13 @@ bool phase_persist_fits_desc(const lbm_desc& d) {
     return phase_persist_fits(k);
 }
 
+// Under the caller's stream capture the steps take the single-step kernel
+// (same states): the many-steps path ends with a synchronisation.
 bool use_persist(const lbm_ctx* c) {
-    return c->desc.lattice == LBM_D2Q9_PHASE && c->fusion == 3 && phase_persist_fits(c->pk);
+    if (c->desc.lattice != LBM_D2Q9_PHASE || c->fusion != 3 || !phase_persist_fits(c->pk))
+        return false;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(c->stream, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone;
 }
 
 // Zero the step counters and the error word: with the state (re)set no

@@ -104,3 +104,43 @@ def test_graph_steps_validation():
     L.set_graph_steps(4)
     L.step(9)
     assert L.t == 9
+
+
+@pytest.mark.parametrize("fusion", [1, 3])
+def test_caller_captured_steps_replay(fusion):
+    """A caller that captures lbm_step(n) on its own stream (torch's graph
+    capture) and replays the graph gets n more steps per replay: the capture
+    takes single-step launches whatever the step fusion mode (the many-steps
+    kernel synchronises and so is not captured), and every replay matches
+    eager single-step launches to the bit.  n is even, so each replay starts
+    from the buffer the capture started in."""
+    import torch
+    from paper_2302_04120_amd import lbm
+    nx, ny, n = 64, 48, 8
+    prm, ini, _ = WL.bubble(n=nx, ny=ny, radii=(10,), batch=1, seed=4)
+    print_case(test="caller-capture", fusion=fusion)
+    s = torch.cuda.Stream()
+
+    def make(stream, mode):
+        L = lbm.Lattice("phase", nx, ny, batch=1, prec="fp32", stream=stream)
+        L.set_step_fusion(mode)
+        L.set_params(prm)
+        L.init(ini["p"], ini["ux"], ini["uy"], None, ini["phi"])
+        return L
+
+    cap = make(s, fusion)
+    ref = make(None, 1)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        cap.step(n)
+    assert cap.t == n  # counted once, at capture
+    fields = ("phi", "p", "ux", "uy")
+    for rep in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        ref.step(n)
+        a, b = cap.macros(fields), ref.macros(fields)
+        for k in fields:
+            assert np.array_equal(a[k], b[k]), (rep, k)
+        assert ref.reduce(("nonfinite",))["nonfinite"].sum() == 0
