@@ -117,3 +117,25 @@ def test_tiny_phase3d_grids(nx, ny, nz, bcs):
     print(errs, flush=True)
     for k, v in errs.items():
         assert v < FP64_TOL, (k, v)
+
+
+@pytest.mark.parametrize("nx,ny", [(2, 1), (3, 2), (5, 1)])
+def test_tiny_heated_channel_grids(nx, ny):
+    """The heated channel (D2Q9 MRT flow, D2Q5 thermal, velocity inlet next
+    to the pressure outlet, flux walls that reflect into the same row when ny
+    = 1, oscillating flux), FP64, 30 steps.  Velocity errors are taken on the
+    scale of |u| (u_y is zero to rounding in one-row channels)."""
+    from gpu_cases import channel_pair, density_scale
+    print_case(test="tiny-channel", nx=nx, ny=ny)
+    prm, ini = WL.channel(nx=nx, ny=ny, dx=5e-5, tau_ratio=0.6, oscillating=True)
+    g, o, _, _ = channel_pair(prm, ini, nx, ny, 30, "fp64")
+    c = prm["dx"] / prm["dt"]
+    umax = float(np.hypot(o["ux"], o["uy"]).max())
+    rs = density_scale(o["rho"], prm["rho_ref"], np.hypot(o["ux"], o["uy"]), c)
+    errs = {"rho": rel_err(g["rho"], o["rho"], prm["rho_ref"], scale=rs),
+            "ux": rel_err(g["ux"], o["ux"], scale=umax),
+            "uy": rel_err(g["uy"], o["uy"], scale=umax),
+            "T": rel_err(g["T"], o["T"], prm["T_ref"])}
+    print(errs, flush=True)
+    for k, v in errs.items():
+        assert v < FP64_TOL, (k, v)
