@@ -38,7 +38,12 @@ def _rel(a, b):
     return float(np.abs(a - b).max() / np.abs(b).max())
 
 
-@pytest.mark.parametrize("nx,ny,steps,ckpt,osc", [(16, 6, 300, 64, False), (70, 12, 400, 64, True)])
+@pytest.mark.parametrize("nx,ny,steps,ckpt,osc", [(16, 6, 300, 64, False), (70, 12, 400, 64, True),
+                                                   # degenerate: inlet beside outlet, one-row
+                                                   # channel, segments that do not divide the
+                                                   # run, a checkpoint every step
+                                                   (2, 1, 40, 16, False), (3, 2, 50, 7, True),
+                                                   (4, 3, 20, 1, False)])
 def test_adjoint_fp64_matches_oracle_adjoint(nx, ny, steps, ckpt, osc):
     print_case(test="adj_fp64", nx=nx, ny=ny, steps=steps)
     prm, ini = _case(nx, ny, 1e-4, oscillating=osc)
