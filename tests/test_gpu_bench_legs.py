@@ -100,3 +100,36 @@ def test_channel_leg_interior_against_periodic_oracle():
         print("column", x, e, flush=True)
         for k, v in e.items():
             assert v < FP32_TOL, (x, k, v)
+
+
+@pytest.mark.timeout(300)
+def test_fp64_bubble_leg_sampled():
+    """The bench's FP64 leg: 256 replicas of the 256 x 256 bubble cell with
+    the two-step kernel, 20 steps; sampled replicas against the oracle to
+    FP64 rounding."""
+    from paper_2302_04120_amd import lbm
+    from gpu_cases import FP64_TOL
+    batch, n, steps = 256, 256, 20
+    prm, ini, _ = WL.bubble(n=n, batch=batch, seed=0)
+    print_case(test="fp64-bubble-leg", batch=batch, steps=steps)
+    L = lbm.Lattice("phase", n, n, batch=batch, prec="fp64")
+    L.set_step_fusion(2)
+    L.set_params(prm)
+    L.init(ini["p"], ini["ux"], ini["uy"], None, ini["phi"])
+    L.step(steps)
+    assert L.reduce(("nonfinite",))["nonfinite"].sum() == 0
+    g = L.macros(("phi", "p", "ux", "uy"))
+    for b in (0, 129, 255):
+        o = O.Phase(n, n, prm)
+        o.init(ini["phi"][b], ini["p"][b], ini["ux"][b], ini["uy"][b])
+        o.step(steps)
+        mo = o.macros()
+        umax = max(float(np.abs(mo["ux"]).max()), float(np.abs(mo["uy"]).max()))
+        scale_p = max(float(np.abs(mo["p"]).max()), prm["sigma"] / prm["W"])
+        e = {"phi": rel_err(g["phi"][b], mo["phi"], scale=1.0),
+             "p": rel_err(g["p"][b], mo["p"], scale=scale_p),
+             "ux": rel_err(g["ux"][b], mo["ux"], scale=umax),
+             "uy": rel_err(g["uy"][b], mo["uy"], scale=umax)}
+        print("replica", b, e, flush=True)
+        for k, v in e.items():
+            assert v < FP64_TOL, (b, k, v)
