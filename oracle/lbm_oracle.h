@@ -13,6 +13,18 @@
  * with x fastest.  One time step = macros -> equilibria/sources -> collision
  * -> streaming -> boundary substitution (Sec. 2.1, Eq. eq_lattice_boltzmann_geral
  * and the text following Eq. colisao_MRT).
+ *
+ * Pins: the CPU tests hold these functions to closed forms, printed values,
+ * invariants and brute force.  Parity unpinned (no closed form or printed
+ * value exists; only the kernel-oracle comparison holds them):
+ *   - orc_chan_* with flux_amp != 0: the mean Nu of the oscillating flux;
+ *   - orc_phase_*: the spurious-current pattern around a bubble;
+ *   - orc_chan_adjoint: the gradients with respect to the relaxation times
+ *     (held by central differences of the oracle's own forward run and by
+ *     the hand-written FP64 adjoint, not by an independent value);
+ *   - orc_d3_*: the rates of the energy-square and pi moments (and of m
+ *     beyond its part in the Poiseuille slip), which act beyond the
+ *     second-order hydrodynamics that the pins measure.
  */
 #ifndef LBM_ORACLE_H
 #define LBM_ORACLE_H
