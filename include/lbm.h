@@ -224,8 +224,9 @@ LBM_API lbm_status lbm_set_graph_steps(lbm_ctx* ctx, int steps);
  *           16, 32), LBM_E_UNSUPPORTED otherwise; grids that split into at
  *           most 16 tiles of 128 or 256 nodes run on those.
  *           lbm_step then synchronises the stream before it returns, to read
- *           the kernel's error word: a wait that timed out (a failed launch
- *           neighbour) gives LBM_E_DEVICE and drops the state.  While the
+ *           the kernel's error word: a wait that timed out (a neighbour that
+ *           failed, or that other work on the GPU kept from becoming
+ *           resident for seconds) gives LBM_E_DEVICE and drops the state.  While the
  *           stream is being captured, steps use the single-step kernel.  The step
  *           counters live in the context's buffer and are reset by
  *           lbm_init_fields and lbm_load_state.
