@@ -103,7 +103,7 @@ def test_autograd_function_matches_lbm_grad():
     J = prob.J(flux, tau)
     (2.0 * J).backward()
     J0, gq0, gt0 = _oracle_adjoint(prm, ini, nx, ny, 200, 50)
-    assert float(J) == pytest.approx(J0, rel=1e-12)
+    assert float(J.detach()) == pytest.approx(J0, rel=1e-12)
     assert _rel(flux.grad.numpy(), 2 * gq0) < 1e-9
     np.testing.assert_allclose(tau.grad.numpy(), 2 * gt0, rtol=1e-8)
 
