@@ -118,6 +118,7 @@ def _declare(L):
     L.orc_d3_step.argtypes = [C.c_void_p, C.c_long]
     L.orc_d3_macros.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp]
     L.orc_d3_get_state.argtypes = [C.c_void_p, _dp]
+    L.orc_d3_set_state.argtypes = [C.c_void_p, _dp]
     L.orc_p3_create.restype = C.c_void_p
     L.orc_p3_create.argtypes = [C.POINTER(P3Params)]
     L.orc_p3_destroy.argtypes = [C.c_void_p]
@@ -371,6 +372,9 @@ class D3:
         f = np.zeros((19,) + self.shape)
         lib().orc_d3_get_state(self.h, _ptr(f))
         return f
+
+    def set_state(self, f):
+        lib().orc_d3_set_state(self.h, _ptr(_f64(f, (19,) + self.shape)))
 
 
 class Phase3:

@@ -1448,6 +1448,10 @@ void orc_d3_get_state(const orc_d3* s, double* f) {
     memcpy(f, s->f, sizeof(double) * 19 * (size_t)s->p.nx * s->p.ny * s->p.nz);
 }
 
+void orc_d3_set_state(orc_d3* s, const double* f) {
+    memcpy(s->f, f, sizeof(double) * 19 * (size_t)s->p.nx * s->p.ny * s->p.nz);
+}
+
 /* ------------------------------------------------------------------------- */
 /* 3D two-phase model: the conservative Allen-Cahn h_i and the pressure-      */
 /* evolution z_i of Sec. 2.3 on D3Q19, z_i with the dimensional MRT of Sec. 3 */

@@ -21,10 +21,7 @@
  *   - orc_phase_*: the spurious-current pattern around a bubble;
  *   - orc_chan_adjoint: the gradients with respect to the relaxation times
  *     (held by central differences of the oracle's own forward run and by
- *     the hand-written FP64 adjoint, not by an independent value);
- *   - orc_d3_*: the rates of the energy-square and pi moments (and of m
- *     beyond its part in the Poiseuille slip), which act beyond the
- *     second-order hydrodynamics that the pins measure.
+ *     the hand-written FP64 adjoint, not by an independent value).
  */
 #ifndef LBM_ORACLE_H
 #define LBM_ORACLE_H
@@ -154,6 +151,7 @@ void orc_d3_init(orc_d3* s, const double* rho, const double* ux, const double* u
 void orc_d3_step(orc_d3* s, long nsteps);
 void orc_d3_macros(const orc_d3* s, double* rho, double* ux, double* uy, double* uz);
 void orc_d3_get_state(const orc_d3* s, double* f /*[19][nz][ny][nx]*/);
+void orc_d3_set_state(orc_d3* s, const double* f /*[19][nz][ny][nx]*/);
 
 /* ---- 3D two-phase model (Sec. 2.3 on D3Q19, z_i with the dimensional MRT) ---- */
 typedef struct {

@@ -288,3 +288,49 @@ def test_square_duct_flow_converges_to_the_series(mrt, tau_hat):
         errs.append(np.abs(u - ex).max() / ex.max())
     assert errs[1] < 5e-3
     assert errs[0] / errs[1] > 3.0
+
+
+@pytest.mark.parametrize("mrt", [True, False])
+def test_each_moment_of_a_uniform_state_relaxes_at_its_rate(mrt):
+    """A uniform state on a periodic box streams into itself, so a step is a
+    bare collision (no force).  Perturbed along one non-conserved row k of
+    the basis, f = f_eq + eps c^order_k M^-1 e_k, the conserved moments and
+    so f_eq stay put, and the perturbation of row k shrinks by exactly
+    1 - s_k per step with no other row excited (Eq. colisao_MRT is diagonal
+    in the moment basis).  This holds every rate, including the eps, pi and m
+    rows that no hydrodynamic pin reaches.  Expected rates (the reading of
+    Sec. 3 in the d'Humieres basis): e and eps at omega_e dt and omega_eps
+    dt, the five stresses at dt/tau, pi at 1, q and m at the s_q with
+    (1/s_nu - 1/2)(1/s_q - 1/2) = 1/12 (the Lambda of the Poiseuille pin);
+    BGK: every non-conserved row at dt/tau."""
+    prm = _prm(tau_hat=0.8, omega_e=0.0, omega_eps=0.0)
+    dt = prm["dt"]
+    prm["omega_e"], prm["omega_eps"] = 1.3 / dt, 0.7 / dt
+    c = prm["dx"] / dt
+    s_nu = 1.0 / 0.8
+    s_q = 1.0 / (0.5 + (1.0 / 12.0) / (1.0 / s_nu - 0.5))
+    if mrt:
+        s = [None, 1.3, 0.7, None, s_q, None, s_q, None, s_q, s_nu, 1.0, s_nu, 1.0, s_nu, s_nu,
+             s_nu, s_q, s_q, s_q]
+    else:
+        s = [None if k in (0, 3, 5, 7) else s_nu for k in range(19)]
+    M, Mi = O.d3_mdim(c)
+    scale = np.array([c ** o for o in ORDER])
+    o = O.D3(2, 2, 2, prm, mrt=mrt)
+    o.init(np.full((2, 2, 2), 1000.2), np.full((2, 2, 2), 2e-3), np.full((2, 2, 2), -1e-3),
+           np.full((2, 2, 2), 1.5e-3))
+    f0 = o.get_state()
+    m0 = np.einsum("ki,izyx->kzyx", M, f0) / scale[:, None, None, None]
+    eps = 1e-3 * 1000.0
+    for k in range(19):
+        if s[k] is None:
+            continue
+        o.set_state(f0 + eps * scale[k] * Mi[:, k][:, None, None, None])
+        for n in (1, 2):
+            o.step(1)
+            m = np.einsum("ki,izyx->kzyx", M, o.get_state()) / scale[:, None, None, None]
+            dm = (m - m0) / eps
+            want = np.zeros(19)
+            want[k] = (1.0 - s[k]) ** n
+            np.testing.assert_allclose(dm, np.broadcast_to(want[:, None, None, None], dm.shape),
+                                       rtol=0, atol=1e-9, err_msg="row %d, step %d" % (k, n))

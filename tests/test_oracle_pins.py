@@ -542,3 +542,45 @@ def test_symmetry_plane_half_channel_equals_full_channel(tq):
     np.testing.assert_allclose(mf["T"][nh:][::-1], mf["T"][:nh], rtol=1e-12)
     # and the half channel's Nusselt number is the full channel's
     np.testing.assert_allclose(half.nusselt()[2], full.nusselt()[2], rtol=1e-9)
+
+
+@pytest.mark.parametrize("mrt", [1, 0])
+def test_each_moment_of_a_uniform_state_relaxes_at_its_rate_d2q9(mrt):
+    """Eq. colisao_MRT with the rates of Sec. 3 (Eq. M_matrix basis): a
+    uniform state on a periodic grid streams into itself, so a step is a bare
+    collision.  Perturbed along one non-conserved row k of the basis
+    (f = f_eq + eps c^order_k M^-1 e_k), its conserved moments and f_eq stay
+    put and row k's perturbation shrinks by exactly 1 - s_k per step with no
+    other row excited.  Expected: e and eps at omega_e dt and omega_eps dt,
+    q_x and q_y at the s_q with (1/s_nu - 1/2)(1/s_q - 1/2) = 1/12 (the
+    Lambda of the Poiseuille pin), p_xx and p_xy at dt/tau; BGK: dt/tau on
+    every non-conserved row."""
+    order = [0, 2, 4, 1, 3, 1, 3, 2, 2]
+    dx, nu, tau_hat = 2.5e-5, 8.382e-7, 0.8
+    dt = (tau_hat - 0.5) * dx * dx / (3 * nu)
+    c = dx / dt
+    prm = dict(dx=dx, dt=dt, rho_ref=996.279, nu=nu, flow_mrt=mrt, omega_e=1.3 / dt,
+               omega_eps=0.7 / dt)
+    s_nu = 1.0 / tau_hat
+    s_q = 1.0 / (0.5 + (1.0 / 12.0) / (1.0 / s_nu - 0.5))
+    s = ([None, 1.3, 0.7, None, s_q, None, s_q, s_nu, s_nu] if mrt else
+         [None, s_nu, s_nu, None, s_nu, None, s_nu, s_nu, s_nu])
+    M, Mi = O.mdim(c)
+    scale = np.array([c ** o for o in order])
+    ch = O.Chan(2, 2, prm)
+    ch.init(np.full((2, 2), 996.5), np.full((2, 2), 3e-3), np.full((2, 2), -2e-3))
+    f0, g0 = ch.get_state()
+    m0 = np.einsum("ki,iyx->kyx", M, f0) / scale[:, None, None]
+    eps = 1e-3 * 996.279
+    for k in range(9):
+        if s[k] is None:
+            continue
+        ch.set_state(f0 + eps * scale[k] * Mi[:, k][:, None, None], g0)
+        for n in (1, 2):
+            ch.step(1)
+            m = np.einsum("ki,iyx->kyx", M, ch.get_state()[0]) / scale[:, None, None]
+            want = np.zeros(9)
+            want[k] = (1.0 - s[k]) ** n
+            np.testing.assert_allclose((m - m0) / eps,
+                                       np.broadcast_to(want[:, None, None], m.shape),
+                                       rtol=0, atol=1e-9, err_msg="row %d, step %d" % (k, n))
