@@ -584,3 +584,51 @@ def test_each_moment_of_a_uniform_state_relaxes_at_its_rate_d2q9(mrt):
             np.testing.assert_allclose((m - m0) / eps,
                                        np.broadcast_to(want[:, None, None], m.shape),
                                        rtol=0, atol=1e-9, err_msg="row %d, step %d" % (k, n))
+
+
+@pytest.mark.parametrize("tmrt", [1, 0])
+@pytest.mark.parametrize("tq", ["d2q5", "d2q9"])
+def test_each_thermal_moment_relaxes_at_its_rate(tq, tmrt):
+    """The thermal collision (Sec. 2.2 with Lambda_T,dim of Sec. 3 for D2Q9;
+    the two-rate D2Q5 reading) on a uniform periodic state with a frozen
+    uniform flow: a step is a bare collision, and a perturbation along one
+    non-conserved direction shrinks by exactly 1 - s per step with no other
+    direction excited.  D2Q5 directions come from the velocity set alone
+    (e_x, e_y, |e_i|^2 - 4/5 and e_x^2 - e_y^2 over the five velocities:
+    mutually orthogonal and orthogonal to T); D2Q9 uses the rows of Eq.
+    M_matrix_dim.
+    Expected: the heat flux rows at dt/tau_T and every other row at 1 (MRT);
+    dt/tau_T everywhere (BGK)."""
+    dx, dt, tauT_hat = 1e-4, 1e-3, 0.9
+    c = dx / dt
+    cs2 = c * c / 3
+    prm = dict(dx=dx, dt=dt, rho_ref=1000.0, nu=1e-6, alpha=(tauT_hat - 0.5) * dt * cs2,
+               thermal_mrt=tmrt, T_ref=300.0, rho_cp=4.2e6)
+    sT = 1.0 / tauT_hat
+    ch = O.Chan(2, 2, prm, flow=False, thermal=tq)
+    ch.init(np.full((2, 2), 1000.0), np.full((2, 2), 2e-3), np.full((2, 2), -1e-3),
+            np.full((2, 2), 310.0))
+    f0, g0 = ch.get_state()
+    if tq == "d2q5":
+        dirs = np.array([[0, 1, 0, -1, 0], [0, 0, 1, 0, -1], [-4, 1, 1, 1, 1],
+                         [0, 1, -1, 1, -1]], dtype=float)
+        rates = [sT, sT, 1.0, 1.0] if tmrt else [sT] * 4
+        proj = dirs / np.sum(dirs * dirs, axis=1)[:, None]  # orthogonal: dual = scaled rows
+    else:
+        M, Mi = O.mdim(c)
+        rows = [1, 2, 3, 4, 5, 6, 7, 8]
+        dirs = Mi[:, rows].T
+        proj = M[rows]
+        rates = [sT if k in (3, 5) else 1.0 for k in rows] if tmrt else [sT] * len(rows)
+    amp = 0.1
+    for d, (v, s) in enumerate(zip(dirs, rates)):
+        v = v * amp / np.abs(v).max()
+        ch.set_state(f0, g0 + v[:, None, None])
+        for n in (1, 2):
+            ch.step(1)
+            coef = np.einsum("ki,iyx->kyx", proj, ch.get_state()[1] - g0)
+            want = np.zeros(len(dirs))
+            want[d] = (1.0 - s) ** n
+            ref = np.einsum("ki,i->k", proj, v)[d]
+            np.testing.assert_allclose(coef / ref, np.broadcast_to(want[:, None, None], coef.shape),
+                                       rtol=0, atol=1e-9, err_msg="%s direction %d step %d" % (tq, d, n))
