@@ -127,6 +127,7 @@ def _declare(L):
     L.orc_p3_macros.argtypes = [C.c_void_p] + [_dp] * 7
     L.orc_p3_gradients.argtypes = [C.c_void_p] + [_dp] * 4
     L.orc_p3_get_state.argtypes = [C.c_void_p, _dp, _dp, _dp]
+    L.orc_p3_set_state.argtypes = [C.c_void_p, _dp, _dp, _dp]
 
 
 def _f64(a, shape=None):
@@ -432,6 +433,11 @@ class Phase3:
         pu = np.zeros((3,) + self.shape)
         lib().orc_p3_get_state(self.h, _ptr(h), _ptr(z), _ptr(pu))
         return h, z, pu
+
+    def set_state(self, h, z, pu):
+        sh = self.shape
+        lib().orc_p3_set_state(self.h, _ptr(_f64(h, (19,) + sh)), _ptr(_f64(z, (19,) + sh)),
+                               _ptr(_f64(pu, (3,) + sh)))
 
 
 # --------------------------------------------------------------------------

@@ -1744,3 +1744,10 @@ void orc_p3_get_state(const orc_p3* s, double* h, double* z, double* phiu) {
     if (z) memcpy(z, s->z, sizeof(double) * 19 * N);
     if (phiu) memcpy(phiu, s->phiu, sizeof(double) * 3 * N);
 }
+
+void orc_p3_set_state(orc_p3* s, const double* h, const double* z, const double* phiu) {
+    size_t N = (size_t)s->p.nx * s->p.ny * s->p.nz;
+    if (h) memcpy(s->h, h, sizeof(double) * 19 * N);
+    if (z) memcpy(s->z, z, sizeof(double) * 19 * N);
+    if (phiu) memcpy(s->phiu, phiu, sizeof(double) * 3 * N);
+}

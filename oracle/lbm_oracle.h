@@ -178,6 +178,8 @@ void orc_p3_macros(const orc_p3* s, double* phi, double* rho, double* p, double*
 void orc_p3_gradients(const orc_p3* s, double* gx, double* gy, double* gz, double* lap);
 void orc_p3_get_state(const orc_p3* s, double* h /*[19]*/, double* z /*[19]*/,
                       double* phiu /*[3]*/);
+void orc_p3_set_state(orc_p3* s, const double* h /*[19]*/, const double* z /*[19]*/,
+                      const double* phiu /*[3]*/);
 
 #ifdef __cplusplus
 }

@@ -175,3 +175,45 @@ def test_dimensional_equals_conventional_3d_phase():
     for k in ("ux", "uy", "uz"):
         np.testing.assert_allclose(ma[k], mb[k] * Cu, rtol=0, atol=1e-9 * np.abs(ma[k]).max())
     np.testing.assert_allclose(ma["p"], mb["p"] * Cu * Cu, rtol=0, atol=1e-9 * np.abs(ma["p"]).max())
+
+
+def test_pressure_moments_of_a_uniform_state_relax_at_their_rates():
+    """The z_i collision (Sec. 2.3 with the MRT of Sec. 3, read row by row in
+    the d'Humieres basis) on a uniform state in a uniform flow: the
+    state streams into itself and phi is uniform (no gradient, no surface
+    force), so a step is a bare collision.  A perturbation along a row that
+    leaves z_0, sum z_i and j unchanged (every row but rho, e, eps and j, whose
+    perturbations would change the pressure or the velocity the equilibrium
+    is built from) shrinks by exactly 1 - s_k per step with no other row
+    excited: q and m at s_q = 3(2 - s_nu)/(3 - s_nu) (the 2D omega_q of
+    Sec. 3), the five stresses at s_nu = dt/tau(phi), pi at 1."""
+    prm, _ = WL.bubble3d(n=2, R_nodes=1.0, seed=0)  # its properties; phi set uniform below
+    dt, dx = prm["dt"], prm["dx"]
+    c = dx / dt
+    phi0 = 0.7
+    nu = prm["nu_g"] + phi0 * (prm["nu_l"] - prm["nu_g"])
+    s_nu = 1.0 / (3.0 * nu * dt / dx ** 2 + 0.5)
+    s_q = 3.0 * (2.0 - s_nu) / (3.0 - s_nu)
+    rates = {4: s_q, 6: s_q, 8: s_q, 9: s_nu, 10: 1.0, 11: s_nu, 12: 1.0, 13: s_nu, 14: s_nu,
+             15: s_nu, 16: s_q, 17: s_q, 18: s_q}
+    order = [0, 2, 4, 1, 3, 1, 3, 1, 3, 2, 4, 2, 4, 2, 2, 2, 3, 3, 3]
+    M, Mi = O.d3_mdim(c)
+    scale = np.array([c ** o for o in order])
+    sh = (2, 2, 2)
+    o = O.Phase3(2, 2, 2, prm)
+    o.init(np.full(sh, phi0), np.full(sh, 40.0), np.full(sh, 2e-3), np.full(sh, -1e-3),
+           np.full(sh, 1.5e-3))
+    o.step(1)  # (phi u) of the previous step now matches the state
+    h0, z0, pu0 = o.get_state()
+    m0 = np.einsum("ki,izyx->kzyx", M, z0) / scale[:, None, None, None]
+    eps = 1e-3
+    for k, s in rates.items():
+        o.set_state(h0, z0 + eps * scale[k] * Mi[:, k][:, None, None, None], pu0)
+        for n in (1, 2):
+            o.step(1)
+            m = np.einsum("ki,izyx->kzyx", M, o.get_state()[1]) / scale[:, None, None, None]
+            want = np.zeros(19)
+            want[k] = (1.0 - s) ** n
+            np.testing.assert_allclose((m - m0) / eps,
+                                       np.broadcast_to(want[:, None, None, None], m.shape),
+                                       rtol=0, atol=1e-8, err_msg="row %d, step %d" % (k, n))

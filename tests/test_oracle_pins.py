@@ -632,3 +632,43 @@ def test_each_thermal_moment_relaxes_at_its_rate(tq, tmrt):
             ref = np.einsum("ki,i->k", proj, v)[d]
             np.testing.assert_allclose(coef / ref, np.broadcast_to(want[:, None, None], coef.shape),
                                        rtol=0, atol=1e-9, err_msg="%s direction %d step %d" % (tq, d, n))
+
+
+@pytest.mark.parametrize("qy_printed", [0, 1])
+def test_pressure_moments_of_a_uniform_state_relax_at_their_rates(qy_printed):
+    """The z_i collision of Sec. 2.3 with the MRT rates of Sec. 3 on a
+    uniform state in a uniform flow: the state streams into itself and phi is
+    uniform (no gradient, no surface force), so a step is a bare collision.
+    A perturbation along q_x, q_y, p_xx or p_xy (rows that leave z_0, sum z_i
+    and j, hence the pressure and velocity of the equilibrium, unchanged)
+    shrinks by exactly 1 - s_k per step with no other row excited: q_x at
+    omega_q2 dt = 3(2 - s_nu)/(3 - s_nu); q_y the same, or 1 with the printed
+    q_y entry (reading 2); the stresses at s_nu = dt/tau(phi)."""
+    prm, _, _ = WL.bubble(n=2, radii=(1,), batch=1, seed=0)
+    prm["qy_printed"] = qy_printed
+    dt, dx = prm["dt"], prm["dx"]
+    c = dx / dt
+    phi0 = 0.7
+    nu = prm["nu_g"] + phi0 * (prm["nu_l"] - prm["nu_g"])
+    s_nu = 1.0 / (3.0 * nu * dt / dx ** 2 + 0.5)
+    s_q = 3.0 * (2.0 - s_nu) / (3.0 - s_nu)
+    rates = {4: s_q, 6: 1.0 if qy_printed else s_q, 7: s_nu, 8: s_nu}
+    order = [0, 2, 4, 1, 3, 1, 3, 2, 2]
+    M, Mi = O.mdim(c)
+    scale = np.array([c ** o for o in order])
+    o = O.Phase(2, 2, prm)
+    o.init(np.full((2, 2), phi0), np.full((2, 2), 40.0), np.full((2, 2), 2e-3),
+           np.full((2, 2), -1e-3))
+    o.step(1)  # (phi u) of the previous step now matches the state
+    h0, z0, pu0 = o.get_state()
+    m0 = np.einsum("ki,iyx->kyx", M, z0) / scale[:, None, None]
+    eps = 1e-3
+    for k, s in rates.items():
+        o.set_state(h0, z0 + eps * scale[k] * Mi[:, k][:, None, None], pu0)
+        for n in (1, 2):
+            o.step(1)
+            m = np.einsum("ki,iyx->kyx", M, o.get_state()[1]) / scale[:, None, None]
+            want = np.zeros(9)
+            want[k] = (1.0 - s) ** n
+            np.testing.assert_allclose((m - m0) / eps, np.broadcast_to(want[:, None, None], m.shape),
+                                       rtol=0, atol=1e-8, err_msg="row %d, step %d" % (k, n))
