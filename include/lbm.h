@@ -230,8 +230,11 @@ LBM_API lbm_status lbm_set_graph_steps(lbm_ctx* ctx, int steps);
  *           stream is being captured, steps use the single-step kernel.  The step
  *           counters live in the context's buffer and are reset by
  *           lbm_init_fields and lbm_load_state.
- *   mode 0 (default): mode 2 when its workgroups (one per 128-row segment of
- *           a replica) number at least 512, else mode 1.
+ *   mode 0 (default): mode 2 when its workgroups (one per segment of a
+ *           replica: the whole replica when it has fewer than 256 rows, or
+ *           at most 512 rows and the replicas alone fill the GPU's resident
+ *           workgroup slots; else 128 rows) number at least 512, else
+ *           mode 1.
  * The kernels evaluate the same per-node arithmetic in the same order, so
  * the modes agree to the last bit.  Not an operation of the paper: a
  * performance control.  Other lattices ignore it.  LBM_E_ARG on an unknown

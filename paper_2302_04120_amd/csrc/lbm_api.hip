@@ -215,9 +215,9 @@ hipError_t step_once(lbm_ctx* c) {
 // are resident per CU) fill the 256 CUs; smaller grids keep the single-step
 // kernel, whose tiles spread over more CUs.
 bool use_tb2(const lbm_ctx* c) {
-    if (c->desc.lattice != LBM_D2Q9_PHASE || c->fusion == 1 || !phase_tb2_fits(c->pk)) return false;
+    if (c->desc.lattice != LBM_D2Q9_PHASE || c->fusion == 1 || c->tb2_seg < 1) return false;
     if (c->fusion == 2) return true;
-    return phase_tb2_workgroups(c->pk) >= 512;
+    return phase_tb2_workgroups(c->pk, c->tb2_seg) >= 512;
 }
 
 // The many-steps kernel needs the grid split into at most kPersistMaxTiles
@@ -281,7 +281,8 @@ template <typename S>
 hipError_t advance(lbm_ctx* c, int m, int* swaps) {
     *swaps = 0;
     if (m == 2 && use_tb2(c)) {
-        hipError_t e = launch_phase_tb2<S>(c->pk, (const S*)bufA(c), (S*)bufB(c), c->stream);
+        hipError_t e = launch_phase_tb2<S>(c->pk, (const S*)bufA(c), (S*)bufB(c), c->tb2_seg,
+                                           c->stream);
         if (e != hipSuccess) return e;
         c->cur ^= 1;
         c->t += 2;
@@ -648,6 +649,11 @@ lbm_status lbm_set_params_SI(lbm_ctx* c, const lbm_params_si* p) {
     }
     c->ck = ck;
     c->pk = pk;
+    c->tb2_seg = 0;
+    if (d.lattice == LBM_D2Q9_PHASE && phase_tb2_fits(pk)) {
+        DeviceGuard g(c->device);
+        c->tb2_seg = d.prec == LBM_FP64 ? phase_tb2_seg<double>(pk) : phase_tb2_seg<float>(pk);
+    }
     c->dk = dk;
     c->d3k = d3k;
     c->p3k = p3k;

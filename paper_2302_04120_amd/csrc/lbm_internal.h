@@ -151,6 +151,7 @@ struct lbm_ctx {
     // two-phase steps: 0 automatic, 1 single-step kernel only, 2 two-step
     // kernel whenever the grid allows it, 3 many steps per cooperative launch
     int fusion = 0;
+    int tb2_seg = 0;                    // rows per two-step workgroup (0: kernel not usable)
     unsigned* persist_flags = nullptr;  // kPersistMaxTiles step counters, then the error word
     unsigned persist_epoch = 0;         // steps taken by persistent launches since the reset
 };
@@ -167,11 +168,14 @@ template <typename S>
 hipError_t launch_phase_step(const PhaseK& k, const S* hc, S* hn, const S* zc, S* zn, const S* puc,
                              S* pun, hipStream_t s);
 // two steps in one launch; the whole state (populations and (phi u)) moves
-// from buffer a to buffer b; needs phase_tb2_fits
+// from buffer a to buffer b; needs phase_tb2_fits.  seg: rows per workgroup
+// (phase_tb2_seg, fixed when the parameters are set)
 bool phase_tb2_fits(const PhaseK& k);
-long long phase_tb2_workgroups(const PhaseK& k);
 template <typename S>
-hipError_t launch_phase_tb2(const PhaseK& k, const S* a, S* b, hipStream_t s);
+int phase_tb2_seg(const PhaseK& k);
+long long phase_tb2_workgroups(const PhaseK& k, int seg);
+template <typename S>
+hipError_t launch_phase_tb2(const PhaseK& k, const S* a, S* b, int seg, hipStream_t s);
 // many steps in one cooperative launch for grids that split into at most
 // kPersistMaxTiles tiles of 512 threads (phase_persist_fits); flags: one step
 // counter per tile (zeroed with the state, advanced to epoch0 + steps), err:

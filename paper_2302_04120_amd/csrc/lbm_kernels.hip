@@ -645,8 +645,8 @@ __global__ __launch_bounds__(TX * TY) void k_phase_persist(PhaseK k, S* __restri
 // ---------------------------------------------------------------------------
 // Two steps per launch (temporal blocking).  A workgroup of nx threads (one
 // per column, nx a multiple of 64 up to 256) marches up the rows of one
-// segment [a, e) of one replica (128 rows, or the whole replica if shorter
-// than 256 rows).  At row v it collides step n at row v and
+// segment [a, e) of one replica (rows per segment: phase_tb2_seg).  At row
+// v it collides step n at row v and
 // step n + 1 at row v - 3:
 //   - the post-collision values of step n are exchanged in x through LDS and
 //     accumulated, per column, into the step-(n + 1) state of rows v - 1, v
@@ -1303,21 +1303,37 @@ hipError_t launch_phase_step(const PhaseK& k, const S* hc, S* hn, const S* zc, S
 
 bool phase_tb2_fits(const PhaseK& k) { return k.nx % 64 == 0 && k.nx <= kTbMaxNx && k.ny >= 4; }
 
-// rows per segment: kTbSeg, or the whole replica when it has fewer than two
-// segments' worth of rows
-int tb2_seg(const PhaseK& k) { return k.ny < 2 * kTbSeg ? k.ny : kTbSeg; }
+// Rows per segment: the whole replica when it has fewer than two segments'
+// worth of rows, or when it has at most four and the replicas alone already
+// fill every resident workgroup slot of the GPU (then segments would only add
+// the 6 overlap rows each: 1024 replicas of 256^2, FP32 +0.5 %; 256 replicas
+// in FP64, one workgroup per CU, +3.6 %); else kTbSeg rows, whose extra
+// workgroups keep smaller batches busy.
+template <typename S>
+int phase_tb2_seg(const PhaseK& k) {
+    if (k.ny < 2 * kTbSeg) return k.ny;
+    if (k.ny <= 4 * kTbSeg) {
+        int dev = 0, cus = 0, per_cu = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_phase_tb2<S>, k.nx, 0) ==
+                hipSuccess &&
+            per_cu > 0 && (long long)k.batch >= (long long)cus * per_cu)
+            return k.ny;
+    }
+    return kTbSeg;
+}
 
-long long phase_tb2_workgroups(const PhaseK& k) {
-    const int seg = tb2_seg(k);
+long long phase_tb2_workgroups(const PhaseK& k, int seg) {
     return (long long)((k.ny + seg - 1) / seg) * k.batch;
 }
 
 template <typename S>
-hipError_t launch_phase_tb2(const PhaseK& k, const S* a, S* b, hipStream_t s) {
-    if (!phase_tb2_fits(k)) return hipErrorInvalidValue;
-    const long long wgs = phase_tb2_workgroups(k);
+hipError_t launch_phase_tb2(const PhaseK& k, const S* a, S* b, int seg, hipStream_t s) {
+    if (!phase_tb2_fits(k) || seg < 1) return hipErrorInvalidValue;
+    const long long wgs = phase_tb2_workgroups(k, seg);
     dim3 blk(k.nx), grd(unsigned((wgs + kXCD - 1) / kXCD * kXCD));
-    hipLaunchKernelGGL(k_phase_tb2<S>, grd, blk, 0, s, k, a, b, tb2_seg(k));
+    hipLaunchKernelGGL(k_phase_tb2<S>, grd, blk, 0, s, k, a, b, seg);
     return hipGetLastError();
 }
 
@@ -1403,7 +1419,8 @@ hipError_t launch_nusselt(const ChanK& k, const S* f, const S* g, const S* qw, d
                                             const S*, const S*, double, hipStream_t);             \
     template hipError_t launch_phase_step<S>(const PhaseK&, const S*, S*, const S*, S*,          \
                                              const S*, S*, hipStream_t);                          \
-    template hipError_t launch_phase_tb2<S>(const PhaseK&, const S*, S*, hipStream_t);           \
+    template hipError_t launch_phase_tb2<S>(const PhaseK&, const S*, S*, int, hipStream_t);      \
+    template int phase_tb2_seg<S>(const PhaseK&);                                                \
     template hipError_t launch_phase_persist<S>(const PhaseK&, S*, S*, int, unsigned, unsigned*,  \
                                                 unsigned*, hipStream_t);                          \
     template hipError_t launch_chan_init<S>(const ChanK&, const double*, S*, S*, hipStream_t);   \

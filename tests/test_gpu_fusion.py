@@ -177,3 +177,34 @@ def test_narrow_replica_tiles_against_oracle(nx, ny, walls, prec, tol):
              rel_err(m["ux"][b], mo["ux"]))
         print("replica %d: phi %.2e p %.2e ux %.2e" % (b, *e), flush=True)
         assert e[0] < tol and e[1] < tol and e[2] < (tol if prec == "fp64" else 1e-4)
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("prec,batch", [("fp32", 512), ("fp64", 256)])
+def test_whole_replica_segments_bit_identical(prec, batch):
+    """Batches large enough to fill the GPU's resident workgroups on their
+    own run the two-step kernel on whole 256-row replicas (no segments); the
+    state after 4 steps (both paths then hold it in buffer A) equals that of
+    single-step launches node by node, compared on the device."""
+    import torch
+    from paper_2302_04120_amd import lbm
+    n = 256
+    prm, ini, _ = WL.bubble(n=n, batch=batch, seed=7)
+    print_case(test="tb2-whole-replicas", prec=prec, batch=batch)
+    runs = []
+    for fusion in (1, 2):
+        L = lbm.Lattice("phase", n, n, batch=batch, prec=prec)
+        L.set_step_fusion(fusion)
+        L.set_params(prm)
+        L.init(ini["p"], ini["ux"], ini["uy"], None, ini["phi"])
+        L.step(4)
+        torch.cuda.synchronize()
+        runs.append(L)
+    N = batch * n * n
+    P = (N + 63) // 64 * 64 + 16448
+    planes = 21 if prec == "fp32" else 20
+    dt = torch.float32 if prec == "fp32" else torch.float64
+    es = 4 if prec == "fp32" else 8
+    views = [L.buf[:planes * P * es].view(dt).view(planes, P)[:, :N] for L in runs]
+    assert torch.equal(views[0], views[1])
+    assert runs[1].reduce(("nonfinite",))["nonfinite"].sum() == 0
