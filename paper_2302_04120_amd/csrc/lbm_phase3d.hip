@@ -6,9 +6,10 @@
 //   k_p3_phi   phi = sum_i h_i of the stored state into one plane (Eq.
 //              zero_moment_h), so that no node has to re-read the 19 h_i of
 //              its 18 neighbours;
-//   k_p3_step  tiles of 64 x 4 x 2 nodes; phi of the tile and a one-node halo
-//              (66 x 6 x 4 values) in LDS for the isotropic stencils, then
-//              the node's collision in registers and push streaming.
+//   k_p3_step  tiles of 64 x 4 x 1 nodes (FP32) or 64 x 2 x 2 (FP64); phi of
+//              the tile and a one-node halo in LDS for the isotropic
+//              stencils, then the node's collision in registers and push
+//              streaming.
 // Layout: planes h 0-18, z 19-37, the low part of h_0 at 38 (FP32 storage:
 // the rest population is an FP32 hi/lo pair that carries the node's exact
 // phi balance, as in 2D), then (phi u) of the previous step (3 planes).
@@ -24,10 +25,19 @@
 namespace lbm {
 namespace {
 
-constexpr int kPX = 64, kPY = 4, kPZ = 2;         // tile
-constexpr int kHX = kPX + 2, kHY = kPY + 2, kHZ = kPZ + 2;
-constexpr int kHalo = kHX * kHY * kHZ;            // phi values in LDS
-constexpr int kPThreads = kPX * kPY * kPZ;
+// Step tiles, measured on the 256^3 bubble box (ms per step, FP32 / FP64):
+// 64 x 4 x 2 1.507 / 2.936, 64 x 2 x 2 1.498 / 2.806, 64 x 4 x 1 1.473 /
+// 2.849, 64 x 2 x 4 1.514 / 2.912, 64 x 1 x 4 1.504 / 2.811, 64 x 8 x 1
+// 1.568, 1024-thread tiles 1.58-1.62 / 3.59.  The states do not depend on
+// the tiling.
+template <typename S>
+struct P3Tile {
+    static constexpr int X = 64, Y = std::is_same<S, float>::value ? 4 : 2,
+                         Z = std::is_same<S, float>::value ? 1 : 2;
+    static constexpr int HX = X + 2, HY = Y + 2, HZ = Z + 2;
+    static constexpr int Halo = HX * HY * HZ;  // phi values in LDS
+    static constexpr int Threads = X * Y * Z;
+};
 
 __device__ __forceinline__ float rcp3(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double rcp3(double x) { return 1.0 / x; }
@@ -243,14 +253,16 @@ __device__ __forceinline__ void p3_node(const P3K& k, const S (&pn)[19], const S
 
 // One step (or, with MACROS, the macroscopic fields of the stored state).
 template <typename S, bool MACROS>
-__global__ __launch_bounds__(kPThreads) void k_p3_step(P3K k, const S* __restrict__ a,
+__global__ __launch_bounds__(P3Tile<S>::Threads) void k_p3_step(P3K k, const S* __restrict__ a,
                                                         S* __restrict__ b,
                                                         const S* __restrict__ phig,
                                                         double* __restrict__ mout) {
     using C = S;
     constexpr bool RMASS = std::is_same<S, float>::value;
     constexpr int PU = RMASS ? 39 : 38;  // first (phi u) plane
-    __shared__ C sphi[kHZ][kHY][kHX];
+    using T = P3Tile<S>;
+    constexpr int kPX = T::X, kPY = T::Y, kPZ = T::Z, kHX = T::HX, kHY = T::HY;
+    __shared__ C sphi[T::HZ][T::HY][T::HX];
     const int nx = k.nx, ny = k.ny, nz = k.nz;
     const long long P = k.P;
     const int gx = (nx + kPX - 1) / kPX, gy = (ny + kPY - 1) / kPY, gz = (nz + kPZ - 1) / kPZ;
@@ -280,7 +292,7 @@ __global__ __launch_bounds__(kPThreads) void k_p3_step(P3K k, const S* __restric
         }
     }
     const int t = (tz * kPY + ty) * kPX + tx;
-    for (int j = t; j < kHalo; j += kPThreads) {
+    for (int j = t; j < T::Halo; j += T::Threads) {
         const int hx = j % kHX, hy = (j / kHX) % kHY, hz = j / (kHX * kHY);
         const int gxx = ghost(x0 + hx - 1, nx, k.bcx);
         const int gyy = ghost(y0 + hy - 1, ny, k.bcy);
@@ -343,9 +355,11 @@ hipError_t launch_phi(const P3K& k, const S* a, S* phi, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <typename S>
 long long p3_tiles(const P3K& k) {
-    return (long long)((k.nx + kPX - 1) / kPX) * ((k.ny + kPY - 1) / kPY) *
-           ((k.nz + kPZ - 1) / kPZ) * k.batch;
+    using T = P3Tile<S>;
+    return (long long)((k.nx + T::X - 1) / T::X) * ((k.ny + T::Y - 1) / T::Y) *
+           ((k.nz + T::Z - 1) / T::Z) * k.batch;
 }
 
 }  // namespace
@@ -354,8 +368,8 @@ template <typename S>
 hipError_t launch_p3_step(const P3K& k, const S* a, S* b, S* phi, hipStream_t s) {
     hipError_t e = launch_phi<S>(k, a, phi, s);
     if (e != hipSuccess) return e;
-    const long long tiles = p3_tiles(k);
-    dim3 blk(kPX, kPY, kPZ), grd(unsigned((tiles + kXCD - 1) / kXCD * kXCD));
+    const long long tiles = p3_tiles<S>(k);
+    dim3 blk(P3Tile<S>::X, P3Tile<S>::Y, P3Tile<S>::Z), grd(unsigned((tiles + kXCD - 1) / kXCD * kXCD));
     hipLaunchKernelGGL((k_p3_step<S, false>), grd, blk, 0, s, k, a, b, (const S*)phi,
                        (double*)nullptr);
     return hipGetLastError();
@@ -372,8 +386,8 @@ template <typename S>
 hipError_t launch_p3_macros(const P3K& k, const S* a, S* phi, double* out, hipStream_t s) {
     hipError_t e = launch_phi<S>(k, a, phi, s);
     if (e != hipSuccess) return e;
-    const long long tiles = p3_tiles(k);
-    dim3 blk(kPX, kPY, kPZ), grd(unsigned((tiles + kXCD - 1) / kXCD * kXCD));
+    const long long tiles = p3_tiles<S>(k);
+    dim3 blk(P3Tile<S>::X, P3Tile<S>::Y, P3Tile<S>::Z), grd(unsigned((tiles + kXCD - 1) / kXCD * kXCD));
     hipLaunchKernelGGL((k_p3_step<S, true>), grd, blk, 0, s, k, a, (S*)nullptr, (const S*)phi, out);
     return hipGetLastError();
 }

@@ -1,8 +1,8 @@
 """The 3D two-phase kernels (phi pass + step with an LDS phi halo) against
 the FP64 oracle, node by node, through the C ABI.
 
-Grids span several 64 x 4 x 2 tiles with ragged x, y and z tails, replicas
-and every boundary combination; the inputs are bubbles with a random
+Grids span several tiles (64 x 4 x 1 in FP32, 64 x 2 x 2 in FP64) with ragged
+tails, replicas and every boundary combination; the inputs are bubbles with a random
 velocity field so that every term of the model is active.  As in 2D the
 two-phase model amplifies rounding differences over long runs, so pointwise
 parity is taken over short horizons and long runs are compared through
