@@ -256,13 +256,13 @@ __global__ __launch_bounds__(256) void k_chan_step(ChanK k, const S* __restrict_
 #define LBM_PHASE_TY 8
 #endif
 constexpr int TX = 64, TY = LBM_PHASE_TY;
-// LDS reserved by each FP32 single-step workgroup beyond its own 2.6 KB: it
-// holds residency at two 512-thread workgroups per CU (4 waves per SIMD).
+// LDS reserved by each FP32 single-step workgroup beyond its own ~1.5 KB: it
+// holds residency at four 256-thread workgroups per CU (4 waves per SIMD).
 // With more waves resident, more of the 42 population streams per wave are
 // open in DRAM at once and the step runs slower (67M-node bubble batch:
 // 2.82 ms at 8 waves per SIMD, 2.56 ms at 4).  The FP64 kernel's register
 // use already gives 4 waves per SIMD.
-constexpr unsigned kPhaseLdsReserve = 61440;
+constexpr unsigned kPhaseLdsReserve = 36864;
 // phi of a node from its stored h_i, Eq. zero_moment_h (rest population with
 // its low part).  One summation order everywhere, so that every kernel sees
 // the same phi for the same populations.
@@ -1210,17 +1210,37 @@ hipError_t launch_chan_step(const ChanK& k, const S* fc, S* fn, const S* gc, S* 
     return hipGetLastError();
 }
 
+// FP32 steps run on 256-node tiles, four resident per CU (kPhaseLdsReserve).
+// Measured against 512-node tiles (two per CU): equal on 1024 replicas of
+// 256^2, faster on smaller grids (64 replicas 146 -> 141 us per step, C4's
+// 4 x 512 replica under graph replay 5.22 -> 4.61 us).  FP64 steps and the
+// macro evaluation keep 512-node tiles (FP64: 4 % slower on 256-node tiles).
+
 // One launch of k_phase with the tile shape for the replica width: 64 x TY,
-// or, for nx in {4, 8, 16, 32}, nx x (512 / nx).
+// or, for nx in {4, 8, 16, 32}, nx x (512 / nx); half as many rows for FP32
+// steps.
 template <typename S, typename C, bool MACROS>
 hipError_t launch_phase_kernel(const PhaseK& k, const S* hc, S* hn, const S* zc, S* zn,
                                const S* puc, S* pun, double* out, unsigned lds, hipStream_t s) {
+    auto ntiles = [&](int tx, int ty) {
+        return (long long)((k.nx + tx - 1) / tx) * ((k.ny + ty - 1) / ty) * k.batch;
+    };
+    const bool half = !MACROS && std::is_same<S, float>::value;
     auto go = [&](auto kern, int tx, int ty) {
-        const long long tiles = (long long)((k.nx + tx - 1) / tx) * ((k.ny + ty - 1) / ty) * k.batch;
+        const long long tiles = ntiles(tx, ty);
         dim3 blk(tx, ty), grd(unsigned((tiles + kXCD - 1) / kXCD * kXCD));
         hipLaunchKernelGGL(kern, grd, blk, lds, s, k, hc, hn, zc, zn, puc, pun, out);
         return hipGetLastError();
     };
+    if (half) {
+        switch (k.nx) {
+            case 4: return go(k_phase<S, C, MACROS, 4, 64>, 4, 64);
+            case 8: return go(k_phase<S, C, MACROS, 8, 32>, 8, 32);
+            case 16: return go(k_phase<S, C, MACROS, 16, 16>, 16, 16);
+            case 32: return go(k_phase<S, C, MACROS, 32, 8>, 32, 8);
+            default: return go(k_phase<S, C, MACROS, TX, TY / 2>, TX, TY / 2);
+        }
+    }
     switch (k.nx) {
         case 4: return go(k_phase<S, C, MACROS, 4, 128>, 4, 128);
         case 8: return go(k_phase<S, C, MACROS, 8, 64>, 8, 64);
@@ -1297,7 +1317,7 @@ hipError_t launch_phase_persist(const PhaseK& k, S* A, S* B, int nsteps, unsigne
 template <typename S>
 hipError_t launch_phase_step(const PhaseK& k, const S* hc, S* hn, const S* zc, S* zn, const S* puc,
                              S* pun, hipStream_t s) {
-    const unsigned lds = std::is_same<S, float>::value ? kPhaseLdsReserve : 0u;
+    const unsigned lds = std::is_same<S, float>::value ? kPhaseLdsReserve : 0u;  // half tiles
     return launch_phase_kernel<S, S, false>(k, hc, hn, zc, zn, puc, pun, (double*)nullptr, lds, s);
 }
 
