@@ -145,7 +145,7 @@ def test_bench_size_two_step_sampled_against_oracle():
                                          (32, 45, False)])
 def test_narrow_replica_tiles_against_oracle(nx, ny, walls, prec, tol):
     """Replicas narrower than 64 nodes (the C4 shape is 4 x 512) run on tiles
-    of nx x 512/nx nodes: every lane holds a node and ragged rows cross tile
+    of nx x 256/nx nodes (FP32; nx x 512/nx in FP64): every lane holds a node and ragged rows cross tile
     edges.  Parity with the oracle for three replicas, 20 steps: the layered
     channel between walls, and a bubble for the periodic case (a layered
     profile is not periodic in y)."""
