@@ -35,8 +35,10 @@
  *     never allocates device memory itself.  The buffer and the HIP stream
  *     (desc.hip_stream) must stay valid until lbm_destroy.
  *   - All device work is enqueued on desc.hip_stream.  Calls that return host
- *     data synchronise that stream; lbm_step only enqueues.
- *   - Every call returns an lbm_status; on error the context is unchanged and
+ *     data synchronise that stream; lbm_step only enqueues (except in step
+ *     fusion mode 3, see lbm_set_step_fusion).
+ *   - Every call returns an lbm_status; on error the context is unchanged
+ *     (except that a failed many-steps launch drops the state) and
  *     lbm_last_error() describes the cause.  Argument checks happen before
  *     any device work.  A context is used by one host thread at a time.
  *   - Precision LBM_FP32_DEV stores populations in FP32 as deviations from
