@@ -132,3 +132,32 @@ def test_many_steps_mode_validation():
     with pytest.raises(lbm.LbmError):
         L2.set_step_fusion(3)
     lbm.Lattice("phase", 4, 512, batch=4, prec="fp32").set_step_fusion(3)  # 16 tiles
+
+
+def test_many_steps_error_word_is_reported_and_the_state_dropped():
+    """The host-side error path of the many-steps mode, forced from the host:
+    the error word that a timed-out wait would set is written into the
+    context's buffer before the call (it follows the 16 step counters in the
+    buffer's last 256 bytes for this lattice).  The kernel's waits see it and
+    leave (or the run completes), lbm_step reports LBM_E_DEVICE and drops the
+    state, and a new initialisation clears the word and steps normally."""
+    import torch
+    from paper_2302_04120_amd import lbm
+    nx, ny = 64, 40
+    prm, ini = _case(nx, ny, 1, False, seed=12)
+    print_case(test="persist-error-word")
+    L = _lattice(prm, ini, nx, ny, 1, "fp32", False, 3)
+    torch.cuda.synchronize()
+    L.buf[-256 + 64:-256 + 68] = torch.tensor([1, 0, 0, 0], dtype=torch.uint8, device=L.buf.device)
+    torch.cuda.synchronize()
+    with pytest.raises(lbm.LbmError) as e:
+        L.step(20)
+    assert e.value.status == lbm.LBM_E_DEVICE
+    with pytest.raises(lbm.LbmError) as e:
+        L.step(1)
+    assert e.value.status == lbm.LBM_E_STATE
+    L.init(ini["p"], ini["ux"], ini["uy"], None, ini["phi"])
+    L.step(20)
+    ref = _lattice(prm, ini, nx, ny, 1, "fp32", False, 1)
+    ref.step(20)
+    assert L.save_state() == ref.save_state()
