@@ -543,12 +543,13 @@ __global__ __launch_bounds__(TX * TY) void k_phase(PhaseK k, const S* __restrict
 
 // ---------------------------------------------------------------------------
 // Many steps in one launch for grids of a few tiles (the paper's C4 channel is
-// 4 x 512 nodes: four 4 x 128 tiles).  One workgroup per tile, all resident
+// 4 x 512 nodes: sixteen 4 x 32 tiles).  One workgroup per tile, all resident
 // at once (cooperative launch).  Between steps a tile waits only for the
-// tiles within one node of it -- those whose pushes it reads and whose reads
-// its next pushes would overwrite -- through per-tile step counters with
-// device-scope release / acquire; a grid-wide barrier costs several times
-// more on this GPU.  Every wait is bounded: past the bound the workgroup
+// tiles that, in the previous step, pushed into the nodes it reads or read
+// the nodes its next pushes overwrite (the tiles around it; every tile of
+// its replica when a ragged tail is one node thick), through per-tile step
+// counters with device-scope release / acquire; a grid-wide barrier costs
+// several times more on this GPU.  Every wait is bounded: past the bound the workgroup
 // flags an error and leaves, and so do its neighbours in turn, so the grid
 // always drains.  The per-tile work is phase_tile, as in k_phase, so the
 // states agree with single-step launches to the last bit.
