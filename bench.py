@@ -241,6 +241,58 @@ def run_c4_single(steps=20000, warmup=200, prec="fp32"):
     return out
 
 
+def run_c4_steady(system="sat_water_25C", prec="fp32", decay_times=6.5, chunk=2_000_000):
+    """C4's layered Poiseuille flow at the paper's finest grid (dx = 1.25 um,
+    dt = 12.5 ns, W = 20 dx = 25 um, 512 nodes across: H = 0.64 mm) run from
+    rest to steady state with the many-steps kernel: decay_times times the
+    liquid layer's slowest decay time 4 h^2 / (pi^2 nu_l).  Reports the E2 of
+    the final profile against the steady momentum balance of Eq.
+    NSE_for_layered_poiseuille integrated with the simulated phi (diffuse
+    interface) and with a sharp interface at the initial height, and the
+    relative change over the last chunk of steps."""
+    import math
+    import torch
+    from paper_2302_04120_amd import lbm, workloads as WL
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from layered_ref import diffuse_profile, sharp_profile
+    props = {k: v for k, v in WL.TWO_PHASE_SYSTEMS[system].items()
+             if k in ("rho_l", "rho_g", "nu_l", "nu_g", "sigma")}
+    ny = 512
+    prm, ini, offs = WL.layered(nx=4, ny=ny, seed=0, dx=1.25e-6, dt=1.25e-8, W_nodes=20.0, **props)
+    L = lbm.Lattice("phase", 4, ny, prec=prec, bc=(0, 0, lbm.BC_WALL, lbm.BC_WALL))
+    L.set_step_fusion(3)
+    L.set_params(prm)
+    L.init(ini["p"], ini["ux"], ini["uy"], None, ini["phi"])
+    H = ny * prm["dx"]
+    h = 0.5 * H
+    steps = int(math.ceil(decay_times * 4 * h * h / (math.pi ** 2 * prm["nu_l"]) / prm["dt"]))
+    done, prev = 0, None
+    t0 = time.perf_counter()
+    while done < steps:
+        n = min(chunk, steps - done)
+        if done + n >= steps:
+            prev = L.macros(("ux",))["ux"][0, :, 0]
+        L.step(n)
+        done += n
+        log("bench: c4 steady %s: %d / %d steps" % (system, done, steps))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    if L.reduce(("nonfinite",))["nonfinite"].sum() != 0:
+        raise RuntimeError("non-finite populations")
+    m = L.macros(("ux", "phi"))
+    u, phi = m["ux"][0, :, 0], m["phi"][0, :, 0]
+    y = (np.arange(ny) + 0.5) * prm["dx"]
+
+    def e2(ref, num):
+        return float(100.0 * np.sqrt(np.sum((ref - num) ** 2) / np.sum(ref ** 2)))
+
+    return dict(system=system, prec=prec, steps=steps, us_per_step=wall / steps * 1e6,
+                E2_vs_diffuse_percent=e2(diffuse_profile(y, phi, prm, H), u),
+                E2_vs_sharp_percent=e2(sharp_profile(y, offs[0], prm, H), u),
+                last_chunk_rel_change=float(np.abs(u - prev).max() / np.abs(u).max()),
+                u_max=float(np.abs(u).max()))
+
+
 def adjoint_cost(steps=20000, ckpt=500, prec="fp32"):
     """Adjoint/forward cost on the C5 heated channel (1600 x 80 nodes, flow from
     rest): plain forward time, record time (forward + checkpoints) and the
@@ -371,9 +423,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP64 and batch-4 legs")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_phase_step.json"))
-    ap.add_argument("--leg", choices=("channel", "adjoint", "d3q19", "phase3d", "layered", "c4single"),
+    ap.add_argument("--leg", choices=("channel", "adjoint", "d3q19", "phase3d", "layered", "c4single",
+                                      "c4steady"),
                     default=None,
                     help="only run one secondary leg and print its figures (for profiling)")
+    ap.add_argument("--systems", default="sat_water_25C,air_water_25C",
+                    help="two-phase systems of the c4steady leg (comma-separated)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain copy of BYTES (counter calibration)")
     args = ap.parse_args()
@@ -397,6 +452,10 @@ def main():
         return 0
     if args.leg == "c4single":
         print(json.dumps(run_c4_single(args.steps, args.warmup, args.prec)), flush=True)
+        return 0
+    if args.leg == "c4steady":
+        for system in args.systems.split(","):
+            print(json.dumps(run_c4_steady(system, args.prec)), flush=True)
         return 0
     if args.gpus != 1:
         print("bench.py measures one GPU only; --gpus %d is not supported" % args.gpus,
