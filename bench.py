@@ -27,6 +27,8 @@ HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per lattice update (each population read once and written
 # once): z 9 + h 9 + low part of h_0 + (phi u) 2, read + write
 BYTES_PER_LU = {"fp32": (9 + 9 + 1 + 2) * 4 * 2, "fp64": (9 + 9 + 2) * 8 * 2}
+# FP32 storage with FP64 step arithmetic moves the FP32 bytes
+BYTES_PER_LU["fp32_arith64"] = BYTES_PER_LU["fp32"]
 # heated channel (D2Q9 f + D2Q5 g), read + write
 CHAN_BYTES_PER_LU = {"fp32": (9 + 5) * 4 * 2, "fp64": (9 + 5) * 8 * 2}
 # D3Q19 momentum, read + write
@@ -417,7 +419,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--batch", type=int, default=1024, help="256x256 replicas per step")
-    ap.add_argument("--prec", default="fp32", choices=("fp32", "fp64"))
+    ap.add_argument("--prec", default="fp32", choices=("fp32", "fp64", "fp32_arith64"))
     ap.add_argument("--fusion", type=int, default=2, choices=(0, 1, 2),
                     help="two-phase kernel: 2 two-step (default), 1 single-step, 0 library's choice")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -435,6 +437,10 @@ def main():
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
         return 0
+    if args.prec == "fp32_arith64" and args.leg not in ("layered", "c4single", "c4steady"):
+        print("--prec fp32_arith64 applies to the two-phase legs layered, c4single and c4steady",
+              file=sys.stderr)
+        return 2
     if args.leg == "channel":
         print(json.dumps(run_channel(16384, 2048, args.steps, args.warmup, args.prec)), flush=True)
         return 0

@@ -45,7 +45,10 @@ lbm_status check_desc(const lbm_desc* d, Layout* L, std::string* err) {
     };
     if (!d) return fail(LBM_E_ARG, "desc is NULL");
     if (d->nx < 1 || d->ny < 1 || d->batch < 1) return fail(LBM_E_ARG, "nx, ny, batch must be >= 1");
-    if (d->prec != LBM_FP32_DEV && d->prec != LBM_FP64) return fail(LBM_E_ARG, "unknown precision");
+    if (d->prec != LBM_FP32_DEV && d->prec != LBM_FP64 && d->prec != LBM_FP32_DEV_ARITH64)
+        return fail(LBM_E_ARG, "unknown precision");
+    if (d->prec == LBM_FP32_DEV_ARITH64 && d->lattice != LBM_D2Q9_PHASE)
+        return fail(LBM_E_UNSUPPORTED, "FP64 arithmetic on FP32 storage: LBM_D2Q9_PHASE only");
     if (d->batch > 65535 || d->ny > 65535 * 4) return fail(LBM_E_ARG, "grid too large for the launch geometry");
     for (int s = 0; s < 4; ++s)
         if (d->bc[s] < LBM_BC_PERIODIC || d->bc[s] > LBM_BC_SYMMETRY) return fail(LBM_E_ARG, "unknown boundary kind");
@@ -95,7 +98,7 @@ lbm_status check_desc(const lbm_desc* d, Layout* L, std::string* err) {
             const bool yp = d->bc[2] == LBM_BC_PERIODIC && d->bc[3] == LBM_BC_PERIODIC;
             const bool yw = d->bc[2] == LBM_BC_WALL && d->bc[3] == LBM_BC_WALL;
             if (!xp || !(yp || yw)) return fail(LBM_E_UNSUPPORTED, "PHASE: x periodic, y periodic or walls");
-            l.npop = 18 + (d->prec == LBM_FP32_DEV ? 1 : 0);
+            l.npop = 18 + (d->prec != LBM_FP64 ? 1 : 0);
             break;
         }
         case LBM_D3Q19: {
@@ -207,7 +210,7 @@ hipError_t step_once(lbm_ctx* c) {
                                    c->stream);
     }
     return launch_phase_step<S>(c->pk, a, b, a + 9 * P, b + 9 * P, a + c->npop * P,
-                                b + c->npop * P, c->stream);
+                                b + c->npop * P, c->desc.prec == LBM_FP32_DEV_ARITH64, c->stream);
 }
 
 // Whether the next two steps go through the two-step kernel.  Automatic
@@ -256,7 +259,8 @@ lbm_status step_persist(lbm_ctx* c, int n) {
     for (int s = 0; s < n;) {
         const int m = std::min(kPersistChunk, n - s);
         hipError_t e = launch_phase_persist<S>(c->pk, (S*)bufA(c), (S*)bufB(c), m, c->persist_epoch,
-                                               c->persist_flags, err, c->stream);
+                                               c->persist_flags, err,
+                                               c->desc.prec == LBM_FP32_DEV_ARITH64, c->stream);
         if (e != hipSuccess) return hip_fail(c, e, "many-steps kernel");
         c->persist_epoch += unsigned(m);
         c->cur ^= (m & 1);
@@ -460,6 +464,8 @@ lbm_status lbm_set_step_fusion(lbm_ctx* c, int mode) {
     if (mode == 2 && c->desc.lattice == LBM_D2Q9_PHASE &&
         (c->desc.nx % 64 != 0 || c->desc.nx > 256))
         return set_err(c, LBM_E_UNSUPPORTED, "two-step kernel needs nx a multiple of 64, at most 256");
+    if (mode == 2 && c->desc.lattice == LBM_D2Q9_PHASE && c->desc.prec == LBM_FP32_DEV_ARITH64)
+        return set_err(c, LBM_E_UNSUPPORTED, "two-step kernel: not with FP64 arithmetic on FP32 storage");
     if (mode != c->fusion) {
         DeviceGuard g(c->device);
         drop_graphs(c);
@@ -652,7 +658,9 @@ lbm_status lbm_set_params_SI(lbm_ctx* c, const lbm_params_si* p) {
     c->tb2_seg = 0;
     if (d.lattice == LBM_D2Q9_PHASE && phase_tb2_fits(pk)) {
         DeviceGuard g(c->device);
-        c->tb2_seg = d.prec == LBM_FP64 ? phase_tb2_seg<double>(pk) : phase_tb2_seg<float>(pk);
+        c->tb2_seg = d.prec == LBM_FP64                ? phase_tb2_seg<double>(pk)
+                     : d.prec == LBM_FP32_DEV_ARITH64 ? 0  // the two-step kernel computes in S
+                                                       : phase_tb2_seg<float>(pk);
     }
     c->dk = dk;
     c->d3k = d3k;

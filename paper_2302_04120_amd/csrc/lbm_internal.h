@@ -164,9 +164,10 @@ constexpr int kRedBlocks = 256;  // first-pass blocks per replica and field
 template <typename S>
 hipError_t launch_chan_step(const ChanK& k, const S* fc, S* fn, const S* gc, S* gn,
                             const S* qw, const S* uin, const S* tin, double mod, hipStream_t s);
+// arith64: evaluate the step in FP64 on FP32 storage (S = float)
 template <typename S>
 hipError_t launch_phase_step(const PhaseK& k, const S* hc, S* hn, const S* zc, S* zn, const S* puc,
-                             S* pun, hipStream_t s);
+                             S* pun, bool arith64, hipStream_t s);
 // two steps in one launch; the whole state (populations and (phi u)) moves
 // from buffer a to buffer b; needs phase_tb2_fits.  seg: rows per workgroup
 // (phase_tb2_seg, fixed when the parameters are set)
@@ -188,7 +189,7 @@ constexpr size_t kPersistFlagBytes = 256 * ((kPersistMaxTiles + 1) * 4 / 256 + 1
 bool phase_persist_fits(const PhaseK& k);
 template <typename S>
 hipError_t launch_phase_persist(const PhaseK& k, S* A, S* B, int nsteps, unsigned epoch0,
-                                unsigned* flags, unsigned* err, hipStream_t s);
+                                unsigned* flags, unsigned* err, bool arith64, hipStream_t s);
 hipError_t launch_d1(const D1K& k, double* g, int nsteps, hipStream_t s);
 
 template <typename S>

@@ -556,14 +556,14 @@ __global__ __launch_bounds__(TX * TY) void k_phase(PhaseK k, const S* __restrict
 // ---------------------------------------------------------------------------
 constexpr unsigned kPersistSpin = 1u << 22;  // polls before a wait counts as failed
 
-template <typename S, int TX, int TY>
+template <typename S, typename C, int TX, int TY>
 __global__ __launch_bounds__(TX * TY) void k_phase_persist(PhaseK k, S* __restrict__ A,
                                                            S* __restrict__ B, int nsteps,
                                                            unsigned epoch0,
                                                            unsigned* __restrict__ flags,
                                                            unsigned* __restrict__ err) {
     static_assert(2 * (TX + 2) + 2 * TY <= TX * TY, "the ring of a tile needs a thread per node");
-    __shared__ S sphi[TY + 2][TX + 2];
+    __shared__ C sphi[TY + 2][TX + 2];
     __shared__ int bad;
     const long long P = k.P;
     const int npop = std::is_same<S, float>::value ? 19 : 18;
@@ -627,7 +627,7 @@ __global__ __launch_bounds__(TX * TY) void k_phase_persist(PhaseK k, S* __restri
         if (bad) return;  // uniform: every thread read it after the barrier
         const S* a = (s & 1) ? B : A;
         S* o = (s & 1) ? A : B;
-        phase_tile<S, S, false, TX, TY>(k, tile, a, o, a + 9 * P, o + 9 * P, a + npop * P,
+        phase_tile<S, C, false, TX, TY>(k, tile, a, o, a + 9 * P, o + 9 * P, a + npop * P,
                                         o + npop * P, (double*)nullptr, sphi);
         // Every wave waits until its stores have reached the L2 (vmcnt counts
         // stores on this GPU), the barrier orders them before the first
@@ -1310,7 +1310,8 @@ bool phase_persist_fits(const PhaseK& k) { return persist_threads(k) != 0; }
 
 template <typename S>
 hipError_t launch_phase_persist(const PhaseK& k, S* A, S* B, int nsteps, unsigned epoch0,
-                                unsigned* flags, unsigned* err, hipStream_t s) {
+                                unsigned* flags, unsigned* err, bool arith64, hipStream_t s) {
+    if (arith64 && !std::is_same<S, float>::value) return hipErrorInvalidValue;
     const int threads = persist_threads(k);
     if (!threads || nsteps < 1) return hipErrorInvalidValue;
     int tx, ty;
@@ -1321,8 +1322,10 @@ hipError_t launch_phase_persist(const PhaseK& k, S* A, S* B, int nsteps, unsigne
     auto go = [&](const void* kern) {
         return hipLaunchCooperativeKernel(kern, dim3(tiles), dim3(tx, ty), args, 0, s);
     };
-#define LBM_PERSIST_CASE(X, Y) \
-    if (tx == X && ty == Y) return go(reinterpret_cast<const void*>(&k_phase_persist<S, X, Y>));
+#define LBM_PERSIST_CASE(X, Y)                                                                 \
+    if (tx == X && ty == Y)                                                                    \
+        return go(arith64 ? reinterpret_cast<const void*>(&k_phase_persist<S, double, X, Y>)   \
+                          : reinterpret_cast<const void*>(&k_phase_persist<S, S, X, Y>));
     LBM_PERSIST_CASE(4, 32) LBM_PERSIST_CASE(4, 64) LBM_PERSIST_CASE(4, 128)
     LBM_PERSIST_CASE(8, 16) LBM_PERSIST_CASE(8, 32) LBM_PERSIST_CASE(8, 64)
     LBM_PERSIST_CASE(16, 8) LBM_PERSIST_CASE(16, 16) LBM_PERSIST_CASE(16, 32)
@@ -1334,8 +1337,13 @@ hipError_t launch_phase_persist(const PhaseK& k, S* A, S* B, int nsteps, unsigne
 
 template <typename S>
 hipError_t launch_phase_step(const PhaseK& k, const S* hc, S* hn, const S* zc, S* zn, const S* puc,
-                             S* pun, hipStream_t s) {
+                             S* pun, bool arith64, hipStream_t s) {
     const unsigned lds = std::is_same<S, float>::value ? kPhaseLdsReserve : 0u;  // half tiles
+    if (arith64) {  // FP32 storage, every step evaluated in FP64
+        if (!std::is_same<S, float>::value) return hipErrorInvalidValue;
+        return launch_phase_kernel<S, double, false>(k, hc, hn, zc, zn, puc, pun, (double*)nullptr,
+                                                     lds, s);
+    }
     return launch_phase_kernel<S, S, false>(k, hc, hn, zc, zn, puc, pun, (double*)nullptr, lds, s);
 }
 
@@ -1456,11 +1464,11 @@ hipError_t launch_nusselt(const ChanK& k, const S* f, const S* g, const S* qw, d
     template hipError_t launch_chan_step<S>(const ChanK&, const S*, S*, const S*, S*, const S*, \
                                             const S*, const S*, double, hipStream_t);             \
     template hipError_t launch_phase_step<S>(const PhaseK&, const S*, S*, const S*, S*,          \
-                                             const S*, S*, hipStream_t);                          \
+                                             const S*, S*, bool, hipStream_t);                    \
     template hipError_t launch_phase_tb2<S>(const PhaseK&, const S*, S*, int, hipStream_t);      \
     template int phase_tb2_seg<S>(const PhaseK&);                                                \
     template hipError_t launch_phase_persist<S>(const PhaseK&, S*, S*, int, unsigned, unsigned*,  \
-                                                unsigned*, hipStream_t);                          \
+                                                unsigned*, bool, hipStream_t);                    \
     template hipError_t launch_chan_init<S>(const ChanK&, const double*, S*, S*, hipStream_t);   \
     template hipError_t launch_phase_init<S>(const PhaseK&, const double*, S*, S*, S*,           \
                                              hipStream_t);                                        \

@@ -22,7 +22,8 @@ LIB_PATH = os.path.join(_HERE, "liblbm.so")
 LBM_OK, LBM_E_ARG, LBM_E_TAU, LBM_E_DEVICE, LBM_E_STATE, LBM_E_NONFINITE, LBM_E_UNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6
 LBM_D1Q2, LBM_D1Q3, LBM_D2Q9_D2Q5, LBM_D2Q9_PHASE, LBM_D3Q19, LBM_D3Q19_PHASE = 1, 2, 3, 4, 5, 6
-LBM_FP32_DEV, LBM_FP64 = 0, 1
+LBM_FP32_DEV, LBM_FP64, LBM_FP32_DEV_ARITH64 = 0, 1, 2
+PRECISIONS = {"fp32": LBM_FP32_DEV, "fp64": LBM_FP64, "fp32_arith64": LBM_FP32_DEV_ARITH64}
 BC_PERIODIC, BC_WALL, BC_VEL_INLET, BC_P_OUTLET, BC_DIRICHLET, BC_SYMMETRY = 0, 1, 2, 3, 4, 5
 LBM_BGK, LBM_MRT = 0, 1
 FLAG_FLOW, FLAG_THERMAL, FLAG_THERMAL_D2Q9 = 1, 2, 4
@@ -174,7 +175,8 @@ class Lattice:
 
     lattice: 'd1q2' | 'd1q3' | 'channel' | 'phase' | 'd3q19' | 'phase3d'.  bc: 4 kinds
     (x-, x+, y-, y+), plus bc_z (z-, z+) and nz for the 3D lattices.
-    prec: 'fp32' (FP32 deviation storage) | 'fp64'.
+    prec: 'fp32' (FP32 deviation storage) | 'fp64' | 'fp32_arith64' (FP32 deviation
+    storage, FP64 step arithmetic; two-phase D2Q9 only).
     """
 
     def __init__(self, lattice, nx, ny=1, batch=1, prec="fp32", bc=None, flow=True,
@@ -192,7 +194,9 @@ class Lattice:
             bc = {"d1q2": (4, 4, 0, 0), "d1q3": (4, 4, 0, 0)}.get(lattice, (0, 0, 0, 0))
         d = Desc()
         d.lattice, d.nx, d.ny, d.batch = lat, nx, ny, batch
-        d.prec = LBM_FP64 if prec == "fp64" else LBM_FP32_DEV
+        if prec not in PRECISIONS:
+            raise ValueError("prec must be one of %s" % sorted(PRECISIONS))
+        d.prec = PRECISIONS[prec]
         for i in range(4):
             d.bc[i] = bc[i]
         three_d = lat in (LBM_D3Q19, LBM_D3Q19_PHASE)

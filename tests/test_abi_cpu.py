@@ -80,6 +80,22 @@ def test_query_bytes_layout_and_validation():
     assert L.lbm_query_bytes(C.byref(ok), None) == lbm.LBM_E_ARG
 
 
+def test_fp64_arithmetic_mode_layout_and_validation():
+    """FP32 storage with FP64 step arithmetic: the FP32 layout, two-phase D2Q9 only."""
+    lbm = _lbm()
+    L = lbm.lib()
+    n32, na = C.c_size_t(), C.c_size_t()
+    assert L.lbm_query_bytes(C.byref(_desc(lbm)), C.byref(n32)) == lbm.LBM_OK
+    d = _desc(lbm, prec=lbm.LBM_FP32_DEV_ARITH64)
+    assert L.lbm_query_bytes(C.byref(d), C.byref(na)) == lbm.LBM_OK
+    assert na.value == n32.value
+    for lat in (lbm.LBM_D2Q9_D2Q5, lbm.LBM_D3Q19, lbm.LBM_D3Q19_PHASE):
+        d = _desc(lbm, lattice=lat, nx=32, ny=16, prec=lbm.LBM_FP32_DEV_ARITH64)
+        d.nz = 8
+        assert L.lbm_query_bytes(C.byref(d), C.byref(na)) == lbm.LBM_E_UNSUPPORTED
+    assert lbm.PRECISIONS["fp32_arith64"] == lbm.LBM_FP32_DEV_ARITH64
+
+
 def test_create_rejects_small_or_misaligned_buffer():
     lbm = _lbm()
     L = lbm.lib()

@@ -1,0 +1,124 @@
+"""FP32 deviation storage with FP64 step arithmetic (prec 'fp32_arith64',
+two-phase D2Q9 only).  The state is stored exactly as in the FP32 mode; only
+the per-node collision, forcing and streaming arithmetic runs in FP64.  Checks:
+parity with the FP64 oracle to the FP32 storage bar, the many-steps kernel
+bit-identical to single-step launches in this mode, the library's automatic
+choice equal to single steps (the two-step kernel computes in the storage
+type, so it is never chosen), the rejected combinations, and that over a long
+run from rest the mode stays closer to the FP64 run than the FP32 mode does
+(the per-step body-force increment is small against the accumulated velocity,
+Eq. 23 and Sec. 3.3, and FP32 arithmetic rounds part of it away every step)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2302_04120_amd import workloads as WL
+
+from gpu_cases import print_case, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _lattice(prm, ini, nx, ny, batch, prec, walls, fusion):
+    from paper_2302_04120_amd import lbm
+    bc = (0, 0, lbm.BC_WALL, lbm.BC_WALL) if walls else (0, 0, 0, 0)
+    L = lbm.Lattice("phase", nx, ny, batch=batch, prec=prec, bc=bc)
+    L.set_step_fusion(fusion)
+    L.set_params(prm)
+    L.init(ini["p"], ini["ux"], ini["uy"], None, ini["phi"])
+    return L
+
+
+def _case(nx, ny, batch, walls, seed):
+    if walls:
+        prm, ini, _ = WL.layered(nx=nx, ny=ny, seed=seed, dx=5e-6, dt=2.5e-7, W_nodes=6,
+                                 batch=batch)
+    else:
+        prm, ini, _ = WL.bubble(n=nx, ny=ny, radii=(max(2, min(nx, ny) // 4),), batch=batch,
+                                seed=seed)
+    g = WL.rng(seed + 1)
+    ini = dict(ini, ux=5e-3 * g.uniform(-1, 1, ini["phi"].shape),
+               uy=5e-3 * g.uniform(-1, 1, ini["phi"].shape))
+    return prm, ini
+
+
+@pytest.mark.parametrize("nx,ny,walls,fusion", [(64, 48, False, 1), (70, 37, False, 3),
+                                                 (4, 512, True, 3), (130, 26, True, 1)])
+def test_arith64_against_oracle(nx, ny, walls, fusion):
+    steps = 40
+    print_case(test="arith64-oracle", nx=nx, ny=ny, walls=walls, fusion=fusion)
+    prm, ini = _case(nx, ny, 1, walls, seed=nx + 2 * ny)
+    L = _lattice(prm, ini, nx, ny, 1, "fp32_arith64", walls, fusion)
+    L.step(steps)
+    m = {k: v[0] for k, v in L.macros(("phi", "p", "ux", "uy")).items()}
+    o = O.Phase(nx, ny, prm, bc_y="walls" if walls else "periodic")
+    o.init(ini["phi"][0], ini["p"][0], ini["ux"][0], ini["uy"][0])
+    o.step(steps)
+    mo = o.macros()
+    scale_p = max(float(np.abs(mo["p"]).max()), prm["sigma"] / prm["W"])
+    assert rel_err(m["phi"], mo["phi"], scale=1.0) < 1e-5
+    assert rel_err(m["p"], mo["p"], scale=scale_p) < 1e-5
+    assert rel_err(m["ux"], mo["ux"]) < 1e-4
+    assert rel_err(m["uy"], mo["uy"], scale=float(np.abs(mo["ux"]).max())) < 1e-4
+
+
+@pytest.mark.parametrize("nx,ny,batch,walls,calls", [(4, 512, 1, True, (101,)),
+                                                     (32, 33, 2, False, (40, 7)),
+                                                     (130, 26, 1, True, (25, 24))])
+def test_arith64_many_steps_bit_identical(nx, ny, batch, walls, calls):
+    print_case(test="arith64-persist", nx=nx, ny=ny, batch=batch, walls=walls)
+    prm, ini = _case(nx, ny, batch, walls, seed=nx + ny)
+    one = _lattice(prm, ini, nx, ny, batch, "fp32_arith64", walls, 1)
+    many = _lattice(prm, ini, nx, ny, batch, "fp32_arith64", walls, 3)
+    auto = _lattice(prm, ini, nx, ny, batch, "fp32_arith64", walls, 0)
+    for n in calls:
+        for L in (one, many, auto):
+            L.step(n)
+        assert one.save_state() == many.save_state()
+        assert one.save_state() == auto.save_state()
+
+
+def test_arith64_rejected_combinations():
+    from paper_2302_04120_amd import lbm
+    print_case(test="arith64-validation")
+    L = lbm.Lattice("phase", 64, 64, prec="fp32_arith64")
+    with pytest.raises(lbm.LbmError) as e:
+        L.set_step_fusion(2)
+    assert e.value.status == lbm.LBM_E_UNSUPPORTED
+    for lattice, kw in (("channel", {}), ("d3q19", {"nz": 8}), ("phase3d", {"nz": 8})):
+        with pytest.raises(lbm.LbmError) as e:
+            lbm.Lattice(lattice, 32, 16, prec="fp32_arith64", **kw)
+        assert e.value.status == lbm.LBM_E_UNSUPPORTED
+    with pytest.raises(ValueError):
+        lbm.Lattice("phase", 64, 64, prec="bf16")
+    # a state saved in one precision mode does not load into another
+    a = lbm.Lattice("phase", 64, 64, prec="fp32")
+    prm, ini = _case(64, 64, 1, False, seed=5)
+    a.set_params(prm)
+    a.init(ini["p"], ini["ux"], ini["uy"], None, ini["phi"])
+    L.set_params(prm)
+    with pytest.raises(lbm.LbmError):
+        L.load_state(a.save_state())
+
+
+def test_arith64_long_run_tracks_fp64():
+    """The layered channel (saturated water and steam at 100 C, 4 x 128 nodes
+    between walls) driven from rest for 200 000 steps: the FP32-storage run
+    with FP64 arithmetic stays much closer to the FP64 run than the FP32 run."""
+    props = {k: v for k, v in WL.TWO_PHASE_SYSTEMS["sat_water_100C"].items()
+             if k in ("rho_l", "rho_g", "nu_l", "nu_g", "sigma")}
+    prm, ini, _ = WL.layered(nx=4, ny=128, seed=0, dx=5e-6, dt=2.5e-7, W_nodes=6, **props)
+    steps = 200_000
+    u = {}
+    for prec in ("fp64", "fp32", "fp32_arith64"):
+        print_case(test="arith64-long", prec=prec, steps=steps)
+        L = _lattice(prm, ini, 4, 128, 1, prec, True, 3)
+        L.step(steps)
+        assert L.reduce(("nonfinite",))["nonfinite"].sum() == 0
+        u[prec] = L.macros(("ux",))["ux"][0, :, 0]
+    scale = float(np.abs(u["fp64"]).max())
+    err32 = float(np.abs(u["fp32"] - u["fp64"]).max()) / scale
+    err_a = float(np.abs(u["fp32_arith64"] - u["fp64"]).max()) / scale
+    print("max |u - u_fp64| / max|u_fp64|: fp32 %.3e, fp32_arith64 %.3e" % (err32, err_a),
+          flush=True)
+    assert err_a < 0.5 * err32
