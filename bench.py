@@ -437,9 +437,10 @@ def main():
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
         return 0
-    if args.prec == "fp32_arith64" and args.leg not in ("layered", "c4single", "c4steady"):
-        print("--prec fp32_arith64 applies to the two-phase legs layered, c4single and c4steady",
-              file=sys.stderr)
+    if args.prec == "fp32_arith64" and (args.leg not in (None, "layered", "c4single", "c4steady")
+                                        or (args.leg is None and args.fusion == 2)):
+        print("--prec fp32_arith64 applies to the two-phase legs (with --fusion 0 or 1 for the "
+              "bubble workload)", file=sys.stderr)
         return 2
     if args.leg == "channel":
         print(json.dumps(run_channel(16384, 2048, args.steps, args.warmup, args.prec)), flush=True)
@@ -477,7 +478,8 @@ def main():
     bpl = BYTES_PER_LU[args.prec]
     spl = 2 if args.fusion == 2 else 1  # steps per launch
     kname = ("k_phase_tb2<%s>" % ("float" if args.prec == "fp32" else "double") if spl == 2 else
-             "k_phase<%s>" % ("float,float,false" if args.prec == "fp32" else "double,double,false"))
+             "k_phase<%s>" % {"fp32": "float,float,false", "fp64": "double,double,false",
+                              "fp32_arith64": "float,double,false"}[args.prec])
     launch_ms = r["kernel_ms"] * spl
     # algorithmic bytes of one launch (bpl x nodes x steps it performs) / its duration
     achieved = bpl * r["nodes"] * spl / (launch_ms * 1e-3) / 1e9
@@ -528,12 +530,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.prec == "fp32" else "f64",
+        "dtype": "f32" if args.prec == "fp32" else "f64",  # the step's arithmetic type
         "data": "synthetic",
         "config": {"workload": "stationary bubble, D2Q9 MRT z + D2Q9 Allen-Cahn h, 256x256 "
                                "periodic cell, rho_l/rho_g=43290, nu_g/nu_l=471, radii 20/30/40/50 "
                                "nodes, %d replicas per step" % args.batch,
-                   "nodes_per_step": r["nodes"], "storage": args.prec + "-deviation"},
+                   "nodes_per_step": r["nodes"],
+                   "storage": "fp64-deviation" if args.prec == "fp64" else "fp32-deviation"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "bytes_per_lu": bpl, "kernel": kname, "steps_per_launch": spl,
