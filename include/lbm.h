@@ -50,8 +50,9 @@
  *     FP64: in FP32 arithmetic the per-step force increment of a slow liquid
  *     layer at small dt falls below the resolution of the moments it is added
  *     to, and runs of 1e7 steps and more drift (the layered channel at the
- *     paper's finest grid: 9-12 % against FP64's 1.2 %); the two-step kernel
- *     is not available in this mode.  Reductions are FP64 in all modes.
+ *     paper's finest grid: 9-12 % against FP64's 1.2 %; in this mode it
+ *     matches FP64); the two-step kernel is not available in this mode.
+ *     Reductions are FP64 in all modes.
  */
 #ifndef LBM_H
 #define LBM_H
@@ -222,8 +223,8 @@ LBM_API lbm_status lbm_set_graph_steps(lbm_ctx* ctx, int steps);
  *   mode 2: pairs of steps run as one launch of the two-step kernel, which
  *           keeps the intermediate state on chip and so moves half the bytes
  *           per step; needs nx a multiple of 64 and at most 256
- *           (LBM_E_UNSUPPORTED otherwise); ny < 4 and an odd last step use
- *           the single-step kernel.
+ *           (LBM_E_UNSUPPORTED otherwise, and with LBM_FP32_DEV_ARITH64);
+ *           ny < 4 and an odd last step use the single-step kernel.
  *   mode 3: every lbm_step call runs as one cooperative launch (per 16384
  *           steps) of the many-steps kernel: one resident workgroup per
  *           tile, which steps its tile and waits for its neighbouring tiles'
@@ -243,7 +244,7 @@ LBM_API lbm_status lbm_set_graph_steps(lbm_ctx* ctx, int steps);
  *           replica: the whole replica when it has fewer than 256 rows, or
  *           at most 512 rows and the replicas alone fill the GPU's resident
  *           workgroup slots; else 128 rows) number at least 512, else
- *           mode 1.
+ *           mode 1 (always mode 1 with LBM_FP32_DEV_ARITH64).
  * The kernels evaluate the same per-node arithmetic in the same order, so
  * the modes agree to the last bit.  Not an operation of the paper: a
  * performance control.  Other lattices ignore it.  LBM_E_ARG on an unknown
