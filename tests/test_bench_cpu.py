@@ -22,6 +22,14 @@ def test_odd_step_count_with_the_two_step_kernel_is_refused():
     assert "even" in r.stderr
 
 
+def test_fp64_arithmetic_mode_is_refused_outside_the_two_phase_legs():
+    for leg in ("channel", "d3q19", "phase3d", "adjoint"):
+        r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--leg", leg,
+                            "--prec", "fp32_arith64"], capture_output=True, text=True, timeout=120)
+        assert r.returncode == 2
+        assert "two-phase" in r.stderr
+
+
 def test_source_hash_and_host_description():
     sys.path.insert(0, ROOT)
     import bench
