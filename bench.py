@@ -416,8 +416,10 @@ def copy_calibration(nbytes, reps=5):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default 200; 20000 for --leg c4single)")
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed steps first (default 20; 200 for --leg c4single)")
     ap.add_argument("--batch", type=int, default=1024, help="256x256 replicas per step")
     ap.add_argument("--prec", default="fp32", choices=("fp32", "fp64", "fp32_arith64"))
     ap.add_argument("--fusion", type=int, default=2, choices=(0, 1, 2),
@@ -434,6 +436,10 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain copy of BYTES (counter calibration)")
     args = ap.parse_args()
+    if args.steps is None:
+        args.steps = 20000 if args.leg == "c4single" else 200
+    if args.warmup is None:
+        args.warmup = 200 if args.leg == "c4single" else 20
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
         return 0
