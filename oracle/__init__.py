@@ -17,6 +17,7 @@ import numpy as np
 from . import build as _build
 
 _lib = None
+_lib_omp = None
 
 
 def lib():
@@ -27,6 +28,18 @@ def lib():
         _lib = C.CDLL(_build.LIB)
         _declare(_lib)
     return _lib
+
+
+def lib_omp():
+    """The same oracle source built with its OpenMP row loops (the two-phase
+    step on several threads; identical results)."""
+    global _lib_omp
+    if _lib_omp is None:
+        if not os.path.exists(_build.LIB_OMP):
+            _build.build()
+        _lib_omp = C.CDLL(_build.LIB_OMP)
+        _declare(_lib_omp)
+    return _lib_omp
 
 
 _dp = C.POINTER(C.c_double)
@@ -78,7 +91,20 @@ class P3Params(C.Structure):
                 ("normal_eps", C.c_double)]
 
 
+_variants = {}
+
+
+def _variant(path):
+    if path not in _variants:
+        L = C.CDLL(path)
+        _declare(L)
+        _variants[path] = L
+    return _variants[path]
+
+
 def _declare(L):
+    L.orc_set_threads.restype = C.c_int
+    L.orc_set_threads.argtypes = [C.c_int]
     L.orc_d1_run.restype = C.c_int
     L.orc_d1_run.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, C.c_double, C.c_double,
                              C.c_double, C.c_double, C.c_double, _dp, C.c_long, _dp]
@@ -186,7 +212,8 @@ class Chan:
         P.thermal_mrt = int(prm.get("thermal_mrt", 1))
         P.alpha = prm.get("alpha", 1e-7)
         P.rho_cp = prm.get("rho_cp", 1.0)
-        P.qdot = prm.get("qdot", 0.0)
+        # heat source in K/s from the volumetric rate, qdot = qvol / rho_cp (Eq. forcing_term_g)
+        P.qdot = prm.get("qvol", 0.0) / P.rho_cp
         P.T_ref = prm.get("T_ref", 0.0)
         P.flux_amp = prm.get("flux_amp", 0.0)
         P.flux_omega = prm.get("flux_omega", 0.0)
@@ -263,10 +290,16 @@ class Chan:
 
 class Phase:
     """Conservative Allen-Cahn h + pressure-evolution z on an nx x ny grid
-    (x periodic; y periodic or halfway walls)."""
+    (x periodic; y periodic or halfway walls).  threads > 0 runs the step on
+    that many threads (the OpenMP build of the same source); self.threads is
+    the count in effect."""
 
-    def __init__(self, nx, ny, prm, bc_y="periodic"):
+    def __init__(self, nx, ny, prm, bc_y="periodic", threads=0, variant=None):
         self.nx, self.ny = nx, ny
+        self._L = lib_omp() if threads > 0 else lib()
+        if variant is not None:  # a copy built by build.build_variant (pin self-check)
+            self._L = _variant(variant)
+        self.threads = self._L.orc_set_threads(int(threads)) if threads > 0 else 1
         P = PhaseParams()
         P.nx, P.ny = nx, ny
         P.bc_y = {"periodic": 0, "walls": 1}[bc_y]
@@ -281,45 +314,45 @@ class Phase:
         P.qy_printed = int(prm.get("qy_printed", 0))
         P.normal_eps = prm.get("normal_eps", 1e-12 / prm["dx"])
         self.P = P
-        self.h = lib().orc_phase_create(C.byref(P))
+        self.h = self._L.orc_phase_create(C.byref(P))
         if not self.h:
             raise ValueError("orc_phase_create failed")
 
     def __del__(self):
         if getattr(self, "h", None):
-            lib().orc_phase_destroy(self.h)
+            self._L.orc_phase_destroy(self.h)
             self.h = None
 
     def init(self, phi, p, ux, uy):
         sh = (self.ny, self.nx)
-        lib().orc_phase_init(self.h, _ptr(_f64(phi, sh)), _ptr(_f64(p, sh)), _ptr(_f64(ux, sh)),
+        self._L.orc_phase_init(self.h, _ptr(_f64(phi, sh)), _ptr(_f64(p, sh)), _ptr(_f64(ux, sh)),
                              _ptr(_f64(uy, sh)))
 
     def step(self, n):
-        lib().orc_phase_step(self.h, int(n))
+        self._L.orc_phase_step(self.h, int(n))
 
     def macros(self):
         sh = (self.ny, self.nx)
         out = {k: np.zeros(sh) for k in ("phi", "rho", "p", "ux", "uy", "mu")}
-        lib().orc_phase_macros(self.h, *(_ptr(out[k]) for k in
+        self._L.orc_phase_macros(self.h, *(_ptr(out[k]) for k in
                                          ("phi", "rho", "p", "ux", "uy", "mu")))
         return out
 
     def gradients(self):
         sh = (self.ny, self.nx)
         gx, gy, lap = np.zeros(sh), np.zeros(sh), np.zeros(sh)
-        lib().orc_phase_gradients(self.h, _ptr(gx), _ptr(gy), _ptr(lap))
+        self._L.orc_phase_gradients(self.h, _ptr(gx), _ptr(gy), _ptr(lap))
         return gx, gy, lap
 
     def get_state(self):
         h = np.zeros((9, self.ny, self.nx))
         z = np.zeros((9, self.ny, self.nx))
         pu = np.zeros((2, self.ny, self.nx))
-        lib().orc_phase_get_state(self.h, _ptr(h), _ptr(z), _ptr(pu))
+        self._L.orc_phase_get_state(self.h, _ptr(h), _ptr(z), _ptr(pu))
         return h, z, pu
 
     def set_state(self, h, z, pu):
-        lib().orc_phase_set_state(self.h, _ptr(_f64(h)), _ptr(_f64(z)), _ptr(_f64(pu)))
+        self._L.orc_phase_set_state(self.h, _ptr(_f64(h)), _ptr(_f64(z)), _ptr(_f64(pu)))
 
 
 def d3_mdim(c):

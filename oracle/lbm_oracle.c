@@ -14,6 +14,25 @@
 #include <stdlib.h>
 #include <string.h>
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Threads of the two-phase step.  The plain build ignores the OpenMP pragmas
+ * and runs on one thread; the OpenMP build (the benchmark's all-cores
+ * baseline) splits the rows of each node loop of that step over n threads.
+ * Each iteration writes only its own node, so both builds give the same
+ * numbers.  Returns the thread count in effect. */
+int orc_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
+
 /* ------------------------------------------------------------------------- */
 /* Velocity sets                                                              */
 /* ------------------------------------------------------------------------- */
@@ -1004,6 +1023,19 @@ void orc_phase_destroy(orc_phase* s) {
     free(s);
 }
 
+/* Planted-mistake switches, for the test that checks the transport pins
+ * themselves: ORC_PLANT_HEQ_U multiplies the c_i.u term of Eq. heq_liang in
+ * the collision and ORC_PLANT_DTPHIU the d_t(phi u) term of Eq.
+ * source_term_interface.  Both are 1 in every build the oracle is used from;
+ * only that test compiles copies with 0 (term dropped) or -1 (sign flipped)
+ * and requires the pins to fail on them. */
+#ifndef ORC_PLANT_HEQ_U
+#define ORC_PLANT_HEQ_U 1.0
+#endif
+#ifndef ORC_PLANT_DTPHIU
+#define ORC_PLANT_DTPHIU 1.0
+#endif
+
 /* s_i(u) of Eq. s_i_Liang */
 static double s_liang(int i, double ux, double uy, double c, double cs2) {
     double cu = c * (EX9[i] * ux + EY9[i] * uy);
@@ -1099,6 +1131,7 @@ static void phase_node(const orc_phase* s, int x, int y, phase_macro* m) {
 
 static void phase_compute_phi(orc_phase* s) {
     int nx = s->p.nx, ny = s->p.ny;
+#pragma omp parallel for schedule(static)
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             double a = 0;
@@ -1132,6 +1165,7 @@ static void phase_one_step(orc_phase* s) {
     size_t N = (size_t)nx * ny;
     double c = s->c, cs2 = s->cs2, dt = p->dt;
     phase_compute_phi(s);
+#pragma omp parallel for schedule(static)
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             size_t n = (size_t)y * nx + x;
@@ -1144,11 +1178,12 @@ static void phase_one_step(orc_phase* s) {
             s->phiu[N + n] = puy;
             /* interface populations: BGK with source (Eq. eq_lattice_boltzmann_interface,
              * source_term_interface, heq_liang) */
-            double ax = dtx + cs2 * 4.0 * m.phi * (1.0 - m.phi) * m.nx / p->W;
-            double ay = dty + cs2 * 4.0 * m.phi * (1.0 - m.phi) * m.ny / p->W;
+            double ax = ORC_PLANT_DTPHIU * dtx + cs2 * 4.0 * m.phi * (1.0 - m.phi) * m.nx / p->W;
+            double ay = ORC_PLANT_DTPHIU * dty + cs2 * 4.0 * m.phi * (1.0 - m.phi) * m.ny / p->W;
             for (int i = 0; i < 9; ++i) {
                 double cx = c * EX9[i], cy = c * EY9[i];
-                double heq = m.phi * W9[i] * (1.0 + (cx * m.ux + cy * m.uy) / cs2);
+                double heq = m.phi * W9[i] *
+                             (1.0 + ORC_PLANT_HEQ_U * (cx * m.ux + cy * m.uy) / cs2);
                 double Sh = (1.0 - dt / (2.0 * s->tau_phi)) * W9[i] * (cx * ax + cy * ay) / cs2;
                 double hi = s->h[PIDX(s, i, x, y)];
                 s->hs[PIDX(s, i, x, y)] = hi - dt / s->tau_phi * (hi - heq) + dt * Sh;
@@ -1190,6 +1225,7 @@ static void phase_one_step(orc_phase* s) {
         }
     /* streaming; x periodic, y periodic or halfway bounce-back walls for both
      * populations (Eq. BB_vel with u_w = 0; no-flux for h) */
+#pragma omp parallel for schedule(static)
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x)
             for (int i = 0; i < 9; ++i) {
