@@ -158,6 +158,14 @@ typedef struct {
        pi at 1/dt (BGK: every non-conserved moment at 1/tau).  LBM_D3Q19_PHASE
        takes the two-phase fields above */
     double Fb_z;            /* N/m^3                                                         */
+    /* Relaxation times given directly (s).  tau > 0 replaces nu and tau_T > 0
+       replaces alpha, through tau = nu / c_s^2 + dt/2 (Eq. eq_kinematic_viscosity)
+       and its thermal analogue: tau for LBM_D2Q9_D2Q5 flow and LBM_D3Q19, tau_T
+       for the LBM_D2Q9_D2Q5 temperature and the 1D lattices.  0 = derive them
+       from nu and alpha.  The discrete adjoint differentiates with respect to
+       these times, so a caller that steps along its gradient passes them here.
+       LBM_E_TAU if the resulting time is not above dt/2. */
+    double tau, tau_T;
 } lbm_params_si;
 
 /* Size in bytes of the device buffer a context with this description needs.
@@ -173,10 +181,14 @@ LBM_API lbm_status lbm_create(const lbm_desc* desc, lbm_ctx** out);
 LBM_API void lbm_destroy(lbm_ctx* ctx);
 
 /* Compile SI parameters into relaxation rates and kernel constants (Sec. 3:
- * c = dx/dt, c_s^2 = c^2/3 (D1Q2: c^2), tau from nu, tau_T from alpha, tau_phi
- * from M, the dimensional MRT rates, beta, kappa, qdot).  Returns LBM_E_TAU if
- * any relaxation time is not above dt/2, LBM_E_ARG for non-positive dx, dt or
- * densities.  Copies the flux / inlet arrays to the device. */
+ * c = dx/dt, c_s^2 = c^2/3 (D1Q2: c^2), tau from nu (or given), tau_T from
+ * alpha (or given), tau_phi from M (Eq. source_term_interface text), the
+ * dimensional MRT rates of Eq. M_matrix_dim with the omega_q relation of Sec. 3,
+ * beta = 12 sigma / W and kappa = 3 sigma W / 2 (Eq. chemical_potential text),
+ * qdot = qvol / rho_cp (Eq. forcing_term_g)).  Returns LBM_E_TAU if any
+ * relaxation time is not above dt/2, LBM_E_ARG for non-positive dx, dt or
+ * densities.  Copies the flux / inlet arrays to the device; the caller keeps
+ * ownership of p and of the arrays it points to. */
 LBM_API lbm_status lbm_set_params_SI(lbm_ctx* ctx, const lbm_params_si* p);
 
 /* 3D lattices: the populations at the equilibria of the given fields, host
@@ -189,11 +201,16 @@ LBM_API lbm_status lbm_init_fields3d(lbm_ctx* ctx, const double* rho_or_p, const
                                      const double* uy, const double* uz, const double* phi);
 
 /* Set the populations to the equilibria of the given macroscopic fields
- * (host float64 [batch][ny][nx], SI).  rho_or_p: density (D2Q9_D2Q5, ignored
- * otherwise) or pressure in Pa (PHASE); ux, uy: m/s (NULL = 0); T: K
- * (thermal and 1D); phi: order parameter (PHASE).  Also resets the step
- * counter and, for PHASE, sets (phi u) of the previous step to phi u.
- * Requires lbm_set_params_SI first. */
+ * (host float64 [batch][ny][nx], SI): f_i = f_i^eq of Eq. feq_geral, g_i =
+ * g_i^eq of Eq. geq_geral (advective part taken about T_ref), h_i = h_i^eq of
+ * Eq. heq_liang and z_i = z_i^eq of Eq. zeq_liang with s_i of Eq. s_i_Liang
+ * (the paper gives no initial condition; the equilibrium of the initial fields
+ * is the reading taken).  rho_or_p: density (D2Q9_D2Q5, ignored otherwise) or
+ * pressure in Pa (PHASE, NULL = 0); ux, uy: m/s (NULL = 0); T: K (thermal and
+ * 1D, required there); phi: order parameter (PHASE, required).  The arrays are
+ * read before the call returns.  Also resets the step counter and, for PHASE,
+ * sets (phi u) of the previous step to phi u.  LBM_E_STATE without
+ * lbm_set_params_SI first; LBM_E_ARG for a missing required field. */
 LBM_API lbm_status lbm_init_fields(lbm_ctx* ctx, const double* rho_or_p, const double* ux,
                            const double* uy, const double* T, const double* phi);
 
@@ -252,8 +269,13 @@ LBM_API lbm_status lbm_set_graph_steps(lbm_ctx* ctx, int steps);
 LBM_API lbm_status lbm_set_step_fusion(lbm_ctx* ctx, int mode);
 
 /* Macroscopic fields of the current state, evaluated in FP64 from the stored
- * populations.  mask selects fields; out receives them in bit order, each
- * [batch][ny][nx] float64:
+ * populations: rho = sum f_i (Eq. zero_moment_f), u = (sum c_i f_i + dt F/2) /
+ * rho (Eq. first_moment_f), T = sum g_i + dt qdot/2 (Eq. zero_moment_g); for
+ * the two-phase models phi = sum h_i (Eq. zero_moment_h), rho linear in phi
+ * (text after Eq. zero_moment_h), u from the z_i (Eq. u_Liang), p (Eq.
+ * p_Liang) and mu (Eq. chemical_potential).  mask selects fields; out receives
+ * them in bit order, each [batch][ny][nx] float64 (caller-owned, popcount(mask)
+ * x batch x ny x nx doubles):
  *   LBM_M_RHO (density), LBM_M_P (PHASE pressure, Pa), LBM_M_UX, LBM_M_UY (m/s),
  *   LBM_M_T (K), LBM_M_PHI, LBM_M_MU (chemical potential, Pa), LBM_M_UZ (m/s,
  *   3D lattices).  LBM_D3Q19_PHASE offers RHO, P, UX, UY, UZ, PHI and MU.
@@ -264,7 +286,13 @@ enum { LBM_M_RHO = 1, LBM_M_P = 2, LBM_M_UX = 4, LBM_M_UY = 8, LBM_M_T = 16,
 LBM_API lbm_status lbm_macros(lbm_ctx* ctx, unsigned mask, double* out, int out_on_device);
 
 /* FP64 global sums per replica, deterministic (fixed-order two-pass
- * reduction).  out receives, per selected bit in bit order, batch values:
+ * reduction): the conserved totals of the method -- the mass sum rho (Eq.
+ * zero_moment_f, conserved by the collision of Eq. colisao_MRT), the order
+ * parameter sum phi (Eq. zero_moment_h, conserved by the conservative
+ * Allen-Cahn equation, Eq. Allen_cahn) and the energy sum T (Eq.
+ * zero_moment_g) -- evaluated from the stored populations.  out (host,
+ * caller-owned, popcount(mask) x batch doubles) receives, per selected bit in
+ * bit order, batch values:
  *   LBM_R_MASS (sum of rho, kg/m^3 * nodes), LBM_R_PHASE (sum of phi),
  *   LBM_R_ENERGY (sum of T, K * nodes), LBM_R_NONFINITE (count of NaN/Inf
  *   populations).  Synchronous.  Returns LBM_E_NONFINITE when any population

@@ -6,7 +6,15 @@ tau)`` returns the objective J = w_tout T_out + w_nu mean Nu after ``nsteps``
 steps as a torch scalar whose backward runs the library's hand-written
 adjoint (lbm_grad): gradients with respect to the wall-flux profile
 (W/m^2, one value per column) and to (tau, tau_T) (s).  Forward and backward
-both run in the HIP kernels behind the C ABI; this module only marshals.
+both run in the HIP kernels behind the C ABI; this module only marshals (the
+relaxation times go to the library as they are, through the tau and tau_T
+parameters).
+
+The library keeps the checkpoints of the last recorded forward run only.
+Each forward run gets a generation number; a backward through an older
+graph node re-records that node's own forward run (flux and tau saved with
+it) before differentiating, so every backward returns the gradient at its own
+inputs, whatever ran in between.
 """
 import numpy as np
 
@@ -19,16 +27,23 @@ def _make_function():
     class ChannelObjective(torch.autograd.Function):
         @staticmethod
         def forward(ctx, flux, tau, problem):
-            J = problem._forward(flux.detach().cpu().double().numpy(),
-                                 tau.detach().cpu().double().numpy())
+            q = flux.detach().cpu().double().numpy().copy()
+            t = tau.detach().cpu().double().numpy().copy()
+            J = problem._forward(q, t)
             ctx.problem = problem
+            ctx.generation = problem.generation
+            ctx.inputs = (q, t)
             ctx.flux_meta = (flux.dtype, flux.device)
             ctx.tau_meta = (tau.dtype, tau.device)
             return torch.tensor(J, dtype=torch.float64)
 
         @staticmethod
         def backward(ctx, gJ):
-            gq, gt = ctx.problem.L.grad(float(gJ))
+            prob = ctx.problem
+            if prob.generation != ctx.generation:
+                # another forward run replaced the library's checkpoints
+                prob._forward(*ctx.inputs)
+            gq, gt = prob.L.grad(float(gJ))
             dq = torch.as_tensor(gq, dtype=ctx.flux_meta[0], device=ctx.flux_meta[1])
             dt = torch.as_tensor(gt, dtype=ctx.tau_meta[0], device=ctx.tau_meta[1])
             return dq, dt, None
@@ -51,27 +66,24 @@ class ChannelAdjoint:
         self.nsteps, self.ckpt = nsteps, ckpt_every
         self.x_dev = nx // 2 if x_dev is None else x_dev
         self.w = (w_tout, w_nu)
+        self.generation = 0
         self.L = lbm.Lattice("channel", nx, ny, prec=prec,
                              bc=(lbm.BC_VEL_INLET, lbm.BC_P_OUTLET, lbm.BC_WALL, lbm.BC_WALL),
                              flow=True, thermal=True, device=device)
-        dx, dt = prm["dx"], prm["dt"]
-        self.cs2 = (dx / dt) ** 2 / 3.0
-
-    def tau_of(self):
-        """Current (tau, tau_T) implied by nu and alpha."""
-        dt = self.prm["dt"]
-        return np.array([self.prm["nu"] / self.cs2 + dt / 2, self.prm["alpha"] / self.cs2 + dt / 2])
 
     def _forward(self, flux, tau):
-        dt = self.prm["dt"]
-        prm = dict(self.prm, flux=flux, nu=(tau[0] - dt / 2) * self.cs2,
-                   alpha=(tau[1] - dt / 2) * self.cs2)
+        prm = dict(self.prm, flux=flux, tau=float(tau[0]), tau_T=float(tau[1]))
         self.L.set_params(prm)
         self.L.init(self.ini["rho"], self.ini["ux"], self.ini["uy"], self.ini["T"])
-        return self.L.record(self.nsteps, self.ckpt, self.x_dev, *self.w)
+        J = self.L.record(self.nsteps, self.ckpt, self.x_dev, *self.w)
+        self.generation += 1
+        return J
 
     def J(self, flux, tau):
         global _FN
         if _FN is None:
             _FN = _make_function()
         return _FN.apply(flux, tau, self)
+
+    def close(self):
+        self.L.close()

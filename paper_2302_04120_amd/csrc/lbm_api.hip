@@ -367,6 +367,13 @@ hipError_t step_replay(lbm_ctx* c) {
     return e;
 }
 
+// Relaxation time from a diffusivity, tau = D / c_s^2 + dt/2 (Eq.
+// eq_kinematic_viscosity and its thermal analogue), unless the caller gave
+// tau itself (tau_given > 0).
+double tau_or_nu(double tau_given, double D, double cs2, double dt) {
+    return tau_given > 0 ? tau_given : D / cs2 + 0.5 * dt;
+}
+
 template <typename S>
 hipError_t upload_aux(lbm_ctx* c, const lbm_params_si* p) {
     const int nx = c->desc.nx, ny = c->desc.ny;
@@ -490,6 +497,7 @@ lbm_status lbm_set_params_SI(lbm_ctx* c, const lbm_params_si* p) {
     D3K d3k{};
     P3K p3k{};
     AdjK ak{};
+    double alpha_eff = p->alpha;  // thermal diffusivity implied by tau_T, m^2/s
     if (d.lattice == LBM_D3Q19_PHASE) {
         const double cs2 = cc * cc / 3.0;
         p3k.nx = d.nx; p3k.ny = d.ny; p3k.nz = d.nz; p3k.batch = d.batch; p3k.P = c->P;
@@ -531,9 +539,9 @@ lbm_status lbm_set_params_SI(lbm_ctx* c, const lbm_params_si* p) {
         d3k.bcy = d.bc[2] == LBM_BC_WALL;
         d3k.bcz = d.bc_z[0] == LBM_BC_WALL;
         if (!(p->rho_ref > 0)) return set_err(c, LBM_E_ARG, "rho_ref must be positive");
-        if (!(p->nu > 0)) return set_err(c, LBM_E_TAU, "tau not above dt/2 (nu <= 0)");
+        const double tau = tau_or_nu(p->tau, p->nu, cs2, dt);  // Eq. eq_kinematic_viscosity
+        if (!(tau > 0.5 * dt)) return set_err(c, LBM_E_TAU, "tau not above dt/2");
         d3k.rho_ref = p->rho_ref;
-        const double tau = p->nu / cs2 + 0.5 * dt;  // Eq. eq_kinematic_viscosity
         const double wn = dt / tau;
         if (p->flow_collision == LBM_MRT) {
             // Sec. 3 in the 3D basis: e, eps free; stresses at 1/tau; q (and the
@@ -555,8 +563,9 @@ lbm_status lbm_set_params_SI(lbm_ctx* c, const lbm_params_si* p) {
     } else if (d.lattice == LBM_D1Q2 || d.lattice == LBM_D1Q3) {
         const double cs2 = d.lattice == LBM_D1Q2 ? cc * cc : cc * cc / 3.0;
         if (!(p->rho_cp > 0)) return set_err(c, LBM_E_ARG, "rho_cp must be positive");
-        if (!(p->alpha > 0)) return set_err(c, LBM_E_TAU, "tau_T not above dt/2 (alpha <= 0)");
-        const double tau = p->alpha / cs2 + 0.5 * dt;
+        const double tau = tau_or_nu(p->tau_T, p->alpha, cs2, dt);
+        if (!(tau > 0.5 * dt)) return set_err(c, LBM_E_TAU, "tau_T not above dt/2");
+        alpha_eff = (tau - 0.5 * dt) * cs2;
         dk.n = d.nx;
         dk.q = d.lattice == LBM_D1Q2 ? 2 : 3;
         dk.w_tau = dt / tau;
@@ -577,8 +586,8 @@ lbm_status lbm_set_params_SI(lbm_ctx* c, const lbm_params_si* p) {
         if (!(p->rho_ref > 0)) return set_err(c, LBM_E_ARG, "rho_ref must be positive");
         ck.rho_ref = p->rho_ref;
         if (ck.flow) {
-            if (!(p->nu > 0)) return set_err(c, LBM_E_TAU, "tau not above dt/2 (nu <= 0)");
-            const double tau = p->nu / cs2 + 0.5 * dt;  // Eq. eq_kinematic_viscosity
+            const double tau = tau_or_nu(p->tau, p->nu, cs2, dt);  // Eq. eq_kinematic_viscosity
+            if (!(tau > 0.5 * dt)) return set_err(c, LBM_E_TAU, "tau not above dt/2");
             const double wn = dt / tau;
             // dimensional w_q = (3/dt)(2/dt - w_nu)/(3/dt - w_nu) (Sec. 3), times dt
             const double wq = 3.0 * (2.0 - wn) / (3.0 - wn);
@@ -595,9 +604,10 @@ lbm_status lbm_set_params_SI(lbm_ctx* c, const lbm_params_si* p) {
         ck.Ft[0] = p->Fb[0] * dt * dt / dx;
         ck.Ft[1] = p->Fb[1] * dt * dt / dx;
         if (ck.thermal) {
-            if (!(p->alpha > 0)) return set_err(c, LBM_E_TAU, "tau_T not above dt/2 (alpha <= 0)");
+            const double tauT = tau_or_nu(p->tau_T, p->alpha, cs2, dt);
+            if (!(tauT > 0.5 * dt)) return set_err(c, LBM_E_TAU, "tau_T not above dt/2");
             if (!(p->rho_cp > 0)) return set_err(c, LBM_E_ARG, "rho_cp must be positive");
-            const double tauT = p->alpha / cs2 + 0.5 * dt;
+            alpha_eff = (tauT - 0.5 * dt) * cs2;
             const double wT = dt / tauT, dwT = -dt / (tauT * tauT);
             // MRT: the fluxes j relax at dt/tau_T, the conserved T not at all, the
             // rest at 1 (Lambda_T,dim of Sec. 3 on D2Q9; its two-rate analogue on D2Q5)
@@ -675,7 +685,7 @@ lbm_status lbm_set_params_SI(lbm_ctx* c, const lbm_params_si* p) {
     c->dt = dt;
     c->dx = dx;
     c->rho_cp = p->rho_cp;
-    c->k_cond = p->rho_cp * p->alpha;
+    c->k_cond = p->rho_cp * alpha_eff;
     // hydraulic diameter 2H; with a symmetry plane the grid is half of H
     c->Dh = 2.0 * d.ny * dx * (d.lattice == LBM_D2Q9_D2Q5 && d.bc[3] == LBM_BC_SYMMETRY ? 2.0 : 1.0);
     uint64_t h = 1469598103934665603ull;

@@ -7,12 +7,18 @@ to anything else: if ``liblbm.so`` is missing or no GPU is visible it raises.
 
 Parameter dicts use SI units and the keys of ``workloads``: dx, dt, rho_ref,
 nu, omega_e, omega_eps, Fx, Fy, flow_mrt, thermal_mrt, T_ref, alpha, rho_cp,
-qdot (K/s), flux, flux_amp, flux_omega, inlet_u, inlet_T, T0, TL, rho_l,
+qvol (W/m^3), flux, flux_amp, flux_omega, inlet_u, inlet_T, T0, TL, rho_l,
 rho_g, nu_l, nu_g, zeta_l, zeta_g, visc_mode, sigma, W, M, z_mrt, qy_printed,
-normal_eps, beta_T, gravity, T_wall; and for D3Q19 F = (Fx, Fy, Fz).
+normal_eps, beta_T, gravity, T_wall, tau, tau_T; and for D3Q19 F = (Fx, Fy, Fz).
+Every value is passed to the library as given (no unit conversion here).
+
+Contexts are destroyed by ``Lattice.close()``, when the object is collected,
+or at the latest by an exit hook that runs while the HIP runtime is still up.
 """
+import atexit
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 
@@ -70,7 +76,7 @@ class ParamsSI(C.Structure):
                 ("visc_mode", C.c_int), ("sigma", C.c_double), ("W", C.c_double),
                 ("mobility", C.c_double), ("z_collision", C.c_int), ("qy_printed", C.c_int),
                 ("normal_eps", C.c_double), ("beta_T", C.c_double), ("gravity", C.c_double * 2),
-                ("Fb_z", C.c_double)]
+                ("Fb_z", C.c_double), ("tau", C.c_double), ("tau_T", C.c_double)]
 
 
 _lib = None
@@ -144,7 +150,7 @@ def make_params(prm, nx=None, ny=None):
     P.T_ref = float(prm.get("T_ref", 0.0))
     P.alpha = float(prm.get("alpha", 1e-7))
     P.rho_cp = float(prm.get("rho_cp", 1.0))
-    P.qvol = float(prm.get("qdot", 0.0)) * P.rho_cp
+    P.qvol = float(prm.get("qvol", 0.0))
     for key in ("flux", "inlet_u", "inlet_T"):
         if prm.get(key) is not None:
             n = nx if key == "flux" else ny
@@ -167,7 +173,19 @@ def make_params(prm, nx=None, ny=None):
     P.z_collision = LBM_MRT if int(prm.get("z_mrt", 1)) else LBM_BGK
     P.qy_printed = int(prm.get("qy_printed", 0))
     P.normal_eps = float(prm.get("normal_eps", 0.0))
+    P.tau = float(prm.get("tau", 0.0))
+    P.tau_T = float(prm.get("tau_T", 0.0))
     return P, keep
+
+
+# live contexts, destroyed at exit (before the interpreter tears torch down)
+_LIVE = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    for lat in list(_LIVE):
+        lat.close()
 
 
 class Lattice:
@@ -220,6 +238,7 @@ class Lattice:
         self.lattice, self.nx, self.ny, self.batch, self.prec = lattice, nx, ny, batch, prec
         self.nz = nz if three_d else 1
         self.bytes = int(nbytes.value)
+        _LIVE.add(self)
 
     def _check(self, st, ctx="self"):
         if st != LBM_OK:
@@ -227,17 +246,31 @@ class Lattice:
             msg = lib().lbm_last_error(c).decode() if c else "(no context)"
             raise LbmError(st, msg)
 
-    def __del__(self):
-        # the library handle is held on the instance: at interpreter shutdown
-        # the module globals may already be gone
+    def close(self):
+        """Wait for the context's stream, destroy the context (its captured
+        graphs and capture stream) and release the device buffers.  Idempotent."""
         L = getattr(self, "_lib", None)
         if getattr(self, "ctx", None) and L is not None:
             try:
-                self.torch.cuda.synchronize(self.device)
+                self.stream.synchronize()
             except Exception:
                 pass
             L.lbm_destroy(self.ctx)
             self.ctx = None
+        self.buf = None
+        self._work = None
+
+    def __del__(self):
+        # the library handle is held on the instance: at interpreter shutdown
+        # the module globals may already be gone
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
 
     @property
     def shape(self):

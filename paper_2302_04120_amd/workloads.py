@@ -78,8 +78,8 @@ def slab_1d(seed=0, n=101, L=0.1, alpha=1e-5, k=1.0, qvol=1e4, T_wall=300.0, dt=
     rho_cp = k / alpha
     T0 = np.full(n, T_wall)
     T0[1:-1] += rng(seed).uniform(-noise, noise, n - 2)
-    prm = dict(dx=dx, dt=dt, alpha=alpha, rho_cp=rho_cp, qdot=qvol / rho_cp, T0=T_wall,
-               TL=T_wall, k=k, L=L, qvol=qvol)
+    prm = dict(dx=dx, dt=dt, alpha=alpha, rho_cp=rho_cp, T0=T_wall, TL=T_wall, k=k, L=L,
+               qvol=qvol)
     return prm, T0
 
 
@@ -110,7 +110,7 @@ def channel(nx=800, ny=40, dx=2.5e-5, nu=1e-6, Pr=7.0, Re=50.0, q_s=1e4, T_in=30
     u_in = poiseuille_profile(y, H, u_m)
     T_prof = developed_temperature_profile(y, H, T_in, q_s, k) if developed else np.full(ny, T_in)
     prm = dict(dx=dx, dt=dt, rho_ref=rho, nu=nu, omega_e=1.0 / dt, omega_eps=1.0 / dt,
-               Fx=0.0, Fy=0.0, alpha=alpha, rho_cp=rho_cp, qdot=0.0, T_ref=T_in,
+               Fx=0.0, Fy=0.0, alpha=alpha, rho_cp=rho_cp, qvol=0.0, T_ref=T_in,
                flux=np.full(nx, q_s), flux_amp=0.5 if oscillating else 0.0,
                flux_omega=2.0 * math.pi * u_m / L if oscillating else 0.0,
                inlet_u=u_in, inlet_T=T_prof, flow_mrt=1, thermal_mrt=1,
@@ -223,7 +223,7 @@ def cavity(Ra=1e4, dx=2e-4, dt=2e-4, n=None, g=9.81):
     a = AIR_333K
     T_ref = 333.50
     prm = dict(dx=dx, dt=dt, rho_ref=a["rho"], nu=a["nu"], omega_e=1.0 / dt, omega_eps=1.0 / dt,
-               Fx=0.0, Fy=0.0, alpha=a["alpha"], rho_cp=a["rho"] * a["cp"], qdot=0.0,
+               Fx=0.0, Fy=0.0, alpha=a["alpha"], rho_cp=a["rho"] * a["cp"], qvol=0.0,
                T_ref=T_ref, flux=np.zeros(n), flux_amp=0.0, flux_omega=0.0,
                inlet_u=np.zeros(n), inlet_T=np.full(n, T_ref), flow_mrt=0, thermal_mrt=1,
                T_wall=(Th, Tc), beta_T=a["beta"], gravity=(0.0, -g),
@@ -271,7 +271,7 @@ def paper_channel(case, H=0.5e-3, L=10e-3, T_in=300.0, q_s=4e4, dq=4e4, L_h=1e-3
         u_in = np.full(ny, u_m)
         T_prof = np.full(ny, T_in)
     prm = dict(dx=dx, dt=dt, rho_ref=w["rho"], nu=w["nu"], omega_e=1.0 / dt, omega_eps=1.0 / dt,
-               Fx=0.0, Fy=0.0, alpha=w["alpha"], rho_cp=rho_cp, qdot=0.0, T_ref=T_in,
+               Fx=0.0, Fy=0.0, alpha=w["alpha"], rho_cp=rho_cp, qvol=0.0, T_ref=T_in,
                flux=flux, flux_amp=0.0, flux_omega=0.0, inlet_u=u_in, inlet_T=T_prof,
                flow_mrt=0, thermal_mrt=1, k=k, H=H, L=L, u_m=u_m, q_s=q_s, T_in=T_in)
     ux0 = np.repeat(u_in[:, None], nx, axis=1) if developed else np.zeros((ny, nx))

@@ -26,7 +26,7 @@ def chan_to_lattice(prm):
                nu=prm.get("nu", 1e-6) / S["nu"], alpha=prm.get("alpha", 1e-7) / S["nu"],
                omega_e=prm.get("omega_e", 1.0 / dt) * dt, omega_eps=prm.get("omega_eps", 1.0 / dt) * dt,
                Fx=prm.get("Fx", 0.0) / S["force"], Fy=prm.get("Fy", 0.0) / S["force"],
-               qdot=prm.get("qdot", 0.0) * dt, T_ref=0.0,
+               qvol=prm.get("qvol", 0.0) / prm.get("rho_cp", 1.0) * dt, T_ref=0.0,
                rho_cp=1.0,
                flux=np.asarray(prm.get("flux", 0.0)) * dt / (dx * prm.get("rho_cp", 1.0)),
                flux_omega=prm.get("flux_omega", 0.0) * dt,

@@ -91,6 +91,13 @@ def test_adjoint_c5_copy_200x10(prec, tol):
     np.testing.assert_allclose(gt, gt0, rtol=max(tol, 1e-8) * 10)
 
 
+def _taus(prm):
+    """(tau, tau_T) of the case: tau = nu / c_s^2 + dt/2 and its thermal analogue."""
+    c = prm["dx"] / prm["dt"]
+    cs2 = c * c / 3
+    return np.array([prm["nu"] / cs2 + prm["dt"] / 2, prm["alpha"] / cs2 + prm["dt"] / 2])
+
+
 def test_autograd_function_matches_lbm_grad():
     import torch
     from paper_2302_04120_amd.adjoint import ChannelAdjoint
@@ -99,13 +106,49 @@ def test_autograd_function_matches_lbm_grad():
     prm, ini = _case(nx, ny, 1e-4)
     prob = ChannelAdjoint(prm, ini, nx, ny, nsteps=200, ckpt_every=50, prec="fp64")
     flux = torch.tensor(prm["flux"], dtype=torch.float64, requires_grad=True)
-    tau = torch.tensor(prob.tau_of(), dtype=torch.float64, requires_grad=True)
+    tau = torch.tensor(_taus(prm), dtype=torch.float64, requires_grad=True)
     J = prob.J(flux, tau)
     (2.0 * J).backward()
     J0, gq0, gt0 = _oracle_adjoint(prm, ini, nx, ny, 200, 50)
     assert float(J.detach()) == pytest.approx(J0, rel=1e-12)
     assert _rel(flux.grad.numpy(), 2 * gq0) < 1e-9
     np.testing.assert_allclose(tau.grad.numpy(), 2 * gt0, rtol=1e-8)
+    prob.close()
+
+
+def test_autograd_backward_after_a_second_forward():
+    """J(q1, tau1), then J(q2, tau2), then backward through the first: the
+    gradient must be the one at (q1, tau1), equal to a single call's, although
+    the library's checkpoints hold the second run; then backward through the
+    second gives the single-call gradient at (q2, tau2)."""
+    import torch
+    from paper_2302_04120_amd.adjoint import ChannelAdjoint
+    print_case(test="autograd_two_forwards")
+    nx, ny = 40, 8
+    prm, ini = _case(nx, ny, 1e-4)
+    prob = ChannelAdjoint(prm, ini, nx, ny, nsteps=200, ckpt_every=50, prec="fp64")
+    t1 = _taus(prm)
+    q2 = prm["flux"] * WL.rng(7).uniform(0.5, 1.5, nx)
+    t2 = t1 * np.array([1.05, 0.97])
+
+    def leaf(a):
+        return torch.tensor(a, dtype=torch.float64, requires_grad=True)
+
+    ref = {}
+    for name, (q, t) in (("one", (prm["flux"], t1)), ("two", (q2, t2))):
+        fq, ft = leaf(q), leaf(t)
+        prob.J(fq, ft).backward()
+        ref[name] = (fq.grad.numpy().copy(), ft.grad.numpy().copy())
+    assert _rel(ref["one"][0], ref["two"][0]) > 1e-3  # the two points differ
+    fq1, ft1, fq2, ft2 = leaf(prm["flux"]), leaf(t1), leaf(q2), leaf(t2)
+    J1 = prob.J(fq1, ft1)
+    J2 = prob.J(fq2, ft2)
+    J1.backward()
+    J2.backward()
+    for (gq, gt), (fq, ft) in ((ref["one"], (fq1, ft1)), (ref["two"], (fq2, ft2))):
+        np.testing.assert_array_equal(fq.grad.numpy(), gq)
+        np.testing.assert_array_equal(ft.grad.numpy(), gt)
+    prob.close()
 
 
 def test_adjoint_c5_full_size_vs_finite_differences():

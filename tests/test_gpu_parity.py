@@ -83,7 +83,7 @@ def test_channel_thermal_only_bgk_source(prec, tol):
     dt = 0.2 * dx * dx / (3 * alpha)
     g0 = WL.rng(5)
     prm = dict(dx=dx, dt=dt, rho_ref=1000.0, alpha=alpha, rho_cp=4e6, T_ref=300.0,
-               qdot=0.5, thermal_mrt=0, flux=g0.uniform(0, 2e4, nx))
+               qvol=2e6, thermal_mrt=0, flux=g0.uniform(0, 2e4, nx))
     ini = dict(rho=np.full((ny, nx), 1000.0), ux=np.full((ny, nx), 2e-3),
                uy=np.zeros((ny, nx)), T=300 + g0.uniform(-1, 1, (ny, nx)))
     g, o, _, _ = channel_pair(prm, ini, nx, ny, 250, prec, bc_x="periodic", bc_y="walls",
@@ -205,7 +205,7 @@ def test_d1_slab_matches_oracle_and_analytic():
         L.init(T=T0)
         L.step(200000)
         T = L.macros(("T",))["T"][0, 0]
-        To = O.d1_run(q, 101, prm["dx"], prm["dt"], prm["alpha"], prm["qdot"], 300, 300, T0, 200000)
+        To = O.d1_run(q, 101, prm["dx"], prm["dt"], prm["alpha"], prm["qvol"] / prm["rho_cp"], 300, 300, T0, 200000)
         assert np.abs(T - To).max() < 1e-9
         assert np.abs(T - Ta).max() < 1e-6
 

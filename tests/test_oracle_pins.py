@@ -223,7 +223,7 @@ def test_slab_with_source_steady_profile(q):
     steady state is T = T_w + q''' x (L - x) / (2 k) (Sec. 4.1 machinery with
     the wet-node Dirichlet rule of App. B)."""
     prm, T0 = WL.slab_1d(seed=0)
-    T = O.d1_run(q, 101, prm["dx"], prm["dt"], prm["alpha"], prm["qdot"], prm["T0"], prm["TL"],
+    T = O.d1_run(q, 101, prm["dx"], prm["dt"], prm["alpha"], prm["qvol"] / prm["rho_cp"], prm["T0"], prm["TL"],
                  T0, 200000)
     x = np.arange(101) * prm["dx"]
     Ta = 300 + prm["qvol"] * x * (prm["L"] - x) / (2 * prm["k"])
