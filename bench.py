@@ -57,7 +57,36 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_gpu(batch, steps, warmup, prec, n=256, fusion=0):
+def timed(L, steps):
+    """HIP events on the library's stream around lbm_step(steps), and the
+    host wall time of the same interval: (event ms, wall s)."""
+    import torch
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(L.stream)
+    t0 = time.perf_counter()
+    L.step(steps)
+    e1.record(L.stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1), time.perf_counter() - t0
+
+
+def sustained(L, nodes, ms_per_step, windows=5, seconds=1.0, even=True):
+    """Throughput over `windows` windows of at least `seconds` each: the
+    median, min and max MLUPS (HIP events) and the steps per window."""
+    n = max(2, int(np.ceil(seconds * 1e3 / max(ms_per_step, 1e-6))))
+    if even:
+        n += n & 1
+    rates = []
+    for _ in range(windows):
+        ms, _ = timed(L, n)
+        rates.append(nodes * n / (ms * 1e-3) / 1e6)
+    return dict(median_mlups=float(np.median(rates)), min_mlups=float(min(rates)),
+                max_mlups=float(max(rates)), windows=windows, steps_per_window=n)
+
+
+def run_gpu(batch, steps, warmup, prec, n=256, fusion=0, windows=0):
     import torch
     from paper_2302_04120_amd import lbm, workloads as WL
     prm, ini, _ = WL.bubble(n=n, batch=batch, seed=0)
@@ -85,8 +114,12 @@ def run_gpu(batch, steps, warmup, prec, n=256, fusion=0):
     nodes = batch * n * n
     # sum of phi per replica, FP64 reduction: drift over warm-up + timed steps
     drift = float((abs(red["phase"] - phase0) / abs(phase0)).max())
-    return dict(wall=wall, ev_ms=ev_ms, nodes=nodes, kernel_ms=ev_ms / steps,
-                bytes_gb=L.bytes / 1e9, phi_sum_drift=drift)
+    out = dict(wall=wall, ev_ms=ev_ms, nodes=nodes, kernel_ms=ev_ms / steps,
+               bytes_gb=L.bytes / 1e9, phi_sum_drift=drift)
+    if windows:
+        out["sustained"] = sustained(L, nodes, ev_ms / steps, windows)
+    L.close()
+    return out
 
 
 def run_channel(nx, ny, steps, warmup, prec):
@@ -113,6 +146,7 @@ def run_channel(nx, ny, steps, warmup, prec):
     wall = time.perf_counter() - t0
     kernel_ms = e0.elapsed_time(e1) / steps
     nodes = nx * ny
+    L.close()
     return dict(mlups=nodes * steps / wall / 1e6, kernel_ms=kernel_ms,
                 hbm_frac=CHAN_BYTES_PER_LU[prec] * nodes / (kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                 grid="%dx%d" % (nx, ny))
@@ -142,6 +176,7 @@ def run_d3(n, steps, warmup, prec, mrt=True):
         raise RuntimeError("non-finite populations after the timed steps")
     kernel_ms = e0.elapsed_time(e1) / steps
     nodes = n ** 3
+    L.close()
     gbs = D3_BYTES_PER_LU[prec] * nodes / (kernel_ms * 1e-3) / 1e9
     return dict(mlups=nodes * steps / wall / 1e6, kernel_ms=kernel_ms, hbm_GBps=gbs,
                 hbm_frac=gbs / HBM_PEAK_GBS, grid="%d^3" % n, collision="mrt" if mrt else "bgk",
@@ -177,6 +212,7 @@ def run_p3(n, steps, warmup, prec, cell=64, R_nodes=16.0):
         raise RuntimeError("non-finite populations after the timed steps")
     step_ms = e0.elapsed_time(e1) / steps
     nodes = n ** 3
+    L.close()
     gbs = P3_BYTES_PER_LU[prec] * nodes / (step_ms * 1e-3) / 1e9
     return dict(mlups=nodes * steps / wall / 1e6, step_ms=step_ms, state_GBps=gbs,
                 state_frac=gbs / HBM_PEAK_GBS, grid="%d^3" % n,
@@ -208,6 +244,7 @@ def run_layered_batch(batch, steps, warmup, prec):
         raise RuntimeError("non-finite populations after the timed steps")
     step_ms = e0.elapsed_time(e1) / steps
     nodes = batch * 4 * 512
+    L.close()
     gbs = BYTES_PER_LU[prec] * nodes / (step_ms * 1e-3) / 1e9
     return dict(mlups=nodes * steps / wall / 1e6, step_ms=step_ms, hbm_GBps=gbs,
                 hbm_frac=gbs / HBM_PEAK_GBS, replicas=batch, grid="4x512")
@@ -238,6 +275,7 @@ def run_c4_single(steps=20000, warmup=200, prec="fp32"):
         torch.cuda.synchronize()
         out[name + "_us_per_step"] = e0.elapsed_time(e1) / steps * 1e3
         states[name] = L.save_state()
+        L.close()
     out["bit_identical"] = states["graph_replay"] == states["many_steps"]
     out["steps"] = steps
     return out
@@ -282,6 +320,7 @@ def run_c4_steady(system="sat_water_25C", prec="fp32", decay_times=6.5, chunk=2_
     if L.reduce(("nonfinite",))["nonfinite"].sum() != 0:
         raise RuntimeError("non-finite populations")
     m = L.macros(("ux", "phi"))
+    L.close()
     u, phi = m["ux"][0, :, 0], m["phi"][0, :, 0]
     y = (np.arange(ny) + 0.5) * prm["dx"]
 
@@ -322,6 +361,7 @@ def adjoint_cost(steps=20000, ckpt=500, prec="fp32"):
     t0 = time.perf_counter()
     L.grad()
     t_grad = time.perf_counter() - t0
+    L.close()
     return dict(forward_s=t_fwd, record_s=t_rec, grad_s=t_grad,
                 adjoint_over_forward=t_grad / t_fwd,
                 record_plus_grad_over_forward=(t_rec + t_grad) / t_fwd,
@@ -342,23 +382,39 @@ def host_cpu():
     return {"nproc": len(os.sched_getaffinity(0)), "model": model}
 
 
-def cpu_baseline(seconds=12.0):
-    """The FP64 oracle on one 256 x 256 replica of the same workload."""
+def cpu_baseline(seconds=8.0):
+    """The FP64 oracle on one 256 x 256 replica of the same workload: on one
+    thread, and the same source with its OpenMP row loops on every host core
+    (identical state after the same steps, checked)."""
     import oracle as O
     from paper_2302_04120_amd import workloads as WL
     prm, ini, _ = WL.bubble(n=256, batch=1, seed=0)
-    ph = O.Phase(256, 256, prm)
-    ph.init(ini["phi"][0], ini["p"][0], ini["ux"][0], ini["uy"][0])
-    t0 = time.perf_counter()
-    steps = 0
-    while time.perf_counter() - t0 < seconds:
-        ph.step(10)
-        steps += 10
-    dt = time.perf_counter() - t0
-    base = dict(value=256 * 256 * steps / dt / 1e6, unit="MLUPS", cores=1, kind="oracle",
-                sample="one 256x256 replica of the bubble workload, %d steps, FP64, single thread"
-                       % steps, host=host_cpu())
-    return base, parity_vs_oracle(prm, ini, ph.macros(), steps)
+    host = host_cpu()
+
+    def timed_oracle(threads):
+        ph = O.Phase(256, 256, prm, threads=threads)
+        ph.init(ini["phi"][0], ini["p"][0], ini["ux"][0], ini["uy"][0])
+        t0 = time.perf_counter()
+        steps = 0
+        while time.perf_counter() - t0 < seconds:
+            ph.step(10)
+            steps += 10
+        return ph, steps, time.perf_counter() - t0
+
+    ph1, s1, t1 = timed_oracle(0)
+    phn, sn, tn = timed_oracle(host["nproc"])
+    # same source, same order of operations per node: the states after the
+    # same number of steps are identical
+    ref = O.Phase(256, 256, prm)
+    ref.init(ini["phi"][0], ini["p"][0], ini["ux"][0], ini["uy"][0])
+    ref.step(sn)
+    identical = all(np.array_equal(a, b) for a, b in zip(ref.get_state(), phn.get_state()))
+    single = dict(value=256 * 256 * s1 / t1 / 1e6, unit="MLUPS", cores=1, steps=s1)
+    base = dict(value=256 * 256 * sn / tn / 1e6, unit="MLUPS", cores=phn.threads, kind="oracle",
+                sample="one 256x256 replica of the bubble workload, %d steps, FP64, the oracle's "
+                       "OpenMP build on %d threads (rows split per node loop)" % (sn, phn.threads),
+                single_thread=single, identical_to_single_thread=bool(identical), host=host)
+    return base, parity_vs_oracle(prm, ini, ph1.macros(), s1)
 
 
 def parity_vs_oracle(prm, ini, mo_long, steps_long, steps_short=20):
@@ -395,6 +451,7 @@ def parity_vs_oracle(prm, ini, mo_long, steps_long, steps_short=20):
         g = {k: v[0] for k, v in L.macros(("p", "phi")).items()}
         r["dP_rel"] = abs(jump(g) / jump(mo_long) - 1.0)
         r["phi_sum_rel"] = abs(float(g["phi"].sum()) / float(mo_long["phi"].sum()) - 1.0)
+        L.close()
         out[prec] = r
     return out
 
@@ -479,7 +536,8 @@ def main():
         return 2
     log("bench: phase workload batch=%d steps=%d warmup=%d prec=%s fusion=%d" %
         (args.batch, args.steps, args.warmup, args.prec, args.fusion))
-    r = run_gpu(args.batch, args.steps, args.warmup, args.prec, fusion=args.fusion)
+    r = run_gpu(args.batch, args.steps, args.warmup, args.prec, fusion=args.fusion,
+                windows=0 if args.no_extras else 5)
     mlups = r["nodes"] * args.steps / r["wall"] / 1e6
     bpl = BYTES_PER_LU[args.prec]
     spl = 2 if args.fusion == 2 else 1  # steps per launch
@@ -487,8 +545,15 @@ def main():
              "k_phase<%s>" % {"fp32": "float,float,false", "fp64": "double,double,false",
                               "fp32_arith64": "float,double,false"}[args.prec])
     launch_ms = r["kernel_ms"] * spl
-    # algorithmic bytes of one launch (bpl x nodes x steps it performs) / its duration
-    achieved = bpl * r["nodes"] * spl / (launch_ms * 1e-3) / 1e9
+    # Bytes one launch must move: the stored state (21 FP32 planes: h, the low
+    # part of h_0, z and (phi u)) read once and written once per node, whatever
+    # the number of steps the launch performs -- bpl x nodes.  The two-step
+    # kernel keeps the intermediate state on chip, so per lattice update it
+    # needs bpl / 2; the step-equivalent rate (bpl per update) is reported
+    # beside it and is not a fraction of any peak.
+    launch_bytes = bpl * r["nodes"]
+    achieved = launch_bytes / (launch_ms * 1e-3) / 1e9
+    step_equivalent = bpl * r["nodes"] * spl / (launch_ms * 1e-3) / 1e9
     traffic = None
     if os.path.exists(args.traffic):
         with open(args.traffic) as f:
@@ -503,8 +568,10 @@ def main():
         s64 = max(20, args.steps // 4) // 2 * 2
         r64 = run_gpu(max(1, args.batch // 4), s64, 6, "fp64", fusion=args.fusion)
         extras["fp64_mlups"] = r64["nodes"] * s64 / r64["wall"] / 1e6
-        extras["fp64_hbm_frac"] = (BYTES_PER_LU["fp64"] * r64["nodes"] / (r64["kernel_ms"] * 1e-3)
-                                   / 1e9 / HBM_PEAK_GBS)
+        # the state (20 FP64 planes) once in and once out per launch of spl steps
+        l64 = r64["kernel_ms"] * spl * 1e-3
+        extras["fp64_hbm_frac"] = BYTES_PER_LU["fp64"] * r64["nodes"] / l64 / 1e9 / HBM_PEAK_GBS
+        extras["fp64_step_equivalent_GBps"] = BYTES_PER_LU["fp64"] * r64["nodes"] * spl / l64 / 1e9
         log("bench: paper-sized leg (4 replicas)")
         r4 = run_gpu(4, 1000, 50, args.prec)
         extras["paper_config_batch4_mlups"] = r4["nodes"] * 1000 / r4["wall"] / 1e6
@@ -545,9 +612,12 @@ def main():
                    "storage": "fp64-deviation" if args.prec == "fp64" else "fp32-deviation"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "bytes_per_lu": bpl, "kernel": kname, "steps_per_launch": spl,
+                     "bytes_per_node_per_launch": bpl, "nodes_per_launch": r["nodes"],
+                     "launch_bytes": launch_bytes, "kernel": kname, "steps_per_launch": spl,
                      "launch_ms": launch_ms,
                      "lu_per_launch": r["nodes"] * spl,
+                     "bytes_per_lu_single_step": bpl,
+                     "step_equivalent_GBps": step_equivalent,
                      "hbm_measured_GBps": (traffic / (launch_ms * 1e-3) / 1e9
                                            if traffic is not None else None),
                      "hbm_measured_frac": (traffic / (launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS
@@ -555,6 +625,7 @@ def main():
         "cpu_baseline": cpu,
         "parity_vs_oracle": parity,
         "phi_sum_drift": r["phi_sum_drift"],
+        "sustained": r.get("sustained"),
         "adjoint_over_forward": None,
     }
     line.update(extras)

@@ -13,6 +13,30 @@ import oracle as O
 
 FP32_TOL = 1e-5
 FP64_TOL = 1e-10
+EPS32 = 2.0 ** -23  # spacing of FP32 numbers at 1
+# FP32 rounding units of the stored pressure populations allowed in the
+# velocity of the lightest phase (see u_fp32_tol)
+U_RES_UNITS = 4.0
+
+
+def u_fp32_resolution(prm, p_orc):
+    """Velocity that one FP32 rounding unit of the stored pressure populations
+    stands for in the lightest phase.  The z_i carry p / c_s^2 (kg/m^3) while
+    the momentum they hold is rho u, and u = c sum(e_i z_i) / rho (Eq. u_Liang),
+    so FP32 storage resolves u only to EPS32 c max(|p|, sigma / W) / c_s^2 /
+    rho_g -- in the gas of the bubble case (rho_g = 0.0231 kg/m^3) about
+    1e4 times coarser than the 1e-5 target relative to the spurious currents."""
+    c = prm["dx"] / prm["dt"]
+    p_scale = max(float(np.max(np.abs(p_orc))), prm.get("sigma", 0.0) / prm["W"])
+    return EPS32 * c * p_scale / (c * c / 3.0) / min(prm["rho_g"], prm["rho_l"])
+
+
+def u_fp32_tol(prm, o):
+    """Absolute FP32 velocity bound: the 1e-5 accuracy target relative to
+    max |u|, or U_RES_UNITS rounding units of the stored pressure
+    populations in the lightest phase, whichever is larger."""
+    umax = max(float(np.max(np.abs(o["ux"]))), float(np.max(np.abs(o["uy"]))))
+    return max(FP32_TOL * umax, U_RES_UNITS * u_fp32_resolution(prm, o["p"]))
 
 
 def rel_err(gpu, orc, ref=0.0, scale=None):

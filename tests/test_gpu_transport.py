@@ -1,0 +1,89 @@
+"""GPU (through the C ABI) against the FP64 oracle on the interface-transport
+cases of test_oracle_transport: a slab and a disc carried by a uniform flow,
+the slab with the bubble case's properties, and a slab accelerated from rest
+by a body force.  Node by node after the whole run, FP64 and FP32 storage,
+single-step and two-step kernels."""
+import numpy as np
+import pytest
+
+import oracle as O
+
+from gpu_cases import print_case, rel_err, u_fp32_resolution, u_fp32_tol
+from test_oracle_transport import BUBBLE, C, EQUAL, LX, W, _prm, _slab, _wrap
+
+pytestmark = pytest.mark.gpu
+
+
+def _pair(prm, phi0, ux0, steps, prec, fusion):
+    from paper_2302_04120_amd import lbm
+    ny, nx = phi0.shape
+    L = lbm.Lattice("phase", nx, ny, prec=prec)
+    L.set_step_fusion(fusion)
+    L.set_params(prm)
+    z = np.zeros_like(phi0)
+    L.init(z, ux0, z, None, phi0)
+    L.step(steps)
+    g = {k: v[0] for k, v in L.macros(("phi", "p", "ux", "uy")).items()}
+    L.close()
+    o = O.Phase(nx, ny, prm)
+    o.init(phi0, z, ux0, z)
+    o.step(steps)
+    return g, o.macros()
+
+
+def _cases():
+    out = []
+    # slab in uniform flow, a quarter box (64 x 4 and the two-step kernel's 64 x 64)
+    for ny in (4, 64):
+        prm = _prm(64, EQUAL)
+        x = (np.arange(64) + 0.5) * prm["dx"]
+        phi0 = np.broadcast_to(_slab(x), (ny, 64)).copy()
+        U = 0.05 * C
+        out.append(("slab_%d" % ny, prm, phi0, np.full_like(phi0, U), 320))
+    # disc in uniform flow
+    prm = _prm(64, EQUAL)
+    x = (np.arange(64) + 0.5) * prm["dx"]
+    X, Y = np.meshgrid(x, x)
+    phi0 = 0.5 - 0.5 * np.tanh(2 * (np.hypot(_wrap(X - LX / 2), Y - LX / 2) - 0.25 * LX) / W)
+    out.append(("disc", prm, phi0, np.full_like(phi0, 0.05 * C), 320))
+    # slab with the bubble case's properties
+    prm = _prm(128, BUBBLE)
+    x = (np.arange(128) + 0.5) * prm["dx"]
+    phi0 = np.broadcast_to(_slab(x), (64, 128)).copy()
+    out.append(("slab_bubble_props", prm, phi0, np.full_like(phi0, 0.03 * C), 400))
+    # slab accelerated from rest: 10 nodes in 200 steps
+    prm = _prm(64, EQUAL, tau_phi=0.75)
+    x = (np.arange(64) + 0.5) * prm["dx"]
+    phi0 = np.broadcast_to(_slab(x), (64, 64)).copy()
+    a = 2 * 10 * prm["dx"] / (200 * prm["dt"]) ** 2
+    prm["Fx"] = prm["rho_l"] * a
+    out.append(("accelerated", prm, phi0, np.zeros_like(phi0), 200))
+    return out
+
+
+CASES = _cases()
+
+
+@pytest.mark.parametrize("prec,fusion", [("fp64", 1), ("fp32", 1), ("fp32", 2)])
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_transport_cases_against_oracle(case, prec, fusion):
+    name, prm, phi0, ux0, steps = case
+    print_case(test="transport", case=name, prec=prec, fusion=fusion, steps=steps)
+    g, o = _pair(prm, phi0, ux0, steps, prec, fusion)
+    umax = max(float(np.abs(o["ux"]).max()), float(np.abs(o["uy"]).max()))
+    scale_p = max(float(np.abs(o["p"]).max()), prm["sigma"] / prm["W"], 1e-300)
+    e = {"phi": rel_err(g["phi"], o["phi"], scale=1.0),
+         "p": rel_err(g["p"], o["p"], scale=scale_p),
+         "ux": rel_err(g["ux"], o["ux"], scale=umax),
+         "uy": rel_err(g["uy"], o["uy"], scale=umax)}
+    du = max(float(np.abs(g["ux"] - o["ux"]).max()), float(np.abs(g["uy"] - o["uy"]).max()))
+    print("errors", e, "max |du| %.3e m/s = %.3f FP32 resolution units" %
+          (du, du / u_fp32_resolution(prm, o["p"])), flush=True)
+    tol = 1e-10 if prec == "fp64" else 1e-5
+    assert e["phi"] < tol, e["phi"]
+    if prec == "fp64":
+        assert max(e["ux"], e["uy"]) < tol
+    else:
+        assert du < u_fp32_tol(prm, o)
+    if prm["sigma"] > 0:  # with sigma = 0 and equal densities p stays 0 to rounding
+        assert e["p"] < tol, e["p"]
