@@ -447,6 +447,16 @@ def parity_vs_oracle(prm, ini, mo_long, steps_long, steps_short=20):
         L.step(steps_short)
         g = L.macros(tuple(scales))
         r = {"pointwise": {k: float(np.abs(g[k][0] - mo[k]).max() / sc) for k, sc in scales.items()}}
+        # the velocity against the storage's resolution of the gas momentum:
+        # one rounding unit of the stored pressure populations (p / c_s^2)
+        # stands for eps c max(|p|, sigma / W) / c_s^2 / rho_g of velocity
+        c = prm["dx"] / prm["dt"]
+        eps = 2.0 ** -23 if prec == "fp32" else 2.0 ** -52
+        u_res = eps * c * scale_p / (c * c / 3.0) / prm["rho_g"]
+        du = max(float(np.abs(g[k][0] - mo[k]).max()) for k in ("ux", "uy"))
+        r["u_abs_err_mps"] = du
+        r["u_resolution_mps"] = u_res
+        r["u_err_in_resolution_units"] = du / u_res
         L.step(steps_long - steps_short)
         g = {k: v[0] for k, v in L.macros(("p", "phi")).items()}
         r["dP_rel"] = abs(jump(g) / jump(mo_long) - 1.0)

@@ -291,15 +291,20 @@ __device__ __forceinline__ PhaseLocal<C> phase_local(const PhaseK& k, const C (&
                                                      const C (&z)[9]) {
     PhaseLocal<C> L;
     // ---- stencils, Eq. gradient and Eq. laplacian in lattice form:
-    //      grad phi = 3 G / dx, lap phi = 6 L / dx^2
+    //      grad phi = 3 G / dx, lap phi = 6 L / dx^2 with G = sum w_i e_i phi_i and
+    //      L = sum w_i (phi_i - phi), summed by weight class (1/9 on the axes,
+    //      1/36 on the diagonals).  Both are built from differences of
+    //      neighbouring values, which are exact in floating point; a sum of the
+    //      neighbours minus (5/9) phi would cancel terms of size phi down to the
+    //      Laplacian and lose most of its digits in FP32.
     const C phi = pn[0];
-    C Gx = C(0), Gy = C(0), Lp = C(0);
-#pragma unroll
-    for (int i = 1; i < 9; ++i) {
-        Gx += wgt<C>(i) * C(EX[i]) * pn[i];
-        Gy += wgt<C>(i) * C(EY[i]) * pn[i];
-        Lp += wgt<C>(i) * (pn[i] - phi);
-    }
+    const C dpp = pn[5] - pn[7];  // (+1,+1) - (-1,-1)
+    const C dpm = pn[8] - pn[6];  // (+1,-1) - (-1,+1)
+    const C Gx = C(1.0 / 9.0) * (pn[1] - pn[3]) + C(1.0 / 36.0) * (dpp + dpm);
+    const C Gy = C(1.0 / 9.0) * (pn[2] - pn[4]) + C(1.0 / 36.0) * (dpp - dpm);
+    const C sax = ((pn[1] - phi) + (pn[3] - phi)) + ((pn[2] - phi) + (pn[4] - phi));
+    const C sdg = ((pn[5] - phi) + (pn[7] - phi)) + ((pn[6] - phi) + (pn[8] - phi));
+    const C Lp = C(1.0 / 9.0) * sax + C(1.0 / 36.0) * sdg;
     const C drl = C(k.rho_l - k.rho_g);
     const C rho = C(k.rho_g) + phi * drl;  // linear in phi (Sec. 2.3)
     const C ir = rcp(rho);
@@ -362,16 +367,23 @@ __device__ __forceinline__ void phase_collide(const PhaseK& k, const PhaseLocal<
     const C wphi = C(k.w_phi);
     const C sfac = C(1) - C(0.5) * wphi;
     const C sharp = C(4) * phi * (C(1) - phi) * C(k.dxW);
+    // h_i* = h_i - w (h_i - h_i^eq) + S_i with h_i^eq = phi w_i (1 + 3 e_i.u) and
+    // S_i = (1 - w/2) w_i e_i.(3 d(phi u) + sharp n) collects into
+    //   h_i* = h_i + (t_i - w h_i),  t_i = w_i (a + e_i.B),
+    //   a = w phi,  B = 3 w phi u + (1 - w/2)(3 d(phi u) + sharp n);
+    // t_i - w h_i is the step's small change, taken in one fused multiply-add
+    // (one rounding of the change, as the non-equilibrium form has).
+    const C a = wphi * phi;
+    const C a3 = C(3) * a;
+    const C Bx = a3 * ux + sfac * (C(3) * dpx + sharp * L.nxv);
+    const C By = a3 * uy + sfac * (C(3) * dpy + sharp * L.nyv);
+    const C qa = C(1.0 / 9.0) * a, qx = C(1.0 / 9.0) * Bx, qy = C(1.0 / 9.0) * By;
+    const C da = C(1.0 / 36.0) * a, ds = C(1.0 / 36.0) * (Bx + By), dd = C(1.0 / 36.0) * (Bx - By);
+    const C t[9] = {C(4.0 / 9.0) * a, qa + qx, qa + qy, qa - qx, qa - qy,  // 0, (+1,0) (0,+1) (-1,0) (0,-1)
+                    da + ds, da - dd, da - ds, da + dd};                   // (+1,+1) (-1,+1) (-1,-1) (+1,-1)
     hs[0] = C(0);
 #pragma unroll
-    for (int i = 1; i < 9; ++i) {
-        const C eu = C(EX[i]) * ux + C(EY[i]) * uy;
-        const C heq = phi * wgt<C>(i) * (C(1) + C(3) * eu);
-        const C sh = sfac * wgt<C>(i) *
-                     (C(3) * (C(EX[i]) * dpx + C(EY[i]) * dpy) +
-                      sharp * (C(EX[i]) * L.nxv + C(EY[i]) * L.nyv));
-        hs[i] = h[i] - wphi * (h[i] - heq) + sh;
-    }
+    for (int i = 1; i < 9; ++i) hs[i] = h[i] + (t[i] - wphi * h[i]);
     h0lo = S(0);
     if constexpr (RMASS) {
         // rest population takes the node's exact balance: h0* = phi - sum_{i>0} h_i*
@@ -386,8 +398,7 @@ __device__ __forceinline__ void phase_collide(const PhaseK& k, const PhaseLocal<
         h0hi = float(acc);
         h0lo = float(acc - double(h0hi));
     } else {
-        const C heq0 = phi * wgt<C>(0);
-        h0hi = S(h[0] - wphi * (h[0] - heq0));
+        h0hi = S(h[0] + (t[0] - wphi * h[0]));  // h_0^eq = (4/9) phi, no source
     }
     // ---- pressure collision in moment space.  The moments of z_i^eq
     //      (Eq. zeq_liang with Eq. s_i_Liang) and of dt F^z_i (Eq.
@@ -400,21 +411,41 @@ __device__ __forceinline__ void phase_collide(const PhaseK& k, const PhaseLocal<
     //      with p~ = p / c_s^2, D = drho (u . G) and every velocity in units
     //      of c.  BGK is the same update with every rate equal to dt/tau.
     const C rho = L.rho, drl = L.drl, wn = L.wn, Gx = L.Gx, Gy = L.Gy;
+    const C ruu = rho * L.uu, D = drl * L.ug;
+    const C meq[9] = {C(0), C(2) * L.ph + C(3) * ruu, C(-3) * (L.ph + ruu), rho * ux, -rho * ux,
+                      rho * uy, -rho * uy, rho * (ux * ux - uy * uy), rho * ux * uy};
+    const C mf[9] = {C(3) * D, C(0), C(-3) * D, L.fsx, -L.fsx, L.fsy, -L.fsy,
+                     C(2) * drl * (Gx * ux - Gy * uy), drl * (Gx * uy + Gy * ux)};
     C m[9];
-    moments9(z, m);
-    {
-        const C ruu = rho * L.uu, D = drl * L.ug;
-        const C meq[9] = {C(0), C(2) * L.ph + C(3) * ruu, C(-3) * (L.ph + ruu), rho * ux, -rho * ux,
-                          rho * uy, -rho * uy, rho * (ux * ux - uy * uy), rho * ux * uy};
-        const C mf[9] = {C(3) * D, C(0), C(-3) * D, L.fsx, -L.fsx, L.fsy, -L.fsy,
-                         C(2) * drl * (Gx * ux - Gy * uy), drl * (Gx * uy + Gy * ux)};
+    if (k.z_mrt) {
+        // Sec. 3 rates: rho, e, eps, j_x, j_y relax at 1/dt, which leaves
+        // m* = m^eq + m^F / 2 whatever the incoming moment; q_x and q_y relax at
+        // w_q (q_y at 1/dt in the printed variant), the stresses at w_nu.  Only
+        // the moments of those four rows are taken from z.
+        const C x13 = z[1] - z[3], y24 = z[2] - z[4];
+        const C x58 = (z[5] - z[7]) + (z[8] - z[6]);
+        const C y58 = (z[5] - z[7]) + (z[6] - z[8]);
         const C wq = C(3) * (C(2) - wn) * rcp(C(3) - wn);
-        const C Lm[9] = {C(1), C(1), C(1), C(1), wq, C(1), k.qy_printed ? C(1) : wq, wn, wn};
+        const C wqy = k.qy_printed ? C(1) : wq;
+        const C mq[4] = {C(-2) * x13 + x58, C(-2) * y24 + y58, (z[1] + z[3]) - (z[2] + z[4]),
+                         (z[5] + z[7]) - (z[6] + z[8])};
+        const C Lq[4] = {wq, wqy, wn, wn};
+        const int row[4] = {4, 6, 7, 8};
 #pragma unroll
-        for (int q = 0; q < 9; ++q) {
-            const C Lq = k.z_mrt ? Lm[q] : wn;
-            m[q] += -Lq * (m[q] - meq[q]) + (C(1) - C(0.5) * Lq) * mf[q];
+        for (int j = 0; j < 4; ++j) {
+            const int q = row[j];
+            m[q] = mq[j] - Lq[j] * (mq[j] - meq[q]) + (C(1) - C(0.5) * Lq[j]) * mf[q];
         }
+        m[0] = meq[0] + C(0.5) * mf[0];
+        m[1] = meq[1];  // m^F has no e component
+        m[2] = meq[2] + C(0.5) * mf[2];
+        m[3] = meq[3] + C(0.5) * mf[3];
+        m[5] = meq[5] + C(0.5) * mf[5];
+    } else {
+        // BGK: every row at dt / tau
+        moments9(z, m);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) m[q] += -wn * (m[q] - meq[q]) + (C(1) - C(0.5) * wn) * mf[q];
     }
     inverse9(m, zst);
 }

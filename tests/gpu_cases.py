@@ -13,30 +13,59 @@ import oracle as O
 
 FP32_TOL = 1e-5
 FP64_TOL = 1e-10
-EPS32 = 2.0 ** -23  # spacing of FP32 numbers at 1
-# FP32 rounding units of the stored pressure populations allowed in the
-# velocity of the lightest phase (see u_fp32_tol)
+EPS = {"fp32": 2.0 ** -23, "fp64": 2.0 ** -52}  # spacing of the numbers at 1
+EPS32 = EPS["fp32"]
+# FP32 and FP64 rounding units of the stored pressure populations allowed in
+# the velocity of the lightest phase (see u_tol)
 U_RES_UNITS = 4.0
+# relative velocity floor of u_tol: the accuracy target in FP32, rounding in
+# FP64 (the pressure populations of the two-phase model carry ~1e3 times the
+# gas momentum, so FP64 velocities agree to ~1e-13 of max |u|)
+U_REL = {"fp32": 1e-5, "fp64": 1e-12}
+
+
+def u_resolution(prm, p_orc, prec="fp32"):
+    """Velocity that one rounding unit of the stored pressure populations
+    stands for in the lightest phase.  The z_i carry p / c_s^2 (kg/m^3) while
+    the momentum they hold is rho u, and u = c sum(e_i z_i) / rho (Eq. u_Liang),
+    so storage in precision prec resolves u only to EPS c max(|p|, sigma / W) /
+    c_s^2 / rho_g -- in FP32, in the gas of the bubble case (rho_g = 0.0231
+    kg/m^3), about 1e-3 of the spurious currents."""
+    c = prm["dx"] / prm["dt"]
+    p_scale = max(float(np.max(np.abs(p_orc))), prm.get("sigma", 0.0) / prm["W"])
+    return EPS[prec] * c * p_scale / (c * c / 3.0) / min(prm["rho_g"], prm["rho_l"])
 
 
 def u_fp32_resolution(prm, p_orc):
-    """Velocity that one FP32 rounding unit of the stored pressure populations
-    stands for in the lightest phase.  The z_i carry p / c_s^2 (kg/m^3) while
-    the momentum they hold is rho u, and u = c sum(e_i z_i) / rho (Eq. u_Liang),
-    so FP32 storage resolves u only to EPS32 c max(|p|, sigma / W) / c_s^2 /
-    rho_g -- in the gas of the bubble case (rho_g = 0.0231 kg/m^3) about
-    1e4 times coarser than the 1e-5 target relative to the spurious currents."""
-    c = prm["dx"] / prm["dt"]
-    p_scale = max(float(np.max(np.abs(p_orc))), prm.get("sigma", 0.0) / prm["W"])
-    return EPS32 * c * p_scale / (c * c / 3.0) / min(prm["rho_g"], prm["rho_l"])
+    return u_resolution(prm, p_orc, "fp32")
+
+
+def u_tol(prm, o, prec="fp32"):
+    """Absolute velocity bound of the two-phase parity tests: U_REL[prec] of
+    max |u|, or U_RES_UNITS rounding units of the stored pressure populations
+    in the lightest phase, whichever is larger.  o: the oracle's macros."""
+    keys = [k for k in ("ux", "uy", "uz") if k in o]
+    umax = max(float(np.max(np.abs(o[k]))) for k in keys)
+    return max(U_REL[prec] * umax, U_RES_UNITS * u_resolution(prm, o["p"], prec))
 
 
 def u_fp32_tol(prm, o):
-    """Absolute FP32 velocity bound: the 1e-5 accuracy target relative to
-    max |u|, or U_RES_UNITS rounding units of the stored pressure
-    populations in the lightest phase, whichever is larger."""
-    umax = max(float(np.max(np.abs(o["ux"]))), float(np.max(np.abs(o["uy"]))))
-    return max(FP32_TOL * umax, U_RES_UNITS * u_fp32_resolution(prm, o["p"]))
+    return u_tol(prm, o, "fp32")
+
+
+def u_abs_err(g, o):
+    """max |u_gpu - u_oracle| over the velocity components present in both."""
+    keys = [k for k in ("ux", "uy", "uz") if k in o and k in g]
+    return max(float(np.max(np.abs(np.asarray(g[k]) - o[k]))) for k in keys)
+
+
+def accumulated_tol(steps, prec="fp32"):
+    """A priori bound for a field of unit scale after `steps` steps whose
+    every step adds at most one rounding unit of the storage precision:
+    steps * EPS (the run's own FP32 error budget, used where a uniform flow
+    of 5-10 % of c makes each step's rounding of the growing momentum and of
+    the moving interface add up)."""
+    return steps * EPS[prec]
 
 
 def rel_err(gpu, orc, ref=0.0, scale=None):

@@ -14,7 +14,7 @@ import pytest
 import oracle as O
 from paper_2302_04120_amd import workloads as WL
 
-from gpu_cases import print_case, rel_err
+from gpu_cases import print_case, rel_err, u_abs_err, u_tol
 
 pytestmark = pytest.mark.gpu
 
@@ -58,8 +58,9 @@ def test_arith64_against_oracle(nx, ny, walls, fusion):
     scale_p = max(float(np.abs(mo["p"]).max()), prm["sigma"] / prm["W"])
     assert rel_err(m["phi"], mo["phi"], scale=1.0) < 1e-5
     assert rel_err(m["p"], mo["p"], scale=scale_p) < 1e-5
-    assert rel_err(m["ux"], mo["ux"]) < 1e-4
-    assert rel_err(m["uy"], mo["uy"], scale=float(np.abs(mo["ux"]).max())) < 1e-4
+    # FP32 storage: the velocity to the resolution of the stored pressure
+    # populations (FP64 arithmetic does not refine what the storage holds)
+    assert u_abs_err(m, mo) < u_tol(prm, mo)
 
 
 @pytest.mark.parametrize("nx,ny,batch,walls,calls", [(4, 512, 1, True, (101,)),

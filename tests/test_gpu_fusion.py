@@ -10,7 +10,7 @@ import pytest
 import oracle as O
 from paper_2302_04120_amd import workloads as WL
 
-from gpu_cases import phase_pair, print_case, rel_err
+from gpu_cases import phase_pair, print_case, rel_err, u_abs_err, u_tol
 
 pytestmark = pytest.mark.gpu
 
@@ -93,7 +93,7 @@ def test_two_step_kernel_against_oracle():
     scale_p = max(float(np.abs(o["p"]).max()), prm["sigma"] / prm["W"])
     assert rel_err(g["phi"], o["phi"], scale=1.0) < 1e-5
     assert rel_err(g["p"], o["p"], scale=scale_p) < 1e-5
-    assert rel_err(g["ux"], o["ux"]) < 1e-4
+    assert u_abs_err(g, o) < u_tol(prm, o)
 
 
 def test_fusion_validation():
@@ -136,8 +136,9 @@ def test_bench_size_two_step_sampled_against_oracle():
         scale_p = max(float(np.abs(mo["p"]).max()), prm["sigma"] / prm["W"])
         e = (rel_err(m["phi"][b], mo["phi"], scale=1.0), rel_err(m["p"][b], mo["p"], scale=scale_p),
              rel_err(m["ux"][b], mo["ux"]))
-        print("replica %d: phi %.2e p %.2e ux %.2e" % (b, *e), flush=True)
-        assert e[0] < 1e-5 and e[1] < 1e-5 and e[2] < 1e-4
+        du = u_abs_err({"ux": m["ux"][b]}, mo)
+        print("replica %d: phi %.2e p %.2e ux %.2e (|du| %.2e m/s)" % (b, *e, du), flush=True)
+        assert e[0] < 1e-5 and e[1] < 1e-5 and du < u_tol(prm, mo)
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
@@ -176,7 +177,11 @@ def test_narrow_replica_tiles_against_oracle(nx, ny, walls, prec, tol):
         e = (rel_err(m["phi"][b], mo["phi"], scale=1.0), rel_err(m["p"][b], mo["p"], scale=scale_p),
              rel_err(m["ux"][b], mo["ux"]))
         print("replica %d: phi %.2e p %.2e ux %.2e" % (b, *e), flush=True)
-        assert e[0] < tol and e[1] < tol and e[2] < (tol if prec == "fp64" else 1e-4)
+        assert e[0] < tol and e[1] < tol
+        if prec == "fp64":
+            assert e[2] < tol
+        else:
+            assert u_abs_err({"ux": m["ux"][b]}, mo) < u_tol(prm, mo)
 
 
 @pytest.mark.timeout(300)

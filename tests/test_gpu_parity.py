@@ -11,7 +11,7 @@ import oracle as O
 from paper_2302_04120_amd import workloads as WL
 
 from gpu_cases import (FP32_TOL, FP64_TOL, channel_pair, density_scale, phase_pair, print_case,
-                       rel_err)
+                       rel_err, u_abs_err, u_tol)
 
 pytestmark = pytest.mark.gpu
 
@@ -24,9 +24,9 @@ pytestmark = pytest.mark.gpu
 # compared through their physical observables.
 PHASE_FP32_STEPS = 20
 PHASE_FP64_STEPS = 60
-# FP32 resolves the gas velocity only to ~eps32 * (p / c_s^2) / rho_g: the
+# FP32 resolves the gas velocity only to ~eps32 c (p / c_s^2) / rho_g: the
 # pressure populations carry the pressure scale while the gas momentum is tiny
-U_GAS_FP32_TOL = 1e-4
+# (gpu_cases.u_tol)
 
 
 def _chan_fields_check(g, o, prm, tol, thermal=True):
@@ -118,22 +118,30 @@ def test_phase_bubble_ragged(prec, tol):
     g, o, _, _ = phase_pair(prm, ini, nx, ny, steps, prec)
     errs = {k: rel_err(g[k], o[k]) for k in ("phi", "p", "ux", "uy")}
     errs["rho"] = rel_err(g["rho"], o["rho"], prm["rho_g"])
-    print("errors", errs, flush=True)
+    print("errors", errs, "|du| %.3e m/s, bound %.3e" % (u_abs_err(g, o), u_tol(prm, o)), flush=True)
     for k, v in errs.items():
-        lim = U_GAS_FP32_TOL if (prec == "fp32" and k in ("ux", "uy")) else tol
-        assert v < lim, (k, v)
+        if prec == "fp64" or k not in ("ux", "uy"):
+            assert v < tol, (k, v)
+    if prec == "fp32":
+        assert u_abs_err(g, o) < u_tol(prm, o)
 
 
 @pytest.mark.slow
 def test_phase_bubble_long_run_observables_fp32():
     """3000 steps of the C3 bubble at 64 x 64 in FP32: the Laplace pressure
-    jump and the density-profile error agree with the FP64 oracle's, and the
-    order-parameter sum is conserved to FP64 reduction rounding."""
+    jump and the density-profile error agree with the FP64 oracle's, phi
+    agrees node by node, and the order-parameter sum is conserved to FP64
+    reduction rounding.  Both sides take the raised normal guard (1e-3 / dx):
+    with the default one, rounding flips the interface normal where grad phi
+    vanishes and the two runs drift apart chaotically (phi differs by ~5e-3
+    after 3000 steps, and the density-profile E2 by ~1 %, whichever of two
+    equally correct FP32 arithmetic orders is used), which says nothing about
+    the accuracy of either."""
     from paper_2302_04120_amd import lbm
     n, steps = 64, 3000
     print_case(test="phase_long", steps=steps)
     prm, ini, cen = WL.bubble(n=n, radii=(16,), batch=1, seed=0)
-    prm["normal_eps"] = 1e-6 / prm["dx"]
+    prm["normal_eps"] = 1e-3 / prm["dx"]
     L = lbm.Lattice("phase", n, n, prec="fp32")
     L.set_params(prm)
     L.init(ini["p"], ini["ux"], ini["uy"], None, ini["phi"])
@@ -156,8 +164,10 @@ def test_phase_bubble_long_run_observables_fp32():
     print("dP gpu %.6f oracle %.6f sigma/R %.6f; E2 gpu %.4f oracle %.4f; mass drift %.3e" %
           (dp_g, dp_o, prm["sigma"] / R, O.e2(rho_a, g["rho"]), O.e2(rho_a, m["rho"]),
            abs(m1 - m0) / m0), flush=True)
-    assert dp_g == pytest.approx(dp_o, rel=1e-3)
-    assert O.e2(rho_a, g["rho"]) == pytest.approx(O.e2(rho_a, m["rho"]), rel=5e-3)
+    print("max |phi_gpu - phi_oracle| %.3e" % np.abs(g["phi"] - m["phi"]).max(), flush=True)
+    assert dp_g == pytest.approx(dp_o, rel=1e-4)
+    assert O.e2(rho_a, g["rho"]) == pytest.approx(O.e2(rho_a, m["rho"]), rel=1e-4)
+    assert np.abs(g["phi"] - m["phi"]).max() < 2e-6  # measured 1.8e-7
     assert abs(m1 - m0) < 1e-13 * m0
 
 
@@ -302,4 +312,4 @@ def test_full_size_bubble_replica_sampled():
     print("errors", errs, flush=True)
     for k in ("phi", "p"):
         assert errs[k] < FP32_TOL, k
-    assert max(errs["ux"], errs["uy"]) < U_GAS_FP32_TOL
+    assert u_abs_err(g, o) < u_tol(prm, o)

@@ -2,13 +2,22 @@
 cases of test_oracle_transport: a slab and a disc carried by a uniform flow,
 the slab with the bubble case's properties, and a slab accelerated from rest
 by a body force.  Node by node after the whole run, FP64 and FP32 storage,
-single-step and two-step kernels."""
+single-step and two-step kernels.
+
+Both sides take the raised interface-normal guard (1e-3 / dx, the setting
+under which test_gpu_horizon shows FP64 agreement to rounding): the default
+guard lets rounding flip the normal where grad phi vanishes, which the
+oracle and the GPU then resolve differently.  FP32 bound on phi and p: the
+1e-5 target, or one FP32 rounding unit per step over the run
+(gpu_cases.accumulated_tol) -- with a uniform flow of 5-10 % of c each step
+rounds the growing momentum and moves the interface by a rounded amount.
+Velocity: gpu_cases.u_tol."""
 import numpy as np
 import pytest
 
 import oracle as O
 
-from gpu_cases import print_case, rel_err, u_fp32_resolution, u_fp32_tol
+from gpu_cases import accumulated_tol, print_case, rel_err, u_abs_err, u_resolution, u_tol
 from test_oracle_transport import BUBBLE, C, EQUAL, LX, W, _prm, _slab, _wrap
 
 pytestmark = pytest.mark.gpu
@@ -16,6 +25,7 @@ pytestmark = pytest.mark.gpu
 
 def _pair(prm, phi0, ux0, steps, prec, fusion):
     from paper_2302_04120_amd import lbm
+    prm = dict(prm, normal_eps=1e-3 / prm["dx"])
     ny, nx = phi0.shape
     L = lbm.Lattice("phase", nx, ny, prec=prec)
     L.set_step_fusion(fusion)
@@ -76,14 +86,11 @@ def test_transport_cases_against_oracle(case, prec, fusion):
          "p": rel_err(g["p"], o["p"], scale=scale_p),
          "ux": rel_err(g["ux"], o["ux"], scale=umax),
          "uy": rel_err(g["uy"], o["uy"], scale=umax)}
-    du = max(float(np.abs(g["ux"] - o["ux"]).max()), float(np.abs(g["uy"] - o["uy"]).max()))
-    print("errors", e, "max |du| %.3e m/s = %.3f FP32 resolution units" %
-          (du, du / u_fp32_resolution(prm, o["p"])), flush=True)
-    tol = 1e-10 if prec == "fp64" else 1e-5
+    du = u_abs_err(g, o)
+    print("errors", e, "max |du| %.3e m/s = %.3g resolution units" %
+          (du, du / max(u_resolution(prm, o["p"], prec), 1e-300)), flush=True)
+    tol = 1e-10 if prec == "fp64" else max(1e-5, accumulated_tol(steps))
     assert e["phi"] < tol, e["phi"]
-    if prec == "fp64":
-        assert max(e["ux"], e["uy"]) < tol
-    else:
-        assert du < u_fp32_tol(prm, o)
+    assert du < u_tol(prm, o, prec)
     if prm["sigma"] > 0:  # with sigma = 0 and equal densities p stays 0 to rounding
         assert e["p"] < tol, e["p"]
