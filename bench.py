@@ -122,6 +122,35 @@ def run_gpu(batch, steps, warmup, prec, n=256, fusion=0, windows=0):
     return out
 
 
+def run_wide(cells, steps, warmup, prec, fusion=0):
+    """One periodic domain of cells x cells bubble cells (256^2 each, radii
+    cycling, jitter per cell): 32 x 32 gives the 8192^2 bubble array.  Its
+    rows are wider than 256 nodes, so the two-step kernel takes them in
+    x-tiles of 250 stored columns."""
+    import torch
+    from paper_2302_04120_amd import lbm, workloads as WL
+    prm, ini, _ = WL.bubble_array(cells, 256, seed=0)
+    n = cells * 256
+    L = lbm.Lattice("phase", n, n, prec=prec)
+    L.set_step_fusion(fusion)
+    L.set_params(prm)
+    L.init(ini["p"], ini["ux"], ini["uy"], None, ini["phi"])
+    del ini
+    L.step(warmup)
+    ms, wall = timed(L, steps)
+    if L.reduce(("nonfinite",))["nonfinite"].sum() != 0:
+        raise RuntimeError("non-finite populations after the timed steps")
+    L.close()
+    nodes = n * n
+    spl = 2 if fusion != 1 else 1
+    launch_ms = ms / steps * spl
+    return dict(mlups=nodes * steps / (ms * 1e-3) / 1e6, grid="%dx%d" % (n, n),
+                ms_per_step=ms / steps, launch_ms=launch_ms,
+                hbm_frac=BYTES_PER_LU[prec] * nodes / (launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                kernel="k_phase_tb2<%s,true>" % ("float" if prec == "fp32" else "double")
+                if spl == 2 else "k_phase")
+
+
 def run_channel(nx, ny, steps, warmup, prec):
     """The heated-channel step (D2Q9 MRT flow + D2Q5 thermal, velocity inlet,
     pressure outlet, flux walls) on a roofline-sized grid."""
@@ -495,7 +524,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the FP64 and batch-4 legs")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_phase_step.json"))
     ap.add_argument("--leg", choices=("channel", "adjoint", "d3q19", "phase3d", "layered", "c4single",
-                                      "c4steady"),
+                                      "c4steady", "wide"),
                     default=None,
                     help="only run one secondary leg and print its figures (for profiling)")
     ap.add_argument("--systems", default="sat_water_25C,air_water_25C",
@@ -517,6 +546,9 @@ def main():
         return 2
     if args.leg == "channel":
         print(json.dumps(run_channel(16384, 2048, args.steps, args.warmup, args.prec)), flush=True)
+        return 0
+    if args.leg == "wide":
+        print(json.dumps(run_wide(32, args.steps, args.warmup, args.prec, args.fusion)), flush=True)
         return 0
     if args.leg == "adjoint":
         print(json.dumps(adjoint_cost(prec=args.prec)), flush=True)
@@ -585,6 +617,8 @@ def main():
         log("bench: paper-sized leg (4 replicas)")
         r4 = run_gpu(4, 1000, 50, args.prec)
         extras["paper_config_batch4_mlups"] = r4["nodes"] * 1000 / r4["wall"] / 1e6
+        log("bench: single wide domain leg (8192^2 bubble array)")
+        extras["wide_domain_fp32"] = run_wide(32, 100, 10, "fp32")
         log("bench: C4 layered batch leg (4096 x 4 x 512)")
         extras["layered_batch_fp32"] = run_layered_batch(4096, 200, 20, "fp32")
         log("bench: C4 single replica, graph replay and many-steps kernel")

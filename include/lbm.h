@@ -239,9 +239,11 @@ LBM_API lbm_status lbm_set_graph_steps(lbm_ctx* ctx, int steps);
  *   mode 1: one launch per step (the tiled single-step kernel).
  *   mode 2: pairs of steps run as one launch of the two-step kernel, which
  *           keeps the intermediate state on chip and so moves half the bytes
- *           per step; needs nx a multiple of 64 and at most 256
- *           (LBM_E_UNSUPPORTED otherwise, and with LBM_FP32_DEV_ARITH64);
- *           ny < 4 and an odd last step use the single-step kernel.
+ *           per step: a whole row per workgroup when nx is a multiple of 64
+ *           up to 256, otherwise x-tiles of 256 lanes that store 250 columns
+ *           each and overlap their neighbours by 3 columns per side (any nx);
+ *           LBM_E_UNSUPPORTED with LBM_FP32_DEV_ARITH64; ny < 4 and an odd
+ *           last step use the single-step kernel.
  *   mode 3: every lbm_step call runs as one cooperative launch (per 16384
  *           steps) of the many-steps kernel: one resident workgroup per
  *           tile, which steps its tile and waits for its neighbouring tiles'
@@ -257,11 +259,13 @@ LBM_API lbm_status lbm_set_graph_steps(lbm_ctx* ctx, int steps);
  *           stream is being captured, steps use the single-step kernel.  The step
  *           counters live in the context's buffer and are reset by
  *           lbm_init_fields and lbm_load_state.
- *   mode 0 (default): mode 2 when its workgroups (one per segment of a
- *           replica: the whole replica when it has fewer than 256 rows, or
- *           at most 512 rows and the replicas alone fill the GPU's resident
- *           workgroup slots; else 128 rows) number at least 512, else
- *           mode 1 (always mode 1 with LBM_FP32_DEV_ARITH64).
+ *   mode 0 (default): mode 2 when its workgroups (one per x-tile and
+ *           segment of a replica: the whole replica when it has fewer than
+ *           256 rows, or at most 512 rows and the workgroups of whole
+ *           replicas alone fill the GPU's resident workgroup slots; else 128
+ *           rows) number at least 512 and, with x-tiles, at least 90 % of
+ *           the launched lanes hold stored columns; else mode 1 (always mode
+ *           1 with LBM_FP32_DEV_ARITH64).
  * The kernels evaluate the same per-node arithmetic in the same order, so
  * the modes agree to the last bit.  Not an operation of the paper: a
  * performance control.  Other lattices ignore it.  LBM_E_ARG on an unknown

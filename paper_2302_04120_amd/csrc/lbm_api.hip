@@ -214,13 +214,14 @@ hipError_t step_once(lbm_ctx* c) {
 }
 
 // Whether the next two steps go through the two-step kernel.  Automatic
-// mode takes it when its workgroups (one per row segment and replica; two
-// are resident per CU) fill the 256 CUs; smaller grids keep the single-step
-// kernel, whose tiles spread over more CUs.
+// mode takes it when its workgroups (one per row segment, x-tile and replica;
+// two are resident per CU) fill the 256 CUs and, for rows in x-tiles, at
+// least 90 % of the launched lanes hold stored columns; smaller or narrow
+// grids keep the single-step kernel, whose tiles spread over more CUs.
 bool use_tb2(const lbm_ctx* c) {
     if (c->desc.lattice != LBM_D2Q9_PHASE || c->fusion == 1 || c->tb2_seg < 1) return false;
     if (c->fusion == 2) return true;
-    return phase_tb2_workgroups(c->pk, c->tb2_seg) >= 512;
+    return phase_tb2_workgroups(c->pk, c->tb2_seg) >= 512 && phase_tb2_lane_use(c->pk) >= 0.9;
 }
 
 // The many-steps kernel needs the grid split into at most kPersistMaxTiles
@@ -468,9 +469,6 @@ lbm_status lbm_set_step_fusion(lbm_ctx* c, int mode) {
     if (mode == 3 && c->desc.lattice == LBM_D2Q9_PHASE && !phase_persist_fits_desc(c->desc))
         return set_err(c, LBM_E_UNSUPPORTED,
                        "many-steps kernel needs at most 16 tiles of 512 nodes over all replicas");
-    if (mode == 2 && c->desc.lattice == LBM_D2Q9_PHASE &&
-        (c->desc.nx % 64 != 0 || c->desc.nx > 256))
-        return set_err(c, LBM_E_UNSUPPORTED, "two-step kernel needs nx a multiple of 64, at most 256");
     if (mode == 2 && c->desc.lattice == LBM_D2Q9_PHASE && c->desc.prec == LBM_FP32_DEV_ARITH64)
         return set_err(c, LBM_E_UNSUPPORTED, "two-step kernel: not with FP64 arithmetic on FP32 storage");
     if (mode != c->fusion) {

@@ -172,6 +172,10 @@ hipError_t launch_phase_step(const PhaseK& k, const S* hc, S* hn, const S* zc, S
 // from buffer a to buffer b; needs phase_tb2_fits.  seg: rows per workgroup
 // (phase_tb2_seg, fixed when the parameters are set)
 bool phase_tb2_fits(const PhaseK& k);
+// whether rows go in x-tiles (nx not a multiple of 64 up to 256), and the
+// share of the launched lanes whose columns are stored
+bool phase_tb2_tiled(const PhaseK& k);
+double phase_tb2_lane_use(const PhaseK& k);
 template <typename S>
 int phase_tb2_seg(const PhaseK& k);
 long long phase_tb2_workgroups(const PhaseK& k, int seg);

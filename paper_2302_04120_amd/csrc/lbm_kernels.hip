@@ -693,8 +693,20 @@ __global__ __launch_bounds__(TX * TY) void k_phase_persist(PhaseK k, S* __restri
 // every segment is independent.  Walls: rows outside [0, ny) do not exist
 // and the bounce-back of the single step applies at both walls.  The
 // arithmetic per node is phase_local + phase_collide, as in k_phase.
+//
+// TILED: the same march for rows of any width, in x-tiles of 256 lanes that
+// overlap by 3 columns on each side (the segment overlap of y applied in
+// x).  Lane l of tile t holds column x0 - 3 + l (mod nx), x0 = 250 t; x
+// neighbours in LDS are lanes l -+ 1, so step n is exact on lanes 1..254
+// (phi_n of both neighbours), the step-(n + 1) state on lanes 2..253 (pushes
+// from both neighbours), and step n + 1 on lanes 3..252 (phi_{n+1} of both
+// neighbours): those 250 columns are stored, the edge lanes' values are
+// never used.  The stored columns of neighbouring tiles are disjoint, and
+// every destination slot is still written by exactly one source node.
 // ---------------------------------------------------------------------------
 constexpr int kTbMaxNx = 256;
+constexpr int kTbHalo = 3;                          // overlap columns per side (TILED)
+constexpr int kTbTileOut = kTbMaxNx - 2 * kTbHalo;  // stored columns per tile
 #ifndef LBM_TB_SEG
 #define LBM_TB_SEG 128
 #endif
@@ -703,7 +715,7 @@ constexpr int kTbSeg = LBM_TB_SEG;  // rows per segment
 // register state of one row of one column: h 0-8, low part of h_0, z 0-8, (phi u)
 constexpr int kH = 0, kLO = 9, kZ = 10, kPU = 19, kNS = 21;
 
-template <typename S>
+template <typename S, bool TILED>
 __global__ __launch_bounds__(kTbMaxNx) void k_phase_tb2(PhaseK k, const S* __restrict__ A,
                                                         S* __restrict__ B, int seg) {
     using C = S;
@@ -712,8 +724,11 @@ __global__ __launch_bounds__(kTbMaxNx) void k_phase_tb2(PhaseK k, const S* __res
     const long long P = k.P;
     const int npop = RMASS ? 19 : 18;
     const int nseg = (ny + seg - 1) / seg;
+    const int ntx = TILED ? (nx + kTbTileOut - 1) / kTbTileOut : 1;
     int w;
-    if (!xcd_tile(nseg * k.batch, w)) return;  // whole workgroup, before any barrier
+    if (!xcd_tile(ntx * nseg * k.batch, w)) return;  // whole workgroup, before any barrier
+    const int tx = w % ntx;  // x-tile (TILED), x fastest
+    w /= ntx;
     const int b = w / nseg;
     const int a = (w - b * nseg) * seg;
     const int e = min(a + seg, ny);
@@ -723,10 +738,21 @@ __global__ __launch_bounds__(kTbMaxNx) void k_phase_tb2(PhaseK k, const S* __res
     const int lastload = walls ? min(e1, ny - 1) : e1;
     const long long base = (long long)b * ny * nx;
     // lane offsets are unsigned 32-bit and row bases uniform, so memory
-    // accesses take the scalar-base + vector-offset form
-    const unsigned x = threadIdx.x;
+    // accesses take the scalar-base + vector-offset form.  x, xm, xp: the
+    // lane's column and its periodic neighbours in memory; lx, lxm, lxp: the
+    // lane and its neighbour lanes in LDS (the same unless TILED).
+    const unsigned lx = threadIdx.x;
+    unsigned x = lx;
+    bool out = true;  // this lane stores its step-(n + 1) result
+    if constexpr (TILED) {
+        const int c = tx * kTbTileOut - kTbHalo + int(lx);
+        x = unsigned(((c % nx) + nx) % nx);
+        out = int(lx) >= kTbHalo && int(lx) < kTbMaxNx - kTbHalo && c < nx;
+    }
     const unsigned xm = x == 0 ? nx - 1 : x - 1;
     const unsigned xp = x == unsigned(nx - 1) ? 0u : x + 1;
+    const unsigned lxm = TILED ? (lx == 0 ? 0u : lx - 1) : xm;
+    const unsigned lxp = TILED ? (lx == kTbMaxNx - 1 ? lx : lx + 1) : xp;
 
     __shared__ C phN[4][kTbMaxNx];   // phi_n, rows v mod 4
     __shared__ C phN1[4][kTbMaxNx];  // phi_{n+1}
@@ -755,23 +781,23 @@ __global__ __launch_bounds__(kTbMaxNx) void k_phase_tb2(PhaseK k, const S* __res
     // phi of row v into a ring, with the wall ghost rows (copies of the
     // first and last rows: zero normal gradient)
     auto put_phi = [&](C (&ring)[4][kTbMaxNx], int v, C ph) {
-        ring[v & 3][x] = ph;
-        if (walls && v == 0) ring[3][x] = ph;                // row -1
-        if (walls && v == ny - 1) ring[ny & 3][x] = ph;      // row ny
+        ring[v & 3][lx] = ph;
+        if (walls && v == 0) ring[3][lx] = ph;                // row -1
+        if (walls && v == ny - 1) ring[ny & 3][lx] = ph;      // row ny
     };
     auto gather = [&](C (&ring)[4][kTbMaxNx], int v, C (&pn)[9]) {
         const C* rm = ring[(v - 1) & 3];
         const C* r0 = ring[v & 3];
         const C* rp = ring[(v + 1) & 3];
-        pn[0] = r0[x];
-        pn[1] = r0[xp];
-        pn[2] = rp[x];
-        pn[3] = r0[xm];
-        pn[4] = rm[x];
-        pn[5] = rp[xp];
-        pn[6] = rp[xm];
-        pn[7] = rm[xm];
-        pn[8] = rm[xp];
+        pn[0] = r0[lx];
+        pn[1] = r0[lxp];
+        pn[2] = rp[lx];
+        pn[3] = r0[lxm];
+        pn[4] = rm[lx];
+        pn[5] = rp[lxp];
+        pn[6] = rp[lxm];
+        pn[7] = rm[lxm];
+        pn[8] = rm[lxp];
     };
 
     C cur[kNS], nxt[kNS];
@@ -798,7 +824,7 @@ __global__ __launch_bounds__(kTbMaxNx) void k_phase_tb2(PhaseK k, const S* __res
         if (do_load) load_row(v + 1, nxt);
         __syncthreads();  // phi_{n+1} of row v - 2 and the previous exchange reads are done
         // ---- step n + 1 at row r = v - 3, straight to memory
-        if (r >= a && r < e) {
+        if (r >= a && r < e && out) {
             C pn[9], h[9], z[9], hs[9], zst[9], pux, puy;
             S h0hi, h0lo;
             gather(phN1, r, pn);
@@ -847,18 +873,18 @@ __global__ __launch_bounds__(kTbMaxNx) void k_phase_tb2(PhaseK k, const S* __res
             const PhaseLocal<C> L = phase_local(k, pn, z);
             phase_collide<S, C>(k, L, h, cur[kLO], z, cur[kPU], cur[kPU + 1], hs, h0hi, h0lo, zst,
                                 pux, puy);
-            xch[0][x] = hs[1];
-            xch[1][x] = hs[3];
-            xch[2][x] = hs[5];
-            xch[3][x] = hs[6];
-            xch[4][x] = hs[7];
-            xch[5][x] = hs[8];
-            xch[6][x] = zst[1];
-            xch[7][x] = zst[3];
-            xch[8][x] = zst[5];
-            xch[9][x] = zst[6];
-            xch[10][x] = zst[7];
-            xch[11][x] = zst[8];
+            xch[0][lx] = hs[1];
+            xch[1][lx] = hs[3];
+            xch[2][lx] = hs[5];
+            xch[3][lx] = hs[6];
+            xch[4][lx] = hs[7];
+            xch[5][lx] = hs[8];
+            xch[6][lx] = zst[1];
+            xch[7][lx] = zst[3];
+            xch[8][lx] = zst[5];
+            xch[9][lx] = zst[6];
+            xch[10][lx] = zst[7];
+            xch[11][lx] = zst[8];
         }
         __syncthreads();
         if (do_n) {
@@ -869,10 +895,10 @@ __global__ __launch_bounds__(kTbMaxNx) void k_phase_tb2(PhaseK k, const S* __res
             A0[kZ + 0] = zst[0];
             A0[kPU] = pux;
             A0[kPU + 1] = puy;
-            A0[kH + 1] = xch[0][xm];
-            A0[kH + 3] = xch[1][xp];
-            A0[kZ + 1] = xch[6][xm];
-            A0[kZ + 3] = xch[7][xp];
+            A0[kH + 1] = xch[0][lxm];
+            A0[kH + 3] = xch[1][lxp];
+            A0[kZ + 1] = xch[6][lxm];
+            A0[kZ + 3] = xch[7][lxp];
             if (walls && v == ny - 1) {  // top wall: +y movers come back reversed
                 A0[kH + 4] = hs[2];
                 A0[kH + 7] = hs[5];
@@ -882,11 +908,11 @@ __global__ __launch_bounds__(kTbMaxNx) void k_phase_tb2(PhaseK k, const S* __res
                 A0[kZ + 8] = zst[6];
             } else {
                 Ap[kH + 2] = hs[2];
-                Ap[kH + 5] = xch[2][xm];
-                Ap[kH + 6] = xch[3][xp];
+                Ap[kH + 5] = xch[2][lxm];
+                Ap[kH + 6] = xch[3][lxp];
                 Ap[kZ + 2] = zst[2];
-                Ap[kZ + 5] = xch[8][xm];
-                Ap[kZ + 6] = xch[9][xp];
+                Ap[kZ + 5] = xch[8][lxm];
+                Ap[kZ + 6] = xch[9][lxp];
             }
             if (walls && v == 0) {  // bottom wall: -y movers come back reversed
                 A0[kH + 2] = hs[4];
@@ -897,11 +923,11 @@ __global__ __launch_bounds__(kTbMaxNx) void k_phase_tb2(PhaseK k, const S* __res
                 A0[kZ + 6] = zst[8];
             } else {
                 A1[kH + 4] = hs[4];
-                A1[kH + 7] = xch[4][xp];
-                A1[kH + 8] = xch[5][xm];
+                A1[kH + 7] = xch[4][lxp];
+                A1[kH + 8] = xch[5][lxm];
                 A1[kZ + 4] = zst[4];
-                A1[kZ + 7] = xch[10][xp];
-                A1[kZ + 8] = xch[11][xm];
+                A1[kZ + 7] = xch[10][lxp];
+                A1[kZ + 8] = xch[11][lxm];
             }
         }
         // ---- phi_{n+1} of row v - 1, whose state is complete now
@@ -1378,39 +1404,74 @@ hipError_t launch_phase_step(const PhaseK& k, const S* hc, S* hn, const S* zc, S
     return launch_phase_kernel<S, S, false>(k, hc, hn, zc, zn, puc, pun, (double*)nullptr, lds, s);
 }
 
-bool phase_tb2_fits(const PhaseK& k) { return k.nx % 64 == 0 && k.nx <= kTbMaxNx && k.ny >= 4; }
+// The two-step kernel takes a whole row per workgroup when nx is a multiple
+// of 64 up to 256, and x-tiles of kTbTileOut stored columns otherwise; y
+// needs at least 4 rows (virtual rows wrap with one correction).
+bool phase_tb2_fits(const PhaseK& k) { return k.ny >= 4 && k.nx >= 1; }
+bool phase_tb2_tiled(const PhaseK& k) { return !(k.nx % 64 == 0 && k.nx <= kTbMaxNx); }
+int phase_tb2_ntx(const PhaseK& k) {
+    return phase_tb2_tiled(k) ? (k.nx + kTbTileOut - 1) / kTbTileOut : 1;
+}
+// Share of the launched lanes whose columns are stored (1 for whole rows).
+double phase_tb2_lane_use(const PhaseK& k) {
+    return phase_tb2_tiled(k) ? double(k.nx) / (double(phase_tb2_ntx(k)) * kTbMaxNx) : 1.0;
+}
 
-// Rows per segment: the whole replica when it has fewer than two segments'
-// worth of rows, or when it has at most four and the replicas alone already
-// fill every resident workgroup slot of the GPU (then segments would only add
-// the 6 overlap rows each: 1024 replicas of 256^2, FP32 +0.5 %; 256 replicas
-// in FP64, one workgroup per CU, +3.6 %); else kTbSeg rows, whose extra
-// workgroups keep smaller batches busy.
+// Rows per segment.  Every workgroup marches seg + 5 rows (its segment, two
+// rows of overlap below and three of lag above), all workgroups take the
+// same time, and the GPU holds `slots` of them at once, so a launch costs
+// about ceil(workgroups / slots) (seg + 5) row steps.  The segment length
+// (at least 64 rows, or the whole replica) minimises that, preferring longer
+// segments on ties: 1024 replicas of 256^2 in FP32 (512 slots) keep whole
+// replicas (two full rounds); the 8192^2 domain in 33 x-tiles takes 265-row
+// segments (1023 workgroups, two rounds) instead of 128-row ones (2112
+// workgroups: a fifth, nearly empty round).
 template <typename S>
 int phase_tb2_seg(const PhaseK& k) {
-    if (k.ny < 2 * kTbSeg) return k.ny;
-    if (k.ny <= 4 * kTbSeg) {
-        int dev = 0, cus = 0, per_cu = 0;
-        if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_phase_tb2<S>, k.nx, 0) ==
-                hipSuccess &&
-            per_cu > 0 && (long long)k.batch >= (long long)cus * per_cu)
-            return k.ny;
+    const int ny = k.ny;
+    int dev = 0, cus = 0, per_cu = 0;
+    const bool tiled = phase_tb2_tiled(k);
+    long long slots = 512;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        (tiled ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_phase_tb2<S, true>,
+                                                              kTbMaxNx, 0)
+               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_phase_tb2<S, false>,
+                                                              k.nx, 0)) == hipSuccess &&
+        cus > 0 && per_cu > 0)
+        slots = (long long)cus * per_cu;
+    const long long units = (long long)k.batch * phase_tb2_ntx(k);
+    const int lo = ny < kTbSeg ? ny : kTbSeg / 2;
+    int best = ny;
+    long long best_cost = -1;
+    for (int seg = ny; seg >= lo; --seg) {
+        const long long nseg = (ny + seg - 1) / seg;
+        if (seg < ny && (ny + seg - 2) / (seg - 1 > 0 ? seg - 1 : 1) == nseg && seg - 1 >= lo)
+            continue;  // a shorter segment gives the same count: take the shortest of them
+        const long long rounds = (units * nseg + slots - 1) / slots;
+        const long long cost = rounds * (seg + 5);
+        if (best_cost < 0 || cost < best_cost) {
+            best_cost = cost;
+            best = seg;
+        }
     }
-    return kTbSeg;
+    return best;
 }
 
 long long phase_tb2_workgroups(const PhaseK& k, int seg) {
-    return (long long)((k.ny + seg - 1) / seg) * k.batch;
+    return (long long)((k.ny + seg - 1) / seg) * k.batch * phase_tb2_ntx(k);
 }
 
 template <typename S>
 hipError_t launch_phase_tb2(const PhaseK& k, const S* a, S* b, int seg, hipStream_t s) {
     if (!phase_tb2_fits(k) || seg < 1) return hipErrorInvalidValue;
     const long long wgs = phase_tb2_workgroups(k, seg);
-    dim3 blk(k.nx), grd(unsigned((wgs + kXCD - 1) / kXCD * kXCD));
-    hipLaunchKernelGGL(k_phase_tb2<S>, grd, blk, 0, s, k, a, b, seg);
+    if ((wgs + kXCD - 1) / kXCD * kXCD > 0x7fffffffLL) return hipErrorInvalidValue;
+    dim3 grd(unsigned((wgs + kXCD - 1) / kXCD * kXCD));
+    if (phase_tb2_tiled(k))
+        hipLaunchKernelGGL((k_phase_tb2<S, true>), grd, dim3(kTbMaxNx), 0, s, k, a, b, seg);
+    else
+        hipLaunchKernelGGL((k_phase_tb2<S, false>), grd, dim3(k.nx), 0, s, k, a, b, seg);
     return hipGetLastError();
 }
 

@@ -164,6 +164,21 @@ def bubble(n=256, radii=(20, 30, 40, 50), seed=0, dx=5e-6, dt=1e-7, W_nodes=4.0,
     return prm, dict(phi=phi, p=zeros.copy(), ux=zeros.copy(), uy=zeros.copy()), centres
 
 
+def bubble_array(cells=32, n=256, seed=0, **kw):
+    """The bubble cell tiled into one periodic (cells n) x (cells n) domain:
+    cell (i, j) (row i, column j) holds replica i cells + j of bubble(n,
+    batch=cells^2, seed) -- radii cycling over 20/30/40/50 nodes, centre
+    jitter drawn per cell.  The roofline-sized single-domain form of the
+    bubble case (32 x 32 cells: 8192^2 nodes).  Returns (prm, ini, centres)
+    with ini fields [1][cells n][cells n]."""
+    prm, ini, cen = bubble(n=n, batch=cells * cells, seed=seed, **kw)
+    out = {}
+    for k, v in ini.items():
+        out[k] = np.ascontiguousarray(
+            v.reshape(cells, cells, n, n).transpose(0, 2, 1, 3).reshape(1, cells * n, cells * n))
+    return prm, out, cen
+
+
 # --------------------------------------------------------------------------
 # C4: layered two-phase Poiseuille flow (Sec. 4.4)
 # --------------------------------------------------------------------------

@@ -1,9 +1,9 @@
 """The two-step (temporally blocked) two-phase kernel against the single-step
 kernel and the oracle.  Both kernels evaluate the same per-node arithmetic
 in the same order, so a run of either must give the same state to the last
-bit; the cases cover periodic and walled y, one and several 64-row
-segments (128 rows each), odd step counts (the last step single) and graph
-replay."""
+bit; the cases cover periodic and walled y, one and several 128-row
+segments, rows in x-tiles (ragged, single, wrapped), odd step counts (the
+last step single) and graph replay."""
 import numpy as np
 import pytest
 
@@ -46,6 +46,14 @@ CASES = [
     (256, 256, 2, False, (6, 5)),     # two segments, the bench cell
     (64, 300, 1, True, (9, 8)),       # walls, ragged segments
     (192, 40, 1, True, (10,)),        # walls, one short segment
+    # rows in x-tiles of 250 stored columns (nx not a multiple of 64 up to 256)
+    (300, 70, 1, False, (9, 8)),      # two tiles, the second one ragged
+    (250, 40, 2, False, (6,)),        # exactly one tile
+    (251, 33, 1, False, (5,)),        # one tile and one column
+    (100, 64, 1, False, (4,)),        # one tile holding the row 2.5 times
+    (7, 20, 1, False, (3, 4)),        # a very narrow row
+    (520, 300, 1, True, (9, 8)),      # walls, three tiles, ragged segments
+    (600, 130, 2, False, (5,)),       # three tiles, one segment per replica
 ]
 
 
@@ -100,10 +108,11 @@ def test_fusion_validation():
     from paper_2302_04120_amd import lbm
     prm, ini = _bubble_case(96, 64, 1, seed=0)
     L = lbm.Lattice("phase", 96, 64, prec="fp32")
-    with pytest.raises(lbm.LbmError):
-        L.set_step_fusion(2)  # nx not a multiple of 64
-    with pytest.raises(lbm.LbmError):
-        L.set_step_fusion(4)
+    L.set_step_fusion(2)  # nx not a multiple of 64: rows in x-tiles
+    for bad in (4, -1):
+        with pytest.raises(lbm.LbmError) as e:
+            L.set_step_fusion(bad)
+        assert e.value.status == lbm.LBM_E_ARG
     L.set_step_fusion(1)
 
 
