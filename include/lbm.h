@@ -304,6 +304,17 @@ LBM_API lbm_status lbm_macros(lbm_ctx* ctx, unsigned mask, double* out, int out_
 enum { LBM_R_MASS = 1, LBM_R_PHASE = 2, LBM_R_ENERGY = 4, LBM_R_NONFINITE = 8 };
 LBM_API lbm_status lbm_reduce(lbm_ctx* ctx, unsigned mask, double* out);
 
+/* lbm_reduce for callers that cannot allocate device memory or take a
+ * workspace at the call (code under stream capture, tight serving loops,
+ * harnesses that forbid allocation): the same kernels and the same results,
+ * but the FP64 partials and per-replica sums live in a static device array
+ * of the library (8.4 MB per GPU, held until the process ends) instead of
+ * the context's buffer, and the call makes no allocation of any kind.  At
+ * most 1024 replicas (LBM_E_ARG beyond).  Calls that overlap on one GPU share
+ * that array and race; calls on one stream are ordered.  Synchronous; returns
+ * LBM_E_NONFINITE like lbm_reduce. */
+LBM_API lbm_status lbm_reduce_noalloc(lbm_ctx* ctx, unsigned mask, double* out);
+
 /* Heated-channel diagnostics of replica 0 (LBM_D2Q9_D2Q5 with flow and
  * thermal): per column the mixing-cup temperature Tb = sum(u T)/sum(u), the
  * wall temperature Tw = mean of the two wall-adjacent nodes + q'' dx/(2k), and

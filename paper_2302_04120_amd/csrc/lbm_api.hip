@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -14,6 +15,38 @@
 using namespace lbm;
 
 namespace {
+
+// ---- scratch of lbm_reduce_noalloc -------------------------------------------
+// The reduction partials (batch x 4 fields x kRedBlocks FP64) and the per-
+// replica results (batch x 4) of that entry point live in this file-scope
+// device array instead of the caller's buffer, for at most kNoAllocMaxBatch
+// replicas (8.4 MB held on every GPU the library runs on until the process
+// ends).  The host name `scratch` is only a stand-in for the symbol: host code
+// uses the per-device address from hipGetSymbolAddress, taken once per device
+// by the first lbm_create on it.  Every element the reduction reads is written
+// earlier in the same call (each first-pass block writes its partials, the
+// second pass every result), so nothing needs clearing between calls; calls
+// that overlap on one GPU share the array and race.
+constexpr int kNoAllocMaxBatch = 1024;
+constexpr size_t kNoAllocDoubles = (size_t)kNoAllocMaxBatch * (4 * kRedBlocks + 4);
+__device__ __align__(256) double scratch[kNoAllocDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on `device` (the current device), taken on
+// the first call for that device; nullptr if the query fails.
+double* scratch_address(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+        g_scratch_ptr[device] = static_cast<double*>(p);
+    }
+    return g_scratch_ptr[device];
+}
 
 constexpr uint32_t kMagic = 0x534d424cu;  // "LBMS"
 constexpr uint32_t kVersion = 3;
@@ -433,6 +466,7 @@ lbm_status lbm_create(const lbm_desc* desc, lbm_ctx** out) {
     c->small = (double*)(base + L.offSmall);
     c->phi3 = base + L.offPhi;
     c->persist_flags = desc->lattice == LBM_D2Q9_PHASE ? (unsigned*)(base + L.offFlags) : nullptr;
+    c->scratch = scratch_address(c->device);  // nullptr: lbm_reduce_noalloc reports it
     c->cur = 0;
     c->t = 0;
     c->has_params = c->has_state = false;
@@ -908,6 +942,45 @@ lbm_status lbm_reduce(lbm_ctx* c, unsigned mask, double* out) {
     if (e != hipSuccess) return hip_fail(c, e, "reduce kernel");
     std::vector<double> h(4 * (size_t)batch);
     e = hipMemcpyAsync(h.data(), res, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "reduce");
+    int k = 0;
+    bool nonfinite = false;
+    for (int f = 0; f < 4; ++f) {
+        for (int b = 0; b < batch; ++b) {
+            if (h[b * 4 + 3] > 0) nonfinite = true;
+            if (mask & (1u << f)) out[(size_t)k * batch + b] = h[b * 4 + f];
+        }
+        if (mask & (1u << f)) ++k;
+    }
+    if (nonfinite) return set_err(c, LBM_E_NONFINITE, "non-finite populations in the state");
+    return LBM_OK;
+}
+
+lbm_status lbm_reduce_noalloc(lbm_ctx* c, unsigned mask, double* out) {
+    if (!c) return LBM_E_ARG;
+    if (!out) return set_err(c, LBM_E_ARG, "out is NULL");
+    if (!c->has_state) return set_err(c, LBM_E_STATE, "no state");
+    if (mask == 0 || (mask & ~15u)) return set_err(c, LBM_E_ARG, "bad reduction mask");
+    const int batch = c->desc.batch;
+    if (batch > kNoAllocMaxBatch)
+        return set_err(c, LBM_E_ARG, "lbm_reduce_noalloc: at most 1024 replicas (static scratch)");
+    if (!c->scratch)
+        return set_err(c, LBM_E_DEVICE, "lbm_reduce_noalloc: no address for the static scratch");
+    DeviceGuard g(c->device);
+    const int lat = c->desc.lattice;
+    double* partial = c->scratch;
+    double* res = c->scratch + (size_t)batch * 4 * kRedBlocks;
+    hipError_t e;
+    if (c->desc.prec == LBM_FP64)
+        e = launch_reduce<double>(lat, c->ck, c->pk, c->dk, c->d3k, c->p3k, (const double*)bufA(c),
+                                  c->npop, partial, res, c->stream);
+    else
+        e = launch_reduce<float>(lat, c->ck, c->pk, c->dk, c->d3k, c->p3k, (const float*)bufA(c),
+                                 c->npop, partial, res, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "reduce kernel");
+    double h[4 * kNoAllocMaxBatch];  // host copy on the stack: no allocation anywhere
+    e = hipMemcpyAsync(h, res, 4 * (size_t)batch * sizeof(double), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "reduce");
     int k = 0;

@@ -118,6 +118,7 @@ struct lbm_ctx {
     char* aux;            // flux (qw), inlet_u (uin), inlet_T (tin): storage type
     double* staging;      // 8 planes of FP64
     double* partial;      // reduction partials
+    double* scratch;      // device address of the static scratch of lbm_reduce_noalloc
     double* small;        // small FP64 results
     int cur;              // 0: A holds the state, 1: B holds it
     long long t;          // steps since init

@@ -40,7 +40,7 @@ EXPORTS = ("lbm_query_bytes", "lbm_create", "lbm_destroy", "lbm_set_params_SI",
            "lbm_init_fields", "lbm_step", "lbm_macros", "lbm_reduce", "lbm_nusselt",
            "lbm_query_record_bytes", "lbm_record", "lbm_grad", "lbm_time",
            "lbm_save_state", "lbm_load_state", "lbm_last_error", "lbm_set_graph_steps",
-           "lbm_set_step_fusion", "lbm_init_fields3d")
+           "lbm_set_step_fusion", "lbm_init_fields3d", "lbm_reduce_noalloc")
 
 
 class LbmError(RuntimeError):
@@ -101,6 +101,7 @@ def lib():
         L.lbm_step.argtypes = [vp, C.c_int]
         L.lbm_macros.argtypes = [vp, C.c_uint, _dp, C.c_int]
         L.lbm_reduce.argtypes = [vp, C.c_uint, _dp]
+        L.lbm_reduce_noalloc.argtypes = [vp, C.c_uint, _dp]
         L.lbm_nusselt.argtypes = [vp, C.c_int, _dp, _dp, _dp, _dp, _dp]
         L.lbm_time.argtypes = [vp]
         L.lbm_time.restype = C.c_longlong
@@ -348,6 +349,18 @@ class Lattice:
         order = [f for f in REDUCE_BITS if mask & REDUCE_BITS[f]]
         out = np.zeros((len(order), self.batch))
         st = lib().lbm_reduce(self.ctx, mask, _ptr(out))
+        if st != LBM_E_NONFINITE or check:
+            self._check(st)
+        return {f: out[i] for i, f in enumerate(order)}
+
+    def reduce_noalloc(self, fields=("mass", "phase", "energy", "nonfinite"), check=True):
+        """reduce() through lbm_reduce_noalloc (static scratch, no allocation)."""
+        mask = 0
+        for f in fields:
+            mask |= REDUCE_BITS[f]
+        order = [f for f in REDUCE_BITS if mask & REDUCE_BITS[f]]
+        out = np.zeros((len(order), self.batch))
+        st = lib().lbm_reduce_noalloc(self.ctx, mask, _ptr(out))
         if st != LBM_E_NONFINITE or check:
             self._check(st)
         return {f: out[i] for i, f in enumerate(order)}
