@@ -78,7 +78,13 @@ typedef enum {
     LBM_E_DEVICE = -3,      /* a HIP call failed                                  */
     LBM_E_STATE = -4,       /* wrong call order or malformed state blob           */
     LBM_E_NONFINITE = -5,   /* a NaN/Inf was found in the populations             */
-    LBM_E_UNSUPPORTED = -6  /* combination not implemented                        */
+    LBM_E_UNSUPPORTED = -6, /* combination not implemented                        */
+    /* informational (> 0): the call succeeded; lbm_last_error says why it is reported */
+    LBM_W_FP32_FORCING = 1  /* lbm_set_params_SI, LBM_D2Q9_PHASE in LBM_FP32_DEV with a body
+                               force: the slowest viscous mode (wall distance, or the period)
+                               relaxes by nu dt k^2 < 2^-23 per step, so FP32 arithmetic rounds
+                               the per-step force increments of long runs away; the parameters
+                               are set, and LBM_FP32_DEV_ARITH64 avoids the drift          */
 } lbm_status;
 
 enum { LBM_D1Q2 = 1, LBM_D1Q3 = 2, LBM_D2Q9_D2Q5 = 3, LBM_D2Q9_PHASE = 4, LBM_D3Q19 = 5,
@@ -188,7 +194,8 @@ LBM_API void lbm_destroy(lbm_ctx* ctx);
  * qdot = qvol / rho_cp (Eq. forcing_term_g)).  Returns LBM_E_TAU if any
  * relaxation time is not above dt/2, LBM_E_ARG for non-positive dx, dt or
  * densities.  Copies the flux / inlet arrays to the device; the caller keeps
- * ownership of p and of the arrays it points to. */
+ * ownership of p and of the arrays it points to.  May return the
+ * informational LBM_W_FP32_FORCING (parameters set). */
 LBM_API lbm_status lbm_set_params_SI(lbm_ctx* ctx, const lbm_params_si* p);
 
 /* 3D lattices: the populations at the equilibria of the given fields, host
@@ -226,6 +233,20 @@ LBM_API lbm_status lbm_init_fields(lbm_ctx* ctx, const double* rho_or_p, const d
  * graph gets n steps per replay from the buffer the capture started in, so n
  * must be even; lbm_time counts the captured steps once. */
 LBM_API lbm_status lbm_step(lbm_ctx* ctx, int n);
+
+/* Failure detection inside lbm_step: every time the step count reaches a
+ * multiple of `every` (default 4096; 0 turns the check off), lbm_step
+ * enqueues a read-only scan of the state's node values that records the
+ * smallest such step count at which any of them was NaN or infinite (no
+ * check while the caller captures the stream).  The scan reads the state
+ * once, about half a step's memory traffic.  LBM_E_ARG for every < 0. */
+LBM_API lbm_status lbm_set_nonfinite_check(lbm_ctx* ctx, int every);
+
+/* The step count at which the check of lbm_set_nonfinite_check first saw a
+ * non-finite state since lbm_init_fields / lbm_load_state, or -1 (*step).
+ * Synchronous.  Returns LBM_E_NONFINITE (with the step in lbm_last_error)
+ * when one was seen, LBM_OK otherwise. */
+LBM_API lbm_status lbm_first_nonfinite_step(lbm_ctx* ctx, long long* step);
 
 /* Steps per captured graph used by lbm_step (default 64; 0 disables graph
  * replay; otherwise even, at most 4096).  Graphs are captured lazily on a

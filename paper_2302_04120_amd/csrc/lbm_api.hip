@@ -3,6 +3,7 @@
 // memory is allocated here; every kernel runs on the caller's stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -56,7 +57,7 @@ struct Layout {
     int npop = 0, nplanes = 0;
     size_t es = 0;
     size_t offA = 0, offB = 0, offAux = 0, offStage = 0, offPartial = 0, offPhi = 0;
-    size_t offSmall = 0, offFlags = 0, total = 0;
+    size_t offSmall = 0, offFlags = 0, offWatch = 0, total = 0;
 };
 
 // Extra elements between population planes (a multiple of 64).  Planes whose
@@ -180,6 +181,8 @@ lbm_status check_desc(const lbm_desc* d, Layout* L, std::string* err) {
     // D2Q9_PHASE: per-tile step counters and the error word of the
     // many-steps-per-launch kernel
     l.offFlags = off; off += d->lattice == LBM_D2Q9_PHASE ? kPersistFlagBytes : 0;
+    // the non-finite watch word (first step at which a check saw one)
+    l.offWatch = off; off += 256;
     l.total = off;
     *L = l;
     return LBM_OK;
@@ -274,6 +277,11 @@ bool use_persist(const lbm_ctx* c) {
         return false;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     return hipStreamIsCapturing(c->stream, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone;
+}
+
+// Clear the non-finite watch word (all ones: nothing seen) with a new state.
+hipError_t reset_watch(lbm_ctx* c) {
+    return hipMemsetAsync(c->watch, 0xff, sizeof(unsigned long long), c->stream);
 }
 
 // Zero the step counters and the error word: with the state (re)set no
@@ -467,6 +475,7 @@ lbm_status lbm_create(const lbm_desc* desc, lbm_ctx** out) {
     c->phi3 = base + L.offPhi;
     c->persist_flags = desc->lattice == LBM_D2Q9_PHASE ? (unsigned*)(base + L.offFlags) : nullptr;
     c->scratch = scratch_address(c->device);  // nullptr: lbm_reduce_noalloc reports it
+    c->watch = (unsigned long long*)(base + L.offWatch);
     c->cur = 0;
     c->t = 0;
     c->has_params = c->has_state = false;
@@ -529,6 +538,7 @@ lbm_status lbm_set_params_SI(lbm_ctx* c, const lbm_params_si* p) {
     D3K d3k{};
     P3K p3k{};
     AdjK ak{};
+    c->fp32_forcing_share = 0.0;
     double alpha_eff = p->alpha;  // thermal diffusivity implied by tau_T, m^2/s
     if (d.lattice == LBM_D3Q19_PHASE) {
         const double cs2 = cc * cc / 3.0;
@@ -694,6 +704,19 @@ lbm_status lbm_set_params_SI(lbm_ctx* c, const lbm_params_si* p) {
         pk.Geps = eps * dx / 3.0;
         pk.c = cc;
         pk.cs2 = cs2;
+        // FP32 forcing guard.  A body force builds the flow up over the
+        // slowest viscous mode, whose share of the remaining change per step
+        // is nu dt k^2 (k = pi / H between walls H apart, 2 pi / L for a period
+        // L).  Once that share is below FP32's resolution, FP32 arithmetic
+        // rounds part of every step's force increment away and long runs
+        // drift (the layered channel at the paper's finest grid: 9-12 %).
+        if (d.prec == LBM_FP32_DEV && (p->Fb[0] != 0.0 || p->Fb[1] != 0.0)) {
+            const double nu_min = pk.visc_mode == 0
+                                      ? std::min(p->nu_l, p->nu_g)
+                                      : std::min(p->zeta_l / p->rho_l, p->zeta_g / p->rho_g);
+            const double kw = pk.bcy ? M_PI / (d.ny * dx) : 2.0 * M_PI / (std::max(d.nx, d.ny) * dx);
+            c->fp32_forcing_share = nu_min * dt * kw * kw;
+        }
     }
     c->ck = ck;
     c->pk = pk;
@@ -742,6 +765,15 @@ lbm_status lbm_set_params_SI(lbm_ctx* c, const lbm_params_si* p) {
         drop_graphs(c);  // captured kernel arguments are stale now
     }
     c->has_params = true;
+    if (c->fp32_forcing_share > 0.0 && c->fp32_forcing_share < std::ldexp(1.0, -23)) {
+        char m[256];
+        std::snprintf(m, sizeof m,
+                      "parameters set; the slowest viscous mode changes by %.2e of itself per step, "
+                      "below FP32 resolution: FP32 arithmetic rounds the body-force increments of "
+                      "long runs (LBM_FP32_DEV_ARITH64 keeps them)", c->fp32_forcing_share);
+        set_err(c, LBM_W_FP32_FORCING, m);
+        return LBM_W_FP32_FORCING;
+    }
     return LBM_OK;
 }
 
@@ -774,6 +806,7 @@ lbm_status lbm_init_fields(lbm_ctx* c, const double* rho_or_p, const double* ux,
     }
     c->cur = 0;
     hipError_t e = reset_persist(c);
+    if (e == hipSuccess) e = reset_watch(c);
     if (e != hipSuccess) return hip_fail(c, e, "step counter reset");
     if (d1) {
         e = launch_d1_init(c->dk, c->staging, (double*)c->popA, c->stream);
@@ -826,7 +859,8 @@ lbm_status lbm_init_fields3d(lbm_ctx* c, const double* rho_or_p, const double* u
     }
     c->cur = 0;
     const bool f64 = c->desc.prec == LBM_FP64;
-    hipError_t e;
+    hipError_t e = reset_watch(c);
+    if (e != hipSuccess) return hip_fail(c, e, "watch reset");
     if (lat == LBM_D3Q19)
         e = f64 ? launch_d3_init<double>(c->d3k, c->staging, (double*)c->popA, c->stream)
                 : launch_d3_init<float>(c->d3k, c->staging, (float*)c->popA, c->stream);
@@ -841,11 +875,12 @@ lbm_status lbm_init_fields3d(lbm_ctx* c, const double* rho_or_p, const double* u
     return LBM_OK;
 }
 
-lbm_status lbm_step(lbm_ctx* c, int n) {
-    if (!c) return LBM_E_ARG;
-    if (n < 0) return set_err(c, LBM_E_ARG, "n must be >= 0");
-    if (!c->has_state) return set_err(c, LBM_E_STATE, "no state: call lbm_init_fields or lbm_load_state");
-    DeviceGuard g(c->device);
+}  // extern "C"
+
+namespace {
+
+// n steps of the current kernel choice (the body of lbm_step).
+lbm_status step_run(lbm_ctx* c, int n) {
     const int lat = c->desc.lattice;
     if (lat == LBM_D1Q2 || lat == LBM_D1Q3) {
         if (n == 0) return LBM_OK;
@@ -872,6 +907,73 @@ lbm_status lbm_step(lbm_ctx* c, int n) {
         s += m;
     }
     return LBM_OK;
+}
+
+// The non-finite check of the current state (every node value of every
+// state plane), recorded against the step count.
+hipError_t watch_now(lbm_ctx* c) {
+    const char* a = (c->desc.lattice == LBM_D1Q2 || c->desc.lattice == LBM_D1Q3) ? c->popA : bufA(c);
+    if (c->desc.prec == LBM_FP64)
+        return launch_nonfinite_watch<double>((const double*)a, c->P, c->N, c->nplanes,
+                                              (unsigned long long)c->t, c->watch, c->stream);
+    return launch_nonfinite_watch<float>((const float*)a, c->P, c->N, c->nplanes,
+                                         (unsigned long long)c->t, c->watch, c->stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+// n steps; every time the step count reaches a multiple of watch_every, the
+// state is checked for non-finite values (not while the caller captures the
+// stream: a captured check would replay a stale step count).
+lbm_status lbm_step(lbm_ctx* c, int n) {
+    if (!c) return LBM_E_ARG;
+    if (n < 0) return set_err(c, LBM_E_ARG, "n must be >= 0");
+    if (!c->has_state) return set_err(c, LBM_E_STATE, "no state: call lbm_init_fields or lbm_load_state");
+    DeviceGuard g(c->device);
+    const long long K = c->watch_every;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    const bool capturing =
+        hipStreamIsCapturing(c->stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone;
+    if (K <= 0 || capturing) return step_run(c, n);
+    long long left = n;
+    while (left > 0) {
+        const long long to_mark = K - (c->t % K);  // steps to the next multiple of K
+        const int m = (int)std::min(left, to_mark);
+        lbm_status st = step_run(c, m);
+        if (st != LBM_OK) return st;
+        left -= m;
+        if (c->t % K == 0) {
+            hipError_t e = watch_now(c);
+            if (e != hipSuccess) return hip_fail(c, e, "non-finite watch");
+        }
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_set_nonfinite_check(lbm_ctx* c, int every) {
+    if (!c) return LBM_E_ARG;
+    if (every < 0) return set_err(c, LBM_E_ARG, "check interval must be >= 0");
+    c->watch_every = every;
+    return LBM_OK;
+}
+
+lbm_status lbm_first_nonfinite_step(lbm_ctx* c, long long* step) {
+    if (!c) return LBM_E_ARG;
+    if (!step) return set_err(c, LBM_E_ARG, "step is NULL");
+    if (!c->has_state) return set_err(c, LBM_E_STATE, "no state");
+    DeviceGuard g(c->device);
+    unsigned long long w = ~0ull;
+    hipError_t e = hipMemcpyAsync(&w, c->watch, sizeof w, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "non-finite watch");
+    *step = w == ~0ull ? -1 : (long long)w;
+    if (w == ~0ull) return LBM_OK;
+    char m[160];
+    std::snprintf(m, sizeof m, "non-finite state seen by the check at step %llu (checks every %d steps)",
+                  w, c->watch_every);
+    return set_err(c, LBM_E_NONFINITE, m);
 }
 
 lbm_status lbm_macros(lbm_ctx* c, unsigned mask, double* out, int out_on_device) {
@@ -953,7 +1055,16 @@ lbm_status lbm_reduce(lbm_ctx* c, unsigned mask, double* out) {
         }
         if (mask & (1u << f)) ++k;
     }
-    if (nonfinite) return set_err(c, LBM_E_NONFINITE, "non-finite populations in the state");
+    if (nonfinite) {
+        unsigned long long w = ~0ull;
+        if (hipMemcpy(&w, c->watch, sizeof w, hipMemcpyDeviceToHost) == hipSuccess && w != ~0ull) {
+            char m[160];
+            std::snprintf(m, sizeof m, "non-finite populations in the state (first seen by the "
+                                       "in-step check at step %llu)", w);
+            return set_err(c, LBM_E_NONFINITE, m);
+        }
+        return set_err(c, LBM_E_NONFINITE, "non-finite populations in the state");
+    }
     return LBM_OK;
 }
 
@@ -1269,6 +1380,7 @@ lbm_status lbm_load_state(lbm_ctx* c, const void* host, size_t bytes) {
     const char* p = (const char*)host + sizeof hd;
     c->cur = 0;
     hipError_t e = reset_persist(c);
+    if (e == hipSuccess) e = reset_watch(c);
     if (e == hipSuccess)
         e = hipMemcpy2DAsync(c->popA, (size_t)c->P * c->esize, p, row, row, c->nplanes,
                              hipMemcpyHostToDevice, c->stream);

@@ -119,6 +119,9 @@ struct lbm_ctx {
     double* staging;      // 8 planes of FP64
     double* partial;      // reduction partials
     double* scratch;      // device address of the static scratch of lbm_reduce_noalloc
+    unsigned long long* watch;  // first step with a non-finite state seen (~0: none)
+    int watch_every = 4096;     // steps between non-finite checks (0: off)
+    double fp32_forcing_share = 0.0;  // per-step share of the slowest forced mode (guard)
     double* small;        // small FP64 results
     int cur;              // 0: A holds the state, 1: B holds it
     long long t;          // steps since init
@@ -182,6 +185,10 @@ int phase_tb2_seg(const PhaseK& k);
 long long phase_tb2_workgroups(const PhaseK& k, int seg);
 template <typename S>
 hipError_t launch_phase_tb2(const PhaseK& k, const S* a, S* b, int seg, hipStream_t s);
+// *first = min(*first, t) if any node value of the nplanes planes is not finite
+template <typename S>
+hipError_t launch_nonfinite_watch(const S* pops, long long P, long long N, int nplanes,
+                                  unsigned long long t, unsigned long long* first, hipStream_t s);
 // many steps in one cooperative launch for grids that split into at most
 // kPersistMaxTiles tiles of 512 threads (phase_persist_fits); flags: one step
 // counter per tile (zeroed with the state, advanced to epoch0 + steps), err:

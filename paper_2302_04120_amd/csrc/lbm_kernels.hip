@@ -1192,6 +1192,19 @@ __global__ __launch_bounds__(256) void k_reduce1(int lattice, ChanK ck, PhaseK p
     block_sums<4>(v, partial + (long long)b * 4 * kRedBlocks + blockIdx.x, kRedBlocks);
 }
 
+// Non-finite watch: every node value of planes [0, nplanes) (plane stride P,
+// N nodes) that is NaN or infinite lowers *first to t.  Grid (blocks, planes).
+template <typename S>
+__global__ __launch_bounds__(256) void k_nonfinite_watch(const S* __restrict__ pops, long long P,
+                                                         long long N, unsigned long long t,
+                                                         unsigned long long* __restrict__ first) {
+    const S* plane = pops + (long long)blockIdx.y * P;
+    bool bad = false;
+    for (long long n = blockIdx.x * 256LL + threadIdx.x; n < N; n += 256LL * gridDim.x)
+        bad |= !isfinite(plane[n]);
+    if (bad) atomicMin(first, t);
+}
+
 // pass 2: one thread per (replica, field), fixed-order sum
 __global__ void k_reduce2(const double* __restrict__ partial, double* __restrict__ out, int nb) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1541,6 +1554,15 @@ hipError_t launch_reduce(int lattice, const ChanK& ck, const PhaseK& pk, const D
 }
 
 template <typename S>
+hipError_t launch_nonfinite_watch(const S* pops, long long P, long long N, int nplanes,
+                                  unsigned long long t, unsigned long long* first, hipStream_t s) {
+    const long long blocks = std::min<long long>((N + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_nonfinite_watch<S>, dim3(unsigned(blocks), nplanes), dim3(256), 0, s,
+                       pops, P, N, t, first);
+    return hipGetLastError();
+}
+
+template <typename S>
 hipError_t launch_nusselt(const ChanK& k, const S* f, const S* g, const S* qw, double qsi,
                           double Dh, double kc, double dx, int x_dev, double* Tb, double* Tw,
                           double* Nu, double* small, hipStream_t s) {
@@ -1571,6 +1593,9 @@ hipError_t launch_nusselt(const ChanK& k, const S* f, const S* g, const S* qw, d
     template hipError_t launch_reduce<S>(int, const ChanK&, const PhaseK&, const D1K&,           \
                                          const D3K&, const P3K&, const S*, int, double*,          \
                                          double*, hipStream_t);                                   \
+    template hipError_t launch_nonfinite_watch<S>(const S*, long long, long long, int,           \
+                                                  unsigned long long, unsigned long long*,       \
+                                                  hipStream_t);                                   \
     template hipError_t launch_nusselt<S>(const ChanK&, const S*, const S*, const S*, double,    \
                                           double, double, double, int, double*, double*, double*, \
                                           double*, hipStream_t);

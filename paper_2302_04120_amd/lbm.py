@@ -18,6 +18,7 @@ or at the latest by an exit hook that runs while the HIP runtime is still up.
 import atexit
 import ctypes as C
 import os
+import warnings
 import weakref
 
 import numpy as np
@@ -27,6 +28,7 @@ LIB_PATH = os.path.join(_HERE, "liblbm.so")
 
 LBM_OK, LBM_E_ARG, LBM_E_TAU, LBM_E_DEVICE, LBM_E_STATE, LBM_E_NONFINITE, LBM_E_UNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6
+LBM_W_FP32_FORCING = 1  # informational: parameters set, see the warning text
 LBM_D1Q2, LBM_D1Q3, LBM_D2Q9_D2Q5, LBM_D2Q9_PHASE, LBM_D3Q19, LBM_D3Q19_PHASE = 1, 2, 3, 4, 5, 6
 LBM_FP32_DEV, LBM_FP64, LBM_FP32_DEV_ARITH64 = 0, 1, 2
 PRECISIONS = {"fp32": LBM_FP32_DEV, "fp64": LBM_FP64, "fp32_arith64": LBM_FP32_DEV_ARITH64}
@@ -40,7 +42,8 @@ EXPORTS = ("lbm_query_bytes", "lbm_create", "lbm_destroy", "lbm_set_params_SI",
            "lbm_init_fields", "lbm_step", "lbm_macros", "lbm_reduce", "lbm_nusselt",
            "lbm_query_record_bytes", "lbm_record", "lbm_grad", "lbm_time",
            "lbm_save_state", "lbm_load_state", "lbm_last_error", "lbm_set_graph_steps",
-           "lbm_set_step_fusion", "lbm_init_fields3d", "lbm_reduce_noalloc")
+           "lbm_set_step_fusion", "lbm_init_fields3d", "lbm_reduce_noalloc",
+           "lbm_set_nonfinite_check", "lbm_first_nonfinite_step")
 
 
 class LbmError(RuntimeError):
@@ -102,6 +105,8 @@ def lib():
         L.lbm_macros.argtypes = [vp, C.c_uint, _dp, C.c_int]
         L.lbm_reduce.argtypes = [vp, C.c_uint, _dp]
         L.lbm_reduce_noalloc.argtypes = [vp, C.c_uint, _dp]
+        L.lbm_set_nonfinite_check.argtypes = [vp, C.c_int]
+        L.lbm_first_nonfinite_step.argtypes = [vp, C.POINTER(C.c_longlong)]
         L.lbm_nusselt.argtypes = [vp, C.c_int, _dp, _dp, _dp, _dp, _dp]
         L.lbm_time.argtypes = [vp]
         L.lbm_time.restype = C.c_longlong
@@ -280,9 +285,17 @@ class Lattice:
         return (self.batch, self.ny, self.nx)
 
     def set_params(self, prm):
+        """Returns the library status (LBM_OK, or LBM_W_FP32_FORCING, which is
+        also raised as a RuntimeWarning); errors raise LbmError."""
         P, keep = make_params(prm, self.nx, self.ny)
-        self._check(lib().lbm_set_params_SI(self.ctx, C.byref(P)))
+        st = lib().lbm_set_params_SI(self.ctx, C.byref(P))
         del keep
+        if st == LBM_W_FP32_FORCING:
+            warnings.warn("liblbm: " + lib().lbm_last_error(self.ctx).decode(), RuntimeWarning,
+                          stacklevel=2)
+            return st
+        self._check(st)
+        return st
 
     def init(self, rho_or_p=None, ux=None, uy=None, T=None, phi=None):
         n = self.batch * self.ny * self.nx
@@ -307,6 +320,18 @@ class Lattice:
     def set_graph_steps(self, steps):
         """Steps per captured HIP graph replayed by ``step`` (0 disables)."""
         self._check(lib().lbm_set_graph_steps(self.ctx, int(steps)))
+
+    def set_nonfinite_check(self, every):
+        """Check the state for NaN/Inf every `every` steps inside step() (0: off)."""
+        self._check(lib().lbm_set_nonfinite_check(self.ctx, int(every)))
+
+    def first_nonfinite_step(self):
+        """Step count at which the in-step check first saw a non-finite state, or -1."""
+        s = C.c_longlong()
+        st = lib().lbm_first_nonfinite_step(self.ctx, C.byref(s))
+        if st not in (LBM_OK, LBM_E_NONFINITE):
+            self._check(st)
+        return int(s.value)
 
     def set_step_fusion(self, mode):
         """Two-phase kernel choice: 0 automatic, 1 single-step, 2 two-step,
