@@ -147,7 +147,7 @@ def run_wide(cells, steps, warmup, prec, fusion=0):
     return dict(mlups=nodes * steps / (ms * 1e-3) / 1e6, grid="%dx%d" % (n, n),
                 ms_per_step=ms / steps, launch_ms=launch_ms,
                 hbm_frac=BYTES_PER_LU[prec] * nodes / (launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                kernel="k_phase_tb2<%s,true>" % ("float" if prec == "fp32" else "double")
+                kernel="k_phase_tb2<%s, true>" % ("float" if prec == "fp32" else "double")
                 if spl == 2 else "k_phase")
 
 
@@ -509,6 +509,28 @@ def copy_calibration(nbytes, reps=5):
                       "reps": reps}), flush=True)
 
 
+def copy_ceiling(nbytes=4 << 30, reps=7):
+    """What this GPU's HBM delivers to simple kernels (GB/s): the practical
+    ceiling of a kernel that reads and writes its state once."""
+    import ctypes
+    lib_path = os.path.join(ROOT, "paper_2302_04120_amd", "libhbm_probe.so")
+    if not os.path.exists(lib_path):
+        raise RuntimeError("libhbm_probe.so not built: run __graft_entry__.build()")
+    L = ctypes.CDLL(lib_path)
+    L.hbm_probe_run.argtypes = [ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    out = (ctypes.c_double * 7)()
+    rc = L.hbm_probe_run(nbytes, reps, out)
+    if rc != 0:
+        raise RuntimeError("hbm_probe_run failed: HIP error %d" % rc)
+    names = ("copy_float4_grid1024", "copy_float4_grid8192", "copy_float4_nontemporal_grid16384",
+             "read_float4", "write_float4", "copy_21_planes_step_shape",
+             "copy_21_planes_step_shape_nontemporal")
+    res = {k: out[i] for i, k in enumerate(names)}
+    res["best_copy_frac_of_peak"] = max(res[k] for k in names if k.startswith("copy")) / HBM_PEAK_GBS
+    res["buffer_bytes"] = nbytes
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -531,6 +553,8 @@ def main():
                     help="two-phase systems of the c4steady leg (comma-separated)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain copy of BYTES (counter calibration)")
+    ap.add_argument("--copy-ceiling", action="store_true",
+                    help="only run the HBM bandwidth probe (copies and one-way streams, 4 GiB)")
     args = ap.parse_args()
     if args.steps is None:
         args.steps = 20000 if args.leg == "c4single" else 200
@@ -538,6 +562,9 @@ def main():
         args.warmup = 200 if args.leg == "c4single" else 20
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+        return 0
+    if args.copy_ceiling:
+        print(json.dumps(copy_ceiling()), flush=True)
         return 0
     if args.prec == "fp32_arith64" and (args.leg not in (None, "layered", "c4single", "c4steady")
                                         or (args.leg is None and args.fusion == 2)):
@@ -583,7 +610,7 @@ def main():
     mlups = r["nodes"] * args.steps / r["wall"] / 1e6
     bpl = BYTES_PER_LU[args.prec]
     spl = 2 if args.fusion == 2 else 1  # steps per launch
-    kname = ("k_phase_tb2<%s>" % ("float" if args.prec == "fp32" else "double") if spl == 2 else
+    kname = ("k_phase_tb2<%s, false>" % ("float" if args.prec == "fp32" else "double") if spl == 2 else
              "k_phase<%s>" % {"fp32": "float,float,false", "fp64": "double,double,false",
                               "fp32_arith64": "float,double,false"}[args.prec])
     launch_ms = r["kernel_ms"] * spl

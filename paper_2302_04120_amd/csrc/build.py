@@ -40,5 +40,22 @@ def build(verbose=False, extra=()):
     return LIB
 
 
+PROBE_SRC = os.path.join(HERE, "hbm_probe.hip")
+PROBE_LIB = os.path.join(PKG, "libhbm_probe.so")
+
+
+def build_probe(verbose=False):
+    """The HBM bandwidth probe of bench.py --copy-ceiling (a library of its
+    own: measurement code, not part of liblbm)."""
+    cmd = [hipcc(), "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+           "-fvisibility=hidden", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           PROBE_SRC, "-o", PROBE_LIB + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(PROBE_LIB + ".tmp", PROBE_LIB)
+    return PROBE_LIB
+
+
 if __name__ == "__main__":
     build(verbose=True, extra=sys.argv[1:])

@@ -75,20 +75,35 @@ def test_adjoint_fp32_matches_oracle_adjoint():
     np.testing.assert_allclose(gt, gt0, rtol=1e-3)
 
 
+_C5_COPY = {}
+
+
+def _c5_copy_oracle():
+    """The FP64 CPU adjoint of the 200 x 10 copy over C5's 20 000 steps
+    (computed once per session: about a minute on one core)."""
+    if not _C5_COPY:
+        prm, ini = WL.adjoint_channel(nx=200, ny=10)
+        _C5_COPY["prm"], _C5_COPY["ini"] = prm, ini
+        _C5_COPY["ref"] = _oracle_adjoint(prm, ini, 200, 10, 20000, 500)
+    return _C5_COPY["prm"], _C5_COPY["ini"], _C5_COPY["ref"]
+
+
+@pytest.mark.timeout(600)
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32", 1e-4)])
 def test_adjoint_c5_copy_200x10(prec, tol):
     """The C5 channel's 200 x 10 copy (same spacing, properties and inlet
-    speed), 2000 steps with a checkpoint every 500, against the FP64 CPU
-    adjoint."""
+    speed), C5's 20 000 steps with a checkpoint every 500, against the FP64
+    CPU adjoint: flux and relaxation-time gradients to tol."""
     print_case(test="adj_c5_copy", prec=prec)
-    prm, ini = WL.adjoint_channel(nx=200, ny=10)
-    J0, gq0, gt0 = _oracle_adjoint(prm, ini, 200, 10, 2000, 500)
+    prm, ini, (J0, gq0, gt0) = _c5_copy_oracle()
     L = _lattice(prm, ini, 200, 10, prec)
-    J = L.record(2000, 500, 100)
+    J = L.record(20000, 500, 100)
     gq, gt = L.grad()
-    print("J", J, J0, "flux rel", _rel(gq, gq0), "tau", gt, gt0, flush=True)
+    L.close()
+    print("J", J, J0, "flux rel", _rel(gq, gq0), "tau", gt, gt0,
+          "tau rel", np.abs(gt - gt0) / np.abs(gt0), flush=True)
     assert _rel(gq, gq0) < tol
-    np.testing.assert_allclose(gt, gt0, rtol=max(tol, 1e-8) * 10)
+    np.testing.assert_allclose(gt, gt0, rtol=tol)
 
 
 def _taus(prm):
@@ -151,12 +166,17 @@ def test_autograd_backward_after_a_second_forward():
     prob.close()
 
 
+@pytest.mark.timeout(600)
 def test_adjoint_c5_full_size_vs_finite_differences():
     """C5 at its full 1600 x 80 size, 20 000 steps, checkpoint every 500:
     FP32 and FP64 adjoint gradients against central differences of FP64
     forward runs on 16 seeded flux nodes of the downstream half and on both
-    relaxation times.  Step h = 1e-4 relative (the objective's curvature makes
-    the truncation error of h = 1e-3 reach 1e-3 relative at some nodes)."""
+    relaxation times, all to 1e-4.  The flux differences are taken at the
+    configuration's h = 1e-3 (relative), at 5e-4 and at 1e-4, and Richardson's
+    combination (4 D(h/2) - D(h)) / 3 of the first two removes their O(h^2)
+    truncation error: the FP64 adjoint agrees with all of them to 2e-7 (h =
+    1e-3 itself to 3e-8: the curvature of the objective in one q''_k is small
+    at this h, and h = 1e-4 carries more rounding), the FP32 adjoint to 3e-5."""
     nx, ny, steps, ckpt = 1600, 80, 20000, 500
     prm, ini = WL.adjoint_channel()
     x_dev = nx // 2
@@ -177,14 +197,18 @@ def test_adjoint_c5_full_size_vs_finite_differences():
         _, _, _, nm, tout = L.nusselt(x_dev)
         return tout + nm
 
-    fd = []
-    for k in nodes:
-        h = 1e-4 * prm["flux"][k]
-        fp, fm = prm["flux"].copy(), prm["flux"].copy()
-        fp[k] += h
-        fm[k] -= h
-        fd.append((J_of(dict(prm, flux=fp)) - J_of(dict(prm, flux=fm))) / (2 * h))
-    fd = np.array(fd)
+    def fd_flux(rel):
+        out = []
+        for k in nodes:
+            h = rel * prm["flux"][k]
+            fp, fm = prm["flux"].copy(), prm["flux"].copy()
+            fp[k] += h
+            fm[k] -= h
+            out.append((J_of(dict(prm, flux=fp)) - J_of(dict(prm, flux=fm))) / (2 * h))
+        return np.array(out)
+
+    fd3, fd5, fd = fd_flux(1e-3), fd_flux(5e-4), fd_flux(1e-4)
+    fd_rich = (4 * fd5 - fd3) / 3
     c = prm["dx"] / prm["dt"]
     cs2 = c * c / 3
     fdt = []
@@ -195,8 +219,11 @@ def test_adjoint_c5_full_size_vs_finite_differences():
         Jm = J_of(dict(prm, **{key: (tau - h - prm["dt"] / 2) * cs2}))
         fdt.append((Jp - Jm) / (2 * h))
     for prec, (J, gq, gt) in grads.items():
-        e_q = np.abs(gq[nodes] - fd).max() / np.abs(fd).max()
+        def rel(ref):
+            return float(np.abs(gq[nodes] - ref).max() / np.abs(ref).max())
+        e_q, e_q3, e_qr = rel(fd), rel(fd3), rel(fd_rich)
         e_t = np.abs(gt - np.array(fdt)) / np.abs(np.array(fdt))
-        print(prec, "J", J, "flux grad rel err vs FD", e_q, "tau rel err", e_t, flush=True)
-        assert e_q < 1e-4
-        assert e_t.max() < 1e-3
+        print(prec, "J", J, "flux grad rel err vs FD: h=1e-4 %.2e, h=1e-3 %.2e, "
+              "Richardson(1e-3, 5e-4) %.2e" % (e_q, e_q3, e_qr), "tau rel err", e_t, flush=True)
+        assert e_q < 1e-4 and e_q3 < 1e-4 and e_qr < 1e-4
+        assert e_t.max() < 1e-4
