@@ -178,11 +178,11 @@ lbm_status check_desc(const lbm_desc* d, Layout* L, std::string* err) {
     l.offSmall = off; off += align256((size_t)(3 * d->nx + 64 + 4 * d->batch) * sizeof(double));
     // D3Q19_PHASE: phi of the current state, recomputed before every step
     l.offPhi = off; off += d->lattice == LBM_D3Q19_PHASE ? align256((size_t)l.P * l.es) : 0;
-    // D2Q9_PHASE: per-tile step counters and the error word of the
-    // many-steps-per-launch kernel
-    l.offFlags = off; off += d->lattice == LBM_D2Q9_PHASE ? kPersistFlagBytes : 0;
     // the non-finite watch word (first step at which a check saw one)
     l.offWatch = off; off += 256;
+    // D2Q9_PHASE: per-tile step counters and the error word of the
+    // many-steps-per-launch kernel, in the buffer's last 256 bytes
+    l.offFlags = off; off += d->lattice == LBM_D2Q9_PHASE ? kPersistFlagBytes : 0;
     l.total = off;
     *L = l;
     return LBM_OK;
