@@ -227,3 +227,4 @@ def test_adjoint_c5_full_size_vs_finite_differences():
               "Richardson(1e-3, 5e-4) %.2e" % (e_q, e_q3, e_qr), "tau rel err", e_t, flush=True)
         assert e_q < 1e-4 and e_q3 < 1e-4 and e_qr < 1e-4
         assert e_t.max() < 1e-4
+

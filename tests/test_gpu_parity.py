@@ -313,3 +313,37 @@ def test_full_size_bubble_replica_sampled():
     for k in ("phi", "p"):
         assert errs[k] < FP32_TOL, k
     assert u_abs_err(g, o) < u_tol(prm, o)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_relaxation_times_given_directly_equal_those_from_nu_and_alpha(prec):
+    """lbm_set_params_SI with tau and tau_T given directly (the adjoint's
+    parameters) steps the channel exactly as with the nu and alpha they stand
+    for (tau = nu / c_s^2 + dt / 2, Eq. eq_kinematic_viscosity), and the
+    Nusselt diagnostics (which use k = rho c_p alpha) agree; a time not above
+    dt / 2 is refused with LBM_E_TAU."""
+    from paper_2302_04120_amd import lbm
+    nx, ny = 60, 14
+    print_case(test="tau-direct", prec=prec)
+    prm, ini = WL.channel(nx=nx, ny=ny, dx=5e-5, tau_ratio=0.6)
+    c = prm["dx"] / prm["dt"]
+    cs2 = c * c / 3
+    taus = dict(tau=prm["nu"] / cs2 + prm["dt"] / 2, tau_T=prm["alpha"] / cs2 + prm["dt"] / 2)
+    states, nus = [], []
+    for p in (prm, dict(prm, nu=123.0, alpha=456.0, **taus)):  # nu, alpha ignored when tau given
+        L = lbm.Lattice("channel", nx, ny, prec=prec,
+                        bc=(lbm.BC_VEL_INLET, lbm.BC_P_OUTLET, lbm.BC_WALL, lbm.BC_WALL),
+                        flow=True, thermal=True)
+        L.set_params(p)
+        L.init(ini["rho"], ini["ux"], ini["uy"], ini["T"])
+        L.step(150)
+        states.append(L.save_state()[64:])  # the blob header holds a hash of the parameters
+        nus.append(L.nusselt(nx // 2)[3])
+        L.close()
+    assert states[0] == states[1]
+    assert nus[0] == pytest.approx(nus[1], rel=1e-12)
+    L = lbm.Lattice("channel", nx, ny, prec=prec, flow=True, thermal=True)
+    with pytest.raises(lbm.LbmError) as e:
+        L.set_params(dict(prm, tau=0.5 * prm["dt"]))
+    assert e.value.status == lbm.LBM_E_TAU
+    L.close()
