@@ -79,12 +79,19 @@ typedef enum {
     LBM_E_STATE = -4,       /* wrong call order or malformed state blob           */
     LBM_E_NONFINITE = -5,   /* a NaN/Inf was found in the populations             */
     LBM_E_UNSUPPORTED = -6, /* combination not implemented                        */
-    /* informational (> 0): the call succeeded; lbm_last_error says why it is reported */
-    LBM_W_FP32_FORCING = 1  /* lbm_set_params_SI, LBM_D2Q9_PHASE in LBM_FP32_DEV with a body
+    /* informational (> 0, a bit set of the values below): the call succeeded;
+       lbm_last_error says why it is reported */
+    LBM_W_FP32_FORCING = 1, /* lbm_set_params_SI, LBM_D2Q9_PHASE in LBM_FP32_DEV with a body
                                force: the slowest viscous mode (wall distance, or the period)
                                relaxes by nu dt k^2 < 2^-23 per step, so FP32 arithmetic rounds
                                the per-step force increments of long runs away; the parameters
                                are set, and LBM_FP32_DEV_ARITH64 avoids the drift          */
+    LBM_W_MACH = 2          /* lbm_set_params_SI (the inlet profile of a flow channel with a
+                               velocity inlet) or lbm_init_fields / lbm_init_fields3d (the
+                               initial velocity): some |u| dt / dx exceeds 0.3, i.e. the Mach
+                               number |u| / c_s exceeds 0.52, where the equilibria of
+                               Eq. feq_geral, second order in u / c_s, are neither accurate
+                               nor reliably stable (also set for a NaN speed)              */
 } lbm_status;
 
 enum { LBM_D1Q2 = 1, LBM_D1Q3 = 2, LBM_D2Q9_D2Q5 = 3, LBM_D2Q9_PHASE = 4, LBM_D3Q19 = 5,
@@ -195,7 +202,7 @@ LBM_API void lbm_destroy(lbm_ctx* ctx);
  * relaxation time is not above dt/2, LBM_E_ARG for non-positive dx, dt or
  * densities.  Copies the flux / inlet arrays to the device; the caller keeps
  * ownership of p and of the arrays it points to.  May return the
- * informational LBM_W_FP32_FORCING (parameters set). */
+ * informational LBM_W_FP32_FORCING and LBM_W_MACH bits (parameters set). */
 LBM_API lbm_status lbm_set_params_SI(lbm_ctx* ctx, const lbm_params_si* p);
 
 /* 3D lattices: the populations at the equilibria of the given fields, host
@@ -203,7 +210,8 @@ LBM_API lbm_status lbm_set_params_SI(lbm_ctx* ctx, const lbm_params_si* p);
  * required), phi is ignored.  LBM_D3Q19_PHASE: rho_or_p is the pressure (Pa,
  * NULL = 0), phi the order parameter (required), and (phi u) of the previous
  * step is set to phi u.  ux, uy, uz in m/s (NULL = 0).  Resets the step
- * counter.  Requires lbm_set_params_SI first; LBM_E_ARG for 2D lattices. */
+ * counter.  Requires lbm_set_params_SI first; LBM_E_ARG for 2D lattices;
+ * the informational LBM_W_MACH as for lbm_init_fields. */
 LBM_API lbm_status lbm_init_fields3d(lbm_ctx* ctx, const double* rho_or_p, const double* ux,
                                      const double* uy, const double* uz, const double* phi);
 
@@ -217,13 +225,15 @@ LBM_API lbm_status lbm_init_fields3d(lbm_ctx* ctx, const double* rho_or_p, const
  * 1D, required there); phi: order parameter (PHASE, required).  The arrays are
  * read before the call returns.  Also resets the step counter and, for PHASE,
  * sets (phi u) of the previous step to phi u.  LBM_E_STATE without
- * lbm_set_params_SI first; LBM_E_ARG for a missing required field. */
+ * lbm_set_params_SI first; LBM_E_ARG for a missing required field; the
+ * informational LBM_W_MACH (fields set) when an initial speed exceeds 0.3 dx/dt. */
 LBM_API lbm_status lbm_init_fields(lbm_ctx* ctx, const double* rho_or_p, const double* ux,
                            const double* uy, const double* T, const double* phi);
 
 /* Enqueue n time steps (collide + stream + boundary rules, Eq.
  * eq_lattice_boltzmann_geral).  Asynchronous: a non-finite state is reported
- * by lbm_reduce.  When n is at least twice the graph step count (see
+ * by lbm_reduce and, with the step count at which it was first seen, by
+ * lbm_first_nonfinite_step (see lbm_set_nonfinite_check).  When n is at least twice the graph step count (see
  * lbm_set_graph_steps), runs of that many steps are enqueued as one replay
  * of a HIP graph captured from the same kernel launches (bit-identical
  * results, one launch instead of many on small grids); the remainder and

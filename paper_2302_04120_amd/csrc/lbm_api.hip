@@ -197,6 +197,33 @@ lbm_status hip_fail(lbm_ctx* c, hipError_t e, const char* where) {
     return set_err(c, LBM_E_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
 }
 
+// Largest speed in a velocity component, in units of the lattice speed c = dx/dt;
+// a NaN counts as above every limit.
+double speed_over_c(const double* u, long long n, double dt_over_dx) {
+    double m = 0.0;
+    if (!u) return m;
+    for (long long i = 0; i < n; ++i) {
+        const double a = std::fabs(u[i]) * dt_over_dx;
+        if (!(a <= m)) m = a;
+    }
+    return m;
+}
+
+// Speed limit of the warning, in units of c = dx/dt.  The equilibria are expanded
+// to second order in u / c_s and their error grows as (u / c_s)^2; beyond 0.3 c
+// (Ma = u / c_s = 0.52) a step is neither accurate nor reliably stable.
+constexpr double kMachLimit = 0.3;
+
+// Informational LBM_W_MACH when a given speed reaches kMachLimit of c.
+lbm_status mach_status(lbm_ctx* c, double u_over_c, const char* what) {
+    if (u_over_c <= kMachLimit) return LBM_OK;
+    char m[200];
+    std::snprintf(m, sizeof m, "%s: max |u| dt / dx = %.3g above %.2g (Ma = |u| / c_s = %.3g); "
+                  "the second-order equilibria lose accuracy and stability", what, u_over_c,
+                  kMachLimit, u_over_c * std::sqrt(3.0));
+    return set_err(c, LBM_W_MACH, m);
+}
+
 struct DeviceGuard {
     int prev = -1;
     explicit DeviceGuard(int dev) {
@@ -765,16 +792,24 @@ lbm_status lbm_set_params_SI(lbm_ctx* c, const lbm_params_si* p) {
         drop_graphs(c);  // captured kernel arguments are stale now
     }
     c->has_params = true;
+    int warn = 0;
+    std::string msg;
     if (c->fp32_forcing_share > 0.0 && c->fp32_forcing_share < std::ldexp(1.0, -23)) {
         char m[256];
         std::snprintf(m, sizeof m,
                       "parameters set; the slowest viscous mode changes by %.2e of itself per step, "
                       "below FP32 resolution: FP32 arithmetic rounds the body-force increments of "
                       "long runs (LBM_FP32_DEV_ARITH64 keeps them)", c->fp32_forcing_share);
-        set_err(c, LBM_W_FP32_FORCING, m);
-        return LBM_W_FP32_FORCING;
+        warn |= LBM_W_FP32_FORCING;
+        msg = m;
     }
-    return LBM_OK;
+    if (d.lattice == LBM_D2Q9_D2Q5 && (d.flags & LBM_FLAG_FLOW) && d.bc[0] == LBM_BC_VEL_INLET &&
+        mach_status(c, speed_over_c(p->inlet_u, d.ny, dt / dx), "inlet profile") != LBM_OK) {
+        warn |= LBM_W_MACH;
+        msg = msg.empty() ? c->err : msg + "; " + c->err;
+    }
+    if (warn) set_err(c, (lbm_status)warn, msg);
+    return (lbm_status)warn;
 }
 
 lbm_status lbm_init_fields(lbm_ctx* c, const double* rho_or_p, const double* ux, const double* uy,
@@ -831,7 +866,9 @@ lbm_status lbm_init_fields(lbm_ctx* c, const double* rho_or_p, const double* ux,
     if (e != hipSuccess) return hip_fail(c, e, "init");
     c->t = 0;
     c->has_state = true;
-    return LBM_OK;
+    const double r = c->dt / c->dx;
+    return mach_status(c, std::max(speed_over_c(ux, N, r), speed_over_c(uy, N, r)),
+                       "initial velocity");
 }
 
 lbm_status lbm_init_fields3d(lbm_ctx* c, const double* rho_or_p, const double* ux,
@@ -872,7 +909,10 @@ lbm_status lbm_init_fields3d(lbm_ctx* c, const double* rho_or_p, const double* u
     if (e != hipSuccess) return hip_fail(c, e, "init");
     c->t = 0;
     c->has_state = true;
-    return LBM_OK;
+    const double r = c->dt / c->dx;
+    return mach_status(c, std::max({speed_over_c(ux, N, r), speed_over_c(uy, N, r),
+                                    speed_over_c(uz, N, r)}),
+                       "initial velocity");
 }
 
 }  // extern "C"

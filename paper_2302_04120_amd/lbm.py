@@ -28,7 +28,8 @@ LIB_PATH = os.path.join(_HERE, "liblbm.so")
 
 LBM_OK, LBM_E_ARG, LBM_E_TAU, LBM_E_DEVICE, LBM_E_STATE, LBM_E_NONFINITE, LBM_E_UNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6
-LBM_W_FP32_FORCING = 1  # informational: parameters set, see the warning text
+LBM_W_FP32_FORCING = 1  # informational bits: the call succeeded, see the warning text
+LBM_W_MACH = 2
 LBM_D1Q2, LBM_D1Q3, LBM_D2Q9_D2Q5, LBM_D2Q9_PHASE, LBM_D3Q19, LBM_D3Q19_PHASE = 1, 2, 3, 4, 5, 6
 LBM_FP32_DEV, LBM_FP64, LBM_FP32_DEV_ARITH64 = 0, 1, 2
 PRECISIONS = {"fp32": LBM_FP32_DEV, "fp64": LBM_FP64, "fp32_arith64": LBM_FP32_DEV_ARITH64}
@@ -247,10 +248,16 @@ class Lattice:
         _LIVE.add(self)
 
     def _check(self, st, ctx="self"):
+        """Raise LbmError on an error status; an informational one (a bit set
+        of LBM_W_*, the call succeeded) is raised as a RuntimeWarning."""
         if st != LBM_OK:
             c = self.ctx if ctx == "self" else None
             msg = lib().lbm_last_error(c).decode() if c else "(no context)"
+            if st > 0:
+                warnings.warn("liblbm: " + msg, RuntimeWarning, stacklevel=3)
+                return st
             raise LbmError(st, msg)
+        return st
 
     def close(self):
         """Wait for the context's stream, destroy the context (its captured
@@ -285,17 +292,12 @@ class Lattice:
         return (self.batch, self.ny, self.nx)
 
     def set_params(self, prm):
-        """Returns the library status (LBM_OK, or LBM_W_FP32_FORCING, which is
-        also raised as a RuntimeWarning); errors raise LbmError."""
+        """Returns the library status (LBM_OK, or a bit set of LBM_W_FP32_FORCING
+        and LBM_W_MACH, also raised as a RuntimeWarning); errors raise LbmError."""
         P, keep = make_params(prm, self.nx, self.ny)
         st = lib().lbm_set_params_SI(self.ctx, C.byref(P))
         del keep
-        if st == LBM_W_FP32_FORCING:
-            warnings.warn("liblbm: " + lib().lbm_last_error(self.ctx).decode(), RuntimeWarning,
-                          stacklevel=2)
-            return st
-        self._check(st)
-        return st
+        return self._check(st)
 
     def init(self, rho_or_p=None, ux=None, uy=None, T=None, phi=None):
         n = self.batch * self.ny * self.nx
@@ -304,7 +306,7 @@ class Lattice:
                 for a in (rho_or_p, ux, uy, T, phi)]
         for a in arrs:
             assert a is None or a.size == n
-        self._check(lib().lbm_init_fields(self.ctx, *(_ptr(a) for a in arrs)))
+        return self._check(lib().lbm_init_fields(self.ctx, *(_ptr(a) for a in arrs)))
 
     def init3d(self, rho_or_p=None, ux=None, uy=None, uz=None, phi=None):
         """3D lattices: equilibria of rho (D3Q19) or p and phi (phase3d) and u;
@@ -312,7 +314,7 @@ class Lattice:
         arrs = [None if a is None else _f64(np.broadcast_to(np.asarray(a, dtype=np.float64),
                                                             self.shape).reshape(-1))
                 for a in (rho_or_p, ux, uy, uz, phi)]
-        self._check(lib().lbm_init_fields3d(self.ctx, *(_ptr(a) for a in arrs)))
+        return self._check(lib().lbm_init_fields3d(self.ctx, *(_ptr(a) for a in arrs)))
 
     def step(self, n=1):
         self._check(lib().lbm_step(self.ctx, int(n)))

@@ -68,6 +68,17 @@ def accumulated_tol(steps, prec="fp32"):
     return steps * EPS[prec]
 
 
+def fixed_point_tol(rate_per_step, prec="fp32"):
+    """A priori bound, relative to a field's scale, on how far a run that has
+    settled (or is settling) in precision prec can sit from the exact one:
+    each step rounds the field by about one rounding unit EPS / 2 of its scale,
+    while the slowest mode is pulled back toward the exact solution by the
+    fraction rate_per_step per step (viscous: nu dt k^2 with k = pi / H;
+    flushed through a channel: u_m dt / L), so a fixed point of the rounded
+    map lies within (EPS / 2) / rate_per_step of the exact one."""
+    return 0.5 * EPS[prec] / rate_per_step
+
+
 def rel_err(gpu, orc, ref=0.0, scale=None):
     """max |gpu - orc| / max |orc - ref|; ``scale`` overrides the denominator
     when the field's deviation range is smaller than the size of the stored
