@@ -518,15 +518,18 @@ def copy_ceiling(nbytes=4 << 30, reps=7):
         raise RuntimeError("libhbm_probe.so not built: run __graft_entry__.build()")
     L = ctypes.CDLL(lib_path)
     L.hbm_probe_run.argtypes = [ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
-    out = (ctypes.c_double * 7)()
+    L.hbm_probe_name.restype = ctypes.c_char_p
+    n = L.hbm_probe_count()
+    out = (ctypes.c_double * n)()
     rc = L.hbm_probe_run(nbytes, reps, out)
     if rc != 0:
         raise RuntimeError("hbm_probe_run failed: HIP error %d" % rc)
-    names = ("copy_float4_grid1024", "copy_float4_grid8192", "copy_float4_nontemporal_grid16384",
-             "read_float4", "write_float4", "copy_21_planes_step_shape",
-             "copy_21_planes_step_shape_nontemporal")
-    res = {k: out[i] for i, k in enumerate(names)}
-    res["best_copy_frac_of_peak"] = max(res[k] for k in names if k.startswith("copy")) / HBM_PEAK_GBS
+    res = {L.hbm_probe_name(i).decode(): out[i] for i in range(n)}
+    best = {kind: max((k for k in res if k.startswith(kind)), key=res.get)
+            for kind in ("copy", "read", "write", "planes")}
+    res["best"] = {kind: {"probe": k, "GBps": res[k], "frac_of_peak": res[k] / HBM_PEAK_GBS}
+                   for kind, k in best.items()}
+    res["best_copy_frac_of_peak"] = max(res[best["copy"]], res[best["planes"]]) / HBM_PEAK_GBS
     res["buffer_bytes"] = nbytes
     return res
 

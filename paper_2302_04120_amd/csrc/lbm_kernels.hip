@@ -800,28 +800,37 @@ __global__ __launch_bounds__(kTbMaxNx) void k_phase_tb2(PhaseK k, const S* __res
         pn[8] = rm[lxp];
     };
 
-    C cur[kNS], nxt[kNS];
-    // accumulated step-(n+1) state of rows v-3 (A3) .. v+1 (Ap)
-    C A3[kNS], A2[kNS], A1[kNS], A0[kNS], Ap[kNS];
+    // Register slots: slot (u - s1) mod 5 holds row u of
+    //   Ld: the stored state (rows v and v + 1 are live),
+    //   Ac: the accumulated step-(n+1) state (rows v - 3 .. v + 1).
+    // The row loop is unrolled five times, so every slot index is a
+    // compile-time constant and no row is copied between registers.
+    C Ld[5][kNS], Ac[5][kNS];
 #pragma unroll
-    for (int q = 0; q < kNS; ++q) {
-        nxt[q] = C(0);
-        A3[q] = A2[q] = A1[q] = A0[q] = Ap[q] = C(0);
-    }
-    // prologue: phi_n of rows s1 - 1 and s1, state of row s1
+    for (int j = 0; j < 5; ++j)
+#pragma unroll
+        for (int q = 0; q < kNS; ++q) Ld[j][q] = Ac[j][q] = C(0);
+    // prologue: phi_n of rows s1 - 1 and s1, state of row s1 (slot 0)
     if (!walls || s1 > 0) {
-        load_row(s1 - 1, nxt);
-        put_phi(phN, s1 - 1, phi_of(nxt));
+        load_row(s1 - 1, Ld[4]);
+        put_phi(phN, s1 - 1, phi_of(Ld[4]));
     }
-    load_row(s1, cur);
-    put_phi(phN, s1, phi_of(cur));
-    // (the first barrier of the loop orders these LDS writes)
+    load_row(s1, Ld[0]);
+    put_phi(phN, s1, phi_of(Ld[0]));
+    // (the first barrier of the row step orders these LDS writes)
 
-    for (int v = s1; v < e + 3; ++v) {
+    // one row step at row v, v - s1 = J (mod 5)
+    auto row_step = [&](int v, auto Jc) {
+        constexpr int J = decltype(Jc)::value;
+        constexpr int s0 = J % 5, sn = (J + 1) % 5;          // rows v, v + 1
+        constexpr int sm1 = (J + 4) % 5, sm3 = (J + 2) % 5;  // rows v - 1, v - 3
         const bool do_n = v < e1;
         const bool do_load = v + 1 <= lastload;
         const int r = v - 3;
-        if (do_load) load_row(v + 1, nxt);
+        // the load is unconditional (the last rows re-read an in-bounds row),
+        // so the compiler can see that every slot is overwritten before it
+        // is read and keeps only the live rows in registers
+        load_row(do_load ? v + 1 : lastload, Ld[sn]);
         __syncthreads();  // phi_{n+1} of row v - 2 and the previous exchange reads are done
         // ---- step n + 1 at row r = v - 3, straight to memory
         if (r >= a && r < e && out) {
@@ -830,12 +839,12 @@ __global__ __launch_bounds__(kTbMaxNx) void k_phase_tb2(PhaseK k, const S* __res
             gather(phN1, r, pn);
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
-                h[i] = A3[kH + i];
-                z[i] = A3[kZ + i];
+                h[i] = Ac[sm3][kH + i];
+                z[i] = Ac[sm3][kZ + i];
             }
             const PhaseLocal<C> L = phase_local(k, pn, z);
-            phase_collide<S, C>(k, L, h, A3[kLO], z, A3[kPU], A3[kPU + 1], hs, h0hi, h0lo, zst, pux,
-                                puy);
+            phase_collide<S, C>(k, L, h, Ac[sm3][kLO], z, Ac[sm3][kPU], Ac[sm3][kPU + 1], hs, h0hi,
+                                h0lo, zst, pux, puy);
             S* row = B + rowoff(r);
             st(row + npop * P + x, S(pux));
             st(row + (npop + 1) * P + x, S(puy));
@@ -857,7 +866,7 @@ __global__ __launch_bounds__(kTbMaxNx) void k_phase_tb2(PhaseK k, const S* __res
             }
         }
         // ---- phi_n of row v + 1
-        if (do_load) put_phi(phN, v + 1, phi_of(nxt));
+        if (do_load) put_phi(phN, v + 1, phi_of(Ld[sn]));
         __syncthreads();
         // ---- step n at row v
         C hs[9], zst[9], pux = C(0), puy = C(0);
@@ -867,12 +876,12 @@ __global__ __launch_bounds__(kTbMaxNx) void k_phase_tb2(PhaseK k, const S* __res
             gather(phN, v, pn);
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
-                h[i] = cur[kH + i];
-                z[i] = cur[kZ + i];
+                h[i] = Ld[s0][kH + i];
+                z[i] = Ld[s0][kZ + i];
             }
             const PhaseLocal<C> L = phase_local(k, pn, z);
-            phase_collide<S, C>(k, L, h, cur[kLO], z, cur[kPU], cur[kPU + 1], hs, h0hi, h0lo, zst,
-                                pux, puy);
+            phase_collide<S, C>(k, L, h, Ld[s0][kLO], z, Ld[s0][kPU], Ld[s0][kPU + 1], hs, h0hi,
+                                h0lo, zst, pux, puy);
             xch[0][lx] = hs[1];
             xch[1][lx] = hs[3];
             xch[2][lx] = hs[5];
@@ -890,6 +899,9 @@ __global__ __launch_bounds__(kTbMaxNx) void k_phase_tb2(PhaseK k, const S* __res
         if (do_n) {
             // pushes of row v: +y movers to row v + 1, rest and x movers to
             // row v, -y movers to row v - 1 (x movers come from x -+ 1)
+            C(&A0)[kNS] = Ac[s0];
+            C(&Ap)[kNS] = Ac[sn];
+            C(&A1)[kNS] = Ac[sm1];
             A0[kH + 0] = C(h0hi);
             A0[kLO] = C(h0lo);
             A0[kZ + 0] = zst[0];
@@ -899,52 +911,58 @@ __global__ __launch_bounds__(kTbMaxNx) void k_phase_tb2(PhaseK k, const S* __res
             A0[kH + 3] = xch[1][lxp];
             A0[kZ + 1] = xch[6][lxm];
             A0[kZ + 3] = xch[7][lxp];
-            if (walls && v == ny - 1) {  // top wall: +y movers come back reversed
-                A0[kH + 4] = hs[2];
-                A0[kH + 7] = hs[5];
-                A0[kH + 8] = hs[6];
-                A0[kZ + 4] = zst[2];
-                A0[kZ + 7] = zst[5];
-                A0[kZ + 8] = zst[6];
-            } else {
-                Ap[kH + 2] = hs[2];
-                Ap[kH + 5] = xch[2][lxm];
-                Ap[kH + 6] = xch[3][lxp];
-                Ap[kZ + 2] = zst[2];
-                Ap[kZ + 5] = xch[8][lxm];
-                Ap[kZ + 6] = xch[9][lxp];
-            }
-            if (walls && v == 0) {  // bottom wall: -y movers come back reversed
-                A0[kH + 2] = hs[4];
-                A0[kH + 5] = hs[7];
-                A0[kH + 6] = hs[8];
-                A0[kZ + 2] = zst[4];
-                A0[kZ + 5] = zst[7];
-                A0[kZ + 6] = zst[8];
-            } else {
-                A1[kH + 4] = hs[4];
-                A1[kH + 7] = xch[4][lxp];
-                A1[kH + 8] = xch[5][lxm];
-                A1[kZ + 4] = zst[4];
-                A1[kZ + 7] = xch[10][lxp];
-                A1[kZ + 8] = xch[11][lxm];
-            }
+            // +y movers to row v + 1, -y movers to row v - 1.  Written
+            // unconditionally (branch-free, so every slot stays in registers):
+            // at a wall the row beyond it does not exist and its slot is
+            // overwritten before it is read again.
+            Ap[kH + 2] = hs[2];
+            Ap[kH + 5] = xch[2][lxm];
+            Ap[kH + 6] = xch[3][lxp];
+            Ap[kZ + 2] = zst[2];
+            Ap[kZ + 5] = xch[8][lxm];
+            Ap[kZ + 6] = xch[9][lxp];
+            A1[kH + 4] = hs[4];
+            A1[kH + 7] = xch[4][lxp];
+            A1[kH + 8] = xch[5][lxm];
+            A1[kZ + 4] = zst[4];
+            A1[kZ + 7] = xch[10][lxp];
+            A1[kZ + 8] = xch[11][lxm];
+            // top wall: the +y movers come back reversed into the node's -y
+            // slots (below the top row, the next row's pushes overwrite them)
+            A0[kH + 4] = hs[2];
+            A0[kH + 7] = hs[5];
+            A0[kH + 8] = hs[6];
+            A0[kZ + 4] = zst[2];
+            A0[kZ + 7] = zst[5];
+            A0[kZ + 8] = zst[6];
+            // bottom wall: the -y movers come back reversed into the +y slots
+            // (elsewhere those hold the pushes of the row below)
+            const bool bottom = walls && v == 0;
+            A0[kH + 2] = bottom ? hs[4] : A0[kH + 2];
+            A0[kH + 5] = bottom ? hs[7] : A0[kH + 5];
+            A0[kH + 6] = bottom ? hs[8] : A0[kH + 6];
+            A0[kZ + 2] = bottom ? zst[4] : A0[kZ + 2];
+            A0[kZ + 5] = bottom ? zst[7] : A0[kZ + 5];
+            A0[kZ + 6] = bottom ? zst[8] : A0[kZ + 6];
         }
         // ---- phi_{n+1} of row v - 1, whose state is complete now
         {
             const int q = v - 1;
             const bool need = q >= a - 1 && q <= e && (!walls || (q >= 0 && q < ny));
-            if (need) put_phi(phN1, q, phi_of(A1));
+            if (need) put_phi(phN1, q, phi_of(Ac[sm1]));
         }
-        // ---- rotate
-#pragma unroll
-        for (int q = 0; q < kNS; ++q) {
-            A3[q] = A2[q];
-            A2[q] = A1[q];
-            A1[q] = A0[q];
-            A0[q] = Ap[q];
-            cur[q] = nxt[q];
-        }
+    };
+    const int vend = e + 3;
+    for (int v = s1; v < vend; v += 5) {
+        row_step(v, std::integral_constant<int, 0>{});
+        if (v + 1 >= vend) break;
+        row_step(v + 1, std::integral_constant<int, 1>{});
+        if (v + 2 >= vend) break;
+        row_step(v + 2, std::integral_constant<int, 2>{});
+        if (v + 3 >= vend) break;
+        row_step(v + 3, std::integral_constant<int, 3>{});
+        if (v + 4 >= vend) break;
+        row_step(v + 4, std::integral_constant<int, 4>{});
     }
 }
 
