@@ -105,7 +105,10 @@ def test_arith64_rejected_combinations():
 def test_arith64_long_run_tracks_fp64():
     """The layered channel (saturated water and steam at 100 C, 4 x 128 nodes
     between walls) driven from rest for 200 000 steps: the FP32-storage run
-    with FP64 arithmetic stays much closer to the FP64 run than the FP32 run."""
+    with FP64 arithmetic stays much closer to the FP64 run than the FP32 run
+    (measured: max |u - u_fp64| / max |u_fp64| = 1.09e-5 with FP64 arithmetic,
+    9.3e-3 in FP32); the absolute bound 5e-5 holds the mode within a factor
+    of five of that figure."""
     props = {k: v for k, v in WL.TWO_PHASE_SYSTEMS["sat_water_100C"].items()
              if k in ("rho_l", "rho_g", "nu_l", "nu_g", "sigma")}
     prm, ini, _ = WL.layered(nx=4, ny=128, seed=0, dx=5e-6, dt=2.5e-7, W_nodes=6, **props)
@@ -122,4 +125,5 @@ def test_arith64_long_run_tracks_fp64():
     err_a = float(np.abs(u["fp32_arith64"] - u["fp64"]).max()) / scale
     print("max |u - u_fp64| / max|u_fp64|: fp32 %.3e, fp32_arith64 %.3e" % (err32, err_a),
           flush=True)
+    assert err_a < 5e-5
     assert err_a < 0.5 * err32
