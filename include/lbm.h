@@ -396,8 +396,9 @@ LBM_API lbm_status lbm_grad(lbm_ctx* ctx, double dL_dJ, double* dJ_dflux, double
 LBM_API long long lbm_time(const lbm_ctx* ctx);
 
 /* Serialise the state (populations, (phi u), step counter, a hash of the
- * description and parameters) to host memory: the node values of each plane,
- * without the device layout's padding, so equal states give equal blobs.
+ * description and parameters) to host memory: every node value of the state in
+ * the device layout's order, without its padding, so equal states give equal
+ * blobs.
  * Call with host = NULL to get the size in *bytes.  Synchronous. */
 LBM_API lbm_status lbm_save_state(lbm_ctx* ctx, void* host, size_t* bytes);
 

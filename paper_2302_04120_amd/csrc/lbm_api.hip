@@ -50,7 +50,7 @@ double* scratch_address(int device) {
 }
 
 constexpr uint32_t kMagic = 0x534d424cu;  // "LBMS"
-constexpr uint32_t kVersion = 3;
+constexpr uint32_t kVersion = 4;
 
 struct Layout {
     long long N = 0, P = 0;
@@ -272,8 +272,7 @@ hipError_t step_once(lbm_ctx* c) {
                                    aux_qw<S>(c), aux_uin<S>(c), aux_tin<S>(c), flux_mod(c),
                                    c->stream);
     }
-    return launch_phase_step<S>(c->pk, a, b, a + 9 * P, b + 9 * P, a + c->npop * P,
-                                b + c->npop * P, c->desc.prec == LBM_FP32_DEV_ARITH64, c->stream);
+    return launch_phase_step<S>(c->pk, a, b, c->desc.prec == LBM_FP32_DEV_ARITH64, c->stream);
 }
 
 // Whether the next two steps go through the two-step kernel.  Automatic
@@ -854,12 +853,9 @@ lbm_status lbm_init_fields(lbm_ctx* c, const double* rho_or_p, const double* ux,
                                         c->ck.thermal ? (float*)c->popA + 9 * P : nullptr, c->stream);
     } else {
         if (d.prec == LBM_FP64)
-            e = launch_phase_init<double>(c->pk, c->staging, (double*)c->popA,
-                                          (double*)c->popA + 9 * P,
-                                          (double*)c->popA + c->npop * P, c->stream);
+            e = launch_phase_init<double>(c->pk, c->staging, (double*)c->popA, c->stream);
         else
-            e = launch_phase_init<float>(c->pk, c->staging, (float*)c->popA, (float*)c->popA + 9 * P,
-                                         (float*)c->popA + c->npop * P, c->stream);
+            e = launch_phase_init<float>(c->pk, c->staging, (float*)c->popA, c->stream);
     }
     if (e != hipSuccess) return hip_fail(c, e, "init kernel");
     e = hipStreamSynchronize(c->stream);
@@ -953,10 +949,11 @@ lbm_status step_run(lbm_ctx* c, int n) {
 // state plane), recorded against the step count.
 hipError_t watch_now(lbm_ctx* c) {
     const char* a = (c->desc.lattice == LBM_D1Q2 || c->desc.lattice == LBM_D1Q3) ? c->popA : bufA(c);
+    const bool blocked = c->desc.lattice == LBM_D2Q9_PHASE;
     if (c->desc.prec == LBM_FP64)
-        return launch_nonfinite_watch<double>((const double*)a, c->P, c->N, c->nplanes,
+        return launch_nonfinite_watch<double>((const double*)a, c->P, c->N, c->nplanes, blocked,
                                               (unsigned long long)c->t, c->watch, c->stream);
-    return launch_nonfinite_watch<float>((const float*)a, c->P, c->N, c->nplanes,
+    return launch_nonfinite_watch<float>((const float*)a, c->P, c->N, c->nplanes, blocked,
                                          (unsigned long long)c->t, c->watch, c->stream);
 }
 
@@ -1044,8 +1041,8 @@ lbm_status lbm_macros(lbm_ctx* c, unsigned mask, double* out, int out_on_device)
         if (f64) e = launch_chan_macros<double>(c->ck, (double*)a, c->ck.thermal ? (double*)a + 9 * P : nullptr, c->staging, c->stream);
         else e = launch_chan_macros<float>(c->ck, (float*)a, c->ck.thermal ? (float*)a + 9 * P : nullptr, c->staging, c->stream);
     } else if (lat == LBM_D2Q9_PHASE) {
-        if (f64) e = launch_phase_macros<double>(c->pk, (double*)a, (double*)a + 9 * P, c->staging, c->stream);
-        else e = launch_phase_macros<float>(c->pk, (float*)a, (float*)a + 9 * P, c->staging, c->stream);
+        if (f64) e = launch_phase_macros<double>(c->pk, (double*)a, c->staging, c->stream);
+        else e = launch_phase_macros<float>(c->pk, (float*)a, c->staging, c->stream);
     } else {
         e = launch_d1_macros(c->dk, (double*)c->popA, c->staging, P, c->stream);
     }
@@ -1371,11 +1368,36 @@ struct StateHeader {
     uint64_t pop_bytes, phiu_bytes;
 };
 
+// State planes between device and a host blob holding N values per plane:
+// planes with stride P, or for the two-phase D2Q9 state the node blocks with
+// the padding of the last block left out (the full blocks in one copy, then
+// the last block's N mod 64 nodes plane by plane).
+static hipError_t copy_state(lbm_ctx* c, char* host, char* dev, bool to_host) {
+    const size_t es = c->esize, row = (size_t)c->N * es;
+    const hipMemcpyKind kind = to_host ? hipMemcpyDeviceToHost : hipMemcpyHostToDevice;
+    if (c->desc.lattice != LBM_D2Q9_PHASE) {
+        const size_t pitch = (size_t)c->P * es;
+        return to_host ? hipMemcpy2DAsync(host, row, dev, pitch, row, c->nplanes, kind, c->stream)
+                       : hipMemcpy2DAsync(dev, pitch, host, row, row, c->nplanes, kind, c->stream);
+    }
+    const size_t blk = (size_t)kBlk * es, full = (size_t)(c->N / kBlk) * c->nplanes * blk;
+    const size_t rest = (size_t)(c->N % kBlk) * es;
+    hipError_t e = full ? (to_host ? hipMemcpyAsync(host, dev, full, kind, c->stream)
+                                   : hipMemcpyAsync(dev, host, full, kind, c->stream))
+                        : hipSuccess;
+    if (e == hipSuccess && rest)
+        e = to_host ? hipMemcpy2DAsync(host + full, rest, dev + full, blk, rest, c->nplanes, kind,
+                                       c->stream)
+                    : hipMemcpy2DAsync(dev + full, blk, host + full, rest, rest, c->nplanes, kind,
+                                       c->stream);
+    return e;
+}
+
 lbm_status lbm_save_state(lbm_ctx* c, void* host, size_t* bytes) {
     if (!c) return LBM_E_ARG;
     if (!bytes) return set_err(c, LBM_E_ARG, "bytes is NULL");
     // the blob holds the N node values of each plane, without the padding
-    // between planes (which no kernel writes)
+    // between planes or after the last node block (which no kernel writes)
     const size_t row = (size_t)c->N * c->esize;
     const size_t pop = (size_t)c->nplanes * row;
     const size_t pu = 0;  // (phi u) is part of the state buffer
@@ -1391,8 +1413,7 @@ lbm_status lbm_save_state(lbm_ctx* c, void* host, size_t* bytes) {
                    c->desc.prec, c->npop, c->hash, c->t, pop, pu};
     std::memcpy(host, &hd, sizeof hd);
     char* p = (char*)host + sizeof hd;
-    hipError_t e = hipMemcpy2DAsync(p, row, bufA(c), (size_t)c->P * c->esize, row, c->nplanes,
-                                    hipMemcpyDeviceToHost, c->stream);
+    hipError_t e = copy_state(c, p, bufA(c), true);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "save state");
     *bytes = need;
@@ -1421,9 +1442,7 @@ lbm_status lbm_load_state(lbm_ctx* c, const void* host, size_t bytes) {
     c->cur = 0;
     hipError_t e = reset_persist(c);
     if (e == hipSuccess) e = reset_watch(c);
-    if (e == hipSuccess)
-        e = hipMemcpy2DAsync(c->popA, (size_t)c->P * c->esize, p, row, row, c->nplanes,
-                             hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = copy_state(c, const_cast<char*>(p), c->popA, false);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "load state");
     c->t = hd.t;

@@ -12,6 +12,19 @@
 
 namespace lbm {
 
+// Node-block layout of the two-phase D2Q9 state: nodes in blocks of 64
+// consecutive node indices, each block holding all npl values of its nodes,
+// plane by plane (plane i of node n at ((n / 64) npl + i) 64 + n mod 64).  A
+// wave that loads 64 consecutive nodes reads one contiguous block of npl x
+// 256 bytes (FP32), and a row of 256 nodes is one contiguous 21 KB span; in
+// one plane array per population the same wave opens npl separate streams
+// (67 M-node bubble batch, FP32: single step 2.27 -> 2.00 ms, two-step launch
+// 2.31 -> 2.24 ms).  The padding of the last block is never read or written.
+constexpr int kBlk = 64;
+__host__ __device__ __forceinline__ long long bidx(int npl, int i, long long n) {
+    return ((n >> 6) * npl + i) * kBlk + (n & (kBlk - 1));
+}
+
 // Kernel constants of the D2Q9 momentum + D2Q5 temperature step.  Everything
 // is pre-scaled by the host into lattice-normalised form (velocities in units
 // of c, forces as F dt^2/dx, rates as Lambda dt): the dimensional matrix of
@@ -168,10 +181,10 @@ constexpr int kRedBlocks = 256;  // first-pass blocks per replica and field
 template <typename S>
 hipError_t launch_chan_step(const ChanK& k, const S* fc, S* fn, const S* gc, S* gn,
                             const S* qw, const S* uin, const S* tin, double mod, hipStream_t s);
-// arith64: evaluate the step in FP64 on FP32 storage (S = float)
+// one two-phase step from state a to state b (node-block layout); arith64:
+// evaluate the step in FP64 on FP32 storage (S = float)
 template <typename S>
-hipError_t launch_phase_step(const PhaseK& k, const S* hc, S* hn, const S* zc, S* zn, const S* puc,
-                             S* pun, bool arith64, hipStream_t s);
+hipError_t launch_phase_step(const PhaseK& k, const S* a, S* b, bool arith64, hipStream_t s);
 // two steps in one launch; the whole state (populations and (phi u)) moves
 // from buffer a to buffer b; needs phase_tb2_fits.  seg: rows per workgroup
 // (phase_tb2_seg, fixed when the parameters are set)
@@ -185,10 +198,12 @@ int phase_tb2_seg(const PhaseK& k);
 long long phase_tb2_workgroups(const PhaseK& k, int seg);
 template <typename S>
 hipError_t launch_phase_tb2(const PhaseK& k, const S* a, S* b, int seg, hipStream_t s);
-// *first = min(*first, t) if any node value of the nplanes planes is not finite
+// *first = min(*first, t) if any node value of the nplanes planes is not
+// finite (plane stride P, or the node-block layout when blocked)
 template <typename S>
 hipError_t launch_nonfinite_watch(const S* pops, long long P, long long N, int nplanes,
-                                  unsigned long long t, unsigned long long* first, hipStream_t s);
+                                  bool blocked, unsigned long long t, unsigned long long* first,
+                                  hipStream_t s);
 // many steps in one cooperative launch for grids that split into at most
 // kPersistMaxTiles tiles of 512 threads (phase_persist_fits); flags: one step
 // counter per tile (zeroed with the state, advanced to epoch0 + steps), err:
@@ -207,8 +222,7 @@ hipError_t launch_d1(const D1K& k, double* g, int nsteps, hipStream_t s);
 template <typename S>
 hipError_t launch_chan_init(const ChanK& k, const double* fields, S* f, S* g, hipStream_t s);
 template <typename S>
-hipError_t launch_phase_init(const PhaseK& k, const double* fields, S* h, S* z, S* phiu,
-                             hipStream_t s);
+hipError_t launch_phase_init(const PhaseK& k, const double* fields, S* a, hipStream_t s);
 hipError_t launch_d1_init(const D1K& k, const double* T, double* g, hipStream_t s);
 
 // D3Q19 (lbm_d3q19.hip)
@@ -235,8 +249,7 @@ hipError_t launch_p3_macros(const P3K& k, const S* a, S* phi, double* out, hipSt
 template <typename S>
 hipError_t launch_chan_macros(const ChanK& k, const S* f, const S* g, double* out, hipStream_t s);
 template <typename S>
-hipError_t launch_phase_macros(const PhaseK& k, const S* h, const S* z, double* out,
-                               hipStream_t s);
+hipError_t launch_phase_macros(const PhaseK& k, const S* a, double* out, hipStream_t s);
 hipError_t launch_d1_macros(const D1K& k, const double* g, double* out, long long P,
                             hipStream_t s);
 

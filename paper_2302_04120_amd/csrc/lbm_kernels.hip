@@ -247,9 +247,9 @@ __global__ __launch_bounds__(64 * CTY) void k_chan_step(ChanK k, const S* __rest
 
 // ---------------------------------------------------------------------------
 // Two-phase model: conservative Allen-Cahn h_i (BGK) + pressure z_i (MRT/BGK)
-// Buffer planes: 0-8 h_i, 9-17 z_i, then (FP32 storage only) the low part of
-// h_0, then (phi u) of the previous step (2 planes): npop = 19 (FP32) or 18
-// (FP64) population planes plus 2.
+// State planes (node-block layout, PhasePlanes): 0-8 h_i, 9-17 z_i, then
+// (FP32 storage only) the low part of h_0, then (phi u) of the previous step
+// (2 planes): npop = 19 (FP32) or 18 (FP64) population planes plus 2.
 // ---------------------------------------------------------------------------
 
 #ifndef LBM_PHASE_TY
@@ -263,6 +263,19 @@ constexpr int TX = 64, TY = LBM_PHASE_TY;
 // 2.82 ms at 8 waves per SIMD, 2.56 ms at 4).  The FP64 kernel's register
 // use already gives 4 waves per SIMD.
 constexpr unsigned kPhaseLdsReserve = 36864;
+// Planes of the two-phase D2Q9 state in the node-block layout (bidx): h_0..h_8,
+// z_0..z_8, in FP32 the low part of h_0, then (phi u)_x and (phi u)_y.
+template <typename S>
+struct PhasePlanes {
+    static constexpr bool RMASS = std::is_same<S, float>::value;
+    static constexpr int NPL = RMASS ? 21 : 20;
+    static constexpr int H = 0, Z = 9, LO = 18, PU = RMASS ? 19 : 18;
+};
+template <typename S>
+__device__ __forceinline__ long long pidx(int i, long long n) {
+    return bidx(PhasePlanes<S>::NPL, i, n);
+}
+
 // phi of a node from its stored h_i, Eq. zero_moment_h (rest population with
 // its low part).  One summation order everywhere, so that every kernel sees
 // the same phi for the same populations.
@@ -460,20 +473,17 @@ __device__ __forceinline__ void phase_collide(const PhaseK& k, const PhaseLocal<
 // One tile of the single step (every thread of the block calls it; it has
 // one barrier).  Returns early for threads without a node, after the barrier.
 template <typename S, typename C, bool MACROS, int TX, int TY>
-__device__ __forceinline__ void phase_tile(const PhaseK& k, int tile, const S* __restrict__ hc,
-                                           S* __restrict__ hn, const S* __restrict__ zc,
-                                           S* __restrict__ zn, const S* __restrict__ puc,
-                                           S* __restrict__ pun, double* __restrict__ mout,
+__device__ __forceinline__ void phase_tile(const PhaseK& k, int tile, const S* __restrict__ A,
+                                           S* __restrict__ B, double* __restrict__ mout,
                                            C (&sphi)[TY + 2][TX + 2]) {
     constexpr bool RMASS = std::is_same<S, float>::value;
+    using PL = PhasePlanes<S>;
     const int nx = k.nx, ny = k.ny;
-    const long long P = k.P;
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int gx = (nx + TX - 1) / TX, gy = (ny + TY - 1) / TY;
     const int b = tile / (gx * gy), r = tile - b * gx * gy;
     const int x0 = (r % gx) * TX, y0 = (r / gx) * TY;
     const long long base = (long long)b * ny * nx;
-    const S* hlo_c = RMASS ? hc + 18 * P : nullptr;  // h_0 low part (plane 18)
     auto gxw = [&](int gx) { return ((gx % nx) + nx) % nx; };
     auto gyw = [&](int gy) {
         if (k.bcy) return gy < 0 ? 0 : (gy >= ny ? ny - 1 : gy);  // mirror ghost at walls
@@ -487,14 +497,14 @@ __device__ __forceinline__ void phase_tile(const PhaseK& k, int tile, const S* _
     const long long n = base + (long long)gyw(y) * nx + gxw(x);  // == own node when valid
     C h[9], z[9], hlo = C(0), pu0 = C(0), pu1 = C(0);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) h[i] = C(hc[i * P + n]);
-    if (RMASS) hlo = C(hlo_c[n]);
+    for (int i = 0; i < 9; ++i) h[i] = C(A[pidx<S>(PL::H + i, n)]);
+    if (RMASS) hlo = C(A[pidx<S>(PL::LO, n)]);
     if (valid) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) z[i] = C(zc[i * P + n]);
+        for (int i = 0; i < 9; ++i) z[i] = C(A[pidx<S>(PL::Z + i, n)]);
         if constexpr (!MACROS) {
-            pu0 = C(puc[n]);
-            pu1 = C(puc[P + n]);
+            pu0 = C(A[pidx<S>(PL::PU, n)]);
+            pu1 = C(A[pidx<S>(PL::PU + 1, n)]);
         }
     }
     int hx = -2, hy = -2;
@@ -510,8 +520,8 @@ __device__ __forceinline__ void phase_tile(const PhaseK& k, int tile, const S* _
         const long long nn = base + (long long)gyw(y0 + hy) * nx + gxw(x0 + hx);
         C hr[9];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) hr[i] = C(hc[i * P + nn]);
-        ring = phi_sum(hr, RMASS ? C(hlo_c[nn]) : C(0));
+        for (int i = 0; i < 9; ++i) hr[i] = C(A[pidx<S>(PL::H + i, nn)]);
+        ring = phi_sum(hr, RMASS ? C(A[pidx<S>(PL::LO, nn)]) : C(0));
     }
     sphi[ty + 1][tx + 1] = phi_sum(h, hlo);
     if (hx > -2) sphi[hy + 1][hx + 1] = ring;
@@ -537,39 +547,37 @@ __device__ __forceinline__ void phase_tile(const PhaseK& k, int tile, const S* _
         C hs[9], zst[9], pux, puy;
         S h0hi, h0lo;
         phase_collide<S, C>(k, L, h, hlo, z, pu0, pu1, hs, h0hi, h0lo, zst, pux, puy);
-        st(pun + n, S(pux));
-        st(pun + P + n, S(puy));
+        st(B + pidx<S>(PL::PU, n), S(pux));
+        st(B + pidx<S>(PL::PU + 1, n), S(puy));
         // ---- streaming of h and z: x periodic; y periodic or halfway
         //      bounce-back walls
-        st(hn + n, h0hi);
-        if constexpr (RMASS) st(hn + 18 * P + n, h0lo);
-        st(zn + n, S(zst[0]));
+        st(B + pidx<S>(PL::H, n), h0hi);
+        if constexpr (RMASS) st(B + pidx<S>(PL::LO, n), h0lo);
+        st(B + pidx<S>(PL::Z, n), S(zst[0]));
 #pragma unroll
         for (int i = 1; i < 9; ++i) {
             const int tyd = y + EY[i];
             if (k.bcy && (tyd < 0 || tyd >= ny)) {
-                st(hn + OPP[i] * P + n, S(hs[i]));
-                st(zn + OPP[i] * P + n, S(zst[i]));
+                st(B + pidx<S>(PL::H + OPP[i], n), S(hs[i]));
+                st(B + pidx<S>(PL::Z + OPP[i], n), S(zst[i]));
             } else {
                 const long long d = base + (long long)wrap(tyd, ny) * nx + wrap(x + EX[i], nx);
-                st(hn + i * P + d, S(hs[i]));
-                st(zn + i * P + d, S(zst[i]));
+                st(B + pidx<S>(PL::H + i, d), S(hs[i]));
+                st(B + pidx<S>(PL::Z + i, d), S(zst[i]));
             }
         }
     }
 }
 
 template <typename S, typename C, bool MACROS, int TX = lbm::TX, int TY = lbm::TY>
-__global__ __launch_bounds__(TX * TY) void k_phase(PhaseK k, const S* __restrict__ hc,
-                                               S* __restrict__ hn, const S* __restrict__ zc,
-                                               S* __restrict__ zn, const S* __restrict__ puc,
-                                               S* __restrict__ pun, double* __restrict__ mout) {
+__global__ __launch_bounds__(TX * TY) void k_phase(PhaseK k, const S* __restrict__ A,
+                                               S* __restrict__ B, double* __restrict__ mout) {
     static_assert(2 * (TX + 2) + 2 * TY <= TX * TY, "the ring must fit in one pass of the block");
     __shared__ C sphi[TY + 2][TX + 2];
     const int gx = (k.nx + TX - 1) / TX, gy = (k.ny + TY - 1) / TY;
     int tile;
     if (!xcd_tile(gx * gy * k.batch, tile)) return;  // whole workgroup, before any barrier
-    phase_tile<S, C, MACROS, TX, TY>(k, tile, hc, hn, zc, zn, puc, pun, mout, sphi);
+    phase_tile<S, C, MACROS, TX, TY>(k, tile, A, B, mout, sphi);
 }
 
 // ---------------------------------------------------------------------------
@@ -596,8 +604,6 @@ __global__ __launch_bounds__(TX * TY) void k_phase_persist(PhaseK k, S* __restri
     static_assert(2 * (TX + 2) + 2 * TY <= TX * TY, "the ring of a tile needs a thread per node");
     __shared__ C sphi[TY + 2][TX + 2];
     __shared__ int bad;
-    const long long P = k.P;
-    const int npop = std::is_same<S, float>::value ? 19 : 18;
     const int gx = (k.nx + TX - 1) / TX, gy = (k.ny + TY - 1) / TY;
     const int tile = blockIdx.x;
     const int b = tile / (gx * gy), r = tile - b * gx * gy;
@@ -658,8 +664,7 @@ __global__ __launch_bounds__(TX * TY) void k_phase_persist(PhaseK k, S* __restri
         if (bad) return;  // uniform: every thread read it after the barrier
         const S* a = (s & 1) ? B : A;
         S* o = (s & 1) ? A : B;
-        phase_tile<S, C, false, TX, TY>(k, tile, a, o, a + 9 * P, o + 9 * P, a + npop * P,
-                                        o + npop * P, (double*)nullptr, sphi);
+        phase_tile<S, C, false, TX, TY>(k, tile, a, o, (double*)nullptr, sphi);
         // Every wave waits until its stores have reached the L2 (vmcnt counts
         // stores on this GPU), the barrier orders them before the first
         // lane's device-scope release, whose L2 write-back then carries the
@@ -720,9 +725,8 @@ __global__ __launch_bounds__(kTbMaxNx) void k_phase_tb2(PhaseK k, const S* __res
                                                         S* __restrict__ B, int seg) {
     using C = S;
     constexpr bool RMASS = std::is_same<S, float>::value;
+    using PL = PhasePlanes<S>;
     const int nx = k.nx, ny = k.ny;
-    const long long P = k.P;
-    const int npop = RMASS ? 19 : 18;
     const int nseg = (ny + seg - 1) / seg;
     const int ntx = TILED ? (nx + kTbTileOut - 1) / kTbTileOut : 1;
     int w;
@@ -737,10 +741,9 @@ __global__ __launch_bounds__(kTbMaxNx) void k_phase_tb2(PhaseK k, const S* __res
     const int e1 = walls ? min(e + 2, ny) : e + 2;  // end of step-n rows
     const int lastload = walls ? min(e1, ny - 1) : e1;
     const long long base = (long long)b * ny * nx;
-    // lane offsets are unsigned 32-bit and row bases uniform, so memory
-    // accesses take the scalar-base + vector-offset form.  x, xm, xp: the
-    // lane's column and its periodic neighbours in memory; lx, lxm, lxp: the
-    // lane and its neighbour lanes in LDS (the same unless TILED).
+    // x, xm, xp: the lane's column and its periodic neighbours in memory; lx,
+    // lxm, lxp: the lane and its neighbour lanes in LDS (the same unless
+    // TILED).
     const unsigned lx = threadIdx.x;
     unsigned x = lx;
     bool out = true;  // this lane stores its step-(n + 1) result
@@ -765,14 +768,14 @@ __global__ __launch_bounds__(kTbMaxNx) void k_phase_tb2(PhaseK k, const S* __res
         return base + (long long)r * nx;
     };
     auto load_row = [&](int v, C (&s)[kNS]) {
-        const S* row = A + rowoff(v);
+        const long long n = rowoff(v) + x;
 #pragma unroll
-        for (int i = 0; i < 9; ++i) s[kH + i] = C(row[i * P + x]);
+        for (int i = 0; i < 9; ++i) s[kH + i] = C(A[pidx<S>(PL::H + i, n)]);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) s[kZ + i] = C(row[(9 + i) * P + x]);
-        s[kLO] = RMASS ? C(row[18 * P + x]) : C(0);
-        s[kPU] = C(row[npop * P + x]);
-        s[kPU + 1] = C(row[(npop + 1) * P + x]);
+        for (int i = 0; i < 9; ++i) s[kZ + i] = C(A[pidx<S>(PL::Z + i, n)]);
+        s[kLO] = RMASS ? C(A[pidx<S>(PL::LO, n)]) : C(0);
+        s[kPU] = C(A[pidx<S>(PL::PU, n)]);
+        s[kPU + 1] = C(A[pidx<S>(PL::PU + 1, n)]);
     };
     auto phi_of = [&](const C (&s)[kNS]) {
         const C hh[9] = {s[0], s[1], s[2], s[3], s[4], s[5], s[6], s[7], s[8]};
@@ -845,23 +848,23 @@ __global__ __launch_bounds__(kTbMaxNx) void k_phase_tb2(PhaseK k, const S* __res
             const PhaseLocal<C> L = phase_local(k, pn, z);
             phase_collide<S, C>(k, L, h, Ac[sm3][kLO], z, Ac[sm3][kPU], Ac[sm3][kPU + 1], hs, h0hi,
                                 h0lo, zst, pux, puy);
-            S* row = B + rowoff(r);
-            st(row + npop * P + x, S(pux));
-            st(row + (npop + 1) * P + x, S(puy));
-            st(row + x, h0hi);
-            if constexpr (RMASS) st(row + 18 * P + x, h0lo);
-            st(row + 9 * P + x, S(zst[0]));
+            const long long n = rowoff(r) + x;
+            st(B + pidx<S>(PL::PU, n), S(pux));
+            st(B + pidx<S>(PL::PU + 1, n), S(puy));
+            st(B + pidx<S>(PL::H, n), h0hi);
+            if constexpr (RMASS) st(B + pidx<S>(PL::LO, n), h0lo);
+            st(B + pidx<S>(PL::Z, n), S(zst[0]));
 #pragma unroll
             for (int i = 1; i < 9; ++i) {
                 const int ryd = r + EY[i];
                 if (walls && (ryd < 0 || ryd >= ny)) {
-                    st(row + OPP[i] * P + x, S(hs[i]));
-                    st(row + (9 + OPP[i]) * P + x, S(zst[i]));
+                    st(B + pidx<S>(PL::H + OPP[i], n), S(hs[i]));
+                    st(B + pidx<S>(PL::Z + OPP[i], n), S(zst[i]));
                 } else {
                     const unsigned xd = EX[i] == 0 ? x : (EX[i] > 0 ? xp : xm);
-                    S* drow = B + rowoff(ryd);
-                    st(drow + i * P + xd, S(hs[i]));
-                    st(drow + (9 + i) * P + xd, S(zst[i]));
+                    const long long d = rowoff(ryd) + xd;
+                    st(B + pidx<S>(PL::H + i, d), S(hs[i]));
+                    st(B + pidx<S>(PL::Z + i, d), S(zst[i]));
                 }
             }
         }
@@ -1049,9 +1052,9 @@ __global__ void k_chan_init(ChanK k, const double* __restrict__ fld, S* __restri
 }
 
 template <typename S>
-__global__ void k_phase_init(PhaseK k, const double* __restrict__ fld, S* __restrict__ h,
-                             S* __restrict__ z, S* __restrict__ phiu) {
+__global__ void k_phase_init(PhaseK k, const double* __restrict__ fld, S* __restrict__ A) {
     constexpr bool RMASS = std::is_same<S, float>::value;
+    using PL = PhasePlanes<S>;
     const long long N = (long long)k.batch * k.nx * k.ny;
     const long long P = k.P;
     for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < N;
@@ -1064,20 +1067,21 @@ __global__ void k_phase_init(PhaseK k, const double* __restrict__ fld, S* __rest
         for (int i = 1; i < 9; ++i) {
             const double eu = EX[i] * ux + EY[i] * uy;
             const S hv = S(phi * wgt<double>(i) * (1 + 3 * eu));
-            h[i * P + n] = hv;
+            A[pidx<S>(PL::H + i, n)] = hv;
             hsum += double(hv);
         }
         const double h0 = phi - hsum;  // rest population closes the node's phi exactly
         const S hi = S(h0);
-        h[n] = hi;
-        if (RMASS) h[18 * P + n] = S(h0 - double(hi));
+        A[pidx<S>(PL::H, n)] = hi;
+        if (RMASS) A[pidx<S>(PL::LO, n)] = S(h0 - double(hi));
         for (int i = 0; i < 9; ++i) {
             const double eu = EX[i] * ux + EY[i] * uy;
             const double w = wgt<double>(i);
-            z[i * P + n] = S(ph * (i == 0 ? w - 1 : w) + rho * w * (3 * eu + 4.5 * eu * eu - 1.5 * uu));
+            A[pidx<S>(PL::Z + i, n)] =
+                S(ph * (i == 0 ? w - 1 : w) + rho * w * (3 * eu + 4.5 * eu * eu - 1.5 * uu));
         }
-        phiu[n] = S(phi * ux);
-        phiu[P + n] = S(phi * uy);
+        A[pidx<S>(PL::PU, n)] = S(phi * ux);
+        A[pidx<S>(PL::PU + 1, n)] = S(phi * uy);
     }
 }
 
@@ -1170,16 +1174,18 @@ __global__ __launch_bounds__(256) void k_reduce1(int lattice, ChanK ck, PhaseK p
     double v[4] = {0, 0, 0, 0};
     for (long long j = blockIdx.x * 256LL + threadIdx.x; j < M; j += 256LL * gridDim.x) {
         const long long n = base + j;
+        // value of plane i at node n (the two-phase D2Q9 state is node-blocked)
+        auto at = [&](int i) {
+            return double(lattice == LBM_D2Q9_PHASE ? pops[pidx<S>(i, n)] : pops[i * P + n]);
+        };
         double cnt = 0;
-        for (int i = 0; i < npop; ++i) {
-            const double a = double(pops[i * P + n]);
-            if (!isfinite(a)) cnt += 1;
-        }
+        for (int i = 0; i < npop; ++i)
+            if (!isfinite(at(i))) cnt += 1;
         v[3] += cnt;
         if (lattice == LBM_D2Q9_PHASE) {
             double a = 0;
-            for (int i = 0; i < 9; ++i) a += double(pops[i * P + n]);
-            if (std::is_same<S, float>::value) a += double(pops[18 * P + n]);
+            for (int i = 0; i < 9; ++i) a += at(PhasePlanes<S>::H + i);
+            if (std::is_same<S, float>::value) a += at(PhasePlanes<S>::LO);
             v[1] += a;
             v[0] += pk.rho_g + a * (pk.rho_l - pk.rho_g);
         } else if (lattice == LBM_D3Q19_PHASE) {
@@ -1210,16 +1216,18 @@ __global__ __launch_bounds__(256) void k_reduce1(int lattice, ChanK ck, PhaseK p
     block_sums<4>(v, partial + (long long)b * 4 * kRedBlocks + blockIdx.x, kRedBlocks);
 }
 
-// Non-finite watch: every node value of planes [0, nplanes) (plane stride P,
-// N nodes) that is NaN or infinite lowers *first to t.  Grid (blocks, planes).
+// Non-finite watch: every node value of planes [0, nplanes) (N nodes; plane
+// stride P, or the node-block layout of nplanes planes when blocked) that is
+// NaN or infinite lowers *first to t.  Grid (blocks, planes).
 template <typename S>
 __global__ __launch_bounds__(256) void k_nonfinite_watch(const S* __restrict__ pops, long long P,
-                                                         long long N, unsigned long long t,
+                                                         long long N, int blocked,
+                                                         unsigned long long t,
                                                          unsigned long long* __restrict__ first) {
-    const S* plane = pops + (long long)blockIdx.y * P;
+    const int i = blockIdx.y;
     bool bad = false;
     for (long long n = blockIdx.x * 256LL + threadIdx.x; n < N; n += 256LL * gridDim.x)
-        bad |= !isfinite(plane[n]);
+        bad |= !isfinite(pops[blocked ? bidx(gridDim.y, i, n) : i * P + n]);
     if (bad) atomicMin(first, t);
 }
 
@@ -1326,8 +1334,8 @@ hipError_t launch_chan_step(const ChanK& k, const S* fc, S* fn, const S* gc, S* 
 // or, for nx in {4, 8, 16, 32}, nx x (512 / nx); half as many rows for FP32
 // steps.
 template <typename S, typename C, bool MACROS>
-hipError_t launch_phase_kernel(const PhaseK& k, const S* hc, S* hn, const S* zc, S* zn,
-                               const S* puc, S* pun, double* out, unsigned lds, hipStream_t s) {
+hipError_t launch_phase_kernel(const PhaseK& k, const S* a, S* b, double* out, unsigned lds,
+                               hipStream_t s) {
     auto ntiles = [&](int tx, int ty) {
         return (long long)((k.nx + tx - 1) / tx) * ((k.ny + ty - 1) / ty) * k.batch;
     };
@@ -1335,7 +1343,7 @@ hipError_t launch_phase_kernel(const PhaseK& k, const S* hc, S* hn, const S* zc,
     auto go = [&](auto kern, int tx, int ty) {
         const long long tiles = ntiles(tx, ty);
         dim3 blk(tx, ty), grd(unsigned((tiles + kXCD - 1) / kXCD * kXCD));
-        hipLaunchKernelGGL(kern, grd, blk, lds, s, k, hc, hn, zc, zn, puc, pun, out);
+        hipLaunchKernelGGL(kern, grd, blk, lds, s, k, a, b, out);
         return hipGetLastError();
     };
     if (half) {
@@ -1424,15 +1432,13 @@ hipError_t launch_phase_persist(const PhaseK& k, S* A, S* B, int nsteps, unsigne
 }
 
 template <typename S>
-hipError_t launch_phase_step(const PhaseK& k, const S* hc, S* hn, const S* zc, S* zn, const S* puc,
-                             S* pun, bool arith64, hipStream_t s) {
+hipError_t launch_phase_step(const PhaseK& k, const S* a, S* b, bool arith64, hipStream_t s) {
     const unsigned lds = std::is_same<S, float>::value ? kPhaseLdsReserve : 0u;  // half tiles
     if (arith64) {  // FP32 storage, every step evaluated in FP64
         if (!std::is_same<S, float>::value) return hipErrorInvalidValue;
-        return launch_phase_kernel<S, double, false>(k, hc, hn, zc, zn, puc, pun, (double*)nullptr,
-                                                     lds, s);
+        return launch_phase_kernel<S, double, false>(k, a, b, (double*)nullptr, lds, s);
     }
-    return launch_phase_kernel<S, S, false>(k, hc, hn, zc, zn, puc, pun, (double*)nullptr, lds, s);
+    return launch_phase_kernel<S, S, false>(k, a, b, (double*)nullptr, lds, s);
 }
 
 // The two-step kernel takes a whole row per workgroup when nx is a multiple
@@ -1519,11 +1525,9 @@ hipError_t launch_chan_init(const ChanK& k, const double* fields, S* f, S* g, hi
 }
 
 template <typename S>
-hipError_t launch_phase_init(const PhaseK& k, const double* fields, S* h, S* z, S* phiu,
-                             hipStream_t s) {
+hipError_t launch_phase_init(const PhaseK& k, const double* fields, S* a, hipStream_t s) {
     const long long N = (long long)k.batch * k.nx * k.ny;
-    hipLaunchKernelGGL(k_phase_init<S>, dim3(grid1(N, 256)), dim3(256), 0, s, k, fields, h, z,
-                       phiu);
+    hipLaunchKernelGGL(k_phase_init<S>, dim3(grid1(N, 256)), dim3(256), 0, s, k, fields, a);
     return hipGetLastError();
 }
 
@@ -1541,10 +1545,8 @@ hipError_t launch_chan_macros(const ChanK& k, const S* f, const S* g, double* ou
 }
 
 template <typename S>
-hipError_t launch_phase_macros(const PhaseK& k, const S* h, const S* z, double* out,
-                               hipStream_t s) {
-    return launch_phase_kernel<S, double, true>(k, h, (S*)nullptr, z, (S*)nullptr,
-                                                (const S*)nullptr, (S*)nullptr, out, 0u, s);
+hipError_t launch_phase_macros(const PhaseK& k, const S* a, double* out, hipStream_t s) {
+    return launch_phase_kernel<S, double, true>(k, a, (S*)nullptr, out, 0u, s);
 }
 
 hipError_t launch_d1_macros(const D1K& k, const double* g, double* out, long long P,
@@ -1573,10 +1575,11 @@ hipError_t launch_reduce(int lattice, const ChanK& ck, const PhaseK& pk, const D
 
 template <typename S>
 hipError_t launch_nonfinite_watch(const S* pops, long long P, long long N, int nplanes,
-                                  unsigned long long t, unsigned long long* first, hipStream_t s) {
+                                  bool blocked, unsigned long long t, unsigned long long* first,
+                                  hipStream_t s) {
     const long long blocks = std::min<long long>((N + 255) / 256, 1024);
     hipLaunchKernelGGL(k_nonfinite_watch<S>, dim3(unsigned(blocks), nplanes), dim3(256), 0, s,
-                       pops, P, N, t, first);
+                       pops, P, N, int(blocked), t, first);
     return hipGetLastError();
 }
 
@@ -1595,23 +1598,20 @@ hipError_t launch_nusselt(const ChanK& k, const S* f, const S* g, const S* qw, d
 #define LBM_INST(S)                                                                              \
     template hipError_t launch_chan_step<S>(const ChanK&, const S*, S*, const S*, S*, const S*, \
                                             const S*, const S*, double, hipStream_t);             \
-    template hipError_t launch_phase_step<S>(const PhaseK&, const S*, S*, const S*, S*,          \
-                                             const S*, S*, bool, hipStream_t);                    \
+    template hipError_t launch_phase_step<S>(const PhaseK&, const S*, S*, bool, hipStream_t);    \
     template hipError_t launch_phase_tb2<S>(const PhaseK&, const S*, S*, int, hipStream_t);      \
     template int phase_tb2_seg<S>(const PhaseK&);                                                \
     template hipError_t launch_phase_persist<S>(const PhaseK&, S*, S*, int, unsigned, unsigned*,  \
                                                 unsigned*, bool, hipStream_t);                    \
     template hipError_t launch_chan_init<S>(const ChanK&, const double*, S*, S*, hipStream_t);   \
-    template hipError_t launch_phase_init<S>(const PhaseK&, const double*, S*, S*, S*,           \
-                                             hipStream_t);                                        \
+    template hipError_t launch_phase_init<S>(const PhaseK&, const double*, S*, hipStream_t);    \
     template hipError_t launch_chan_macros<S>(const ChanK&, const S*, const S*, double*,         \
                                               hipStream_t);                                       \
-    template hipError_t launch_phase_macros<S>(const PhaseK&, const S*, const S*, double*,       \
-                                               hipStream_t);                                      \
+    template hipError_t launch_phase_macros<S>(const PhaseK&, const S*, double*, hipStream_t);  \
     template hipError_t launch_reduce<S>(int, const ChanK&, const PhaseK&, const D1K&,           \
                                          const D3K&, const P3K&, const S*, int, double*,          \
                                          double*, hipStream_t);                                   \
-    template hipError_t launch_nonfinite_watch<S>(const S*, long long, long long, int,           \
+    template hipError_t launch_nonfinite_watch<S>(const S*, long long, long long, int, bool,     \
                                                   unsigned long long, unsigned long long*,       \
                                                   hipStream_t);                                   \
     template hipError_t launch_nusselt<S>(const ChanK&, const S*, const S*, const S*, double,    \
