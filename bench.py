@@ -644,6 +644,14 @@ def main():
         l64 = r64["kernel_ms"] * spl * 1e-3
         extras["fp64_hbm_frac"] = BYTES_PER_LU["fp64"] * r64["nodes"] / l64 / 1e9 / HBM_PEAK_GBS
         extras["fp64_step_equivalent_GBps"] = BYTES_PER_LU["fp64"] * r64["nodes"] * spl / l64 / 1e9
+        log("bench: single-step kernel on the same workload")
+        r1 = run_gpu(args.batch, 100, 6, "fp32", fusion=1)
+        extras["single_step_fp32"] = dict(
+            mlups=r1["nodes"] * 100 / (r1["ev_ms"] * 1e-3) / 1e6, kernel_ms=r1["kernel_ms"],
+            hbm_GBps=BYTES_PER_LU["fp32"] * r1["nodes"] / (r1["kernel_ms"] * 1e-3) / 1e9,
+            hbm_frac=BYTES_PER_LU["fp32"] * r1["nodes"] / (r1["kernel_ms"] * 1e-3) / 1e9
+            / HBM_PEAK_GBS,
+            kernel="k_phase<float, float, false, 64, 4>")
         log("bench: paper-sized leg (4 replicas)")
         r4 = run_gpu(4, 1000, 50, args.prec)
         extras["paper_config_batch4_mlups"] = r4["nodes"] * 1000 / r4["wall"] / 1e6
