@@ -949,7 +949,7 @@ lbm_status step_run(lbm_ctx* c, int n) {
 // state plane), recorded against the step count.
 hipError_t watch_now(lbm_ctx* c) {
     const char* a = (c->desc.lattice == LBM_D1Q2 || c->desc.lattice == LBM_D1Q3) ? c->popA : bufA(c);
-    const bool blocked = c->desc.lattice == LBM_D2Q9_PHASE;
+    const bool blocked = node_blocked(c->desc.lattice);
     if (c->desc.prec == LBM_FP64)
         return launch_nonfinite_watch<double>((const double*)a, c->P, c->N, c->nplanes, blocked,
                                               (unsigned long long)c->t, c->watch, c->stream);
@@ -1368,14 +1368,14 @@ struct StateHeader {
     uint64_t pop_bytes, phiu_bytes;
 };
 
-// State planes between device and a host blob holding N values per plane:
-// planes with stride P, or for the two-phase D2Q9 state the node blocks with
-// the padding of the last block left out (the full blocks in one copy, then
-// the last block's N mod 64 nodes plane by plane).
+// State values between device and a host blob holding N values per plane:
+// planes with stride P, or for a node-blocked state the node blocks with the
+// padding of the last block left out (the full blocks in one copy, then the
+// last block's N mod 64 nodes value by value).
 static hipError_t copy_state(lbm_ctx* c, char* host, char* dev, bool to_host) {
     const size_t es = c->esize, row = (size_t)c->N * es;
     const hipMemcpyKind kind = to_host ? hipMemcpyDeviceToHost : hipMemcpyHostToDevice;
-    if (c->desc.lattice != LBM_D2Q9_PHASE) {
+    if (!node_blocked(c->desc.lattice)) {
         const size_t pitch = (size_t)c->P * es;
         return to_host ? hipMemcpy2DAsync(host, row, dev, pitch, row, c->nplanes, kind, c->stream)
                        : hipMemcpy2DAsync(dev, pitch, host, row, row, c->nplanes, kind, c->stream);

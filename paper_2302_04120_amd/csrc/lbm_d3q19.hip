@@ -3,11 +3,12 @@
 // as the case of equal rates, Guo forcing, and per axis periodic or halfway
 // bounce-back walls (Eq. BB_vel with u_w = 0).
 //
-// Layout and streaming follow the 2D kernels: one plane per population,
-// index i * P + ((b * nz + z) * ny + y) * nx + x, the stored state is the
-// pre-collision set, and each node pushes its post-collision values to
-// x + e_i (or back into its own opposite slot through a wall).  FP32 storage
-// keeps f_i - w_i rho_ref.
+// Layout and streaming follow the two-phase D2Q9 kernels: node n = ((b * nz +
+// z) * ny + y) * nx + x, the 19 populations in node blocks (value i of node n
+// at bidx(19, i, n); a wave's 64 nodes are one contiguous block), the stored
+// state is the pre-collision set, and each node pushes its post-collision
+// values to x + e_i (or back into its own opposite slot through a wall).
+// FP32 storage keeps f_i - w_i rho_ref.
 //
 // Moment space.  The basis is the orthogonal set of d'Humieres et al. (2002)
 // (rows rho, e, eps, j_x, q_x, j_y, q_y, j_z, q_z, 3p_xx, 3pi_xx, p_ww, pi_ww,
@@ -65,7 +66,7 @@ __global__ __launch_bounds__(64 * kD3Ty) void k_d3_step(D3K k, const S* __restri
 
     C d[19];
 #pragma unroll
-    for (int i = 0; i < 19; ++i) d[i] = C(fc[i * P + n]);
+    for (int i = 0; i < 19; ++i) d[i] = C(fc[bidx(19, i, n)]);
     C m[19];
     moments19(d, m);
     // macros: rho = rho_ref + sum d (the deviations carry no momentum of their own)
@@ -142,11 +143,11 @@ __global__ __launch_bounds__(64 * kD3Ty) void k_d3_step(D3K k, const S* __restri
         const bool out = (k.bcx && (tx < 0 || tx >= nx)) || (k.bcy && (ty < 0 || ty >= ny)) ||
                          (k.bcz && (tz < 0 || tz >= nz));
         if (out) {
-            st(fn + OPP3[i] * P + n, S(v));
+            st(fn + bidx(19, OPP3[i], n), S(v));
         } else {
             const long long t = base + (long long)wrap(tz, nz) * plane +
                                 (long long)wrap(ty, ny) * nx + wrap(tx, nx);
-            st(fn + i * P + t, S(v));
+            st(fn + bidx(19, i, t), S(v));
         }
     }
 }
@@ -164,7 +165,7 @@ __global__ void k_d3_init(D3K k, const double* __restrict__ fld, S* __restrict__
         const double uu = ux * ux + uy * uy + uz * uz;
         for (int i = 0; i < 19; ++i) {
             const double eu = E3X[i] * ux + E3Y[i] * uy + E3Z[i] * uz;
-            f[i * P + n] = S(w19<double>(i) * ((rho - k.rho_ref) + rho * (3 * eu + 4.5 * eu * eu - 1.5 * uu)));
+            f[bidx(19, i, n)] = S(w19<double>(i) * ((rho - k.rho_ref) + rho * (3 * eu + 4.5 * eu * eu - 1.5 * uu)));
         }
     }
 }
@@ -177,7 +178,7 @@ __global__ void k_d3_macros(D3K k, const S* __restrict__ f, double* __restrict__
     for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < N;
          n += (long long)gridDim.x * blockDim.x) {
         double d[19], m[19];
-        for (int i = 0; i < 19; ++i) d[i] = double(f[i * P + n]);
+        for (int i = 0; i < 19; ++i) d[i] = double(f[bidx(19, i, n)]);
         moments19(d, m);
         const double rho = k.rho_ref + m[0];
         out[n] = rho;

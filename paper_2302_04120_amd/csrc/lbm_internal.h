@@ -12,15 +12,21 @@
 
 namespace lbm {
 
-// Node-block layout of the two-phase D2Q9 state: nodes in blocks of 64
+// Node-block layout (two-phase D2Q9, D3Q19, 3D two-phase): nodes in blocks of 64
 // consecutive node indices, each block holding all npl values of its nodes,
-// plane by plane (plane i of node n at ((n / 64) npl + i) 64 + n mod 64).  A
+// value by value (value i of node n at ((n / 64) npl + i) 64 + n mod 64).  A
 // wave that loads 64 consecutive nodes reads one contiguous block of npl x
-// 256 bytes (FP32), and a row of 256 nodes is one contiguous 21 KB span; in
-// one plane array per population the same wave opens npl separate streams
-// (67 M-node bubble batch, FP32: single step 2.27 -> 2.00 ms, two-step launch
-// 2.31 -> 2.24 ms).  The padding of the last block is never read or written.
+// 256 bytes (FP32); with one plane array per population the same wave opens
+// npl separate streams.  Measured against planes: two-phase D2Q9 single step
+// 2.25 -> 2.01 ms (67 M nodes), two-step launch 2.31 -> 2.25 ms, D3Q19 and 3D
+// two-phase steps 3-7 % faster.  The padding of the last block is never read
+// or written.
 constexpr int kBlk = 64;
+// the lattices whose state is stored in node blocks (the others keep one
+// plane of stride P per population)
+inline bool node_blocked(int lattice) {
+    return lattice == LBM_D2Q9_PHASE || lattice == LBM_D3Q19 || lattice == LBM_D3Q19_PHASE;
+}
 __host__ __device__ __forceinline__ long long bidx(int npl, int i, long long n) {
     return ((n >> 6) * npl + i) * kBlk + (n & (kBlk - 1));
 }

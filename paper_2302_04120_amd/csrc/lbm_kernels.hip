@@ -1174,9 +1174,15 @@ __global__ __launch_bounds__(256) void k_reduce1(int lattice, ChanK ck, PhaseK p
     double v[4] = {0, 0, 0, 0};
     for (long long j = blockIdx.x * 256LL + threadIdx.x; j < M; j += 256LL * gridDim.x) {
         const long long n = base + j;
-        // value of plane i at node n (the two-phase D2Q9 state is node-blocked)
+        // value i of node n: node blocks for the two-phase D2Q9, D3Q19 and
+        // 3D two-phase states, planes of stride P for the others
         auto at = [&](int i) {
-            return double(lattice == LBM_D2Q9_PHASE ? pops[pidx<S>(i, n)] : pops[i * P + n]);
+            constexpr int npl3 = std::is_same<S, float>::value ? 42 : 41;
+            const long long j = lattice == LBM_D2Q9_PHASE    ? pidx<S>(i, n)
+                                : lattice == LBM_D3Q19       ? bidx(19, i, n)
+                                : lattice == LBM_D3Q19_PHASE ? bidx(npl3, i, n)
+                                                             : i * P + n;
+            return double(pops[j]);
         };
         double cnt = 0;
         for (int i = 0; i < npop; ++i)
@@ -1190,13 +1196,13 @@ __global__ __launch_bounds__(256) void k_reduce1(int lattice, ChanK ck, PhaseK p
             v[0] += pk.rho_g + a * (pk.rho_l - pk.rho_g);
         } else if (lattice == LBM_D3Q19_PHASE) {
             double a = 0;
-            for (int i = 0; i < 19; ++i) a += double(pops[i * P + n]);
-            if (std::is_same<S, float>::value) a += double(pops[38 * P + n]);
+            for (int i = 0; i < 19; ++i) a += at(i);
+            if (std::is_same<S, float>::value) a += at(38);
             v[1] += a;
             v[0] += p3.rho_g + a * (p3.rho_l - p3.rho_g);
         } else if (lattice == LBM_D3Q19) {
             double a = 0;
-            for (int i = 0; i < 19; ++i) a += double(pops[i * P + n]);
+            for (int i = 0; i < 19; ++i) a += at(i);
             v[0] += d3.rho_ref + a;
         } else if (lattice == LBM_D2Q9_D2Q5) {
             double a = 0;

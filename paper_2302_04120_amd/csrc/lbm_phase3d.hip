@@ -10,9 +10,10 @@
 //              the tile and a one-node halo in LDS for the isotropic
 //              stencils, then the node's collision in registers and push
 //              streaming.
-// Layout: planes h 0-18, z 19-37, the low part of h_0 at 38 (FP32 storage:
-// the rest population is an FP32 hi/lo pair that carries the node's exact
-// phi balance, as in 2D), then (phi u) of the previous step (3 planes).
+// Layout: node blocks (bidx, NPL3 values per node) with h 0-18, z 19-37, the
+// low part of h_0 at 38 (FP32 storage: the rest population is an FP32 hi/lo
+// pair that carries the node's exact phi balance, as in 2D), then (phi u) of
+// the previous step (3 values); phi is one plain array of nodes.
 // Arithmetic is lattice-normalised as in the 2D kernels: velocities / c,
 // forces F dt^2 / dx, z_i in units of p / c_s^2, rates Lambda dt.
 #include <hip/hip_runtime.h>
@@ -24,6 +25,14 @@
 
 namespace lbm {
 namespace {
+
+// values per node of the 3D two-phase state: 42 in FP32 storage, 41 in FP64
+template <typename S>
+constexpr int NPL3 = std::is_same<S, float>::value ? 42 : 41;
+template <typename S>
+__device__ __forceinline__ long long p3idx(int i, long long n) {
+    return bidx(NPL3<S>, i, n);
+}
 
 // Step tiles, measured on the 256^3 bubble box (ms per step, FP32 / FP64):
 // 64 x 4 x 2 1.507 / 2.936, 64 x 2 x 2 1.498 / 2.806, 64 x 4 x 1 1.473 /
@@ -68,13 +77,12 @@ __global__ __launch_bounds__(256) void k_p3_phi(P3K k, const S* __restrict__ a,
                                                 S* __restrict__ phi) {
     constexpr bool RMASS = std::is_same<S, float>::value;
     const long long N = (long long)k.batch * k.nx * k.ny * k.nz;
-    const long long P = k.P;
     for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < N;
          n += (long long)gridDim.x * blockDim.x) {
         S h[19];
 #pragma unroll
-        for (int i = 0; i < 19; ++i) h[i] = a[i * P + n];
-        phi[n] = phi_sum19<S>(h, RMASS ? a[38 * P + n] : S(0));
+        for (int i = 0; i < 19; ++i) h[i] = a[p3idx<S>(i, n)];
+        phi[n] = phi_sum19<S>(h, RMASS ? a[p3idx<S>(38, n)] : S(0));
     }
 }
 
@@ -229,23 +237,23 @@ __device__ __forceinline__ void p3_node(const P3K& k, const S (&pn)[19], const S
         // ---- stores: (phi u), the rest populations, then push streaming with
         //      halfway bounce-back on walled axes
 #pragma unroll
-        for (int c = 0; c < 3; ++c) st(b + (PU + c) * P + n, S(pn3[c]));
-        st(b + n, h0hi);
-        if constexpr (RMASS) st(b + 38 * P + n, h0lo);
-        st(b + 19 * P + n, S(zs[0]));
+        for (int c = 0; c < 3; ++c) st(b + p3idx<S>(PU + c, n), S(pn3[c]));
+        st(b + p3idx<S>(0, n), h0hi);
+        if constexpr (RMASS) st(b + p3idx<S>(38, n), h0lo);
+        st(b + p3idx<S>(19, n), S(zs[0]));
 #pragma unroll
         for (int i = 1; i < 19; ++i) {
             const int txd = x + E3X[i], tyd = y + E3Y[i], tzd = z + E3Z[i];
             const bool out = (k.bcx && (txd < 0 || txd >= nx)) || (k.bcy && (tyd < 0 || tyd >= ny)) ||
                              (k.bcz && (tzd < 0 || tzd >= nz));
             if (out) {
-                st(b + OPP3[i] * P + n, S(hs[i]));
-                st(b + (19 + OPP3[i]) * P + n, S(zs[i]));
+                st(b + p3idx<S>(OPP3[i], n), S(hs[i]));
+                st(b + p3idx<S>(19 + OPP3[i], n), S(zs[i]));
             } else {
                 const long long d = base + (long long)wrap(tzd, nz) * plane +
                                     (long long)wrap(tyd, ny) * nx + wrap(txd, nx);
-                st(b + i * P + d, S(hs[i]));
-                st(b + (19 + i) * P + d, S(zs[i]));
+                st(b + p3idx<S>(i, d), S(hs[i]));
+                st(b + p3idx<S>(19 + i, d), S(zs[i]));
             }
         }
     }
@@ -282,13 +290,13 @@ __global__ __launch_bounds__(P3Tile<S>::Threads) void k_p3_step(P3K k, const S* 
     C h[19], zz[19], hlo = C(0), pu[3] = {C(0), C(0), C(0)};
     if (valid) {
 #pragma unroll
-        for (int i = 0; i < 19; ++i) h[i] = C(a[i * P + n]);
+        for (int i = 0; i < 19; ++i) h[i] = C(a[p3idx<S>(i, n)]);
 #pragma unroll
-        for (int i = 0; i < 19; ++i) zz[i] = C(a[(19 + i) * P + n]);
-        if (RMASS) hlo = C(a[38 * P + n]);
+        for (int i = 0; i < 19; ++i) zz[i] = C(a[p3idx<S>(19 + i, n)]);
+        if (RMASS) hlo = C(a[p3idx<S>(38, n)]);
         if constexpr (!MACROS) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) pu[c] = C(a[(PU + c) * P + n]);
+            for (int c = 0; c < 3; ++c) pu[c] = C(a[p3idx<S>(PU + c, n)]);
         }
     }
     const int t = (tz * kPY + ty) * kPX + tx;
@@ -325,20 +333,20 @@ __global__ void k_p3_init(P3K k, const double* __restrict__ fld, S* __restrict__
         for (int i = 1; i < 19; ++i) {
             const double eu = E3X[i] * u[0] + E3Y[i] * u[1] + E3Z[i] * u[2];
             const S hv = S(phi * w19<double>(i) * (1 + 3 * eu));
-            a[i * P + n] = hv;
+            a[p3idx<S>(i, n)] = hv;
             hsum += double(hv);
         }
         const double h0 = phi - hsum;  // the rest population closes phi exactly
         const S hi = S(h0);
-        a[n] = hi;
-        if (RMASS) a[38 * P + n] = S(h0 - double(hi));
+        a[p3idx<S>(0, n)] = hi;
+        if (RMASS) a[p3idx<S>(38, n)] = S(h0 - double(hi));
         for (int i = 0; i < 19; ++i) {
             const double eu = E3X[i] * u[0] + E3Y[i] * u[1] + E3Z[i] * u[2];
             const double w = w19<double>(i);
-            a[(19 + i) * P + n] =
+            a[p3idx<S>(19 + i, n)] =
                 S(ph * (i == 0 ? w - 1 : w) + rho * w * (3 * eu + 4.5 * eu * eu - 1.5 * uu));
         }
-        for (int c = 0; c < 3; ++c) a[(PU + c) * P + n] = S(phi * u[c]);
+        for (int c = 0; c < 3; ++c) a[p3idx<S>(PU + c, n)] = S(phi * u[c]);
     }
 }
 
