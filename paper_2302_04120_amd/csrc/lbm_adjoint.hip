@@ -32,11 +32,9 @@ __device__ __forceinline__ double wave_sum64(double v) {
 }
 
 template <typename S>
-__global__ __launch_bounds__(256) void k_adj_step(ChanK k, AdjK a, const S* __restrict__ f,
-                                                  const S* __restrict__ g,
-                                                  const S* __restrict__ lfn,
-                                                  const S* __restrict__ lgn, S* __restrict__ lf,
-                                                  S* __restrict__ lg, S mod,
+__global__ __launch_bounds__(256) void k_adj_step(ChanK k, AdjK a, const S* __restrict__ st,
+                                                  const S* __restrict__ ln,
+                                                  S* __restrict__ l, S mod,
                                                   double* __restrict__ dq_bot,
                                                   double* __restrict__ dq_top,
                                                   double* __restrict__ dtau_acc) {
@@ -49,16 +47,16 @@ __global__ __launch_bounds__(256) void k_adj_step(ChanK k, AdjK a, const S* __re
     const int x = (tile % gx) * 64 + threadIdx.x;
     const int y = (tile / gx) * 4 + threadIdx.y;
     const bool active = x < nx && y < ny;
-    const long long P = k.P;
+    const int npl = k.npl;  // node blocks: f 0-8, g 9-13
     double dtn = 0.0, dtt = 0.0;
     if (active) {
         const long long n = (long long)y * nx + x;
         const C rho_ref = C(k.rho_ref), ftx = C(k.Ft[0]), fty = C(k.Ft[1]);
         C d[9], drho, rho, ux, uy;
-        chan_flow_macros<C, S>(f, P, n, rho_ref, ftx, fty, d, drho, rho, ux, uy);
+        chan_flow_macros<C, S>(st, npl, n, rho_ref, ftx, fty, d, drho, rho, ux, uy);
         C e[5];
 #pragma unroll
-        for (int i = 0; i < 5; ++i) e[i] = C(g[i * P + n]);
+        for (int i = 0; i < 5; ++i) e[i] = C(st[bidx(npl, 9 + i, n)]);
         const C qdt = C(k.qdt);
         const C th = (e[0] + (e[1] + e[3]) + (e[2] + e[4])) + C(0.5) * qdt;
 
@@ -67,7 +65,7 @@ __global__ __launch_bounds__(256) void k_adj_step(ChanK k, AdjK a, const S* __re
         C uwx = C(0), uwy = C(0);
         if (k.bcx && x == nx - 1) {
             C d2[9], dr2, r2, ux2, uy2;
-            chan_flow_macros<C, S>(f, P, n - 1, rho_ref, ftx, fty, d2, dr2, r2, ux2, uy2);
+            chan_flow_macros<C, S>(st, npl, n - 1, rho_ref, ftx, fty, d2, dr2, r2, ux2, uy2);
             uwx = C(1.5) * ux - C(0.5) * ux2;
             uwy = C(1.5) * uy - C(0.5) * uy2;
         }
@@ -80,12 +78,12 @@ __global__ __launch_bounds__(256) void k_adj_step(ChanK k, AdjK a, const S* __re
             if (!outy && !outx) {
                 tx = wrap(tx, nx);
                 ty = wrap(ty, ny);
-                ls[i] = C(lfn[i * P + (long long)ty * nx + tx]);
+                ls[i] = C(ln[bidx(npl, i, (long long)ty * nx + tx)]);
             } else if (outy || tx < 0) {
-                ls[i] = C(lfn[OPP[i] * P + n]);  // bounce-back (wall, moving inlet)
+                ls[i] = C(ln[bidx(npl, OPP[i], n)]);  // bounce-back (wall, moving inlet)
             } else {
                 // anti-bounce-back outlet: -f_i* + 2 w rho_ref [4.5 (e.u_w)^2 - 1.5 u_w^2]
-                const C lam = C(lfn[OPP[i] * P + n]);
+                const C lam = C(ln[bidx(npl, OPP[i], n)]);
                 ls[i] = -lam;
                 const C eu = C(EX[i]) * uwx + C(EY[i]) * uwy;
                 const C k2 = C(2) * wgt<C>(i) * rho_ref;
@@ -97,14 +95,14 @@ __global__ __launch_bounds__(256) void k_adj_step(ChanK k, AdjK a, const S* __re
         if (k.bcx && nx >= 2 && x == nx - 2) {
             // the outlet node to the right depends on this node's velocity
             C d2[9], dr2, r2, ux2, uy2;
-            chan_flow_macros<C, S>(f, P, n + 1, rho_ref, ftx, fty, d2, dr2, r2, ux2, uy2);
+            chan_flow_macros<C, S>(st, npl, n + 1, rho_ref, ftx, fty, d2, dr2, r2, ux2, uy2);
             const C vx = C(1.5) * ux2 - C(0.5) * ux, vy = C(1.5) * uy2 - C(0.5) * uy;
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
                 if (EX[i] != 1) continue;
                 const int ty = y + EY[i];
                 if (k.bcy && (ty < 0 || ty >= ny)) continue;  // wall rule at the corner
-                const C lam = C(lfn[OPP[i] * P + n + 1]);
+                const C lam = C(ln[bidx(npl, OPP[i], n + 1)]);
                 const C eu = C(EX[i]) * vx + C(EY[i]) * vy;
                 const C k2 = C(2) * wgt<C>(i) * rho_ref;
                 ubx += C(-0.5) * lam * k2 * (C(9) * eu * C(EX[i]) - C(3) * vx);
@@ -122,20 +120,21 @@ __global__ __launch_bounds__(256) void k_adj_step(ChanK k, AdjK a, const S* __re
             if (!outy && !outx) {
                 tx = wrap(tx, nx);
                 ty = wrap(ty, ny);
-                lsg[i] = C(lgn[i * P + (long long)ty * nx + tx]);
+                lsg[i] = C(ln[bidx(npl, 9 + i, (long long)ty * nx + tx)]);
             } else if (outy) {
-                const C lam = C(lgn[OPP5[i] * P + n]);  // flux wall: + lambda (dt/dx) q'' / rho c_p
+                // flux wall: + lambda (dt/dx) q'' / rho c_p
+                const C lam = C(ln[bidx(npl, 9 + OPP5[i], n)]);
                 lsg[i] = lam;
                 const double gq = double(lam) * a.qgrad * double(mod);
                 if (ty < 0) dqb += gq;
                 else dqt += gq;
             } else if (tx < 0) {
-                lsg[i] = -C(lgn[OPP5[i] * P + n]);  // anti-bounce-back inlet
+                lsg[i] = -C(ln[bidx(npl, 9 + OPP5[i], n)]);  // anti-bounce-back inlet
             } else {
                 lsg[i] = C(0);  // dropped at the extrapolation outlet
             }
         }
-        if (k.bcx && x == nx - 1) lsg[3] += C(lgn[3 * P + n]);  // outlet slot took g_3*
+        if (k.bcx && x == nx - 1) lsg[3] += C(ln[bidx(npl, 9 + 3, n)]);  // outlet slot took g_3*
         // ---- transpose of the thermal collision g* = g - A_T (g - g_eq(T, u)) + B_T S
         {
             C mL[5], mN[5], neq[5], tmp[5], ag[5];
@@ -160,7 +159,7 @@ __global__ __launch_bounds__(256) void k_adj_step(ChanK k, AdjK a, const S* __re
                 uby += ag[i] * wgt5<C>(i) * th * C(3) * C(EY5[i]);
             }
 #pragma unroll
-            for (int i = 0; i < 5; ++i) lg[i * P + n] = S(lsg[i] - ag[i] + tb);
+            for (int i = 0; i < 5; ++i) l[bidx(npl, 9 + i, n)] = S(lsg[i] - ag[i] + tb);
         }
         // ---- transpose of the momentum collision f* = f - A (f - f_eq(rho, u)) + B F(u)
         {
@@ -212,7 +211,7 @@ __global__ __launch_bounds__(256) void k_adj_step(ChanK k, AdjK a, const S* __re
             const C ir = C(1) / rho;
 #pragma unroll
             for (int i = 0; i < 9; ++i)
-                lf[i * P + n] = S(ls[i] - av[i] + rb +
+                l[bidx(npl, i, n)] = S(ls[i] - av[i] + rb +
                                   ((C(EX[i]) - ux) * ubx + (C(EY[i]) - uy) * uby) * ir);
         }
         if (k.bcy && y == 0) dq_bot[x] += dqb;
@@ -235,22 +234,22 @@ __global__ __launch_bounds__(256) void k_adj_step(ChanK k, AdjK a, const S* __re
 // Objective J = w_tout T_out + w_nu mean_{x >= x_dev} Nu(x) at the final state
 // (definitions as in lbm_nusselt); one thread per column.
 template <typename S>
-__global__ void k_adj_seed(ChanK k, const S* __restrict__ f, const S* __restrict__ g,
-                           const S* __restrict__ qw, double qsi, double mod, double Dh, double kc,
+__global__ void k_adj_seed(ChanK k, const S* __restrict__ st, const S* __restrict__ qw, double qsi, double mod, double Dh, double kc,
                            double dx, double rho_cp, double cs2, int x_dev, double w_tout,
-                           double w_nu, S* __restrict__ lf, S* __restrict__ lg,
+                           double w_nu, S* __restrict__ l,
                            double* __restrict__ dq_direct, double* __restrict__ dtauT_direct) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int nx = k.nx, ny = k.ny;
     if (x >= nx) return;
-    const long long P = k.P;
+    const int npl = k.npl;  // node blocks: f 0-8, g 9-13
     double su = 0, suT = 0, T0 = 0, T1 = 0;
     for (int y = 0; y < ny; ++y) {
         const long long n = (long long)y * nx + x;
         double d[9], drho, rho, ux, uy;
-        chan_flow_macros<double, S>(f, P, n, k.rho_ref, k.Ft[0], k.Ft[1], d, drho, rho, ux, uy);
+        chan_flow_macros<double, S>(st, npl, n, k.rho_ref, k.Ft[0], k.Ft[1], d, drho, rho, ux,
+                                    uy);
         double s = 0;
-        for (int i = 0; i < 5; ++i) s += double(g[i * P + n]);
+        for (int i = 0; i < 5; ++i) s += double(st[bidx(npl, 9 + i, n)]);
         const double T = k.T_ref + s + 0.5 * k.qdt;
         su += ux * k.c;
         suT += ux * k.c * T;
@@ -275,16 +274,17 @@ __global__ void k_adj_seed(ChanK k, const S* __restrict__ f, const S* __restrict
     for (int y = 0; y < ny; ++y) {
         const long long n = (long long)y * nx + x;
         double d[9], drho, rho, ux, uy;
-        chan_flow_macros<double, S>(f, P, n, k.rho_ref, k.Ft[0], k.Ft[1], d, drho, rho, ux, uy);
+        chan_flow_macros<double, S>(st, npl, n, k.rho_ref, k.Ft[0], k.Ft[1], d, drho, rho, ux,
+                                    uy);
         double s = 0;
-        for (int i = 0; i < 5; ++i) s += double(g[i * P + n]);
+        for (int i = 0; i < 5; ++i) s += double(st[bidx(npl, 9 + i, n)]);
         const double T = k.T_ref + s + 0.5 * k.qdt;
         double Tbar = bTb * ux * k.c / su;
         if (y == 0) Tbar += 0.5 * bTw;
         if (y == ny - 1) Tbar += 0.5 * bTw;
         const double Ubar = bTb * (T - tb) / su * k.c;  // adjoint of u_x / c
-        for (int i = 0; i < 5; ++i) lg[i * P + n] = S(Tbar);
-        for (int i = 0; i < 9; ++i) lf[i * P + n] = S(Ubar * (EX[i] - ux) / rho);
+        for (int i = 0; i < 5; ++i) l[bidx(npl, 9 + i, n)] = S(Tbar);
+        for (int i = 0; i < 9; ++i) l[bidx(npl, i, n)] = S(Ubar * (EX[i] - ux) / rho);
     }
 }
 
@@ -313,24 +313,23 @@ __global__ void k_adj_final(int nx, int ntiles, double scale, const double* __re
 int chan_tiles(const ChanK& k) { return ((k.nx + 63) / 64) * ((k.ny + 3) / 4); }
 
 template <typename S>
-hipError_t launch_adj_seed(const ChanK& k, const S* f, const S* g, const S* qw, double qsi,
-                           double mod, double Dh, double kc, double dx, double rho_cp, double cs2,
-                           int x_dev, double w_tout, double w_nu, S* lf, S* lg, double* dq_direct,
+hipError_t launch_adj_seed(const ChanK& k, const S* st, const S* qw, double qsi, double mod,
+                           double Dh, double kc, double dx, double rho_cp, double cs2, int x_dev,
+                           double w_tout, double w_nu, S* l, double* dq_direct,
                            double* dtauT_direct, hipStream_t s) {
-    hipLaunchKernelGGL(k_adj_seed<S>, dim3((k.nx + 63) / 64), dim3(64), 0, s, k, f, g, qw, qsi,
-                       mod, Dh, kc, dx, rho_cp, cs2, x_dev, w_tout, w_nu, lf, lg, dq_direct,
-                       dtauT_direct);
+    hipLaunchKernelGGL(k_adj_seed<S>, dim3((k.nx + 63) / 64), dim3(64), 0, s, k, st, qw, qsi, mod,
+                       Dh, kc, dx, rho_cp, cs2, x_dev, w_tout, w_nu, l, dq_direct, dtauT_direct);
     return hipGetLastError();
 }
 
 template <typename S>
-hipError_t launch_adj_step(const ChanK& k, const AdjK& a, const S* f, const S* g, const S* lfn,
-                           const S* lgn, S* lf, S* lg, double mod, double* dq_bot, double* dq_top,
-                           double* dtau_acc, hipStream_t s) {
+hipError_t launch_adj_step(const ChanK& k, const AdjK& a, const S* st, const S* ln, S* l,
+                           double mod, double* dq_bot, double* dq_top, double* dtau_acc,
+                           hipStream_t s) {
     const int tiles = chan_tiles(k);
     dim3 blk(64, 4), grd(unsigned((tiles + kXCD - 1) / kXCD * kXCD));
-    hipLaunchKernelGGL(k_adj_step<S>, grd, blk, 0, s, k, a, f, g, lfn, lgn, lf, lg, S(mod), dq_bot,
-                       dq_top, dtau_acc);
+    hipLaunchKernelGGL(k_adj_step<S>, grd, blk, 0, s, k, a, st, ln, l, S(mod), dq_bot, dq_top,
+                       dtau_acc);
     return hipGetLastError();
 }
 
@@ -344,12 +343,11 @@ hipError_t launch_adj_final(int nx, int ntiles, double scale, const double* dq_b
 }
 
 #define LBM_ADJ_INST(S)                                                                          \
-    template hipError_t launch_adj_seed<S>(const ChanK&, const S*, const S*, const S*, double,   \
-                                           double, double, double, double, double, double, int,   \
-                                           double, double, S*, S*, double*, double*, hipStream_t); \
-    template hipError_t launch_adj_step<S>(const ChanK&, const AdjK&, const S*, const S*,        \
-                                           const S*, const S*, S*, S*, double, double*, double*,  \
-                                           double*, hipStream_t);
+    template hipError_t launch_adj_seed<S>(const ChanK&, const S*, const S*, double, double,     \
+                                           double, double, double, double, double, int, double,   \
+                                           double, S*, double*, double*, hipStream_t);            \
+    template hipError_t launch_adj_step<S>(const ChanK&, const AdjK&, const S*, const S*, S*,    \
+                                           double, double*, double*, double*, hipStream_t);
 LBM_ADJ_INST(float)
 LBM_ADJ_INST(double)
 

@@ -267,10 +267,8 @@ hipError_t step_once(lbm_ctx* c) {
     if (lat == LBM_D3Q19) return launch_d3_step<S>(c->d3k, a, b, c->stream);
     if (lat == LBM_D3Q19_PHASE) return launch_p3_step<S>(c->p3k, a, b, (S*)c->phi3, c->stream);
     if (lat == LBM_D2Q9_D2Q5) {
-        const bool th = c->ck.thermal;
-        return launch_chan_step<S>(c->ck, a, b, th ? a + 9 * P : nullptr, th ? b + 9 * P : nullptr,
-                                   aux_qw<S>(c), aux_uin<S>(c), aux_tin<S>(c), flux_mod(c),
-                                   c->stream);
+        return launch_chan_step<S>(c->ck, a, b, aux_qw<S>(c), aux_uin<S>(c), aux_tin<S>(c),
+                                   flux_mod(c), c->stream);
     }
     return launch_phase_step<S>(c->pk, a, b, c->desc.prec == LBM_FP32_DEV_ARITH64, c->stream);
 }
@@ -643,7 +641,7 @@ lbm_status lbm_set_params_SI(lbm_ctx* c, const lbm_params_si* p) {
         dk.TL = p->T_wall[1];
     } else if (d.lattice == LBM_D2Q9_D2Q5) {
         const double cs2 = cc * cc / 3.0;
-        ck.nx = d.nx; ck.ny = d.ny; ck.batch = d.batch; ck.P = c->P;
+        ck.nx = d.nx; ck.ny = d.ny; ck.batch = d.batch; ck.P = c->P; ck.npl = c->nplanes;
         ck.bcx = d.bc[0] == LBM_BC_VEL_INLET ? 1 : (d.bc[0] == LBM_BC_DIRICHLET ? 2 : 0);
         ck.bcy = d.bc[2] == LBM_BC_WALL ? (d.bc[3] == LBM_BC_SYMMETRY ? 2 : 1) : 0;
         ck.flow = (d.flags & LBM_FLAG_FLOW) ? 1 : 0;
@@ -846,11 +844,9 @@ lbm_status lbm_init_fields(lbm_ctx* c, const double* rho_or_p, const double* ux,
         e = launch_d1_init(c->dk, c->staging, (double*)c->popA, c->stream);
     } else if (d.lattice == LBM_D2Q9_D2Q5) {
         if (d.prec == LBM_FP64)
-            e = launch_chan_init<double>(c->ck, c->staging, (double*)c->popA,
-                                         c->ck.thermal ? (double*)c->popA + 9 * P : nullptr, c->stream);
+            e = launch_chan_init<double>(c->ck, c->staging, (double*)c->popA, c->stream);
         else
-            e = launch_chan_init<float>(c->ck, c->staging, (float*)c->popA,
-                                        c->ck.thermal ? (float*)c->popA + 9 * P : nullptr, c->stream);
+            e = launch_chan_init<float>(c->ck, c->staging, (float*)c->popA, c->stream);
     } else {
         if (d.prec == LBM_FP64)
             e = launch_phase_init<double>(c->pk, c->staging, (double*)c->popA, c->stream);
@@ -1038,8 +1034,8 @@ lbm_status lbm_macros(lbm_ctx* c, unsigned mask, double* out, int out_on_device)
         if (f64) e = launch_p3_macros<double>(c->p3k, (double*)a, (double*)c->phi3, c->staging, c->stream);
         else e = launch_p3_macros<float>(c->p3k, (float*)a, (float*)c->phi3, c->staging, c->stream);
     } else if (lat == LBM_D2Q9_D2Q5) {
-        if (f64) e = launch_chan_macros<double>(c->ck, (double*)a, c->ck.thermal ? (double*)a + 9 * P : nullptr, c->staging, c->stream);
-        else e = launch_chan_macros<float>(c->ck, (float*)a, c->ck.thermal ? (float*)a + 9 * P : nullptr, c->staging, c->stream);
+        if (f64) e = launch_chan_macros<double>(c->ck, (double*)a, c->staging, c->stream);
+        else e = launch_chan_macros<float>(c->ck, (float*)a, c->staging, c->stream);
     } else if (lat == LBM_D2Q9_PHASE) {
         if (f64) e = launch_phase_macros<double>(c->pk, (double*)a, c->staging, c->stream);
         else e = launch_phase_macros<float>(c->pk, (float*)a, c->staging, c->stream);
@@ -1162,12 +1158,12 @@ lbm_status lbm_nusselt(lbm_ctx* c, int x_dev, double* Tb, double* Tw, double* Nu
     hipError_t e;
     if (c->desc.prec == LBM_FP64) {
         const double* a = (const double*)bufA(c);
-        e = launch_nusselt<double>(c->ck, a, a + 9 * P, aux_qw<double>(c), qsi, c->Dh, c->k_cond,
-                                   c->dx, x_dev, dTb, dTw, dNu, dres, c->stream);
+        e = launch_nusselt<double>(c->ck, a, aux_qw<double>(c), qsi, c->Dh, c->k_cond, c->dx, x_dev,
+                                   dTb, dTw, dNu, dres, c->stream);
     } else {
         const float* a = (const float*)bufA(c);
-        e = launch_nusselt<float>(c->ck, a, a + 9 * P, aux_qw<float>(c), qsi, c->Dh, c->k_cond, c->dx,
-                                  x_dev, dTb, dTw, dNu, dres, c->stream);
+        e = launch_nusselt<float>(c->ck, a, aux_qw<float>(c), qsi, c->Dh, c->k_cond, c->dx, x_dev,
+                                  dTb, dTw, dNu, dres, c->stream);
     }
     if (e != hipSuccess) return hip_fail(c, e, "nusselt kernel");
     std::vector<double> h(3 * (size_t)nx + 2);
@@ -1224,15 +1220,13 @@ lbm_status rec_layout(const lbm_ctx* c, int nsteps, int K, RecLayout* R, std::st
 
 template <typename S>
 hipError_t chan_step_ptr(lbm_ctx* c, const S* a, S* b, long long t) {
-    const long long P = c->P;
     const double mod = 1.0 + c->flux_amp * std::sin(c->flux_omega * (double)t * c->dt);
-    return launch_chan_step<S>(c->ck, a, b, a + 9 * P, b + 9 * P, aux_qw<S>(c), aux_uin<S>(c),
-                               aux_tin<S>(c), mod, c->stream);
+    return launch_chan_step<S>(c->ck, a, b, aux_qw<S>(c), aux_uin<S>(c), aux_tin<S>(c), mod,
+                               c->stream);
 }
 
 template <typename S>
 hipError_t grad_impl(lbm_ctx* c, const RecLayout& R, double scale) {
-    const long long P = c->P;
     const int nx = c->desc.nx;
     char* w = c->rec_work;
     double* dq = (double*)(w + R.offDq);
@@ -1246,10 +1240,9 @@ hipError_t grad_impl(lbm_ctx* c, const RecLayout& R, double scale) {
     const long long tN = c->rec_t0 + c->rec_nsteps;
     const double modN = 1.0 + c->flux_amp * std::sin(c->flux_omega * (double)tN * c->dt);
     const S* fin = (const S*)bufA(c);
-    e = launch_adj_seed<S>(c->ck, fin, fin + 9 * P, aux_qw<S>(c), c->dx * c->rho_cp / c->dt * modN,
-                           modN, c->Dh, c->k_cond, c->dx, c->rho_cp, c->cs2, c->rec_obj.x_dev,
-                           c->rec_obj.w_tout, c->rec_obj.w_nu, lam[0], lam[0] + 9 * P, dq + 2 * nx,
-                           dq + 3 * nx, c->stream);
+    e = launch_adj_seed<S>(c->ck, fin, aux_qw<S>(c), c->dx * c->rho_cp / c->dt * modN, modN, c->Dh,
+                           c->k_cond, c->dx, c->rho_cp, c->cs2, c->rec_obj.x_dev, c->rec_obj.w_tout,
+                           c->rec_obj.w_nu, lam[0], dq + 2 * nx, dq + 3 * nx, c->stream);
     if (e != hipSuccess) return e;
     int cur = 0;
     for (int sg = R.nseg - 1; sg >= 0; --sg) {
@@ -1267,8 +1260,7 @@ hipError_t grad_impl(lbm_ctx* c, const RecLayout& R, double scale) {
         for (int j = len - 1; j >= 0; --j) {
             const S* st = (const S*)((char*)tape + (size_t)j * R.state);
             const double mod = 1.0 + c->flux_amp * std::sin(c->flux_omega * (double)(t0 + j) * c->dt);
-            e = launch_adj_step<S>(c->ck, c->ak, st, st + 9 * P, lam[cur], lam[cur] + 9 * P,
-                                   lam[cur ^ 1], lam[cur ^ 1] + 9 * P, mod, dq, dq + nx, acc,
+            e = launch_adj_step<S>(c->ck, c->ak, st, lam[cur], lam[cur ^ 1], mod, dq, dq + nx, acc,
                                    c->stream);
             if (e != hipSuccess) return e;
             cur ^= 1;

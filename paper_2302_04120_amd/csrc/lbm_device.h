@@ -134,13 +134,14 @@ __device__ __forceinline__ int wrap(int v, int n) {
 // D2Q9 flow + D2Q5 temperature: one node per thread
 // ---------------------------------------------------------------------------
 
-// lattice-normalised macros of one node from its deviation populations
+// lattice-normalised macros of one node from its deviation populations (the
+// f values 0-8 of a node-blocked state of npl values per node)
 template <typename C, typename S>
-__device__ __forceinline__ void chan_flow_macros(const S* __restrict__ f, long long P,
-                                                 long long n, C rho_ref, C ftx, C fty,
-                                                 C d[9], C& drho, C& rho, C& ux, C& uy) {
+__device__ __forceinline__ void chan_flow_macros(const S* __restrict__ f, int npl, long long n,
+                                                 C rho_ref, C ftx, C fty, C d[9], C& drho,
+                                                 C& rho, C& ux, C& uy) {
 #pragma unroll
-    for (int i = 0; i < 9; ++i) d[i] = C(f[i * P + n]);
+    for (int i = 0; i < 9; ++i) d[i] = C(f[bidx(npl, i, n)]);
     drho = ((d[0] + (d[1] + d[3])) + (d[2] + d[4])) + ((d[5] + d[7]) + (d[6] + d[8]));
     rho = rho_ref + drho;
     const C jx = (d[1] - d[3]) + ((d[5] - d[7]) + (d[8] - d[6]));
@@ -148,16 +149,6 @@ __device__ __forceinline__ void chan_flow_macros(const S* __restrict__ f, long l
     const C ir = C(1) / rho;
     ux = (jx + C(0.5) * ftx) * ir;  // Eq. first_moment_f, divided by c
     uy = (jy + C(0.5) * fty) * ir;
-}
-
-// T - T_ref of a node from its stored (deviation) D2Q5 populations, with the
-// half source (Eq. zero_moment_g)
-template <typename C, typename S>
-__device__ __forceinline__ C chan_theta(const S* __restrict__ g, long long P, long long n, C qdt) {
-    C e[5];
-#pragma unroll
-    for (int i = 0; i < 5; ++i) e[i] = C(g[i * P + n]);
-    return (e[0] + (e[1] + e[3]) + (e[2] + e[4])) + C(0.5) * qdt;  // D2Q5 (adjoint path)
 }
 
 // Lattice body force at a node whose temperature is T = T_ref + th: the

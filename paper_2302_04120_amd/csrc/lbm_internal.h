@@ -12,7 +12,7 @@
 
 namespace lbm {
 
-// Node-block layout (two-phase D2Q9, D3Q19, 3D two-phase): nodes in blocks of 64
+// Node-block layout (every 2D and 3D lattice state): nodes in blocks of 64
 // consecutive node indices, each block holding all npl values of its nodes,
 // value by value (value i of node n at ((n / 64) npl + i) 64 + n mod 64).  A
 // wave that loads 64 consecutive nodes reads one contiguous block of npl x
@@ -25,7 +25,8 @@ constexpr int kBlk = 64;
 // the lattices whose state is stored in node blocks (the others keep one
 // plane of stride P per population)
 inline bool node_blocked(int lattice) {
-    return lattice == LBM_D2Q9_PHASE || lattice == LBM_D3Q19 || lattice == LBM_D3Q19_PHASE;
+    return lattice == LBM_D2Q9_PHASE || lattice == LBM_D2Q9_D2Q5 || lattice == LBM_D3Q19 ||
+           lattice == LBM_D3Q19_PHASE;
 }
 __host__ __device__ __forceinline__ long long bidx(int npl, int i, long long n) {
     return ((n >> 6) * npl + i) * kBlk + (n & (kBlk - 1));
@@ -38,7 +39,8 @@ __host__ __device__ __forceinline__ long long bidx(int npl, int i, long long n) 
 // relaxation gives identical populations in either normalisation.
 struct ChanK {
     int nx, ny, batch;
-    long long P;          // plane stride (elements)
+    long long P;          // plane stride of the FP64 staging fields (elements)
+    int npl;              // values per node of the state (node blocks): f 9, then g 5 or 9
     int bcx, bcy;         // 0 periodic; bcx 1 inlet/outlet, 2 fixed-T walls;
                           // bcy 1 walls, 2 wall at y- + symmetry plane at y+
     int flow, thermal, flow_mrt, thermal_mrt;
@@ -184,9 +186,10 @@ namespace lbm {
 constexpr int kRedBlocks = 256;  // first-pass blocks per replica and field
 
 // launch wrappers (lbm_kernels.hip); all enqueue on s and return hipGetLastError()
+// one channel step from state a to state b (node blocks: f 0-8, g from 9)
 template <typename S>
-hipError_t launch_chan_step(const ChanK& k, const S* fc, S* fn, const S* gc, S* gn,
-                            const S* qw, const S* uin, const S* tin, double mod, hipStream_t s);
+hipError_t launch_chan_step(const ChanK& k, const S* a, S* b, const S* qw, const S* uin,
+                            const S* tin, double mod, hipStream_t s);
 // one two-phase step from state a to state b (node-block layout); arith64:
 // evaluate the step in FP64 on FP32 storage (S = float)
 template <typename S>
@@ -226,7 +229,7 @@ hipError_t launch_phase_persist(const PhaseK& k, S* A, S* B, int nsteps, unsigne
 hipError_t launch_d1(const D1K& k, double* g, int nsteps, hipStream_t s);
 
 template <typename S>
-hipError_t launch_chan_init(const ChanK& k, const double* fields, S* f, S* g, hipStream_t s);
+hipError_t launch_chan_init(const ChanK& k, const double* fields, S* a, hipStream_t s);
 template <typename S>
 hipError_t launch_phase_init(const PhaseK& k, const double* fields, S* a, hipStream_t s);
 hipError_t launch_d1_init(const D1K& k, const double* T, double* g, hipStream_t s);
@@ -253,7 +256,7 @@ hipError_t launch_p3_macros(const P3K& k, const S* a, S* phi, double* out, hipSt
 
 // macros into staging slots [8][P]: rho, p, ux, uy, T, phi, mu, uz
 template <typename S>
-hipError_t launch_chan_macros(const ChanK& k, const S* f, const S* g, double* out, hipStream_t s);
+hipError_t launch_chan_macros(const ChanK& k, const S* a, double* out, hipStream_t s);
 template <typename S>
 hipError_t launch_phase_macros(const PhaseK& k, const S* a, double* out, hipStream_t s);
 hipError_t launch_d1_macros(const D1K& k, const double* g, double* out, long long P,
@@ -268,23 +271,24 @@ hipError_t launch_reduce(int lattice, const ChanK& ck, const PhaseK& pk, const D
 // qsi converts the stored scaled flux to W/m^2 (including the time modulation);
 // small receives (mean Nu over x >= x_dev, Tb[nx-1])
 template <typename S>
-hipError_t launch_nusselt(const ChanK& k, const S* f, const S* g, const S* qw, double qsi,
-                          double Dh, double kc, double dx, int x_dev, double* Tb, double* Tw,
-                          double* Nu, double* small, hipStream_t s);
+hipError_t launch_nusselt(const ChanK& k, const S* a, const S* qw, double qsi, double Dh,
+                          double kc, double dx, int x_dev, double* Tb, double* Tw, double* Nu,
+                          double* small, hipStream_t s);
 
 // ---- discrete adjoint of the heated channel (lbm_adjoint.hip)
-// seed at the final state: lambda_f, lambda_g, and the objective's direct
-// derivatives per column (dq_direct[x], dtauT_direct[x])
+// The adjoint state has the layout of the channel state (node blocks: lambda_f
+// 0-8, lambda_g 9-13).  Seed at the final state st: lambda into l, and the
+// objective's direct derivatives per column (dq_direct[x], dtauT_direct[x])
 template <typename S>
-hipError_t launch_adj_seed(const ChanK& k, const S* f, const S* g, const S* qw, double qsi,
-                           double mod, double Dh, double kc, double dx, double rho_cp,
-                           double cs2, int x_dev, double w_tout, double w_nu, S* lf, S* lg,
-                           double* dq_direct, double* dtauT_direct, hipStream_t s);
-// one reverse step: lambda(n) from lambda(n+1) and the state at n
+hipError_t launch_adj_seed(const ChanK& k, const S* st, const S* qw, double qsi, double mod,
+                           double Dh, double kc, double dx, double rho_cp, double cs2, int x_dev,
+                           double w_tout, double w_nu, S* l, double* dq_direct,
+                           double* dtauT_direct, hipStream_t s);
+// one reverse step: lambda(n) into l from lambda(n+1) in ln and the state st at n
 template <typename S>
-hipError_t launch_adj_step(const ChanK& k, const AdjK& a, const S* f, const S* g, const S* lfn,
-                           const S* lgn, S* lf, S* lg, double mod, double* dq_bot,
-                           double* dq_top, double* dtau_acc, hipStream_t s);
+hipError_t launch_adj_step(const ChanK& k, const AdjK& a, const S* st, const S* ln, S* l,
+                           double mod, double* dq_bot, double* dq_top, double* dtau_acc,
+                           hipStream_t s);
 // gradient assembly (fixed order): grad_flux[nx], grad_tau[2]
 hipError_t launch_adj_final(int nx, int ntiles, double scale, const double* dq_bot,
                             const double* dq_top, const double* dq_direct,

@@ -38,9 +38,8 @@ template <int QT, typename C> __device__ __forceinline__ C twt(int i) {
 // the symmetry plane of Eq. simetria at y+ (2).  x: periodic (bcx 0), velocity
 // inlet + pressure outlet (1), fixed-temperature walls (2).
 template <typename S, int QT, int CTY = 4>
-__global__ __launch_bounds__(64 * CTY) void k_chan_step(ChanK k, const S* __restrict__ fc,
-                                                        S* __restrict__ fn, const S* __restrict__ gc,
-                                                        S* __restrict__ gn, const S* __restrict__ qw,
+__global__ __launch_bounds__(64 * CTY) void k_chan_step(ChanK k, const S* __restrict__ A,
+                                                        S* __restrict__ B, const S* __restrict__ qw,
                                                         const S* __restrict__ uin,
                                                         const S* __restrict__ tin, S mod) {
     using C = S;
@@ -52,7 +51,7 @@ __global__ __launch_bounds__(64 * CTY) void k_chan_step(ChanK k, const S* __rest
     const int x = (r % gx) * 64 + threadIdx.x;
     const int y = (r / gx) * CTY + threadIdx.y;
     if (x >= nx || y >= ny) return;
-    const long long P = k.P;
+    const int npl = k.npl;  // node blocks: f 0-8, g 9 .. 9 + QT - 1
     const long long base = (long long)b * ny * nx;
     const long long n = base + (long long)y * nx + x;
     const C rho_ref = C(k.rho_ref);
@@ -62,7 +61,7 @@ __global__ __launch_bounds__(64 * CTY) void k_chan_step(ChanK k, const S* __rest
     C e[QT], th = C(0);
     if (k.thermal) {
 #pragma unroll
-        for (int i = 0; i < QT; ++i) e[i] = C(gc[i * P + n]);
+        for (int i = 0; i < QT; ++i) e[i] = C(A[bidx(npl, 9 + i, n)]);
         if constexpr (QT == 9)
             th = ((e[0] + (e[1] + e[3]) + (e[2] + e[4])) + ((e[5] + e[7]) + (e[6] + e[8]))) +
                  C(0.5) * qdt;  // Eq. zero_moment_g
@@ -73,7 +72,7 @@ __global__ __launch_bounds__(64 * CTY) void k_chan_step(ChanK k, const S* __rest
     chan_force(k, th, ftx, fty);
 
     C d[9], drho, rho, ux, uy;
-    chan_flow_macros<C, S>(fc, P, n, rho_ref, ftx, fty, d, drho, rho, ux, uy);
+    chan_flow_macros<C, S>(A, npl, n, rho_ref, ftx, fty, d, drho, rho, ux, uy);
 
     // ---- momentum collision (Eq. colisao_MRT or Eq. eq_lattice_boltzmann_BGK)
     C ds[9];
@@ -153,10 +152,10 @@ __global__ __launch_bounds__(64 * CTY) void k_chan_step(ChanK k, const S* __rest
         if (k.buoy) {
             C th2 = C(0);
 #pragma unroll
-            for (int i = 0; i < QT; ++i) th2 += C(gc[i * P + n - 1]);
+            for (int i = 0; i < QT; ++i) th2 += C(A[bidx(npl, 9 + i, n - 1)]);
             chan_force(k, th2 + C(0.5) * qdt, fx2, fy2);
         }
-        chan_flow_macros<C, S>(fc, P, n - 1, rho_ref, fx2, fy2, d2, dr2, r2, ux2, uy2);
+        chan_flow_macros<C, S>(A, npl, n - 1, rho_ref, fx2, fy2, d2, dr2, r2, ux2, uy2);
         uwx = C(1.5) * ux - C(0.5) * ux2;
         uwy = C(1.5) * uy - C(0.5) * uy2;
     }
@@ -167,7 +166,7 @@ __global__ __launch_bounds__(64 * CTY) void k_chan_step(ChanK k, const S* __rest
     //      lies outside in x the x rule applies.
     if (!k.flow) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) fn[i * P + n] = S(d[i]);
+        for (int i = 0; i < 9; ++i) B[bidx(npl, i, n)] = S(d[i]);
     } else {
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
@@ -182,7 +181,7 @@ __global__ __launch_bounds__(64 * CTY) void k_chan_step(ChanK k, const S* __rest
             if (!outy && !outx) {
                 tx = wrap(tx, nx);
                 ty = wrap(ty, ny);
-                fn[j * P + base + (long long)ty * nx + tx] = S(ds[i]);
+                B[bidx(npl, j, base + (long long)ty * nx + tx)] = S(ds[i]);
             } else {
                 C v;
                 if (outy || k.bcx == 2) {
@@ -196,7 +195,7 @@ __global__ __launch_bounds__(64 * CTY) void k_chan_step(ChanK k, const S* __rest
                     v = -ds[i] + C(2) * wgt<C>(i) * rho_ref *
                                      (C(4.5) * eu * eu - C(1.5) * (uwx * uwx + uwy * uwy));
                 }
-                fn[OPP[i] * P + n] = S(v);
+                B[bidx(npl, OPP[i], n)] = S(v);
             }
         }
     }
@@ -206,11 +205,11 @@ __global__ __launch_bounds__(64 * CTY) void k_chan_step(ChanK k, const S* __rest
         // c_x < 0 is stored into the outlet column as well, unless a wall rule
         // owns that outlet slot (its source lies beyond a wall in y).
         auto put = [&](int j, int tx, int ty, C v) {
-            gn[j * P + base + (long long)ty * nx + tx] = S(v);
+            B[bidx(npl, 9 + j, base + (long long)ty * nx + tx)] = S(v);
             if (k.bcx == 1 && tx == nx - 2 && tex<QT>(j) < 0) {
                 const int sy = ty - tey<QT>(j);
                 const bool wall_owned = k.bcy && (sy < 0 || (k.bcy == 1 && sy >= ny));
-                if (!wall_owned) gn[j * P + base + (long long)ty * nx + nx - 1] = S(v);
+                if (!wall_owned) B[bidx(npl, 9 + j, base + (long long)ty * nx + nx - 1)] = S(v);
             }
         };
 #pragma unroll
@@ -1028,8 +1027,7 @@ __global__ __launch_bounds__(1024) void k_d1(D1K k, double* __restrict__ g, int 
 // 3 T, 4 phi; all FP64, velocities in m/s)
 // ---------------------------------------------------------------------------
 template <typename S>
-__global__ void k_chan_init(ChanK k, const double* __restrict__ fld, S* __restrict__ f,
-                            S* __restrict__ g) {
+__global__ void k_chan_init(ChanK k, const double* __restrict__ fld, S* __restrict__ A) {
     const long long N = (long long)k.batch * k.nx * k.ny;
     const long long P = k.P;
     for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < N;
@@ -1039,15 +1037,17 @@ __global__ void k_chan_init(ChanK k, const double* __restrict__ fld, S* __restri
         const double uu = ux * ux + uy * uy;
         for (int i = 0; i < 9; ++i) {
             const double eu = EX[i] * ux + EY[i] * uy;
-            f[i * P + n] = S(wgt<double>(i) * ((rho - k.rho_ref) +
-                                               rho * (3 * eu + 4.5 * eu * eu - 1.5 * uu)));
+            A[bidx(k.npl, i, n)] = S(wgt<double>(i) * ((rho - k.rho_ref) +
+                                                       rho * (3 * eu + 4.5 * eu * eu - 1.5 * uu)));
         }
-        if (g && k.tq == 9)
+        if (k.thermal && k.tq == 9)
             for (int i = 0; i < 9; ++i)
-                g[i * P + n] = S(wgt<double>(i) * th * (1 + 3 * (EX[i] * ux + EY[i] * uy)));
-        else if (g)
+                A[bidx(k.npl, 9 + i, n)] =
+                    S(wgt<double>(i) * th * (1 + 3 * (EX[i] * ux + EY[i] * uy)));
+        else if (k.thermal)
             for (int i = 0; i < 5; ++i)
-                g[i * P + n] = S(wgt5<double>(i) * th * (1 + 3 * (EX5[i] * ux + EY5[i] * uy)));
+                A[bidx(k.npl, 9 + i, n)] =
+                    S(wgt5<double>(i) * th * (1 + 3 * (EX5[i] * ux + EY5[i] * uy)));
     }
 }
 
@@ -1102,22 +1102,21 @@ __global__ void k_d1_init(D1K k, const double* __restrict__ T, double* __restric
 // FP64 macros of the stored state
 // ---------------------------------------------------------------------------
 template <typename S>
-__global__ void k_chan_macros(ChanK k, const S* __restrict__ f, const S* __restrict__ g,
-                              double* __restrict__ out) {
+__global__ void k_chan_macros(ChanK k, const S* __restrict__ A, double* __restrict__ out) {
     const long long N = (long long)k.batch * k.nx * k.ny;
     const long long P = k.P;
     for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < N;
          n += (long long)gridDim.x * blockDim.x) {
         double th = 0.0;
-        if (g) {
+        if (k.thermal) {
             double s = 0;
-            for (int i = 0; i < k.tq; ++i) s += double(g[i * P + n]);
+            for (int i = 0; i < k.tq; ++i) s += double(A[bidx(k.npl, 9 + i, n)]);
             th = s + 0.5 * k.qdt;
         }
         double fx, fy;
         chan_force(k, th, fx, fy);
         double d[9], drho, rho, ux, uy;
-        chan_flow_macros<double, S>(f, P, n, k.rho_ref, fx, fy, d, drho, rho, ux, uy);
+        chan_flow_macros<double, S>(A, k.npl, n, k.rho_ref, fx, fy, d, drho, rho, ux, uy);
         out[n] = rho;
         out[2 * P + n] = ux * k.c;
         out[3 * P + n] = uy * k.c;
@@ -1174,11 +1173,12 @@ __global__ __launch_bounds__(256) void k_reduce1(int lattice, ChanK ck, PhaseK p
     double v[4] = {0, 0, 0, 0};
     for (long long j = blockIdx.x * 256LL + threadIdx.x; j < M; j += 256LL * gridDim.x) {
         const long long n = base + j;
-        // value i of node n: node blocks for the two-phase D2Q9, D3Q19 and
-        // 3D two-phase states, planes of stride P for the others
+        // value i of node n: node blocks for the 2D and 3D lattices, planes
+        // of stride P for the 1D ones
         auto at = [&](int i) {
             constexpr int npl3 = std::is_same<S, float>::value ? 42 : 41;
             const long long j = lattice == LBM_D2Q9_PHASE    ? pidx<S>(i, n)
+                                : lattice == LBM_D2Q9_D2Q5   ? bidx(ck.npl, i, n)
                                 : lattice == LBM_D3Q19       ? bidx(19, i, n)
                                 : lattice == LBM_D3Q19_PHASE ? bidx(npl3, i, n)
                                                              : i * P + n;
@@ -1206,11 +1206,11 @@ __global__ __launch_bounds__(256) void k_reduce1(int lattice, ChanK ck, PhaseK p
             v[0] += d3.rho_ref + a;
         } else if (lattice == LBM_D2Q9_D2Q5) {
             double a = 0;
-            for (int i = 0; i < 9; ++i) a += double(pops[i * P + n]);
+            for (int i = 0; i < 9; ++i) a += at(i);
             v[0] += ck.rho_ref + a;
             if (ck.thermal) {
                 double s = 0;
-                for (int i = 0; i < ck.tq; ++i) s += double(pops[(9 + i) * P + n]);
+                for (int i = 0; i < ck.tq; ++i) s += at(9 + i);
                 v[2] += ck.T_ref + s + 0.5 * ck.qdt;
             }
         } else {
@@ -1249,23 +1249,22 @@ __global__ void k_reduce2(const double* __restrict__ partial, double* __restrict
 
 // channel diagnostics of replica 0: one thread per column
 template <typename S>
-__global__ void k_nusselt(ChanK k, const S* __restrict__ f, const S* __restrict__ g,
-                          const S* __restrict__ qw, double qsi, double Dh, double kc, double dx,
+__global__ void k_nusselt(ChanK k, const S* __restrict__ A, const S* __restrict__ qw,
+                          double qsi, double Dh, double kc, double dx,
                           double* __restrict__ Tb, double* __restrict__ Tw,
                           double* __restrict__ Nu) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= k.nx) return;
-    const long long P = k.P;
     double su = 0, suT = 0, T0 = 0, T1 = 0;
     for (int y = 0; y < k.ny; ++y) {
         const long long n = (long long)y * k.nx + x;
         double s = 0;
-        for (int i = 0; i < k.tq; ++i) s += double(g[i * P + n]);
+        for (int i = 0; i < k.tq; ++i) s += double(A[bidx(k.npl, 9 + i, n)]);
         const double T = k.T_ref + s + 0.5 * k.qdt;
         double fx, fy;
         chan_force(k, T - k.T_ref, fx, fy);
         double d[9], drho, rho, ux, uy;
-        chan_flow_macros<double, S>(f, P, n, k.rho_ref, fx, fy, d, drho, rho, ux, uy);
+        chan_flow_macros<double, S>(A, k.npl, n, k.rho_ref, fx, fy, d, drho, rho, ux, uy);
         su += ux;
         suT += ux * T;
         if (y == 0) T0 = T;
@@ -1312,15 +1311,15 @@ inline unsigned grid1(long long N, int bs) {
 #define LBM_CHAN_SMALL_TY 1
 #endif
 template <typename S>
-hipError_t launch_chan_step(const ChanK& k, const S* fc, S* fn, const S* gc, S* gn, const S* qw,
-                            const S* uin, const S* tin, double mod, hipStream_t s) {
+hipError_t launch_chan_step(const ChanK& k, const S* a, S* b, const S* qw, const S* uin,
+                            const S* tin, double mod, hipStream_t s) {
     auto go = [&](auto k9, auto k5, int ty) {
         const long long tiles = (long long)((k.nx + 63) / 64) * ((k.ny + ty - 1) / ty) * k.batch;
         dim3 blk(64, ty), grd(unsigned((tiles + kXCD - 1) / kXCD * kXCD));
         if (k.tq == 9)
-            hipLaunchKernelGGL(k9, grd, blk, 0, s, k, fc, fn, gc, gn, qw, uin, tin, S(mod));
+            hipLaunchKernelGGL(k9, grd, blk, 0, s, k, a, b, qw, uin, tin, S(mod));
         else
-            hipLaunchKernelGGL(k5, grd, blk, 0, s, k, fc, fn, gc, gn, qw, uin, tin, S(mod));
+            hipLaunchKernelGGL(k5, grd, blk, 0, s, k, a, b, qw, uin, tin, S(mod));
         return hipGetLastError();
     };
     const long long tiles4 = (long long)((k.nx + 63) / 64) * ((k.ny + 3) / 4) * k.batch;
@@ -1524,9 +1523,9 @@ hipError_t launch_d1(const D1K& k, double* g, int nsteps, hipStream_t s) {
 }
 
 template <typename S>
-hipError_t launch_chan_init(const ChanK& k, const double* fields, S* f, S* g, hipStream_t s) {
+hipError_t launch_chan_init(const ChanK& k, const double* fields, S* a, hipStream_t s) {
     const long long N = (long long)k.batch * k.nx * k.ny;
-    hipLaunchKernelGGL(k_chan_init<S>, dim3(grid1(N, 256)), dim3(256), 0, s, k, fields, f, g);
+    hipLaunchKernelGGL(k_chan_init<S>, dim3(grid1(N, 256)), dim3(256), 0, s, k, fields, a);
     return hipGetLastError();
 }
 
@@ -1543,10 +1542,9 @@ hipError_t launch_d1_init(const D1K& k, const double* T, double* g, hipStream_t 
 }
 
 template <typename S>
-hipError_t launch_chan_macros(const ChanK& k, const S* f, const S* g, double* out,
-                              hipStream_t s) {
+hipError_t launch_chan_macros(const ChanK& k, const S* a, double* out, hipStream_t s) {
     const long long N = (long long)k.batch * k.nx * k.ny;
-    hipLaunchKernelGGL(k_chan_macros<S>, dim3(grid1(N, 256)), dim3(256), 0, s, k, f, g, out);
+    hipLaunchKernelGGL(k_chan_macros<S>, dim3(grid1(N, 256)), dim3(256), 0, s, k, a, out);
     return hipGetLastError();
 }
 
@@ -1590,10 +1588,10 @@ hipError_t launch_nonfinite_watch(const S* pops, long long P, long long N, int n
 }
 
 template <typename S>
-hipError_t launch_nusselt(const ChanK& k, const S* f, const S* g, const S* qw, double qsi,
-                          double Dh, double kc, double dx, int x_dev, double* Tb, double* Tw,
-                          double* Nu, double* small, hipStream_t s) {
-    hipLaunchKernelGGL(k_nusselt<S>, dim3((k.nx + 255) / 256), dim3(256), 0, s, k, f, g, qw, qsi,
+hipError_t launch_nusselt(const ChanK& k, const S* a, const S* qw, double qsi, double Dh,
+                          double kc, double dx, int x_dev, double* Tb, double* Tw, double* Nu,
+                          double* small, hipStream_t s) {
+    hipLaunchKernelGGL(k_nusselt<S>, dim3((k.nx + 255) / 256), dim3(256), 0, s, k, a, qw, qsi,
                        Dh, kc, dx, Tb, Tw, Nu);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -1602,17 +1600,16 @@ hipError_t launch_nusselt(const ChanK& k, const S* f, const S* g, const S* qw, d
 }
 
 #define LBM_INST(S)                                                                              \
-    template hipError_t launch_chan_step<S>(const ChanK&, const S*, S*, const S*, S*, const S*, \
-                                            const S*, const S*, double, hipStream_t);             \
+    template hipError_t launch_chan_step<S>(const ChanK&, const S*, S*, const S*, const S*,     \
+                                            const S*, double, hipStream_t);                       \
     template hipError_t launch_phase_step<S>(const PhaseK&, const S*, S*, bool, hipStream_t);    \
     template hipError_t launch_phase_tb2<S>(const PhaseK&, const S*, S*, int, hipStream_t);      \
     template int phase_tb2_seg<S>(const PhaseK&);                                                \
     template hipError_t launch_phase_persist<S>(const PhaseK&, S*, S*, int, unsigned, unsigned*,  \
                                                 unsigned*, bool, hipStream_t);                    \
-    template hipError_t launch_chan_init<S>(const ChanK&, const double*, S*, S*, hipStream_t);   \
+    template hipError_t launch_chan_init<S>(const ChanK&, const double*, S*, hipStream_t);       \
     template hipError_t launch_phase_init<S>(const PhaseK&, const double*, S*, hipStream_t);    \
-    template hipError_t launch_chan_macros<S>(const ChanK&, const S*, const S*, double*,         \
-                                              hipStream_t);                                       \
+    template hipError_t launch_chan_macros<S>(const ChanK&, const S*, double*, hipStream_t);    \
     template hipError_t launch_phase_macros<S>(const PhaseK&, const S*, double*, hipStream_t);  \
     template hipError_t launch_reduce<S>(int, const ChanK&, const PhaseK&, const D1K&,           \
                                          const D3K&, const P3K&, const S*, int, double*,          \
@@ -1620,9 +1617,9 @@ hipError_t launch_nusselt(const ChanK& k, const S* f, const S* g, const S* qw, d
     template hipError_t launch_nonfinite_watch<S>(const S*, long long, long long, int, bool,     \
                                                   unsigned long long, unsigned long long*,       \
                                                   hipStream_t);                                   \
-    template hipError_t launch_nusselt<S>(const ChanK&, const S*, const S*, const S*, double,    \
-                                          double, double, double, int, double*, double*, double*, \
-                                          double*, hipStream_t);
+    template hipError_t launch_nusselt<S>(const ChanK&, const S*, const S*, double, double,      \
+                                          double, double, int, double*, double*, double*, double*, \
+                                          hipStream_t);
 LBM_INST(float)
 LBM_INST(double)
 

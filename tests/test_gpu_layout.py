@@ -1,6 +1,7 @@
-"""The node-block state layout (two-phase D2Q9, D3Q19, 3D two-phase): every
-value of 64 consecutive nodes stored together, the last block padded.  With a
-node count that is not a multiple of 64 the last block is partial, and:
+"""The node-block state layout (two-phase D2Q9, heated channel, D3Q19, 3D
+two-phase): every value of 64 consecutive nodes stored together, the last
+block padded.  With a node count that is not a multiple of 64 the last block
+is partial, and:
 
 - a state blob holds exactly the N node values of each stored quantity (no
   padding), and a run resumed from it equals the uninterrupted run bit for
@@ -30,6 +31,20 @@ def _phase(prec):
     return make, batch * nx * ny, (21 if prec == "fp32" else 20)
 
 
+def _chan(prec):
+    from paper_2302_04120_amd import lbm
+    nx, ny = 150, 22  # 3300 nodes: 51 full blocks and 36 nodes
+    prm, ini = WL.channel(nx=nx, ny=ny, dx=5e-5, tau_ratio=0.6, oscillating=True)
+
+    def make():
+        L = lbm.Lattice("channel", nx, ny, prec=prec,
+                        bc=(lbm.BC_VEL_INLET, lbm.BC_P_OUTLET, lbm.BC_WALL, lbm.BC_WALL),
+                        flow=True, thermal=True)
+        L.set_params(prm)
+        return L, lambda L: L.init(ini["rho"], ini["ux"], ini["uy"], ini["T"])
+    return make, nx * ny, 14
+
+
 def _d3(prec):
     from paper_2302_04120_amd import lbm
     nx, ny, nz = 10, 7, 5  # 350 nodes: 5 full blocks and 30 nodes
@@ -56,7 +71,7 @@ def _p3(prec):
     return make, nx * ny * nz, (42 if prec == "fp32" else 41)
 
 
-CASES = {"phase": _phase, "d3q19": _d3, "phase3d": _p3}
+CASES = {"phase": _phase, "channel": _chan, "d3q19": _d3, "phase3d": _p3}
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
@@ -79,14 +94,22 @@ def test_ragged_blocks_save_load_resume(lattice, prec):
     assert a.save_state() == b.save_state()
 
 
+PAD = 16448  # extra elements per value array of the library's buffer layout
+
+
 @pytest.mark.parametrize("lattice", sorted(CASES))
 def test_padding_never_read(lattice):
     import torch
     print_case(test="layout-padding", lattice=lattice)
-    make, _, _ = CASES[lattice]("fp32")
+    make, N, nvals = CASES[lattice]("fp32")
     poisoned, init = make()
+    # the two state buffers lead the device buffer, each nvals arrays of
+    # P = ceil64(N) + PAD elements rounded up to 256 bytes; what follows them
+    # (the channel's wall-flux and inlet arrays) is left alone
+    P = (N + 63) // 64 * 64 + PAD
+    state_bytes = 2 * ((nvals * P * 4 + 255) // 256 * 256)
     torch.cuda.synchronize()
-    poisoned.buf.fill_(255)  # NaN bytes everywhere, the padding of both state buffers included
+    poisoned.buf[:state_bytes].fill_(255)  # NaN bytes, the padding of both buffers included
     torch.cuda.synchronize()
     init(poisoned)
     clean, _ = make()
