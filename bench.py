@@ -147,7 +147,8 @@ def run_wide(cells, steps, warmup, prec, fusion=0):
     return dict(mlups=nodes * steps / (ms * 1e-3) / 1e6, grid="%dx%d" % (n, n),
                 ms_per_step=ms / steps, launch_ms=launch_ms,
                 hbm_frac=BYTES_PER_LU[prec] * nodes / (launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                kernel="k_phase_tb2<%s, true>" % ("float" if prec == "fp32" else "double")
+                kernel="k_phase_tb2<%s, true, %s>" % ("float" if prec == "fp32" else "double",
+                                                      "true" if n % 64 == 0 else "false")
                 if spl == 2 else "k_phase")
 
 
@@ -613,7 +614,8 @@ def main():
     mlups = r["nodes"] * args.steps / r["wall"] / 1e6
     bpl = BYTES_PER_LU[args.prec]
     spl = 2 if args.fusion == 2 else 1  # steps per launch
-    kname = ("k_phase_tb2<%s, false>" % ("float" if args.prec == "fp32" else "double") if spl == 2 else
+    kname = ("k_phase_tb2<%s, false, true>" % ("float" if args.prec == "fp32" else "double")
+             if spl == 2 else
              "k_phase<%s>" % {"fp32": "float,float,false", "fp64": "double,double,false",
                               "fp32_arith64": "float,double,false"}[args.prec])
     launch_ms = r["kernel_ms"] * spl

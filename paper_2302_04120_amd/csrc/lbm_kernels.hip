@@ -707,6 +707,13 @@ __global__ __launch_bounds__(TX * TY) void k_phase_persist(PhaseK k, S* __restri
 // neighbours): those 250 columns are stored, the edge lanes' values are
 // never used.  The stored columns of neighbouring tiles are disjoint, and
 // every destination slot is still written by exactly one source node.
+//
+// ALIGNED (nx a multiple of 64): every row starts on a node-block boundary,
+// so value i of column c in row v lies at the row's block base (uniform over
+// the workgroup: scalar registers) plus the column's offset within the row's
+// blocks (per lane, fixed for x, x - 1 and x + 1) plus i blocks of 64
+// values, and no access needs per-lane 64-bit index arithmetic.  Other widths
+// take the general node-block index.
 // ---------------------------------------------------------------------------
 constexpr int kTbMaxNx = 256;
 constexpr int kTbHalo = 3;                          // overlap columns per side (TILED)
@@ -719,9 +726,10 @@ constexpr int kTbSeg = LBM_TB_SEG;  // rows per segment
 // register state of one row of one column: h 0-8, low part of h_0, z 0-8, (phi u)
 constexpr int kH = 0, kLO = 9, kZ = 10, kPU = 19, kNS = 21;
 
-template <typename S, bool TILED>
+template <typename S, bool TILED, bool ALIGNED>
 __global__ __launch_bounds__(kTbMaxNx) void k_phase_tb2(PhaseK k, const S* __restrict__ A,
                                                         S* __restrict__ B, int seg) {
+    static_assert(TILED || ALIGNED, "whole rows are 64, 128, 192 or 256 columns");
     using C = S;
     constexpr bool RMASS = std::is_same<S, float>::value;
     using PL = PhasePlanes<S>;
@@ -766,15 +774,30 @@ __global__ __launch_bounds__(kTbMaxNx) void k_phase_tb2(PhaseK k, const S* __res
         const int r = v < 0 ? v + ny : (v >= ny ? v - ny : v);
         return base + (long long)r * nx;
     };
+    // value i of the node in column slot c (0: x, 1: x - 1, 2: x + 1) of row v
+    const unsigned xcol[3] = {x, xm, xp};
+    unsigned boff[3];  // ALIGNED: byte offset of value 0 of those columns within a row
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        boff[c] = unsigned(((xcol[c] >> 6) * PL::NPL * kBlk + (xcol[c] & (kBlk - 1))) * sizeof(S));
+    auto at = [&](auto* P, int v, int c, int i) {
+        if constexpr (ALIGNED) {
+            using B8 = std::conditional_t<std::is_const_v<std::remove_pointer_t<decltype(P)>>,
+                                          const char, char>;
+            auto* row = (B8*)P + (rowoff(v) >> 6) * (long long)(PL::NPL * kBlk * sizeof(S));
+            return (decltype(P))(row + boff[c]) + i * kBlk;
+        } else {
+            return P + pidx<S>(i, rowoff(v) + xcol[c]);
+        }
+    };
     auto load_row = [&](int v, C (&s)[kNS]) {
-        const long long n = rowoff(v) + x;
 #pragma unroll
-        for (int i = 0; i < 9; ++i) s[kH + i] = C(A[pidx<S>(PL::H + i, n)]);
+        for (int i = 0; i < 9; ++i) s[kH + i] = C(*at(A, v, 0, PL::H + i));
 #pragma unroll
-        for (int i = 0; i < 9; ++i) s[kZ + i] = C(A[pidx<S>(PL::Z + i, n)]);
-        s[kLO] = RMASS ? C(A[pidx<S>(PL::LO, n)]) : C(0);
-        s[kPU] = C(A[pidx<S>(PL::PU, n)]);
-        s[kPU + 1] = C(A[pidx<S>(PL::PU + 1, n)]);
+        for (int i = 0; i < 9; ++i) s[kZ + i] = C(*at(A, v, 0, PL::Z + i));
+        s[kLO] = RMASS ? C(*at(A, v, 0, PL::LO)) : C(0);
+        s[kPU] = C(*at(A, v, 0, PL::PU));
+        s[kPU + 1] = C(*at(A, v, 0, PL::PU + 1));
     };
     auto phi_of = [&](const C (&s)[kNS]) {
         const C hh[9] = {s[0], s[1], s[2], s[3], s[4], s[5], s[6], s[7], s[8]};
@@ -847,23 +870,21 @@ __global__ __launch_bounds__(kTbMaxNx) void k_phase_tb2(PhaseK k, const S* __res
             const PhaseLocal<C> L = phase_local(k, pn, z);
             phase_collide<S, C>(k, L, h, Ac[sm3][kLO], z, Ac[sm3][kPU], Ac[sm3][kPU + 1], hs, h0hi,
                                 h0lo, zst, pux, puy);
-            const long long n = rowoff(r) + x;
-            st(B + pidx<S>(PL::PU, n), S(pux));
-            st(B + pidx<S>(PL::PU + 1, n), S(puy));
-            st(B + pidx<S>(PL::H, n), h0hi);
-            if constexpr (RMASS) st(B + pidx<S>(PL::LO, n), h0lo);
-            st(B + pidx<S>(PL::Z, n), S(zst[0]));
+            st(at(B, r, 0, PL::PU), S(pux));
+            st(at(B, r, 0, PL::PU + 1), S(puy));
+            st(at(B, r, 0, PL::H), h0hi);
+            if constexpr (RMASS) st(at(B, r, 0, PL::LO), h0lo);
+            st(at(B, r, 0, PL::Z), S(zst[0]));
 #pragma unroll
             for (int i = 1; i < 9; ++i) {
                 const int ryd = r + EY[i];
                 if (walls && (ryd < 0 || ryd >= ny)) {
-                    st(B + pidx<S>(PL::H + OPP[i], n), S(hs[i]));
-                    st(B + pidx<S>(PL::Z + OPP[i], n), S(zst[i]));
+                    st(at(B, r, 0, PL::H + OPP[i]), S(hs[i]));
+                    st(at(B, r, 0, PL::Z + OPP[i]), S(zst[i]));
                 } else {
-                    const unsigned xd = EX[i] == 0 ? x : (EX[i] > 0 ? xp : xm);
-                    const long long d = rowoff(ryd) + xd;
-                    st(B + pidx<S>(PL::H + i, d), S(hs[i]));
-                    st(B + pidx<S>(PL::Z + i, d), S(zst[i]));
+                    const int c = EX[i] == 0 ? 0 : (EX[i] > 0 ? 2 : 1);
+                    st(at(B, ryd, c, PL::H + i), S(hs[i]));
+                    st(at(B, ryd, c, PL::Z + i), S(zst[i]));
                 }
             }
         }
@@ -1476,9 +1497,12 @@ int phase_tb2_seg(const PhaseK& k) {
     long long slots = 512;
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-        (tiled ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_phase_tb2<S, true>,
-                                                              kTbMaxNx, 0)
-               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_phase_tb2<S, false>,
+        (tiled ? (k.nx % kBlk == 0
+                      ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                            &per_cu, k_phase_tb2<S, true, true>, kTbMaxNx, 0)
+                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                            &per_cu, k_phase_tb2<S, true, false>, kTbMaxNx, 0))
+               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_phase_tb2<S, false, true>,
                                                               k.nx, 0)) == hipSuccess &&
         cus > 0 && per_cu > 0)
         slots = (long long)cus * per_cu;
@@ -1510,10 +1534,12 @@ hipError_t launch_phase_tb2(const PhaseK& k, const S* a, S* b, int seg, hipStrea
     const long long wgs = phase_tb2_workgroups(k, seg);
     if ((wgs + kXCD - 1) / kXCD * kXCD > 0x7fffffffLL) return hipErrorInvalidValue;
     dim3 grd(unsigned((wgs + kXCD - 1) / kXCD * kXCD));
-    if (phase_tb2_tiled(k))
-        hipLaunchKernelGGL((k_phase_tb2<S, true>), grd, dim3(kTbMaxNx), 0, s, k, a, b, seg);
+    if (!phase_tb2_tiled(k))
+        hipLaunchKernelGGL((k_phase_tb2<S, false, true>), grd, dim3(k.nx), 0, s, k, a, b, seg);
+    else if (k.nx % kBlk == 0)
+        hipLaunchKernelGGL((k_phase_tb2<S, true, true>), grd, dim3(kTbMaxNx), 0, s, k, a, b, seg);
     else
-        hipLaunchKernelGGL((k_phase_tb2<S, false>), grd, dim3(k.nx), 0, s, k, a, b, seg);
+        hipLaunchKernelGGL((k_phase_tb2<S, true, false>), grd, dim3(kTbMaxNx), 0, s, k, a, b, seg);
     return hipGetLastError();
 }
 
