@@ -60,12 +60,15 @@ struct Layout {
     size_t offSmall = 0, offFlags = 0, offWatch = 0, total = 0;
 };
 
-// Extra elements between population planes (a multiple of 64).  Planes whose
-// spacing is a power of two (a 256^3 box, a batch of 2^k 256^2 cells) start
-// at addresses congruent modulo every power of two up to the plane size, so
-// the 19-38 streams of a step hit the same HBM channels at once; a spacing of
-// 2^k + 64 KiB + 256 B (FP32) spreads them (256^3 D3Q19 step: 27.8 -> 31.0
-// GLUPS; 67 M-node single-step phase kernel: 2.45 -> 2.25 ms).
+// Extra elements per value array (a multiple of 64).  P = N rounded up to 64
+// plus this pad sizes each state buffer (nplanes P values, the node blocks at
+// its start) and spaces the planes of the FP64 staging fields and of the 1D
+// lattices.  When the states were stored as planes, planes a power of two
+// apart (a 256^3 box, a batch of 2^k 256^2 cells) started at addresses
+// congruent modulo every power of two up to the plane size, so the 19-38
+// streams of a step hit the same HBM channels at once, and this spacing
+// spread them (256^3 D3Q19 step: 27.8 -> 31.0 GLUPS; 67 M-node single-step
+// phase kernel: 2.45 -> 2.25 ms).
 #ifndef LBM_PLANE_PAD
 #define LBM_PLANE_PAD 16448
 #endif

@@ -1,7 +1,9 @@
 // HIP kernels of the dimensional LBM hot path for gfx950 (CDNA4, wave64).
 //
-// Data layout: structure of arrays, one plane per population, plane index
-// i * P + (b * ny + y) * nx + x (x fastest, P a multiple of 64 elements).
+// Data layout: node n = (b * ny + y) * nx + x (x fastest); the 2D states in
+// node blocks (value i of node n at bidx(npl, i, n): the npl values of 64
+// consecutive nodes together), the 1D lattices and the FP64 staging fields in
+// planes of stride P.
 // The stored state is the pre-collision ("post-streaming") population set;
 // each step reads a node's own populations (coalesced), collides in
 // registers and pushes the post-collision values to x + e_i in the other
