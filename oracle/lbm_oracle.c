@@ -1023,17 +1023,21 @@ void orc_phase_destroy(orc_phase* s) {
     free(s);
 }
 
-/* Planted-mistake switches, for the test that checks the transport pins
- * themselves: ORC_PLANT_HEQ_U multiplies the c_i.u term of Eq. heq_liang in
- * the collision and ORC_PLANT_DTPHIU the d_t(phi u) term of Eq.
- * source_term_interface.  Both are 1 in every build the oracle is used from;
- * only that test compiles copies with 0 (term dropped) or -1 (sign flipped)
- * and requires the pins to fail on them. */
+/* Planted-mistake switches, for the tests that check pins themselves:
+ * ORC_PLANT_HEQ_U multiplies the c_i.u term of Eq. heq_liang in the
+ * collision, ORC_PLANT_DTPHIU the d_t(phi u) term of Eq.
+ * source_term_interface (transport pins), and ORC_PLANT_FY the y component of
+ * the surface-tension force mu grad phi (symmetry pins).  All are 1 in every
+ * build the oracle is used from; only those tests compile copies with 0
+ * (term dropped) or -1 (sign flipped) and require the pins to fail on them. */
 #ifndef ORC_PLANT_HEQ_U
 #define ORC_PLANT_HEQ_U 1.0
 #endif
 #ifndef ORC_PLANT_DTPHIU
 #define ORC_PLANT_DTPHIU 1.0
+#endif
+#ifndef ORC_PLANT_FY
+#define ORC_PLANT_FY 1.0
 #endif
 
 /* s_i(u) of Eq. s_i_Liang */
@@ -1112,7 +1116,7 @@ static void phase_node(const orc_phase* s, int x, int y, phase_macro* m) {
     m->mu = 4.0 * s->beta * phi * (phi - 1.0) * (phi - 0.5) - s->kappa * lap;
     /* F = F_s + F_b with F_s = mu grad phi */
     m->Fx = m->mu * gx + p->Fbx;
-    m->Fy = m->mu * gy + p->Fby;
+    m->Fy = ORC_PLANT_FY * m->mu * gy + p->Fby;
     double jx = 0, jy = 0, zsum = 0;
     for (int i = 0; i < 9; ++i) {
         double zi = s->z[PIDX(s, i, x, y)];

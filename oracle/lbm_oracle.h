@@ -17,8 +17,10 @@
  * Pins: the CPU tests hold these functions to closed forms, printed values,
  * invariants and brute force.  Parity unpinned (no closed form or printed
  * value exists; only the kernel-oracle comparison holds them):
- *   - orc_chan_* with flux_amp != 0: the mean Nu of the oscillating flux;
- *   - orc_phase_*: the spurious-current pattern around a bubble;
+ *   - orc_chan_* with flux_amp != 0: the mean Nu of the oscillating flux
+ *     (the flux modulation itself is pinned by the exact wall energy input);
+ *   - orc_phase_*: the magnitude of the spurious currents around a bubble
+ *     (their square symmetry is pinned by the mirror and transpose tests);
  *   - orc_chan_adjoint: the gradients with respect to the relaxation times
  *     (held by central differences of the oracle's own forward run and by
  *     the hand-written FP64 adjoint, not by an independent value).

@@ -6,12 +6,15 @@ conservation invariants, the dimensional == conventional claim, and symmetry.
 """
 import json
 import os
+import shutil
+import tempfile
 from fractions import Fraction
 
 import numpy as np
 import pytest
 
 import oracle as O
+from oracle import build as OB
 from paper_2302_04120_amd import workloads as WL
 
 from lattice_units import chan_to_lattice, phase_to_lattice
@@ -468,6 +471,81 @@ def test_mirror_symmetry_two_phase():
     np.testing.assert_allclose(ma["phi"], mb["phi"][:, ::-1], atol=1e-13)
     np.testing.assert_allclose(ma["ux"], -mb["ux"][:, ::-1], atol=1e-13 * np.abs(ma["ux"]).max() + 1e-17)
     np.testing.assert_allclose(ma["p"], mb["p"][:, ::-1], atol=1e-10 * np.abs(ma["p"]).max())
+
+
+def transposed_runs(qy_printed=0, variant=None, n=20, steps=50):
+    """A random two-phase state and its transpose (velocity components
+    exchanged) on a square periodic grid, both stepped; returns the largest
+    deviation from transpose symmetry of u (relative), phi and p (relative)."""
+    prm, ini, _ = WL.bubble(n=n, radii=(5,), batch=1, seed=4)
+    prm = dict(prm, qy_printed=qy_printed)
+    g = WL.rng(11)
+    ux0 = g.uniform(-1e-3, 1e-3, (n, n))
+    uy0 = g.uniform(-1e-3, 1e-3, (n, n))
+    phi0, p0 = ini["phi"][0], g.uniform(0.0, 50.0, (n, n))
+    a = O.Phase(n, n, prm, variant=variant)
+    a.init(phi0, p0, ux0, uy0)
+    b = O.Phase(n, n, prm, variant=variant)
+    b.init(phi0.T.copy(), p0.T.copy(), uy0.T.copy(), ux0.T.copy())
+    a.step(steps)
+    b.step(steps)
+    ma, mb = a.macros(), b.macros()
+    umax = max(np.abs(ma["ux"]).max(), np.abs(ma["uy"]).max())
+    du = max(np.abs(ma["ux"] - mb["uy"].T).max(), np.abs(ma["uy"] - mb["ux"].T).max()) / umax
+    return (du, np.abs(ma["phi"] - mb["phi"].T).max(),
+            np.abs(ma["p"] - mb["p"].T).max() / np.abs(ma["p"]).max())
+
+
+def mirrored_runs(variant=None, n=20, steps=50):
+    """The mirror test's runs (x mirrored); returns the largest deviation from
+    mirror symmetry of u_x (relative) and phi."""
+    prm, ini, _ = WL.bubble(n=n, radii=(5,), batch=1, seed=2)
+    g = WL.rng(9)
+    ux0 = g.uniform(-1e-3, 1e-3, (n, n))
+    uy0 = g.uniform(-1e-3, 1e-3, (n, n))
+    a = O.Phase(n, n, prm, variant=variant)
+    a.init(ini["phi"][0], ini["p"][0], ux0, uy0)
+    b = O.Phase(n, n, prm, variant=variant)
+    b.init(ini["phi"][0][:, ::-1].copy(), ini["p"][0][:, ::-1].copy(), -ux0[:, ::-1].copy(),
+           uy0[:, ::-1].copy())
+    a.step(steps)
+    b.step(steps)
+    ma, mb = a.macros(), b.macros()
+    return (np.abs(ma["ux"] + mb["ux"][:, ::-1]).max() / np.abs(ma["ux"]).max(),
+            np.abs(ma["phi"] - mb["phi"][:, ::-1]).max())
+
+
+@pytest.mark.parametrize("qy_printed", [0, 1])
+def test_transpose_symmetry_two_phase(qy_printed):
+    """Swapping x and y (the state transposed, the velocity components
+    exchanged) gives the transposed result on a square periodic grid: every
+    stencil, force and moment acts on its own axis with the same weight.  The
+    mirror test cannot see a mistake confined to one axis that keeps the
+    x-parity (a sign or factor on a y component); this one can.  The reading
+    of the two-phase MRT rates (omega_q2 on q_x and q_y, Sec. 2.3 and Sec. 3)
+    keeps the square symmetry; the printed rates (1/dt on q_y) break it."""
+    du, dphi, dp = transposed_runs(qy_printed)
+    if qy_printed:
+        assert du > 1e-4
+        return
+    assert du < 1e-12 and dphi < 1e-13 and dp < 1e-10
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="gcc not available")
+def test_transpose_pin_fails_on_a_planted_axis_mistake():
+    """The y component of the surface-tension force with its sign flipped (an
+    oracle copy built with ORC_PLANT_FY = -1) keeps the mirror symmetry in x
+    but must fail the transpose pin."""
+    d = tempfile.mkdtemp()
+    try:
+        path = OB.build_variant(os.path.join(d, "orc_fy.so"), {"ORC_PLANT_FY": "-1.0"})
+        du_m, dphi_m = mirrored_runs(variant=path)
+        du, dphi, dp = transposed_runs(variant=path)
+        print("planted: mirror", du_m, dphi_m, "transpose", du, dphi, dp)
+        assert du_m < 1e-12 and dphi_m < 1e-13  # the mirror pin does not see it
+        assert du > 1e-4  # the transpose pin does
+    finally:
+        shutil.rmtree(d)
 
 
 def test_mirror_symmetry_channel_walls():
