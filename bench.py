@@ -619,8 +619,8 @@ def main():
              "k_phase<%s>" % {"fp32": "float,float,false", "fp64": "double,double,false",
                               "fp32_arith64": "float,double,false"}[args.prec])
     launch_ms = r["kernel_ms"] * spl
-    # Bytes one launch must move: the stored state (21 FP32 planes: h, the low
-    # part of h_0, z and (phi u)) read once and written once per node, whatever
+    # Bytes one launch must move: the stored state (21 FP32 values per node: h,
+    # the low part of h_0, z and (phi u)) read once and written once, whatever
     # the number of steps the launch performs -- bpl x nodes.  The two-step
     # kernel keeps the intermediate state on chip, so per lattice update it
     # needs bpl / 2; the step-equivalent rate (bpl per update) is reported
@@ -642,7 +642,7 @@ def main():
         s64 = max(20, args.steps // 4) // 2 * 2
         r64 = run_gpu(max(1, args.batch // 4), s64, 6, "fp64", fusion=args.fusion)
         extras["fp64_mlups"] = r64["nodes"] * s64 / r64["wall"] / 1e6
-        # the state (20 FP64 planes) once in and once out per launch of spl steps
+        # the state (20 FP64 values per node) once in and once out per launch of spl steps
         l64 = r64["kernel_ms"] * spl * 1e-3
         extras["fp64_hbm_frac"] = BYTES_PER_LU["fp64"] * r64["nodes"] / l64 / 1e9 / HBM_PEAK_GBS
         extras["fp64_step_equivalent_GBps"] = BYTES_PER_LU["fp64"] * r64["nodes"] * spl / l64 / 1e9
