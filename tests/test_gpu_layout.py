@@ -19,10 +19,10 @@ from gpu_cases import print_case
 pytestmark = pytest.mark.gpu
 
 
-def _phase(prec):
+def _phase(prec, nx=37, ny=23, batch=2):
     from paper_2302_04120_amd import lbm
-    nx, ny, batch = 37, 23, 2  # 1702 nodes: 26 full blocks and 38 nodes
-    prm, ini, _ = WL.bubble(n=nx, ny=ny, radii=(7,), batch=batch, seed=3)
+    # default 1702 nodes: 26 full blocks and 38 nodes
+    prm, ini, _ = WL.bubble(n=nx, ny=ny, radii=(min(7, nx // 3, ny // 3),), batch=batch, seed=3)
 
     def make():
         L = lbm.Lattice("phase", nx, ny, batch=batch, prec=prec)
@@ -71,7 +71,10 @@ def _p3(prec):
     return make, nx * ny * nz, (42 if prec == "fp32" else 41)
 
 
-CASES = {"phase": _phase, "channel": _chan, "d3q19": _d3, "phase3d": _p3}
+CASES = {"phase": _phase, "channel": _chan, "d3q19": _d3, "phase3d": _p3,
+         # 35 nodes: only a partial block; 128 nodes: two full blocks, no partial one
+         "phase_35": lambda prec: _phase(prec, 7, 5, 1),
+         "phase_128": lambda prec: _phase(prec, 16, 8, 1)}
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
