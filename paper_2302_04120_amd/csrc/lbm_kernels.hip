@@ -36,23 +36,24 @@ template <int QT, typename C> __device__ __forceinline__ C twt(int i) {
 
 // One step of the channel model: D2Q9 flow (BGK or dimensional MRT, Guo
 // forcing, optional Boussinesq force) + D2Q5 or D2Q9 temperature.  Tiles of
-// 64 x 4 nodes.  y: periodic (bcy 0), halfway walls (1), or a wall at y- and
-// the symmetry plane of Eq. simetria at y+ (2).  x: periodic (bcx 0), velocity
-// inlet + pressure outlet (1), fixed-temperature walls (2).
-template <typename S, int QT, int CTY = 4>
-__global__ __launch_bounds__(64 * CTY) void k_chan_step(ChanK k, const S* __restrict__ A,
+// 64 nodes of one row (one wave each).  y: periodic (bcy 0), halfway walls
+// (1), or a wall at y- and the symmetry plane of Eq. simetria at y+ (2).  x:
+// periodic (bcx 0), velocity inlet + pressure outlet (1), fixed-temperature
+// walls (2).
+template <typename S, int QT>
+__global__ __launch_bounds__(64) void k_chan_step(ChanK k, const S* __restrict__ A,
                                                         S* __restrict__ B, const S* __restrict__ qw,
                                                         const S* __restrict__ uin,
                                                         const S* __restrict__ tin, S mod) {
     using C = S;
     const int nx = k.nx, ny = k.ny;
-    const int gx = (nx + 63) / 64, gy = (ny + CTY - 1) / CTY;
+    const int gx = (nx + 63) / 64;
     int tile;
-    if (!xcd_tile(gx * gy * k.batch, tile)) return;
-    const int b = tile / (gx * gy), r = tile - b * gx * gy;
+    if (!xcd_tile(gx * ny * k.batch, tile)) return;
+    const int b = tile / (gx * ny), r = tile - b * gx * ny;
     const int x = (r % gx) * 64 + threadIdx.x;
-    const int y = (r / gx) * CTY + threadIdx.y;
-    if (x >= nx || y >= ny) return;
+    const int y = r / gx;
+    if (x >= nx) return;
     const int npl = k.npl;  // node blocks: f 0-8, g 9 .. 9 + QT - 1
     const long long base = (long long)b * ny * nx;
     const long long n = base + (long long)y * nx + x;
@@ -1323,33 +1324,23 @@ inline unsigned grid1(long long N, int bs) {
 // ---------------------------------------------------------------------------
 // launch wrappers
 // ---------------------------------------------------------------------------
-// Grids of fewer than LBM_CHAN_SMALL_TILES 64 x 4 tiles (the paper-sized
-// channels) run on one-row tiles, which spread them over more CUs: C2's
-// 800 x 40 under graph replay 5.37 -> 5.15 us per step, C5's 1600 x 80
-// 6.37 -> 6.23 us (two-row tiles: 5.27 and 6.15); large grids keep 64 x 4.
-#ifndef LBM_CHAN_SMALL_TILES
-#define LBM_CHAN_SMALL_TILES 4096
-#endif
-#ifndef LBM_CHAN_SMALL_TY
-#define LBM_CHAN_SMALL_TY 1
-#endif
+// The channel step runs on one-row tiles (64 x 1, one wave per workgroup) at
+// every size.  On the paper-sized channels they spread the grid over more CUs
+// than 64 x 4 tiles (C2's 800 x 40 under graph replay 5.37 -> 5.15 us per
+// step, C5's 1600 x 80 6.37 -> 6.23 us; two-row tiles 5.27 and 6.15), and on
+// the 16384 x 2048 grid the step takes 0.715-0.723 ms against 0.728-0.737 ms
+// with 64 x 4 tiles (64 x 2: 0.715-0.722; 64 x 8: 0.771; 64 x 4 capped at
+// four or three workgroups per CU by an LDS reserve: 0.793 and 1.236 ms).
 template <typename S>
 hipError_t launch_chan_step(const ChanK& k, const S* a, S* b, const S* qw, const S* uin,
                             const S* tin, double mod, hipStream_t s) {
-    auto go = [&](auto k9, auto k5, int ty) {
-        const long long tiles = (long long)((k.nx + 63) / 64) * ((k.ny + ty - 1) / ty) * k.batch;
-        dim3 blk(64, ty), grd(unsigned((tiles + kXCD - 1) / kXCD * kXCD));
-        if (k.tq == 9)
-            hipLaunchKernelGGL(k9, grd, blk, 0, s, k, a, b, qw, uin, tin, S(mod));
-        else
-            hipLaunchKernelGGL(k5, grd, blk, 0, s, k, a, b, qw, uin, tin, S(mod));
-        return hipGetLastError();
-    };
-    const long long tiles4 = (long long)((k.nx + 63) / 64) * ((k.ny + 3) / 4) * k.batch;
-    if (tiles4 < LBM_CHAN_SMALL_TILES)
-        return go(k_chan_step<S, 9, LBM_CHAN_SMALL_TY>, k_chan_step<S, 5, LBM_CHAN_SMALL_TY>,
-                  LBM_CHAN_SMALL_TY);
-    return go(k_chan_step<S, 9>, k_chan_step<S, 5>, 4);
+    const long long tiles = (long long)((k.nx + 63) / 64) * k.ny * k.batch;
+    dim3 blk(64), grd(unsigned((tiles + kXCD - 1) / kXCD * kXCD));
+    if (k.tq == 9)
+        hipLaunchKernelGGL((k_chan_step<S, 9>), grd, blk, 0, s, k, a, b, qw, uin, tin, S(mod));
+    else
+        hipLaunchKernelGGL((k_chan_step<S, 5>), grd, blk, 0, s, k, a, b, qw, uin, tin, S(mod));
+    return hipGetLastError();
 }
 
 // FP32 steps run on 256-node tiles, four resident per CU (kPhaseLdsReserve).
