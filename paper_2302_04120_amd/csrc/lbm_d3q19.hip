@@ -25,15 +25,14 @@
 #include "lbm_d3q19.h"
 #include "lbm_device.h"
 
+// Rows of 64 nodes per workgroup.  Measured on the 256^3 box with the state in
+// node blocks (ms per FP32 step): 64 x 4 0.489, 64 x 2 0.490, 64 x 1 0.497;
+// FP64 0.937-0.942 for all three.  Capping residency at 4 waves per SIMD by
+// an LDS reserve, which helped when the state was stored as planes (0.541 ->
+// 0.522 ms), now costs time (64 x 4: 0.502-0.504 ms; 64 x 2 0.515, 64 x 1
+// 0.505), so every workgroup takes only the LDS it uses (none).
 #ifndef LBM_D3_TY
 #define LBM_D3_TY 4
-#endif
-// LDS reserved by each FP32 workgroup (it uses none): it caps residency at
-// four 256-thread workgroups per CU, 4 waves per SIMD instead of 6, and
-// with fewer population streams open at once the step runs faster (256^3:
-// 0.541 -> 0.522 ms).  The FP64 kernel's registers already allow only 3.
-#ifndef LBM_D3_LDS
-#define LBM_D3_LDS 40960
 #endif
 
 namespace lbm {
@@ -204,8 +203,7 @@ template <typename S>
 hipError_t launch_d3_step(const D3K& k, const S* fc, S* fn, hipStream_t s) {
     const long long tiles = d3_tiles(k);
     dim3 blk(64, kD3Ty), grd(unsigned((tiles + kXCD - 1) / kXCD * kXCD));
-    const unsigned lds = std::is_same<S, float>::value ? LBM_D3_LDS : 0u;
-    hipLaunchKernelGGL(k_d3_step<S>, grd, blk, lds, s, k, fc, fn);
+    hipLaunchKernelGGL(k_d3_step<S>, grd, blk, 0, s, k, fc, fn);
     return hipGetLastError();
 }
 
