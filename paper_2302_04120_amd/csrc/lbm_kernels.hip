@@ -1473,6 +1473,15 @@ double phase_tb2_lane_use(const PhaseK& k) {
     return phase_tb2_tiled(k) ? double(k.nx) / (double(phase_tb2_ntx(k)) * kTbMaxNx) : 1.0;
 }
 
+// Whether the two-step kernel addresses rows through a scalar block base and
+// 32-bit lane offsets: nx a multiple of 64, and the byte offset of the last
+// column within a row's node blocks (nx values per state value) below 2^31.
+template <typename S>
+bool phase_tb2_aligned(const PhaseK& k) {
+    return k.nx % kBlk == 0 &&
+           (long long)k.nx * PhasePlanes<S>::NPL * (long long)sizeof(S) < (1LL << 31);
+}
+
 // Rows per segment.  Every workgroup marches seg + 5 rows (its segment, two
 // rows of overlap below and three of lag above), all workgroups take the
 // same time, and the GPU holds `slots` of them at once, so a launch costs
@@ -1490,7 +1499,7 @@ int phase_tb2_seg(const PhaseK& k) {
     long long slots = 512;
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-        (tiled ? (k.nx % kBlk == 0
+        (tiled ? (phase_tb2_aligned<S>(k)
                       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
                             &per_cu, k_phase_tb2<S, true, true>, kTbMaxNx, 0)
                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(
@@ -1529,7 +1538,7 @@ hipError_t launch_phase_tb2(const PhaseK& k, const S* a, S* b, int seg, hipStrea
     dim3 grd(unsigned((wgs + kXCD - 1) / kXCD * kXCD));
     if (!phase_tb2_tiled(k))
         hipLaunchKernelGGL((k_phase_tb2<S, false, true>), grd, dim3(k.nx), 0, s, k, a, b, seg);
-    else if (k.nx % kBlk == 0)
+    else if (phase_tb2_aligned<S>(k))
         hipLaunchKernelGGL((k_phase_tb2<S, true, true>), grd, dim3(kTbMaxNx), 0, s, k, a, b, seg);
     else
         hipLaunchKernelGGL((k_phase_tb2<S, true, false>), grd, dim3(kTbMaxNx), 0, s, k, a, b, seg);
