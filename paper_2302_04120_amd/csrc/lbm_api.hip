@@ -266,7 +266,6 @@ hipError_t step_once(lbm_ctx* c) {
     const int lat = c->desc.lattice;
     S* a = (S*)bufA(c);
     S* b = (S*)bufB(c);
-    const long long P = c->P;
     if (lat == LBM_D3Q19) return launch_d3_step<S>(c->d3k, a, b, c->stream);
     if (lat == LBM_D3Q19_PHASE) return launch_p3_step<S>(c->p3k, a, b, (S*)c->phi3, c->stream);
     if (lat == LBM_D2Q9_D2Q5) {
@@ -1157,7 +1156,6 @@ lbm_status lbm_nusselt(lbm_ctx* c, int x_dev, double* Tb, double* Tw, double* Nu
     double* dNu = c->small + 2 * nx;
     double* dres = c->small + 3 * nx;
     const double qsi = c->dx * c->rho_cp / c->dt * flux_mod(c);
-    const long long P = c->P;
     hipError_t e;
     if (c->desc.prec == LBM_FP64) {
         const double* a = (const double*)bufA(c);

@@ -58,7 +58,6 @@ __global__ __launch_bounds__(64 * kD3Ty) void k_d3_step(D3K k, const S* __restri
     const int x = (r % gx) * 64 + threadIdx.x;
     const int y = (r / gx) * kD3Ty + threadIdx.y;
     if (x >= nx || y >= ny) return;
-    const long long P = k.P;
     const long long plane = (long long)nx * ny;
     const long long base = (long long)(bz - z) * plane;  // first node of the replica
     const long long n = base + (long long)z * plane + (long long)y * nx + x;

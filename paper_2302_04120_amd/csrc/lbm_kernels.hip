@@ -711,11 +711,12 @@ __global__ __launch_bounds__(TX * TY) void k_phase_persist(PhaseK k, S* __restri
 // never used.  The stored columns of neighbouring tiles are disjoint, and
 // every destination slot is still written by exactly one source node.
 //
-// ALIGNED (nx a multiple of 64): every row starts on a node-block boundary,
-// so value i of column c in row v lies at the row's block base (uniform over
-// the workgroup: scalar registers) plus the column's offset within the row's
-// blocks (per lane, fixed for x, x - 1 and x + 1) plus i blocks of 64
-// values, and no access needs per-lane 64-bit index arithmetic.  Other widths
+// ALIGNED (nx a multiple of 64, a row's node blocks under 2 GiB:
+// phase_tb2_aligned): every row starts on a node-block boundary, so value i of
+// column c in row v lies at the row's block base (uniform over the workgroup:
+// scalar registers) plus the column's byte offset within the row's blocks
+// (per lane, 32 bits, fixed for x, x - 1 and x + 1) plus i blocks of 64
+// values, and no access needs per-lane 64-bit index arithmetic.  Other rows
 // take the general node-block index.
 // ---------------------------------------------------------------------------
 constexpr int kTbMaxNx = 256;
