@@ -134,14 +134,10 @@ __device__ __forceinline__ int wrap(int v, int n) {
 // D2Q9 flow + D2Q5 temperature: one node per thread
 // ---------------------------------------------------------------------------
 
-// lattice-normalised macros of one node from its deviation populations (the
-// f values 0-8 of a node-blocked state of npl values per node)
-template <typename C, typename S>
-__device__ __forceinline__ void chan_flow_macros(const S* __restrict__ f, int npl, long long n,
-                                                 C rho_ref, C ftx, C fty, C d[9], C& drho,
-                                                 C& rho, C& ux, C& uy) {
-#pragma unroll
-    for (int i = 0; i < 9; ++i) d[i] = C(f[bidx(npl, i, n)]);
+// lattice-normalised macros of one node from its deviation populations d
+template <typename C>
+__device__ __forceinline__ void chan_flow_macros_v(const C d[9], C rho_ref, C ftx, C fty, C& drho,
+                                                   C& rho, C& ux, C& uy) {
     drho = ((d[0] + (d[1] + d[3])) + (d[2] + d[4])) + ((d[5] + d[7]) + (d[6] + d[8]));
     rho = rho_ref + drho;
     const C jx = (d[1] - d[3]) + ((d[5] - d[7]) + (d[8] - d[6]));
@@ -149,6 +145,17 @@ __device__ __forceinline__ void chan_flow_macros(const S* __restrict__ f, int np
     const C ir = C(1) / rho;
     ux = (jx + C(0.5) * ftx) * ir;  // Eq. first_moment_f, divided by c
     uy = (jy + C(0.5) * fty) * ir;
+}
+
+// the same from the f values 0-8 of a node-blocked state of npl values per
+// node (d receives them)
+template <typename C, typename S>
+__device__ __forceinline__ void chan_flow_macros(const S* __restrict__ f, int npl, long long n,
+                                                 C rho_ref, C ftx, C fty, C d[9], C& drho,
+                                                 C& rho, C& ux, C& uy) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) d[i] = C(f[bidx(npl, i, n)]);
+    chan_flow_macros_v<C>(d, rho_ref, ftx, fty, drho, rho, ux, uy);
 }
 
 // Lattice body force at a node whose temperature is T = T_ref + th: the

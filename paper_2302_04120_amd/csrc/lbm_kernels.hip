@@ -34,51 +34,27 @@ template <int QT, typename C> __device__ __forceinline__ C twt(int i) {
     return QT == 9 ? wgt<C>(i) : wgt5<C>(i);
 }
 
-// One step of the channel model: D2Q9 flow (BGK or dimensional MRT, Guo
-// forcing, optional Boussinesq force) + D2Q5 or D2Q9 temperature.  Tiles of
-// 64 nodes of one row (one wave each).  y: periodic (bcy 0), halfway walls
-// (1), or a wall at y- and the symmetry plane of Eq. simetria at y+ (2).  x:
-// periodic (bcx 0), velocity inlet + pressure outlet (1), fixed-temperature
-// walls (2).
-template <typename S, int QT>
-__global__ __launch_bounds__(64) void k_chan_step(ChanK k, const S* __restrict__ A,
-                                                        S* __restrict__ B, const S* __restrict__ qw,
-                                                        const S* __restrict__ uin,
-                                                        const S* __restrict__ tin, S mod) {
-    using C = S;
-    const int nx = k.nx, ny = k.ny;
-    const int gx = (nx + 63) / 64;
-    int tile;
-    if (!xcd_tile(gx * ny * k.batch, tile)) return;
-    const int b = tile / (gx * ny), r = tile - b * gx * ny;
-    const int x = (r % gx) * 64 + threadIdx.x;
-    const int y = r / gx;
-    if (x >= nx) return;
-    const int npl = k.npl;  // node blocks: f 0-8, g 9 .. 9 + QT - 1
-    const long long base = (long long)b * ny * nx;
-    const long long n = base + (long long)y * nx + x;
-    const C rho_ref = C(k.rho_ref);
-    const C qdt = C(k.qdt);
+// ---- per-node pieces of the channel step, shared by the one- and two-step
+//      kernels so that both round identically
+// T - T_ref of a node from its (deviation) thermal populations, with the half
+// source (Eq. zero_moment_g)
+template <int QT, typename C>
+__device__ __forceinline__ C chan_th(const C (&e)[QT], C qdt) {
+    if constexpr (QT == 9)
+        return ((e[0] + (e[1] + e[3]) + (e[2] + e[4])) + ((e[5] + e[7]) + (e[6] + e[8]))) +
+               C(0.5) * qdt;
+    else
+        return (e[0] + (e[1] + e[3]) + (e[2] + e[4])) + C(0.5) * qdt;
+}
 
-    // temperature first: the Boussinesq force depends on it
-    C e[QT], th = C(0);
-    if (k.thermal) {
-#pragma unroll
-        for (int i = 0; i < QT; ++i) e[i] = C(A[bidx(npl, 9 + i, n)]);
-        if constexpr (QT == 9)
-            th = ((e[0] + (e[1] + e[3]) + (e[2] + e[4])) + ((e[5] + e[7]) + (e[6] + e[8]))) +
-                 C(0.5) * qdt;  // Eq. zero_moment_g
-        else
-            th = (e[0] + (e[1] + e[3]) + (e[2] + e[4])) + C(0.5) * qdt;
-    }
-    C ftx, fty;
-    chan_force(k, th, ftx, fty);
-
-    C d[9], drho, rho, ux, uy;
-    chan_flow_macros<C, S>(A, npl, n, rho_ref, ftx, fty, d, drho, rho, ux, uy);
-
-    // ---- momentum collision (Eq. colisao_MRT or Eq. eq_lattice_boltzmann_BGK)
-    C ds[9];
+// Both collisions of a node: ds from the deviations d (Eq. colisao_MRT or Eq.
+// eq_lattice_boltzmann_BGK with Guo forcing; a frozen flow keeps d), es from
+// the thermal populations e (Sec. 2.2 and Sec. 3, advective part built on
+// T - T_ref, in moment space with the rates Lt).
+template <typename C, int QT>
+__device__ __forceinline__ void chan_collide(const ChanK& k, const C (&d)[9], C drho, C rho, C ux,
+                                             C uy, C ftx, C fty, const C (&e)[QT], C th, C qdt,
+                                             C (&ds)[9], C (&es)[QT]) {
     if (k.flow) {
         const C uu = ux * ux + uy * uy;
         C neq[9], fh[9];
@@ -113,10 +89,6 @@ __global__ __launch_bounds__(64) void k_chan_step(ChanK k, const S* __restrict__
 #pragma unroll
         for (int i = 0; i < 9; ++i) ds[i] = d[i];
     }
-
-    // ---- temperature collision (Sec. 2.2 and Sec. 3), advective part built on
-    //      T - T_ref, in moment space with the rates Lt
-    C es[QT];
     if (k.thermal) {
         C neq[QT], m[QT], dm[QT], dv[QT];
 #pragma unroll
@@ -146,6 +118,76 @@ __global__ __launch_bounds__(64) void k_chan_step(ChanK k, const S* __restrict__
 #pragma unroll
         for (int i = 0; i < QT; ++i) es[i] = e[i] + dv[i];
     }
+}
+
+// Values a boundary rule puts into the node's opposite slot OPP[i] for a
+// population i that leaves the domain:
+// moving-wall bounce-back with the inlet profile u_in (Eq. BB_vel)
+template <typename C>
+__device__ __forceinline__ C chan_inlet_f(int i, C dsi, C rho_ref, C uin) {
+    return dsi - C(6) * wgt<C>(i) * rho_ref * (C(EX[i]) * uin);
+}
+// anti-bounce-back pressure outlet with the wall velocity u_w (Eq.
+// anti_BB_vel, rho_w = rho_ref)
+template <typename C>
+__device__ __forceinline__ C chan_outlet_f(int i, C dsi, C rho_ref, C uwx, C uwy) {
+    const C eu = C(EX[i]) * uwx + C(EY[i]) * uwy;
+    return -dsi + C(2) * wgt<C>(i) * rho_ref * (C(4.5) * eu * eu - C(1.5) * (uwx * uwx + uwy * uwy));
+}
+// prescribed wall flux q (scaled, times the time modulation mod), Eq. BB_T
+// with lambda_i = 6 w_i (1 on D2Q5), into slot topp(i)
+template <int QT, typename C>
+__device__ __forceinline__ C chan_flux_g(int i, C esi, C q, C mod) {
+    const C lam = QT == 9 ? C(6) * wgt<C>(i) : C(1);
+    return esi + lam * q * mod;
+}
+// anti-bounce-back fixed temperature tw (deviation form, Eq. anti_BB_T), into
+// slot topp(i)
+template <int QT, typename C>
+__device__ __forceinline__ C chan_antibb_g(int i, C esi, C tw) {
+    return -esi + C(2) * twt<QT, C>(i) * tw;
+}
+
+// One step of the channel model: D2Q9 flow (BGK or dimensional MRT, Guo
+// forcing, optional Boussinesq force) + D2Q5 or D2Q9 temperature.  Tiles of
+// 64 nodes of one row (one wave each).  y: periodic (bcy 0), halfway walls
+// (1), or a wall at y- and the symmetry plane of Eq. simetria at y+ (2).  x:
+// periodic (bcx 0), velocity inlet + pressure outlet (1), fixed-temperature
+// walls (2).
+template <typename S, int QT>
+__global__ __launch_bounds__(64) void k_chan_step(ChanK k, const S* __restrict__ A,
+                                                        S* __restrict__ B, const S* __restrict__ qw,
+                                                        const S* __restrict__ uin,
+                                                        const S* __restrict__ tin, S mod) {
+    using C = S;
+    const int nx = k.nx, ny = k.ny;
+    const int gx = (nx + 63) / 64;
+    int tile;
+    if (!xcd_tile(gx * ny * k.batch, tile)) return;
+    const int b = tile / (gx * ny), r = tile - b * gx * ny;
+    const int x = (r % gx) * 64 + threadIdx.x;
+    const int y = r / gx;
+    if (x >= nx) return;
+    const int npl = k.npl;  // node blocks: f 0-8, g 9 .. 9 + QT - 1
+    const long long base = (long long)b * ny * nx;
+    const long long n = base + (long long)y * nx + x;
+    const C rho_ref = C(k.rho_ref);
+    const C qdt = C(k.qdt);
+
+    // temperature first: the Boussinesq force depends on it
+    C e[QT], th = C(0);
+    if (k.thermal) {
+#pragma unroll
+        for (int i = 0; i < QT; ++i) e[i] = C(A[bidx(npl, 9 + i, n)]);
+        th = chan_th<QT, C>(e, qdt);
+    }
+    C ftx, fty;
+    chan_force(k, th, ftx, fty);
+
+    C d[9], drho, rho, ux, uy;
+    chan_flow_macros<C, S>(A, npl, n, rho_ref, ftx, fty, d, drho, rho, ux, uy);
+    C ds[9], es[QT];
+    chan_collide<C, QT>(k, d, drho, rho, ux, uy, ftx, fty, e, th, qdt, ds, es);
 
     // ---- outlet wall velocity: 1.5 u(x_b) - 0.5 u(x_b - 1) at time t
     C uwx = C(0), uwy = C(0);
@@ -187,17 +229,12 @@ __global__ __launch_bounds__(64) void k_chan_step(ChanK k, const S* __restrict__
                 B[bidx(npl, j, base + (long long)ty * nx + tx)] = S(ds[i]);
             } else {
                 C v;
-                if (outy || k.bcx == 2) {
+                if (outy || k.bcx == 2)
                     v = ds[i];  // halfway bounce-back, Eq. BB_vel with u_w = 0
-                } else if (tx < 0) {
-                    // moving-wall bounce-back with the inlet profile, Eq. BB_vel
-                    v = ds[i] - C(6) * wgt<C>(i) * rho_ref * (C(EX[i]) * C(uin[y]));
-                } else {
-                    // anti-bounce-back pressure outlet, Eq. anti_BB_vel, rho_w = rho_ref
-                    const C eu = C(EX[i]) * uwx + C(EY[i]) * uwy;
-                    v = -ds[i] + C(2) * wgt<C>(i) * rho_ref *
-                                     (C(4.5) * eu * eu - C(1.5) * (uwx * uwx + uwy * uwy));
-                }
+                else if (tx < 0)
+                    v = chan_inlet_f<C>(i, ds[i], rho_ref, C(uin[y]));
+                else
+                    v = chan_outlet_f<C>(i, ds[i], rho_ref, uwx, uwy);
                 B[bidx(npl, OPP[i], n)] = S(v);
             }
         }
@@ -228,18 +265,16 @@ __global__ __launch_bounds__(64) void k_chan_step(ChanK k, const S* __restrict__
             if (!outy && !outx) {
                 put(j, wrap(tx, nx), wrap(ty, ny), es[i]);
             } else if (outy) {
-                // prescribed flux, Eq. BB_T with lambda_i = 6 w_i (1 on D2Q5)
-                const C lam = QT == 9 ? C(6) * wgt<C>(i) : C(1);
-                put(topp<QT>(i), x, y, es[i] + lam * C(qw[x]) * C(mod));
+                put(topp<QT>(i), x, y, chan_flux_g<QT, C>(i, es[i], C(qw[x]), C(mod)));
             } else if (k.bcx == 2) {
-                // fixed-temperature side wall (App. D): Eq. anti_BB_T (deviation form)
-                put(topp<QT>(i), x, y, -es[i] + C(2) * twt<QT, C>(i) * C(k.Tw[tx < 0 ? 0 : 1]));
+                // fixed-temperature side wall (App. D)
+                put(topp<QT>(i), x, y, chan_antibb_g<QT, C>(i, es[i], C(k.Tw[tx < 0 ? 0 : 1])));
             } else if (tx < 0) {
-                // anti-bounce-back Dirichlet inlet, Eq. anti_BB_T (deviation form),
-                // T_w where the link crosses the inlet (between rows y and y + c_y)
+                // anti-bounce-back Dirichlet inlet, T_w where the link crosses
+                // the inlet (between rows y and y + c_y)
                 const int y2 = y + tey<QT>(i);
                 const C tw = (y2 >= 0 && y2 < ny) ? C(0.5) * (C(tin[y]) + C(tin[y2])) : C(tin[y]);
-                put(topp<QT>(i), x, y, -es[i] + C(2) * twt<QT, C>(i) * tw);
+                put(topp<QT>(i), x, y, chan_antibb_g<QT, C>(i, es[i], tw));
             }
             // populations leaving through the outlet: the outlet slots are filled
             // by the extrapolation stores of put()
