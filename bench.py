@@ -165,9 +165,10 @@ def run_wide(cells, steps, warmup, prec, fusion=0):
                 if spl == 2 else "k_phase")
 
 
-def run_channel(nx, ny, steps, warmup, prec):
+def run_channel(nx, ny, steps, warmup, prec, fusion=1):
     """The heated-channel step (D2Q9 MRT flow + D2Q5 thermal, velocity inlet,
-    pressure outlet, flux walls) on a roofline-sized grid."""
+    pressure outlet, flux walls) on a roofline-sized grid; fusion 2 runs two
+    steps per launch (the state crosses HBM once per two steps)."""
     import torch
     from paper_2302_04120_amd import lbm, workloads as WL
     prm, ini = WL.channel(nx=nx, ny=ny)
@@ -176,6 +177,7 @@ def run_channel(nx, ny, steps, warmup, prec):
                     flow=True, thermal=True)
     direct_launches(L)
     L.set_params(prm)
+    L.set_step_fusion(fusion)
     L.init(ini["rho"], ini["ux"], ini["uy"], ini["T"])
     del ini
     L.step(warmup)
@@ -190,10 +192,16 @@ def run_channel(nx, ny, steps, warmup, prec):
     wall = time.perf_counter() - t0
     kernel_ms = e0.elapsed_time(e1) / steps
     nodes = nx * ny
+    if L.reduce(("nonfinite",))["nonfinite"].sum() != 0:
+        raise RuntimeError("non-finite populations after the timed steps")
     L.close()
+    S = "float" if prec == "fp32" else "double"
+    per_step = CHAN_BYTES_PER_LU[prec] * nodes / (2 if fusion == 2 else 1)  # bytes a step moves
     return dict(mlups=nodes * steps / wall / 1e6, kernel_ms=kernel_ms,
-                hbm_frac=CHAN_BYTES_PER_LU[prec] * nodes / (kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                grid="%dx%d" % (nx, ny))
+                hbm_frac=per_step / (kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                grid="%dx%d" % (nx, ny), fusion=fusion,
+                kernel=("k_chan_tb2<%s, %s>" % (S, "true" if nx % 64 == 0 else "false")
+                        if fusion == 2 else "k_chan_step<%s, 5>" % S))
 
 
 def run_d3(n, steps, warmup, prec, mrt=True):
@@ -593,7 +601,8 @@ def main():
               "bubble workload)", file=sys.stderr)
         return 2
     if args.leg == "channel":
-        print(json.dumps(run_channel(16384, 2048, args.steps, args.warmup, args.prec)), flush=True)
+        print(json.dumps(run_channel(16384, 2048, args.steps, args.warmup, args.prec,
+                                     1 if args.fusion == 0 else args.fusion)), flush=True)
         return 0
     if args.leg == "wide":
         print(json.dumps(run_wide(32, args.steps, args.warmup, args.prec, args.fusion)), flush=True)

@@ -257,9 +257,11 @@ S* aux_uin(lbm_ctx* c) { return (S*)c->aux + c->desc.nx; }
 template <typename S>
 S* aux_tin(lbm_ctx* c) { return (S*)c->aux + c->desc.nx + c->desc.ny; }
 
-double flux_mod(const lbm_ctx* c) {
-    return 1.0 + c->flux_amp * std::sin(c->flux_omega * (double)c->t * c->dt);
+// wall-flux modulation of the step from time t dt
+double flux_mod_at(const lbm_ctx* c, long long t) {
+    return 1.0 + c->flux_amp * std::sin(c->flux_omega * (double)t * c->dt);
 }
+double flux_mod(const lbm_ctx* c) { return flux_mod_at(c, c->t); }
 
 template <typename S>
 hipError_t step_once(lbm_ctx* c) {
@@ -275,13 +277,15 @@ hipError_t step_once(lbm_ctx* c) {
     return launch_phase_step<S>(c->pk, a, b, c->desc.prec == LBM_FP32_DEV_ARITH64, c->stream);
 }
 
-// Whether the next two steps go through the two-step kernel.  Automatic
-// mode takes it when its workgroups (one per row segment, x-tile and replica;
+// Whether the next two steps go through a two-step kernel.  Channel: in mode
+// 2 when the kernel covers the configuration.  Two-phase: automatic mode takes it when its workgroups (one per row segment, x-tile and replica;
 // two are resident per CU) fill the 256 CUs and, for rows in x-tiles, at
 // least 90 % of the launched lanes hold stored columns; smaller or narrow
 // grids keep the single-step kernel, whose tiles spread over more CUs.
 bool use_tb2(const lbm_ctx* c) {
-    if (c->desc.lattice != LBM_D2Q9_PHASE || c->fusion == 1 || c->tb2_seg < 1) return false;
+    if (c->fusion == 1 || c->tb2_seg < 1) return false;
+    if (c->desc.lattice == LBM_D2Q9_D2Q5) return c->fusion == 2;
+    if (c->desc.lattice != LBM_D2Q9_PHASE) return false;
     if (c->fusion == 2) return true;
     return phase_tb2_workgroups(c->pk, c->tb2_seg) >= 512 && phase_tb2_lane_use(c->pk) >= 0.9;
 }
@@ -353,8 +357,13 @@ template <typename S>
 hipError_t advance(lbm_ctx* c, int m, int* swaps) {
     *swaps = 0;
     if (m == 2 && use_tb2(c)) {
-        hipError_t e = launch_phase_tb2<S>(c->pk, (const S*)bufA(c), (S*)bufB(c), c->tb2_seg,
-                                           c->stream);
+        hipError_t e =
+            c->desc.lattice == LBM_D2Q9_D2Q5
+                ? launch_chan_tb2<S>(c->ck, (const S*)bufA(c), (S*)bufB(c), aux_qw<S>(c),
+                                     aux_uin<S>(c), aux_tin<S>(c), flux_mod_at(c, c->t),
+                                     flux_mod_at(c, c->t + 1), c->tb2_seg, c->stream)
+                : launch_phase_tb2<S>(c->pk, (const S*)bufA(c), (S*)bufB(c), c->tb2_seg,
+                                      c->stream);
         if (e != hipSuccess) return e;
         c->cur ^= 1;
         c->t += 2;
@@ -540,6 +549,10 @@ lbm_status lbm_set_step_fusion(lbm_ctx* c, int mode) {
                        "many-steps kernel needs at most 16 tiles of 512 nodes over all replicas");
     if (mode == 2 && c->desc.lattice == LBM_D2Q9_PHASE && c->desc.prec == LBM_FP32_DEV_ARITH64)
         return set_err(c, LBM_E_UNSUPPORTED, "two-step kernel: not with FP64 arithmetic on FP32 storage");
+    if (mode == 2 && c->desc.lattice == LBM_D2Q9_D2Q5 && c->has_params && !chan_tb2_fits(c->ck))
+        return set_err(c, LBM_E_UNSUPPORTED,
+                       "two-step channel kernel: needs flow with D2Q5 temperature, x periodic or "
+                       "inlet/outlet, y periodic or walls, no buoyancy");
     if (mode != c->fusion) {
         DeviceGuard g(c->device);
         drop_graphs(c);
@@ -752,6 +765,10 @@ lbm_status lbm_set_params_SI(lbm_ctx* c, const lbm_params_si* p) {
         c->tb2_seg = d.prec == LBM_FP64                ? phase_tb2_seg<double>(pk)
                      : d.prec == LBM_FP32_DEV_ARITH64 ? 0  // the two-step kernel computes in S
                                                        : phase_tb2_seg<float>(pk);
+    }
+    if (d.lattice == LBM_D2Q9_D2Q5 && chan_tb2_fits(ck)) {
+        DeviceGuard g(c->device);
+        c->tb2_seg = d.prec == LBM_FP64 ? chan_tb2_seg<double>(ck) : chan_tb2_seg<float>(ck);
     }
     c->dk = dk;
     c->d3k = d3k;

@@ -190,6 +190,17 @@ constexpr int kRedBlocks = 256;  // first-pass blocks per replica and field
 template <typename S>
 hipError_t launch_chan_step(const ChanK& k, const S* a, S* b, const S* qw, const S* uin,
                             const S* tin, double mod, hipStream_t s);
+// two channel steps in one launch from state a to state b; needs
+// chan_tb2_fits.  mod0, mod1: the wall-flux modulations of the two steps;
+// seg: rows per workgroup (chan_tb2_seg, fixed when the parameters are set)
+bool chan_tb2_fits(const ChanK& k);
+double chan_tb2_lane_use(const ChanK& k);
+long long chan_tb2_workgroups(const ChanK& k, int seg);
+template <typename S>
+int chan_tb2_seg(const ChanK& k);
+template <typename S>
+hipError_t launch_chan_tb2(const ChanK& k, const S* a, S* b, const S* qw, const S* uin,
+                           const S* tin, double mod0, double mod1, int seg, hipStream_t s);
 // one two-phase step from state a to state b (node-block layout); arith64:
 // evaluate the step in FP64 on FP32 storage (S = float)
 template <typename S>

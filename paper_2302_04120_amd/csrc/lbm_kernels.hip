@@ -57,21 +57,29 @@ __device__ __forceinline__ void chan_collide(const ChanK& k, const C (&d)[9], C 
                                              C (&ds)[9], C (&es)[QT]) {
     if (k.flow) {
         const C uu = ux * ux + uy * uy;
-        C neq[9], fh[9];
-#pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            const C eu = C(EX[i]) * ux + C(EY[i]) * uy;
-            // deviation of Eq. feq_geral from w_i rho_ref
-            const C feq = wgt<C>(i) * (drho + rho * (C(3) * eu + C(4.5) * eu * eu - C(1.5) * uu));
-            neq[i] = d[i] - feq;
-            // dt * Guo term of Eq. forcing_term (without its prefactor)
-            fh[i] = wgt<C>(i) * ((C(3) * (C(EX[i]) - ux) + C(9) * eu * C(EX[i])) * ftx +
-                                 (C(3) * (C(EY[i]) - uy) + C(9) * eu * C(EY[i])) * fty);
-        }
         if (k.flow_mrt) {
-            C mn[9], mf[9], dm[9], dv[9];
-            moments9(neq, mn);
-            moments9(fh, mf);
+            // Moment space: the non-equilibrium moments are M d minus the
+            // moments of the deviation equilibrium (Eq. feq_geral less
+            // w_i rho_ref) in closed form, (drho, -2 drho + 3 rho |u|^2,
+            // drho - 3 rho |u|^2, rho u_x, -rho u_x, rho u_y, -rho u_y,
+            // rho (u_x^2 - u_y^2), rho u_x u_y); the Guo term of Eq.
+            // forcing_term has the moments (0, 6 u.F, -6 u.F, F_x, -F_x, F_y,
+            // -F_y, 2 (u_x F_x - u_y F_y), u_x F_y + u_y F_x).
+            C md[9], dm[9], dv[9];
+            moments9(d, md);
+            const C ru2 = rho * uu, rux = rho * ux, ruy = rho * uy;
+            const C mn[9] = {md[0] - drho,
+                             md[1] - (C(-2) * drho + C(3) * ru2),
+                             md[2] - (drho - C(3) * ru2),
+                             md[3] - rux,
+                             md[4] + rux,
+                             md[5] - ruy,
+                             md[6] + ruy,
+                             md[7] - (rux * ux - ruy * uy),
+                             md[8] - rux * uy};
+            const C uf = ux * ftx + uy * fty;
+            const C mf[9] = {C(0),  C(6) * uf, C(-6) * uf, ftx, -ftx, fty, -fty,
+                             C(2) * (ux * ftx - uy * fty), ux * fty + uy * ftx};
 #pragma unroll
             for (int q = 0; q < 9; ++q) {
                 const C L = C(k.Lf[q]);
@@ -81,6 +89,18 @@ __device__ __forceinline__ void chan_collide(const ChanK& k, const C (&d)[9], C 
 #pragma unroll
             for (int i = 0; i < 9; ++i) ds[i] = d[i] + dv[i];
         } else {
+            C neq[9], fh[9];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const C eu = C(EX[i]) * ux + C(EY[i]) * uy;
+                // deviation of Eq. feq_geral from w_i rho_ref
+                const C feq =
+                    wgt<C>(i) * (drho + rho * (C(3) * eu + C(4.5) * eu * eu - C(1.5) * uu));
+                neq[i] = d[i] - feq;
+                // dt * Guo term of Eq. forcing_term (without its prefactor)
+                fh[i] = wgt<C>(i) * ((C(3) * (C(EX[i]) - ux) + C(9) * eu * C(EX[i])) * ftx +
+                                     (C(3) * (C(EY[i]) - uy) + C(9) * eu * C(EY[i])) * fty);
+            }
             const C L = C(k.Lf[7]);
 #pragma unroll
             for (int i = 0; i < 9; ++i) ds[i] = d[i] - L * neq[i] + (C(1) - C(0.5) * L) * fh[i];
@@ -90,11 +110,12 @@ __device__ __forceinline__ void chan_collide(const ChanK& k, const C (&d)[9], C 
         for (int i = 0; i < 9; ++i) ds[i] = d[i];
     }
     if (k.thermal) {
-        C neq[QT], m[QT], dm[QT], dv[QT];
-#pragma unroll
-        for (int i = 0; i < QT; ++i)
-            neq[i] = e[i] - twt<QT, C>(i) * th * (C(1) + C(3) * (C(tex<QT>(i)) * ux + C(tey<QT>(i)) * uy));
+        C m[QT], dm[QT], dv[QT];
         if constexpr (QT == 9) {
+            C neq[9];
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                neq[i] = e[i] - twt<QT, C>(i) * th * (C(1) + C(3) * (C(tex<QT>(i)) * ux + C(tey<QT>(i)) * uy));
             moments9(neq, m);
             // moments of the source w_i qdot dt: qdt (1, -2, 1, 0, ...)
 #pragma unroll
@@ -105,7 +126,15 @@ __device__ __forceinline__ void chan_collide(const ChanK& k, const C (&d)[9], C 
             }
             inverse9(dm, dv);
         } else {
-            moments5(neq, m);
+            // moments of e less those of the equilibrium w_i th (1 + 3 c_i.u):
+            // (th, th u_x, th u_y, -2/3 th, 0)
+            C me[5];
+            moments5(e, me);
+            m[0] = me[0] - th;
+            m[1] = me[1] - th * ux;
+            m[2] = me[2] - th * uy;
+            m[3] = me[3] - C(-2) / C(3) * th;
+            m[4] = me[4];
             // moments of the source w_i qdot dt: qdt (1, 0, 0, -2/3, 0)
             const C ms[5] = {qdt, C(0), C(0), C(-2) / C(3) * qdt, C(0)};
 #pragma unroll
@@ -279,6 +308,262 @@ __global__ __launch_bounds__(64) void k_chan_step(ChanK k, const S* __restrict__
             // populations leaving through the outlet: the outlet slots are filled
             // by the extrapolation stores of put()
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Two channel steps per launch (temporal blocking) for the flow + D2Q5
+// temperature model with x periodic or inlet/outlet, y periodic or walls and
+// no Boussinesq force.  A workgroup of 256 lanes takes one x-tile of one row
+// segment [a, e) of one replica: lane l holds column c = 252 t - 2 + l
+// (modulo nx for periodic x; in an inlet/outlet channel, lanes whose column
+// lies outside [0, nx) read a clamped column and their results are never
+// used).  At row v it collides step n at row v and step n + 1 at row v - 1:
+//   - step n hands its x-moving post-collision values (and u, for the
+//     outlet's wall velocity) to the neighbour lanes through LDS and
+//     accumulates them into the step-(n + 1) state of rows v - 1, v and
+//     v + 1, which stays in registers; row v - 1 is complete once row v has
+//     collided;
+//   - step n + 1 at row v - 1 pushes straight to memory with the streaming
+//     and boundary rules of k_chan_step; its u reaches the next lane through
+//     LDS for the outlet (a second barrier, inlet/outlet channels only).
+// Step n is exact on every lane, the step-(n + 1) state on lanes 1..254 and
+// the step-(n + 1) outlet velocity on lanes 2..254: lanes 2..253 store, so
+// neighbouring tiles store disjoint columns.  Step n runs on rows a - 1 .. e
+// (those that exist), step n + 1 on the segment's own rows, and every slot
+// of the new state is written by its source node only.  Per node the
+// arithmetic is that of k_chan_step (chan_th, chan_collide and the boundary
+// values), so two steps here equal two single steps bit for bit.  mod0 and
+// mod1 are the wall-flux modulations at t and t + dt.
+// ALIGNED: nx a multiple of 64 and a row's node blocks under 2 GiB, so every
+// row starts on a node block and an access is the row's block base (uniform)
+// plus a 32-bit lane offset.
+// ---------------------------------------------------------------------------
+constexpr int kCtLanes = 256;
+constexpr int kCtHalo = 2;                      // overlap columns per side
+constexpr int kCtOut = kCtLanes - 2 * kCtHalo;  // stored columns per tile
+constexpr int kCtNV = 14;                       // values per node: f 0-8, g 9-13
+constexpr int kCtX = 10;                        // LDS exchange rows of step n
+
+template <typename S, bool ALIGNED>
+__global__ __launch_bounds__(kCtLanes) void k_chan_tb2(ChanK k, const S* __restrict__ A,
+                                                      S* __restrict__ B, const S* __restrict__ qw,
+                                                      const S* __restrict__ uin,
+                                                      const S* __restrict__ tin, S mod0, S mod1,
+                                                      int seg) {
+    using C = S;
+    constexpr int QT = 5, NV = kCtNV, G = 9;
+    const int nx = k.nx, ny = k.ny;
+    const int nseg = (ny + seg - 1) / seg;
+    const int ntx = (nx + kCtOut - 1) / kCtOut;
+    int w;
+    if (!xcd_tile(ntx * nseg * k.batch, w)) return;  // whole workgroup, before any barrier
+    const int tx = w % ntx;  // x fastest
+    w /= ntx;
+    const int b = w / nseg;
+    const int a = (w - b * nseg) * seg;
+    const int e = min(a + seg, ny);
+    const bool walls = k.bcy != 0;
+    const bool io = k.bcx != 0;
+    const int s1 = walls ? max(a - 1, 0) : a - 1;   // first row of step n
+    const int e1 = walls ? min(e + 1, ny) : e + 1;  // end of the step-n rows
+    const long long base = (long long)b * ny * nx;
+    const unsigned lx = threadIdx.x;
+    const int col = tx * kCtOut - kCtHalo + int(lx);
+    const unsigned x = unsigned(io ? min(max(col, 0), nx - 1) : ((col % nx) + nx) % nx);
+    const bool own = int(lx) >= kCtHalo && int(lx) < kCtLanes - kCtHalo && col < nx;
+    const bool at_in = io && col == 0, at_out = io && col == nx - 1;
+    const unsigned xm = x == 0 ? nx - 1 : x - 1;
+    const unsigned xp = x == unsigned(nx - 1) ? 0u : x + 1;
+    const unsigned lxm = lx == 0 ? 0u : lx - 1;
+    const unsigned lxp = lx == kCtLanes - 1 ? lx : lx + 1;
+    const C rho_ref = C(k.rho_ref), qdt = C(k.qdt);
+    const C q = C(qw[x]);
+
+    __shared__ C xch[2][kCtX][kCtLanes];  // step n: x movers and u, rows v mod 2
+    __shared__ C un1[2][2][kCtLanes];     // step n + 1: u, rows v mod 2
+
+    // memory row of virtual row v: step-n rows of a periodic segment lie in
+    // [-1, ny], so one correction wraps them
+    auto rowof = [&](int v) { return v < 0 ? v + ny : (v >= ny ? v - ny : v); };
+    // value i of the node in column slot c (0: x, 1: x - 1, 2: x + 1) of row v
+    const unsigned xcol[3] = {x, xm, xp};
+    unsigned boff[3];  // ALIGNED: byte offset of value 0 of those columns within a row
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        boff[c] = unsigned(((xcol[c] >> 6) * NV * kBlk + (xcol[c] & (kBlk - 1))) * sizeof(S));
+    auto at = [&](auto* P, int v, int c, int i) {
+        const long long ro = base + (long long)rowof(v) * nx;
+        if constexpr (ALIGNED) {
+            using B8 = std::conditional_t<std::is_const_v<std::remove_pointer_t<decltype(P)>>,
+                                          const char, char>;
+            auto* row = (B8*)P + (ro >> 6) * (long long)(NV * kBlk * sizeof(S));
+            return (decltype(P))(row + boff[c]) + i * kBlk;
+        } else {
+            return P + bidx(NV, i, ro + xcol[c]);
+        }
+    };
+    auto load_row = [&](int v, C (&s)[NV]) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) s[i] = C(*at(A, v, 0, i));
+    };
+    // macros and both collisions of one node, as in k_chan_step
+    auto collide = [&](const C (&s)[NV], C& ux, C& uy, C (&ds)[9], C (&es)[QT]) {
+        C d[9], g[QT], drho, rho, ftx, fty;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) d[i] = s[i];
+#pragma unroll
+        for (int i = 0; i < QT; ++i) g[i] = s[G + i];
+        const C th = chan_th<QT, C>(g, qdt);
+        chan_force(k, th, ftx, fty);
+        chan_flow_macros_v<C>(d, rho_ref, ftx, fty, drho, rho, ux, uy);
+        chan_collide<C, QT>(k, d, drho, rho, ux, uy, ftx, fty, g, th, qdt, ds, es);
+    };
+
+    // Register slots: slot (u - s1) mod 3 holds row u of
+    //   Ld: the stored state (rows v and v + 1 are live),
+    //   Ac: the accumulated step-(n + 1) state (rows v - 1 .. v + 1).
+    // The row loop is unrolled three times, so every slot index is a
+    // compile-time constant.
+    C Ld[3][NV], Ac[3][NV];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int i = 0; i < NV; ++i) Ld[j][i] = Ac[j][i] = C(0);
+    load_row(s1, Ld[0]);
+
+    auto row_step = [&](int v, auto Jc) {
+        constexpr int J = decltype(Jc)::value;
+        constexpr int s0 = J, sn = (J + 1) % 3, sm1 = (J + 2) % 3;  // rows v, v + 1, v - 1
+        const bool do_n = v < e1;
+        // unconditional (the last row re-reads an existing row), so every
+        // slot is seen to be overwritten before it is read
+        load_row(v + 1 < e1 ? v + 1 : e1 - 1, Ld[sn]);
+        C(&xb)[kCtX][kCtLanes] = xch[v & 1];
+        // ---- step n at row v
+        C ds[9], es[QT], ux = C(0), uy = C(0);
+        if (do_n) {
+            collide(Ld[s0], ux, uy, ds, es);
+            xb[0][lx] = ds[1];
+            xb[1][lx] = ds[3];
+            xb[2][lx] = ds[5];
+            xb[3][lx] = ds[6];
+            xb[4][lx] = ds[7];
+            xb[5][lx] = ds[8];
+            xb[6][lx] = es[1];
+            xb[7][lx] = es[3];
+            xb[8][lx] = ux;
+            xb[9][lx] = uy;
+        }
+        __syncthreads();  // the other buffer's reads ended a row ago
+        if (do_n) {
+            // pushes of row v: rest and x movers to row v, +y movers to row
+            // v + 1, -y movers to row v - 1 (x movers from the lanes x -+ 1)
+            C(&A0)[NV] = Ac[s0];
+            C(&Ap)[NV] = Ac[sn];
+            C(&A1)[NV] = Ac[sm1];
+            const bool top = walls && v == ny - 1, bottom = walls && v == 0;
+            C uwx = C(0), uwy = C(0), u_in = C(0), t_in = C(0);
+            if (io) {
+                const int y = rowof(v);
+                u_in = C(uin[y]);
+                t_in = C(0.5) * (C(tin[y]) + C(tin[y]));  // the inlet link stays in row y
+                uwx = C(1.5) * ux - C(0.5) * xb[8][lxm];
+                uwy = C(1.5) * uy - C(0.5) * xb[9][lxm];
+            }
+            A0[0] = ds[0];
+            A0[1] = at_in ? chan_inlet_f<C>(3, ds[3], rho_ref, u_in) : xb[0][lxm];
+            A0[3] = at_out ? chan_outlet_f<C>(1, ds[1], rho_ref, uwx, uwy) : xb[1][lxp];
+            // the -y slots take the top wall's values; below the top row the
+            // next row's pushes overwrite them (not the inlet's and outlet's
+            // own values)
+            A0[4] = ds[2];
+            A0[7] = at_out && !top ? chan_outlet_f<C>(5, ds[5], rho_ref, uwx, uwy) : ds[5];
+            A0[8] = at_in && !top ? chan_inlet_f<C>(6, ds[6], rho_ref, u_in) : ds[6];
+            // the +y slots hold the row below's pushes, except at the bottom
+            // wall and where the source lies beyond the inlet or outlet
+            A0[2] = bottom ? ds[4] : A0[2];
+            A0[5] = bottom ? ds[7] : (at_in ? chan_inlet_f<C>(7, ds[7], rho_ref, u_in) : A0[5]);
+            A0[6] = bottom ? ds[8] : (at_out ? chan_outlet_f<C>(8, ds[8], rho_ref, uwx, uwy) : A0[6]);
+            Ap[2] = ds[2];
+            Ap[5] = xb[2][lxm];
+            Ap[6] = xb[3][lxp];
+            A1[4] = ds[4];
+            A1[7] = at_out ? A1[7] : xb[4][lxp];
+            A1[8] = at_in ? A1[8] : xb[5][lxm];
+            // temperature: Dirichlet inlet, outlet extrapolation (its own
+            // value, the one its left neighbour receives), flux walls
+            A0[G + 0] = es[0];
+            A0[G + 1] = at_in ? chan_antibb_g<QT, C>(3, es[3], t_in) : xb[6][lxm];
+            A0[G + 3] = at_out ? es[3] : xb[7][lxp];
+            A0[G + 4] = chan_flux_g<QT, C>(2, es[2], q, mod0);
+            A0[G + 2] = bottom ? chan_flux_g<QT, C>(4, es[4], q, mod0) : A0[G + 2];
+            Ap[G + 2] = es[2];
+            A1[G + 4] = es[4];
+        }
+        // ---- step n + 1 at row r = v - 1, complete now, straight to memory
+        const int r = v - 1;
+        const bool do_n1 = r >= a && r < e;
+        C ds1[9], es1[QT], ux1 = C(0), uy1 = C(0);
+        if (do_n1) {
+            collide(Ac[sm1], ux1, uy1, ds1, es1);
+            if (io) {
+                un1[v & 1][0][lx] = ux1;
+                un1[v & 1][1][lx] = uy1;
+            }
+        }
+        if (io) __syncthreads();
+        if (do_n1 && own) {
+            C uwx = C(0), uwy = C(0), u_in = C(0), t_in = C(0);
+            if (io) {
+                u_in = C(uin[r]);
+                t_in = C(0.5) * (C(tin[r]) + C(tin[r]));
+                uwx = C(1.5) * ux1 - C(0.5) * un1[v & 1][0][lxm];
+                uwy = C(1.5) * uy1 - C(0.5) * un1[v & 1][1][lxm];
+            }
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const int ty = r + EY[i];
+                const bool outy = walls && (ty < 0 || ty >= ny);
+                const bool outx = (EX[i] < 0 && at_in) || (EX[i] > 0 && at_out);
+                if (!outy && !outx) {
+                    st(at(B, ty, EX[i] == 0 ? 0 : (EX[i] > 0 ? 2 : 1), i), S(ds1[i]));
+                } else {
+                    C val;
+                    if (outy)
+                        val = ds1[i];
+                    else if (EX[i] < 0)
+                        val = chan_inlet_f<C>(i, ds1[i], rho_ref, u_in);
+                    else
+                        val = chan_outlet_f<C>(i, ds1[i], rho_ref, uwx, uwy);
+                    st(at(B, r, 0, OPP[i]), S(val));
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < QT; ++i) {
+                const int ty = r + EY5[i];
+                const bool outy = walls && (ty < 0 || ty >= ny);
+                const bool outx = (EX5[i] < 0 && at_in) || (EX5[i] > 0 && at_out);
+                if (!outy && !outx) {
+                    st(at(B, ty, EX5[i] == 0 ? 0 : (EX5[i] > 0 ? 2 : 1), G + i), S(es1[i]));
+                    // outlet extrapolation: what column nx - 2 receives
+                    if (EX5[i] < 0 && at_out) st(at(B, ty, 0, G + i), S(es1[i]));
+                } else if (outy) {
+                    st(at(B, r, 0, G + OPP5[i]), S(chan_flux_g<QT, C>(i, es1[i], q, mod1)));
+                } else if (EX5[i] < 0) {
+                    st(at(B, r, 0, G + OPP5[i]), S(chan_antibb_g<QT, C>(i, es1[i], t_in)));
+                }
+                // the outlet's own +x mover leaves; its slot is extrapolated
+            }
+        }
+    };
+    const int vend = e + 1;
+    for (int v = s1; v < vend; v += 3) {
+        row_step(v, std::integral_constant<int, 0>{});
+        if (v + 1 >= vend) break;
+        row_step(v + 1, std::integral_constant<int, 1>{});
+        if (v + 2 >= vend) break;
+        row_step(v + 2, std::integral_constant<int, 2>{});
     }
 }
 
@@ -1379,6 +1664,78 @@ hipError_t launch_chan_step(const ChanK& k, const S* a, S* b, const S* qw, const
     return hipGetLastError();
 }
 
+// The two-step channel kernel covers flow with D2Q5 temperature, x periodic
+// or inlet/outlet, y periodic or walls, no Boussinesq force, and at least
+// two columns and rows.
+bool chan_tb2_fits(const ChanK& k) {
+    return k.flow && k.thermal && k.tq == 5 && k.npl == kCtNV && !k.buoy &&
+           (k.bcx == 0 || k.bcx == 1) && (k.bcy == 0 || k.bcy == 1) && k.nx >= 2 && k.ny >= 2;
+}
+int chan_tb2_ntx(const ChanK& k) { return (k.nx + kCtOut - 1) / kCtOut; }
+// Share of the launched lanes whose columns are stored.
+double chan_tb2_lane_use(const ChanK& k) {
+    return double(k.nx) / (double(chan_tb2_ntx(k)) * kCtLanes);
+}
+template <typename S>
+bool chan_tb2_aligned(const ChanK& k) {
+    return k.nx % kBlk == 0 && (long long)k.nx * kCtNV * (long long)sizeof(S) < (1LL << 31);
+}
+long long chan_tb2_workgroups(const ChanK& k, int seg) {
+    return (long long)((k.ny + seg - 1) / seg) * k.batch * chan_tb2_ntx(k);
+}
+
+// Rows per segment, by the launch-round model of the two-phase kernel: a
+// workgroup marches seg + 2 rows (its segment, one row of overlap below and
+// one of lag above), the GPU holds `slots` workgroups at once, and the
+// segment length (at least 32 rows, or the whole replica) minimises
+// ceil(workgroups / slots) (seg + 2).
+template <typename S>
+int chan_tb2_seg(const ChanK& k) {
+    const int ny = k.ny;
+    int dev = 0, cus = 0, per_cu = 0;
+    long long slots = 1024;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        (chan_tb2_aligned<S>(k) ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                      &per_cu, k_chan_tb2<S, true>, kCtLanes, 0)
+                                : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                      &per_cu, k_chan_tb2<S, false>, kCtLanes, 0)) == hipSuccess &&
+        cus > 0 && per_cu > 0)
+        slots = (long long)cus * per_cu;
+    const long long units = (long long)k.batch * chan_tb2_ntx(k);
+    const int lo = ny < 32 ? ny : 32;
+    int best = ny;
+    long long best_cost = -1;
+    for (int seg = ny; seg >= lo; --seg) {
+        const long long nseg = (ny + seg - 1) / seg;
+        if (seg < ny && seg - 1 >= lo && (ny + seg - 2) / (seg - 1) == nseg)
+            continue;  // a shorter segment gives the same count: take the shortest of them
+        const long long rounds = (units * nseg + slots - 1) / slots;
+        const long long cost = rounds * (seg + 2);
+        if (best_cost < 0 || cost < best_cost) {
+            best_cost = cost;
+            best = seg;
+        }
+    }
+    return best;
+}
+
+template <typename S>
+hipError_t launch_chan_tb2(const ChanK& k, const S* a, S* b, const S* qw, const S* uin,
+                           const S* tin, double mod0, double mod1, int seg, hipStream_t s) {
+    if (!chan_tb2_fits(k) || seg < 1) return hipErrorInvalidValue;
+    const long long wgs = chan_tb2_workgroups(k, seg);
+    if ((wgs + kXCD - 1) / kXCD * kXCD > 0x7fffffffLL) return hipErrorInvalidValue;
+    dim3 grd(unsigned((wgs + kXCD - 1) / kXCD * kXCD)), blk(kCtLanes);
+    if (chan_tb2_aligned<S>(k))
+        hipLaunchKernelGGL((k_chan_tb2<S, true>), grd, blk, 0, s, k, a, b, qw, uin, tin, S(mod0),
+                           S(mod1), seg);
+    else
+        hipLaunchKernelGGL((k_chan_tb2<S, false>), grd, blk, 0, s, k, a, b, qw, uin, tin, S(mod0),
+                           S(mod1), seg);
+    return hipGetLastError();
+}
+
 // FP32 steps run on 256-node tiles, four resident per CU (kPhaseLdsReserve).
 // Measured against 512-node tiles (two per CU): equal on 1024 replicas of
 // 256^2, faster on smaller grids (64 replicas 146 -> 141 us per step, C4's
@@ -1668,6 +2025,9 @@ hipError_t launch_nusselt(const ChanK& k, const S* a, const S* qw, double qsi, d
                                             const S*, double, hipStream_t);                       \
     template hipError_t launch_phase_step<S>(const PhaseK&, const S*, S*, bool, hipStream_t);    \
     template hipError_t launch_phase_tb2<S>(const PhaseK&, const S*, S*, int, hipStream_t);      \
+    template hipError_t launch_chan_tb2<S>(const ChanK&, const S*, S*, const S*, const S*,      \
+                                           const S*, double, double, int, hipStream_t);           \
+    template int chan_tb2_seg<S>(const ChanK&);                                                  \
     template int phase_tb2_seg<S>(const PhaseK&);                                                \
     template hipError_t launch_phase_persist<S>(const PhaseK&, S*, S*, int, unsigned, unsigned*,  \
                                                 unsigned*, bool, hipStream_t);                    \

@@ -1,0 +1,116 @@
+"""The two-step (temporally blocked) channel kernel against the single-step
+kernel.  Both evaluate the same per-node arithmetic (the shared collision and
+boundary-value functions) in the same order, so a run of either must give the
+same state to the last bit.  The cases cover the velocity inlet and pressure
+outlet with the flux walls of the heated channel (Sec. 4.2), periodic x and y,
+one and several x-tiles (ragged and a multiple of 64), one and several row
+segments, a replica batch, BGK and MRT, FP32 and FP64, the oscillating wall
+flux (a different modulation in each of the two steps), a flux that varies
+along the wall, odd step counts (the last step single) and graph replay."""
+import numpy as np
+import pytest
+
+from paper_2302_04120_amd import workloads as WL
+
+from gpu_cases import print_case
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(nx, ny, seed, oscillating=False, **over):
+    prm, ini = WL.channel(nx=nx, ny=ny, dx=5e-5, tau_ratio=0.7, oscillating=oscillating)
+    g = WL.rng(seed)
+    prm = dict(prm, **over)
+    prm["flux"] = prm["q_s"] * g.uniform(0.5, 1.5, nx)
+    ini = dict(ini)
+    ini["ux"] = ini["ux"] + g.uniform(-1e-3, 1e-3, ini["ux"].shape)
+    ini["uy"] = ini["uy"] + g.uniform(-1e-3, 1e-3, ini["uy"].shape)
+    ini["T"] = ini["T"] + g.uniform(-0.5, 0.5, ini["T"].shape)
+    return prm, ini
+
+
+def _state(prm, ini, nx, ny, bc, fusion, steps, prec="fp32", batch=1, graph_steps=0):
+    from paper_2302_04120_amd import lbm
+    L = lbm.Lattice("channel", nx, ny, prec=prec, bc=bc, batch=batch, thermal=True)
+    L.set_graph_steps(graph_steps)
+    L.set_params(prm)
+    L.set_step_fusion(fusion)
+    if batch > 1:
+        ini = {k: np.broadcast_to(v, (batch,) + v.shape[-2:]).copy() for k, v in ini.items()}
+    L.init(ini["rho"], ini["ux"], ini["uy"], ini["T"])
+    for s in steps:
+        L.step(s)
+    blob = L.save_state()
+    nonfinite = L.reduce(("nonfinite",))["nonfinite"].sum()
+    L.close()
+    return blob, nonfinite
+
+
+def _bc(name):
+    from paper_2302_04120_amd import lbm
+    io = (lbm.BC_VEL_INLET, lbm.BC_P_OUTLET)
+    walls = (lbm.BC_WALL, lbm.BC_WALL)
+    return {"io_walls": io + walls, "px_walls": (0, 0) + walls, "periodic": (0, 0, 0, 0),
+            "io_py": io + (0, 0)}[name]
+
+
+CASES = [
+    # name, nx, ny, bc, prec, batch, oscillating, overrides
+    ("one_tile_osc", 200, 20, "io_walls", "fp32", 1, True, {}),
+    ("tiles_ragged_segments", 600, 70, "io_walls", "fp32", 1, False, {}),
+    ("tiles_aligned_segments", 512, 72, "io_walls", "fp32", 1, True, {}),
+    ("bgk", 200, 20, "io_walls", "fp32", 1, False, {"flow_mrt": 0, "thermal_mrt": 0}),
+    ("px_walls_force_wrapped", 128, 16, "px_walls", "fp32", 1, False, {"Fx": 50.0}),
+    ("periodic_tiles_segments", 300, 70, "periodic", "fp32", 1, False, {"Fx": 50.0}),
+    ("io_periodic_y", 256, 33, "io_py", "fp32", 1, False, {}),
+    ("batch2", 128, 40, "px_walls", "fp32", 2, True, {"Fx": 50.0}),
+    ("tiny_io", 3, 2, "io_walls", "fp32", 1, False, {}),
+    ("tiny_periodic", 2, 2, "periodic", "fp32", 1, False, {"Fx": 50.0}),
+    ("one_tile_osc_fp64", 200, 20, "io_walls", "fp64", 1, True, {}),
+    ("tiles_ragged_segments_fp64", 600, 70, "io_walls", "fp64", 1, False, {}),
+    ("tiles_aligned_fp64", 512, 40, "io_walls", "fp64", 1, False, {}),
+    ("periodic_tiles_segments_fp64", 300, 70, "periodic", "fp64", 1, False, {"Fx": 50.0}),
+]
+
+
+@pytest.mark.parametrize("name,nx,ny,bc,prec,batch,osc,over", CASES, ids=[c[0] for c in CASES])
+def test_two_step_channel_kernel_bit_identical(name, nx, ny, bc, prec, batch, osc, over):
+    print_case(test="chan-fusion", case=name, nx=nx, ny=ny, prec=prec, batch=batch)
+    prm, ini = _case(nx, ny, seed=len(name), oscillating=osc, **over)
+    steps = [7, 30]
+    one, nf1 = _state(prm, ini, nx, ny, _bc(bc), 1, steps, prec=prec, batch=batch)
+    two, nf2 = _state(prm, ini, nx, ny, _bc(bc), 2, steps, prec=prec, batch=batch)
+    assert nf1 == 0 and nf2 == 0
+    if one != two:
+        a = np.frombuffer(one, np.uint8)
+        b = np.frombuffer(two, np.uint8)
+        pytest.fail("states differ in %d of %d bytes" % (int((a != b).sum()), a.size))
+
+
+def test_two_step_channel_kernel_under_graph_replay():
+    """Captured runs of the two-step kernel (steady wall flux) replay to the
+    same state as single steps launched one by one."""
+    nx, ny = 600, 70
+    print_case(test="chan-fusion-graph", nx=nx, ny=ny)
+    prm, ini = _case(nx, ny, seed=3)
+    one, _ = _state(prm, ini, nx, ny, _bc("io_walls"), 1, [41])
+    two, _ = _state(prm, ini, nx, ny, _bc("io_walls"), 2, [41], graph_steps=8)
+    assert one == two
+
+
+def test_two_step_channel_mode_rejected_where_not_covered():
+    """Mode 2 on a channel configuration the two-step kernel does not cover
+    (D2Q9 temperature, buoyancy, fixed-temperature side walls, symmetry
+    plane) is refused once the parameters are set."""
+    from paper_2302_04120_amd import lbm
+    print_case(test="chan-fusion-unsupported")
+    prm, ini = _case(64, 16, seed=1)
+    L = lbm.Lattice("channel", 64, 16, bc=_bc("io_walls"), thermal="d2q9")
+    try:
+        L.set_params(prm)
+        with pytest.raises(lbm.LbmError) as ex:
+            L.set_step_fusion(2)
+        assert ex.value.status == lbm.LBM_E_UNSUPPORTED
+        L.set_step_fusion(1)
+    finally:
+        L.close()
