@@ -196,12 +196,13 @@ def run_channel(nx, ny, steps, warmup, prec, fusion=1):
         raise RuntimeError("non-finite populations after the timed steps")
     L.close()
     S = "float" if prec == "fp32" else "double"
-    per_step = CHAN_BYTES_PER_LU[prec] * nodes / (2 if fusion == 2 else 1)  # bytes a step moves
+    two = fusion != 1  # the library's choice at this size is the two-step kernel
+    per_step = CHAN_BYTES_PER_LU[prec] * nodes / (2 if two else 1)  # bytes a step moves
     return dict(mlups=nodes * steps / wall / 1e6, kernel_ms=kernel_ms,
                 hbm_frac=per_step / (kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                 grid="%dx%d" % (nx, ny), fusion=fusion,
                 kernel=("k_chan_tb2<%s, %s>" % (S, "true" if nx % 64 == 0 else "false")
-                        if fusion == 2 else "k_chan_step<%s, 5>" % S))
+                        if two else "k_chan_step<%s, 5>" % S))
 
 
 def run_d3(n, steps, warmup, prec, mrt=True):
@@ -570,7 +571,8 @@ def main():
     ap.add_argument("--batch", type=int, default=1024, help="256x256 replicas per step")
     ap.add_argument("--prec", default="fp32", choices=("fp32", "fp64", "fp32_arith64"))
     ap.add_argument("--fusion", type=int, default=2, choices=(0, 1, 2),
-                    help="two-phase kernel: 2 two-step (default), 1 single-step, 0 library's choice")
+                    help="2 two-step kernel (default), 1 single-step, 0 library's choice (the "
+                         "two-phase workloads and --leg channel)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP64 and batch-4 legs")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_phase_step.json"))
@@ -602,7 +604,7 @@ def main():
         return 2
     if args.leg == "channel":
         print(json.dumps(run_channel(16384, 2048, args.steps, args.warmup, args.prec,
-                                     1 if args.fusion == 0 else args.fusion)), flush=True)
+                                     args.fusion)), flush=True)
         return 0
     if args.leg == "wide":
         print(json.dumps(run_wide(32, args.steps, args.warmup, args.prec, args.fusion)), flush=True)
@@ -692,7 +694,8 @@ def main():
         log("bench: C4 single replica, graph replay and many-steps kernel")
         extras["c4_single_replica"] = run_c4_single()
         log("bench: heated-channel leg (16384 x 2048)")
-        extras["channel_fp32"] = run_channel(16384, 2048, 100, 10, "fp32")
+        extras["channel_fp32"] = run_channel(16384, 2048, 100, 10, "fp32", fusion=2)
+        extras["channel_single_step_fp32"] = run_channel(16384, 2048, 100, 10, "fp32", fusion=1)
         log("bench: D3Q19 leg (256^3)")
         extras["d3q19_fp32"] = run_d3(256, 100, 10, "fp32")
         extras["d3q19_fp64"] = run_d3(256, 40, 4, "fp64")

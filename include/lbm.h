@@ -266,16 +266,24 @@ LBM_API lbm_status lbm_first_nonfinite_step(lbm_ctx* ctx, long long* step);
  * LBM_E_ARG on an odd, negative or too large count. */
 LBM_API lbm_status lbm_set_graph_steps(lbm_ctx* ctx, int steps);
 
-/* Kernel choice for LBM_D2Q9_PHASE steps.
- *   mode 1: one launch per step (the tiled single-step kernel).
- *   mode 2: pairs of steps run as one launch of the two-step kernel, which
+/* Kernel choice for LBM_D2Q9_PHASE and LBM_D2Q9_D2Q5 steps.
+ *   mode 1: one launch per step (the single-step kernel).
+ *   mode 2: pairs of steps run as one launch of a two-step kernel, which
  *           keeps the intermediate state on chip and so moves half the bytes
- *           per step: a whole row per workgroup when nx is a multiple of 64
- *           up to 256, otherwise x-tiles of 256 lanes that store 250 columns
- *           each and overlap their neighbours by 3 columns per side (any nx);
- *           LBM_E_UNSUPPORTED with LBM_FP32_DEV_ARITH64; ny < 4 and an odd
- *           last step use the single-step kernel.
- *   mode 3: every lbm_step call runs as one cooperative launch (per 16384
+ *           per step; an odd last step uses the single-step kernel.
+ *           LBM_D2Q9_PHASE: a whole row per workgroup when nx is a multiple
+ *           of 64 up to 256, otherwise x-tiles of 256 lanes that store 250
+ *           columns each and overlap their neighbours by 3 columns per side
+ *           (any nx); LBM_E_UNSUPPORTED with LBM_FP32_DEV_ARITH64; ny < 4
+ *           uses the single-step kernel.
+ *           LBM_D2Q9_D2Q5: x-tiles of 256 lanes that store 252 columns and
+ *           overlap by 2 per side; covers flow with D2Q5 temperature, x
+ *           periodic or inlet/outlet, y periodic or walls, no buoyancy;
+ *           LBM_E_UNSUPPORTED for other configurations once
+ *           lbm_set_params_SI has been called (before it, such a
+ *           configuration steps with the single-step kernel).
+ *   mode 3 (LBM_D2Q9_PHASE): every lbm_step call runs as one cooperative
+ *           launch (per 16384
  *           steps) of the many-steps kernel: one resident workgroup per
  *           tile, which steps its tile and waits for its neighbouring tiles'
  *           step counters before the next step, so small grids pay no
@@ -289,14 +297,14 @@ LBM_API lbm_status lbm_set_graph_steps(lbm_ctx* ctx, int steps);
  *           resident for seconds) gives LBM_E_DEVICE and drops the state.  While the
  *           stream is being captured, steps use the single-step kernel.  The step
  *           counters live in the context's buffer and are reset by
- *           lbm_init_fields and lbm_load_state.
- *   mode 0 (default): mode 2 when its workgroups (one per x-tile and
- *           segment of a replica: the whole replica when it has fewer than
- *           256 rows, or at most 512 rows and the workgroups of whole
- *           replicas alone fill the GPU's resident workgroup slots; else 128
- *           rows) number at least 512 and, with x-tiles, at least 90 % of
- *           the launched lanes hold stored columns; else mode 1 (always mode
- *           1 with LBM_FP32_DEV_ARITH64).
+ *           lbm_init_fields and lbm_load_state.  On LBM_D2Q9_D2Q5, mode 3
+ *           steps as mode 1.
+ *   mode 0 (default): mode 2 where it applies and its workgroups (one per
+ *           x-tile and row segment of a replica, the segment length chosen
+ *           by a launch-round model when the parameters are set) number at
+ *           least 512 and, with x-tiles, at least 90 % of the launched lanes
+ *           hold stored columns; else mode 1 (always mode 1 with
+ *           LBM_FP32_DEV_ARITH64).
  * The kernels evaluate the same per-node arithmetic in the same order, so
  * the modes agree to the last bit.  Not an operation of the paper: a
  * performance control.  Other lattices ignore it.  LBM_E_ARG on an unknown

@@ -277,14 +277,17 @@ hipError_t step_once(lbm_ctx* c) {
     return launch_phase_step<S>(c->pk, a, b, c->desc.prec == LBM_FP32_DEV_ARITH64, c->stream);
 }
 
-// Whether the next two steps go through a two-step kernel.  Channel: in mode
-// 2 when the kernel covers the configuration.  Two-phase: automatic mode takes it when its workgroups (one per row segment, x-tile and replica;
-// two are resident per CU) fill the 256 CUs and, for rows in x-tiles, at
-// least 90 % of the launched lanes hold stored columns; smaller or narrow
-// grids keep the single-step kernel, whose tiles spread over more CUs.
+// Whether the next two steps go through a two-step kernel (mode 2 takes it
+// where the kernel covers the configuration).  Automatic mode takes it when
+// its workgroups (one per row segment, x-tile and replica; two or three are
+// resident per CU) fill the 256 CUs and, for rows in x-tiles, at least 90 %
+// of the launched lanes hold stored columns; smaller or narrow grids keep
+// the single-step kernel, whose tiles spread over more CUs.
 bool use_tb2(const lbm_ctx* c) {
     if (c->fusion == 1 || c->tb2_seg < 1) return false;
-    if (c->desc.lattice == LBM_D2Q9_D2Q5) return c->fusion == 2;
+    if (c->desc.lattice == LBM_D2Q9_D2Q5)
+        return c->fusion == 2 || (c->fusion == 0 && chan_tb2_workgroups(c->ck, c->tb2_seg) >= 512 &&
+                                  chan_tb2_lane_use(c->ck) >= 0.9);
     if (c->desc.lattice != LBM_D2Q9_PHASE) return false;
     if (c->fusion == 2) return true;
     return phase_tb2_workgroups(c->pk, c->tb2_seg) >= 512 && phase_tb2_lane_use(c->pk) >= 0.9;

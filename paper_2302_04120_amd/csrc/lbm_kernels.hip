@@ -420,30 +420,28 @@ __global__ __launch_bounds__(kCtLanes) void k_chan_tb2(ChanK k, const S* __restr
         chan_collide<C, QT>(k, d, drho, rho, ux, uy, ftx, fty, g, th, qdt, ds, es);
     };
 
-    // Register slots: slot (u - s1) mod 3 holds row u of
-    //   Ld: the stored state (rows v and v + 1 are live),
-    //   Ac: the accumulated step-(n + 1) state (rows v - 1 .. v + 1).
-    // The row loop is unrolled three times, so every slot index is a
-    // compile-time constant.
-    C Ld[3][NV], Ac[3][NV];
+    // Register slots: slot (u - s1) mod 3 holds the accumulated step-(n + 1)
+    // state of row u (rows v - 1 .. v + 1 are live).  The row loop is
+    // unrolled three times, so every slot index is a compile-time constant.
+    // The stored state of row v is read at the start of its own row step:
+    // reading it a row ahead (in registers) took 6 % longer.
+    C Ld[NV], Ac[3][NV];
 #pragma unroll
     for (int j = 0; j < 3; ++j)
 #pragma unroll
-        for (int i = 0; i < NV; ++i) Ld[j][i] = Ac[j][i] = C(0);
-    load_row(s1, Ld[0]);
+        for (int i = 0; i < NV; ++i) Ac[j][i] = C(0);
 
     auto row_step = [&](int v, auto Jc) {
         constexpr int J = decltype(Jc)::value;
         constexpr int s0 = J, sn = (J + 1) % 3, sm1 = (J + 2) % 3;  // rows v, v + 1, v - 1
         const bool do_n = v < e1;
-        // unconditional (the last row re-reads an existing row), so every
-        // slot is seen to be overwritten before it is read
-        load_row(v + 1 < e1 ? v + 1 : e1 - 1, Ld[sn]);
+        // unconditional (the last row step re-reads an existing row)
+        load_row(do_n ? v : e1 - 1, Ld);
         C(&xb)[kCtX][kCtLanes] = xch[v & 1];
         // ---- step n at row v
         C ds[9], es[QT], ux = C(0), uy = C(0);
         if (do_n) {
-            collide(Ld[s0], ux, uy, ds, es);
+            collide(Ld, ux, uy, ds, es);
             xb[0][lx] = ds[1];
             xb[1][lx] = ds[3];
             xb[2][lx] = ds[5];
@@ -1652,15 +1650,24 @@ inline unsigned grid1(long long N, int bs) {
 // the 16384 x 2048 grid the step takes 0.715-0.723 ms against 0.728-0.737 ms
 // with 64 x 4 tiles (64 x 2: 0.715-0.722; 64 x 8: 0.771; 64 x 4 capped at
 // four or three workgroups per CU by an LDS reserve: 0.793 and 1.236 ms).
+// An LDS reserve per one-wave workgroup caps the waves resident per CU: 26
+// in FP32 (the register count alone allows 32), 12 in FP64 (20).  With more
+// waves, more population streams are open in DRAM at once; on the 16384 x
+// 2048 grid: FP32 0.700 ms per step uncapped, 0.666 ms at 26 or 30 waves,
+// 0.671 at 22 or 24, 0.699 at 20, 0.737 at 16; FP64 1.420 ms uncapped,
+// 1.349 at 16, 1.318 at 12, 1.360 at 10, 1.429 at 8.  The paper-sized grids
+// (launch-bound) are unchanged.
+constexpr unsigned kChanLdsReserve32 = 6144, kChanLdsReserve64 = 13312;
 template <typename S>
 hipError_t launch_chan_step(const ChanK& k, const S* a, S* b, const S* qw, const S* uin,
                             const S* tin, double mod, hipStream_t s) {
     const long long tiles = (long long)((k.nx + 63) / 64) * k.ny * k.batch;
     dim3 blk(64), grd(unsigned((tiles + kXCD - 1) / kXCD * kXCD));
+    const unsigned lds = sizeof(S) == 4 ? kChanLdsReserve32 : kChanLdsReserve64;
     if (k.tq == 9)
-        hipLaunchKernelGGL((k_chan_step<S, 9>), grd, blk, 0, s, k, a, b, qw, uin, tin, S(mod));
+        hipLaunchKernelGGL((k_chan_step<S, 9>), grd, blk, lds, s, k, a, b, qw, uin, tin, S(mod));
     else
-        hipLaunchKernelGGL((k_chan_step<S, 5>), grd, blk, 0, s, k, a, b, qw, uin, tin, S(mod));
+        hipLaunchKernelGGL((k_chan_step<S, 5>), grd, blk, lds, s, k, a, b, qw, uin, tin, S(mod));
     return hipGetLastError();
 }
 
