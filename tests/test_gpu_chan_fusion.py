@@ -114,3 +114,30 @@ def test_two_step_channel_mode_rejected_where_not_covered():
         L.set_step_fusion(1)
     finally:
         L.close()
+
+
+def test_two_step_channel_kernel_bench_size():
+    """The roofline-sized channel of the bench (16384 x 2048, C2 physics) in
+    the launch configuration the bench times (x-tiles on node-block-aligned
+    rows, the segment model's row segments): the same state as single steps
+    after two launches and a single step."""
+    import hashlib
+
+    from paper_2302_04120_amd import lbm
+    nx, ny = 16384, 2048
+    print_case(test="chan-fusion-bench-size", nx=nx, ny=ny)
+    prm, ini = WL.channel(nx=nx, ny=ny)
+    bc = _bc("io_walls")
+    digests = []
+    for fusion in (1, 2):
+        L = lbm.Lattice("channel", nx, ny, bc=bc, thermal=True)
+        L.set_graph_steps(0)
+        L.set_params(prm)
+        L.set_step_fusion(fusion)
+        L.init(ini["rho"], ini["ux"], ini["uy"], ini["T"])
+        L.step(2)
+        L.step(3)
+        assert L.reduce(("nonfinite",))["nonfinite"].sum() == 0
+        digests.append(hashlib.sha256(L.save_state()).hexdigest())
+        L.close()
+    assert digests[0] == digests[1]
