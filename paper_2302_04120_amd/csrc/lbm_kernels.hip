@@ -223,11 +223,11 @@ __global__ __launch_bounds__(64) void k_chan_step(ChanK k, const S* __restrict__
     const bool outlet = k.bcx == 1 && x == nx - 1;
     if (k.flow && outlet) {
         C d2[9], dr2, r2, ux2, uy2, fx2 = ftx, fy2 = fty;
-        if (k.buoy) {
-            C th2 = C(0);
+        if (k.buoy) {  // the force of that node, as it computes it itself
+            C e2[QT];
 #pragma unroll
-            for (int i = 0; i < QT; ++i) th2 += C(A[bidx(npl, 9 + i, n - 1)]);
-            chan_force(k, th2 + C(0.5) * qdt, fx2, fy2);
+            for (int i = 0; i < QT; ++i) e2[i] = C(A[bidx(npl, 9 + i, n - 1)]);
+            chan_force(k, chan_th<QT, C>(e2, qdt), fx2, fy2);
         }
         chan_flow_macros<C, S>(A, npl, n - 1, rho_ref, fx2, fy2, d2, dr2, r2, ux2, uy2);
         uwx = C(1.5) * ux - C(0.5) * ux2;
@@ -313,12 +313,12 @@ __global__ __launch_bounds__(64) void k_chan_step(ChanK k, const S* __restrict__
 
 // ---------------------------------------------------------------------------
 // Two channel steps per launch (temporal blocking) for the flow + D2Q5
-// temperature model with x periodic or inlet/outlet, y periodic or walls and
-// no Boussinesq force.  A workgroup of 256 lanes takes one x-tile of one row
-// segment [a, e) of one replica: lane l holds column c = 252 t - 2 + l
-// (modulo nx for periodic x; in an inlet/outlet channel, lanes whose column
-// lies outside [0, nx) read a clamped column and their results are never
-// used).  At row v it collides step n at row v and step n + 1 at row v - 1:
+// temperature model (Boussinesq force optional) with x periodic, inlet/outlet
+// or fixed-temperature end walls and y periodic or walls.  A workgroup of 256
+// lanes takes one x-tile of one row segment [a, e) of one replica: lane l
+// holds column c = 252 t - 2 + l (modulo nx for periodic x; with x ends,
+// lanes whose column lies outside [0, nx) read a clamped column and their
+// results are never used).  At row v it collides step n at row v and step n + 1 at row v - 1:
 //   - step n hands its x-moving post-collision values (and u, for the
 //     outlet's wall velocity) to the neighbour lanes through LDS and
 //     accumulates them into the step-(n + 1) state of rows v - 1, v and
@@ -364,21 +364,25 @@ __global__ __launch_bounds__(kCtLanes) void k_chan_tb2(ChanK k, const S* __restr
     const int a = (w - b * nseg) * seg;
     const int e = min(a + seg, ny);
     const bool walls = k.bcy != 0;
-    const bool io = k.bcx != 0;
+    const bool xends = k.bcx != 0;  // x not periodic: the channel has a left and a right end
+    const bool io = k.bcx == 1;     // velocity inlet (left), pressure outlet (right)
+    const bool xw = k.bcx == 2;     // fixed-temperature no-slip walls at both ends
     const int s1 = walls ? max(a - 1, 0) : a - 1;   // first row of step n
     const int e1 = walls ? min(e + 1, ny) : e + 1;  // end of the step-n rows
     const long long base = (long long)b * ny * nx;
     const unsigned lx = threadIdx.x;
     const int col = tx * kCtOut - kCtHalo + int(lx);
-    const unsigned x = unsigned(io ? min(max(col, 0), nx - 1) : ((col % nx) + nx) % nx);
+    const unsigned x = unsigned(xends ? min(max(col, 0), nx - 1) : ((col % nx) + nx) % nx);
     const bool own = int(lx) >= kCtHalo && int(lx) < kCtLanes - kCtHalo && col < nx;
-    const bool at_in = io && col == 0, at_out = io && col == nx - 1;
+    const bool x_lo = xends && col == 0, x_hi = xends && col == nx - 1;  // the end columns
+    const bool at_in = io && x_lo, at_out = io && x_hi;
     const unsigned xm = x == 0 ? nx - 1 : x - 1;
     const unsigned xp = x == unsigned(nx - 1) ? 0u : x + 1;
     const unsigned lxm = lx == 0 ? 0u : lx - 1;
     const unsigned lxp = lx == kCtLanes - 1 ? lx : lx + 1;
     const C rho_ref = C(k.rho_ref), qdt = C(k.qdt);
     const C q = C(qw[x]);
+    const C tw_lo = C(k.Tw[0]), tw_hi = C(k.Tw[1]);
 
     __shared__ C xch[2][kCtX][kCtLanes];  // step n: x movers and u, rows v mod 2
     __shared__ C un1[2][2][kCtLanes];     // step n + 1: u, rows v mod 2
@@ -469,9 +473,10 @@ __global__ __launch_bounds__(kCtLanes) void k_chan_tb2(ChanK k, const S* __restr
                 uwx = C(1.5) * ux - C(0.5) * xb[8][lxm];
                 uwy = C(1.5) * uy - C(0.5) * xb[9][lxm];
             }
+            // an end wall (xw) bounces back like the y walls (u_w = 0)
             A0[0] = ds[0];
-            A0[1] = at_in ? chan_inlet_f<C>(3, ds[3], rho_ref, u_in) : xb[0][lxm];
-            A0[3] = at_out ? chan_outlet_f<C>(1, ds[1], rho_ref, uwx, uwy) : xb[1][lxp];
+            A0[1] = x_lo ? (io ? chan_inlet_f<C>(3, ds[3], rho_ref, u_in) : ds[3]) : xb[0][lxm];
+            A0[3] = x_hi ? (io ? chan_outlet_f<C>(1, ds[1], rho_ref, uwx, uwy) : ds[1]) : xb[1][lxp];
             // the -y slots take the top wall's values; below the top row the
             // next row's pushes overwrite them (not the inlet's and outlet's
             // own values)
@@ -479,21 +484,25 @@ __global__ __launch_bounds__(kCtLanes) void k_chan_tb2(ChanK k, const S* __restr
             A0[7] = at_out && !top ? chan_outlet_f<C>(5, ds[5], rho_ref, uwx, uwy) : ds[5];
             A0[8] = at_in && !top ? chan_inlet_f<C>(6, ds[6], rho_ref, u_in) : ds[6];
             // the +y slots hold the row below's pushes, except at the bottom
-            // wall and where the source lies beyond the inlet or outlet
+            // wall and where the source lies beyond an x end
             A0[2] = bottom ? ds[4] : A0[2];
-            A0[5] = bottom ? ds[7] : (at_in ? chan_inlet_f<C>(7, ds[7], rho_ref, u_in) : A0[5]);
-            A0[6] = bottom ? ds[8] : (at_out ? chan_outlet_f<C>(8, ds[8], rho_ref, uwx, uwy) : A0[6]);
+            A0[5] = bottom ? ds[7]
+                           : (x_lo ? (io ? chan_inlet_f<C>(7, ds[7], rho_ref, u_in) : ds[7]) : A0[5]);
+            A0[6] = bottom ? ds[8]
+                           : (x_hi ? (io ? chan_outlet_f<C>(8, ds[8], rho_ref, uwx, uwy) : ds[8])
+                                   : A0[6]);
             Ap[2] = ds[2];
             Ap[5] = xb[2][lxm];
             Ap[6] = xb[3][lxp];
             A1[4] = ds[4];
-            A1[7] = at_out ? A1[7] : xb[4][lxp];
-            A1[8] = at_in ? A1[8] : xb[5][lxm];
-            // temperature: Dirichlet inlet, outlet extrapolation (its own
-            // value, the one its left neighbour receives), flux walls
+            A1[7] = x_hi ? A1[7] : xb[4][lxp];
+            A1[8] = x_lo ? A1[8] : xb[5][lxm];
+            // temperature: Dirichlet inlet or end walls (anti-bounce-back),
+            // outlet extrapolation (its own value, the one its left neighbour
+            // receives), flux walls
             A0[G + 0] = es[0];
-            A0[G + 1] = at_in ? chan_antibb_g<QT, C>(3, es[3], t_in) : xb[6][lxm];
-            A0[G + 3] = at_out ? es[3] : xb[7][lxp];
+            A0[G + 1] = x_lo ? chan_antibb_g<QT, C>(3, es[3], io ? t_in : tw_lo) : xb[6][lxm];
+            A0[G + 3] = x_hi ? (io ? es[3] : chan_antibb_g<QT, C>(1, es[1], tw_hi)) : xb[7][lxp];
             A0[G + 4] = chan_flux_g<QT, C>(2, es[2], q, mod0);
             A0[G + 2] = bottom ? chan_flux_g<QT, C>(4, es[4], q, mod0) : A0[G + 2];
             Ap[G + 2] = es[2];
@@ -523,12 +532,12 @@ __global__ __launch_bounds__(kCtLanes) void k_chan_tb2(ChanK k, const S* __restr
             for (int i = 0; i < 9; ++i) {
                 const int ty = r + EY[i];
                 const bool outy = walls && (ty < 0 || ty >= ny);
-                const bool outx = (EX[i] < 0 && at_in) || (EX[i] > 0 && at_out);
+                const bool outx = (EX[i] < 0 && x_lo) || (EX[i] > 0 && x_hi);
                 if (!outy && !outx) {
                     st(at(B, ty, EX[i] == 0 ? 0 : (EX[i] > 0 ? 2 : 1), i), S(ds1[i]));
                 } else {
                     C val;
-                    if (outy)
+                    if (outy || xw)
                         val = ds1[i];
                     else if (EX[i] < 0)
                         val = chan_inlet_f<C>(i, ds1[i], rho_ref, u_in);
@@ -541,13 +550,16 @@ __global__ __launch_bounds__(kCtLanes) void k_chan_tb2(ChanK k, const S* __restr
             for (int i = 0; i < QT; ++i) {
                 const int ty = r + EY5[i];
                 const bool outy = walls && (ty < 0 || ty >= ny);
-                const bool outx = (EX5[i] < 0 && at_in) || (EX5[i] > 0 && at_out);
+                const bool outx = (EX5[i] < 0 && x_lo) || (EX5[i] > 0 && x_hi);
                 if (!outy && !outx) {
                     st(at(B, ty, EX5[i] == 0 ? 0 : (EX5[i] > 0 ? 2 : 1), G + i), S(es1[i]));
                     // outlet extrapolation: what column nx - 2 receives
                     if (EX5[i] < 0 && at_out) st(at(B, ty, 0, G + i), S(es1[i]));
                 } else if (outy) {
                     st(at(B, r, 0, G + OPP5[i]), S(chan_flux_g<QT, C>(i, es1[i], q, mod1)));
+                } else if (xw) {
+                    st(at(B, r, 0, G + OPP5[i]),
+                       S(chan_antibb_g<QT, C>(i, es1[i], EX5[i] < 0 ? tw_lo : tw_hi)));
                 } else if (EX5[i] < 0) {
                     st(at(B, r, 0, G + OPP5[i]), S(chan_antibb_g<QT, C>(i, es1[i], t_in)));
                 }
@@ -1671,12 +1683,12 @@ hipError_t launch_chan_step(const ChanK& k, const S* a, S* b, const S* qw, const
     return hipGetLastError();
 }
 
-// The two-step channel kernel covers flow with D2Q5 temperature, x periodic
-// or inlet/outlet, y periodic or walls, no Boussinesq force, and at least
-// two columns and rows.
+// The two-step channel kernel covers flow with D2Q5 temperature (with or
+// without the Boussinesq force), x periodic, inlet/outlet or fixed-temperature
+// walls, y periodic or walls, and at least two columns and rows.
 bool chan_tb2_fits(const ChanK& k) {
-    return k.flow && k.thermal && k.tq == 5 && k.npl == kCtNV && !k.buoy &&
-           (k.bcx == 0 || k.bcx == 1) && (k.bcy == 0 || k.bcy == 1) && k.nx >= 2 && k.ny >= 2;
+    return k.flow && k.thermal && k.tq == 5 && k.npl == kCtNV && k.bcx >= 0 && k.bcx <= 2 &&
+           (k.bcy == 0 || k.bcy == 1) && k.nx >= 2 && k.ny >= 2;
 }
 int chan_tb2_ntx(const ChanK& k) { return (k.nx + kCtOut - 1) / kCtOut; }
 // Share of the launched lanes whose columns are stored.

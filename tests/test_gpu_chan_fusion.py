@@ -2,11 +2,13 @@
 kernel.  Both evaluate the same per-node arithmetic (the shared collision and
 boundary-value functions) in the same order, so a run of either must give the
 same state to the last bit.  The cases cover the velocity inlet and pressure
-outlet with the flux walls of the heated channel (Sec. 4.2), periodic x and y,
-one and several x-tiles (ragged and a multiple of 64), one and several row
-segments, a replica batch, BGK and MRT, FP32 and FP64, the oscillating wall
-flux (a different modulation in each of the two steps), a flux that varies
-along the wall, odd step counts (the last step single) and graph replay."""
+outlet with the flux walls of the heated channel (Sec. 4.2), the differentially
+heated cavity with the Boussinesq force (App. D), a buoyant channel with inlet
+and outlet, periodic x and y, one and several x-tiles (ragged and a multiple of
+64), one and several row segments, a replica batch, BGK and MRT, FP32 and
+FP64, the oscillating wall flux (a different modulation in each of the two
+steps), a flux that varies along the wall, odd step counts (the last step
+single) and graph replay."""
 import numpy as np
 import pytest
 
@@ -26,6 +28,18 @@ def _case(nx, ny, seed, oscillating=False, **over):
     ini["ux"] = ini["ux"] + g.uniform(-1e-3, 1e-3, ini["ux"].shape)
     ini["uy"] = ini["uy"] + g.uniform(-1e-3, 1e-3, ini["uy"].shape)
     ini["T"] = ini["T"] + g.uniform(-0.5, 0.5, ini["T"].shape)
+    return prm, ini
+
+
+def _cavity_case(n, seed):
+    """The App. D cavity (hot left wall, cold right wall, insulated top and
+    bottom) with a perturbed start, so that the buoyancy acts everywhere."""
+    prm, ini = WL.cavity(Ra=1e4, n=n)
+    g = WL.rng(seed)
+    ini = dict(ini)
+    ini["T"] = ini["T"] + g.uniform(0.0, 40.0, ini["T"].shape)
+    ini["ux"] = ini["ux"] + g.uniform(-1e-3, 1e-3, ini["ux"].shape)
+    ini["uy"] = ini["uy"] + g.uniform(-1e-3, 1e-3, ini["uy"].shape)
     return prm, ini
 
 
@@ -50,8 +64,10 @@ def _bc(name):
     from paper_2302_04120_amd import lbm
     io = (lbm.BC_VEL_INLET, lbm.BC_P_OUTLET)
     walls = (lbm.BC_WALL, lbm.BC_WALL)
+    xw = (lbm.BC_DIRICHLET, lbm.BC_DIRICHLET)
     return {"io_walls": io + walls, "px_walls": (0, 0) + walls, "periodic": (0, 0, 0, 0),
-            "io_py": io + (0, 0)}[name]
+            "io_py": io + (0, 0), "cavity": xw + walls, "xw_py": xw + (0, 0),
+            "io_symmetry": io + (lbm.BC_WALL, lbm.BC_SYMMETRY)}[name]
 
 
 CASES = [
@@ -70,6 +86,17 @@ CASES = [
     ("tiles_ragged_segments_fp64", 600, 70, "io_walls", "fp64", 1, False, {}),
     ("tiles_aligned_fp64", 512, 40, "io_walls", "fp64", 1, False, {}),
     ("periodic_tiles_segments_fp64", 300, 70, "periodic", "fp64", 1, False, {"Fx": 50.0}),
+    ("buoyant_io", 600, 70, "io_walls", "fp32", 1, False, {"beta_T": 3e-4, "gravity": (0.0, -9.81)}),
+    ("buoyant_px_fp64", 300, 70, "px_walls", "fp64", 1, False,
+     {"beta_T": 3e-4, "gravity": (2.0, -9.81)}),
+]
+CAVITY_CASES = [
+    # name, n, bc, prec
+    ("cavity_tiles_segments", 300, "cavity", "fp32"),
+    ("cavity_aligned", 512, "cavity", "fp32"),
+    ("cavity_fp64", 300, "cavity", "fp64"),
+    ("end_walls_periodic_y", 260, "xw_py", "fp32"),
+    ("cavity_tiny", 3, "cavity", "fp32"),
 ]
 
 
@@ -80,6 +107,20 @@ def test_two_step_channel_kernel_bit_identical(name, nx, ny, bc, prec, batch, os
     steps = [7, 30]
     one, nf1 = _state(prm, ini, nx, ny, _bc(bc), 1, steps, prec=prec, batch=batch)
     two, nf2 = _state(prm, ini, nx, ny, _bc(bc), 2, steps, prec=prec, batch=batch)
+    assert nf1 == 0 and nf2 == 0
+    if one != two:
+        a = np.frombuffer(one, np.uint8)
+        b = np.frombuffer(two, np.uint8)
+        pytest.fail("states differ in %d of %d bytes" % (int((a != b).sum()), a.size))
+
+
+@pytest.mark.parametrize("name,n,bc,prec", CAVITY_CASES, ids=[c[0] for c in CAVITY_CASES])
+def test_two_step_kernel_cavity_bit_identical(name, n, bc, prec):
+    print_case(test="chan-fusion-cavity", case=name, n=n, prec=prec)
+    prm, ini = _cavity_case(n, seed=len(name))
+    steps = [7, 30]
+    one, nf1 = _state(prm, ini, n, n, _bc(bc), 1, steps, prec=prec)
+    two, nf2 = _state(prm, ini, n, n, _bc(bc), 2, steps, prec=prec)
     assert nf1 == 0 and nf2 == 0
     if one != two:
         a = np.frombuffer(one, np.uint8)
@@ -98,14 +139,16 @@ def test_two_step_channel_kernel_under_graph_replay():
     assert one == two
 
 
-def test_two_step_channel_mode_rejected_where_not_covered():
+@pytest.mark.parametrize("bc,thermal", [("io_walls", "d2q9"), ("io_symmetry", True)],
+                         ids=["d2q9_thermal", "symmetry_plane"])
+def test_two_step_channel_mode_rejected_where_not_covered(bc, thermal):
     """Mode 2 on a channel configuration the two-step kernel does not cover
-    (D2Q9 temperature, buoyancy, fixed-temperature side walls, symmetry
-    plane) is refused once the parameters are set."""
+    (the D2Q9 thermal set, the symmetry plane) is refused once the
+    parameters are set."""
     from paper_2302_04120_amd import lbm
-    print_case(test="chan-fusion-unsupported")
+    print_case(test="chan-fusion-unsupported", bc=bc)
     prm, ini = _case(64, 16, seed=1)
-    L = lbm.Lattice("channel", 64, 16, bc=_bc("io_walls"), thermal="d2q9")
+    L = lbm.Lattice("channel", 64, 16, bc=_bc(bc), thermal=thermal)
     try:
         L.set_params(prm)
         with pytest.raises(lbm.LbmError) as ex:
