@@ -314,7 +314,8 @@ __global__ __launch_bounds__(64) void k_chan_step(ChanK k, const S* __restrict__
 // ---------------------------------------------------------------------------
 // Two channel steps per launch (temporal blocking) for the flow + D2Q5
 // temperature model (Boussinesq force optional) with x periodic, inlet/outlet
-// or fixed-temperature end walls and y periodic or walls.  A workgroup of 256
+// or fixed-temperature end walls and y periodic, walls, or a wall below and the
+// symmetry plane above.  A workgroup of 256
 // lanes takes one x-tile of one row segment [a, e) of one replica: lane l
 // holds column c = 252 t - 2 + l (modulo nx for periodic x; with x ends,
 // lanes whose column lies outside [0, nx) read a clamped column and their
@@ -363,7 +364,8 @@ __global__ __launch_bounds__(kCtLanes) void k_chan_tb2(ChanK k, const S* __restr
     const int b = w / nseg;
     const int a = (w - b * nseg) * seg;
     const int e = min(a + seg, ny);
-    const bool walls = k.bcy != 0;
+    const bool walls = k.bcy != 0;  // y ends: a wall at y-, a wall or the symmetry plane at y+
+    const bool symy = k.bcy == 2;   // the symmetry plane of Eq. simetria at y+
     const bool xends = k.bcx != 0;  // x not periodic: the channel has a left and a right end
     const bool io = k.bcx == 1;     // velocity inlet (left), pressure outlet (right)
     const bool xw = k.bcx == 2;     // fixed-temperature no-slip walls at both ends
@@ -464,7 +466,8 @@ __global__ __launch_bounds__(kCtLanes) void k_chan_tb2(ChanK k, const S* __restr
             C(&A0)[NV] = Ac[s0];
             C(&Ap)[NV] = Ac[sn];
             C(&A1)[NV] = Ac[sm1];
-            const bool top = walls && v == ny - 1, bottom = walls && v == 0;
+            const bool top = k.bcy == 1 && v == ny - 1, bottom = walls && v == 0;
+            const bool stop = symy && v == ny - 1;  // top row under the symmetry plane
             C uwx = C(0), uwy = C(0), u_in = C(0), t_in = C(0);
             if (io) {
                 const int y = rowof(v);
@@ -483,6 +486,10 @@ __global__ __launch_bounds__(kCtLanes) void k_chan_tb2(ChanK k, const S* __restr
             A0[4] = ds[2];
             A0[7] = at_out && !top ? chan_outlet_f<C>(5, ds[5], rho_ref, uwx, uwy) : ds[5];
             A0[8] = at_in && !top ? chan_inlet_f<C>(6, ds[6], rho_ref, u_in) : ds[6];
+            // under the symmetry plane the +y movers come back mirrored at
+            // x + c_x (Eq. simetria), from the neighbour lanes
+            A0[7] = stop && !x_hi ? xb[3][lxp] : A0[7];
+            A0[8] = stop && !x_lo ? xb[2][lxm] : A0[8];
             // the +y slots hold the row below's pushes, except at the bottom
             // wall and where the source lies beyond an x end
             A0[2] = bottom ? ds[4] : A0[2];
@@ -503,7 +510,7 @@ __global__ __launch_bounds__(kCtLanes) void k_chan_tb2(ChanK k, const S* __restr
             A0[G + 0] = es[0];
             A0[G + 1] = x_lo ? chan_antibb_g<QT, C>(3, es[3], io ? t_in : tw_lo) : xb[6][lxm];
             A0[G + 3] = x_hi ? (io ? es[3] : chan_antibb_g<QT, C>(1, es[1], tw_hi)) : xb[7][lxp];
-            A0[G + 4] = chan_flux_g<QT, C>(2, es[2], q, mod0);
+            A0[G + 4] = stop ? es[2] : chan_flux_g<QT, C>(2, es[2], q, mod0);
             A0[G + 2] = bottom ? chan_flux_g<QT, C>(4, es[4], q, mod0) : A0[G + 2];
             Ap[G + 2] = es[2];
             A1[G + 4] = es[4];
@@ -530,11 +537,16 @@ __global__ __launch_bounds__(kCtLanes) void k_chan_tb2(ChanK k, const S* __restr
             }
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
-                const int ty = r + EY[i];
-                const bool outy = walls && (ty < 0 || ty >= ny);
+                int ty = r + EY[i], j = i;
+                const bool sym = symy && ty >= ny;  // mirrored back into the top row
+                if (sym) {
+                    ty = ny - 1;
+                    j = MIRY[i];
+                }
+                const bool outy = walls && !sym && (ty < 0 || ty >= ny);
                 const bool outx = (EX[i] < 0 && x_lo) || (EX[i] > 0 && x_hi);
                 if (!outy && !outx) {
-                    st(at(B, ty, EX[i] == 0 ? 0 : (EX[i] > 0 ? 2 : 1), i), S(ds1[i]));
+                    st(at(B, ty, EX[i] == 0 ? 0 : (EX[i] > 0 ? 2 : 1), j), S(ds1[i]));
                 } else {
                     C val;
                     if (outy || xw)
@@ -548,11 +560,16 @@ __global__ __launch_bounds__(kCtLanes) void k_chan_tb2(ChanK k, const S* __restr
             }
 #pragma unroll
             for (int i = 0; i < QT; ++i) {
-                const int ty = r + EY5[i];
-                const bool outy = walls && (ty < 0 || ty >= ny);
+                int ty = r + EY5[i], j = i;
+                const bool sym = symy && ty >= ny;
+                if (sym) {
+                    ty = ny - 1;
+                    j = MIRY5[i];
+                }
+                const bool outy = walls && !sym && (ty < 0 || ty >= ny);
                 const bool outx = (EX5[i] < 0 && x_lo) || (EX5[i] > 0 && x_hi);
                 if (!outy && !outx) {
-                    st(at(B, ty, EX5[i] == 0 ? 0 : (EX5[i] > 0 ? 2 : 1), G + i), S(es1[i]));
+                    st(at(B, ty, EX5[i] == 0 ? 0 : (EX5[i] > 0 ? 2 : 1), G + j), S(es1[i]));
                     // outlet extrapolation: what column nx - 2 receives
                     if (EX5[i] < 0 && at_out) st(at(B, ty, 0, G + i), S(es1[i]));
                 } else if (outy) {
@@ -1684,11 +1701,11 @@ hipError_t launch_chan_step(const ChanK& k, const S* a, S* b, const S* qw, const
 }
 
 // The two-step channel kernel covers flow with D2Q5 temperature (with or
-// without the Boussinesq force), x periodic, inlet/outlet or fixed-temperature
-// walls, y periodic or walls, and at least two columns and rows.
+// without the Boussinesq force), every x and y boundary of the channel
+// lattice, and at least two columns and rows.
 bool chan_tb2_fits(const ChanK& k) {
     return k.flow && k.thermal && k.tq == 5 && k.npl == kCtNV && k.bcx >= 0 && k.bcx <= 2 &&
-           (k.bcy == 0 || k.bcy == 1) && k.nx >= 2 && k.ny >= 2;
+           k.bcy >= 0 && k.bcy <= 2 && k.nx >= 2 && k.ny >= 2;
 }
 int chan_tb2_ntx(const ChanK& k) { return (k.nx + kCtOut - 1) / kCtOut; }
 // Share of the launched lanes whose columns are stored.

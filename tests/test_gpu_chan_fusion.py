@@ -4,7 +4,7 @@ boundary-value functions) in the same order, so a run of either must give the
 same state to the last bit.  The cases cover the velocity inlet and pressure
 outlet with the flux walls of the heated channel (Sec. 4.2), the differentially
 heated cavity with the Boussinesq force (App. D), a buoyant channel with inlet
-and outlet, periodic x and y, one and several x-tiles (ragged and a multiple of
+and outlet, the half channel under the symmetry plane, periodic x and y, one and several x-tiles (ragged and a multiple of
 64), one and several row segments, a replica batch, BGK and MRT, FP32 and
 FP64, the oscillating wall flux (a different modulation in each of the two
 steps), a flux that varies along the wall, odd step counts (the last step
@@ -67,7 +67,8 @@ def _bc(name):
     xw = (lbm.BC_DIRICHLET, lbm.BC_DIRICHLET)
     return {"io_walls": io + walls, "px_walls": (0, 0) + walls, "periodic": (0, 0, 0, 0),
             "io_py": io + (0, 0), "cavity": xw + walls, "xw_py": xw + (0, 0),
-            "io_symmetry": io + (lbm.BC_WALL, lbm.BC_SYMMETRY)}[name]
+            "io_symmetry": io + (lbm.BC_WALL, lbm.BC_SYMMETRY),
+            "px_symmetry": (0, 0, lbm.BC_WALL, lbm.BC_SYMMETRY)}[name]
 
 
 CASES = [
@@ -89,6 +90,9 @@ CASES = [
     ("buoyant_io", 600, 70, "io_walls", "fp32", 1, False, {"beta_T": 3e-4, "gravity": (0.0, -9.81)}),
     ("buoyant_px_fp64", 300, 70, "px_walls", "fp64", 1, False,
      {"beta_T": 3e-4, "gravity": (2.0, -9.81)}),
+    ("symmetry_plane", 600, 70, "io_symmetry", "fp32", 1, True, {}),
+    ("symmetry_plane_fp64", 200, 20, "io_symmetry", "fp64", 1, False, {}),
+    ("symmetry_periodic_x", 300, 40, "px_symmetry", "fp32", 1, False, {"Fx": 50.0}),
 ]
 CAVITY_CASES = [
     # name, n, bc, prec
@@ -139,12 +143,11 @@ def test_two_step_channel_kernel_under_graph_replay():
     assert one == two
 
 
-@pytest.mark.parametrize("bc,thermal", [("io_walls", "d2q9"), ("io_symmetry", True)],
-                         ids=["d2q9_thermal", "symmetry_plane"])
+@pytest.mark.parametrize("bc,thermal", [("io_walls", "d2q9"), ("io_symmetry", "d2q9")],
+                         ids=["d2q9_thermal", "d2q9_thermal_symmetry"])
 def test_two_step_channel_mode_rejected_where_not_covered(bc, thermal):
     """Mode 2 on a channel configuration the two-step kernel does not cover
-    (the D2Q9 thermal set, the symmetry plane) is refused once the
-    parameters are set."""
+    (the D2Q9 thermal set) is refused once the parameters are set."""
     from paper_2302_04120_amd import lbm
     print_case(test="chan-fusion-unsupported", bc=bc)
     prm, ini = _case(64, 16, seed=1)
