@@ -338,7 +338,9 @@ __global__ __launch_bounds__(64) void k_chan_step(ChanK k, const S* __restrict__
 // mod1 are the wall-flux modulations at t and t + dt.
 // ALIGNED: nx a multiple of 64 and a row's node blocks under 2 GiB, so every
 // row starts on a node block and an access is the row's block base (uniform)
-// plus a 32-bit lane offset.
+// plus a 32-bit lane offset.  ENDS: the code for the cavity's end walls and the
+// symmetry plane is compiled in (kept out of the other configurations: with
+// it the 16384 x 2048 channel step took 0.462 ms instead of 0.419).
 // ---------------------------------------------------------------------------
 constexpr int kCtLanes = 256;
 constexpr int kCtHalo = 2;                      // overlap columns per side
@@ -346,7 +348,7 @@ constexpr int kCtOut = kCtLanes - 2 * kCtHalo;  // stored columns per tile
 constexpr int kCtNV = 14;                       // values per node: f 0-8, g 9-13
 constexpr int kCtX = 10;                        // LDS exchange rows of step n
 
-template <typename S, bool ALIGNED>
+template <typename S, bool ALIGNED, bool ENDS>
 __global__ __launch_bounds__(kCtLanes) void k_chan_tb2(ChanK k, const S* __restrict__ A,
                                                       S* __restrict__ B, const S* __restrict__ qw,
                                                       const S* __restrict__ uin,
@@ -365,10 +367,10 @@ __global__ __launch_bounds__(kCtLanes) void k_chan_tb2(ChanK k, const S* __restr
     const int a = (w - b * nseg) * seg;
     const int e = min(a + seg, ny);
     const bool walls = k.bcy != 0;  // y ends: a wall at y-, a wall or the symmetry plane at y+
-    const bool symy = k.bcy == 2;   // the symmetry plane of Eq. simetria at y+
+    const bool symy = ENDS && k.bcy == 2;  // the symmetry plane of Eq. simetria at y+
     const bool xends = k.bcx != 0;  // x not periodic: the channel has a left and a right end
-    const bool io = k.bcx == 1;     // velocity inlet (left), pressure outlet (right)
-    const bool xw = k.bcx == 2;     // fixed-temperature no-slip walls at both ends
+    const bool io = ENDS ? k.bcx == 1 : xends;  // velocity inlet (left), pressure outlet (right)
+    const bool xw = ENDS && k.bcx == 2;  // fixed-temperature no-slip walls at both ends
     const int s1 = walls ? max(a - 1, 0) : a - 1;   // first row of step n
     const int e1 = walls ? min(e + 1, ny) : e + 1;  // end of the step-n rows
     const long long base = (long long)b * ny * nx;
@@ -537,16 +539,16 @@ __global__ __launch_bounds__(kCtLanes) void k_chan_tb2(ChanK k, const S* __restr
             }
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
-                int ty = r + EY[i], j = i;
-                const bool sym = symy && ty >= ny;  // mirrored back into the top row
-                if (sym) {
-                    ty = ny - 1;
-                    j = MIRY[i];
-                }
+                const int ty = r + EY[i];
+                // under the symmetry plane a +y mover comes back mirrored into the
+                // top row (a separate branch keeps every value index a constant)
+                const bool sym = symy && ty >= ny;
                 const bool outy = walls && !sym && (ty < 0 || ty >= ny);
                 const bool outx = (EX[i] < 0 && x_lo) || (EX[i] > 0 && x_hi);
-                if (!outy && !outx) {
-                    st(at(B, ty, EX[i] == 0 ? 0 : (EX[i] > 0 ? 2 : 1), j), S(ds1[i]));
+                if (sym && !outx) {
+                    st(at(B, r, EX[i] == 0 ? 0 : (EX[i] > 0 ? 2 : 1), MIRY[i]), S(ds1[i]));
+                } else if (!outy && !outx) {
+                    st(at(B, ty, EX[i] == 0 ? 0 : (EX[i] > 0 ? 2 : 1), i), S(ds1[i]));
                 } else {
                     C val;
                     if (outy || xw)
@@ -560,16 +562,14 @@ __global__ __launch_bounds__(kCtLanes) void k_chan_tb2(ChanK k, const S* __restr
             }
 #pragma unroll
             for (int i = 0; i < QT; ++i) {
-                int ty = r + EY5[i], j = i;
+                const int ty = r + EY5[i];
                 const bool sym = symy && ty >= ny;
-                if (sym) {
-                    ty = ny - 1;
-                    j = MIRY5[i];
-                }
                 const bool outy = walls && !sym && (ty < 0 || ty >= ny);
                 const bool outx = (EX5[i] < 0 && x_lo) || (EX5[i] > 0 && x_hi);
-                if (!outy && !outx) {
-                    st(at(B, ty, EX5[i] == 0 ? 0 : (EX5[i] > 0 ? 2 : 1), G + j), S(es1[i]));
+                if (sym && !outx) {
+                    st(at(B, r, EX5[i] == 0 ? 0 : (EX5[i] > 0 ? 2 : 1), G + MIRY5[i]), S(es1[i]));
+                } else if (!outy && !outx) {
+                    st(at(B, ty, EX5[i] == 0 ? 0 : (EX5[i] > 0 ? 2 : 1), G + i), S(es1[i]));
                     // outlet extrapolation: what column nx - 2 receives
                     if (EX5[i] < 0 && at_out) st(at(B, ty, 0, G + i), S(es1[i]));
                 } else if (outy) {
@@ -1728,6 +1728,15 @@ long long chan_tb2_workgroups(const ChanK& k, int seg) {
 // x-tiles, three workgroups per CU) it picks 90 rows, the fastest of 32 to
 // 512 rows in a sweep (0.420 ms per step; 187 rows 0.427, 64 rows 0.434,
 // 128 rows 0.541, 256 rows 0.525).
+// The instance of the two-step channel kernel for a configuration.
+template <typename S>
+auto chan_tb2_kernel(const ChanK& k) {
+    const bool ends = k.bcx == 2 || k.bcy == 2;
+    if (chan_tb2_aligned<S>(k))
+        return ends ? k_chan_tb2<S, true, true> : k_chan_tb2<S, true, false>;
+    return ends ? k_chan_tb2<S, false, true> : k_chan_tb2<S, false, false>;
+}
+
 template <typename S>
 int chan_tb2_seg(const ChanK& k) {
     const int ny = k.ny;
@@ -1735,10 +1744,8 @@ int chan_tb2_seg(const ChanK& k) {
     long long slots = 1024;
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-        (chan_tb2_aligned<S>(k) ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                                      &per_cu, k_chan_tb2<S, true>, kCtLanes, 0)
-                                : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                                      &per_cu, k_chan_tb2<S, false>, kCtLanes, 0)) == hipSuccess &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, chan_tb2_kernel<S>(k), kCtLanes, 0) ==
+            hipSuccess &&
         cus > 0 && per_cu > 0)
         slots = (long long)cus * per_cu;
     const long long units = (long long)k.batch * chan_tb2_ntx(k);
@@ -1766,12 +1773,8 @@ hipError_t launch_chan_tb2(const ChanK& k, const S* a, S* b, const S* qw, const 
     const long long wgs = chan_tb2_workgroups(k, seg);
     if ((wgs + kXCD - 1) / kXCD * kXCD > 0x7fffffffLL) return hipErrorInvalidValue;
     dim3 grd(unsigned((wgs + kXCD - 1) / kXCD * kXCD)), blk(kCtLanes);
-    if (chan_tb2_aligned<S>(k))
-        hipLaunchKernelGGL((k_chan_tb2<S, true>), grd, blk, 0, s, k, a, b, qw, uin, tin, S(mod0),
-                           S(mod1), seg);
-    else
-        hipLaunchKernelGGL((k_chan_tb2<S, false>), grd, blk, 0, s, k, a, b, qw, uin, tin, S(mod0),
-                           S(mod1), seg);
+    hipLaunchKernelGGL(chan_tb2_kernel<S>(k), grd, blk, 0, s, k, a, b, qw, uin, tin, S(mod0),
+                       S(mod1), seg);
     return hipGetLastError();
 }
 
