@@ -115,7 +115,8 @@ __device__ __forceinline__ void chan_collide(const ChanK& k, const C (&d)[9], C 
             C neq[9];
 #pragma unroll
             for (int i = 0; i < 9; ++i)
-                neq[i] = e[i] - twt<QT, C>(i) * th * (C(1) + C(3) * (C(tex<QT>(i)) * ux + C(tey<QT>(i)) * uy));
+                neq[i] = e[i] - twt<QT, C>(i) * th *
+                                    (C(1) + C(3) * (C(tex<QT>(i)) * ux + C(tey<QT>(i)) * uy));
             moments9(neq, m);
             // moments of the source w_i qdot dt: qdt (1, -2, 1, 0, ...)
 #pragma unroll
@@ -314,12 +315,12 @@ __global__ __launch_bounds__(64) void k_chan_step(ChanK k, const S* __restrict__
 // ---------------------------------------------------------------------------
 // Two channel steps per launch (temporal blocking) for the flow + D2Q5
 // temperature model (Boussinesq force optional) with x periodic, inlet/outlet
-// or fixed-temperature end walls and y periodic, walls, or a wall below and the
-// symmetry plane above.  A workgroup of 256
-// lanes takes one x-tile of one row segment [a, e) of one replica: lane l
-// holds column c = 252 t - 2 + l (modulo nx for periodic x; with x ends,
-// lanes whose column lies outside [0, nx) read a clamped column and their
-// results are never used).  At row v it collides step n at row v and step n + 1 at row v - 1:
+// or fixed-temperature end walls and y periodic, walls, or a wall below and
+// the symmetry plane above.  A workgroup of 256 lanes takes one x-tile of one
+// row segment [a, e) of one replica: lane l holds column c = 252 t - 2 + l
+// (modulo nx for periodic x; with x ends, lanes whose column lies outside
+// [0, nx) read a clamped column and their results are never used).  At row v
+// it collides step n at row v and step n + 1 at row v - 1:
 //   - step n hands its x-moving post-collision values (and u, for the
 //     outlet's wall velocity) to the neighbour lanes through LDS and
 //     accumulates them into the step-(n + 1) state of rows v - 1, v and
@@ -338,9 +339,9 @@ __global__ __launch_bounds__(64) void k_chan_step(ChanK k, const S* __restrict__
 // mod1 are the wall-flux modulations at t and t + dt.
 // ALIGNED: nx a multiple of 64 and a row's node blocks under 2 GiB, so every
 // row starts on a node block and an access is the row's block base (uniform)
-// plus a 32-bit lane offset.  ENDS: the code for the cavity's end walls and the
-// symmetry plane is compiled in (kept out of the other configurations: with
-// it the 16384 x 2048 channel step took 0.462 ms instead of 0.419).
+// plus a 32-bit lane offset.  ENDS: the code for the cavity's end walls and
+// the symmetry plane is compiled in (kept out of the other configurations:
+// with it the 16384 x 2048 channel step took 0.462 ms instead of 0.419).
 // ---------------------------------------------------------------------------
 constexpr int kCtLanes = 256;
 constexpr int kCtHalo = 2;                      // overlap columns per side
@@ -481,7 +482,8 @@ __global__ __launch_bounds__(kCtLanes) void k_chan_tb2(ChanK k, const S* __restr
             // an end wall (xw) bounces back like the y walls (u_w = 0)
             A0[0] = ds[0];
             A0[1] = x_lo ? (io ? chan_inlet_f<C>(3, ds[3], rho_ref, u_in) : ds[3]) : xb[0][lxm];
-            A0[3] = x_hi ? (io ? chan_outlet_f<C>(1, ds[1], rho_ref, uwx, uwy) : ds[1]) : xb[1][lxp];
+            A0[3] = x_hi ? (io ? chan_outlet_f<C>(1, ds[1], rho_ref, uwx, uwy) : ds[1])
+                         : xb[1][lxp];
             // the -y slots take the top wall's values; below the top row the
             // next row's pushes overwrite them (not the inlet's and outlet's
             // own values)
@@ -496,7 +498,8 @@ __global__ __launch_bounds__(kCtLanes) void k_chan_tb2(ChanK k, const S* __restr
             // wall and where the source lies beyond an x end
             A0[2] = bottom ? ds[4] : A0[2];
             A0[5] = bottom ? ds[7]
-                           : (x_lo ? (io ? chan_inlet_f<C>(7, ds[7], rho_ref, u_in) : ds[7]) : A0[5]);
+                           : (x_lo ? (io ? chan_inlet_f<C>(7, ds[7], rho_ref, u_in) : ds[7])
+                                   : A0[5]);
             A0[6] = bottom ? ds[8]
                            : (x_hi ? (io ? chan_outlet_f<C>(8, ds[8], rho_ref, uwx, uwy) : ds[8])
                                    : A0[6]);
