@@ -106,15 +106,17 @@ def print_case(**kw):
 
 
 def channel_pair(prm, ini, nx, ny, steps, prec, bc_x="inlet_outlet", bc_y="walls", thermal=True,
-                 flow=True, batch=1):
+                 flow=True, batch=1, fusion=0):
     """Run the channel on the GPU and in the oracle; returns (gpu macros of
-    replica 0, oracle macros, lattice object, oracle object)."""
+    replica 0, oracle macros, lattice object, oracle object).  fusion 2 steps
+    the GPU side in pairs with the two-step kernel."""
     from paper_2302_04120_amd import lbm
     bcx = (lbm.BC_VEL_INLET, lbm.BC_P_OUTLET) if bc_x == "inlet_outlet" else (0, 0)
     bcy = (lbm.BC_WALL, lbm.BC_WALL) if bc_y == "walls" else (0, 0)
     L = lbm.Lattice("channel", nx, ny, batch=batch, prec=prec, bc=bcx + bcy, flow=flow,
                     thermal=thermal)
     L.set_params(prm)
+    L.set_step_fusion(fusion)
     L.init(ini["rho"], ini["ux"], ini["uy"], ini.get("T") if thermal else None)
     L.step(steps)
     g = L.macros()

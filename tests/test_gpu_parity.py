@@ -43,15 +43,17 @@ def _chan_fields_check(g, o, prm, tol, thermal=True):
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", FP64_TOL), ("fp32", FP32_TOL)])
-def test_channel_inlet_outlet_flux_walls(prec, tol):
+@pytest.mark.parametrize("fusion", [0, 2])
+def test_channel_inlet_outlet_flux_walls(prec, tol, fusion):
     """D2Q9 MRT + D2Q5 two-rate, velocity inlet, pressure outlet, flux walls with
-    a spatial square-wave flux and temporal oscillation; ragged 150 x 22 grid."""
+    a spatial square-wave flux and temporal oscillation; ragged 150 x 22 grid;
+    single steps (the automatic choice at this size) and the two-step kernel."""
     nx, ny = 150, 22
-    print_case(test="channel_io", prec=prec, nx=nx, ny=ny)
+    print_case(test="channel_io", prec=prec, nx=nx, ny=ny, fusion=fusion)
     prm, ini = WL.channel(nx=nx, ny=ny, dx=5e-5, tau_ratio=0.6, oscillating=True)
     prm["flux"] = 1e4 * (1 + np.sign(np.sin(2 * np.pi * np.arange(nx) / 40.0)))
     prm["flux_omega"] = 2 * np.pi / (150 * prm["dt"])
-    g, o, _, _ = channel_pair(prm, ini, nx, ny, 300, prec)
+    g, o, _, _ = channel_pair(prm, ini, nx, ny, 300, prec, fusion=fusion)
     _chan_fields_check(g, o, prm, tol)
 
 
@@ -294,11 +296,13 @@ def test_error_paths_on_device():
 
 
 # ---------------------------------------------------------------- full sizes
-def test_full_size_channel_c2_sampled():
-    """C2 at its full 800 x 40 size, FP32-dev, 200 steps, all nodes compared."""
-    print_case(test="c2_full")
+@pytest.mark.parametrize("fusion", [0, 2])
+def test_full_size_channel_c2_sampled(fusion):
+    """C2 at its full 800 x 40 size, FP32-dev, 200 steps, all nodes compared;
+    single steps and the two-step kernel."""
+    print_case(test="c2_full", fusion=fusion)
     prm, ini = WL.channel(nx=800, ny=40, tau_ratio=0.64, oscillating=True)
-    g, o, _, _ = channel_pair(prm, ini, 800, 40, 200, "fp32")
+    g, o, _, _ = channel_pair(prm, ini, 800, 40, 200, "fp32", fusion=fusion)
     _chan_fields_check(g, o, prm, FP32_TOL)
 
 
