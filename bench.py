@@ -696,6 +696,7 @@ def main():
         log("bench: heated-channel leg (16384 x 2048)")
         extras["channel_fp32"] = run_channel(16384, 2048, 100, 10, "fp32", fusion=2)
         extras["channel_single_step_fp32"] = run_channel(16384, 2048, 100, 10, "fp32", fusion=1)
+        extras["channel_fp64"] = run_channel(16384, 2048, 40, 4, "fp64", fusion=2)
         log("bench: D3Q19 leg (256^3)")
         extras["d3q19_fp32"] = run_d3(256, 100, 10, "fp32")
         extras["d3q19_fp64"] = run_d3(256, 40, 4, "fp64")
