@@ -93,6 +93,7 @@ CASES = [
     ("symmetry_plane", 600, 70, "io_symmetry", "fp32", 1, True, {}),
     ("symmetry_plane_fp64", 200, 20, "io_symmetry", "fp64", 1, False, {}),
     ("symmetry_periodic_x", 300, 40, "px_symmetry", "fp32", 1, False, {"Fx": 50.0}),
+    ("batch3_io_aligned", 256, 40, "io_walls", "fp32", 3, True, {}),
 ]
 CAVITY_CASES = [
     # name, n, bc, prec
@@ -183,6 +184,31 @@ def test_two_step_channel_kernel_bench_size():
         L.init(ini["rho"], ini["ux"], ini["uy"], ini["T"])
         L.step(2)
         L.step(3)
+        assert L.reduce(("nonfinite",))["nonfinite"].sum() == 0
+        digests.append(hashlib.sha256(L.save_state()).hexdigest())
+        L.close()
+    assert digests[0] == digests[1]
+
+
+def test_automatic_mode_on_a_large_channel():
+    """8192 x 1024 (33 x-tiles, enough row segments to fill the GPU): the
+    automatic kernel choice (the two-step kernel at this size) gives the same
+    state as single steps."""
+    import hashlib
+
+    from paper_2302_04120_amd import lbm
+    nx, ny = 8192, 1024
+    print_case(test="chan-fusion-auto", nx=nx, ny=ny)
+    prm, ini = _case(nx, ny, seed=9)
+    digests = []
+    for fusion in (1, 0):
+        L = lbm.Lattice("channel", nx, ny, bc=_bc("io_walls"), thermal=True)
+        L.set_graph_steps(0)
+        L.set_params(prm)
+        L.set_step_fusion(fusion)
+        L.init(ini["rho"], ini["ux"], ini["uy"], ini["T"])
+        L.step(2)
+        L.step(5)
         assert L.reduce(("nonfinite",))["nonfinite"].sum() == 0
         digests.append(hashlib.sha256(L.save_state()).hexdigest())
         L.close()
