@@ -277,8 +277,8 @@ LBM_API lbm_status lbm_set_graph_steps(lbm_ctx* ctx, int steps);
  *           (any nx); LBM_E_UNSUPPORTED with LBM_FP32_DEV_ARITH64; ny < 4
  *           uses the single-step kernel.
  *           LBM_D2Q9_D2Q5: x-tiles of 256 lanes that store 252 columns and
- *           overlap by 2 per side; covers flow with D2Q5 temperature (with
- *           or without buoyancy) and every boundary of the lattice;
+ *           overlap by 2 per side; covers flow with temperature (either
+ *           thermal set, with or without buoyancy) and every boundary;
  *           LBM_E_UNSUPPORTED for other configurations once
  *           lbm_set_params_SI has been called (before it, such a
  *           configuration steps with the single-step kernel).

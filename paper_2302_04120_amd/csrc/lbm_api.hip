@@ -554,7 +554,7 @@ lbm_status lbm_set_step_fusion(lbm_ctx* c, int mode) {
         return set_err(c, LBM_E_UNSUPPORTED, "two-step kernel: not with FP64 arithmetic on FP32 storage");
     if (mode == 2 && c->desc.lattice == LBM_D2Q9_D2Q5 && c->has_params && !chan_tb2_fits(c->ck))
         return set_err(c, LBM_E_UNSUPPORTED,
-                       "two-step channel kernel: needs flow with D2Q5 temperature");
+                       "two-step channel kernel: needs both flow and temperature");
     if (mode != c->fusion) {
         DeviceGuard g(c->device);
         drop_graphs(c);

@@ -313,10 +313,10 @@ __global__ __launch_bounds__(64) void k_chan_step(ChanK k, const S* __restrict__
 }
 
 // ---------------------------------------------------------------------------
-// Two channel steps per launch (temporal blocking) for the flow + D2Q5
-// temperature model (Boussinesq force optional) with x periodic, inlet/outlet
-// or fixed-temperature end walls and y periodic, walls, or a wall below and
-// the symmetry plane above.  A workgroup of 256 lanes takes one x-tile of one
+// Two channel steps per launch (temporal blocking) for flow with temperature
+// (QT: the D2Q5 or D2Q9 thermal set; Boussinesq force optional), x periodic,
+// inlet/outlet or fixed-temperature end walls and y periodic, walls, or a wall
+// below and the symmetry plane above.  A workgroup of 256 lanes takes one x-tile of one
 // row segment [a, e) of one replica: lane l holds column c = 252 t - 2 + l
 // (modulo nx for periodic x; with x ends, lanes whose column lies outside
 // [0, nx) read a clamped column and their results are never used).  At row v
@@ -346,17 +346,19 @@ __global__ __launch_bounds__(64) void k_chan_step(ChanK k, const S* __restrict__
 constexpr int kCtLanes = 256;
 constexpr int kCtHalo = 2;                      // overlap columns per side
 constexpr int kCtOut = kCtLanes - 2 * kCtHalo;  // stored columns per tile
-constexpr int kCtNV = 14;                       // values per node: f 0-8, g 9-13
-constexpr int kCtX = 10;                        // LDS exchange rows of step n
+// values per node (f 0-8, g from 9) and LDS exchange rows of step n (6 flow
+// x movers, the thermal x movers 1 and 3, u, then the thermal diagonals 5-8)
+constexpr int ct_nv(int qt) { return 9 + qt; }
+constexpr int ct_x(int qt) { return qt == 9 ? 14 : 10; }
 
-template <typename S, bool ALIGNED, bool ENDS>
+template <typename S, bool ALIGNED, bool ENDS, int QT>
 __global__ __launch_bounds__(kCtLanes) void k_chan_tb2(ChanK k, const S* __restrict__ A,
                                                       S* __restrict__ B, const S* __restrict__ qw,
                                                       const S* __restrict__ uin,
                                                       const S* __restrict__ tin, S mod0, S mod1,
                                                       int seg) {
     using C = S;
-    constexpr int QT = 5, NV = kCtNV, G = 9;
+    constexpr int NV = ct_nv(QT), G = 9, NX = ct_x(QT);
     const int nx = k.nx, ny = k.ny;
     const int nseg = (ny + seg - 1) / seg;
     const int ntx = (nx + kCtOut - 1) / kCtOut;
@@ -389,7 +391,7 @@ __global__ __launch_bounds__(kCtLanes) void k_chan_tb2(ChanK k, const S* __restr
     const C q = C(qw[x]);
     const C tw_lo = C(k.Tw[0]), tw_hi = C(k.Tw[1]);
 
-    __shared__ C xch[2][kCtX][kCtLanes];  // step n: x movers and u, rows v mod 2
+    __shared__ C xch[2][NX][kCtLanes];  // step n: x movers and u, rows v mod 2
     __shared__ C un1[2][2][kCtLanes];     // step n + 1: u, rows v mod 2
 
     // memory row of virtual row v: step-n rows of a periodic segment lie in
@@ -446,7 +448,7 @@ __global__ __launch_bounds__(kCtLanes) void k_chan_tb2(ChanK k, const S* __restr
         const bool do_n = v < e1;
         // unconditional (the last row step re-reads an existing row)
         load_row(do_n ? v : e1 - 1, Ld);
-        C(&xb)[kCtX][kCtLanes] = xch[v & 1];
+        C(&xb)[NX][kCtLanes] = xch[v & 1];
         // ---- step n at row v
         C ds[9], es[QT], ux = C(0), uy = C(0);
         if (do_n) {
@@ -459,6 +461,12 @@ __global__ __launch_bounds__(kCtLanes) void k_chan_tb2(ChanK k, const S* __restr
             xb[5][lx] = ds[8];
             xb[6][lx] = es[1];
             xb[7][lx] = es[3];
+            if constexpr (QT == 9) {
+                xb[10][lx] = es[5];
+                xb[11][lx] = es[6];
+                xb[12][lx] = es[7];
+                xb[13][lx] = es[8];
+            }
             xb[8][lx] = ux;
             xb[9][lx] = uy;
         }
@@ -510,15 +518,52 @@ __global__ __launch_bounds__(kCtLanes) void k_chan_tb2(ChanK k, const S* __restr
             A1[7] = x_hi ? A1[7] : xb[4][lxp];
             A1[8] = x_lo ? A1[8] : xb[5][lxm];
             // temperature: Dirichlet inlet or end walls (anti-bounce-back),
-            // outlet extrapolation (its own value, the one its left neighbour
-            // receives), flux walls
-            A0[G + 0] = es[0];
-            A0[G + 1] = x_lo ? chan_antibb_g<QT, C>(3, es[3], io ? t_in : tw_lo) : xb[6][lxm];
-            A0[G + 3] = x_hi ? (io ? es[3] : chan_antibb_g<QT, C>(1, es[1], tw_hi)) : xb[7][lxp];
-            A0[G + 4] = stop ? es[2] : chan_flux_g<QT, C>(2, es[2], q, mod0);
-            A0[G + 2] = bottom ? chan_flux_g<QT, C>(4, es[4], q, mod0) : A0[G + 2];
-            Ap[G + 2] = es[2];
-            A1[G + 4] = es[4];
+            // outlet extrapolation (the value its left neighbour receives:
+            // the outlet node's own), flux walls
+            if constexpr (QT == 5) {
+                A0[G + 0] = es[0];
+                A0[G + 1] = x_lo ? chan_antibb_g<QT, C>(3, es[3], io ? t_in : tw_lo) : xb[6][lxm];
+                A0[G + 3] = x_hi ? (io ? es[3] : chan_antibb_g<QT, C>(1, es[1], tw_hi)) : xb[7][lxp];
+                A0[G + 4] = stop ? es[2] : chan_flux_g<QT, C>(2, es[2], q, mod0);
+                A0[G + 2] = bottom ? chan_flux_g<QT, C>(4, es[4], q, mod0) : A0[G + 2];
+                Ap[G + 2] = es[2];
+                A1[G + 4] = es[4];
+            } else {
+                // D2Q9 thermal set: the diagonals follow the flow's pattern.
+                // Inlet temperature where a link crosses the inlet: the mean
+                // of its two rows (the row's own value if the other is beyond
+                // the channel).
+                C tw6 = C(0), tw7 = C(0);
+                if (io) {
+                    const int y = rowof(v);
+                    tw6 = y + 1 < ny ? C(0.5) * (C(tin[y]) + C(tin[y + 1])) : C(tin[y]);
+                    tw7 = y - 1 >= 0 ? C(0.5) * (C(tin[y]) + C(tin[y - 1])) : C(tin[y]);
+                }
+                const C l8 = chan_antibb_g<QT, C>(6, es[6], io ? tw6 : tw_lo);
+                const C l5 = chan_antibb_g<QT, C>(7, es[7], io ? tw7 : tw_lo);
+                A0[G + 0] = es[0];
+                A0[G + 1] = x_lo ? chan_antibb_g<QT, C>(3, es[3], io ? t_in : tw_lo) : xb[6][lxm];
+                A0[G + 3] = x_hi ? (io ? es[3] : chan_antibb_g<QT, C>(1, es[1], tw_hi)) : xb[7][lxp];
+                // -y slots: top wall flux, mirrored movers under the symmetry
+                // plane, else provisional (the row above overwrites them, but
+                // not the end columns' own values)
+                A0[G + 4] = stop ? es[2] : chan_flux_g<QT, C>(2, es[2], q, mod0);
+                A0[G + 7] = top ? chan_flux_g<QT, C>(5, es[5], q, mod0)
+                          : x_hi ? (io ? es[6] : chan_antibb_g<QT, C>(5, es[5], tw_hi))
+                                 : xb[11][lxp];
+                A0[G + 8] = top ? chan_flux_g<QT, C>(6, es[6], q, mod0) : x_lo ? l8 : xb[10][lxm];
+                // +y slots: bottom wall flux, the end columns' own values
+                A0[G + 2] = bottom ? chan_flux_g<QT, C>(4, es[4], q, mod0) : A0[G + 2];
+                A0[G + 5] = bottom ? chan_flux_g<QT, C>(7, es[7], q, mod0) : x_lo ? l5 : A0[G + 5];
+                A0[G + 6] = bottom ? chan_flux_g<QT, C>(8, es[8], q, mod0)
+                          : (x_hi && xw) ? chan_antibb_g<QT, C>(8, es[8], tw_hi) : A0[G + 6];
+                Ap[G + 2] = es[2];
+                Ap[G + 5] = xb[10][lxm];
+                Ap[G + 6] = at_out ? es[6] : xb[11][lxp];
+                A1[G + 4] = es[4];
+                A1[G + 7] = (x_hi && xw) ? A1[G + 7] : at_out ? es[7] : xb[12][lxp];
+                A1[G + 8] = x_lo ? A1[G + 8] : xb[13][lxm];
+            }
         }
         // ---- step n + 1 at row r = v - 1, complete now, straight to memory
         const int r = v - 1;
@@ -565,25 +610,35 @@ __global__ __launch_bounds__(kCtLanes) void k_chan_tb2(ChanK k, const S* __restr
             }
 #pragma unroll
             for (int i = 0; i < QT; ++i) {
-                const int ty = r + EY5[i];
+                const int cx = tex<QT>(i), cy = tey<QT>(i);
+                const int ty = r + cy;
                 const bool sym = symy && ty >= ny;
                 const bool outy = walls && !sym && (ty < 0 || ty >= ny);
-                const bool outx = (EX5[i] < 0 && x_lo) || (EX5[i] > 0 && x_hi);
+                const bool outx = (cx < 0 && x_lo) || (cx > 0 && x_hi);
+                const int col = cx == 0 ? 0 : (cx > 0 ? 2 : 1);
+                // outlet extrapolation: what column nx - 2 receives in a slot
+                // with c_x < 0 (never a slot a wall rule owns here: its
+                // source is this row or, mirrored, the row itself)
                 if (sym && !outx) {
-                    st(at(B, r, EX5[i] == 0 ? 0 : (EX5[i] > 0 ? 2 : 1), G + MIRY5[i]), S(es1[i]));
+                    st(at(B, r, col, G + tmir<QT>(i)), S(es1[i]));
+                    if (tex<QT>(tmir<QT>(i)) < 0 && at_out) st(at(B, r, 0, G + tmir<QT>(i)), S(es1[i]));
                 } else if (!outy && !outx) {
-                    st(at(B, ty, EX5[i] == 0 ? 0 : (EX5[i] > 0 ? 2 : 1), G + i), S(es1[i]));
-                    // outlet extrapolation: what column nx - 2 receives
-                    if (EX5[i] < 0 && at_out) st(at(B, ty, 0, G + i), S(es1[i]));
+                    st(at(B, ty, col, G + i), S(es1[i]));
+                    if (cx < 0 && at_out) st(at(B, ty, 0, G + i), S(es1[i]));
                 } else if (outy) {
-                    st(at(B, r, 0, G + OPP5[i]), S(chan_flux_g<QT, C>(i, es1[i], q, mod1)));
+                    st(at(B, r, 0, G + topp<QT>(i)), S(chan_flux_g<QT, C>(i, es1[i], q, mod1)));
                 } else if (xw) {
-                    st(at(B, r, 0, G + OPP5[i]),
-                       S(chan_antibb_g<QT, C>(i, es1[i], EX5[i] < 0 ? tw_lo : tw_hi)));
-                } else if (EX5[i] < 0) {
-                    st(at(B, r, 0, G + OPP5[i]), S(chan_antibb_g<QT, C>(i, es1[i], t_in)));
+                    st(at(B, r, 0, G + topp<QT>(i)),
+                       S(chan_antibb_g<QT, C>(i, es1[i], cx < 0 ? tw_lo : tw_hi)));
+                } else if (cx < 0) {
+                    // the inlet temperature where the link crosses the inlet
+                    const int y2 = r + cy;
+                    const C tw = cy == 0 ? t_in
+                               : (y2 >= 0 && y2 < ny) ? C(0.5) * (C(tin[r]) + C(tin[y2]))
+                                                      : C(tin[r]);
+                    st(at(B, r, 0, G + topp<QT>(i)), S(chan_antibb_g<QT, C>(i, es1[i], tw)));
                 }
-                // the outlet's own +x mover leaves; its slot is extrapolated
+                // the outlet's own +x movers leave; their slots are extrapolated
             }
         }
     };
@@ -1703,12 +1758,12 @@ hipError_t launch_chan_step(const ChanK& k, const S* a, S* b, const S* qw, const
     return hipGetLastError();
 }
 
-// The two-step channel kernel covers flow with D2Q5 temperature (with or
-// without the Boussinesq force), every x and y boundary of the channel
-// lattice, and at least two columns and rows.
+// The two-step channel kernel covers flow with temperature (D2Q5 or the D2Q9
+// set, with or without the Boussinesq force), every x and y boundary of the
+// channel lattice, and at least two columns and rows.
 bool chan_tb2_fits(const ChanK& k) {
-    return k.flow && k.thermal && k.tq == 5 && k.npl == kCtNV && k.bcx >= 0 && k.bcx <= 2 &&
-           k.bcy >= 0 && k.bcy <= 2 && k.nx >= 2 && k.ny >= 2;
+    return k.flow && k.thermal && (k.tq == 5 || k.tq == 9) && k.npl == ct_nv(k.tq) &&
+           k.bcx >= 0 && k.bcx <= 2 && k.bcy >= 0 && k.bcy <= 2 && k.nx >= 2 && k.ny >= 2;
 }
 int chan_tb2_ntx(const ChanK& k) { return (k.nx + kCtOut - 1) / kCtOut; }
 // Share of the launched lanes whose columns are stored.
@@ -1717,7 +1772,7 @@ double chan_tb2_lane_use(const ChanK& k) {
 }
 template <typename S>
 bool chan_tb2_aligned(const ChanK& k) {
-    return k.nx % kBlk == 0 && (long long)k.nx * kCtNV * (long long)sizeof(S) < (1LL << 31);
+    return k.nx % kBlk == 0 && (long long)k.nx * ct_nv(k.tq) * (long long)sizeof(S) < (1LL << 31);
 }
 long long chan_tb2_workgroups(const ChanK& k, int seg) {
     return (long long)((k.ny + seg - 1) / seg) * k.batch * chan_tb2_ntx(k);
@@ -1735,9 +1790,14 @@ long long chan_tb2_workgroups(const ChanK& k, int seg) {
 template <typename S>
 auto chan_tb2_kernel(const ChanK& k) {
     const bool ends = k.bcx == 2 || k.bcy == 2;
+    if (k.tq == 9) {
+        if (chan_tb2_aligned<S>(k))
+            return ends ? k_chan_tb2<S, true, true, 9> : k_chan_tb2<S, true, false, 9>;
+        return ends ? k_chan_tb2<S, false, true, 9> : k_chan_tb2<S, false, false, 9>;
+    }
     if (chan_tb2_aligned<S>(k))
-        return ends ? k_chan_tb2<S, true, true> : k_chan_tb2<S, true, false>;
-    return ends ? k_chan_tb2<S, false, true> : k_chan_tb2<S, false, false>;
+        return ends ? k_chan_tb2<S, true, true, 5> : k_chan_tb2<S, true, false, 5>;
+    return ends ? k_chan_tb2<S, false, true, 5> : k_chan_tb2<S, false, false, 5>;
 }
 
 template <typename S>

@@ -43,9 +43,10 @@ def _cavity_case(n, seed):
     return prm, ini
 
 
-def _state(prm, ini, nx, ny, bc, fusion, steps, prec="fp32", batch=1, graph_steps=0):
+def _state(prm, ini, nx, ny, bc, fusion, steps, prec="fp32", batch=1, graph_steps=0,
+           thermal=True):
     from paper_2302_04120_amd import lbm
-    L = lbm.Lattice("channel", nx, ny, prec=prec, bc=bc, batch=batch, thermal=True)
+    L = lbm.Lattice("channel", nx, ny, prec=prec, bc=bc, batch=batch, thermal=thermal)
     L.set_graph_steps(graph_steps)
     L.set_params(prm)
     L.set_step_fusion(fusion)
@@ -68,7 +69,8 @@ def _bc(name):
     return {"io_walls": io + walls, "px_walls": (0, 0) + walls, "periodic": (0, 0, 0, 0),
             "io_py": io + (0, 0), "cavity": xw + walls, "xw_py": xw + (0, 0),
             "io_symmetry": io + (lbm.BC_WALL, lbm.BC_SYMMETRY),
-            "px_symmetry": (0, 0, lbm.BC_WALL, lbm.BC_SYMMETRY)}[name]
+            "px_symmetry": (0, 0, lbm.BC_WALL, lbm.BC_SYMMETRY),
+            "xw_symmetry": xw + (lbm.BC_WALL, lbm.BC_SYMMETRY)}[name]
 
 
 CASES = [
@@ -119,6 +121,46 @@ def test_two_step_channel_kernel_bit_identical(name, nx, ny, bc, prec, batch, os
         pytest.fail("states differ in %d of %d bytes" % (int((a != b).sum()), a.size))
 
 
+D2Q9_CASES = [
+    # name, nx, ny, bc, prec, cavity, oscillating, overrides
+    ("d2q9_io_walls_osc", 600, 70, "io_walls", "fp32", False, True, {}),
+    ("d2q9_aligned", 512, 40, "io_walls", "fp32", False, False, {}),
+    ("d2q9_half_channel", 600, 70, "io_symmetry", "fp32", False, True, {}),
+    ("d2q9_half_channel_fp64", 200, 20, "io_symmetry", "fp64", False, False, {}),
+    ("d2q9_periodic_buoyant", 300, 70, "periodic", "fp32", False, False,
+     {"Fx": 50.0, "beta_T": 3e-4, "gravity": (0.0, -9.81)}),
+    ("d2q9_io_periodic_y", 256, 33, "io_py", "fp32", False, False, {}),
+    ("d2q9_tiny_io", 3, 2, "io_walls", "fp32", False, False, {}),
+    ("d2q9_cavity", 300, 300, "cavity", "fp32", True, False, {}),
+    ("d2q9_cavity_fp64", 130, 130, "cavity", "fp64", True, False, {}),
+    ("d2q9_end_walls_symmetry", 260, 40, "xw_symmetry", "fp32", True, False, {}),
+]
+
+
+@pytest.mark.parametrize("name,nx,ny,bc,prec,cavity,osc,over", D2Q9_CASES,
+                         ids=[c[0] for c in D2Q9_CASES])
+def test_two_step_kernel_d2q9_thermal_bit_identical(name, nx, ny, bc, prec, cavity, osc, over):
+    """The D2Q9 thermal set (Sec. 3, App. D): its diagonal links at the inlet
+    (the mean inlet temperature of the two rows a link joins), the outlet
+    extrapolation, the flux walls, the end walls and the symmetry plane."""
+    print_case(test="chan-fusion-d2q9", case=name, nx=nx, ny=ny, prec=prec)
+    if cavity:
+        prm, ini = _cavity_case(nx, seed=len(name))
+        if ny != nx:  # a cavity cut to ny rows: per-row inputs of ny entries
+            ini = {k: v[:ny] for k, v in ini.items()}
+            prm = dict(prm, inlet_u=np.zeros(ny), inlet_T=np.full(ny, prm["T_ref"]))
+    else:
+        prm, ini = _case(nx, ny, seed=len(name), oscillating=osc, **over)
+    steps = [7, 30]
+    one, nf1 = _state(prm, ini, nx, ny, _bc(bc), 1, steps, prec=prec, thermal="d2q9")
+    two, nf2 = _state(prm, ini, nx, ny, _bc(bc), 2, steps, prec=prec, thermal="d2q9")
+    assert nf1 == 0 and nf2 == 0
+    if one != two:
+        a = np.frombuffer(one, np.uint8)
+        b = np.frombuffer(two, np.uint8)
+        pytest.fail("states differ in %d of %d bytes" % (int((a != b).sum()), a.size))
+
+
 @pytest.mark.parametrize("name,n,bc,prec", CAVITY_CASES, ids=[c[0] for c in CAVITY_CASES])
 def test_two_step_kernel_cavity_bit_identical(name, n, bc, prec):
     print_case(test="chan-fusion-cavity", case=name, n=n, prec=prec)
@@ -144,15 +186,15 @@ def test_two_step_channel_kernel_under_graph_replay():
     assert one == two
 
 
-@pytest.mark.parametrize("bc,thermal", [("io_walls", "d2q9"), ("io_symmetry", "d2q9")],
-                         ids=["d2q9_thermal", "d2q9_thermal_symmetry"])
-def test_two_step_channel_mode_rejected_where_not_covered(bc, thermal):
+@pytest.mark.parametrize("flow,thermal", [(True, False), (False, True)],
+                         ids=["flow_only", "temperature_only"])
+def test_two_step_channel_mode_rejected_where_not_covered(flow, thermal):
     """Mode 2 on a channel configuration the two-step kernel does not cover
-    (the D2Q9 thermal set) is refused once the parameters are set."""
+    (flow alone, temperature alone) is refused once the parameters are set."""
     from paper_2302_04120_amd import lbm
-    print_case(test="chan-fusion-unsupported", bc=bc)
+    print_case(test="chan-fusion-unsupported", flow=flow, thermal=thermal)
     prm, ini = _case(64, 16, seed=1)
-    L = lbm.Lattice("channel", 64, 16, bc=_bc(bc), thermal=thermal)
+    L = lbm.Lattice("channel", 64, 16, bc=_bc("px_walls"), flow=flow, thermal=thermal)
     try:
         L.set_params(prm)
         with pytest.raises(lbm.LbmError) as ex:
