@@ -201,7 +201,7 @@ def run_channel(nx, ny, steps, warmup, prec, fusion=1):
     return dict(mlups=nodes * steps / wall / 1e6, kernel_ms=kernel_ms,
                 hbm_frac=per_step / (kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                 grid="%dx%d" % (nx, ny), fusion=fusion,
-                kernel=("k_chan_tb2<%s, %s, false>" % (S, "true" if nx % 64 == 0 else "false")
+                kernel=("k_chan_tb2<%s, %s, false, 5>" % (S, "true" if nx % 64 == 0 else "false")
                         if two else "k_chan_step<%s, 5>" % S))
 
 
